@@ -1,0 +1,90 @@
+"""Closed forms of the coupled-mode theory, used to pin the oracle.
+
+TEST INFRASTRUCTURE ONLY.  Part of the CPU oracle: only the tests, the
+smoke check and the CPU-baseline leg of the benchmark may import it.
+"""
+import numpy as np
+
+
+def h0(g, gamma=1.76e11):
+    """Feedback conversion factor h0 = 2 g / gamma [T], Sec. II A Eq. (5)."""
+    return 2.0 * g / gamma
+
+
+def polariton(wc, wm, g):
+    """Hermitian polariton branches, Sec. II B Eq. (6)."""
+    mid = 0.5 * (wc + wm)
+    half = np.sqrt(g * g + (0.5 * (wc - wm)) ** 2)
+    return mid - half, mid + half
+
+
+def polariton_complex(wc, kappa, wm, gamma_m, gt):
+    """Complex branches of (w - wc + i kappa)(w - wm + i gamma_m) = gt^2
+    (Sec. II B Eq. (7); Sec. IV H Eq. (20) with gt = g - i g_d)."""
+    wct = wc - 1j * kappa
+    wmt = wm - 1j * gamma_m
+    mid = 0.5 * (wct + wmt)
+    root = np.sqrt(gt * gt + (0.5 * (wct - wmt)) ** 2 + 0j)
+    return mid - root, mid + root
+
+
+def cooperativity(g, kappa, alpha, wm):
+    """C = g^2 / (kappa gamma_m), gamma_m = alpha w_m, Sec. II C Eq. (8)."""
+    return g * g / (kappa * alpha * wm)
+
+
+def kittel(B0, gamma=1.76e11):
+    """Uniform-precession frequency of a sphere, Sec. II D Eq. (9)."""
+    return gamma * B0
+
+
+def rabi_period(g):
+    """Vacuum Rabi period pi/g at resonance, Sec. IV B."""
+    return np.pi / g
+
+
+def three_mode(w1, wm, w2, g1, g2):
+    """Eigenvalues and eigenvectors of the 3x3 matrix of Sec. II E Eq. (14),
+    basis (|1>, |m>, |2>)."""
+    H = np.array([[w1, g1, 0.0], [g1, wm, g2], [0.0, g2, w2]])
+    return np.linalg.eigh(H)
+
+
+def afmr(BE, BA, gamma=1.76e11):
+    """Zero-field AFM resonance gamma sqrt(2 B_E B_A + B_A^2), Sec. II F
+    Eq. (15), fields in tesla (B = mu0 H)."""
+    return gamma * np.sqrt(2.0 * BE * BA + BA * BA)
+
+
+def afm_split(BE, BA, B, gamma=1.76e11):
+    """Field-split AFM branches w_AFMR -+ gamma B, Sec. II F Eq. (16)."""
+    w0 = afmr(BE, BA, gamma)
+    return w0 - gamma * B, w0 + gamma * B
+
+
+def overlap(u, G=None):
+    """<u> over the magnetic cells, Sec. II E Eq. (10)."""
+    if G is None:
+        return float(np.mean(u))
+    return float(np.sum(u * G) / np.sum(G))
+
+
+def rk4_stability(z):
+    """One-step amplification of classical RK4 on y' = z y / dt."""
+    return 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+
+
+def dp5_stability(z):
+    """5th-order Dormand-Prince stability polynomial."""
+    return 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24 + z ** 5 / 120 + z ** 6 / 600
+
+
+def dp4_stability(z):
+    """Embedded 4th-order Dormand-Prince stability polynomial."""
+    return (1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24 + 1097 / 120000 * z ** 5
+            + 161 / 120000 * z ** 6 + z ** 7 / 24000)
+
+
+def dp_error_polynomial(z):
+    """dp5_stability - dp4_stability written out, free of cancellation."""
+    return -97 / 120000 * z ** 5 + 39 / 120000 * z ** 6 - z ** 7 / 24000
