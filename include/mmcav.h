@@ -1,0 +1,201 @@
+/*
+ * mmcav.h -- C ABI of the MI355X stepper for the Landau-Lifshitz-Gilbert
+ * equation on a finite-difference cell grid coupled to N cavity modes
+ * (arXiv 2603.03706, "Multimode cavity magnonics in mumax+").
+ *
+ * What one step computes (all on the GPU, no host round trip per step):
+ *   - cavity modes (Sec. II A Eq. (1), Sec. II E Eq. (12); dissipative part
+ *     of Sec. IV H Eq. (19) written as a phase Phi_n):
+ *         da_n/dt = (-i w_n - k_n) a_n + i g_n e^{-i Phi_n} m^-_n
+ *   - mode-weighted co-rotating average (Eq. (2) weighted as in Eq. (18)):
+ *         m^-_n = 1/N_geo sum_i G_i u_n(r_i) (1/S) sum_s c_s (m_sx - i m_sy)
+ *   - RF feedback along x (Eq. (3), Eq. (13), h0_n = 2 g_n / gamma, Eq. (5)):
+ *         B_rf(r) = x c_s sum_n h0_n u_n(r) Re[e^{-i Phi_n} a_n]
+ *   - effective field: Zeeman + 6-neighbour exchange (free boundaries) +
+ *     uniaxial anisotropy + demag (none | local diagonal | cell-averaged
+ *     Newell tensor by zero-padded FFT convolution) + B_rf, and for two
+ *     sublattices the intersublattice field -B_E m_{s'}
+ *   - Landau-Lifshitz torque with gamma' = gamma / (1 + alpha^2)
+ *   - magnetisation and cavity advance inside one Runge-Kutta step
+ *     (Sec. III A: the cavity ODEs share the adaptive RK45 step of the LLG
+ *     equation): classical RK4 at a fixed step, or Dormand-Prince 5(4) with
+ *     a max-norm error over cells and modes; |m| renormalised after each
+ *     accepted step.
+ *
+ * Conventions
+ *   - SI units: m, A/m, J/m, J/m^3, T, s; rates w_n, k_n, g_n in rad/s.
+ *   - Host arrays are owned by the caller; set_* copy them in, get_* copy
+ *     out.  Device memory is owned by the library unless a workspace is
+ *     bound (mm_bind_workspace), in which case the caller owns it and must
+ *     keep it alive until mm_destroy.
+ *   - Cell index i = x + nx (y + ny z); per-sublattice vector fields are
+ *     laid out [S][3][nz][ny][nx] (component-major, x fastest).
+ *   - Every function returns an mm_status.  No C++ exception crosses the
+ *     boundary and the library never aborts.  After an error,
+ *     mm_last_error() describes it.  A failed mm_run leaves the state at the
+ *     last accepted step.
+ *   - One context per thread at a time.  Calls block until their GPU work
+ *     has finished.
+ */
+#ifndef MMCAV_H
+#define MMCAV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mm_ctx mm_ctx;
+typedef struct mm_batch mm_batch;
+
+typedef enum {
+  MM_OK = 0,
+  MM_ERR_ARG = -1,           /* invalid argument (value, size, pointer)      */
+  MM_ERR_HIP = -2,           /* HIP runtime error (no device, launch fault)  */
+  MM_ERR_OOM = -3,           /* device or host allocation failed             */
+  MM_ERR_STATE = -4,         /* call not valid in the current state          */
+  MM_ERR_DT_UNDERFLOW = -5,  /* adaptive step fell below dt_min              */
+  MM_ERR_NONFINITE = -6      /* state or error estimate became non-finite    */
+} mm_status;
+
+enum { MM_DEMAG_NONE = 0, MM_DEMAG_LOCAL = 1, MM_DEMAG_FFT = 2 };
+enum { MM_RK4 = 0, MM_DP45 = 1 };
+enum { MM_MAX_MODES = 16 };
+
+typedef struct {
+  int32_t nx, ny, nz;          /* grid, each >= 1                              */
+  double dx, dy, dz;           /* cell size [m], > 0                           */
+  double Ms;                   /* saturation magnetisation per sublattice [A/m] */
+  double Aex;                  /* exchange stiffness [J/m]                     */
+  double alpha;                /* Gilbert damping, >= 0                        */
+  double Ku;                   /* uniaxial anisotropy constant [J/m^3]         */
+  double ku_axis[3];           /* anisotropy axis (normalised internally)      */
+  double gamma;                /* gyromagnetic ratio [rad/(s T)], e.g. 1.76e11 */
+  double B0[3];                /* bias field [T]                               */
+  int32_t demag;               /* MM_DEMAG_*                                   */
+  double n_local[3];           /* diagonal of the local demag tensor           */
+  const uint8_t* geometry;     /* host, nx*ny*nz, nonzero = magnetic; NULL = all */
+  int32_t sublattices;         /* 1 (ferromagnet) or 2 (antiferromagnet)       */
+  double B_E;                  /* intersublattice exchange field [T] (S = 2)   */
+} mm_params;
+
+typedef struct {
+  int64_t accepted, rejected;
+  double t;                    /* simulated time [s]                           */
+  double dt;                   /* current (next proposed) step [s]             */
+  double dt_min_seen, dt_max_seen;  /* over accepted steps                     */
+  double wall_s;               /* wall time spent in mm_run / mm_batch_run     */
+  int32_t status;              /* last run's mm_status                         */
+} mm_stats;
+
+/* Create a context for one instance.  Validates the parameters (grid >= 1,
+ * cells > 0, Ms > 0, gamma > 0, alpha >= 0, demag in range, sublattices in
+ * {1, 2}; FFT demag needs sublattices == 1 and padded sizes <= 1024) and
+ * copies the geometry.  Allocates no device memory.  *out is set only on
+ * success. */
+mm_status mm_create(const mm_params* p, mm_ctx** out);
+
+/* Release all resources of the context.  NULL is accepted. */
+mm_status mm_destroy(mm_ctx* ctx);
+
+/* Device bytes this instance needs for n_modes modes, so a caller can hand
+ * over its own memory (e.g. a torch tensor) with mm_bind_workspace. */
+mm_status mm_workspace_bytes(const mm_params* p, int32_t n_modes, size_t* bytes);
+
+/* Use caller-owned device memory (at least mm_workspace_bytes for the mode
+ * count that mm_set_modes will be given, 256-byte aligned) for all
+ * per-instance device buffers.  Must precede the first mm_set_modes. */
+mm_status mm_bind_workspace(mm_ctx* ctx, void* device_ptr, size_t bytes);
+
+/* Launch the context's work on this HIP stream (default: a stream owned by
+ * the library).  Work submitted by the library waits for work already on
+ * the stream and has finished when the call returns. */
+mm_status mm_set_stream(mm_ctx* ctx, void* hip_stream);
+
+/* Cavity modes (Sec. II E): n in [0, MM_MAX_MODES]; omega, kappa, g [rad/s]
+ * (kappa >= 0); u: host [n][nz][ny][nx] mode profiles, or NULL for u = 1;
+ * phi: dissipative phase per mode [rad] or NULL for 0; sublattice_sign:
+ * c_s per sublattice (+1/-1) or NULL for +1.  h0_n = 2 g_n / gamma is
+ * derived here.  Resets the cavity amplitudes to 0 and the trace. */
+mm_status mm_set_modes(mm_ctx* ctx, int32_t n, const double* omega, const double* kappa,
+                       const double* g, const float* u, const double* phi,
+                       const int8_t* sublattice_sign);
+
+/* Magnetisation, host [S][3][nz][ny][nx].  Normalised per cell on entry;
+ * non-magnetic cells are set to 0.  A magnetic cell with |m| = 0 or a
+ * non-finite value is rejected with MM_ERR_ARG. */
+mm_status mm_set_m(mm_ctx* ctx, const float* m);
+
+/* Cavity amplitudes, host [n][2] (re, im) in FP64. */
+mm_status mm_set_a(mm_ctx* ctx, const double* a);
+
+/* Stepper: method MM_RK4 (fixed step dt0) or MM_DP45 (adaptive, first trial
+ * step dt0); dt_min (> 0) ends an adaptive run with MM_ERR_DT_UNDERFLOW when
+ * the step would fall below it; dt_max caps the step (<= 0: no cap). */
+mm_status mm_set_stepper(mm_ctx* ctx, int32_t method, double dt0, double dt_min, double dt_max);
+
+/* Record a(t_k) and m^-(t_k) at t_k = t_start + k dt_sample into a device
+ * trace of at most max_samples entries, starting at the next run.  DP45:
+ * cubic Hermite interpolation over each accepted step.  RK4: dt_sample must
+ * be a whole multiple of dt0 (relative slack 1e-9) and samples are step-end
+ * values.  max_samples = 0 switches sampling off. */
+mm_status mm_set_sampling(mm_ctx* ctx, double dt_sample, int64_t max_samples);
+
+/* Advance by T > 0 seconds.  tol > 0 is the DP45 error tolerance (ignored
+ * for RK4).  The last step is clipped to land on t + T.  Returns MM_OK,
+ * MM_ERR_DT_UNDERFLOW or MM_ERR_NONFINITE (state kept at the last accepted
+ * step), or an argument/HIP error. */
+mm_status mm_run(mm_ctx* ctx, double T, double tol);
+
+/* Copy out m [S][3][nz][ny][nx] (FP32) and a [n][2] (FP64). */
+mm_status mm_get_m(const mm_ctx* ctx, float* out);
+mm_status mm_get_a(const mm_ctx* ctx, double* out);
+
+/* Copy out the trace: t [n], a [n][modes][2], mminus [n][modes][2]; *n is
+ * in: capacity, out: samples recorded. */
+mm_status mm_get_trace(const mm_ctx* ctx, double* t, double* a, double* mminus, int64_t* n);
+
+mm_status mm_get_stats(const mm_ctx* ctx, mm_stats* out);
+
+/* Checkpoint / resume: serialise (m, a, t, dt, counters) into blob.  Call
+ * with blob = NULL to query *bytes. */
+mm_status mm_get_state(const mm_ctx* ctx, void* blob, size_t* bytes);
+mm_status mm_set_state(mm_ctx* ctx, const void* blob, size_t bytes);
+
+/* ---- batched form: many instances stepped together ------------------- */
+/* Group count >= 1 contexts (all with modes set and the same method).  The
+ * contexts stay owned by the caller and must outlive the batch.  Each
+ * instance keeps its own t, dt, status and trace; one launch sequence
+ * (captured in a HIP graph) advances all of them. */
+mm_status mm_batch_create(mm_ctx* const* ctxs, int32_t count, mm_batch** out);
+/* Advance every instance by T (tol as in mm_run).  Returns the first
+ * non-OK instance status, or MM_OK; per-instance status in mm_get_stats. */
+mm_status mm_batch_run(mm_batch* b, double T, double tol);
+/* Advance every unfinished instance by exactly `steps` attempted steps from
+ * its current state (t_end = +inf), for throughput measurement. */
+mm_status mm_batch_step(mm_batch* b, int64_t steps, double tol);
+mm_status mm_batch_destroy(mm_batch* b);
+
+/* Per-kernel timing: run `steps` steps eagerly, timing each launch with HIP
+ * events on the library stream.  Fills up to `cap` entries: names (each
+ * char[48]), launches, total milliseconds, algorithmic bytes per launch
+ * (the bytes a launch must read and write; see the kernel notes).  *n is
+ * set to the number of kernel kinds. */
+mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, char* names,
+                           int64_t* launches, double* total_ms, double* bytes_per_launch, int32_t* n);
+
+/* ---- host-side checks (no GPU needed) ------------------------------------ */
+/* Cell-averaged demag tensor (xx, yy, zz, xy, xz, yz) at displacement
+ * (X, Y, Z) [m] for cells dx*dy*dz, as the library's setup computes it. */
+mm_status mm_demag_tensor(double X, double Y, double Z, double dx, double dy, double dz,
+                          double* out6);
+
+/* Description of the last error on this thread (never NULL). */
+const char* mm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMCAV_H */

@@ -161,20 +161,29 @@ def padded_size(n):
     return p
 
 
+# parity of each component (xx, yy, zz, xy, xz, yz) under X -> -X, Y -> -Y, Z -> -Z
+PARITY = np.array([[1, 1, 1], [1, 1, 1], [1, 1, 1], [-1, -1, 1], [-1, 1, -1], [1, -1, -1]], float)
+
+
 def padded_kernel(grid, cell):
     """Real-space kernel on the zero-padded grid, components (xx, yy, zz, xy,
     xz, yz), array shape (6, Pz, Py, Px); displacement d is stored at index
-    d mod P for |d| < n."""
+    d mod P for |d| < n.  The tensor is evaluated on displacements >= 0 and
+    mirrored with the parity of each component."""
     nx, ny, nz = grid
     dx, dy, dz = cell
     px, py, pz = padded_size(nx), padded_size(ny), padded_size(nz)
+    Zg, Yg, Xg = np.meshgrid(np.arange(nz) * dz, np.arange(ny) * dy, np.arange(nx) * dx, indexing="ij")
+    octant = tensor(Xg, Yg, Zg, dx, dy, dz)                  # (6, nz, ny, nx)
+    K = np.zeros((6, pz, py, px))
     ix = np.arange(-(nx - 1), nx)
     iy = np.arange(-(ny - 1), ny)
     iz = np.arange(-(nz - 1), nz)
-    Zg, Yg, Xg = np.meshgrid(iz * dz, iy * dy, ix * dx, indexing="ij")
-    vals = tensor(Xg, Yg, Zg, dx, dy, dz)
-    K = np.zeros((6, pz, py, px))
-    K[:, (iz % pz)[:, None, None], (iy % py)[None, :, None], (ix % px)[None, None, :]] = vals
+    vals = octant[:, np.abs(iz)[:, None, None], np.abs(iy)[None, :, None], np.abs(ix)[None, None, :]]
+    sx = np.where(ix < 0, PARITY[:, 0:1], 1.0)[:, None, None, :]
+    sy = np.where(iy < 0, PARITY[:, 1:2], 1.0)[:, None, :, None]
+    sz = np.where(iz < 0, PARITY[:, 2:3], 1.0)[:, :, None, None]
+    K[:, (iz % pz)[:, None, None], (iy % py)[None, :, None], (ix % px)[None, None, :]] = vals * sx * sy * sz
     return K
 
 

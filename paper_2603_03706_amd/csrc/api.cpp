@@ -1,0 +1,1163 @@
+// C-ABI of the stepper: argument validation, device memory layout, run loop
+// (a HIP graph of K steps replayed until every instance is done), batching
+// and per-kernel timing.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mm_host.h"
+#include "mmcav.h"
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+mm_status fail(mm_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define MM_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return fail(MM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double kMu0 = 4e-7 * M_PI;
+constexpr int kStepsPerGraph = 32;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ------------------------------------------------------------ device state
+float2* g_twiddle = nullptr;  // e^{-2 pi i m / 1024}, m < 1024
+std::mutex g_mu;
+
+struct Spectrum {
+  int nx, ny, nz;
+  double dx, dy, dz;
+  float* dev = nullptr;
+  size_t count = 0;
+  int refs = 0;
+};
+std::vector<Spectrum*> g_spectra;
+
+mm_status ensure_twiddles() {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_twiddle) return MM_OK;
+  std::vector<float2> h(MMI_TW_LEN);
+  for (int m = 0; m < MMI_TW_LEN; ++m) {
+    const double a = -2.0 * M_PI * m / MMI_TW_LEN;
+    h[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  MM_HIP(hipMalloc(&g_twiddle, sizeof(float2) * MMI_TW_LEN));
+  MM_HIP(hipMemcpy(g_twiddle, h.data(), sizeof(float2) * MMI_TW_LEN, hipMemcpyHostToDevice));
+  MM_HIP(mmk_set_lds_limits());
+  return MM_OK;
+}
+
+mm_status acquire_spectrum(const mm_params& p, Spectrum** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (Spectrum* s : g_spectra)
+    if (s->nx == p.nx && s->ny == p.ny && s->nz == p.nz && s->dx == p.dx && s->dy == p.dy &&
+        s->dz == p.dz) {
+      s->refs++;
+      *out = s;
+      return MM_OK;
+    }
+  std::vector<float> h;
+  mmh::kernel_spectrum(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, h);
+  auto* s = new Spectrum{p.nx, p.ny, p.nz, p.dx, p.dy, p.dz};
+  s->count = h.size();
+  hipError_t e = hipMalloc(&s->dev, sizeof(float) * h.size());
+  if (e != hipSuccess) {
+    delete s;
+    return fail(MM_ERR_OOM, "demag kernel allocation failed");
+  }
+  e = hipMemcpy(s->dev, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(s->dev);
+    delete s;
+    return fail(MM_ERR_HIP, std::string("demag kernel upload: ") + hipGetErrorString(e));
+  }
+  s->refs = 1;
+  g_spectra.push_back(s);
+  *out = s;
+  return MM_OK;
+}
+
+void release_spectrum(Spectrum* s) {
+  if (!s) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (--s->refs == 0) {
+    hipFree(s->dev);
+    g_spectra.erase(std::find(g_spectra.begin(), g_spectra.end(), s));
+    delete s;
+  }
+}
+
+// --------------------------------------------------------------- layout
+struct Layout {
+  size_t ctl, ticket, y[2], k[7], st[2], geom, partials, bd, fx, fy, u, fixed_end, total;
+  int ncell, nwg, S, px, py, pz, kx;
+  bool fft, split;
+};
+
+bool fused_fits(int py, int pz) {
+  const size_t lds = sizeof(float2) * ((size_t)3 * pz * (py + 1) + py + pz);
+  return lds <= 160 * 1024;
+}
+
+Layout make_layout(const mm_params& p, int n_modes) {
+  Layout L{};
+  L.ncell = p.nx * p.ny * p.nz;
+  L.nwg = (L.ncell + MMI_WG - 1) / MMI_WG;
+  L.S = p.sublattices;
+  L.fft = p.demag == MM_DEMAG_FFT;
+  L.px = mmh::padded(p.nx);
+  L.py = mmh::padded(p.ny);
+  L.pz = mmh::padded(p.nz);
+  L.kx = L.px / 2 + 1;
+  L.split = L.fft && !fused_fits(L.py, L.pz);
+  const size_t vec = align_up(sizeof(float) * 3 * L.S * (size_t)L.ncell);
+  size_t o = 0;
+  L.ctl = o; o += align_up(sizeof(InstCtl));
+  L.ticket = o; o += kAlign;
+  for (int i = 0; i < 2; ++i) { L.y[i] = o; o += vec; }
+  for (int i = 0; i < 7; ++i) { L.k[i] = o; o += vec; }
+  for (int i = 0; i < 2; ++i) { L.st[i] = o; o += vec; }
+  L.geom = o; o += p.geometry ? align_up(L.ncell) : 0;
+  L.partials = o; o += align_up(sizeof(double) * MMI_PSTRIDE * (size_t)L.nwg);
+  if (L.fft) {
+    L.bd = o; o += align_up(sizeof(float) * 3 * (size_t)L.ncell);
+    L.fx = o; o += align_up(sizeof(float2) * (size_t)L.kx * 3 * p.nz * p.ny);
+    if (L.split) { L.fy = o; o += align_up(sizeof(float2) * (size_t)L.kx * 3 * p.nz * L.py); }
+  }
+  L.fixed_end = o;
+  L.u = o;
+  o += align_up(sizeof(float) * (size_t)std::max(0, n_modes) * L.ncell);
+  L.total = o;
+  return L;
+}
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+mm_status validate(const mm_params* p) {
+  if (!p) return fail(MM_ERR_ARG, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(MM_ERR_ARG, "grid sizes must be >= 1");
+  if ((long long)p->nx * p->ny * p->nz > (1LL << 30)) return fail(MM_ERR_ARG, "grid too large");
+  if (!(p->dx > 0 && p->dy > 0 && p->dz > 0) || !std::isfinite(p->dx * p->dy * p->dz))
+    return fail(MM_ERR_ARG, "cell sizes must be finite and > 0");
+  if (!(p->Ms > 0) || !std::isfinite(p->Ms)) return fail(MM_ERR_ARG, "Ms must be > 0");
+  if (!(p->gamma > 0) || !std::isfinite(p->gamma)) return fail(MM_ERR_ARG, "gamma must be > 0");
+  if (!(p->alpha >= 0) || !std::isfinite(p->alpha)) return fail(MM_ERR_ARG, "alpha must be >= 0");
+  if (!std::isfinite(p->Aex) || !std::isfinite(p->Ku) || !finite3(p->ku_axis) || !finite3(p->B0) ||
+      !finite3(p->n_local) || !std::isfinite(p->B_E))
+    return fail(MM_ERR_ARG, "non-finite material parameter");
+  if (p->demag < MM_DEMAG_NONE || p->demag > MM_DEMAG_FFT) return fail(MM_ERR_ARG, "demag mode out of range");
+  if (p->sublattices != 1 && p->sublattices != 2) return fail(MM_ERR_ARG, "sublattices must be 1 or 2");
+  if (p->demag == MM_DEMAG_FFT) {
+    if (p->sublattices != 1) return fail(MM_ERR_ARG, "FFT demag needs sublattices == 1");
+    if (mmh::padded(p->nx) > MMI_TW_LEN || mmh::padded(p->ny) > MMI_TW_LEN || mmh::padded(p->nz) > MMI_TW_LEN)
+      return fail(MM_ERR_ARG, "FFT demag supports grids up to 512 cells per axis");
+  }
+  if (p->geometry) {
+    long long n = 0;
+    const long long nc = (long long)p->nx * p->ny * p->nz;
+    for (long long i = 0; i < nc; ++i) n += p->geometry[i] != 0;
+    if (n == 0) return fail(MM_ERR_ARG, "geometry has no magnetic cell");
+  }
+  return MM_OK;
+}
+
+}  // namespace
+
+// ================================================================== context
+struct mm_ctx {
+  mm_params p{};
+  std::vector<uint8_t> geom;
+  long long n_geo = 0;
+  int dev = 0;
+  Layout L{};
+  // modes
+  int N = 0;
+  bool modes_set = false;
+  bool profiled = false;
+  std::vector<double> omega, kappa, g, phi;
+  int8_t cs[2] = {1, 1};
+  // stepper
+  int method = MM_RK4;
+  double dt0 = 1e-13, dt_min = 1e-18, dt_max = 0.0;
+  // sampling
+  double dt_sample = 0.0;
+  int64_t max_samples = 0;
+  bool sampling_changed = false;
+  // device memory
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool ws_bound = false;
+  bool dev_ready = false;
+  int u_cap = 0;
+  float* u_own = nullptr;        // library-owned mode profiles (no bound workspace)
+  double* trace = nullptr;       // library-owned trace buffer
+  int64_t trace_cap = 0;
+  Spectrum* spec = nullptr;
+  bool m_set = false;
+  hipStream_t user_stream = nullptr;
+  mm_batch* solo = nullptr;      // batch of one for mm_run
+  unsigned version = 1;          // bumps when the descriptor changes
+  mm_stats stats{};
+  InstDesc desc{};
+};
+
+struct mm_batch {
+  std::vector<mm_ctx*> ctxs;
+  int method = MM_RK4;
+  hipStream_t stream = nullptr;
+  InstDesc* d_desc = nullptr;
+  int* d_wg = nullptr;
+  int total_wg = 0;
+  int* d_flags = nullptr;
+  int* h_flags = nullptr;
+  std::vector<unsigned> versions;
+  struct Group {
+    int nx, ny, nz, px, py, pz, kx;
+    bool split;
+    int Wx, Wy, TW;
+    WorkItem *xf = nullptr, *yz = nullptr, *y = nullptr, *zc = nullptr;
+    int n_xf = 0, n_yz = 0, n_y = 0, n_zc = 0;
+    size_t lds_xf = 0, lds_xi = 0, lds_yz = 0, lds_y = 0, lds_zc = 0;
+    std::vector<int> members;
+  };
+  std::vector<Group> groups;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipEvent_t ev = nullptr;
+  // profiling
+  bool profiling = false;
+  struct Prof { std::string name; long long launches = 0; double ms = 0.0; double bytes = 0.0; };
+  std::vector<Prof> prof;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<int> pending_idx;
+};
+
+namespace {
+
+mm_status upload_desc(mm_ctx* c);
+
+mm_status set_device(mm_ctx* c) {
+  MM_HIP(hipSetDevice(c->dev));
+  return MM_OK;
+}
+
+void init_ctl(mm_ctx* c, InstCtl& h) {
+  std::memset(&h, 0, sizeof(h));
+  for (int j = 0; j < 8; ++j) h.slot[j] = j;
+  h.dt = c->dt0;
+  h.dt_fixed = c->dt0;
+  h.dt_min = c->dt_min;
+  h.dt_max = c->dt_max;
+  h.dt_min_seen = INFINITY;
+  h.dt_max_seen = 0.0;
+}
+
+mm_status ctl_pull(const mm_ctx* c, InstCtl& h) {
+  MM_HIP(hipMemcpy(&h, c->ws + c->L.ctl, sizeof(InstCtl), hipMemcpyDeviceToHost));
+  return MM_OK;
+}
+
+mm_status ctl_push(mm_ctx* c, const InstCtl& h) {
+  MM_HIP(hipMemcpy(c->ws + c->L.ctl, &h, sizeof(InstCtl), hipMemcpyHostToDevice));
+  return MM_OK;
+}
+
+// Allocate (or adopt the bound workspace) and initialise device state.
+mm_status ensure_device(mm_ctx* c) {
+  if (c->dev_ready) return MM_OK;
+  if (mm_status s = set_device(c)) return s;
+  if (mm_status s = ensure_twiddles()) return s;
+  if (!c->ws_bound) {
+    const Layout L = make_layout(c->p, 0);
+    void* p = nullptr;
+    if (hipMalloc(&p, L.total) != hipSuccess) return fail(MM_ERR_OOM, "device allocation failed");
+    c->ws = (char*)p;
+    c->ws_bytes = L.total;
+  }
+  c->L = make_layout(c->p, c->u_cap);
+  char* w = c->ws;
+  MM_HIP(hipMemset(w, 0, c->L.fixed_end));
+  if (c->p.geometry) MM_HIP(hipMemcpy(w + c->L.geom, c->geom.data(), c->geom.size(), hipMemcpyHostToDevice));
+  if (c->p.demag == MM_DEMAG_FFT) {
+    if (mm_status s = acquire_spectrum(c->p, &c->spec)) return s;
+  }
+  InstCtl h;
+  init_ctl(c, h);
+  if (mm_status s = ctl_push(c, h)) return s;
+  c->dev_ready = true;
+  return upload_desc(c);
+}
+
+// Build the host copy of the descriptor (device pointers included).
+mm_status upload_desc(mm_ctx* c) {
+  InstDesc& d = c->desc;
+  std::memset(&d, 0, sizeof(d));
+  const mm_params& p = c->p;
+  const Layout& L = c->L;
+  d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.ncell = L.ncell;
+  d.S = p.sublattices; d.N = c->N; d.profiled = c->profiled ? 1 : 0; d.has_geom = p.geometry ? 1 : 0;
+  d.demag = p.demag; d.method = c->method; d.nwg = L.nwg; d.wg0 = 0;
+  const double cex = 2.0 * p.Aex / p.Ms;
+  d.cex_x = p.nx > 1 ? (float)(cex / (p.dx * p.dx)) : 0.f;
+  d.cex_y = p.ny > 1 ? (float)(cex / (p.dy * p.dy)) : 0.f;
+  d.cex_z = p.nz > 1 ? (float)(cex / (p.dz * p.dz)) : 0.f;
+  const double en = std::sqrt(p.ku_axis[0] * p.ku_axis[0] + p.ku_axis[1] * p.ku_axis[1] + p.ku_axis[2] * p.ku_axis[2]);
+  d.cK = en > 0 ? (float)(2.0 * p.Ku / p.Ms) : 0.f;
+  d.ex = en > 0 ? (float)(p.ku_axis[0] / en) : 0.f;
+  d.ey = en > 0 ? (float)(p.ku_axis[1] / en) : 0.f;
+  d.ez = en > 0 ? (float)(p.ku_axis[2] / en) : 0.f;
+  d.B0x = (float)p.B0[0]; d.B0y = (float)p.B0[1]; d.B0z = (float)p.B0[2];
+  d.nlx = (float)(-kMu0 * p.Ms * p.n_local[0]);
+  d.nly = (float)(-kMu0 * p.Ms * p.n_local[1]);
+  d.nlz = (float)(-kMu0 * p.Ms * p.n_local[2]);
+  d.BE = (float)p.B_E;
+  d.gl = (float)(p.gamma / (1.0 + p.alpha * p.alpha));
+  d.alpha = (float)p.alpha;
+  d.csign[0] = c->cs[0];
+  d.csign[1] = c->cs[1];
+  d.px = L.px; d.py = L.py; d.pz = L.pz; d.kx = L.kx;
+  d.bd_scale = (float)(-kMu0 * p.Ms / ((double)L.px * L.py * L.pz));
+  d.inv_ngeo = 1.0 / (double)c->n_geo;
+  for (int n = 0; n < c->N; ++n) {
+    d.omega[n] = c->omega[n];
+    d.kappa[n] = c->kappa[n];
+    d.g[n] = c->g[n];
+    d.cphi[n] = std::cos(c->phi[n]);
+    d.sphi[n] = std::sin(c->phi[n]);
+    d.h0[n] = 2.0 * c->g[n] / p.gamma;
+  }
+  char* w = c->ws;
+  for (int i = 0; i < 2; ++i) d.y[i] = (float*)(w + L.y[i]);
+  for (int i = 0; i < 7; ++i) d.k[i] = (float*)(w + L.k[i]);
+  for (int i = 0; i < 2; ++i) d.st[i] = (float*)(w + L.st[i]);
+  d.geom = p.geometry ? (const uint8_t*)(w + L.geom) : nullptr;
+  d.u = c->profiled ? (c->ws_bound ? (const float*)(w + L.u) : c->u_own) : nullptr;
+  d.partials = (double*)(w + L.partials);
+  d.ticket = (int*)(w + L.ticket);
+  d.ctl = (InstCtl*)(w + L.ctl);
+  if (c->trace) {
+    d.trace_t = c->trace;
+    d.trace_a = c->trace + c->trace_cap;
+    d.trace_m = c->trace + c->trace_cap * (1 + 2 * (int64_t)std::max(1, c->N));
+  }
+  if (L.fft) {
+    d.bd = (float*)(w + L.bd);
+    d.fx = (float2*)(w + L.fx);
+    d.fy = L.split ? (float2*)(w + L.fy) : nullptr;
+    d.kern = c->spec ? c->spec->dev : nullptr;
+  }
+  c->version++;
+  return MM_OK;
+}
+
+// ------------------------------------------------------------- batches
+double algorithmic_bytes(const mm_batch* b, const std::string& name);
+
+mm_status batch_build(mm_batch* b) {
+  const int n = (int)b->ctxs.size();
+  std::vector<InstDesc> descs(n);
+  std::vector<int> wg;
+  for (int i = 0; i < n; ++i) {
+    descs[i] = b->ctxs[i]->desc;
+    descs[i].wg0 = (int)wg.size();
+    for (int w = 0; w < descs[i].nwg; ++w) wg.push_back(i);
+  }
+  b->total_wg = (int)wg.size();
+  MM_HIP(hipMalloc(&b->d_desc, sizeof(InstDesc) * n));
+  MM_HIP(hipMemcpy(b->d_desc, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
+  MM_HIP(hipMalloc(&b->d_wg, sizeof(int) * wg.size()));
+  MM_HIP(hipMemcpy(b->d_wg, wg.data(), sizeof(int) * wg.size(), hipMemcpyHostToDevice));
+  MM_HIP(hipMalloc(&b->d_flags, sizeof(int) * 2 * n));
+  MM_HIP(hipHostMalloc((void**)&b->h_flags, sizeof(int) * 2 * n, hipHostMallocDefault));
+  b->versions.resize(n);
+  for (int i = 0; i < n; ++i) b->versions[i] = b->ctxs[i]->version;
+  // FFT groups by grid shape
+  for (int i = 0; i < n; ++i) {
+    const mm_ctx* c = b->ctxs[i];
+    if (c->p.demag != MM_DEMAG_FFT) continue;
+    mm_batch::Group* g = nullptr;
+    for (auto& q : b->groups)
+      if (q.nx == c->p.nx && q.ny == c->p.ny && q.nz == c->p.nz) g = &q;
+    if (!g) {
+      b->groups.emplace_back();
+      g = &b->groups.back();
+      g->nx = c->p.nx; g->ny = c->p.ny; g->nz = c->p.nz;
+      g->px = c->L.px; g->py = c->L.py; g->pz = c->L.pz; g->kx = c->L.kx;
+      g->split = c->L.split;
+    }
+    g->members.push_back(i);
+  }
+  for (auto& g : b->groups) {
+    g.Wx = std::max(1, std::min(32, 2048 / g.px));
+    g.Wy = std::max(1, std::min(64, 2048 / g.py));
+    int tw = 1;
+    while (tw * 2 <= 16 && 3 * (tw * 2) * g.pz <= 2048) tw *= 2;
+    g.TW = tw;
+    const int rows = 3 * g.ny * g.nz;
+    const int tiles_x = (rows + 2 * g.Wx - 1) / (2 * g.Wx);
+    std::vector<WorkItem> xf, yz, yy, zc;
+    const int ylines = g.kx * 3 * g.nz;
+    const int tiles_y = (ylines + g.Wy - 1) / g.Wy;
+    const int ky_tiles = (g.py + g.TW - 1) / g.TW;
+    for (int m : g.members) {
+      for (int t = 0; t < tiles_x; ++t) xf.push_back({m, t});
+      if (!g.split) {
+        for (int k = 0; k < g.kx; ++k) yz.push_back({m, k});
+      } else {
+        for (int t = 0; t < tiles_y; ++t) yy.push_back({m, t});
+        for (int k = 0; k < g.kx * ky_tiles; ++k) zc.push_back({m, k});
+      }
+    }
+    auto up = [&](std::vector<WorkItem>& v, WorkItem** dst, int* cnt) -> mm_status {
+      *cnt = (int)v.size();
+      if (v.empty()) return MM_OK;
+      MM_HIP(hipMalloc(dst, sizeof(WorkItem) * v.size()));
+      MM_HIP(hipMemcpy(*dst, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
+      return MM_OK;
+    };
+    if (mm_status s = up(xf, &g.xf, &g.n_xf)) return s;
+    if (mm_status s = up(yz, &g.yz, &g.n_yz)) return s;
+    if (mm_status s = up(yy, &g.y, &g.n_y)) return s;
+    if (mm_status s = up(zc, &g.zc, &g.n_zc)) return s;
+    g.lds_xf = sizeof(float2) * ((size_t)g.px * g.Wx + g.px);
+    g.lds_xi = sizeof(float2) * ((size_t)g.px * g.Wx + (size_t)g.kx * 2 * g.Wx + g.px);
+    g.lds_yz = sizeof(float2) * ((size_t)3 * g.pz * (g.py + 1) + g.py + g.pz);
+    g.lds_y = sizeof(float2) * ((size_t)g.py * g.Wy + g.py);
+    g.lds_zc = sizeof(float2) * ((size_t)g.pz * 3 * g.TW + g.pz);
+  }
+  MM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+  MM_HIP(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
+  return MM_OK;
+}
+
+mm_status refresh_descs(mm_batch* b) {
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    if (b->versions[i] == b->ctxs[i]->version) continue;
+    InstDesc d = b->ctxs[i]->desc;
+    int wg0 = 0;
+    for (size_t j = 0; j < i; ++j) wg0 += b->ctxs[j]->desc.nwg;
+    d.wg0 = wg0;
+    MM_HIP(hipMemcpy(b->d_desc + i, &d, sizeof(InstDesc), hipMemcpyHostToDevice));
+    b->versions[i] = b->ctxs[i]->version;
+  }
+  return MM_OK;
+}
+
+// Launch wrapper that times the launch when profiling.
+template <class F>
+mm_status launch(mm_batch* b, const char* name, F&& f) {
+  size_t idx = 0;
+  if (b->profiling) {
+    for (; idx < b->prof.size(); ++idx)
+      if (b->prof[idx].name == name) break;
+    if (idx == b->prof.size()) {
+      b->prof.push_back({name});
+      b->prof.back().bytes = algorithmic_bytes(b, name);
+    }
+    hipEvent_t e0, e1;
+    MM_HIP(hipEventCreate(&e0));
+    MM_HIP(hipEventCreate(&e1));
+    MM_HIP(hipEventRecord(e0, b->stream));
+    MM_HIP(f());
+    MM_HIP(hipEventRecord(e1, b->stream));
+    b->pending.push_back({e0, e1});
+    b->pending_idx.push_back((int)idx);
+    return MM_OK;
+  }
+  MM_HIP(f());
+  return MM_OK;
+}
+
+mm_status enqueue_demag(mm_batch* b, int stage) {
+  for (auto& g : b->groups) {
+    if (mm_status s = launch(b, "fft_x_forward", [&] {
+          return mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, b->method, stage, g_twiddle, b->stream);
+        }))
+      return s;
+    if (!g.split) {
+      if (mm_status s = launch(b, "fft_yz_convolve", [&] {
+            return mmk_launch_fft_yz(g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
+          }))
+        return s;
+    } else {
+      if (mm_status s = launch(b, "fft_y_forward", [&] {
+            return mmk_launch_fft_y(-1, g.Wy, g.n_y, g.lds_y, b->d_desc, g.y, g_twiddle, b->stream);
+          }))
+        return s;
+      if (mm_status s = launch(b, "fft_z_convolve", [&] {
+            return mmk_launch_fft_zc(g.TW, g.n_zc, g.lds_zc, b->d_desc, g.zc, g_twiddle, b->stream);
+          }))
+        return s;
+      if (mm_status s = launch(b, "fft_y_inverse", [&] {
+            return mmk_launch_fft_y(1, g.Wy, g.n_y, g.lds_y, b->d_desc, g.y, g_twiddle, b->stream);
+          }))
+        return s;
+    }
+    if (mm_status s = launch(b, "fft_x_inverse", [&] {
+          return mmk_launch_fft_xi(g.Wx, g.n_xf, g.lds_xi, b->d_desc, g.xf, g_twiddle, b->stream);
+        }))
+      return s;
+  }
+  return MM_OK;
+}
+
+const char* stage_name(int method, int st) {
+  static const char* rk[] = {"stage_rk4_start", "stage_rk4_1", "stage_rk4_2", "stage_rk4_3", "stage_rk4_4"};
+  static const char* dp[] = {"", "stage_dp45_1", "stage_dp45_2", "stage_dp45_3", "stage_dp45_4",
+                             "stage_dp45_5", "stage_dp45_6", "stage_dp45_7"};
+  return method == MM_RK4 ? rk[st] : dp[st];
+}
+
+mm_status enqueue_stage(mm_batch* b, int st) {
+  return launch(b, stage_name(b->method, st), [&] {
+    return mmk_launch_stage(b->method, st, b->total_wg, b->d_desc, b->d_wg, b->stream);
+  });
+}
+
+mm_status enqueue_start(mm_batch* b) {
+  if (b->method == MM_RK4) return enqueue_stage(b, 0);
+  if (mm_status s = enqueue_demag(b, 1)) return s;
+  return enqueue_stage(b, 1);
+}
+
+mm_status enqueue_step(mm_batch* b) {
+  const int s0 = b->method == MM_RK4 ? 1 : 2;
+  const int s1 = b->method == MM_RK4 ? 4 : 7;
+  for (int st = s0; st <= s1; ++st) {
+    if (mm_status s = enqueue_demag(b, st)) return s;
+    if (mm_status s = enqueue_stage(b, st)) return s;
+  }
+  return MM_OK;
+}
+
+mm_status ensure_graph(mm_batch* b) {
+  if (b->exec) return MM_OK;
+  MM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  mm_status st = MM_OK;
+  for (int k = 0; k < kStepsPerGraph && st == MM_OK; ++k) st = enqueue_step(b);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (st != MM_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(MM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  b->graph = g;
+  MM_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  return MM_OK;
+}
+
+mm_status wait_user_streams(mm_batch* b) {
+  for (mm_ctx* c : b->ctxs)
+    if (c->user_stream) {
+      MM_HIP(hipEventRecord(b->ev, c->user_stream));
+      MM_HIP(hipStreamWaitEvent(b->stream, b->ev, 0));
+    }
+  return MM_OK;
+}
+
+mm_status check_ready(mm_ctx* c) {
+  if (!c->modes_set) return fail(MM_ERR_STATE, "modes not set (mm_set_modes)");
+  if (!c->m_set) return fail(MM_ERR_STATE, "magnetisation not set (mm_set_m)");
+  return MM_OK;
+}
+
+// Set run parameters of every instance; t_end = t + T (T <= 0: unbounded).
+mm_status begin_run(mm_batch* b, double T, double tol) {
+  for (mm_ctx* c : b->ctxs) {
+    InstCtl h;
+    if (mm_status s = ctl_pull(c, h)) return s;
+    h.t_end = T > 0 ? h.t + T : 1e300;
+    h.tol = tol;
+    h.dt_fixed = c->dt0;
+    h.dt_min = c->dt_min;
+    h.dt_max = c->dt_max;
+    h.done = 0;
+    h.status = 0;
+    if (c->sampling_changed) {
+      c->sampling_changed = false;
+      h.trace_on = c->max_samples > 0 ? 1 : 0;
+      h.trace_started = 0;
+      h.trace_n = 0;
+      h.trace_steps = 0;
+      h.trace_max = c->max_samples;
+      h.trace_dt = c->dt_sample;
+      h.trace_stride = c->method == MM_RK4 ? std::max<long long>(1, llround(c->dt_sample / c->dt0)) : 1;
+    }
+    if (mm_status s = ctl_push(c, h)) return s;
+  }
+  if (mm_status s = refresh_descs(b)) return s;
+  if (mm_status s = wait_user_streams(b)) return s;
+  return enqueue_start(b);
+}
+
+mm_status end_run(mm_batch* b, double wall) {
+  MM_HIP(hipStreamSynchronize(b->stream));
+  mm_status first = MM_OK;
+  for (mm_ctx* c : b->ctxs) {
+    InstCtl h;
+    if (mm_status s = ctl_pull(c, h)) return s;
+    c->stats.accepted = h.accepted;
+    c->stats.rejected = h.rejected;
+    c->stats.t = h.t;
+    c->stats.dt = c->method == MM_RK4 ? h.dt_fixed : h.dt;
+    c->stats.dt_min_seen = h.dt_min_seen;
+    c->stats.dt_max_seen = h.dt_max_seen;
+    c->stats.wall_s = wall;
+    c->stats.status = h.status;
+    if (h.status != 0 && first == MM_OK) first = (mm_status)h.status;
+  }
+  if (first == MM_ERR_DT_UNDERFLOW) return fail(first, "adaptive step fell below dt_min");
+  if (first == MM_ERR_NONFINITE) return fail(first, "state became non-finite");
+  return first;
+}
+
+mm_status batch_run(mm_batch* b, double T, double tol) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (mm_status s = begin_run(b, T, tol)) return s;
+  if (mm_status s = ensure_graph(b)) return s;
+  const int n = (int)b->ctxs.size();
+  for (;;) {
+    MM_HIP(hipGraphLaunch(b->exec, b->stream));
+    MM_HIP(mmk_launch_gather_done(n, b->d_desc, b->d_flags, b->stream));
+    MM_HIP(hipMemcpyAsync(b->h_flags, b->d_flags, sizeof(int) * 2 * n, hipMemcpyDeviceToHost, b->stream));
+    MM_HIP(hipStreamSynchronize(b->stream));
+    bool all = true;
+    for (int i = 0; i < n; ++i) all = all && b->h_flags[2 * i] != 0;
+    if (all) break;
+  }
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return end_run(b, wall);
+}
+
+mm_status validate_tol(const mm_batch* b, double tol) {
+  if (b->method == MM_DP45 && !(tol > 0 && std::isfinite(tol)))
+    return fail(MM_ERR_ARG, "DP45 needs a finite tol > 0");
+  return MM_OK;
+}
+
+mm_status new_batch(mm_ctx* const* ctxs, int count, mm_batch** out) {
+  auto* b = new mm_batch();
+  b->ctxs.assign(ctxs, ctxs + count);
+  b->method = ctxs[0]->method;
+  if (mm_status s = batch_build(b)) {
+    mm_batch_destroy(b);
+    return s;
+  }
+  *out = b;
+  return MM_OK;
+}
+
+double algorithmic_bytes(const mm_batch* b, const std::string& name) {
+  double total = 0.0;
+  const bool is_stage = name.rfind("stage_", 0) == 0;
+  int st = 0;
+  if (is_stage) st = name.back() - '0';
+  for (size_t gi = 0; gi < b->groups.size() || is_stage; ++gi) {
+    if (is_stage) {
+      for (const mm_ctx* c : b->ctxs) {
+        const double cells = (double)c->L.ncell * c->p.sublattices;
+        double rd = 0, wr = 0;
+        if (b->method == MM_RK4) {
+          if (name == "stage_rk4_start") { rd = 12; wr = 0; }
+          else if (st == 1) { rd = 12; wr = 24; }
+          else if (st == 2 || st == 3) { rd = 36; wr = 24; }
+          else { rd = 36; wr = 12; }
+        } else {
+          static const double R[8] = {0, 12, 24, 48, 60, 72, 72, 72};
+          static const double Wt[8] = {0, 12, 24, 24, 24, 24, 24, 12};
+          rd = R[st];
+          wr = Wt[st];
+        }
+        double extra = (double)c->L.ncell * ((c->p.geometry ? 1.0 : 0.0) + (c->profiled ? 4.0 * c->N : 0.0) +
+                                             (c->p.demag == MM_DEMAG_FFT && name != "stage_rk4_start" ? 12.0 : 0.0));
+        total += cells * (rd + wr) + extra;
+      }
+      break;
+    }
+    const auto& g = b->groups[gi];
+    const double m = (double)g.members.size();
+    const double cells = (double)g.nx * g.ny * g.nz;
+    const double X = 8.0 * g.kx * 3.0 * g.ny * g.nz;       // complex after the x pass
+    const double Y = 8.0 * g.kx * 3.0 * g.nz * g.py;       // complex after the y pass
+    const double kern = 4.0 * 6.0 * (g.pz / 2 + 1) * (g.py / 2 + 1) * g.kx;
+    if (name == "fft_x_forward") total += m * (12.0 * cells + X);
+    if (name == "fft_x_inverse") total += m * (X + 12.0 * cells);
+    if (name == "fft_yz_convolve") total += m * 2.0 * X + kern;
+    if (name == "fft_y_forward" || name == "fft_y_inverse") total += m * (X + Y);
+    if (name == "fft_z_convolve") total += m * 2.0 * Y + kern;
+  }
+  return total;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* mm_last_error(void) { return g_err.c_str(); }
+
+mm_status mm_demag_tensor(double X, double Y, double Z, double dx, double dy, double dz, double* out6) {
+  if (!out6) return fail(MM_ERR_ARG, "out6 is NULL");
+  if (!(dx > 0 && dy > 0 && dz > 0)) return fail(MM_ERR_ARG, "cell sizes must be > 0");
+  if (!std::isfinite(X) || !std::isfinite(Y) || !std::isfinite(Z)) return fail(MM_ERR_ARG, "non-finite displacement");
+  mmh::demag_tensor(X, Y, Z, dx, dy, dz, out6);
+  return MM_OK;
+}
+
+mm_status mm_create(const mm_params* p, mm_ctx** out) {
+  if (!out) return fail(MM_ERR_ARG, "out is NULL");
+  if (mm_status s = validate(p)) return s;
+  auto* c = new (std::nothrow) mm_ctx();
+  if (!c) return fail(MM_ERR_OOM, "host allocation failed");
+  c->p = *p;
+  const size_t nc = (size_t)p->nx * p->ny * p->nz;
+  if (p->geometry) {
+    c->geom.assign(p->geometry, p->geometry + nc);
+    for (auto& v : c->geom) v = v ? 1 : 0;
+    c->p.geometry = c->geom.data();
+    c->n_geo = 0;
+    for (auto v : c->geom) c->n_geo += v;
+  } else {
+    c->n_geo = (long long)nc;
+  }
+  c->L = make_layout(c->p, 0);
+  hipError_t e = hipGetDevice(&c->dev);
+  if (e != hipSuccess) c->dev = 0;
+  c->stats.dt_min_seen = INFINITY;
+  *out = c;
+  return MM_OK;
+}
+
+mm_status mm_destroy(mm_ctx* c) {
+  if (!c) return MM_OK;
+  if (c->solo) mm_batch_destroy(c->solo);
+  if (c->dev_ready || c->ws) hipSetDevice(c->dev);
+  if (!c->ws_bound && c->ws) hipFree(c->ws);
+  if (c->u_own) hipFree(c->u_own);
+  if (c->trace) hipFree(c->trace);
+  release_spectrum(c->spec);
+  delete c;
+  return MM_OK;
+}
+
+mm_status mm_workspace_bytes(const mm_params* p, int32_t n_modes, size_t* bytes) {
+  if (!bytes) return fail(MM_ERR_ARG, "bytes is NULL");
+  if (mm_status s = validate(p)) return s;
+  if (n_modes < 0 || n_modes > MM_MAX_MODES) return fail(MM_ERR_ARG, "n_modes out of range");
+  *bytes = make_layout(*p, n_modes).total;
+  return MM_OK;
+}
+
+mm_status mm_bind_workspace(mm_ctx* c, void* ptr, size_t bytes) {
+  if (!c || !ptr) return fail(MM_ERR_ARG, "NULL context or pointer");
+  if (c->dev_ready) return fail(MM_ERR_STATE, "device memory already in use; bind before mm_set_modes");
+  if (((uintptr_t)ptr) % kAlign) return fail(MM_ERR_ARG, "workspace must be 256-byte aligned");
+  const Layout L0 = make_layout(c->p, 0);
+  if (bytes < L0.total) return fail(MM_ERR_ARG, "workspace too small");
+  const size_t per_mode = align_up(sizeof(float) * (size_t)L0.ncell);
+  c->u_cap = (int)std::min<size_t>(MM_MAX_MODES, (bytes - L0.total) / per_mode);
+  while (c->u_cap > 0 && make_layout(c->p, c->u_cap).total > bytes) c->u_cap--;
+  c->ws = (char*)ptr;
+  c->ws_bytes = bytes;
+  c->ws_bound = true;
+  return MM_OK;
+}
+
+mm_status mm_set_stream(mm_ctx* c, void* stream) {
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  c->user_stream = (hipStream_t)stream;
+  return MM_OK;
+}
+
+mm_status mm_set_modes(mm_ctx* c, int32_t n, const double* omega, const double* kappa, const double* g,
+                       const float* u, const double* phi, const int8_t* sign) {
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  if (n < 0 || n > MM_MAX_MODES) return fail(MM_ERR_ARG, "mode count out of range");
+  if (n > 0 && (!omega || !kappa || !g)) return fail(MM_ERR_ARG, "omega, kappa and g are required");
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(omega[i]) || !std::isfinite(g[i]) || !(kappa[i] >= 0) || !std::isfinite(kappa[i]))
+      return fail(MM_ERR_ARG, "mode parameters must be finite with kappa >= 0");
+    if (phi && !std::isfinite(phi[i])) return fail(MM_ERR_ARG, "non-finite phase");
+  }
+  const int S = c->p.sublattices;
+  if (sign)
+    for (int s = 0; s < S; ++s)
+      if (sign[s] != 1 && sign[s] != -1) return fail(MM_ERR_ARG, "sublattice signs must be +1 or -1");
+  const size_t nc = (size_t)c->L.ncell;
+  if (u)
+    for (size_t i = 0; i < (size_t)n * nc; ++i)
+      if (!std::isfinite(u[i])) return fail(MM_ERR_ARG, "non-finite mode profile");
+  if (c->ws_bound && u && n > c->u_cap) return fail(MM_ERR_ARG, "bound workspace has no room for the mode profiles");
+  if (mm_status s = ensure_device(c)) return s;
+  c->N = n;
+  c->omega.assign(omega, omega + n);
+  c->kappa.assign(kappa, kappa + n);
+  c->g.assign(g, g + n);
+  c->phi.assign(n, 0.0);
+  if (phi) c->phi.assign(phi, phi + n);
+  c->cs[0] = c->cs[1] = 1;
+  if (sign)
+    for (int s = 0; s < S; ++s) c->cs[s] = sign[s];
+  c->profiled = u != nullptr && n > 0;
+  if (c->profiled) {
+    float* dst;
+    if (c->ws_bound) {
+      dst = (float*)(c->ws + c->L.u);
+    } else {
+      if (c->u_own) hipFree(c->u_own);
+      c->u_own = nullptr;
+      if (hipMalloc(&c->u_own, sizeof(float) * n * nc) != hipSuccess) return fail(MM_ERR_OOM, "mode profile allocation failed");
+      dst = c->u_own;
+    }
+    MM_HIP(hipMemcpy(dst, u, sizeof(float) * n * nc, hipMemcpyHostToDevice));
+  }
+  InstCtl h;
+  if (mm_status s = ctl_pull(c, h)) return s;
+  std::memset(h.a, 0, sizeof(h.a));
+  h.trace_n = 0;
+  h.trace_started = 0;
+  if (mm_status s = ctl_push(c, h)) return s;
+  c->modes_set = true;
+  if (c->trace) {  // trace layout depends on N
+    hipFree(c->trace);
+    c->trace = nullptr;
+    c->trace_cap = 0;
+    if (c->max_samples > 0) {
+      const size_t cnt = (size_t)c->max_samples * (1 + 4 * (size_t)std::max(1, n));
+      if (hipMalloc(&c->trace, sizeof(double) * cnt) != hipSuccess) return fail(MM_ERR_OOM, "trace allocation failed");
+      c->trace_cap = c->max_samples;
+      c->sampling_changed = true;
+    }
+  }
+  return upload_desc(c);
+}
+
+mm_status mm_set_m(mm_ctx* c, const float* m) {
+  if (!c || !m) return fail(MM_ERR_ARG, "NULL argument");
+  const size_t nc = (size_t)c->L.ncell;
+  const int S = c->p.sublattices;
+  std::vector<float> h((size_t)3 * S * nc);
+  for (int s = 0; s < S; ++s)
+    for (size_t i = 0; i < nc; ++i) {
+      const bool mag = !c->p.geometry || c->geom[i];
+      double v[3];
+      for (int q = 0; q < 3; ++q) v[q] = m[((size_t)s * 3 + q) * nc + i];
+      if (!mag) {
+        for (int q = 0; q < 3; ++q) h[((size_t)s * 3 + q) * nc + i] = 0.f;
+        continue;
+      }
+      const double nrm = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+      if (!(nrm > 0) || !std::isfinite(nrm)) return fail(MM_ERR_ARG, "magnetic cell with zero or non-finite m");
+      for (int q = 0; q < 3; ++q) h[((size_t)s * 3 + q) * nc + i] = (float)(v[q] / nrm);
+    }
+  if (mm_status s = ensure_device(c)) return s;
+  InstCtl ctl;
+  if (mm_status s = ctl_pull(c, ctl)) return s;
+  MM_HIP(hipMemcpy(c->ws + c->L.y[ctl.cur], h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice));
+  c->m_set = true;
+  return MM_OK;
+}
+
+mm_status mm_set_a(mm_ctx* c, const double* a) {
+  if (!c || !a) return fail(MM_ERR_ARG, "NULL argument");
+  if (!c->modes_set) return fail(MM_ERR_STATE, "modes not set");
+  for (int i = 0; i < 2 * c->N; ++i)
+    if (!std::isfinite(a[i])) return fail(MM_ERR_ARG, "non-finite cavity amplitude");
+  InstCtl h;
+  if (mm_status s = ctl_pull(c, h)) return s;
+  for (int n = 0; n < c->N; ++n) {
+    h.a[n][0] = a[2 * n];
+    h.a[n][1] = a[2 * n + 1];
+  }
+  return ctl_push(c, h);
+}
+
+mm_status mm_set_stepper(mm_ctx* c, int32_t method, double dt0, double dt_min, double dt_max) {
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  if (method != MM_RK4 && method != MM_DP45) return fail(MM_ERR_ARG, "unknown method");
+  if (!(dt0 > 0) || !std::isfinite(dt0)) return fail(MM_ERR_ARG, "dt0 must be > 0");
+  if (!(dt_min > 0) || !std::isfinite(dt_min) || dt_min > dt0) return fail(MM_ERR_ARG, "need 0 < dt_min <= dt0");
+  if (!std::isfinite(dt_max)) return fail(MM_ERR_ARG, "dt_max must be finite");
+  if (c->solo && c->method != method) {
+    mm_batch_destroy(c->solo);
+    c->solo = nullptr;
+  }
+  c->method = method;
+  c->dt0 = dt0;
+  c->dt_min = dt_min;
+  c->dt_max = dt_max;
+  if (c->dev_ready) {
+    InstCtl h;
+    if (mm_status s = ctl_pull(c, h)) return s;
+    h.dt = dt0;
+    h.dt_fixed = dt0;
+    h.last_rejected = 0;
+    if (mm_status s = ctl_push(c, h)) return s;
+    c->desc.method = method;
+    c->version++;
+  }
+  return MM_OK;
+}
+
+mm_status mm_set_sampling(mm_ctx* c, double dt_sample, int64_t max_samples) {
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  if (max_samples < 0) return fail(MM_ERR_ARG, "max_samples must be >= 0");
+  if (max_samples > 0 && !(dt_sample > 0 && std::isfinite(dt_sample))) return fail(MM_ERR_ARG, "dt_sample must be > 0");
+  if (max_samples > 0 && c->method == MM_RK4) {
+    const double r = dt_sample / c->dt0;
+    if (r < 1.0 - 1e-9 || std::fabs(r - std::llround(r)) > 1e-9 * r)
+      return fail(MM_ERR_ARG, "RK4 sampling interval must be a whole multiple of dt0");
+  }
+  if (mm_status s = ensure_device(c)) return s;
+  if (c->trace) hipFree(c->trace);
+  c->trace = nullptr;
+  c->trace_cap = 0;
+  if (max_samples > 0) {
+    const size_t cnt = (size_t)max_samples * (1 + 4 * (size_t)std::max(1, c->N));
+    if (hipMalloc(&c->trace, sizeof(double) * cnt) != hipSuccess) return fail(MM_ERR_OOM, "trace allocation failed");
+    c->trace_cap = max_samples;
+  }
+  c->dt_sample = dt_sample;
+  c->max_samples = max_samples;
+  c->sampling_changed = true;
+  return upload_desc(c);
+}
+
+mm_status mm_run(mm_ctx* c, double T, double tol) {
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  if (!(T > 0) || !std::isfinite(T)) return fail(MM_ERR_ARG, "T must be finite and > 0");
+  if (mm_status s = check_ready(c)) return s;
+  if (!c->solo) {
+    mm_ctx* one[1] = {c};
+    if (mm_status s = new_batch(one, 1, &c->solo)) return s;
+  }
+  if (mm_status s = validate_tol(c->solo, tol)) return s;
+  if (mm_status s = set_device(c)) return s;
+  return batch_run(c->solo, T, tol);
+}
+
+mm_status mm_get_m(const mm_ctx* c, float* out) {
+  if (!c || !out) return fail(MM_ERR_ARG, "NULL argument");
+  if (!c->dev_ready || !c->m_set) return fail(MM_ERR_STATE, "no state on the device");
+  InstCtl h;
+  if (mm_status s = ctl_pull(c, h)) return s;
+  MM_HIP(hipMemcpy(out, c->ws + c->L.y[h.cur], sizeof(float) * 3 * c->p.sublattices * (size_t)c->L.ncell,
+                   hipMemcpyDeviceToHost));
+  return MM_OK;
+}
+
+mm_status mm_get_a(const mm_ctx* c, double* out) {
+  if (!c || !out) return fail(MM_ERR_ARG, "NULL argument");
+  if (!c->dev_ready) return fail(MM_ERR_STATE, "no state on the device");
+  InstCtl h;
+  if (mm_status s = ctl_pull(c, h)) return s;
+  for (int n = 0; n < c->N; ++n) {
+    out[2 * n] = h.a[n][0];
+    out[2 * n + 1] = h.a[n][1];
+  }
+  return MM_OK;
+}
+
+mm_status mm_get_trace(const mm_ctx* c, double* t, double* a, double* mminus, int64_t* n) {
+  if (!c || !n) return fail(MM_ERR_ARG, "NULL argument");
+  if (!c->dev_ready) return fail(MM_ERR_STATE, "no state on the device");
+  InstCtl h;
+  if (mm_status s = ctl_pull(c, h)) return s;
+  const int64_t have = c->trace ? h.trace_n : 0;
+  const int64_t cnt = std::min<int64_t>(have, *n);
+  const int N = c->N;
+  if (cnt > 0) {
+    if (!t || !a || !mminus) return fail(MM_ERR_ARG, "NULL output buffer");
+    const int64_t cap = c->trace_cap;
+    MM_HIP(hipMemcpy(t, c->trace, sizeof(double) * cnt, hipMemcpyDeviceToHost));
+    MM_HIP(hipMemcpy(a, c->trace + cap, sizeof(double) * cnt * 2 * N, hipMemcpyDeviceToHost));
+    MM_HIP(hipMemcpy(mminus, c->trace + cap * (1 + 2 * (int64_t)std::max(1, N)), sizeof(double) * cnt * 2 * N,
+                     hipMemcpyDeviceToHost));
+  }
+  *n = cnt;
+  return MM_OK;
+}
+
+mm_status mm_get_stats(const mm_ctx* c, mm_stats* out) {
+  if (!c || !out) return fail(MM_ERR_ARG, "NULL argument");
+  *out = c->stats;
+  return MM_OK;
+}
+
+namespace {
+struct StateHeader {
+  uint64_t magic;
+  int32_t S, N, ncell, method;
+  uint64_t ctl_bytes, m_bytes;
+};
+constexpr uint64_t kMagic = 0x6d6d636176310001ULL;
+}  // namespace
+
+mm_status mm_get_state(const mm_ctx* c, void* blob, size_t* bytes) {
+  if (!c || !bytes) return fail(MM_ERR_ARG, "NULL argument");
+  const size_t mb = sizeof(float) * 3 * c->p.sublattices * (size_t)c->L.ncell;
+  const size_t need = sizeof(StateHeader) + sizeof(InstCtl) + mb;
+  if (!blob) {
+    *bytes = need;
+    return MM_OK;
+  }
+  if (*bytes < need) return fail(MM_ERR_ARG, "state buffer too small");
+  if (!c->dev_ready || !c->m_set) return fail(MM_ERR_STATE, "no state on the device");
+  StateHeader hd{kMagic, c->p.sublattices, c->N, c->L.ncell, c->method, sizeof(InstCtl), mb};
+  char* o = (char*)blob;
+  std::memcpy(o, &hd, sizeof(hd));
+  InstCtl h;
+  if (mm_status s = ctl_pull(c, h)) return s;
+  std::memcpy(o + sizeof(hd), &h, sizeof(h));
+  MM_HIP(hipMemcpy(o + sizeof(hd) + sizeof(h), c->ws + c->L.y[h.cur], mb, hipMemcpyDeviceToHost));
+  *bytes = need;
+  return MM_OK;
+}
+
+mm_status mm_set_state(mm_ctx* c, const void* blob, size_t bytes) {
+  if (!c || !blob) return fail(MM_ERR_ARG, "NULL argument");
+  if (bytes < sizeof(StateHeader)) return fail(MM_ERR_ARG, "state blob too small");
+  StateHeader hd;
+  std::memcpy(&hd, blob, sizeof(hd));
+  const size_t mb = sizeof(float) * 3 * c->p.sublattices * (size_t)c->L.ncell;
+  if (hd.magic != kMagic || hd.S != c->p.sublattices || hd.N != c->N || hd.ncell != c->L.ncell ||
+      hd.ctl_bytes != sizeof(InstCtl) || hd.m_bytes != mb || bytes < sizeof(hd) + sizeof(InstCtl) + mb)
+    return fail(MM_ERR_ARG, "state blob does not match this context");
+  if (mm_status s = ensure_device(c)) return s;
+  InstCtl h;
+  std::memcpy(&h, (const char*)blob + sizeof(hd), sizeof(h));
+  InstCtl cur;
+  if (mm_status s = ctl_pull(c, cur)) return s;
+  // keep this context's trace settings
+  h.trace_n = cur.trace_n; h.trace_max = cur.trace_max; h.trace_steps = cur.trace_steps;
+  h.trace_stride = cur.trace_stride; h.trace_t0 = cur.trace_t0; h.trace_dt = cur.trace_dt;
+  h.trace_on = cur.trace_on; h.trace_started = cur.trace_started;
+  h.cur = 0;
+  for (int j = 0; j < 8; ++j) h.slot[j] = j;
+  if (mm_status s = ctl_push(c, h)) return s;
+  MM_HIP(hipMemcpy(c->ws + c->L.y[0], (const char*)blob + sizeof(hd) + sizeof(h), mb, hipMemcpyHostToDevice));
+  c->m_set = true;
+  return MM_OK;
+}
+
+mm_status mm_batch_create(mm_ctx* const* ctxs, int32_t count, mm_batch** out) {
+  if (!ctxs || !out || count < 1) return fail(MM_ERR_ARG, "need count >= 1 contexts and an output");
+  for (int i = 0; i < count; ++i) {
+    if (!ctxs[i]) return fail(MM_ERR_ARG, "NULL context in batch");
+    if (mm_status s = check_ready(ctxs[i])) return s;
+    if (ctxs[i]->method != ctxs[0]->method) return fail(MM_ERR_ARG, "all instances need the same method");
+    if (ctxs[i]->dev != ctxs[0]->dev) return fail(MM_ERR_ARG, "all instances need the same device");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(MM_ERR_ARG, "a context appears twice in the batch");
+  }
+  if (mm_status s = set_device(ctxs[0])) return s;
+  return new_batch(ctxs, count, out);
+}
+
+mm_status mm_batch_run(mm_batch* b, double T, double tol) {
+  if (!b) return fail(MM_ERR_ARG, "NULL batch");
+  if (!(T > 0) || !std::isfinite(T)) return fail(MM_ERR_ARG, "T must be finite and > 0");
+  if (mm_status s = validate_tol(b, tol)) return s;
+  for (mm_ctx* c : b->ctxs)
+    if (c->method != b->method) return fail(MM_ERR_STATE, "instance method changed after batch creation");
+  if (mm_status s = set_device(b->ctxs[0])) return s;
+  return batch_run(b, T, tol);
+}
+
+mm_status mm_batch_step(mm_batch* b, int64_t steps, double tol) {
+  if (!b || steps < 0) return fail(MM_ERR_ARG, "bad arguments");
+  if (mm_status s = validate_tol(b, tol)) return s;
+  if (mm_status s = set_device(b->ctxs[0])) return s;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (mm_status s = begin_run(b, -1.0, tol)) return s;
+  if (mm_status s = ensure_graph(b)) return s;
+  int64_t left = steps;
+  while (left >= kStepsPerGraph) {
+    MM_HIP(hipGraphLaunch(b->exec, b->stream));
+    left -= kStepsPerGraph;
+  }
+  for (; left > 0; --left)
+    if (mm_status s = enqueue_step(b)) return s;
+  MM_HIP(hipStreamSynchronize(b->stream));
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return end_run(b, wall);
+}
+
+mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, char* names, int64_t* launches,
+                           double* total_ms, double* bytes_per_launch, int32_t* n) {
+  if (!b || !n || steps < 0 || cap < 0) return fail(MM_ERR_ARG, "bad arguments");
+  if (mm_status s = validate_tol(b, tol)) return s;
+  if (mm_status s = set_device(b->ctxs[0])) return s;
+  b->prof.clear();
+  if (mm_status s = begin_run(b, -1.0, tol)) return s;
+  MM_HIP(hipStreamSynchronize(b->stream));
+  b->profiling = true;
+  mm_status st = MM_OK;
+  for (int64_t k = 0; k < steps && st == MM_OK; ++k) st = enqueue_step(b);
+  b->profiling = false;
+  hipError_t e = hipStreamSynchronize(b->stream);
+  for (size_t q = 0; q < b->pending.size(); ++q) {
+    float ms = 0.f;
+    if (e == hipSuccess) hipEventElapsedTime(&ms, b->pending[q].first, b->pending[q].second);
+    b->prof[b->pending_idx[q]].ms += ms;
+    b->prof[b->pending_idx[q]].launches += 1;
+    hipEventDestroy(b->pending[q].first);
+    hipEventDestroy(b->pending[q].second);
+  }
+  b->pending.clear();
+  b->pending_idx.clear();
+  if (st != MM_OK) return st;
+  if (e != hipSuccess) return fail(MM_ERR_HIP, std::string("profile: ") + hipGetErrorString(e));
+  if (mm_status s = end_run(b, 0.0)) return s;
+  const int cnt = (int)std::min<size_t>(cap, b->prof.size());
+  for (int i = 0; i < cnt; ++i) {
+    if (names) {
+      std::memset(names + 48 * i, 0, 48);
+      std::strncpy(names + 48 * i, b->prof[i].name.c_str(), 47);
+    }
+    if (launches) launches[i] = b->prof[i].launches;
+    if (total_ms) total_ms[i] = b->prof[i].ms;
+    if (bytes_per_launch) bytes_per_launch[i] = b->prof[i].bytes;
+  }
+  *n = (int)b->prof.size();
+  return MM_OK;
+}
+
+mm_status mm_batch_destroy(mm_batch* b) {
+  if (!b) return MM_OK;
+  if (!b->ctxs.empty()) hipSetDevice(b->ctxs[0]->dev);
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (auto& g : b->groups) {
+    if (g.xf) hipFree(g.xf);
+    if (g.yz) hipFree(g.yz);
+    if (g.y) hipFree(g.y);
+    if (g.zc) hipFree(g.zc);
+  }
+  if (b->d_desc) hipFree(b->d_desc);
+  if (b->d_wg) hipFree(b->d_wg);
+  if (b->d_flags) hipFree(b->d_flags);
+  if (b->h_flags) hipHostFree(b->h_flags);
+  if (b->ev) hipEventDestroy(b->ev);
+  if (b->stream) hipStreamDestroy(b->stream);
+  delete b;
+  return MM_OK;
+}
+
+}  // extern "C"

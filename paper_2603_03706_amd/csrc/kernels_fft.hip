@@ -1,0 +1,465 @@
+// Demag field by zero-padded FFT convolution with the cell-averaged tensor.
+//
+// Per stage, for the stage input m (3 real components on nx*ny*nz cells):
+//   x-forward : R2C along x (two real rows packed in one complex line),
+//               zero padded to Px, output X[kx][c][z][y], kx <= Px/2
+//   yz        : C2C along y (zero padded to Py), C2C along z (zero padded to
+//               Pz), multiply by the real symmetric 3x3 kernel spectrum,
+//               inverse z, inverse y, crop to z < nz, y < ny (in place on X).
+//               One workgroup per (instance, kx) when the padded (y, z) plane
+//               of all three components fits in LDS ("fused"), otherwise a
+//               y pass into Y[kx][c][z][ky], a z pass with the multiply on
+//               tiles of ky, and an inverse y pass back into X ("split").
+//   x-inverse : C2R along x, crop to x < nx, scale by -mu0 Ms / (Px Py Pz),
+//               output B_d[c][z][y][x] [T].
+// Every line FFT runs in LDS with in-place radix-2^2 passes: forward
+// transforms by decimation in frequency (bit-reversed output), inverse
+// transforms by decimation in time (bit-reversed input), so no reordering
+// pass is needed between them.
+#include "mm_internal.h"
+#include "kernels_common.h"
+
+namespace mmk {
+
+struct LineMap {
+  int a, sa, sb, es;   // element j of line l at (l % a) * sa + (l / a) * sb + j * es
+  __device__ __forceinline__ int base(int l) const { return (l % a) * sa + (l / a) * sb; }
+};
+
+// Bit reversal of the low lg bits.
+__device__ __forceinline__ int brev(int p, int lg) {
+  return lg ? (int)(__brev((unsigned)p) >> (32 - lg)) : 0;
+}
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 rot(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+template <bool INV>
+__device__ __forceinline__ float2 twid(const float2* twl, int m) {
+  float2 w = twl[m];
+  if (INV) w.y = -w.y;
+  return w;
+}
+
+// Forward DFT of NL lines of length L = 2^lg in LDS, decimation in
+// frequency: natural order in, bit-reversed order out (position p holds
+// frequency brev(p)).  Radix-2^2 passes (two radix-2 stages per pass, each
+// thread updating four elements in place), then one radix-2 stage when lg is
+// odd.  twl[m] = e^{-2 pi i m / L}.  Data must be visible (synced) on entry;
+// the result is visible on exit.
+template <int T>
+__device__ void fft_dif(float2* lds, int L, int lg, int NL, const LineMap& lm, const float2* twl) {
+  int s = 0;
+  for (; s + 2 <= lg; s += 2) {
+    const int h = L >> (s + 1), q = h >> 1;
+    const int lq = lg - s - 2;                 // log2(q)
+    const int NB = NL * (L >> 2);
+    for (int idx = threadIdx.x; idx < NB; idx += T) {
+      const int l = idx % NL, r = idx / NL;
+      const int g = r >> lq, i = r & (q - 1);
+      const int p0 = lm.base(l) + (g * 2 * h + i) * lm.es;
+      const int e1 = q * lm.es, e2 = h * lm.es;
+      const float2 x0 = lds[p0], x1 = lds[p0 + e1], x2 = lds[p0 + e2], x3 = lds[p0 + e2 + e1];
+      const float2 w1 = twl[i << s], w2 = twl[i << (s + 1)];
+      const float2 a0 = cadd(x0, x2), a1 = cadd(x1, x3);
+      const float2 a2 = cmul(csub(x0, x2), w1);
+      const float2 a3 = rot<false>(cmul(csub(x1, x3), w1));
+      lds[p0] = cadd(a0, a1);
+      lds[p0 + e1] = cmul(csub(a0, a1), w2);
+      lds[p0 + e2] = cadd(a2, a3);
+      lds[p0 + e2 + e1] = cmul(csub(a2, a3), w2);
+    }
+    __syncthreads();
+  }
+  if (s < lg) {
+    const int NB = NL * (L >> 1);
+    for (int idx = threadIdx.x; idx < NB; idx += T) {
+      const int l = idx % NL, m = idx / NL;
+      const int p = lm.base(l) + 2 * m * lm.es;
+      const float2 a = lds[p], b = lds[p + lm.es];
+      lds[p] = cadd(a, b);
+      lds[p + lm.es] = csub(a, b);
+    }
+    __syncthreads();
+  }
+}
+
+// Inverse (unscaled) DFT by decimation in time: bit-reversed order in,
+// natural order out.  Mirror image of fft_dif with conjugate twiddles.
+template <int T>
+__device__ void fft_dit(float2* lds, int L, int lg, int NL, const LineMap& lm, const float2* twl) {
+  int t = 0;
+  if (lg & 1) {
+    const int NB = NL * (L >> 1);
+    for (int idx = threadIdx.x; idx < NB; idx += T) {
+      const int l = idx % NL, m = idx / NL;
+      const int p = lm.base(l) + 2 * m * lm.es;
+      const float2 a = lds[p], b = lds[p + lm.es];
+      lds[p] = cadd(a, b);
+      lds[p + lm.es] = csub(a, b);
+    }
+    __syncthreads();
+    t = 1;
+  }
+  for (; t + 2 <= lg; t += 2) {
+    const int q = 1 << t;
+    const int NB = NL * (L >> 2);
+    for (int idx = threadIdx.x; idx < NB; idx += T) {
+      const int l = idx % NL, r = idx / NL;
+      const int g = r >> t, i = r & (q - 1);
+      const int p0 = lm.base(l) + (g * 4 * q + i) * lm.es;
+      const int e1 = q * lm.es;
+      const float2 x0 = lds[p0], x1 = lds[p0 + e1], x2 = lds[p0 + 2 * e1], x3 = lds[p0 + 3 * e1];
+      const float2 wA = twid<true>(twl, i << (lg - t - 1)), wB = twid<true>(twl, i << (lg - t - 2));
+      const float2 t1 = cmul(x1, wA), t3 = cmul(x3, wA);
+      const float2 a0 = cadd(x0, t1), a1 = csub(x0, t1), a2 = cadd(x2, t3), a3 = csub(x2, t3);
+      const float2 u = cmul(a2, wB), v = rot<true>(cmul(a3, wB));
+      lds[p0] = cadd(a0, u);
+      lds[p0 + 2 * e1] = csub(a0, u);
+      lds[p0 + e1] = cadd(a1, v);
+      lds[p0 + 3 * e1] = csub(a1, v);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int ilog2(int L) {
+  int lg = 0;
+  while ((1 << lg) < L) ++lg;
+  return lg;
+}
+
+__device__ __forceinline__ void load_twiddles(float2* twl, int L, const float2* __restrict__ tw,
+                                              int T) {
+  for (int m = threadIdx.x; m < L; m += T) twl[m] = tw[m * (MMI_TW_LEN / L)];
+}
+
+// 3x3 kernel multiply at (kx, ky, kz): H = N M (sign and scale applied later)
+__device__ __forceinline__ void kernel_mul(const InstDesc& D, int kx, int ky, int kz, float2& mx,
+                                           float2& my, float2& mz) {
+  const int hy = D.py / 2, hz = D.pz / 2;
+  int ky2 = ky, kz2 = kz;
+  float sy = 1.f, sz = 1.f;
+  if (ky > hy) { ky2 = D.py - ky; sy = -1.f; }
+  if (kz > hz) { kz2 = D.pz - kz; sz = -1.f; }
+  const size_t plane = (size_t)(hz + 1) * (hy + 1) * D.kx;
+  const size_t o = ((size_t)kz2 * (hy + 1) + ky2) * D.kx + kx;
+  const float* K = D.kern;
+  const float nxx = K[o], nyy = K[plane + o], nzz = K[2 * plane + o];
+  const float nxy = sy * K[3 * plane + o], nxz = sz * K[4 * plane + o], nyz = sy * sz * K[5 * plane + o];
+  const float2 a = mx, b = my, c = mz;
+  mx = make_float2(nxx * a.x + nxy * b.x + nxz * c.x, nxx * a.y + nxy * b.y + nxz * c.y);
+  my = make_float2(nxy * a.x + nyy * b.x + nyz * c.x, nxy * a.y + nyy * b.y + nyz * c.y);
+  mz = make_float2(nxz * a.x + nyz * b.x + nzz * c.x, nxz * a.y + nyz * b.y + nzz * c.y);
+}
+
+// ------------------------------------------------------------ x forward
+// work item = tile of 2W real rows (c, z, y) of one instance
+template <int W>
+__global__ __launch_bounds__(256) void k_fft_xf(const InstDesc* __restrict__ descs,
+                                                const WorkItem* __restrict__ work, int method,
+                                                int stage, const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  const InstCtl* C = D.ctl;
+  if (C->done) return;
+  const int Px = D.px, nx = D.nx, ny = D.ny, nz = D.nz, nc = D.ncell;
+  const int nyz = ny * nz, rows = 3 * nyz;
+  const int r0 = wi.item * 2 * W;
+  const Src src = stage_src(D, C, method, stage);
+  float2* buf = lds;
+  float2* twl = lds + Px * W;
+  load_twiddles(twl, Px, tw, 256);
+  for (int e = threadIdx.x; e < 2 * W * Px; e += 256) {
+    const int rr = e / Px, x = e - rr * Px;
+    const int r = r0 + rr;
+    float v = 0.f;
+    if (x < nx && r < rows) {
+      const int c = r / nyz, yz = r - c * nyz;
+      v = src.ld(c * nc + yz * nx + x);
+    }
+    float* p = reinterpret_cast<float*>(&buf[x * W + (rr >> 1)]);
+    p[rr & 1] = v;
+  }
+  __syncthreads();
+  const LineMap lm{W, 1, 0, W};
+  const int lgx = ilog2(Px);
+  fft_dif<256>(buf, Px, lgx, W, lm, twl);
+  const int Kx = D.kx;
+  for (int e = threadIdx.x; e < Kx * 2 * W; e += 256) {
+    const int kx = e / (2 * W), rr = e - kx * 2 * W;
+    const int r = r0 + rr;
+    if (r >= rows) continue;
+    const int line = rr >> 1;
+    const float2 Z = buf[brev(kx & (Px - 1), lgx) * W + line];
+    const float2 Zm = buf[brev((Px - kx) & (Px - 1), lgx) * W + line];
+    float2 X;
+    if ((rr & 1) == 0) X = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+    else X = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
+    const int c = r / nyz, yz = r - c * nyz;
+    D.fx[((size_t)kx * 3 + c) * nyz + yz] = X;
+  }
+}
+
+// ------------------------------------------------------------ x inverse
+template <int W>
+__global__ __launch_bounds__(256) void k_fft_xi(const InstDesc* __restrict__ descs,
+                                                const WorkItem* __restrict__ work,
+                                                const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (D.ctl->done) return;
+  const int Px = D.px, nx = D.nx, ny = D.ny, nz = D.nz, nc = D.ncell;
+  const int nyz = ny * nz, rows = 3 * nyz;
+  const int r0 = wi.item * 2 * W;
+  const int Kx = D.kx;
+  float2* buf = lds;                    // [Px][W]
+  float2* stg = lds + Px * W;           // [Kx][2W]
+  float2* twl = stg + Kx * 2 * W;
+  load_twiddles(twl, Px, tw, 256);
+  for (int e = threadIdx.x; e < Kx * 2 * W; e += 256) {
+    const int kx = e / (2 * W), rr = e - kx * 2 * W;
+    const int r = r0 + rr;
+    float2 X = make_float2(0.f, 0.f);
+    if (r < rows) {
+      const int c = r / nyz, yz = r - c * nyz;
+      X = D.fx[((size_t)kx * 3 + c) * nyz + yz];
+    }
+    stg[kx * 2 * W + rr] = X;
+  }
+  __syncthreads();
+  const int half = Px / 2;
+  const int lgx = ilog2(Px);
+  for (int e = threadIdx.x; e < Px * W; e += 256) {
+    const int j = e / W, line = e - j * W;
+    float2 Z;
+    if (j <= half) {
+      float2 a = stg[j * 2 * W + 2 * line], b = stg[j * 2 * W + 2 * line + 1];
+      if (j == 0 || j == half) { a.y = 0.f; b.y = 0.f; }
+      Z = make_float2(a.x - b.y, a.y + b.x);
+    } else {
+      const int k = Px - j;
+      const float2 a = stg[k * 2 * W + 2 * line], b = stg[k * 2 * W + 2 * line + 1];
+      Z = make_float2(a.x + b.y, b.x - a.y);
+    }
+    buf[brev(j, lgx) * W + line] = Z;
+  }
+  __syncthreads();
+  const LineMap lm{W, 1, 0, W};
+  fft_dit<256>(buf, Px, lgx, W, lm, twl);
+  const float sc = D.bd_scale;
+  for (int e = threadIdx.x; e < 2 * W * nx; e += 256) {
+    const int rr = e / nx, x = e - rr * nx;
+    const int r = r0 + rr;
+    if (r >= rows) continue;
+    const float2 Z = buf[x * W + (rr >> 1)];
+    const int c = r / nyz, yz = r - c * nyz;
+    D.bd[c * nc + yz * nx + x] = sc * ((rr & 1) ? Z.y : Z.x);
+  }
+}
+
+// ------------------------------------------------------- fused y-z pass
+// work item = kx of one instance; LDS [3][Pz][Py+1] + twiddles
+#define MM_YZ_T 1024
+__global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__ descs,
+                                                    const WorkItem* __restrict__ work,
+                                                    const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (D.ctl->done) return;
+  const int kx = wi.item;
+  const int ny = D.ny, nz = D.nz, Py = D.py, Pz = D.pz;
+  const int RP = Py + 1;
+  const int plane = Pz * RP;
+  float2* buf = lds;
+  float2* twy = lds + 3 * plane;
+  float2* twz = twy + Py;
+  load_twiddles(twy, Py, tw, MM_YZ_T);
+  load_twiddles(twz, Pz, tw, MM_YZ_T);
+  for (int e = threadIdx.x; e < 3 * plane; e += MM_YZ_T) buf[e] = make_float2(0.f, 0.f);
+  __syncthreads();
+  const int nyz = ny * nz;
+  float2* X = D.fx + (size_t)kx * 3 * nyz;
+  for (int e = threadIdx.x; e < 3 * nyz; e += MM_YZ_T) {
+    const int c = e / nyz, yz = e - c * nyz;
+    const int z = yz / ny, y = yz - z * ny;
+    buf[c * plane + z * RP + y] = X[e];
+  }
+  __syncthreads();
+  const LineMap ylines{nz, RP, plane, 1};
+  const LineMap zlines{Py, 1, plane, RP};
+  const int lgy = ilog2(Py), lgz = ilog2(Pz);
+  fft_dif<MM_YZ_T>(buf, Py, lgy, 3 * nz, ylines, twy);
+  fft_dif<MM_YZ_T>(buf, Pz, lgz, 3 * Py, zlines, twz);
+  // spectra sit at bit-reversed positions in y and z
+  for (int e = threadIdx.x; e < Pz * Py; e += MM_YZ_T) {
+    const int pz_ = e / Py, py_ = e - pz_ * Py;
+    const int o = pz_ * RP + py_;
+    float2 mx = buf[o], my = buf[plane + o], mz = buf[2 * plane + o];
+    kernel_mul(D, kx, brev(py_, lgy), brev(pz_, lgz), mx, my, mz);
+    buf[o] = mx;
+    buf[plane + o] = my;
+    buf[2 * plane + o] = mz;
+  }
+  __syncthreads();
+  fft_dit<MM_YZ_T>(buf, Pz, lgz, 3 * Py, zlines, twz);
+  fft_dit<MM_YZ_T>(buf, Py, lgy, 3 * nz, ylines, twy);
+  for (int e = threadIdx.x; e < 3 * nyz; e += MM_YZ_T) {
+    const int c = e / nyz, yz = e - c * nyz;
+    const int z = yz / ny, y = yz - z * ny;
+    X[e] = buf[c * plane + z * RP + y];
+  }
+}
+
+// --------------------------------------------------------- split y passes
+// work item = tile of W lines (kx, c, z) of one instance; LDS [Py][W]
+template <int DIR>
+__global__ __launch_bounds__(256) void k_fft_y(const InstDesc* __restrict__ descs,
+                                               const WorkItem* __restrict__ work, int W,
+                                               const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (D.ctl->done) return;
+  const int ny = D.ny, Py = D.py;
+  const int nlines = D.kx * 3 * D.nz;
+  const int l0 = wi.item * W;
+  float2* buf = lds;
+  float2* twl = lds + Py * W;
+  load_twiddles(twl, Py, tw, 256);
+  const int nin = (DIR < 0) ? ny : Py;
+  const int lgy = ilog2(Py);
+  for (int e = threadIdx.x; e < W * Py; e += 256) {
+    const int ll = e / Py, y = e - ll * Py;
+    const int l = l0 + ll;
+    float2 v = make_float2(0.f, 0.f);
+    if (l < nlines && y < nin) v = (DIR < 0) ? D.fx[(size_t)l * ny + y] : D.fy[(size_t)l * Py + y];
+    // forward: natural order in; inverse: bit-reversed order in
+    buf[((DIR < 0) ? y : brev(y, lgy)) * W + ll] = v;
+  }
+  __syncthreads();
+  const LineMap lm{W, 1, 0, W};
+  if (DIR < 0) fft_dif<256>(buf, Py, lgy, W, lm, twl);
+  else fft_dit<256>(buf, Py, lgy, W, lm, twl);
+  const int nout = (DIR < 0) ? Py : ny;
+  for (int e = threadIdx.x; e < W * nout; e += 256) {
+    const int ll = e / nout, y = e - ll * nout;
+    const int l = l0 + ll;
+    if (l >= nlines) continue;
+    const float2 v = buf[((DIR < 0) ? brev(y, lgy) : y) * W + ll];
+    if (DIR < 0) D.fy[(size_t)l * Py + y] = v;
+    else D.fx[(size_t)l * ny + y] = v;
+  }
+}
+
+// ---------------------------------------------- split z pass with multiply
+// work item = (kx, tile of TW ky) of one instance; LDS [Pz][3 TW]
+__global__ __launch_bounds__(256) void k_fft_zc(const InstDesc* __restrict__ descs,
+                                                const WorkItem* __restrict__ work, int TW,
+                                                const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (D.ctl->done) return;
+  const int nz = D.nz, Py = D.py, Pz = D.pz;
+  const int tiles = (Py + TW - 1) / TW;
+  const int kx = wi.item / tiles;
+  const int ky0 = (wi.item - kx * tiles) * TW;
+  const int NL = 3 * TW;
+  float2* buf = lds;
+  float2* twl = lds + Pz * NL;
+  load_twiddles(twl, Pz, tw, 256);
+  for (int e = threadIdx.x; e < Pz * NL; e += 256) {
+    const int z = e / NL, l = e - z * NL;
+    const int c = l / TW, t = l - c * TW;
+    const int ky = ky0 + t;
+    float2 v = make_float2(0.f, 0.f);
+    if (z < nz && ky < Py) v = D.fy[(((size_t)kx * 3 + c) * nz + z) * Py + ky];
+    buf[e] = v;
+  }
+  __syncthreads();
+  const LineMap lm{NL, 1, 0, NL};
+  const int lgz = ilog2(Pz);
+  fft_dif<256>(buf, Pz, lgz, NL, lm, twl);
+  for (int e = threadIdx.x; e < Pz * TW; e += 256) {
+    const int pz_ = e / TW, t = e - pz_ * TW;
+    const int ky = ky0 + t;
+    if (ky >= Py) continue;
+    float2 mx = buf[pz_ * NL + t], my = buf[pz_ * NL + TW + t], mz = buf[pz_ * NL + 2 * TW + t];
+    kernel_mul(D, kx, ky, brev(pz_, lgz), mx, my, mz);
+    buf[pz_ * NL + t] = mx;
+    buf[pz_ * NL + TW + t] = my;
+    buf[pz_ * NL + 2 * TW + t] = mz;
+  }
+  __syncthreads();
+  fft_dit<256>(buf, Pz, lgz, NL, lm, twl);
+  for (int e = threadIdx.x; e < nz * NL; e += 256) {
+    const int z = e / NL, l = e - z * NL;
+    const int c = l / TW, t = l - c * TW;
+    const int ky = ky0 + t;
+    if (ky < Py) D.fy[(((size_t)kx * 3 + c) * nz + z) * Py + ky] = buf[e];
+  }
+}
+
+}  // namespace mmk
+
+// ------------------------------------------------------------ launchers
+hipError_t mmk_launch_fft_xf(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                             int method, int stage, const float2* tw, hipStream_t s) {
+  switch (W) {
+    case 1: hipLaunchKernelGGL(mmk::k_fft_xf<1>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 2: hipLaunchKernelGGL(mmk::k_fft_xf<2>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 4: hipLaunchKernelGGL(mmk::k_fft_xf<4>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 8: hipLaunchKernelGGL(mmk::k_fft_xf<8>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 16: hipLaunchKernelGGL(mmk::k_fft_xf<16>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 32: hipLaunchKernelGGL(mmk::k_fft_xf<32>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t mmk_launch_fft_xi(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                             const float2* tw, hipStream_t s) {
+  switch (W) {
+    case 1: hipLaunchKernelGGL(mmk::k_fft_xi<1>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 2: hipLaunchKernelGGL(mmk::k_fft_xi<2>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 4: hipLaunchKernelGGL(mmk::k_fft_xi<4>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 8: hipLaunchKernelGGL(mmk::k_fft_xi<8>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 16: hipLaunchKernelGGL(mmk::k_fft_xi<16>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 32: hipLaunchKernelGGL(mmk::k_fft_xi<32>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t mmk_launch_fft_yz(int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                             const float2* tw, hipStream_t s) {
+  hipLaunchKernelGGL(mmk::k_fft_yz, dim3(nblocks), dim3(MM_YZ_T), lds, s, d, w, tw);
+  return hipGetLastError();
+}
+
+hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstDesc* d,
+                            const WorkItem* w, const float2* tw, hipStream_t s) {
+  if (dir < 0) hipLaunchKernelGGL(mmk::k_fft_y<-1>, dim3(nblocks), dim3(256), lds, s, d, w, W, tw);
+  else hipLaunchKernelGGL(mmk::k_fft_y<1>, dim3(nblocks), dim3(256), lds, s, d, w, W, tw);
+  return hipGetLastError();
+}
+
+hipError_t mmk_launch_fft_zc(int TW, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                             const float2* tw, hipStream_t s) {
+  hipLaunchKernelGGL(mmk::k_fft_zc, dim3(nblocks), dim3(256), lds, s, d, w, TW, tw);
+  return hipGetLastError();
+}
+
+hipError_t mmk_set_lds_limits() {
+  hipError_t e = hipFuncSetAttribute((const void*)mmk::k_fft_yz,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  return e;
+}

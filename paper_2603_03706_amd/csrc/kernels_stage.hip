@@ -1,0 +1,667 @@
+// Fused stage kernels: stage input -> effective field -> LL torque -> next
+// stage input, with FP64 mode-weighted reductions and the FP64 cavity step /
+// step-size controller done by the last workgroup of each instance.
+#include "mm_internal.h"
+#include "kernels_common.h"
+
+namespace mmk {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double ar, double ai, double mr,
+                                        double mi, double& fr, double& fi) {
+  // (-i w - kappa) a + i g e^{-i Phi} m^-
+  const double w = D.omega[n], kp = D.kappa[n], g = D.g[n], c = D.cphi[n], s = D.sphi[n];
+  fr = -kp * ar + w * ai + g * (s * mr - c * mi);
+  fi = -w * ar - kp * ai + g * (s * mi + c * mr);
+}
+
+// Effective field and torque on sublattice s at cell i.
+__device__ __forceinline__ void torque_at(const InstDesc& D, const Src& src, int i, int x, int y,
+                                          int z, const float (&m)[2][3], int s, float fb,
+                                          bool has_bd, float (&k)[3]) {
+  const int nc = D.ncell;
+  const int nx = D.nx, ny = D.ny, nz = D.nz;
+  const int base = s * 3 * nc;
+  const float m0 = m[s][0], m1 = m[s][1], m2 = m[s][2];
+  float bx = D.B0x, by = D.B0y, bz = D.B0z;
+  // exchange: 6 neighbours, only magnetic pairs contribute
+  const uint8_t* G = D.has_geom ? D.geom : nullptr;
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+#define MM_NBR(cond, off, coef)                                                     \
+  if (cond) {                                                                       \
+    const int j = i + (off);                                                        \
+    if (!G || G[j]) {                                                               \
+      sx = fmaf(coef, src.ld(base + j) - m0, sx);                                   \
+      sy = fmaf(coef, src.ld(base + nc + j) - m1, sy);                              \
+      sz = fmaf(coef, src.ld(base + 2 * nc + j) - m2, sz);                          \
+    }                                                                               \
+  }
+  MM_NBR(x > 0, -1, D.cex_x)
+  MM_NBR(x < nx - 1, 1, D.cex_x)
+  MM_NBR(y > 0, -nx, D.cex_y)
+  MM_NBR(y < ny - 1, nx, D.cex_y)
+  MM_NBR(z > 0, -nx * ny, D.cex_z)
+  MM_NBR(z < nz - 1, nx * ny, D.cex_z)
+#undef MM_NBR
+  bx += sx;
+  by += sy;
+  bz += sz;
+  // uniaxial anisotropy
+  const float md = m0 * D.ex + m1 * D.ey + m2 * D.ez;
+  const float ck = D.cK * md;
+  bx = fmaf(ck, D.ex, bx);
+  by = fmaf(ck, D.ey, by);
+  bz = fmaf(ck, D.ez, bz);
+  // demag
+  if (D.demag == 1) {
+    float tx = m[0][0], ty = m[0][1], tz = m[0][2];
+    if (D.S == 2) { tx += m[1][0]; ty += m[1][1]; tz += m[1][2]; }
+    bx = fmaf(D.nlx, tx, bx);
+    by = fmaf(D.nly, ty, by);
+    bz = fmaf(D.nlz, tz, bz);
+  } else if (has_bd) {
+    bx += D.bd[i];
+    by += D.bd[nc + i];
+    bz += D.bd[2 * nc + i];
+  }
+  // cavity feedback
+  bx = fmaf(D.csign[s], fb, bx);
+  // intersublattice exchange
+  if (D.S == 2) {
+    const int o = 1 - s;
+    bx = fmaf(-D.BE, m[o][0], bx);
+    by = fmaf(-D.BE, m[o][1], by);
+    bz = fmaf(-D.BE, m[o][2], bz);
+  }
+  // LL torque: -gl [m x B + alpha m x (m x B)]
+  const float cx = m1 * bz - m2 * by;
+  const float cy = m2 * bx - m0 * bz;
+  const float cz = m0 * by - m1 * bx;
+  const float dx = m1 * cz - m2 * cy;
+  const float dy = m2 * cx - m0 * cz;
+  const float dz = m0 * cy - m1 * cx;
+  const float a = D.alpha, gl = -D.gl;
+  k[0] = gl * fmaf(a, dx, cx);
+  k[1] = gl * fmaf(a, dy, cy);
+  k[2] = gl * fmaf(a, dz, cz);
+}
+
+// Block-wide reduction over 256 threads, result valid in thread 0.
+template <bool MAX>
+__device__ __forceinline__ double block_reduce(double v, double* sh) {
+  v = MAX ? wave_max(v) : wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double r = sh[0];
+  if (MAX) {
+    r = nan_max(r, sh[1]);
+    r = nan_max(r, sh[2]);
+    r = nan_max(r, sh[3]);
+  } else {
+    r = ((r + sh[1]) + sh[2]) + sh[3];
+  }
+  return r;
+}
+
+// Reduce the per-thread mode sums of a vector field v (complex weight
+// sum_s c_s (v_x - i v_y) u_n) and store them in the partial record.
+__device__ __forceinline__ void reduce_modes(const InstDesc& D, int i, bool mag, float vr, float vi,
+                                             double* rec, int slot, double* sh) {
+  for (int n = 0; n < D.N; ++n) {
+    double wr = 0.0, wi = 0.0;
+    if (mag) {
+      const double u = D.profiled ? (double)D.u[(size_t)n * D.ncell + i] : 1.0;
+      wr = u * (double)vr;
+      wi = u * (double)vi;
+    }
+    const double sr = block_reduce<false>(wr, sh);
+    const double si = block_reduce<false>(wi, sh);
+    if (threadIdx.x == 0) {
+      rec[slot + 2 * n] = sr;
+      rec[slot + 2 * n + 1] = si;
+    }
+  }
+}
+
+// Sum (or max) one slot of the partial records over all workgroups of an
+// instance in a fixed order; result in thread 0.
+template <bool MAX>
+__device__ __forceinline__ double gather_slot(const InstDesc& D, int slot, double* sh) {
+  double v = MAX ? 0.0 : 0.0;
+  for (int w = threadIdx.x; w < D.nwg; w += MMI_WG) {
+    const double p = __builtin_nontemporal_load(&D.partials[(size_t)w * MMI_PSTRIDE + slot]);
+    v = MAX ? nan_max(v, p) : v + p;
+  }
+  return block_reduce<MAX>(v, sh);
+}
+
+// Append one trace sample (time, a, m^-) from values held in the control
+// block / the gathered sums.
+__device__ __forceinline__ void record_sample(const InstDesc& D, InstCtl* C, double t,
+                                              const double (*a)[2], const double (*mm)[2]) {
+  const long long n = C->trace_n;
+  if (n >= C->trace_max) return;
+  D.trace_t[n] = t;
+  for (int q = 0; q < D.N; ++q) {
+    D.trace_a[(n * D.N + q) * 2] = a[q][0];
+    D.trace_a[(n * D.N + q) * 2 + 1] = a[q][1];
+    D.trace_m[(n * D.N + q) * 2] = mm[q][0];
+    D.trace_m[(n * D.N + q) * 2 + 1] = mm[q][1];
+  }
+  C->trace_n = n + 1;
+}
+
+__device__ __forceinline__ double hermite(double th, double h, double y0, double f0, double y1,
+                                          double f1) {
+  const double t2 = th * th, t3 = t2 * th;
+  return (2 * t3 - 3 * t2 + 1) * y0 + (t3 - 2 * t2 + th) * h * f0 + (-2 * t3 + 3 * t2) * y1 +
+         (t3 - t2) * h * f1;
+}
+
+// next attempted step: min(dt, t_end - t), clipped to land on t_end
+__device__ __forceinline__ void plan_step(InstCtl* C, double dt) {
+  const double rem = C->t_end - C->t;
+  double h = dt;
+  int clipped = 0;
+  if (h * (1.0 + 1e-9) >= rem) {
+    h = rem;
+    clipped = 1;
+  }
+  C->h = h;
+  C->clipped = clipped;
+}
+
+// ------------------------------------------------------------ finalisation
+// Runs in thread 0 of the last workgroup of an instance, with the gathered
+// sums in tot[] (mode sums already scaled by 1/(S N_geo)).
+template <int METHOD, int ST>
+__device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
+  const int N = D.N;
+  const double h = C->h;
+  // m^- of the stage input written by this kernel
+  const double(*mmv)[2] = reinterpret_cast<const double(*)[2]>(tot + MMI_SLOT_MM);
+  if (METHOD == MMI_RK4) {
+    if (ST == 0) {  // run start: m^- of y, first derivative, first step
+      for (int n = 0; n < N; ++n) {
+        cav_rhs(D, n, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+        C->mm1[n][0] = mmv[n][0];
+        C->mm1[n][1] = mmv[n][1];
+        C->as[n][0] = C->a[n][0];
+        C->as[n][1] = C->a[n][1];
+      }
+      if (C->trace_on && !C->trace_started) {
+        C->trace_started = 1;
+        C->trace_t0 = C->t;
+        record_sample(D, C, C->t, C->a, C->mm1);
+      }
+      plan_step(C, C->dt_fixed);
+      return;
+    }
+    if (ST <= 3) {
+      const double c = (ST == 3) ? h : 0.5 * h;
+      for (int n = 0; n < N; ++n) {
+        const double ar = C->a[n][0] + c * C->ka[ST - 1][n][0];
+        const double ai = C->a[n][1] + c * C->ka[ST - 1][n][1];
+        cav_rhs(D, n, ar, ai, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
+        C->as[n][0] = ar;
+        C->as[n][1] = ai;
+      }
+      return;
+    }
+    // ST == 4: step end; the new amplitudes go to C->as first
+    bool bad = tot[MMI_SLOT_BAD] != 0.0;
+    const double c6 = h / 6.0;
+    for (int n = 0; n < N; ++n) {
+      for (int r = 0; r < 2; ++r) {
+        const double v = C->a[n][r] + c6 * (C->ka[0][n][r] + 2.0 * C->ka[1][n][r] +
+                                            2.0 * C->ka[2][n][r] + C->ka[3][n][r]);
+        if (!isfinite(v)) bad = true;
+        C->as[n][r] = v;
+      }
+    }
+    if (bad) {
+      for (int n = 0; n < N; ++n) {
+        C->as[n][0] = C->a[n][0];
+        C->as[n][1] = C->a[n][1];
+      }
+      C->status = -6;
+      C->done = 1;
+      return;
+    }
+    C->cur ^= 1;
+    C->t = C->clipped ? C->t_end : C->t + h;
+    C->accepted += 1;
+    C->dt_min_seen = fmin(C->dt_min_seen, h);
+    C->dt_max_seen = fmax(C->dt_max_seen, h);
+    for (int n = 0; n < N; ++n) {
+      C->a[n][0] = C->as[n][0];
+      C->a[n][1] = C->as[n][1];
+      cav_rhs(D, n, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+      C->mm1[n][0] = mmv[n][0];
+      C->mm1[n][1] = mmv[n][1];
+    }
+    if (C->trace_on) {
+      C->trace_steps += 1;
+      if (C->trace_steps % C->trace_stride == 0) record_sample(D, C, C->t, C->a, C->mm1);
+    }
+    if (C->t >= C->t_end) {
+      C->done = 1;
+      return;
+    }
+    plan_step(C, C->dt_fixed);
+    return;
+  }
+  // ------------------------------------------------------------- DP45
+  using P = DPCoef;
+  if (ST == 1) {  // run start (k1 written by the kernel)
+    for (int n = 0; n < N; ++n) {
+      cav_rhs(D, n, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+      C->mm1[n][0] = mmv[n][0];
+      C->mm1[n][1] = mmv[n][1];
+      C->dmm1[n][0] = tot[MMI_SLOT_DMM + 2 * n];
+      C->dmm1[n][1] = tot[MMI_SLOT_DMM + 2 * n + 1];
+    }
+    if (C->trace_on && !C->trace_started) {
+      C->trace_started = 1;
+      C->trace_t0 = C->t;
+      record_sample(D, C, C->t, C->a, C->mm1);
+    }
+    plan_step(C, C->dt);
+    const double hh = C->h;
+    for (int n = 0; n < N; ++n) {
+      C->as[n][0] = C->a[n][0] + hh * P::a21 * C->ka[0][n][0];
+      C->as[n][1] = C->a[n][1] + hh * P::a21 * C->ka[0][n][1];
+    }
+    return;
+  }
+  if (ST == 2) {
+    // ka2 at (a2, m^-(m2)) [m2 sums in the DMM slot], then ka3 at (a3, m^-(m3))
+    for (int n = 0; n < N; ++n)
+      cav_rhs(D, n, C->as[n][0], C->as[n][1], tot[MMI_SLOT_DMM + 2 * n],
+              tot[MMI_SLOT_DMM + 2 * n + 1], C->ka[1][n][0], C->ka[1][n][1]);
+  }
+  if (ST >= 2 && ST <= 6) {
+    // a_{ST+1} = a + h sum_j A[ST+1][j] ka_j
+    double A[6];
+    if (ST == 2) { A[0] = P::a31; A[1] = P::a32; }
+    if (ST == 3) { A[0] = P::a41; A[1] = P::a42; A[2] = P::a43; }
+    if (ST == 4) { A[0] = P::a51; A[1] = P::a52; A[2] = P::a53; A[3] = P::a54; }
+    if (ST == 5) { A[0] = P::a61; A[1] = P::a62; A[2] = P::a63; A[3] = P::a64; A[4] = P::a65; }
+    if (ST == 6) { A[0] = P::b1; A[1] = 0.0; A[2] = P::b3; A[3] = P::b4; A[4] = P::b5; A[5] = P::b6; }
+    for (int n = 0; n < N; ++n) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int j = 0; j < ST; ++j) {
+        s0 += A[j] * C->ka[j][n][0];
+        s1 += A[j] * C->ka[j][n][1];
+      }
+      const double ar = C->a[n][0] + h * s0;
+      const double ai = C->a[n][1] + h * s1;
+      cav_rhs(D, n, ar, ai, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
+      C->as[n][0] = ar;
+      C->as[n][1] = ai;
+      if (ST == 6) {
+        C->mm7[n][0] = mmv[n][0];
+        C->mm7[n][1] = mmv[n][1];
+      }
+    }
+    return;
+  }
+  // ST == 7: error norm, accept / reject, next step
+  double err = tot[MMI_SLOT_ERR];
+  const double E[7] = {P::e1, 0.0, P::e3, P::e4, P::e5, P::e6, P::e7};
+  for (int n = 0; n < N; ++n) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int j = 0; j < 7; ++j) {
+      s0 += E[j] * C->ka[j][n][0];
+      s1 += E[j] * C->ka[j][n][1];
+    }
+    err = nan_max(err, fabs(h * s0));
+    err = nan_max(err, fabs(h * s1));
+  }
+  const double eps = err / C->tol;
+  const bool finite = isfinite(eps);
+  double fac;
+  if (finite && eps <= 1.0) {
+    // trace: samples in (t, t + h]
+    if (C->trace_on) {
+      const double t0 = C->t;
+      while (C->trace_n < C->trace_max) {
+        const double tk = C->trace_t0 + (double)C->trace_n * C->trace_dt;
+        if (tk > t0 + h * (1.0 + 1e-12) || tk <= t0) break;
+        const double th = (tk - t0) / h;
+        const long long q = C->trace_n;
+        D.trace_t[q] = tk;
+        for (int n = 0; n < N; ++n)
+          for (int r = 0; r < 2; ++r) {
+            D.trace_a[(q * N + n) * 2 + r] =
+                hermite(th, h, C->a[n][r], C->ka[0][n][r], C->as[n][r], C->ka[6][n][r]);
+            D.trace_m[(q * N + n) * 2 + r] = hermite(th, h, C->mm1[n][r], C->dmm1[n][r], C->mm7[n][r],
+                                                     tot[MMI_SLOT_DMM + 2 * n + r]);
+          }
+        C->trace_n = q + 1;
+      }
+    }
+    C->t = C->clipped ? C->t_end : C->t + h;
+    C->accepted += 1;
+    C->dt_min_seen = fmin(C->dt_min_seen, h);
+    C->dt_max_seen = fmax(C->dt_max_seen, h);
+    for (int n = 0; n < N; ++n)
+      for (int r = 0; r < 2; ++r) {
+        C->a[n][r] = C->as[n][r];          // a_7
+        C->ka[0][n][r] = C->ka[6][n][r];   // FSAL
+        C->mm1[n][r] = C->mm7[n][r];
+        C->dmm1[n][r] = tot[MMI_SLOT_DMM + 2 * n + r];
+      }
+    C->cur ^= 1;
+    const int s0 = C->slot[0];
+    C->slot[0] = C->slot[6];
+    C->slot[6] = s0;
+    const double fmx = C->last_rejected ? 1.0 : 5.0;
+    fac = (eps == 0.0) ? 5.0 : 0.9 * pow(eps, -0.2);
+    fac = fmin(fmx, fmax(0.2, fac));
+    C->last_rejected = 0;
+  } else {
+    C->rejected += 1;
+    fac = finite ? fmax(0.2, 0.9 * pow(eps, -0.2)) : 0.2;
+    fac = fmin(1.0, fac);
+    C->last_rejected = 1;
+  }
+  double dtn = h * fac;
+  if (C->dt_max > 0.0) dtn = fmin(dtn, C->dt_max);
+  C->dt = dtn;
+  if (C->t >= C->t_end) {
+    C->done = 1;
+  } else if (dtn < C->dt_min) {
+    C->status = finite ? -5 : -6;
+    C->done = 1;
+  }
+  plan_step(C, dtn);
+  const double hh = C->h;
+  for (int n = 0; n < N; ++n) {
+    C->as[n][0] = C->a[n][0] + hh * P::a21 * C->ka[0][n][0];
+    C->as[n][1] = C->a[n][1] + hh * P::a21 * C->ka[0][n][1];
+  }
+}
+
+// --------------------------------------------------------------- the kernel
+// METHOD RK4: ST = 0 run start (reductions only), 1..4 stages.
+// METHOD DP45: ST = 1 run start (k1), 2..7 stages.
+template <int METHOD, int ST>
+__global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ descs,
+                                                  const int* __restrict__ wg_inst) {
+  __shared__ double sh[4];
+  __shared__ double tot[MMI_PSTRIDE];
+  __shared__ int is_last;
+  const InstDesc& D = descs[wg_inst[blockIdx.x]];
+  InstCtl* C = D.ctl;
+  if (C->done) return;
+  const int lw = blockIdx.x - D.wg0;
+  const int nc = D.ncell;
+  const int i = lw * MMI_WG + threadIdx.x;
+  const bool valid = i < nc;
+  const bool mag = valid && (!D.has_geom || D.geom[i]);
+  const int cur = C->cur;
+  const double h = C->h;
+  const int S = D.S;
+  using P = DPCoef;
+
+  const Src src = stage_src(D, C, METHOD, ST);
+
+  const int x = valid ? i % D.nx : 0;
+  const int yz = valid ? i / D.nx : 0;
+  const int yy = yz % D.ny, zz = yz / D.ny;
+
+  float m[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  float k[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  if (valid) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if (s < S)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) m[s][c] = src.ld((s * 3 + c) * nc + i);
+  }
+  const bool need_torque = !(METHOD == MMI_RK4 && ST == 0);
+  if (need_torque && mag) {
+    // cavity feedback sum_n h0_n u_n Re[e^{-i Phi_n} a_n]
+    float fb = 0.f;
+    for (int n = 0; n < D.N; ++n) {
+      const double b = D.h0[n] * (D.cphi[n] * C->as[n][0] + D.sphi[n] * C->as[n][1]);
+      const float u = D.profiled ? D.u[(size_t)n * nc + i] : 1.f;
+      fb = fmaf((float)b, u, fb);
+    }
+    const bool has_bd = D.demag == 2;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if (s < S) torque_at(D, src, i, x, yy, zz, m, s, fb, has_bd, k[s]);
+  }
+
+  // combination and outputs
+  float nx_[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};   // next stage input (or candidate)
+  float aux[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};   // DP45 stage-2 input values
+  float errm = 0.f;
+  bool bad = false;
+  bool has_next = true;
+  if (valid) {
+    const float* Y = D.y[cur];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (s >= S) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int idx = (s * 3 + c) * nc + i;
+        const float kk = k[s][c];
+        if (METHOD == MMI_RK4) {
+          if (ST == 0) {
+            nx_[s][c] = m[s][c];
+          } else if (ST == 1) {
+            D.k[0][idx] = kk;
+            nx_[s][c] = fmaf((float)(0.5 * h), kk, m[s][c]);
+            D.st[0][idx] = nx_[s][c];
+          } else if (ST == 2 || ST == 3) {
+            const float acc = fmaf(2.f, kk, D.k[0][idx]);
+            D.k[0][idx] = acc;
+            const float cc = (float)(ST == 3 ? h : 0.5 * h);
+            nx_[s][c] = fmaf(cc, kk, Y[idx]);
+            D.st[ST == 2 ? 1 : 0][idx] = nx_[s][c];
+          } else {  // ST == 4
+            nx_[s][c] = fmaf((float)(h / 6.0), D.k[0][idx] + kk, Y[idx]);
+          }
+        } else {
+          const float* K0 = D.k[C->slot[0]];
+          if (ST == 1) {
+            D.k[C->slot[0]][idx] = kk;
+            nx_[s][c] = m[s][c];
+          } else if (ST == 2) {
+            D.k[C->slot[1]][idx] = kk;
+            aux[s][c] = m[s][c];
+            nx_[s][c] = Y[idx] + ((float)(h * P::a31) * K0[idx] + (float)(h * P::a32) * kk);
+            D.st[0][idx] = nx_[s][c];
+          } else if (ST == 3) {
+            D.k[C->slot[2]][idx] = kk;
+            nx_[s][c] = Y[idx] + ((float)(h * P::a41) * K0[idx] +
+                                  (float)(h * P::a42) * D.k[C->slot[1]][idx] +
+                                  (float)(h * P::a43) * kk);
+            D.st[1][idx] = nx_[s][c];
+          } else if (ST == 4) {
+            D.k[C->slot[3]][idx] = kk;
+            nx_[s][c] = Y[idx] + ((float)(h * P::a51) * K0[idx] +
+                                  (float)(h * P::a52) * D.k[C->slot[1]][idx] +
+                                  (float)(h * P::a53) * D.k[C->slot[2]][idx] +
+                                  (float)(h * P::a54) * kk);
+            D.st[0][idx] = nx_[s][c];
+          } else if (ST == 5) {
+            D.k[C->slot[4]][idx] = kk;
+            nx_[s][c] = Y[idx] + ((float)(h * P::a61) * K0[idx] +
+                                  (float)(h * P::a62) * D.k[C->slot[1]][idx] +
+                                  (float)(h * P::a63) * D.k[C->slot[2]][idx] +
+                                  (float)(h * P::a64) * D.k[C->slot[3]][idx] +
+                                  (float)(h * P::a65) * kk);
+            D.st[1][idx] = nx_[s][c];
+          } else if (ST == 6) {
+            D.k[C->slot[5]][idx] = kk;
+            nx_[s][c] = Y[idx] + ((float)(h * P::b1) * K0[idx] +
+                                  (float)(h * P::b3) * D.k[C->slot[2]][idx] +
+                                  (float)(h * P::b4) * D.k[C->slot[3]][idx] +
+                                  (float)(h * P::b5) * D.k[C->slot[4]][idx] +
+                                  (float)(h * P::b6) * kk);
+          } else {  // ST == 7
+            D.k[C->slot[6]][idx] = kk;
+            const float e = (float)P::e1 * K0[idx] + (float)P::e3 * D.k[C->slot[2]][idx] +
+                            (float)P::e4 * D.k[C->slot[3]][idx] +
+                            (float)P::e5 * D.k[C->slot[4]][idx] +
+                            (float)P::e6 * D.k[C->slot[5]][idx] + (float)P::e7 * kk;
+            const float ae = fabsf(e);
+            errm = (ae != ae || errm != errm) ? ae + errm : fmaxf(errm, ae);
+          }
+        }
+      }
+      // normalise the step-end state
+      const bool step_end = (METHOD == MMI_RK4 && ST == 4) || (METHOD == MMI_DP45 && ST == 6);
+      if (step_end) {
+        float v0 = nx_[s][0], v1 = nx_[s][1], v2 = nx_[s][2];
+        if (mag) {
+          const float inv = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+          v0 *= inv;
+          v1 *= inv;
+          v2 *= inv;
+        }
+        if (!(isfinite(v0) && isfinite(v1) && isfinite(v2))) bad = true;
+        nx_[s][0] = v0;
+        nx_[s][1] = v1;
+        nx_[s][2] = v2;
+        float* Yn = D.y[1 - cur];
+        Yn[(s * 3 + 0) * nc + i] = v0;
+        Yn[(s * 3 + 1) * nc + i] = v1;
+        Yn[(s * 3 + 2) * nc + i] = v2;
+      }
+    }
+  }
+  if (METHOD == MMI_DP45 && ST == 7) has_next = false;
+
+  // ---- per-workgroup partials
+  double* rec = D.partials + (size_t)lw * MMI_PSTRIDE;
+  if (has_next) {
+    float vr = 0.f, vi = 0.f;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if (s < S) {
+        vr = fmaf(D.csign[s], nx_[s][0], vr);
+        vi = fmaf(-D.csign[s], nx_[s][1], vi);
+      }
+    reduce_modes(D, i, mag, vr, vi, rec, MMI_SLOT_MM, sh);
+  }
+  if (METHOD == MMI_DP45 && (ST == 1 || ST == 7)) {
+    float vr = 0.f, vi = 0.f;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if (s < S) {
+        vr = fmaf(D.csign[s], k[s][0], vr);
+        vi = fmaf(-D.csign[s], k[s][1], vi);
+      }
+    reduce_modes(D, i, mag, vr, vi, rec, MMI_SLOT_DMM, sh);
+  }
+  if (METHOD == MMI_DP45 && ST == 2) {
+    float vr = 0.f, vi = 0.f;
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if (s < S) {
+        vr = fmaf(D.csign[s], aux[s][0], vr);
+        vi = fmaf(-D.csign[s], aux[s][1], vi);
+      }
+    reduce_modes(D, i, mag, vr, vi, rec, MMI_SLOT_DMM, sh);
+  }
+  if (METHOD == MMI_DP45 && ST == 7) {
+    const double r = block_reduce<true>((double)errm * h, sh);
+    if (threadIdx.x == 0) rec[MMI_SLOT_ERR] = r;
+  }
+  if (METHOD == MMI_RK4 && ST == 4) {
+    const double r = block_reduce<true>(bad ? 1.0 : 0.0, sh);
+    if (threadIdx.x == 0) rec[MMI_SLOT_BAD] = r;
+  }
+
+  // ---- last workgroup of the instance finalises
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = (atomicAdd(D.ticket, 1) == D.nwg - 1);
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  const double scale = D.inv_ngeo / (double)S;
+  if (has_next) {
+    for (int q = 0; q < 2 * D.N; ++q) {
+      const double v = gather_slot<false>(D, MMI_SLOT_MM + q, sh);
+      if (threadIdx.x == 0) tot[MMI_SLOT_MM + q] = v * scale;
+    }
+  }
+  if (METHOD == MMI_DP45 && (ST == 1 || ST == 2 || ST == 7)) {
+    for (int q = 0; q < 2 * D.N; ++q) {
+      const double v = gather_slot<false>(D, MMI_SLOT_DMM + q, sh);
+      if (threadIdx.x == 0) tot[MMI_SLOT_DMM + q] = v * scale;
+    }
+  }
+  if (METHOD == MMI_DP45 && ST == 7) {
+    const double v = gather_slot<true>(D, MMI_SLOT_ERR, sh);
+    if (threadIdx.x == 0) tot[MMI_SLOT_ERR] = v;
+  }
+  if (METHOD == MMI_RK4 && ST == 4) {
+    const double v = gather_slot<true>(D, MMI_SLOT_BAD, sh);
+    if (threadIdx.x == 0) tot[MMI_SLOT_BAD] = v;
+  }
+  if (threadIdx.x == 0) {
+    finalize<METHOD, ST>(D, C, tot);
+    __threadfence();
+    *D.ticket = 0;
+  }
+}
+
+}  // namespace mmk
+
+// explicit launch wrappers --------------------------------------------------
+#define MM_STAGE_LAUNCH(M, S)                                                                   \
+  case S:                                                                                       \
+    hipLaunchKernelGGL((mmk::k_stage<M, S>), dim3(nblocks), dim3(MMI_WG), 0, stream, descs, wg); \
+    break;
+
+hipError_t mmk_launch_stage(int method, int stage, int nblocks, const InstDesc* descs,
+                            const int* wg, hipStream_t stream) {
+  if (method == MMI_RK4) {
+    switch (stage) {
+      MM_STAGE_LAUNCH(MMI_RK4, 0)
+      MM_STAGE_LAUNCH(MMI_RK4, 1)
+      MM_STAGE_LAUNCH(MMI_RK4, 2)
+      MM_STAGE_LAUNCH(MMI_RK4, 3)
+      MM_STAGE_LAUNCH(MMI_RK4, 4)
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (stage) {
+      MM_STAGE_LAUNCH(MMI_DP45, 1)
+      MM_STAGE_LAUNCH(MMI_DP45, 2)
+      MM_STAGE_LAUNCH(MMI_DP45, 3)
+      MM_STAGE_LAUNCH(MMI_DP45, 4)
+      MM_STAGE_LAUNCH(MMI_DP45, 5)
+      MM_STAGE_LAUNCH(MMI_DP45, 6)
+      MM_STAGE_LAUNCH(MMI_DP45, 7)
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+namespace mmk {
+__global__ void k_gather_done(const InstDesc* __restrict__ d, int count, int* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) {
+    const InstCtl* C = d[i].ctl;
+    out[2 * i] = C->done;
+    out[2 * i + 1] = C->status;
+  }
+}
+}  // namespace mmk
+
+hipError_t mmk_launch_gather_done(int count, const InstDesc* d, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(mmk::k_gather_done, dim3((count + 63) / 64), dim3(64), 0, s, d, count, out);
+  return hipGetLastError();
+}

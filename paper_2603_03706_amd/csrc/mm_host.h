@@ -1,0 +1,27 @@
+// Host-side helpers of the library (setup and launch wrappers).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <vector>
+
+#include "mm_internal.h"
+
+namespace mmh {
+void demag_tensor(double X, double Y, double Z, double dx, double dy, double dz, double* out6);
+int padded(int n);
+void kernel_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, std::vector<float>& out);
+}  // namespace mmh
+
+hipError_t mmk_launch_stage(int method, int stage, int nblocks, const InstDesc* descs,
+                            const int* wg, hipStream_t stream);
+hipError_t mmk_launch_fft_xf(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                             int method, int stage, const float2* tw, hipStream_t s);
+hipError_t mmk_launch_fft_xi(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                             const float2* tw, hipStream_t s);
+hipError_t mmk_launch_fft_yz(int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                             const float2* tw, hipStream_t s);
+hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstDesc* d,
+                            const WorkItem* w, const float2* tw, hipStream_t s);
+hipError_t mmk_launch_fft_zc(int TW, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                             const float2* tw, hipStream_t s);
+hipError_t mmk_set_lds_limits();
+hipError_t mmk_launch_gather_done(int count, const InstDesc* d, int* out, hipStream_t s);

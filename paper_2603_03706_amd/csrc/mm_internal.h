@@ -1,0 +1,97 @@
+// Internal data structures shared by the host runtime and the device kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MMI_MAX_MODES 16
+#define MMI_WG 256                 // stage-kernel workgroup size (4 wave64)
+#define MMI_PSTRIDE 72             // doubles per workgroup partial record
+#define MMI_TW_LEN 1024            // length of the twiddle table (max FFT length)
+
+// partial-record slots (doubles)
+//   [0, 2N)       sum of u_n * m^- of the next stage input (re, im)
+//   [32, 32+2N)   sum of u_n * k^- of this stage's torque (re, im), trace rate
+//   [64]          max-norm of the error estimate (NaN-propagating)
+//   [65]          non-finite flag of the written state (RK4 step end)
+#define MMI_SLOT_MM 0
+#define MMI_SLOT_DMM 32
+#define MMI_SLOT_ERR 64
+#define MMI_SLOT_BAD 65
+
+enum { MMI_RK4 = 0, MMI_DP45 = 1 };
+
+// Mutable per-instance control block (device memory).
+struct InstCtl {
+  double t, t_end, h;                 // time, end time, step of the current attempt
+  double dt;                          // proposed next step (adaptive)
+  double dt_fixed, tol, dt_min, dt_max;
+  double dt_min_seen, dt_max_seen;
+  long long accepted, rejected;
+  int status, done, cur, clipped, last_rejected, pad0;
+  int slot[8];                        // physical k-buffer of stage derivative j
+  double a[MMI_MAX_MODES][2];         // cavity amplitudes at the step start
+  double as[MMI_MAX_MODES][2];        // cavity value feeding the next stage kernel
+  double ka[7][MMI_MAX_MODES][2];     // stage derivatives of the cavity
+  double mm1[MMI_MAX_MODES][2];       // m^- at the step start
+  double dmm1[MMI_MAX_MODES][2];      // d m^-/dt at the step start
+  double mm7[MMI_MAX_MODES][2];       // m^- at the candidate (DP45)
+  // trace
+  long long trace_n, trace_max, trace_steps, trace_stride;
+  double trace_t0, trace_dt;
+  int trace_on, trace_started;
+};
+
+// Read-only per-instance descriptor (device memory).
+struct InstDesc {
+  int nx, ny, nz, ncell;
+  int S, N, profiled, has_geom;
+  int demag, method, nwg, wg0;
+  float cex_x, cex_y, cex_z;          // (2A/Ms)/d^2 per axis
+  float cK, ex, ey, ez;               // 2K/Ms and the unit axis
+  float B0x, B0y, B0z;
+  float nlx, nly, nlz;                // -mu0 Ms n_local
+  float BE, gl, alpha;                // B_E, gamma/(1+alpha^2), alpha
+  float csign[2];
+  float bd_scale;                     // -mu0 Ms / (Px Py Pz)
+  double inv_ngeo;
+  double omega[MMI_MAX_MODES], kappa[MMI_MAX_MODES], g[MMI_MAX_MODES];
+  double cphi[MMI_MAX_MODES], sphi[MMI_MAX_MODES], h0[MMI_MAX_MODES];
+  // device buffers
+  float* y[2];                        // state [S][3][cells]
+  float* k[7];                        // stage derivatives (RK4 uses k[0] as the running sum)
+  float* st[2];                       // stage-input ping-pong
+  const uint8_t* geom;                // [cells] or null
+  const float* u;                     // [N][cells] or null (uniform)
+  float* bd;                          // demag field [3][cells] (FFT demag)
+  double* partials;                   // [nwg][MMI_PSTRIDE]
+  int* ticket;
+  InstCtl* ctl;
+  double* trace_t;                    // [max]
+  double* trace_a;                    // [max][N][2]
+  double* trace_m;                    // [max][N][2]
+  // FFT demag
+  float2* fx;                         // [Kx][3][nz][ny]
+  float2* fy;                         // [Kx][3][nz][Py] (split path)
+  const float* kern;                  // [6][Pz/2+1][Py/2+1][Kx]
+  int px, py, pz, kx;
+};
+
+// Dormand-Prince 5(4) coefficients.
+struct DPCoef {
+  static constexpr double a21 = 1.0 / 5;
+  static constexpr double a31 = 3.0 / 40, a32 = 9.0 / 40;
+  static constexpr double a41 = 44.0 / 45, a42 = -56.0 / 15, a43 = 32.0 / 9;
+  static constexpr double a51 = 19372.0 / 6561, a52 = -25360.0 / 2187, a53 = 64448.0 / 6561,
+                          a54 = -212.0 / 729;
+  static constexpr double a61 = 9017.0 / 3168, a62 = -355.0 / 33, a63 = 46732.0 / 5247,
+                          a64 = 49.0 / 176, a65 = -5103.0 / 18656;
+  static constexpr double b1 = 35.0 / 384, b3 = 500.0 / 1113, b4 = 125.0 / 192,
+                          b5 = -2187.0 / 6784, b6 = 11.0 / 84;
+  static constexpr double e1 = 71.0 / 57600, e3 = -71.0 / 16695, e4 = 71.0 / 1920,
+                          e5 = -17253.0 / 339200, e6 = 22.0 / 525, e7 = -1.0 / 40;
+};
+
+// Work item of the FFT kernels: (instance, item index within the instance).
+struct WorkItem {
+  int inst, item;
+};

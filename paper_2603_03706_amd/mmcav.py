@@ -1,0 +1,291 @@
+"""Python binding of libmmcav.so (ctypes; argument marshalling only).
+
+Every step of the stepper runs in the HIP library.  PyTorch supplies device
+memory (a uint8 tensor bound as the workspace) and the stream; it is
+imported first so that the library shares the HIP runtime torch loaded.
+There is no fallback: if the library is missing, loading fails loudly.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmmcav.so")
+
+MM_OK, MM_ERR_ARG, MM_ERR_HIP, MM_ERR_OOM, MM_ERR_STATE, MM_ERR_DT_UNDERFLOW, MM_ERR_NONFINITE = 0, -1, -2, -3, -4, -5, -6
+DEMAG_NONE, DEMAG_LOCAL, DEMAG_FFT = 0, 1, 2
+RK4, DP45 = 0, 1
+MAX_MODES = 16
+
+_STATUS_NAMES = {0: "MM_OK", -1: "MM_ERR_ARG", -2: "MM_ERR_HIP", -3: "MM_ERR_OOM", -4: "MM_ERR_STATE",
+                 -5: "MM_ERR_DT_UNDERFLOW", -6: "MM_ERR_NONFINITE"}
+
+
+class MMError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
+                ("Ms", ctypes.c_double), ("Aex", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("Ku", ctypes.c_double), ("ku_axis", ctypes.c_double * 3), ("gamma", ctypes.c_double),
+                ("B0", ctypes.c_double * 3), ("demag", ctypes.c_int32), ("n_local", ctypes.c_double * 3),
+                ("geometry", ctypes.c_void_p), ("sublattices", ctypes.c_int32), ("B_E", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int64), ("rejected", ctypes.c_int64), ("t", ctypes.c_double),
+                ("dt", ctypes.c_double), ("dt_min_seen", ctypes.c_double), ("dt_max_seen", ctypes.c_double),
+                ("wall_s", ctypes.c_double), ("status", ctypes.c_int32)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_SIGS = {
+    "mm_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(_P)]),
+    "mm_destroy": (ctypes.c_int, [_P]),
+    "mm_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "mm_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "mm_set_stream": (ctypes.c_int, [_P, _P]),
+    "mm_set_modes": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
+    "mm_set_m": (ctypes.c_int, [_P, _P]),
+    "mm_set_a": (ctypes.c_int, [_P, _P]),
+    "mm_set_stepper": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "mm_set_sampling": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64]),
+    "mm_run": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
+    "mm_get_m": (ctypes.c_int, [_P, _P]),
+    "mm_get_a": (ctypes.c_int, [_P, _P]),
+    "mm_get_trace": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
+    "mm_get_stats": (ctypes.c_int, [_P, ctypes.POINTER(Stats)]),
+    "mm_get_state": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_size_t)]),
+    "mm_set_state": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "mm_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "mm_batch_run": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
+    "mm_batch_step": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double]),
+    "mm_batch_destroy": (ctypes.c_int, [_P]),
+    "mm_batch_profile": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P,
+                                        ctypes.POINTER(ctypes.c_int32)]),
+    "mm_demag_tensor": (ctypes.c_int, [ctypes.c_double] * 6 + [_P]),
+    "mm_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libmmcav.so once; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_03706_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != MM_OK:
+        raise MMError(status, lib().mm_last_error().decode())
+    return status
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def demag_tensor(X, Y, Z, dx, dy, dz):
+    out = np.zeros(6)
+    _check(lib().mm_demag_tensor(X, Y, Z, dx, dy, dz, _ptr(out)))
+    return out
+
+
+def make_params(grid, cell, Ms, Aex, alpha, gamma=1.76e11, Ku=0.0, ku_axis=(0, 0, 1), B0=(0, 0, 0),
+                demag=DEMAG_NONE, n_local=(0, 0, 0), geometry=None, sublattices=1, B_E=0.0):
+    p = Params()
+    p.nx, p.ny, p.nz = (int(v) for v in grid)
+    p.dx, p.dy, p.dz = (float(v) for v in cell)
+    p.Ms, p.Aex, p.alpha, p.Ku, p.gamma = float(Ms), float(Aex), float(alpha), float(Ku), float(gamma)
+    p.ku_axis[:] = [float(v) for v in ku_axis]
+    p.B0[:] = [float(v) for v in B0]
+    p.demag = int(demag)
+    p.n_local[:] = [float(v) for v in n_local]
+    p.sublattices = int(sublattices)
+    p.B_E = float(B_E)
+    geo = None
+    if geometry is not None:
+        geo = np.ascontiguousarray(geometry, dtype=np.uint8)
+        p.geometry = geo.ctypes.data
+    return p, geo
+
+
+class Context:
+    """One stepper instance.  workspace='torch' binds a torch uint8 tensor as
+    device memory; 'library' lets the library allocate."""
+
+    def __init__(self, grid, cell, Ms, Aex, alpha, n_modes=1, workspace="torch", stream="torch", **kw):
+        self._lib = lib()
+        p, geo = make_params(grid, cell, Ms, Aex, alpha, **kw)
+        self.params = p
+        self.grid = tuple(int(v) for v in grid)
+        self.S = int(kw.get("sublattices", 1))
+        self.N = 0
+        handle = ctypes.c_void_p()
+        _check(self._lib.mm_create(ctypes.byref(p), ctypes.byref(handle)))
+        self.h = handle
+        self._ws = None
+        if workspace == "torch":
+            nbytes = ctypes.c_size_t()
+            _check(self._lib.mm_workspace_bytes(ctypes.byref(p), int(n_modes), ctypes.byref(nbytes)))
+            self._ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device="cuda")
+            base = self._ws.data_ptr()
+            off = (-base) % 256
+            _check(self._lib.mm_bind_workspace(self.h, ctypes.c_void_p(base + off), int(nbytes.value)))
+        if stream == "torch":
+            _check(self._lib.mm_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+    @classmethod
+    def from_instance(cls, inst, workspace="torch"):
+        """Create, set modes, state and stepper from a workloads.Instance."""
+        c = cls(inst.grid, inst.cell, inst.Ms, inst.Aex, inst.alpha, n_modes=len(inst.omega),
+                workspace=workspace, gamma=inst.gamma, Ku=inst.Ku, ku_axis=inst.ku_axis, B0=inst.B0,
+                demag=inst.demag, n_local=inst.n_local, geometry=inst.geometry,
+                sublattices=inst.sublattices, B_E=inst.B_E)
+        c.set_modes(inst.omega, inst.kappa, inst.g, u=inst.u, phi=inst.phi, csign=inst.csign)
+        c.set_m(inst.m0)
+        c.set_a(inst.a0)
+        c.set_stepper(RK4 if inst.method == "rk4" else DP45, inst.dt0)
+        return c
+
+    def set_modes(self, omega, kappa, g, u=None, phi=None, csign=None):
+        n = len(omega)
+        om = np.ascontiguousarray(omega, np.float64)
+        ka = np.ascontiguousarray(kappa, np.float64)
+        gg = np.ascontiguousarray(g, np.float64)
+        uu = None if u is None else np.ascontiguousarray(u, np.float32)
+        ph = None if phi is None else np.ascontiguousarray(phi, np.float64)
+        cs = None if csign is None else np.ascontiguousarray(csign, np.int8)
+        _check(self._lib.mm_set_modes(self.h, n, _ptr(om), _ptr(ka), _ptr(gg), _ptr(uu), _ptr(ph), _ptr(cs)))
+        self.N = n
+
+    def set_m(self, m):
+        mm = np.ascontiguousarray(m, np.float32)
+        _check(self._lib.mm_set_m(self.h, _ptr(mm)))
+
+    def set_a(self, a):
+        a = np.asarray(a, np.complex128)
+        buf = np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1).reshape(-1))
+        _check(self._lib.mm_set_a(self.h, _ptr(buf)))
+
+    def set_stepper(self, method, dt0, dt_min=1e-18, dt_max=0.0):
+        _check(self._lib.mm_set_stepper(self.h, int(method), float(dt0), float(dt_min), float(dt_max)))
+
+    def set_sampling(self, dt_sample, max_samples):
+        _check(self._lib.mm_set_sampling(self.h, float(dt_sample), int(max_samples)))
+
+    def run(self, T, tol=0.0):
+        _check(self._lib.mm_run(self.h, float(T), float(tol)))
+
+    def get_m(self):
+        nx, ny, nz = self.grid
+        out = np.empty((self.S, 3, nz, ny, nx), np.float32)
+        _check(self._lib.mm_get_m(self.h, _ptr(out)))
+        return out
+
+    def get_a(self):
+        out = np.empty(2 * max(self.N, 1))
+        _check(self._lib.mm_get_a(self.h, _ptr(out)))
+        return out[0:2 * self.N:2] + 1j * out[1:2 * self.N:2]
+
+    def get_trace(self, capacity):
+        t = np.empty(capacity)
+        a = np.empty((capacity, max(self.N, 1), 2))
+        m = np.empty((capacity, max(self.N, 1), 2))
+        n = ctypes.c_int64(capacity)
+        _check(self._lib.mm_get_trace(self.h, _ptr(t), _ptr(a), _ptr(m), ctypes.byref(n)))
+        k = n.value
+        return t[:k], a[:k, :self.N, 0] + 1j * a[:k, :self.N, 1], m[:k, :self.N, 0] + 1j * m[:k, :self.N, 1]
+
+    def stats(self):
+        s = Stats()
+        _check(self._lib.mm_get_stats(self.h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def get_state(self):
+        n = ctypes.c_size_t()
+        _check(self._lib.mm_get_state(self.h, None, ctypes.byref(n)))
+        buf = np.empty(n.value, np.uint8)
+        _check(self._lib.mm_get_state(self.h, _ptr(buf), ctypes.byref(n)))
+        return buf
+
+    def set_state(self, blob):
+        blob = np.ascontiguousarray(blob, np.uint8)
+        _check(self._lib.mm_set_state(self.h, _ptr(blob), blob.size))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.mm_destroy(self.h)
+            self.h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Instances advanced together by one launch sequence per stage."""
+
+    def __init__(self, contexts):
+        self._lib = lib()
+        self.contexts = list(contexts)
+        arr = (ctypes.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        handle = ctypes.c_void_p()
+        _check(self._lib.mm_batch_create(arr, len(self.contexts), ctypes.byref(handle)))
+        self.h = handle
+
+    def run(self, T, tol=0.0):
+        _check(self._lib.mm_batch_run(self.h, float(T), float(tol)))
+
+    def step(self, steps, tol=0.0):
+        _check(self._lib.mm_batch_step(self.h, int(steps), float(tol)))
+
+    def profile(self, steps, tol=0.0, cap=32):
+        names = ctypes.create_string_buffer(48 * cap)
+        launches = np.zeros(cap, np.int64)
+        ms = np.zeros(cap)
+        nbytes = np.zeros(cap)
+        n = ctypes.c_int32()
+        _check(self._lib.mm_batch_profile(self.h, int(steps), float(tol), cap, names, _ptr(launches), _ptr(ms),
+                                          _ptr(nbytes), ctypes.byref(n)))
+        out = []
+        for i in range(min(n.value, cap)):
+            nm = names.raw[48 * i:48 * (i + 1)].split(b"\0", 1)[0].decode()
+            out.append({"name": nm, "launches": int(launches[i]), "total_ms": float(ms[i]),
+                        "bytes_per_launch": float(nbytes[i])})
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.mm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def exported_symbols():
+    """Names declared in include/mmcav.h."""
+    return list(_SIGS)
