@@ -104,7 +104,7 @@ void release_spectrum(Spectrum* s) {
 
 // --------------------------------------------------------------- layout
 struct Layout {
-  size_t ctl, ticket, y[2], k[7], st[2], geom, partials, bd, fx, fy, u, fixed_end, total;
+  size_t ctl, y[2], k[7], st[2], geom, partials, bd, fx, fy, u, fixed_end, total;
   int ncell, nwg, S, px, py, pz, kx;
   bool fft, split;
 };
@@ -128,7 +128,6 @@ Layout make_layout(const mm_params& p, int n_modes) {
   const size_t vec = align_up(sizeof(float) * 3 * L.S * (size_t)L.ncell);
   size_t o = 0;
   L.ctl = o; o += align_up(sizeof(InstCtl));
-  L.ticket = o; o += kAlign;
   for (int i = 0; i < 2; ++i) { L.y[i] = o; o += vec; }
   for (int i = 0; i < 7; ++i) { L.k[i] = o; o += vec; }
   for (int i = 0; i < 2; ++i) { L.st[i] = o; o += vec; }
@@ -348,7 +347,6 @@ mm_status upload_desc(mm_ctx* c) {
   d.geom = p.geometry ? (const uint8_t*)(w + L.geom) : nullptr;
   d.u = c->profiled ? (c->ws_bound ? (const float*)(w + L.u) : c->u_own) : nullptr;
   d.partials = (double*)(w + L.partials);
-  d.ticket = (int*)(w + L.ticket);
   d.ctl = (InstCtl*)(w + L.ctl);
   if (c->trace) {
     d.trace_t = c->trace;
@@ -523,9 +521,21 @@ const char* stage_name(int method, int st) {
   return method == MM_RK4 ? rk[st] : dp[st];
 }
 
+const char* final_name(int method, int st) {
+  static const char* rk[] = {"final_rk4_start", "final_rk4_1", "final_rk4_2", "final_rk4_3", "final_rk4_4"};
+  static const char* dp[] = {"", "final_dp45_1", "final_dp45_2", "final_dp45_3", "final_dp45_4",
+                             "final_dp45_5", "final_dp45_6", "final_dp45_7"};
+  return method == MM_RK4 ? rk[st] : dp[st];
+}
+
 mm_status enqueue_stage(mm_batch* b, int st) {
-  return launch(b, stage_name(b->method, st), [&] {
-    return mmk_launch_stage(b->method, st, b->total_wg, b->d_desc, b->d_wg, b->stream);
+  const int n = (int)b->ctxs.size();
+  if (mm_status s = launch(b, stage_name(b->method, st), [&] {
+        return mmk_launch_stage(b->method, st, false, b->total_wg, n, b->d_desc, b->d_wg, b->stream);
+      }))
+    return s;
+  return launch(b, final_name(b->method, st), [&] {
+    return mmk_launch_stage(b->method, st, true, b->total_wg, n, b->d_desc, b->d_wg, b->stream);
   });
 }
 
@@ -665,6 +675,11 @@ mm_status new_batch(mm_ctx* const* ctxs, int count, mm_batch** out) {
 
 double algorithmic_bytes(const mm_batch* b, const std::string& name) {
   double total = 0.0;
+  if (name.rfind("final_", 0) == 0) {
+    double t = 0.0;   // partial records of every workgroup, read once
+    for (const mm_ctx* c : b->ctxs) t += (double)c->L.nwg * MMI_PSTRIDE * sizeof(double);
+    return t;
+  }
   const bool is_stage = name.rfind("stage_", 0) == 0;
   int st = 0;
   if (is_stage) st = name.back() - '0';

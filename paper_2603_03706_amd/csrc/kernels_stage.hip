@@ -131,7 +131,7 @@ template <bool MAX>
 __device__ __forceinline__ double gather_slot(const InstDesc& D, int slot, double* sh) {
   double v = MAX ? 0.0 : 0.0;
   for (int w = threadIdx.x; w < D.nwg; w += MMI_WG) {
-    const double p = __builtin_nontemporal_load(&D.partials[(size_t)w * MMI_PSTRIDE + slot]);
+    const double p = D.partials[(size_t)w * MMI_PSTRIDE + slot];
     v = MAX ? nan_max(v, p) : v + p;
   }
   return block_reduce<MAX>(v, sh);
@@ -392,8 +392,6 @@ template <int METHOD, int ST>
 __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ descs,
                                                   const int* __restrict__ wg_inst) {
   __shared__ double sh[4];
-  __shared__ double tot[MMI_PSTRIDE];
-  __shared__ int is_last;
   const InstDesc& D = descs[wg_inst[blockIdx.x]];
   InstCtl* C = D.ctl;
   if (C->done) return;
@@ -406,6 +404,14 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   const double h = C->h;
   const int S = D.S;
   using P = DPCoef;
+  // control values used below, read once (global stores cannot alias them)
+  float* K[7];
+#pragma unroll
+  for (int j = 0; j < 7; ++j) K[j] = D.k[(METHOD == MMI_DP45) ? C->slot[j] : j];
+  float fbc[MMI_MAX_MODES];
+  const int NM = D.N;
+  for (int n = 0; n < MMI_MAX_MODES; ++n)
+    fbc[n] = n < NM ? (float)(D.h0[n] * (D.cphi[n] * C->as[n][0] + D.sphi[n] * C->as[n][1])) : 0.f;
 
   const Src src = stage_src(D, C, METHOD, ST);
 
@@ -426,10 +432,10 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   if (need_torque && mag) {
     // cavity feedback sum_n h0_n u_n Re[e^{-i Phi_n} a_n]
     float fb = 0.f;
-    for (int n = 0; n < D.N; ++n) {
-      const double b = D.h0[n] * (D.cphi[n] * C->as[n][0] + D.sphi[n] * C->as[n][1]);
-      const float u = D.profiled ? D.u[(size_t)n * nc + i] : 1.f;
-      fb = fmaf((float)b, u, fb);
+    if (D.profiled) {
+      for (int n = 0; n < NM; ++n) fb = fmaf(fbc[n], D.u[(size_t)n * nc + i], fb);
+    } else {
+      for (int n = 0; n < NM; ++n) fb += fbc[n];
     }
     const bool has_bd = D.demag == 2;
 #pragma unroll
@@ -456,62 +462,62 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
           if (ST == 0) {
             nx_[s][c] = m[s][c];
           } else if (ST == 1) {
-            D.k[0][idx] = kk;
+            K[0][idx] = kk;
             nx_[s][c] = fmaf((float)(0.5 * h), kk, m[s][c]);
             D.st[0][idx] = nx_[s][c];
           } else if (ST == 2 || ST == 3) {
-            const float acc = fmaf(2.f, kk, D.k[0][idx]);
-            D.k[0][idx] = acc;
+            const float acc = fmaf(2.f, kk, K[0][idx]);
+            K[0][idx] = acc;
             const float cc = (float)(ST == 3 ? h : 0.5 * h);
             nx_[s][c] = fmaf(cc, kk, Y[idx]);
             D.st[ST == 2 ? 1 : 0][idx] = nx_[s][c];
           } else {  // ST == 4
-            nx_[s][c] = fmaf((float)(h / 6.0), D.k[0][idx] + kk, Y[idx]);
+            nx_[s][c] = fmaf((float)(h / 6.0), K[0][idx] + kk, Y[idx]);
           }
         } else {
-          const float* K0 = D.k[C->slot[0]];
+          const float* K0 = K[0];
           if (ST == 1) {
-            D.k[C->slot[0]][idx] = kk;
+            K[0][idx] = kk;
             nx_[s][c] = m[s][c];
           } else if (ST == 2) {
-            D.k[C->slot[1]][idx] = kk;
+            K[1][idx] = kk;
             aux[s][c] = m[s][c];
             nx_[s][c] = Y[idx] + ((float)(h * P::a31) * K0[idx] + (float)(h * P::a32) * kk);
             D.st[0][idx] = nx_[s][c];
           } else if (ST == 3) {
-            D.k[C->slot[2]][idx] = kk;
+            K[2][idx] = kk;
             nx_[s][c] = Y[idx] + ((float)(h * P::a41) * K0[idx] +
-                                  (float)(h * P::a42) * D.k[C->slot[1]][idx] +
+                                  (float)(h * P::a42) * K[1][idx] +
                                   (float)(h * P::a43) * kk);
             D.st[1][idx] = nx_[s][c];
           } else if (ST == 4) {
-            D.k[C->slot[3]][idx] = kk;
+            K[3][idx] = kk;
             nx_[s][c] = Y[idx] + ((float)(h * P::a51) * K0[idx] +
-                                  (float)(h * P::a52) * D.k[C->slot[1]][idx] +
-                                  (float)(h * P::a53) * D.k[C->slot[2]][idx] +
+                                  (float)(h * P::a52) * K[1][idx] +
+                                  (float)(h * P::a53) * K[2][idx] +
                                   (float)(h * P::a54) * kk);
             D.st[0][idx] = nx_[s][c];
           } else if (ST == 5) {
-            D.k[C->slot[4]][idx] = kk;
+            K[4][idx] = kk;
             nx_[s][c] = Y[idx] + ((float)(h * P::a61) * K0[idx] +
-                                  (float)(h * P::a62) * D.k[C->slot[1]][idx] +
-                                  (float)(h * P::a63) * D.k[C->slot[2]][idx] +
-                                  (float)(h * P::a64) * D.k[C->slot[3]][idx] +
+                                  (float)(h * P::a62) * K[1][idx] +
+                                  (float)(h * P::a63) * K[2][idx] +
+                                  (float)(h * P::a64) * K[3][idx] +
                                   (float)(h * P::a65) * kk);
             D.st[1][idx] = nx_[s][c];
           } else if (ST == 6) {
-            D.k[C->slot[5]][idx] = kk;
+            K[5][idx] = kk;
             nx_[s][c] = Y[idx] + ((float)(h * P::b1) * K0[idx] +
-                                  (float)(h * P::b3) * D.k[C->slot[2]][idx] +
-                                  (float)(h * P::b4) * D.k[C->slot[3]][idx] +
-                                  (float)(h * P::b5) * D.k[C->slot[4]][idx] +
+                                  (float)(h * P::b3) * K[2][idx] +
+                                  (float)(h * P::b4) * K[3][idx] +
+                                  (float)(h * P::b5) * K[4][idx] +
                                   (float)(h * P::b6) * kk);
           } else {  // ST == 7
-            D.k[C->slot[6]][idx] = kk;
-            const float e = (float)P::e1 * K0[idx] + (float)P::e3 * D.k[C->slot[2]][idx] +
-                            (float)P::e4 * D.k[C->slot[3]][idx] +
-                            (float)P::e5 * D.k[C->slot[4]][idx] +
-                            (float)P::e6 * D.k[C->slot[5]][idx] + (float)P::e7 * kk;
+            K[6][idx] = kk;
+            const float e = (float)P::e1 * K0[idx] + (float)P::e3 * K[2][idx] +
+                            (float)P::e4 * K[3][idx] +
+                            (float)P::e5 * K[4][idx] +
+                            (float)P::e6 * K[5][idx] + (float)P::e7 * kk;
             const float ae = fabsf(e);
             errm = (ae != ae || errm != errm) ? ae + errm : fmaxf(errm, ae);
           }
@@ -581,14 +587,20 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
     if (threadIdx.x == 0) rec[MMI_SLOT_BAD] = r;
   }
 
-  // ---- last workgroup of the instance finalises
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) is_last = (atomicAdd(D.ticket, 1) == D.nwg - 1);
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  const double scale = D.inv_ngeo / (double)S;
+}
+
+// One workgroup per instance: gather the partial records of the stage
+// kernel in a fixed order and run the FP64 cavity step / controller.
+template <int METHOD, int ST>
+__global__ __launch_bounds__(MMI_WG) void k_final(const InstDesc* __restrict__ descs, int count) {
+  __shared__ double sh[4];
+  __shared__ double tot[MMI_PSTRIDE];
+  if ((int)blockIdx.x >= count) return;
+  const InstDesc& D = descs[blockIdx.x];
+  InstCtl* C = D.ctl;
+  if (C->done) return;
+  const bool has_next = !(METHOD == MMI_DP45 && ST == 7);
+  const double scale = D.inv_ngeo / (double)D.S;
   if (has_next) {
     for (int q = 0; q < 2 * D.N; ++q) {
       const double v = gather_slot<false>(D, MMI_SLOT_MM + q, sh);
@@ -609,11 +621,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
     const double v = gather_slot<true>(D, MMI_SLOT_BAD, sh);
     if (threadIdx.x == 0) tot[MMI_SLOT_BAD] = v;
   }
-  if (threadIdx.x == 0) {
-    finalize<METHOD, ST>(D, C, tot);
-    __threadfence();
-    *D.ticket = 0;
-  }
+  if (threadIdx.x == 0) finalize<METHOD, ST>(D, C, tot);
 }
 
 }  // namespace mmk
@@ -621,11 +629,16 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
 // explicit launch wrappers --------------------------------------------------
 #define MM_STAGE_LAUNCH(M, S)                                                                   \
   case S:                                                                                       \
-    hipLaunchKernelGGL((mmk::k_stage<M, S>), dim3(nblocks), dim3(MMI_WG), 0, stream, descs, wg); \
+    if (final_pass)                                                                             \
+      hipLaunchKernelGGL((mmk::k_final<M, S>), dim3(count), dim3(MMI_WG), 0, stream, descs, count); \
+    else                                                                                        \
+      hipLaunchKernelGGL((mmk::k_stage<M, S>), dim3(nblocks), dim3(MMI_WG), 0, stream, descs, wg); \
     break;
 
-hipError_t mmk_launch_stage(int method, int stage, int nblocks, const InstDesc* descs,
-                            const int* wg, hipStream_t stream) {
+// final_pass = false: the cell kernel of a stage; true: its per-instance
+// finalisation (count instances).
+hipError_t mmk_launch_stage(int method, int stage, bool final_pass, int nblocks, int count,
+                            const InstDesc* descs, const int* wg, hipStream_t stream) {
   if (method == MMI_RK4) {
     switch (stage) {
       MM_STAGE_LAUNCH(MMI_RK4, 0)

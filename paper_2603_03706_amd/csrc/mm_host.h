@@ -11,8 +11,8 @@ int padded(int n);
 void kernel_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, std::vector<float>& out);
 }  // namespace mmh
 
-hipError_t mmk_launch_stage(int method, int stage, int nblocks, const InstDesc* descs,
-                            const int* wg, hipStream_t stream);
+hipError_t mmk_launch_stage(int method, int stage, bool final_pass, int nblocks, int count,
+                            const InstDesc* descs, const int* wg, hipStream_t stream);
 hipError_t mmk_launch_fft_xf(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              int method, int stage, const float2* tw, hipStream_t s);
 hipError_t mmk_launch_fft_xi(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,

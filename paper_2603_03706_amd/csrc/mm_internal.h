@@ -64,7 +64,6 @@ struct InstDesc {
   const float* u;                     // [N][cells] or null (uniform)
   float* bd;                          // demag field [3][cells] (FFT demag)
   double* partials;                   // [nwg][MMI_PSTRIDE]
-  int* ticket;
   InstCtl* ctl;
   double* trace_t;                    // [max]
   double* trace_a;                    // [max][N][2]
