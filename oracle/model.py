@@ -62,9 +62,14 @@ class Problem:
 
 
 class Model:
-    """Precomputed constants and the right-hand side for one Problem."""
+    """Precomputed constants and the right-hand side for one Problem.
 
-    def __init__(self, p: Problem):
+    `leaves` may hold torch tensors for 'alpha', 'B0', 'g' and 'u' (e.g.
+    with requires_grad) that replace the Problem's numbers, so that the
+    whole run can be differentiated by autograd."""
+
+    def __init__(self, p: Problem, leaves=None):
+        leaves = leaves or {}
         self.p = p
         nx, ny, nz = (int(v) for v in p.grid)
         self.shape = (nz, ny, nx)
@@ -78,19 +83,22 @@ class Model:
         self.S = int(p.sublattices)
         N = p.n_modes
         self.N = N
-        self.gamma_ll = p.gamma / (1.0 + p.alpha * p.alpha)
+        self.alpha = leaves.get("alpha", p.alpha)
+        self.gamma_ll = p.gamma / (1.0 + self.alpha * self.alpha)
         self.cex = 2.0 * p.Aex / p.Ms
         self.inv_d2 = [1.0 / (c * c) for c in p.cell]              # x, y, z
         e = np.asarray(p.ku_axis, float)
         self.ku_axis = torch.tensor(e / np.linalg.norm(e)) if np.linalg.norm(e) > 0 else torch.zeros(3, dtype=torch.float64)
         self.cK = 2.0 * p.Ku / p.Ms
-        self.B0 = torch.tensor(np.asarray(p.B0, float))
+        self.B0 = leaves["B0"] if "B0" in leaves else torch.tensor(np.asarray(p.B0, float))
         self.omega = torch.tensor(np.asarray(p.omega, float))
         self.kappa = torch.tensor(np.asarray(p.kappa, float))
-        self.g = torch.tensor(np.asarray(p.g, float))
+        self.g = leaves["g"] if "g" in leaves else torch.tensor(np.asarray(p.g, float))
         self.phi = torch.tensor(np.zeros(N) if p.phi is None else np.asarray(p.phi, float))
         self.h0 = 2.0 * self.g / p.gamma                             # Eq. (5)
-        if p.u is None:
+        if "u" in leaves:
+            self.u = leaves["u"]
+        elif p.u is None:
             self.u = torch.ones((N,) + self.shape, dtype=torch.float64)
         else:
             self.u = torch.tensor(np.asarray(p.u, float).reshape((N,) + self.shape))
@@ -168,7 +176,7 @@ class Model:
     def torque(self, m, B):
         mxB = torch.cross(m, B, dim=1)
         mxmxB = torch.cross(m, mxB, dim=1)
-        return -self.gamma_ll * (mxB + self.p.alpha * mxmxB) * self.G
+        return -self.gamma_ll * (mxB + self.alpha * mxmxB) * self.G
 
     # ---------------------------------------------------------------- cavity
     def m_minus(self, m):
@@ -187,9 +195,13 @@ class Model:
         return km, self.cavity_rhs(a, mm), mm
 
     def normalize(self, m):
-        norm = torch.sqrt((m * m).sum(1, keepdim=True))
-        safe = torch.where(norm > 0, norm, torch.ones_like(norm))
-        return torch.where(self.Gmask.view(1, 1, *self.shape), m / safe, m)
+        """m / |m| on magnetic cells, unchanged (zero) elsewhere.  The norm is
+        taken of a value that is never zero, so reverse-mode derivatives stay
+        finite on non-magnetic cells."""
+        norm2 = (m * m).sum(1, keepdim=True)
+        mask = self.Gmask.view(1, 1, *self.shape)
+        safe = torch.where(mask, norm2, torch.ones_like(norm2))
+        return torch.where(mask, m / torch.sqrt(safe), m)
 
 
 def _pad_spec(axis, before=0, after=0):

@@ -213,6 +213,18 @@ struct mm_ctx {
   unsigned version = 1;          // bumps when the descriptor changes
   mm_stats stats{};
   InstDesc desc{};
+  // discrete adjoint
+  int record_next = -1;            // rec_index for the next run (-1: no recording)
+  bool rec_have = false;
+  int64_t rec_steps = 0;
+  int rec_K = 0, rec_nck = 0;
+  double rec_h = 0.0;
+  float* ck_m = nullptr;           // checkpoints [nck][S*3*cells]
+  std::vector<InstCtl> ck_ctl;
+  float* adj_f = nullptr;          // rec_m, rec_norm, lam_y, lam_k, lam_z, mu, lam_B
+  double* adj_d = nullptr;         // rec_a, grad_u
+  int adj_K = -1, adj_N = -1;
+  bool adj_on = false;             // descriptor carries the adjoint pointers
 };
 
 struct mm_batch {
@@ -237,6 +249,8 @@ struct mm_batch {
   std::vector<Group> groups;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  hipGraphExec_t exec_rev = nullptr;
+  hipGraph_t graph_rev = nullptr;
   hipEvent_t ev = nullptr;
   // profiling
   bool profiling = false;
@@ -264,6 +278,7 @@ void init_ctl(mm_ctx* c, InstCtl& h) {
   h.dt_max = c->dt_max;
   h.dt_min_seen = INFINITY;
   h.dt_max_seen = 0.0;
+  h.rec_index = -1;
 }
 
 mm_status ctl_pull(const mm_ctx* c, InstCtl& h) {
@@ -332,6 +347,7 @@ mm_status upload_desc(mm_ctx* c) {
   d.px = L.px; d.py = L.py; d.pz = L.pz; d.kx = L.kx;
   d.bd_scale = (float)(-kMu0 * p.Ms / ((double)L.px * L.py * L.pz));
   d.inv_ngeo = 1.0 / (double)c->n_geo;
+  d.gamma = p.gamma;
   for (int n = 0; n < c->N; ++n) {
     d.omega[n] = c->omega[n];
     d.kappa[n] = c->kappa[n];
@@ -358,6 +374,20 @@ mm_status upload_desc(mm_ctx* c) {
     d.fx = (float2*)(w + L.fx);
     d.fy = L.split ? (float2*)(w + L.fy) : nullptr;
     d.kern = c->spec ? c->spec->dev : nullptr;
+  }
+  if (c->adj_on) {
+    const size_t vec = (size_t)3 * p.sublattices * L.ncell;
+    const int K = c->adj_K;
+    float* f = c->adj_f;
+    d.rec_m = f; f += (size_t)(K + 1) * 4 * vec;
+    d.rec_norm = f; f += (size_t)K * p.sublattices * L.ncell;
+    d.lam_y = f; f += vec;
+    d.lam_k = f; f += vec;
+    d.lam_z = f; f += vec;
+    d.mu = f; f += vec;
+    d.lam_B = f;
+    d.rec_a = c->adj_d;
+    d.grad_u = c->adj_d + (size_t)K * 4 * std::max(1, c->N) * 2;
   }
   c->version++;
   return MM_OK;
@@ -481,10 +511,11 @@ mm_status launch(mm_batch* b, const char* name, F&& f) {
   return MM_OK;
 }
 
-mm_status enqueue_demag(mm_batch* b, int stage) {
+mm_status enqueue_demag(mm_batch* b, int stage, int method = -1) {
+  if (method < 0) method = b->method;
   for (auto& g : b->groups) {
     if (mm_status s = launch(b, "fft_x_forward", [&] {
-          return mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, b->method, stage, g_twiddle, b->stream);
+          return mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, method, stage, g_twiddle, b->stream);
         }))
       return s;
     if (!g.split) {
@@ -572,6 +603,42 @@ mm_status ensure_graph(mm_batch* b) {
   return MM_OK;
 }
 
+// One reverse step of the discrete adjoint for every instance of the batch.
+mm_status enqueue_reverse_step(mm_batch* b) {
+  const int n = (int)b->ctxs.size();
+  if (mm_status s = launch(b, "adj_start", [&] { return mmk_launch_adj(0, 0, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
+    return s;
+  if (mm_status s = launch(b, "adj_cavity", [&] { return mmk_launch_adj(3, 5, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
+    return s;
+  for (int st = 4; st >= 1; --st) {
+    if (mm_status s = enqueue_demag(b, st, MMI_ADJ)) return s;
+    if (mm_status s = launch(b, "adj_stage_a", [&] { return mmk_launch_adj(1, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
+      return s;
+    if (mm_status s = enqueue_demag(b, 5, MMI_ADJ)) return s;
+    if (mm_status s = launch(b, "adj_stage_b", [&] { return mmk_launch_adj(2, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
+      return s;
+    if (mm_status s = launch(b, "adj_cavity", [&] { return mmk_launch_adj(3, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
+      return s;
+  }
+  return MM_OK;
+}
+
+mm_status ensure_reverse_graph(mm_batch* b) {
+  if (b->exec_rev) return MM_OK;
+  MM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  mm_status st = enqueue_reverse_step(b);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (st != MM_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(MM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  b->graph_rev = g;
+  MM_HIP(hipGraphInstantiate(&b->exec_rev, g, nullptr, nullptr, 0));
+  return MM_OK;
+}
+
 mm_status wait_user_streams(mm_batch* b) {
   for (mm_ctx* c : b->ctxs)
     if (c->user_stream) {
@@ -599,6 +666,8 @@ mm_status begin_run(mm_batch* b, double T, double tol) {
     h.dt_max = c->dt_max;
     h.done = 0;
     h.status = 0;
+    h.rec_index = c->record_next;
+    c->record_next = -1;
     if (c->sampling_changed) {
       c->sampling_changed = false;
       h.trace_on = c->max_samples > 0 ? 1 : 0;
@@ -766,6 +835,9 @@ mm_status mm_destroy(mm_ctx* c) {
   if (!c->ws_bound && c->ws) hipFree(c->ws);
   if (c->u_own) hipFree(c->u_own);
   if (c->trace) hipFree(c->trace);
+  if (c->ck_m) hipFree(c->ck_m);
+  if (c->adj_f) hipFree(c->adj_f);
+  if (c->adj_d) hipFree(c->adj_d);
   release_spectrum(c->spec);
   delete c;
   return MM_OK;
@@ -785,9 +857,8 @@ mm_status mm_bind_workspace(mm_ctx* c, void* ptr, size_t bytes) {
   if (((uintptr_t)ptr) % kAlign) return fail(MM_ERR_ARG, "workspace must be 256-byte aligned");
   const Layout L0 = make_layout(c->p, 0);
   if (bytes < L0.total) return fail(MM_ERR_ARG, "workspace too small");
-  const size_t per_mode = align_up(sizeof(float) * (size_t)L0.ncell);
-  c->u_cap = (int)std::min<size_t>(MM_MAX_MODES, (bytes - L0.total) / per_mode);
-  while (c->u_cap > 0 && make_layout(c->p, c->u_cap).total > bytes) c->u_cap--;
+  c->u_cap = 0;
+  while (c->u_cap < MM_MAX_MODES && make_layout(c->p, c->u_cap + 1).total <= bytes) c->u_cap++;
   c->ws = (char*)ptr;
   c->ws_bytes = bytes;
   c->ws_bound = true;
@@ -1064,10 +1135,168 @@ mm_status mm_set_state(mm_ctx* c, const void* blob, size_t bytes) {
   h.trace_stride = cur.trace_stride; h.trace_t0 = cur.trace_t0; h.trace_dt = cur.trace_dt;
   h.trace_on = cur.trace_on; h.trace_started = cur.trace_started;
   h.cur = 0;
+  h.rec_index = -1;
   for (int j = 0; j < 8; ++j) h.slot[j] = j;
   if (mm_status s = ctl_push(c, h)) return s;
   MM_HIP(hipMemcpy(c->ws + c->L.y[0], (const char*)blob + sizeof(hd) + sizeof(h), mb, hipMemcpyHostToDevice));
   c->m_set = true;
+  return MM_OK;
+}
+
+namespace {
+mm_status ensure_solo(mm_ctx* c) {
+  if (c->solo) return MM_OK;
+  mm_ctx* one[1] = {c};
+  return new_batch(one, 1, &c->solo);
+}
+
+// restore the forward part of a checkpointed control block, keeping the
+// adjoint accumulators
+void restore_forward(InstCtl& dst, const InstCtl& ck) {
+  dst.t = ck.t;
+  dst.h = ck.h;
+  dst.dt = ck.dt;
+  dst.clipped = ck.clipped;
+  dst.accepted = ck.accepted;
+  dst.rejected = ck.rejected;
+  std::memcpy(dst.a, ck.a, sizeof(dst.a));
+  dst.cur = 0;
+  dst.trace_on = 0;               // the recomputation records no trace
+}
+}  // namespace
+
+mm_status mm_run_record(mm_ctx* c, double T, int32_t every) {
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  if (c->method != MM_RK4) return fail(MM_ERR_STATE, "recording needs the fixed-step RK4 method");
+  if (!(T > 0) || !std::isfinite(T) || every < 1) return fail(MM_ERR_ARG, "need T > 0 and checkpoint_every >= 1");
+  if (mm_status s = check_ready(c)) return s;
+  const double r = T / c->dt0;
+  const long long nsteps = llround(r);
+  if (nsteps < 1 || std::fabs(r - (double)nsteps) > 1e-9 * r) return fail(MM_ERR_ARG, "T must be a whole number of steps dt0");
+  if (mm_status s = set_device(c)) return s;
+  if (mm_status s = ensure_solo(c)) return s;
+  const int nck = (int)((nsteps + every - 1) / every);
+  const size_t vec = (size_t)3 * c->p.sublattices * c->L.ncell;
+  if (c->ck_m) hipFree(c->ck_m);
+  c->ck_m = nullptr;
+  if (hipMalloc(&c->ck_m, sizeof(float) * vec * nck) != hipSuccess) return fail(MM_ERR_OOM, "checkpoint allocation failed");
+  c->ck_ctl.assign(nck, InstCtl{});
+  c->rec_have = false;
+  long long left = nsteps;
+  for (int k = 0; k < nck; ++k) {
+    InstCtl h;
+    if (mm_status s = ctl_pull(c, h)) return s;
+    c->ck_ctl[k] = h;
+    MM_HIP(hipMemcpy(c->ck_m + vec * k, c->ws + c->L.y[h.cur], sizeof(float) * vec, hipMemcpyDeviceToDevice));
+    const long long steps = std::min<long long>(every, left);
+    if (mm_status s = batch_run(c->solo, (double)steps * c->dt0, 0.0)) return s;
+    left -= steps;
+  }
+  c->rec_have = true;
+  c->rec_steps = nsteps;
+  c->rec_K = every;
+  c->rec_nck = nck;
+  c->rec_h = c->dt0;
+  return MM_OK;
+}
+
+mm_status mm_adjoint(mm_ctx* c, const double* dL_da, const float* dL_dm, float* grad_u, double* grad_g,
+                     double* grad_alpha, double* grad_B0, double* grad_a0, float* grad_m0) {
+  if (!c || !dL_da) return fail(MM_ERR_ARG, "NULL context or dL_da");
+  if (!c->rec_have) return fail(MM_ERR_STATE, "no recorded run (mm_run_record)");
+  if (mm_status s = set_device(c)) return s;
+  const int N = c->N, S = c->p.sublattices, K = c->rec_K;
+  const size_t nc = (size_t)c->L.ncell, vec = (size_t)3 * S * nc;
+  for (int i = 0; i < 2 * N; ++i)
+    if (!std::isfinite(dL_da[i])) return fail(MM_ERR_ARG, "non-finite dL_da");
+  // adjoint buffers for segments of K steps
+  if (c->adj_K != K || c->adj_N != N) {
+    if (c->adj_f) hipFree(c->adj_f);
+    if (c->adj_d) hipFree(c->adj_d);
+    c->adj_f = nullptr;
+    c->adj_d = nullptr;
+    const size_t nf = (size_t)(K + 1) * 4 * vec + (size_t)K * S * nc + 5 * vec;
+    const size_t nd = (size_t)K * 4 * std::max(1, N) * 2 + (size_t)std::max(1, N) * nc;
+    if (hipMalloc(&c->adj_f, sizeof(float) * nf) != hipSuccess) return fail(MM_ERR_OOM, "adjoint allocation failed");
+    if (hipMalloc(&c->adj_d, sizeof(double) * nd) != hipSuccess) return fail(MM_ERR_OOM, "adjoint allocation failed");
+    c->adj_K = K;
+    c->adj_N = N;
+  }
+  c->adj_on = true;
+  if (mm_status s = upload_desc(c)) return s;
+  // the end state, restored afterwards
+  InstCtl end;
+  if (mm_status s = ctl_pull(c, end)) return s;
+  std::vector<float> m_end(vec);
+  MM_HIP(hipMemcpy(m_end.data(), c->ws + c->L.y[end.cur], sizeof(float) * vec, hipMemcpyDeviceToHost));
+  // initial adjoint
+  {
+    InstCtl h = end;
+    std::memset(h.la, 0, sizeof(h.la));
+    for (int n = 0; n < N; ++n) {
+      h.la[n][0] = dL_da[2 * n];
+      h.la[n][1] = dL_da[2 * n + 1];
+    }
+    std::memset(h.grad_g, 0, sizeof(h.grad_g));
+    h.grad_alpha = 0.0;
+    h.grad_B0[0] = h.grad_B0[1] = h.grad_B0[2] = 0.0;
+    h.adj_h = c->rec_h;
+    if (mm_status s = ctl_push(c, h)) return s;
+    std::vector<float> l0(vec, 0.f);
+    if (dL_dm) std::memcpy(l0.data(), dL_dm, sizeof(float) * vec);
+    MM_HIP(hipMemcpy(c->desc.lam_y, l0.data(), sizeof(float) * vec, hipMemcpyHostToDevice));
+    MM_HIP(hipMemset(c->desc.grad_u, 0, sizeof(double) * std::max(1, N) * nc));
+  }
+  mm_batch* b = c->solo;
+  if (mm_status s = refresh_descs(b)) return s;
+  if (mm_status s = ensure_reverse_graph(b)) return s;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (int k = c->rec_nck - 1; k >= 0; --k) {
+    const long long steps = std::min<long long>(K, c->rec_steps - (long long)k * K);
+    // restore the checkpoint and recompute the segment, keeping its stages
+    InstCtl h;
+    if (mm_status s = ctl_pull(c, h)) return s;
+    restore_forward(h, c->ck_ctl[k]);
+    if (mm_status s = ctl_push(c, h)) return s;
+    MM_HIP(hipMemcpy(c->ws + c->L.y[0], c->ck_m + vec * k, sizeof(float) * vec, hipMemcpyDeviceToDevice));
+    c->record_next = 0;
+    if (mm_status s = batch_run(b, (double)steps * c->rec_h, 0.0)) return s;
+    if (mm_status s = ctl_pull(c, h)) return s;
+    MM_HIP(hipMemcpy(c->desc.rec_m + (size_t)steps * 4 * vec, c->ws + c->L.y[h.cur], sizeof(float) * vec,
+                     hipMemcpyDeviceToDevice));
+    // reverse the segment
+    h.rec_index = (int)steps - 1;
+    h.done = 0;
+    h.adj_h = c->rec_h;
+    if (mm_status s = ctl_push(c, h)) return s;
+    for (long long q = 0; q < steps; ++q) MM_HIP(hipGraphLaunch(b->exec_rev, b->stream));
+    MM_HIP(hipStreamSynchronize(b->stream));
+  }
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  // outputs
+  InstCtl h;
+  if (mm_status s = ctl_pull(c, h)) return s;
+  if (grad_g) for (int n = 0; n < N; ++n) grad_g[n] = h.grad_g[n];
+  if (grad_alpha) *grad_alpha = h.grad_alpha;
+  if (grad_B0) for (int q = 0; q < 3; ++q) grad_B0[q] = h.grad_B0[q];
+  if (grad_a0) for (int n = 0; n < N; ++n) { grad_a0[2 * n] = h.la[n][0]; grad_a0[2 * n + 1] = h.la[n][1]; }
+  if (grad_m0) MM_HIP(hipMemcpy(grad_m0, c->desc.lam_y, sizeof(float) * vec, hipMemcpyDeviceToHost));
+  if (grad_u && N > 0) {
+    std::vector<double> gu((size_t)N * nc);
+    MM_HIP(hipMemcpy(gu.data(), c->desc.grad_u, sizeof(double) * gu.size(), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < gu.size(); ++i) grad_u[i] = (float)gu[i];
+  }
+  // back to the end state of the recorded run
+  InstCtl fin = h;
+  restore_forward(fin, end);
+  fin.cur = end.cur;
+  fin.rec_index = -1;
+  fin.status = end.status;
+  fin.done = end.done;
+  fin.trace_on = end.trace_on;
+  if (mm_status s = ctl_push(c, fin)) return s;
+  MM_HIP(hipMemcpy(c->ws + c->L.y[end.cur], m_end.data(), sizeof(float) * vec, hipMemcpyHostToDevice));
+  c->stats.wall_s = wall;
   return MM_OK;
 }
 
@@ -1159,6 +1388,8 @@ mm_status mm_batch_destroy(mm_batch* b) {
   if (!b->ctxs.empty()) hipSetDevice(b->ctxs[0]->dev);
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec_rev) hipGraphExecDestroy(b->exec_rev);
+  if (b->graph_rev) hipGraphDestroy(b->graph_rev);
   for (auto& g : b->groups) {
     if (g.xf) hipFree(g.xf);
     if (g.yz) hipFree(g.yz);

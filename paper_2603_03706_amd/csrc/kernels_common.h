@@ -25,6 +25,12 @@ __device__ __forceinline__ Src stage_src(const InstDesc& D, const InstCtl* C, in
   s.p1 = nullptr;
   s.c1 = 0.f;
   const int cur = C->cur;
+  if (method == MMI_ADJ) {
+    // adjoint: stage 1..4 -> recorded stage input of the current step, 5 -> lambda_B
+    const size_t vec = (size_t)3 * D.S * D.ncell;
+    s.p0 = (stage == 5) ? D.lam_B : D.rec_m + ((size_t)C->rec_index * 4 + (stage - 1)) * vec;
+    return s;
+  }
   if (method == MMI_RK4) {
     s.p0 = (stage <= 1) ? D.y[cur] : (stage == 3 ? D.st[1] : D.st[0]);
   } else {
@@ -41,6 +47,67 @@ __device__ __forceinline__ Src stage_src(const InstDesc& D, const InstCtl* C, in
     }
   }
   return s;
+}
+
+// Effective field [T] on sublattice s at cell i (x, y, z its coordinates):
+// Zeeman + exchange over magnetic neighbour pairs + uniaxial anisotropy +
+// demag (local diagonal, or the FFT result in D.bd) + feedback c_s fb along
+// x + intersublattice -B_E m_{s'}.  m holds the cell's own stage input.
+__device__ __forceinline__ void field_at(const InstDesc& D, const Src& src, int i, int x, int y,
+                                         int z, const float (&m)[2][3], int s, float fb,
+                                         bool has_bd, float (&B)[3]) {
+  const int nc = D.ncell;
+  const int nx = D.nx, ny = D.ny, nz = D.nz;
+  const int base = s * 3 * nc;
+  const float m0 = m[s][0], m1 = m[s][1], m2 = m[s][2];
+  float bx = D.B0x, by = D.B0y, bz = D.B0z;
+  const uint8_t* G = D.has_geom ? D.geom : nullptr;
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+#define MM_NBR(cond, off, coef)                                                     \
+  if (cond) {                                                                       \
+    const int j = i + (off);                                                        \
+    if (!G || G[j]) {                                                               \
+      sx = fmaf(coef, src.ld(base + j) - m0, sx);                                   \
+      sy = fmaf(coef, src.ld(base + nc + j) - m1, sy);                              \
+      sz = fmaf(coef, src.ld(base + 2 * nc + j) - m2, sz);                          \
+    }                                                                               \
+  }
+  MM_NBR(x > 0, -1, D.cex_x)
+  MM_NBR(x < nx - 1, 1, D.cex_x)
+  MM_NBR(y > 0, -nx, D.cex_y)
+  MM_NBR(y < ny - 1, nx, D.cex_y)
+  MM_NBR(z > 0, -nx * ny, D.cex_z)
+  MM_NBR(z < nz - 1, nx * ny, D.cex_z)
+#undef MM_NBR
+  bx += sx;
+  by += sy;
+  bz += sz;
+  const float md = m0 * D.ex + m1 * D.ey + m2 * D.ez;
+  const float ck = D.cK * md;
+  bx = fmaf(ck, D.ex, bx);
+  by = fmaf(ck, D.ey, by);
+  bz = fmaf(ck, D.ez, bz);
+  if (D.demag == 1) {
+    float tx = m[0][0], ty = m[0][1], tz = m[0][2];
+    if (D.S == 2) { tx += m[1][0]; ty += m[1][1]; tz += m[1][2]; }
+    bx = fmaf(D.nlx, tx, bx);
+    by = fmaf(D.nly, ty, by);
+    bz = fmaf(D.nlz, tz, bz);
+  } else if (has_bd) {
+    bx += D.bd[i];
+    by += D.bd[nc + i];
+    bz += D.bd[2 * nc + i];
+  }
+  bx = fmaf(D.csign[s], fb, bx);
+  if (D.S == 2) {
+    const int o = 1 - s;
+    bx = fmaf(-D.BE, m[o][0], bx);
+    by = fmaf(-D.BE, m[o][1], by);
+    bz = fmaf(-D.BE, m[o][2], bz);
+  }
+  B[0] = bx;
+  B[1] = by;
+  B[2] = bz;
 }
 
 // max that propagates NaN (a NaN anywhere makes the result NaN)

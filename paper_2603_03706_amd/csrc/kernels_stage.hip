@@ -15,68 +15,17 @@ __device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double ar, dou
   fi = -w * ar - kp * ai + g * (s * mi + c * mr);
 }
 
-// Effective field and torque on sublattice s at cell i.
+// LL torque on sublattice s at cell i from its effective field.
 __device__ __forceinline__ void torque_at(const InstDesc& D, const Src& src, int i, int x, int y,
                                           int z, const float (&m)[2][3], int s, float fb,
                                           bool has_bd, float (&k)[3]) {
-  const int nc = D.ncell;
-  const int nx = D.nx, ny = D.ny, nz = D.nz;
-  const int base = s * 3 * nc;
+  float B[3];
+  field_at(D, src, i, x, y, z, m, s, fb, has_bd, B);
   const float m0 = m[s][0], m1 = m[s][1], m2 = m[s][2];
-  float bx = D.B0x, by = D.B0y, bz = D.B0z;
-  // exchange: 6 neighbours, only magnetic pairs contribute
-  const uint8_t* G = D.has_geom ? D.geom : nullptr;
-  float sx = 0.f, sy = 0.f, sz = 0.f;
-#define MM_NBR(cond, off, coef)                                                     \
-  if (cond) {                                                                       \
-    const int j = i + (off);                                                        \
-    if (!G || G[j]) {                                                               \
-      sx = fmaf(coef, src.ld(base + j) - m0, sx);                                   \
-      sy = fmaf(coef, src.ld(base + nc + j) - m1, sy);                              \
-      sz = fmaf(coef, src.ld(base + 2 * nc + j) - m2, sz);                          \
-    }                                                                               \
-  }
-  MM_NBR(x > 0, -1, D.cex_x)
-  MM_NBR(x < nx - 1, 1, D.cex_x)
-  MM_NBR(y > 0, -nx, D.cex_y)
-  MM_NBR(y < ny - 1, nx, D.cex_y)
-  MM_NBR(z > 0, -nx * ny, D.cex_z)
-  MM_NBR(z < nz - 1, nx * ny, D.cex_z)
-#undef MM_NBR
-  bx += sx;
-  by += sy;
-  bz += sz;
-  // uniaxial anisotropy
-  const float md = m0 * D.ex + m1 * D.ey + m2 * D.ez;
-  const float ck = D.cK * md;
-  bx = fmaf(ck, D.ex, bx);
-  by = fmaf(ck, D.ey, by);
-  bz = fmaf(ck, D.ez, bz);
-  // demag
-  if (D.demag == 1) {
-    float tx = m[0][0], ty = m[0][1], tz = m[0][2];
-    if (D.S == 2) { tx += m[1][0]; ty += m[1][1]; tz += m[1][2]; }
-    bx = fmaf(D.nlx, tx, bx);
-    by = fmaf(D.nly, ty, by);
-    bz = fmaf(D.nlz, tz, bz);
-  } else if (has_bd) {
-    bx += D.bd[i];
-    by += D.bd[nc + i];
-    bz += D.bd[2 * nc + i];
-  }
-  // cavity feedback
-  bx = fmaf(D.csign[s], fb, bx);
-  // intersublattice exchange
-  if (D.S == 2) {
-    const int o = 1 - s;
-    bx = fmaf(-D.BE, m[o][0], bx);
-    by = fmaf(-D.BE, m[o][1], by);
-    bz = fmaf(-D.BE, m[o][2], bz);
-  }
-  // LL torque: -gl [m x B + alpha m x (m x B)]
-  const float cx = m1 * bz - m2 * by;
-  const float cy = m2 * bx - m0 * bz;
-  const float cz = m0 * by - m1 * bx;
+  // -gl [m x B + alpha m x (m x B)]
+  const float cx = m1 * B[2] - m2 * B[1];
+  const float cy = m2 * B[0] - m0 * B[2];
+  const float cz = m0 * B[1] - m1 * B[0];
   const float dx = m1 * cz - m2 * cy;
   const float dy = m2 * cx - m0 * cz;
   const float dz = m0 * cy - m1 * cx;
@@ -182,6 +131,13 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   const double h = C->h;
   // m^- of the stage input written by this kernel
   const double(*mmv)[2] = reinterpret_cast<const double(*)[2]>(tot + MMI_SLOT_MM);
+  if (METHOD == MMI_RK4 && ST >= 1 && C->rec_index >= 0) {
+    double* ra = D.rec_a + ((size_t)C->rec_index * 4 + (ST - 1)) * N * 2;
+    for (int n = 0; n < N; ++n) {
+      ra[2 * n] = C->as[n][0];
+      ra[2 * n + 1] = C->as[n][1];
+    }
+  }
   if (METHOD == MMI_RK4) {
     if (ST == 0) {  // run start: m^- of y, first derivative, first step
       for (int n = 0; n < N; ++n) {
@@ -233,6 +189,7 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
     C->cur ^= 1;
     C->t = C->clipped ? C->t_end : C->t + h;
     C->accepted += 1;
+    if (C->rec_index >= 0) C->rec_index += 1;
     C->dt_min_seen = fmin(C->dt_min_seen, h);
     C->dt_max_seen = fmax(C->dt_max_seen, h);
     for (int n = 0; n < N; ++n) {
@@ -428,6 +385,16 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
 #pragma unroll
         for (int c = 0; c < 3; ++c) m[s][c] = src.ld((s * 3 + c) * nc + i);
   }
+  // recording for the discrete adjoint: keep every stage input of the step
+  const int ri = (METHOD == MMI_RK4 && ST >= 1) ? C->rec_index : -1;
+  if (METHOD == MMI_RK4 && ST >= 1 && ri >= 0 && valid) {
+    float* R = D.rec_m + ((size_t)ri * 4 + (ST - 1)) * (size_t)(3 * S * nc);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+      if (s < S)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) R[(s * 3 + c) * nc + i] = m[s][c];
+  }
   const bool need_torque = !(METHOD == MMI_RK4 && ST == 0);
   if (need_torque && mag) {
     // cavity feedback sum_n h0_n u_n Re[e^{-i Phi_n} a_n]
@@ -528,7 +495,9 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
       if (step_end) {
         float v0 = nx_[s][0], v1 = nx_[s][1], v2 = nx_[s][2];
         if (mag) {
-          const float inv = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+          const float nrm = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+          if (METHOD == MMI_RK4 && ri >= 0) D.rec_norm[(size_t)ri * S * nc + s * nc + i] = nrm;
+          const float inv = 1.0f / nrm;
           v0 *= inv;
           v1 *= inv;
           v2 *= inv;

@@ -24,4 +24,6 @@ hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstD
 hipError_t mmk_launch_fft_zc(int TW, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              const float2* tw, hipStream_t s);
 hipError_t mmk_set_lds_limits();
+hipError_t mmk_launch_adj(int kind, int stage, int nblocks, int count, const InstDesc* d, const int* wg,
+                          hipStream_t s);
 hipError_t mmk_launch_gather_done(int count, const InstDesc* d, int* out, hipStream_t s);

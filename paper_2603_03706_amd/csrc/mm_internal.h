@@ -18,7 +18,7 @@
 #define MMI_SLOT_ERR 64
 #define MMI_SLOT_BAD 65
 
-enum { MMI_RK4 = 0, MMI_DP45 = 1 };
+enum { MMI_RK4 = 0, MMI_DP45 = 1, MMI_ADJ = 2 };
 
 // Mutable per-instance control block (device memory).
 struct InstCtl {
@@ -39,6 +39,18 @@ struct InstCtl {
   long long trace_n, trace_max, trace_steps, trace_stride;
   double trace_t0, trace_dt;
   int trace_on, trace_started;
+  // discrete adjoint of fixed-step RK4
+  int rec_index;                      // recorded step within the segment (-1: not recording)
+  int pad1;
+  double adj_h;                       // step of the recorded run
+  double rec_a_pad;
+  double la[MMI_MAX_MODES][2];        // adjoint of a at the step start (accumulator)
+  double lza[MMI_MAX_MODES][2];       // adjoint of a after the step
+  double lka[MMI_MAX_MODES][2];       // adjoint of the current stage derivative of a
+  double lmm[MMI_MAX_MODES][2];       // adjoint of m^- at the current stage
+  double grad_g[MMI_MAX_MODES];
+  double grad_alpha;
+  double grad_B0[3];
 };
 
 // Read-only per-instance descriptor (device memory).
@@ -54,6 +66,7 @@ struct InstDesc {
   float csign[2];
   float bd_scale;                     // -mu0 Ms / (Px Py Pz)
   double inv_ngeo;
+  double gamma;                       // gyromagnetic ratio [rad/(s T)]
   double omega[MMI_MAX_MODES], kappa[MMI_MAX_MODES], g[MMI_MAX_MODES];
   double cphi[MMI_MAX_MODES], sphi[MMI_MAX_MODES], h0[MMI_MAX_MODES];
   // device buffers
@@ -73,7 +86,23 @@ struct InstDesc {
   float2* fy;                         // [Kx][3][nz][Py] (split path)
   const float* kern;                  // [6][Pz/2+1][Py/2+1][Kx]
   int px, py, pz, kx;
+  // discrete adjoint (RK4): recorded segment and adjoint fields
+  float* rec_m;                       // [K+1][4][S*3*cells] stage inputs of each recorded step
+  float* rec_norm;                    // [K][S*cells] |z| before the renormalisation
+  double* rec_a;                      // [K][4][N][2] cavity stage inputs
+  float* lam_y;                       // adjoint of the step start state
+  float* lam_k;                       // adjoint of the current stage derivative
+  float* lam_z;                       // adjoint of the pre-normalisation sum
+  float* mu;                          // direct part of the stage VJP
+  float* lam_B;                       // adjoint of the effective field
+  double* grad_u;                     // [N][cells] accumulator (null: not requested)
 };
+
+// adjoint partial-record slots (doubles), reusing the forward partials
+#define MMI_ASLOT_FB 0                // [N]   sum_s,i lambda_Bx c_s u_n
+#define MMI_ASLOT_MM 16               // [2N]  sum u_n G c_s (m_x - i m_y) of the stage state
+#define MMI_ASLOT_ALPHA 48            // dL/dalpha contribution
+#define MMI_ASLOT_B0 49               // [3] dL/dB0 contribution
 
 // Dormand-Prince 5(4) coefficients.
 struct DPCoef {

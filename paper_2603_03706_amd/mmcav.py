@@ -71,6 +71,8 @@ _SIGS = {
     "mm_batch_destroy": (ctypes.c_int, [_P]),
     "mm_batch_profile": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P,
                                         ctypes.POINTER(ctypes.c_int32)]),
+    "mm_run_record": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32]),
+    "mm_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "mm_demag_tensor": (ctypes.c_int, [ctypes.c_double] * 6 + [_P]),
     "mm_last_error": (ctypes.c_char_p, []),
 }
@@ -192,6 +194,26 @@ class Context:
 
     def run(self, T, tol=0.0):
         _check(self._lib.mm_run(self.h, float(T), float(tol)))
+
+    def run_record(self, T, checkpoint_every=256):
+        _check(self._lib.mm_run_record(self.h, float(T), int(checkpoint_every)))
+
+    def adjoint(self, dL_da, dL_dm=None):
+        """Gradients of the loss of the recorded run; dL_da complex (N,)."""
+        nx, ny, nz = self.grid
+        dl = np.asarray(dL_da, np.complex128)
+        buf = np.ascontiguousarray(np.stack([dl.real, dl.imag], axis=-1).reshape(-1))
+        dm = None if dL_dm is None else np.ascontiguousarray(dL_dm, np.float32)
+        gu = np.zeros((max(self.N, 1), nz, ny, nx), np.float32)
+        gg = np.zeros(max(self.N, 1))
+        ga = np.zeros(1)
+        gb = np.zeros(3)
+        ga0 = np.zeros(2 * max(self.N, 1))
+        gm0 = np.zeros((self.S, 3, nz, ny, nx), np.float32)
+        _check(self._lib.mm_adjoint(self.h, _ptr(buf), _ptr(dm), _ptr(gu), _ptr(gg), _ptr(ga), _ptr(gb),
+                                    _ptr(ga0), _ptr(gm0)))
+        return {"u": gu[:self.N], "g": gg[:self.N], "alpha": float(ga[0]), "B0": gb,
+                "a0": ga0[0:2 * self.N:2] + 1j * ga0[1:2 * self.N:2], "m0": gm0}
 
     def get_m(self):
         nx, ny, nz = self.grid

@@ -1,0 +1,85 @@
+"""Discrete adjoint on the GPU (through the C ABI) against the oracle's
+autograd gradient of the same FP64 discrete map (relative error <= 1e-3),
+over several checkpoint segments with a ragged last segment."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.adjoint import run_with_grad
+from oracle.model import Problem
+from paper_2603_03706_amd import workloads as W
+from tests.helpers import gpu_for, variant
+
+pytestmark = pytest.mark.gpu
+
+TWO_PI = 2 * math.pi
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.complex128 if np.iscomplexobj(a) or np.iscomplexobj(b) else np.float64)
+    b = np.asarray(b, dtype=a.dtype)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _check(inst, steps, every, mode=1, tol=1e-3, demag_free_ok=True):
+    T = steps * inst.dt0
+    prob = Problem(**inst.oracle_kwargs())
+
+    def loss(m, a):
+        return a[mode].real ** 2 + a[mode].imag ** 2
+
+    L, g_ref, status = run_with_grad(prob, inst.m0.astype(np.float64), inst.a0, inst.dt0, T, loss)
+    assert status == 0
+    ctx = gpu_for(inst)
+    ctx.run_record(T, every)
+    aT = ctx.get_a()
+    dl = np.zeros(len(inst.omega), complex)
+    dl[mode] = 2 * aT[mode]
+    g = ctx.adjoint(dl)
+    # the state is left at the end of the recorded run
+    assert np.allclose(ctx.get_a(), aT, rtol=0, atol=0)
+    assert _rel(g["u"], g_ref["u"]) <= tol
+    assert _rel(g["g"], g_ref["g"]) <= tol
+    assert abs(g["alpha"] - g_ref["alpha"]) <= tol * abs(g_ref["alpha"])
+    assert _rel(g["B0"], g_ref["B0"]) <= tol
+    assert _rel(g["a0"], g_ref["a0"]) <= tol
+    assert _rel(g["m0"], g_ref["m0"]) <= 5 * tol
+    return g, g_ref
+
+
+def test_adjoint_film_fft_demag_profiled_modes():
+    inst = W.multimode_film(8, 6, 3)
+    rng = np.random.default_rng(12)
+    m0 = inst.m0.astype(np.float64).copy()
+    m0[0, 0] += 0.05 * rng.normal(size=m0.shape[2:])
+    m0[0, 1] += 0.05 * rng.normal(size=m0.shape[2:])
+    inst = variant(inst, method="rk4", dt0=0.5e-12, alpha=0.01, m0=m0.astype(np.float32),
+                   a0=np.array([1.0, 0.2j, 0.0, 0.1]), phi=np.array([0.0, 0.4, 1.2, 0.0]))
+    _check(inst, steps=30, every=7)
+
+
+def test_adjoint_afm_neel_coupling():
+    inst = W.afm_instance(2, size=8, nz=3)      # phase pi/2, signs (+1, -1)
+    m0 = inst.m0.astype(np.float64).copy()
+    x = (np.arange(8) + 0.5) / 8
+    m0[:, 0] += 0.05 * np.cos(np.pi * x)[None, None, None, :] * np.array([1, -1]).reshape(2, 1, 1, 1)
+    inst = variant(inst, method="rk4", dt0=2e-14, m0=m0.astype(np.float32), a0=np.array([0.3 + 0.1j]))
+    _check(inst, steps=24, every=5, mode=0)
+
+
+def test_adjoint_local_demag_geometry_anisotropy():
+    grid = (7, 5, 4)
+    geo = (np.random.default_rng(2).uniform(size=(4, 5, 7)) > 0.25).astype(np.uint8)
+    rng = np.random.default_rng(8)
+    m = rng.normal(size=(1, 3, 4, 5, 7))
+    m[:, 2] += 3.0
+    m /= np.linalg.norm(m, axis=1, keepdims=True)
+    m[:, 2] += (1 - geo)[None]
+    inst = W.Instance(grid=grid, cell=(4e-9, 5e-9, 6e-9), Ms=300e3, Aex=5e-12, alpha=0.02, Ku=2e4,
+                      ku_axis=(0.2, 0.3, 1.0), B0=(0.02, -0.01, 0.1), demag=W.DEMAG_LOCAL, n_local=(0.2, 0.3, 0.5),
+                      geometry=geo, omega=np.array([TWO_PI * 6e9, TWO_PI * 7e9]), kappa=np.array([1e7, 3e7]),
+                      g=np.array([TWO_PI * 40e6, TWO_PI * 20e6]), m0=m.astype(np.float32),
+                      a0=np.array([0.1, -0.2j]), method="rk4", dt0=0.2e-12)
+    _check(inst, steps=20, every=20, mode=1)
