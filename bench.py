@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-afm", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=512)
+    ap.add_argument("--afm-steps", type=int, default=20)
     return ap.parse_args()
 
 
@@ -81,6 +85,72 @@ def plain_rate(insts, k, steps, warmup, tol):
         b.close()
         c.close()
     return total / k, acc / k
+
+
+def adjoint_ratio(steps, every):
+    """Adjoint cost on the multimode film (128 x 128 x 32, 4 profiled modes,
+    FFT demag), RK4 at 0.5 ps: plain forward run vs recorded run vs adjoint
+    (checkpoint every `every` steps), loss |a_2(T)|^2."""
+    import numpy as np
+    import torch
+    from paper_2603_03706_amd import mmcav, workloads as W
+    inst = W.adjoint_film()
+    T = steps * inst.dt0
+    c = mmcav.Context.from_instance(inst)
+    c.run(10 * inst.dt0)                      # warm-up (graph capture, first launch)
+    c.set_m(inst.m0)
+    c.set_a(inst.a0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.run(T)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    c.set_m(inst.m0)
+    c.set_a(inst.a0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c.run_record(T, every)
+    torch.cuda.synchronize()
+    t_rec = time.perf_counter() - t0
+    a = c.get_a()
+    dl = np.zeros(4, complex)
+    dl[1] = 2 * a[1]
+    t0 = time.perf_counter()
+    g = c.adjoint(dl)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    c.close()
+    return {"workload": f"multimode film 128x128x32, 4 profiled modes, FFT demag, RK4 dt 0.5 ps, {steps} steps, "
+                        f"checkpoint every {every}",
+            "forward_s": t_fwd, "record_s": t_rec, "adjoint_s": t_adj,
+            "adjoint_over_forward": t_adj / t_fwd, "record_plus_adjoint_over_forward": (t_rec + t_adj) / t_fwd,
+            "grad_g": [float(v) for v in g["g"]]}
+
+
+def afm_batch(steps, tol):
+    """AFM batch: 32 two-sublattice instances of 64^2x16 .. 256^2x16 at 2 nm,
+    DP45: batched steps vs the same instances stepped one after another."""
+    import torch
+    from paper_2603_03706_amd import mmcav, workloads as W
+    insts = [W.afm_instance(k) for k in range(32)]
+    ctxs = [mmcav.Context.from_instance(i) for i in insts]
+    b = mmcav.Batch(ctxs)
+    b.step(10, tol)
+    dt, acc = timed_steps(b, ctxs, steps, tol)
+    cells = sum(i.cells * 2 for i in insts)
+    b.close()
+    plain = 0.0
+    for inst, c in zip(insts, ctxs):
+        pb = mmcav.Batch([c])
+        pb.step(2, tol)
+        d, _ = timed_steps(pb, [c], steps, tol)
+        plain += d
+        pb.close()
+    for c in ctxs:
+        c.close()
+    return {"workload": "AFM batch: 32 instances, 64^2x16 .. 256^2x16, 2 sublattices, 2 nm, DP45 tol 1e-6",
+            "sublattice_cells": cells, "batched_s": dt, "plain_sequential_s": plain,
+            "batched_vs_plain": plain / dt, "batched_cell_updates_per_s": cells * acc / len(insts) / dt}
 
 
 def cpu_baseline(inst, seconds, tol):
@@ -152,6 +222,17 @@ def main():
         print(f"[bench] plain: {t_plain / args.steps * 1e3:.3f} ms/step per instance ({k} measured), "
               f"batched {batched_per_step * 1e3:.3f} ms/step for {len(insts)}", file=sys.stderr, flush=True)
 
+    adj = None
+    if not args.no_adjoint:
+        print("[bench] adjoint leg", file=sys.stderr, flush=True)
+        adj = adjoint_ratio(args.adjoint_steps, 256)
+        print(f"[bench] adjoint: {json.dumps(adj)}", file=sys.stderr, flush=True)
+    afm = None
+    if not args.no_afm:
+        print("[bench] AFM batch leg", file=sys.stderr, flush=True)
+        afm = afm_batch(args.afm_steps, args.tol)
+        print(f"[bench] afm: {json.dumps(afm)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(insts[0], args.cpu_seconds, args.tol)
@@ -176,7 +257,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched_vs_plain": speedup,
-        "adjoint_over_forward": None,
+        "adjoint_over_forward": None if adj is None else adj["adjoint_over_forward"],
+        "adjoint": adj,
+        "afm_batch": afm,
         "kernels": kernels,
     }
     print(json.dumps(out))

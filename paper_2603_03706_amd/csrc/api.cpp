@@ -110,7 +110,7 @@ struct Layout {
 };
 
 bool fused_fits(int py, int pz) {
-  const size_t lds = sizeof(float2) * ((size_t)3 * pz * (py + 1) + py + pz);
+  const size_t lds = sizeof(float2) * ((size_t)3 * pz * (py + 1) + py + pz) + sizeof(int) * 3 * (size_t)pz;
   return lds <= 160 * 1024;
 }
 
@@ -464,7 +464,7 @@ mm_status batch_build(mm_batch* b) {
     if (mm_status s = up(zc, &g.zc, &g.n_zc)) return s;
     g.lds_xf = sizeof(float2) * ((size_t)g.px * g.Wx + g.px);
     g.lds_xi = sizeof(float2) * ((size_t)g.px * g.Wx + (size_t)g.kx * 2 * g.Wx + g.px);
-    g.lds_yz = sizeof(float2) * ((size_t)3 * g.pz * (g.py + 1) + g.py + g.pz);
+    g.lds_yz = sizeof(float2) * ((size_t)3 * g.pz * (g.py + 1) + g.py + g.pz) + sizeof(int) * 3 * (size_t)g.nz;
     g.lds_y = sizeof(float2) * ((size_t)g.py * g.Wy + g.py);
     g.lds_zc = sizeof(float2) * ((size_t)g.pz * 3 * g.TW + g.pz);
   }

@@ -265,7 +265,142 @@ __global__ __launch_bounds__(256) void k_fft_xi(const InstDesc* __restrict__ des
 }
 
 // ------------------------------------------------------- fused y-z pass
-// work item = kx of one instance; LDS [3][Pz][Py+1] + twiddles
+// In-place radix-2^2 butterflies shared by the line FFTs below.
+// DIF (forward): elements p0, p0+e1, p0+e2, p0+e2+e1 with e1 = q, e2 = h = 2q.
+__device__ __forceinline__ void dif4(float2* lds, int p0, int e1, int e2, float2 w1, float2 w2) {
+  const float2 x0 = lds[p0], x1 = lds[p0 + e1], x2 = lds[p0 + e2], x3 = lds[p0 + e2 + e1];
+  const float2 a0 = cadd(x0, x2), a1 = cadd(x1, x3);
+  const float2 a2 = cmul(csub(x0, x2), w1);
+  const float2 a3 = rot<false>(cmul(csub(x1, x3), w1));
+  lds[p0] = cadd(a0, a1);
+  lds[p0 + e1] = cmul(csub(a0, a1), w2);
+  lds[p0 + e2] = cadd(a2, a3);
+  lds[p0 + e2 + e1] = cmul(csub(a2, a3), w2);
+}
+// DIT (inverse): elements p0 + k e1, k = 0..3, conjugate twiddles wA, wB given.
+__device__ __forceinline__ void dit4(float2* lds, int p0, int e1, float2 wA, float2 wB) {
+  const float2 x0 = lds[p0], x1 = lds[p0 + e1], x2 = lds[p0 + 2 * e1], x3 = lds[p0 + 3 * e1];
+  const float2 t1 = cmul(x1, wA), t3 = cmul(x3, wA);
+  const float2 a0 = cadd(x0, t1), a1 = csub(x0, t1), a2 = cadd(x2, t3), a3 = csub(x2, t3);
+  const float2 u = cmul(a2, wB), v = rot<true>(cmul(a3, wB));
+  lds[p0] = cadd(a0, u);
+  lds[p0 + 2 * e1] = csub(a0, u);
+  lds[p0 + e1] = cadd(a1, v);
+  lds[p0 + 3 * e1] = csub(a1, v);
+}
+__device__ __forceinline__ void bf2(float2* lds, int p, int e) {
+  const float2 a = lds[p], b = lds[p + e];
+  lds[p] = cadd(a, b);
+  lds[p + e] = csub(a, b);
+}
+
+// Lines along a contiguous axis (element stride 1), line bases in tab[].
+// Consecutive threads take consecutive butterflies of a line.
+template <int T, bool DIT>
+__device__ void fft_rows(float2* lds, int L, int lg, int NL, const int* tab, const float2* twl) {
+  if (lg == 0) return;
+  if (!DIT) {
+    int s = 0;
+    for (; s + 2 <= lg; s += 2) {
+      const int h = L >> (s + 1), q = h >> 1, lq = lg - s - 2, lgQ = lg - 2;
+      const int NB = NL << lgQ;
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
+        const int r = idx & ((1 << lgQ) - 1), l = idx >> lgQ;
+        const int g = r >> lq, i = r & (q - 1);
+        dif4(lds, tab[l] + g * 2 * h + i, q, h, twl[i << s], twl[i << (s + 1)]);
+      }
+      __syncthreads();
+    }
+    if (s < lg) {
+      const int NB = NL << (lg - 1);
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
+        const int m = idx & ((1 << (lg - 1)) - 1), l = idx >> (lg - 1);
+        bf2(lds, tab[l] + 2 * m, 1);
+      }
+      __syncthreads();
+    }
+  } else {
+    int t = 0;
+    if (lg & 1) {
+      const int NB = NL << (lg - 1);
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
+        const int m = idx & ((1 << (lg - 1)) - 1), l = idx >> (lg - 1);
+        bf2(lds, tab[l] + 2 * m, 1);
+      }
+      __syncthreads();
+      t = 1;
+    }
+    for (; t + 2 <= lg; t += 2) {
+      const int q = 1 << t, lgQ = lg - 2;
+      const int NB = NL << lgQ;
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
+        const int r = idx & ((1 << lgQ) - 1), l = idx >> lgQ;
+        const int g = r >> t, i = r & (q - 1);
+        dit4(lds, tab[l] + g * 4 * q + i, q, twid<true>(twl, i << (lg - t - 1)),
+             twid<true>(twl, i << (lg - t - 2)));
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Lines along a strided axis: line (c, j) of NC groups of 2^lgJ adjacent
+// lines, element stride es, group stride cs.  Consecutive threads take
+// adjacent lines.
+template <int T, bool DIT>
+__device__ void fft_cols(float2* lds, int L, int lg, int NC, int lgJ, int cs, int es, const float2* twl) {
+  if (lg == 0) return;
+  const int J = 1 << lgJ;
+  if (!DIT) {
+    int s = 0;
+    for (; s + 2 <= lg; s += 2) {
+      const int h = L >> (s + 1), q = h >> 1, lq = lg - s - 2, lgQ = lg - 2;
+      const int NB = (NC << lgQ) << lgJ;
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
+        const int j = idx & (J - 1), rest = idx >> lgJ;
+        const int r = rest & ((1 << lgQ) - 1), c = rest >> lgQ;
+        const int g = r >> lq, i = r & (q - 1);
+        dif4(lds, c * cs + j + (g * 2 * h + i) * es, q * es, h * es, twl[i << s], twl[i << (s + 1)]);
+      }
+      __syncthreads();
+    }
+    if (s < lg) {
+      const int NB = (NC << (lg - 1)) << lgJ;
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
+        const int j = idx & (J - 1), rest = idx >> lgJ;
+        const int m = rest & ((1 << (lg - 1)) - 1), c = rest >> (lg - 1);
+        bf2(lds, c * cs + j + 2 * m * es, es);
+      }
+      __syncthreads();
+    }
+  } else {
+    int t = 0;
+    if (lg & 1) {
+      const int NB = (NC << (lg - 1)) << lgJ;
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
+        const int j = idx & (J - 1), rest = idx >> lgJ;
+        const int m = rest & ((1 << (lg - 1)) - 1), c = rest >> (lg - 1);
+        bf2(lds, c * cs + j + 2 * m * es, es);
+      }
+      __syncthreads();
+      t = 1;
+    }
+    for (; t + 2 <= lg; t += 2) {
+      const int q = 1 << t, lgQ = lg - 2;
+      const int NB = (NC << lgQ) << lgJ;
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
+        const int j = idx & (J - 1), rest = idx >> lgJ;
+        const int r = rest & ((1 << lgQ) - 1), c = rest >> lgQ;
+        const int g = r >> t, i = r & (q - 1);
+        dit4(lds, c * cs + j + (g * 4 * q + i) * es, q * es, twid<true>(twl, i << (lg - t - 1)),
+             twid<true>(twl, i << (lg - t - 2)));
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// work item = kx of one instance; LDS [3][Pz][Py+1] + twiddles + y-line table
 #define MM_YZ_T 1024
 __global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__ descs,
                                                     const WorkItem* __restrict__ work,
@@ -281,8 +416,13 @@ __global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__
   float2* buf = lds;
   float2* twy = lds + 3 * plane;
   float2* twz = twy + Py;
+  int* ytab = reinterpret_cast<int*>(twz + Pz);    // 3 nz line bases
   load_twiddles(twy, Py, tw, MM_YZ_T);
   load_twiddles(twz, Pz, tw, MM_YZ_T);
+  for (int l = threadIdx.x; l < 3 * nz; l += MM_YZ_T) {
+    const int c = l / nz, z = l - c * nz;
+    ytab[l] = c * plane + z * RP;
+  }
   for (int e = threadIdx.x; e < 3 * plane; e += MM_YZ_T) buf[e] = make_float2(0.f, 0.f);
   __syncthreads();
   const int nyz = ny * nz;
@@ -293,14 +433,12 @@ __global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__
     buf[c * plane + z * RP + y] = X[e];
   }
   __syncthreads();
-  const LineMap ylines{nz, RP, plane, 1};
-  const LineMap zlines{Py, 1, plane, RP};
   const int lgy = ilog2(Py), lgz = ilog2(Pz);
-  fft_dif<MM_YZ_T>(buf, Py, lgy, 3 * nz, ylines, twy);
-  fft_dif<MM_YZ_T>(buf, Pz, lgz, 3 * Py, zlines, twz);
+  fft_rows<MM_YZ_T, false>(buf, Py, lgy, 3 * nz, ytab, twy);
+  fft_cols<MM_YZ_T, false>(buf, Pz, lgz, 3, lgy, plane, RP, twz);
   // spectra sit at bit-reversed positions in y and z
   for (int e = threadIdx.x; e < Pz * Py; e += MM_YZ_T) {
-    const int pz_ = e / Py, py_ = e - pz_ * Py;
+    const int pz_ = e >> lgy, py_ = e & (Py - 1);
     const int o = pz_ * RP + py_;
     float2 mx = buf[o], my = buf[plane + o], mz = buf[2 * plane + o];
     kernel_mul(D, kx, brev(py_, lgy), brev(pz_, lgz), mx, my, mz);
@@ -309,8 +447,8 @@ __global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__
     buf[2 * plane + o] = mz;
   }
   __syncthreads();
-  fft_dit<MM_YZ_T>(buf, Pz, lgz, 3 * Py, zlines, twz);
-  fft_dit<MM_YZ_T>(buf, Py, lgy, 3 * nz, ylines, twy);
+  fft_cols<MM_YZ_T, true>(buf, Pz, lgz, 3, lgy, plane, RP, twz);
+  fft_rows<MM_YZ_T, true>(buf, Py, lgy, 3 * nz, ytab, twy);
   for (int e = threadIdx.x; e < 3 * nyz; e += MM_YZ_T) {
     const int c = e / nyz, yz = e - c * nyz;
     const int z = yz / ny, y = yz - z * ny;
