@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-afm", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=512)
     ap.add_argument("--afm-steps", type=int, default=20)
@@ -186,6 +187,10 @@ def main():
 
     insts, ctxs, batch = build_batch(args.instances, args.tol)
     cells = sum(i.cells for i in insts)
+    tuning = None
+    if not args.no_tune:
+        tuning = batch.tune()
+        print(f"[bench] fft tuning: {json.dumps(tuning)}", file=sys.stderr, flush=True)
     print(f"[bench] {len(insts)} instances, {cells} cells; warmup {args.warmup} steps", file=sys.stderr, flush=True)
     batch.step(args.warmup, args.tol)
     torch.cuda.synchronize()
@@ -253,7 +258,9 @@ def main():
         "config": {"workload": f"field sweep: {len(insts)} YIG spheres (diameter 32 cells) on 32^3 grids at 5 nm, "
                                f"FFT demag on 64^3, 1 uniform mode, DP45 tol {args.tol:g}, batched",
                    "instances": len(insts), "grid": [32, 32, 32], "method": "dp45", "tol": args.tol,
-                   "accepted_fraction": acc / (args.steps * len(insts))},
+                   "accepted_fraction": acc / (args.steps * len(insts)),
+                   "fft_tiles": None if tuning is None else [{k: t[k] for k in ("grid", "Wx", "path", "Wy", "TW")}
+                                                            for t in tuning]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched_vs_plain": speedup,

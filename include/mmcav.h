@@ -178,6 +178,13 @@ mm_status mm_batch_run(mm_batch* b, double T, double tol);
 mm_status mm_batch_step(mm_batch* b, int64_t steps, double tol);
 mm_status mm_batch_destroy(mm_batch* b);
 
+/* Autotune the demag FFT of every grid shape in the batch: times the x
+ * passes for each tile width and the y-z work either fused in one LDS-resident
+ * kernel or split into y / z passes for each tile shape, on the current
+ * state, and keeps the fastest.  The state is not advanced.  A JSON summary
+ * of the timings and choices is written to report (may be NULL). */
+mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len);
+
 /* Per-kernel timing: run `steps` steps eagerly, timing each launch with HIP
  * events on the library stream.  Fills up to `cap` entries: names (each
  * char[48]), launches, total milliseconds, algorithmic bytes per launch

@@ -109,10 +109,20 @@ struct Layout {
   bool fft, split;
 };
 
-bool fused_fits(int py, int pz) {
-  const size_t lds = sizeof(float2) * ((size_t)3 * pz * (py + 1) + py + pz) + sizeof(int) * 3 * (size_t)pz;
-  return lds <= 160 * 1024;
+size_t fused_lds(int ny, int nz, int py, int pz, int tk) {
+  (void)ny;
+  return sizeof(float2) * ((size_t)3 * nz * (py + 1) + (size_t)3 * pz * tk + py + pz) + sizeof(int) * 3 * (size_t)nz;
 }
+
+// z-tile width of the fused y-z kernel: the widest power of two <= 16 that
+// fits, or 0 when even a single column does not
+int fused_tile(int ny, int nz, int py, int pz) {
+  for (int tk = std::min(16, py); tk >= 1; tk /= 2)
+    if (fused_lds(ny, nz, py, pz, tk) <= 160 * 1024) return tk;
+  return 0;
+}
+
+bool fused_fits(int ny, int nz, int py, int pz) { return fused_tile(ny, nz, py, pz) > 0; }
 
 Layout make_layout(const mm_params& p, int n_modes) {
   Layout L{};
@@ -124,7 +134,7 @@ Layout make_layout(const mm_params& p, int n_modes) {
   L.py = mmh::padded(p.ny);
   L.pz = mmh::padded(p.nz);
   L.kx = L.px / 2 + 1;
-  L.split = L.fft && !fused_fits(L.py, L.pz);
+  L.split = L.fft && !fused_fits(p.ny, p.nz, L.py, L.pz);
   const size_t vec = align_up(sizeof(float) * 3 * L.S * (size_t)L.ncell);
   size_t o = 0;
   L.ctl = o; o += align_up(sizeof(InstCtl));
@@ -136,7 +146,7 @@ Layout make_layout(const mm_params& p, int n_modes) {
   if (L.fft) {
     L.bd = o; o += align_up(sizeof(float) * 3 * (size_t)L.ncell);
     L.fx = o; o += align_up(sizeof(float2) * (size_t)L.kx * 3 * p.nz * p.ny);
-    if (L.split) { L.fy = o; o += align_up(sizeof(float2) * (size_t)L.kx * 3 * p.nz * L.py); }
+    L.fy = o; o += align_up(sizeof(float2) * (size_t)L.kx * 3 * p.nz * L.py);   // split path (tunable)
   }
   L.fixed_end = o;
   L.u = o;
@@ -240,7 +250,7 @@ struct mm_batch {
   struct Group {
     int nx, ny, nz, px, py, pz, kx;
     bool split;
-    int Wx, Wy, TW;
+    int Wx, Wy, TW, TK = 1;
     WorkItem *xf = nullptr, *yz = nullptr, *y = nullptr, *zc = nullptr;
     int n_xf = 0, n_yz = 0, n_y = 0, n_zc = 0;
     size_t lds_xf = 0, lds_xi = 0, lds_yz = 0, lds_y = 0, lds_zc = 0;
@@ -372,7 +382,7 @@ mm_status upload_desc(mm_ctx* c) {
   if (L.fft) {
     d.bd = (float*)(w + L.bd);
     d.fx = (float2*)(w + L.fx);
-    d.fy = L.split ? (float2*)(w + L.fy) : nullptr;
+    d.fy = (float2*)(w + L.fy);
     d.kern = c->spec ? c->spec->dev : nullptr;
   }
   if (c->adj_on) {
@@ -395,6 +405,47 @@ mm_status upload_desc(mm_ctx* c) {
 
 // ------------------------------------------------------------- batches
 double algorithmic_bytes(const mm_batch* b, const std::string& name);
+
+// Work tables and LDS sizes of one FFT group for its current tile choice.
+mm_status build_group(mm_batch::Group& g) {
+  for (WorkItem** p : {&g.xf, &g.yz, &g.y, &g.zc})
+    if (*p) {
+      hipFree(*p);
+      *p = nullptr;
+    }
+  const int rows = 3 * g.ny * g.nz;
+  const int tiles_x = (rows + 2 * g.Wx - 1) / (2 * g.Wx);
+  std::vector<WorkItem> xf, yz, yy, zc;
+  const int ylines = g.kx * 3 * g.nz;
+  const int tiles_y = (ylines + g.Wy - 1) / g.Wy;
+  const int ky_tiles = (g.py + g.TW - 1) / g.TW;
+  for (int m : g.members) {
+    for (int t = 0; t < tiles_x; ++t) xf.push_back({m, t});
+    if (!g.split) {
+      for (int k = 0; k < g.kx; ++k) yz.push_back({m, k});
+    } else {
+      for (int t = 0; t < tiles_y; ++t) yy.push_back({m, t});
+      for (int k = 0; k < g.kx * ky_tiles; ++k) zc.push_back({m, k});
+    }
+  }
+  auto up = [&](std::vector<WorkItem>& v, WorkItem** dst, int* cnt) -> mm_status {
+    *cnt = (int)v.size();
+    if (v.empty()) return MM_OK;
+    MM_HIP(hipMalloc(dst, sizeof(WorkItem) * v.size()));
+    MM_HIP(hipMemcpy(*dst, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
+    return MM_OK;
+  };
+  if (mm_status s = up(xf, &g.xf, &g.n_xf)) return s;
+  if (mm_status s = up(yz, &g.yz, &g.n_yz)) return s;
+  if (mm_status s = up(yy, &g.y, &g.n_y)) return s;
+  if (mm_status s = up(zc, &g.zc, &g.n_zc)) return s;
+  g.lds_xf = sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + g.px);
+  g.lds_xi = sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + (size_t)g.kx * 2 * g.Wx + g.px);
+  g.lds_yz = fused_lds(g.ny, g.nz, g.py, g.pz, g.TK);
+  g.lds_y = sizeof(float2) * ((size_t)g.py * (g.Wy + 1) + g.py);
+  g.lds_zc = sizeof(float2) * ((size_t)g.pz * 3 * g.TW + g.pz);
+  return MM_OK;
+}
 
 mm_status batch_build(mm_batch* b) {
   const int n = (int)b->ctxs.size();
@@ -436,37 +487,8 @@ mm_status batch_build(mm_batch* b) {
     int tw = 1;
     while (tw * 2 <= 16 && 3 * (tw * 2) * g.pz <= 2048) tw *= 2;
     g.TW = tw;
-    const int rows = 3 * g.ny * g.nz;
-    const int tiles_x = (rows + 2 * g.Wx - 1) / (2 * g.Wx);
-    std::vector<WorkItem> xf, yz, yy, zc;
-    const int ylines = g.kx * 3 * g.nz;
-    const int tiles_y = (ylines + g.Wy - 1) / g.Wy;
-    const int ky_tiles = (g.py + g.TW - 1) / g.TW;
-    for (int m : g.members) {
-      for (int t = 0; t < tiles_x; ++t) xf.push_back({m, t});
-      if (!g.split) {
-        for (int k = 0; k < g.kx; ++k) yz.push_back({m, k});
-      } else {
-        for (int t = 0; t < tiles_y; ++t) yy.push_back({m, t});
-        for (int k = 0; k < g.kx * ky_tiles; ++k) zc.push_back({m, k});
-      }
-    }
-    auto up = [&](std::vector<WorkItem>& v, WorkItem** dst, int* cnt) -> mm_status {
-      *cnt = (int)v.size();
-      if (v.empty()) return MM_OK;
-      MM_HIP(hipMalloc(dst, sizeof(WorkItem) * v.size()));
-      MM_HIP(hipMemcpy(*dst, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
-      return MM_OK;
-    };
-    if (mm_status s = up(xf, &g.xf, &g.n_xf)) return s;
-    if (mm_status s = up(yz, &g.yz, &g.n_yz)) return s;
-    if (mm_status s = up(yy, &g.y, &g.n_y)) return s;
-    if (mm_status s = up(zc, &g.zc, &g.n_zc)) return s;
-    g.lds_xf = sizeof(float2) * ((size_t)g.px * g.Wx + g.px);
-    g.lds_xi = sizeof(float2) * ((size_t)g.px * g.Wx + (size_t)g.kx * 2 * g.Wx + g.px);
-    g.lds_yz = sizeof(float2) * ((size_t)3 * g.pz * (g.py + 1) + g.py + g.pz) + sizeof(int) * 3 * (size_t)g.nz;
-    g.lds_y = sizeof(float2) * ((size_t)g.py * g.Wy + g.py);
-    g.lds_zc = sizeof(float2) * ((size_t)g.pz * 3 * g.TW + g.pz);
+    g.TK = std::max(1, fused_tile(g.ny, g.nz, g.py, g.pz));
+    if (mm_status s = build_group(g)) return s;
   }
   MM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   MM_HIP(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
@@ -520,7 +542,7 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1) {
       return s;
     if (!g.split) {
       if (mm_status s = launch(b, "fft_yz_convolve", [&] {
-            return mmk_launch_fft_yz(g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
+            return mmk_launch_fft_yz(g.TK, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
           }))
         return s;
     } else {
@@ -1380,6 +1402,122 @@ mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, 
     if (bytes_per_launch) bytes_per_launch[i] = b->prof[i].bytes;
   }
   *n = (int)b->prof.size();
+  return MM_OK;
+}
+
+mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
+  if (!b) return fail(MM_ERR_ARG, "NULL batch");
+  if (mm_status s = set_device(b->ctxs[0])) return s;
+  // make every instance runnable without touching its state
+  for (mm_ctx* c : b->ctxs) {
+    InstCtl h;
+    if (mm_status s = ctl_pull(c, h)) return s;
+    h.done = 0;
+    if (mm_status s = ctl_push(c, h)) return s;
+  }
+  if (mm_status s = refresh_descs(b)) return s;
+  hipEvent_t e0, e1;
+  MM_HIP(hipEventCreate(&e0));
+  MM_HIP(hipEventCreate(&e1));
+  std::string rep = "[";
+  const int reps = 3;
+  for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+    auto& g = b->groups[gi];
+    auto timed = [&](auto&& enqueue, double* us) -> mm_status {
+      MM_HIP(enqueue());
+      MM_HIP(hipEventRecord(e0, b->stream));
+      for (int r = 0; r < reps; ++r) MM_HIP(enqueue());
+      MM_HIP(hipEventRecord(e1, b->stream));
+      MM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      MM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      *us = 1e3 * ms / reps;
+      return MM_OK;
+    };
+    const size_t lds_cap = 64 * 1024;
+    // x passes: tile width
+    int bestW = g.Wx;
+    double bestT = 1e30;
+    std::string xrep;
+    for (int W = 2; W <= 32; W *= 2) {
+      if (sizeof(float2) * ((size_t)g.px * (W + 1) + (size_t)g.kx * 2 * W + g.px) > lds_cap) continue;
+      g.Wx = W;
+      if (mm_status s = build_group(g)) return s;
+      double us;
+      if (mm_status s = timed([&] {
+            hipError_t e = mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, b->method, 1, g_twiddle, b->stream);
+            if (e != hipSuccess) return e;
+            return mmk_launch_fft_xi(g.Wx, g.n_xf, g.lds_xi, b->d_desc, g.xf, g_twiddle, b->stream);
+          }, &us))
+        return s;
+      xrep += (xrep.empty() ? "" : ", ") + std::string("\"") + std::to_string(W) + "\": " + std::to_string(us);
+      if (us < bestT) { bestT = us; bestW = W; }
+    }
+    g.Wx = bestW;
+    // y-z passes: fused vs split with tile widths
+    bool bestSplit = g.split;
+    int bestWy = g.Wy, bestTW = g.TW;
+    double bestYZ = 1e30;
+    std::string yrep;
+    int bestTK = g.TK;
+    for (int tk = std::min(16, g.py); tk >= 1 && fused_fits(g.ny, g.nz, g.py, g.pz); tk /= 2) {
+      if (fused_lds(g.ny, g.nz, g.py, g.pz, tk) > 160 * 1024) continue;
+      g.split = false;
+      g.TK = tk;
+      if (mm_status s = build_group(g)) return s;
+      double us;
+      if (mm_status s = timed([&] { return mmk_launch_fft_yz(g.TK, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream); }, &us))
+        return s;
+      yrep += (yrep.empty() ? "" : ", ") + std::string("\"fused_") + std::to_string(tk) + "\": " + std::to_string(us);
+      if (us < bestYZ) { bestYZ = us; bestSplit = false; bestTK = tk; }
+      if (tk <= 2) break;
+    }
+    for (int Wy = 4; Wy <= 64; Wy *= 2) {
+      if (sizeof(float2) * ((size_t)g.py * (Wy + 1) + g.py) > lds_cap) continue;
+      for (int TW = 1; TW <= 16; TW *= 2) {
+        if (sizeof(float2) * ((size_t)g.pz * 3 * TW + g.pz) > lds_cap) continue;
+        g.split = true;
+        g.Wy = Wy;
+        g.TW = TW;
+        if (mm_status s = build_group(g)) return s;
+        double us;
+        if (mm_status s = timed([&] {
+              hipError_t e = mmk_launch_fft_y(-1, g.Wy, g.n_y, g.lds_y, b->d_desc, g.y, g_twiddle, b->stream);
+              if (e != hipSuccess) return e;
+              e = mmk_launch_fft_zc(g.TW, g.n_zc, g.lds_zc, b->d_desc, g.zc, g_twiddle, b->stream);
+              if (e != hipSuccess) return e;
+              return mmk_launch_fft_y(1, g.Wy, g.n_y, g.lds_y, b->d_desc, g.y, g_twiddle, b->stream);
+            }, &us))
+          return s;
+        yrep += (yrep.empty() ? "" : ", ") + std::string("\"split_") + std::to_string(Wy) + "_" +
+                std::to_string(TW) + "\": " + std::to_string(us);
+        if (us < bestYZ) { bestYZ = us; bestSplit = true; bestWy = Wy; bestTW = TW; }
+      }
+    }
+    g.split = bestSplit;
+    g.Wy = bestWy;
+    g.TW = bestTW;
+    g.TK = bestTK;
+    if (mm_status s = build_group(g)) return s;
+    rep += (gi ? ", " : "") + std::string("{\"grid\": [") + std::to_string(g.nx) + ", " + std::to_string(g.ny) + ", " +
+           std::to_string(g.nz) + "], \"instances\": " + std::to_string(g.members.size()) + ", \"Wx\": " +
+           std::to_string(g.Wx) + ", \"path\": \"" + (g.split ? "split" : "fused") + "\", \"Wy\": " +
+           std::to_string(g.Wy) + ", \"TW\": " + std::to_string(g.TW) + ", \"TK\": " + std::to_string(g.TK) + ", \"x_us\": {" + xrep +
+           "}, \"yz_us\": {" + yrep + "}}";
+  }
+  rep += "]";
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  // launch sequences changed: recapture on next use
+  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+  if (b->exec_rev) { hipGraphExecDestroy(b->exec_rev); b->exec_rev = nullptr; }
+  if (b->graph_rev) { hipGraphDestroy(b->graph_rev); b->graph_rev = nullptr; }
+  MM_HIP(hipStreamSynchronize(b->stream));
+  if (report && report_len) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
   return MM_OK;
 }
 

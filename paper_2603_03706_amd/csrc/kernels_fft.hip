@@ -21,11 +21,6 @@
 
 namespace mmk {
 
-struct LineMap {
-  int a, sa, sb, es;   // element j of line l at (l % a) * sa + (l / a) * sb + j * es
-  __device__ __forceinline__ int base(int l) const { return (l % a) * sa + (l / a) * sb; }
-};
-
 // Bit reversal of the low lg bits.
 __device__ __forceinline__ int brev(int p, int lg) {
   return lg ? (int)(__brev((unsigned)p) >> (32 - lg)) : 0;
@@ -45,226 +40,12 @@ __device__ __forceinline__ float2 twid(const float2* twl, int m) {
   return w;
 }
 
-// Forward DFT of NL lines of length L = 2^lg in LDS, decimation in
-// frequency: natural order in, bit-reversed order out (position p holds
-// frequency brev(p)).  Radix-2^2 passes (two radix-2 stages per pass, each
-// thread updating four elements in place), then one radix-2 stage when lg is
-// odd.  twl[m] = e^{-2 pi i m / L}.  Data must be visible (synced) on entry;
-// the result is visible on exit.
-template <int T>
-__device__ void fft_dif(float2* lds, int L, int lg, int NL, const LineMap& lm, const float2* twl) {
-  int s = 0;
-  for (; s + 2 <= lg; s += 2) {
-    const int h = L >> (s + 1), q = h >> 1;
-    const int lq = lg - s - 2;                 // log2(q)
-    const int NB = NL * (L >> 2);
-    for (int idx = threadIdx.x; idx < NB; idx += T) {
-      const int l = idx % NL, r = idx / NL;
-      const int g = r >> lq, i = r & (q - 1);
-      const int p0 = lm.base(l) + (g * 2 * h + i) * lm.es;
-      const int e1 = q * lm.es, e2 = h * lm.es;
-      const float2 x0 = lds[p0], x1 = lds[p0 + e1], x2 = lds[p0 + e2], x3 = lds[p0 + e2 + e1];
-      const float2 w1 = twl[i << s], w2 = twl[i << (s + 1)];
-      const float2 a0 = cadd(x0, x2), a1 = cadd(x1, x3);
-      const float2 a2 = cmul(csub(x0, x2), w1);
-      const float2 a3 = rot<false>(cmul(csub(x1, x3), w1));
-      lds[p0] = cadd(a0, a1);
-      lds[p0 + e1] = cmul(csub(a0, a1), w2);
-      lds[p0 + e2] = cadd(a2, a3);
-      lds[p0 + e2 + e1] = cmul(csub(a2, a3), w2);
-    }
-    __syncthreads();
-  }
-  if (s < lg) {
-    const int NB = NL * (L >> 1);
-    for (int idx = threadIdx.x; idx < NB; idx += T) {
-      const int l = idx % NL, m = idx / NL;
-      const int p = lm.base(l) + 2 * m * lm.es;
-      const float2 a = lds[p], b = lds[p + lm.es];
-      lds[p] = cadd(a, b);
-      lds[p + lm.es] = csub(a, b);
-    }
-    __syncthreads();
-  }
-}
-
-// Inverse (unscaled) DFT by decimation in time: bit-reversed order in,
-// natural order out.  Mirror image of fft_dif with conjugate twiddles.
-template <int T>
-__device__ void fft_dit(float2* lds, int L, int lg, int NL, const LineMap& lm, const float2* twl) {
-  int t = 0;
-  if (lg & 1) {
-    const int NB = NL * (L >> 1);
-    for (int idx = threadIdx.x; idx < NB; idx += T) {
-      const int l = idx % NL, m = idx / NL;
-      const int p = lm.base(l) + 2 * m * lm.es;
-      const float2 a = lds[p], b = lds[p + lm.es];
-      lds[p] = cadd(a, b);
-      lds[p + lm.es] = csub(a, b);
-    }
-    __syncthreads();
-    t = 1;
-  }
-  for (; t + 2 <= lg; t += 2) {
-    const int q = 1 << t;
-    const int NB = NL * (L >> 2);
-    for (int idx = threadIdx.x; idx < NB; idx += T) {
-      const int l = idx % NL, r = idx / NL;
-      const int g = r >> t, i = r & (q - 1);
-      const int p0 = lm.base(l) + (g * 4 * q + i) * lm.es;
-      const int e1 = q * lm.es;
-      const float2 x0 = lds[p0], x1 = lds[p0 + e1], x2 = lds[p0 + 2 * e1], x3 = lds[p0 + 3 * e1];
-      const float2 wA = twid<true>(twl, i << (lg - t - 1)), wB = twid<true>(twl, i << (lg - t - 2));
-      const float2 t1 = cmul(x1, wA), t3 = cmul(x3, wA);
-      const float2 a0 = cadd(x0, t1), a1 = csub(x0, t1), a2 = cadd(x2, t3), a3 = csub(x2, t3);
-      const float2 u = cmul(a2, wB), v = rot<true>(cmul(a3, wB));
-      lds[p0] = cadd(a0, u);
-      lds[p0 + 2 * e1] = csub(a0, u);
-      lds[p0 + e1] = cadd(a1, v);
-      lds[p0 + 3 * e1] = csub(a1, v);
-    }
-    __syncthreads();
-  }
-}
-
 __device__ __forceinline__ int ilog2(int L) {
   int lg = 0;
   while ((1 << lg) < L) ++lg;
   return lg;
 }
 
-__device__ __forceinline__ void load_twiddles(float2* twl, int L, const float2* __restrict__ tw,
-                                              int T) {
-  for (int m = threadIdx.x; m < L; m += T) twl[m] = tw[m * (MMI_TW_LEN / L)];
-}
-
-// 3x3 kernel multiply at (kx, ky, kz): H = N M (sign and scale applied later)
-__device__ __forceinline__ void kernel_mul(const InstDesc& D, int kx, int ky, int kz, float2& mx,
-                                           float2& my, float2& mz) {
-  const int hy = D.py / 2, hz = D.pz / 2;
-  int ky2 = ky, kz2 = kz;
-  float sy = 1.f, sz = 1.f;
-  if (ky > hy) { ky2 = D.py - ky; sy = -1.f; }
-  if (kz > hz) { kz2 = D.pz - kz; sz = -1.f; }
-  const size_t plane = (size_t)(hz + 1) * (hy + 1) * D.kx;
-  const size_t o = ((size_t)kz2 * (hy + 1) + ky2) * D.kx + kx;
-  const float* K = D.kern;
-  const float nxx = K[o], nyy = K[plane + o], nzz = K[2 * plane + o];
-  const float nxy = sy * K[3 * plane + o], nxz = sz * K[4 * plane + o], nyz = sy * sz * K[5 * plane + o];
-  const float2 a = mx, b = my, c = mz;
-  mx = make_float2(nxx * a.x + nxy * b.x + nxz * c.x, nxx * a.y + nxy * b.y + nxz * c.y);
-  my = make_float2(nxy * a.x + nyy * b.x + nyz * c.x, nxy * a.y + nyy * b.y + nyz * c.y);
-  mz = make_float2(nxz * a.x + nyz * b.x + nzz * c.x, nxz * a.y + nyz * b.y + nzz * c.y);
-}
-
-// ------------------------------------------------------------ x forward
-// work item = tile of 2W real rows (c, z, y) of one instance
-template <int W>
-__global__ __launch_bounds__(256) void k_fft_xf(const InstDesc* __restrict__ descs,
-                                                const WorkItem* __restrict__ work, int method,
-                                                int stage, const float2* __restrict__ tw) {
-  extern __shared__ float2 lds[];
-  const WorkItem wi = work[blockIdx.x];
-  const InstDesc& D = descs[wi.inst];
-  const InstCtl* C = D.ctl;
-  if (C->done) return;
-  const int Px = D.px, nx = D.nx, ny = D.ny, nz = D.nz, nc = D.ncell;
-  const int nyz = ny * nz, rows = 3 * nyz;
-  const int r0 = wi.item * 2 * W;
-  const Src src = stage_src(D, C, method, stage);
-  float2* buf = lds;
-  float2* twl = lds + Px * W;
-  load_twiddles(twl, Px, tw, 256);
-  for (int e = threadIdx.x; e < 2 * W * Px; e += 256) {
-    const int rr = e / Px, x = e - rr * Px;
-    const int r = r0 + rr;
-    float v = 0.f;
-    if (x < nx && r < rows) {
-      const int c = r / nyz, yz = r - c * nyz;
-      v = src.ld(c * nc + yz * nx + x);
-    }
-    float* p = reinterpret_cast<float*>(&buf[x * W + (rr >> 1)]);
-    p[rr & 1] = v;
-  }
-  __syncthreads();
-  const LineMap lm{W, 1, 0, W};
-  const int lgx = ilog2(Px);
-  fft_dif<256>(buf, Px, lgx, W, lm, twl);
-  const int Kx = D.kx;
-  for (int e = threadIdx.x; e < Kx * 2 * W; e += 256) {
-    const int kx = e / (2 * W), rr = e - kx * 2 * W;
-    const int r = r0 + rr;
-    if (r >= rows) continue;
-    const int line = rr >> 1;
-    const float2 Z = buf[brev(kx & (Px - 1), lgx) * W + line];
-    const float2 Zm = buf[brev((Px - kx) & (Px - 1), lgx) * W + line];
-    float2 X;
-    if ((rr & 1) == 0) X = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
-    else X = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
-    const int c = r / nyz, yz = r - c * nyz;
-    D.fx[((size_t)kx * 3 + c) * nyz + yz] = X;
-  }
-}
-
-// ------------------------------------------------------------ x inverse
-template <int W>
-__global__ __launch_bounds__(256) void k_fft_xi(const InstDesc* __restrict__ descs,
-                                                const WorkItem* __restrict__ work,
-                                                const float2* __restrict__ tw) {
-  extern __shared__ float2 lds[];
-  const WorkItem wi = work[blockIdx.x];
-  const InstDesc& D = descs[wi.inst];
-  if (D.ctl->done) return;
-  const int Px = D.px, nx = D.nx, ny = D.ny, nz = D.nz, nc = D.ncell;
-  const int nyz = ny * nz, rows = 3 * nyz;
-  const int r0 = wi.item * 2 * W;
-  const int Kx = D.kx;
-  float2* buf = lds;                    // [Px][W]
-  float2* stg = lds + Px * W;           // [Kx][2W]
-  float2* twl = stg + Kx * 2 * W;
-  load_twiddles(twl, Px, tw, 256);
-  for (int e = threadIdx.x; e < Kx * 2 * W; e += 256) {
-    const int kx = e / (2 * W), rr = e - kx * 2 * W;
-    const int r = r0 + rr;
-    float2 X = make_float2(0.f, 0.f);
-    if (r < rows) {
-      const int c = r / nyz, yz = r - c * nyz;
-      X = D.fx[((size_t)kx * 3 + c) * nyz + yz];
-    }
-    stg[kx * 2 * W + rr] = X;
-  }
-  __syncthreads();
-  const int half = Px / 2;
-  const int lgx = ilog2(Px);
-  for (int e = threadIdx.x; e < Px * W; e += 256) {
-    const int j = e / W, line = e - j * W;
-    float2 Z;
-    if (j <= half) {
-      float2 a = stg[j * 2 * W + 2 * line], b = stg[j * 2 * W + 2 * line + 1];
-      if (j == 0 || j == half) { a.y = 0.f; b.y = 0.f; }
-      Z = make_float2(a.x - b.y, a.y + b.x);
-    } else {
-      const int k = Px - j;
-      const float2 a = stg[k * 2 * W + 2 * line], b = stg[k * 2 * W + 2 * line + 1];
-      Z = make_float2(a.x + b.y, b.x - a.y);
-    }
-    buf[brev(j, lgx) * W + line] = Z;
-  }
-  __syncthreads();
-  const LineMap lm{W, 1, 0, W};
-  fft_dit<256>(buf, Px, lgx, W, lm, twl);
-  const float sc = D.bd_scale;
-  for (int e = threadIdx.x; e < 2 * W * nx; e += 256) {
-    const int rr = e / nx, x = e - rr * nx;
-    const int r = r0 + rr;
-    if (r >= rows) continue;
-    const float2 Z = buf[x * W + (rr >> 1)];
-    const int c = r / nyz, yz = r - c * nyz;
-    D.bd[c * nc + yz * nx + x] = sc * ((rr & 1) ? Z.y : Z.x);
-  }
-}
-
-// ------------------------------------------------------- fused y-z pass
 // In-place radix-2^2 butterflies shared by the line FFTs below.
 // DIF (forward): elements p0, p0+e1, p0+e2, p0+e2+e1 with e1 = q, e2 = h = 2q.
 __device__ __forceinline__ void dif4(float2* lds, int p0, int e1, int e2, float2 w1, float2 w2) {
@@ -348,11 +129,13 @@ __device__ void fft_rows(float2* lds, int L, int lg, int NL, const int* tab, con
 // lines, element stride es, group stride cs.  Consecutive threads take
 // adjacent lines.
 template <int T, bool DIT>
-__device__ void fft_cols(float2* lds, int L, int lg, int NC, int lgJ, int cs, int es, const float2* twl) {
+__device__ void fft_cols(float2* lds, int L, int lg, int NC, int lgJ, int cs, int es, const float2* twl,
+                         int s0 = 0, int tmax = -1) {
   if (lg == 0) return;
   const int J = 1 << lgJ;
   if (!DIT) {
-    int s = 0;
+    // DIF stages s0 .. lg-1 (stage s has span L >> (s + 1))
+    int s = s0;
     for (; s + 2 <= lg; s += 2) {
       const int h = L >> (s + 1), q = h >> 1, lq = lg - s - 2, lgQ = lg - 2;
       const int NB = (NC << lgQ) << lgJ;
@@ -374,8 +157,10 @@ __device__ void fft_cols(float2* lds, int L, int lg, int NC, int lgJ, int cs, in
       __syncthreads();
     }
   } else {
+    // DIT stages 0 .. tmax-1 (stage t has span 1 << t)
+    if (tmax < 0) tmax = lg;
     int t = 0;
-    if (lg & 1) {
+    if (tmax & 1) {
       const int NB = (NC << (lg - 1)) << lgJ;
       for (int idx = threadIdx.x; idx < NB; idx += T) {
         const int j = idx & (J - 1), rest = idx >> lgJ;
@@ -385,7 +170,7 @@ __device__ void fft_cols(float2* lds, int L, int lg, int NC, int lgJ, int cs, in
       __syncthreads();
       t = 1;
     }
-    for (; t + 2 <= lg; t += 2) {
+    for (; t + 2 <= tmax; t += 2) {
       const int q = 1 << t, lgQ = lg - 2;
       const int NB = (NC << lgQ) << lgJ;
       for (int idx = threadIdx.x; idx < NB; idx += T) {
@@ -400,11 +185,148 @@ __device__ void fft_cols(float2* lds, int L, int lg, int NC, int lgJ, int cs, in
   }
 }
 
-// work item = kx of one instance; LDS [3][Pz][Py+1] + twiddles + y-line table
-#define MM_YZ_T 1024
+__device__ __forceinline__ void load_twiddles(float2* twl, int L, const float2* __restrict__ tw,
+                                              int T) {
+  for (int m = threadIdx.x; m < L; m += T) twl[m] = tw[m * (MMI_TW_LEN / L)];
+}
+
+// 3x3 kernel multiply at (kx, ky, kz): H = N M (sign and scale applied later)
+__device__ __forceinline__ void kernel_mul(const InstDesc& D, int kx, int ky, int kz, float2& mx,
+                                           float2& my, float2& mz) {
+  const int hy = D.py / 2, hz = D.pz / 2;
+  int ky2 = ky, kz2 = kz;
+  float sy = 1.f, sz = 1.f;
+  if (ky > hy) { ky2 = D.py - ky; sy = -1.f; }
+  if (kz > hz) { kz2 = D.pz - kz; sz = -1.f; }
+  const size_t plane = (size_t)(hz + 1) * (hy + 1) * D.kx;
+  const size_t o = ((size_t)kz2 * (hy + 1) + ky2) * D.kx + kx;
+  const float* K = D.kern;
+  const float nxx = K[o], nyy = K[plane + o], nzz = K[2 * plane + o];
+  const float nxy = sy * K[3 * plane + o], nxz = sz * K[4 * plane + o], nyz = sy * sz * K[5 * plane + o];
+  const float2 a = mx, b = my, c = mz;
+  mx = make_float2(nxx * a.x + nxy * b.x + nxz * c.x, nxx * a.y + nxy * b.y + nxz * c.y);
+  my = make_float2(nxy * a.x + nyy * b.x + nyz * c.x, nxy * a.y + nyy * b.y + nyz * c.y);
+  mz = make_float2(nxz * a.x + nyz * b.x + nzz * c.x, nxz * a.y + nyz * b.y + nzz * c.y);
+}
+
+// ------------------------------------------------------------ x forward
+// work item = tile of 2W real rows (c, z, y) of one instance
+template <int W>
+__global__ __launch_bounds__(256) void k_fft_xf(const InstDesc* __restrict__ descs,
+                                                const WorkItem* __restrict__ work, int method,
+                                                int stage, const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  const InstCtl* C = D.ctl;
+  if (C->done) return;
+  const int Px = D.px, nx = D.nx, ny = D.ny, nz = D.nz, nc = D.ncell;
+  const int nyz = ny * nz, rows = 3 * nyz;
+  const int r0 = wi.item * 2 * W;
+  const Src src = stage_src(D, C, method, stage);
+  constexpr int WP = W + 1;                 // padded line stride (bank conflicts)
+  float2* buf = lds;
+  float2* twl = lds + Px * WP;
+  load_twiddles(twl, Px, tw, 256);
+  const int lgx = ilog2(Px);
+  for (int e = threadIdx.x; e < 2 * W * Px; e += 256) {
+    const int rr = e >> lgx, x = e & (Px - 1);
+    const int r = r0 + rr;
+    float v = 0.f;
+    if (x < nx && r < rows) {
+      const int c = r / nyz, yz = r - c * nyz;
+      v = src.ld(c * nc + yz * nx + x);
+    }
+    float* p = reinterpret_cast<float*>(&buf[x * WP + (rr >> 1)]);
+    p[rr & 1] = v;
+  }
+  __syncthreads();
+  fft_cols<256, false>(buf, Px, lgx, 1, ilog2(W), 0, WP, twl);
+  const int Kx = D.kx;
+  for (int e = threadIdx.x; e < Kx * 2 * W; e += 256) {
+    const int kx = e / (2 * W), rr = e - kx * 2 * W;
+    const int r = r0 + rr;
+    if (r >= rows) continue;
+    const int line = rr >> 1;
+    const float2 Z = buf[brev(kx & (Px - 1), lgx) * WP + line];
+    const float2 Zm = buf[brev((Px - kx) & (Px - 1), lgx) * WP + line];
+    float2 X;
+    if ((rr & 1) == 0) X = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+    else X = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
+    const int c = r / nyz, yz = r - c * nyz;
+    D.fx[((size_t)kx * 3 + c) * nyz + yz] = X;
+  }
+}
+
+// ------------------------------------------------------------ x inverse
+template <int W>
+__global__ __launch_bounds__(256) void k_fft_xi(const InstDesc* __restrict__ descs,
+                                                const WorkItem* __restrict__ work,
+                                                const float2* __restrict__ tw) {
+  extern __shared__ float2 lds[];
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (D.ctl->done) return;
+  const int Px = D.px, nx = D.nx, ny = D.ny, nz = D.nz, nc = D.ncell;
+  const int nyz = ny * nz, rows = 3 * nyz;
+  const int r0 = wi.item * 2 * W;
+  const int Kx = D.kx;
+  constexpr int WP = W + 1;             // padded line stride (bank conflicts)
+  float2* buf = lds;                    // [Px][W + 1]
+  float2* stg = lds + Px * WP;          // [Kx][2W]
+  float2* twl = stg + Kx * 2 * W;
+  load_twiddles(twl, Px, tw, 256);
+  for (int e = threadIdx.x; e < Kx * 2 * W; e += 256) {
+    const int kx = e / (2 * W), rr = e - kx * 2 * W;
+    const int r = r0 + rr;
+    float2 X = make_float2(0.f, 0.f);
+    if (r < rows) {
+      const int c = r / nyz, yz = r - c * nyz;
+      X = D.fx[((size_t)kx * 3 + c) * nyz + yz];
+    }
+    stg[kx * 2 * W + rr] = X;
+  }
+  __syncthreads();
+  const int half = Px / 2;
+  const int lgx = ilog2(Px);
+  for (int e = threadIdx.x; e < Px * W; e += 256) {
+    const int j = e / W, line = e - j * W;
+    float2 Z;
+    if (j <= half) {
+      float2 a = stg[j * 2 * W + 2 * line], b = stg[j * 2 * W + 2 * line + 1];
+      if (j == 0 || j == half) { a.y = 0.f; b.y = 0.f; }
+      Z = make_float2(a.x - b.y, a.y + b.x);
+    } else {
+      const int k = Px - j;
+      const float2 a = stg[k * 2 * W + 2 * line], b = stg[k * 2 * W + 2 * line + 1];
+      Z = make_float2(a.x + b.y, b.x - a.y);
+    }
+    buf[brev(j, lgx) * WP + line] = Z;
+  }
+  __syncthreads();
+  fft_cols<256, true>(buf, Px, lgx, 1, ilog2(W), 0, WP, twl);
+  const float sc = D.bd_scale;
+  for (int e = threadIdx.x; e < 2 * W * nx; e += 256) {
+    const int rr = e / nx, x = e - rr * nx;
+    const int r = r0 + rr;
+    if (r >= rows) continue;
+    const float2 Z = buf[x * WP + (rr >> 1)];
+    const int c = r / nyz, yz = r - c * nyz;
+    D.bd[c * nc + yz * nx + x] = sc * ((rr & 1) ? Z.y : Z.x);
+  }
+}
+
+// ------------------------------------------------------- fused y-z pass
+// work item = kx of one instance.
+// LDS: Y rows [3][nz][Py+1] (y transforms), a z work tile [3][Pz][TK] for TK
+// adjacent ky columns, twiddles, y-line table.  The z transform of a tile
+// starts from nz nonzero rows: its first DIF stage (span Pz/2, upper half
+// zero) is folded into the copy into the tile, and the last DIT stage is
+// folded into the copy back, which keeps only z < nz.
+#define MM_YZ_T 512
 __global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__ descs,
                                                     const WorkItem* __restrict__ work,
-                                                    const float2* __restrict__ tw) {
+                                                    const float2* __restrict__ tw, int TK) {
   extern __shared__ float2 lds[];
   const WorkItem wi = work[blockIdx.x];
   const InstDesc& D = descs[wi.inst];
@@ -412,47 +334,72 @@ __global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__
   const int kx = wi.item;
   const int ny = D.ny, nz = D.nz, Py = D.py, Pz = D.pz;
   const int RP = Py + 1;
-  const int plane = Pz * RP;
-  float2* buf = lds;
-  float2* twy = lds + 3 * plane;
+  const int yplane = nz * RP;                 // one component of the Y rows
+  const int zplane = Pz * TK;                 // one component of the z tile
+  float2* ybuf = lds;
+  float2* zbuf = ybuf + 3 * yplane;
+  float2* twy = zbuf + 3 * zplane;
   float2* twz = twy + Py;
-  int* ytab = reinterpret_cast<int*>(twz + Pz);    // 3 nz line bases
+  int* ytab = reinterpret_cast<int*>(twz + Pz);
   load_twiddles(twy, Py, tw, MM_YZ_T);
   load_twiddles(twz, Pz, tw, MM_YZ_T);
-  for (int l = threadIdx.x; l < 3 * nz; l += MM_YZ_T) {
-    const int c = l / nz, z = l - c * nz;
-    ytab[l] = c * plane + z * RP;
-  }
-  for (int e = threadIdx.x; e < 3 * plane; e += MM_YZ_T) buf[e] = make_float2(0.f, 0.f);
-  __syncthreads();
+  for (int l = threadIdx.x; l < 3 * nz; l += MM_YZ_T) ytab[l] = l * RP;
+  const int lgy = ilog2(Py), lgz = ilog2(Pz), lgT = ilog2(TK);
   const int nyz = ny * nz;
   float2* X = D.fx + (size_t)kx * 3 * nyz;
-  for (int e = threadIdx.x; e < 3 * nyz; e += MM_YZ_T) {
-    const int c = e / nyz, yz = e - c * nyz;
-    const int z = yz / ny, y = yz - z * ny;
-    buf[c * plane + z * RP + y] = X[e];
+  // load rows, zero-padded in y
+  for (int e = threadIdx.x; e < 3 * nz * Py; e += MM_YZ_T) {
+    const int l = e >> lgy, y = e & (Py - 1);
+    ybuf[l * RP + y] = (y < ny) ? X[l * ny + y] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  const int lgy = ilog2(Py), lgz = ilog2(Pz);
-  fft_rows<MM_YZ_T, false>(buf, Py, lgy, 3 * nz, ytab, twy);
-  fft_cols<MM_YZ_T, false>(buf, Pz, lgz, 3, lgy, plane, RP, twz);
-  // spectra sit at bit-reversed positions in y and z
-  for (int e = threadIdx.x; e < Pz * Py; e += MM_YZ_T) {
-    const int pz_ = e >> lgy, py_ = e & (Py - 1);
-    const int o = pz_ * RP + py_;
-    float2 mx = buf[o], my = buf[plane + o], mz = buf[2 * plane + o];
-    kernel_mul(D, kx, brev(py_, lgy), brev(pz_, lgz), mx, my, mz);
-    buf[o] = mx;
-    buf[plane + o] = my;
-    buf[2 * plane + o] = mz;
+  fft_rows<MM_YZ_T, false>(ybuf, Py, lgy, 3 * nz, ytab, twy);
+  const int hz = Pz >> 1;
+  for (int k0 = 0; k0 < Py; k0 += TK) {
+    // copy in with the first DIF stage: out[z] = x[z], out[z + Pz/2] = x[z] W^z
+    if (Pz == 1) {
+      for (int e = threadIdx.x; e < 3 * TK; e += MM_YZ_T) {
+        const int c = e >> lgT, t = e & (TK - 1);
+        zbuf[c * zplane + t] = ybuf[c * yplane + k0 + t];
+      }
+    } else {
+      for (int e = threadIdx.x; e < 3 * hz * TK; e += MM_YZ_T) {
+        const int t = e & (TK - 1), rest = e >> lgT;
+        const int z = rest & (hz - 1), c = rest >> (lgz - 1);
+        float2 v = make_float2(0.f, 0.f);
+        if (z < nz) v = ybuf[c * yplane + z * RP + k0 + t];
+        zbuf[c * zplane + z * TK + t] = v;
+        zbuf[c * zplane + (z + hz) * TK + t] = cmul(v, twz[z]);
+      }
+    }
+    __syncthreads();
+    if (Pz > 1) fft_cols<MM_YZ_T, false>(zbuf, Pz, lgz, 3, lgT, zplane, TK, twz, 1);
+    // spectra at bit-reversed positions in y and z
+    for (int e = threadIdx.x; e < Pz * TK; e += MM_YZ_T) {
+      const int pz_ = e >> lgT, t = e & (TK - 1);
+      const int o = pz_ * TK + t;
+      float2 mx = zbuf[o], my = zbuf[zplane + o], mz = zbuf[2 * zplane + o];
+      kernel_mul(D, kx, brev(k0 + t, lgy), brev(pz_, lgz), mx, my, mz);
+      zbuf[o] = mx;
+      zbuf[zplane + o] = my;
+      zbuf[2 * zplane + o] = mz;
+    }
+    __syncthreads();
+    if (Pz > 1) fft_cols<MM_YZ_T, true>(zbuf, Pz, lgz, 3, lgT, zplane, TK, twz, 0, lgz - 1);
+    // copy back with the last DIT stage: out[z] = x[z] + x[z + Pz/2] conj(W^z), z < nz
+    for (int e = threadIdx.x; e < 3 * nz * TK; e += MM_YZ_T) {
+      const int t = e & (TK - 1), rest = e >> lgT;
+      const int c = rest / nz, z = rest - c * nz;
+      float2 v = zbuf[c * zplane + z * TK + t];
+      if (Pz > 1) v = cadd(v, cmul(zbuf[c * zplane + (z + hz) * TK + t], twid<true>(twz, z)));
+      ybuf[c * yplane + z * RP + k0 + t] = v;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  fft_cols<MM_YZ_T, true>(buf, Pz, lgz, 3, lgy, plane, RP, twz);
-  fft_rows<MM_YZ_T, true>(buf, Py, lgy, 3 * nz, ytab, twy);
-  for (int e = threadIdx.x; e < 3 * nyz; e += MM_YZ_T) {
-    const int c = e / nyz, yz = e - c * nyz;
-    const int z = yz / ny, y = yz - z * ny;
-    X[e] = buf[c * plane + z * RP + y];
+  fft_rows<MM_YZ_T, true>(ybuf, Py, lgy, 3 * nz, ytab, twy);
+  for (int e = threadIdx.x; e < 3 * nz * Py; e += MM_YZ_T) {
+    const int l = e >> lgy, y = e & (Py - 1);
+    if (y < ny) X[l * ny + y] = ybuf[l * RP + y];
   }
 }
 
@@ -469,29 +416,29 @@ __global__ __launch_bounds__(256) void k_fft_y(const InstDesc* __restrict__ desc
   const int ny = D.ny, Py = D.py;
   const int nlines = D.kx * 3 * D.nz;
   const int l0 = wi.item * W;
+  const int WP = W + 1;                   // padded line stride (bank conflicts)
   float2* buf = lds;
-  float2* twl = lds + Py * W;
+  float2* twl = lds + Py * WP;
   load_twiddles(twl, Py, tw, 256);
   const int nin = (DIR < 0) ? ny : Py;
   const int lgy = ilog2(Py);
   for (int e = threadIdx.x; e < W * Py; e += 256) {
-    const int ll = e / Py, y = e - ll * Py;
+    const int ll = e >> lgy, y = e & (Py - 1);
     const int l = l0 + ll;
     float2 v = make_float2(0.f, 0.f);
     if (l < nlines && y < nin) v = (DIR < 0) ? D.fx[(size_t)l * ny + y] : D.fy[(size_t)l * Py + y];
     // forward: natural order in; inverse: bit-reversed order in
-    buf[((DIR < 0) ? y : brev(y, lgy)) * W + ll] = v;
+    buf[((DIR < 0) ? y : brev(y, lgy)) * WP + ll] = v;
   }
   __syncthreads();
-  const LineMap lm{W, 1, 0, W};
-  if (DIR < 0) fft_dif<256>(buf, Py, lgy, W, lm, twl);
-  else fft_dit<256>(buf, Py, lgy, W, lm, twl);
+  if (DIR < 0) fft_cols<256, false>(buf, Py, lgy, 1, ilog2(W), 0, WP, twl);
+  else fft_cols<256, true>(buf, Py, lgy, 1, ilog2(W), 0, WP, twl);
   const int nout = (DIR < 0) ? Py : ny;
   for (int e = threadIdx.x; e < W * nout; e += 256) {
     const int ll = e / nout, y = e - ll * nout;
     const int l = l0 + ll;
     if (l >= nlines) continue;
-    const float2 v = buf[((DIR < 0) ? brev(y, lgy) : y) * W + ll];
+    const float2 v = buf[((DIR < 0) ? brev(y, lgy) : y) * WP + ll];
     if (DIR < 0) D.fy[(size_t)l * Py + y] = v;
     else D.fx[(size_t)l * ny + y] = v;
   }
@@ -523,9 +470,8 @@ __global__ __launch_bounds__(256) void k_fft_zc(const InstDesc* __restrict__ des
     buf[e] = v;
   }
   __syncthreads();
-  const LineMap lm{NL, 1, 0, NL};
-  const int lgz = ilog2(Pz);
-  fft_dif<256>(buf, Pz, lgz, NL, lm, twl);
+  const int lgz = ilog2(Pz), lgT = ilog2(TW);
+  fft_cols<256, false>(buf, Pz, lgz, 3, lgT, TW, NL, twl);
   for (int e = threadIdx.x; e < Pz * TW; e += 256) {
     const int pz_ = e / TW, t = e - pz_ * TW;
     const int ky = ky0 + t;
@@ -537,7 +483,7 @@ __global__ __launch_bounds__(256) void k_fft_zc(const InstDesc* __restrict__ des
     buf[pz_ * NL + 2 * TW + t] = mz;
   }
   __syncthreads();
-  fft_dit<256>(buf, Pz, lgz, NL, lm, twl);
+  fft_cols<256, true>(buf, Pz, lgz, 3, lgT, TW, NL, twl);
   for (int e = threadIdx.x; e < nz * NL; e += 256) {
     const int z = e / NL, l = e - z * NL;
     const int c = l / TW, t = l - c * TW;
@@ -577,9 +523,9 @@ hipError_t mmk_launch_fft_xi(int W, int nblocks, size_t lds, const InstDesc* d, 
   return hipGetLastError();
 }
 
-hipError_t mmk_launch_fft_yz(int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+hipError_t mmk_launch_fft_yz(int TK, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              const float2* tw, hipStream_t s) {
-  hipLaunchKernelGGL(mmk::k_fft_yz, dim3(nblocks), dim3(MM_YZ_T), lds, s, d, w, tw);
+  hipLaunchKernelGGL(mmk::k_fft_yz, dim3(nblocks), dim3(MM_YZ_T), lds, s, d, w, tw, TK);
   return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ hipError_t mmk_launch_fft_xf(int W, int nblocks, size_t lds, const InstDesc* d, 
                              int method, int stage, const float2* tw, hipStream_t s);
 hipError_t mmk_launch_fft_xi(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              const float2* tw, hipStream_t s);
-hipError_t mmk_launch_fft_yz(int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+hipError_t mmk_launch_fft_yz(int TK, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              const float2* tw, hipStream_t s);
 hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstDesc* d,
                             const WorkItem* w, const float2* tw, hipStream_t s);

@@ -71,6 +71,7 @@ _SIGS = {
     "mm_batch_destroy": (ctypes.c_int, [_P]),
     "mm_batch_profile": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P,
                                         ctypes.POINTER(ctypes.c_int32)]),
+    "mm_batch_tune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
     "mm_run_record": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32]),
     "mm_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "mm_demag_tensor": (ctypes.c_int, [ctypes.c_double] * 6 + [_P]),
@@ -280,6 +281,13 @@ class Batch:
 
     def step(self, steps, tol=0.0):
         _check(self._lib.mm_batch_step(self.h, int(steps), float(tol)))
+
+    def tune(self):
+        """Autotune the FFT tiles / path per grid shape; returns the report."""
+        import json
+        buf = ctypes.create_string_buffer(65536)
+        _check(self._lib.mm_batch_tune(self.h, buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def profile(self, steps, tol=0.0, cap=32):
         names = ctypes.create_string_buffer(48 * cap)

@@ -288,3 +288,28 @@ def test_afm_batch_sizes_one_step(k):
     inst = variant(inst, method="rk4", dt0=2e-14)
     st, ctx = _run_pair(inst, 1e-13)
     assert m_err(ctx.get_m(), st) <= 1e-6
+
+
+def test_tuned_batch_keeps_parity():
+    """The autotuner changes only tile shapes / the y-z path: results stay
+    within FP32 rounding of the untuned batch and the state is not advanced."""
+    from paper_2603_03706_amd import mmcav
+    insts = [W.sweep_sphere(k, count=3, n=12) for k in range(3)]
+    for inst in insts:
+        inst.method, inst.dt0 = "rk4", 0.2e-12
+    ref = [gpu_for(i) for i in insts]
+    b0 = mmcav.Batch(ref)
+    b0.run(20e-12)
+    ctxs = [gpu_for(i) for i in insts]
+    b1 = mmcav.Batch(ctxs)
+    rep = b1.tune()
+    assert len(rep) == 1 and rep[0]["path"] in ("fused", "split")
+    assert all(c.stats()["accepted"] == 0 for c in ctxs)
+    b1.run(20e-12)
+    for c, r in zip(ctxs, ref):
+        assert np.abs(c.get_m() - r.get_m()).max() <= 2e-6
+    st = oracle_for(insts[1])
+    run_oracle(st, 20e-12)
+    assert m_err(ctxs[1].get_m(), st) <= 2e-5
+    b0.close()
+    b1.close()
