@@ -45,7 +45,146 @@ def parse():
     ap.add_argument("--no-afm", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=512)
     ap.add_argument("--afm-steps", type=int, default=20)
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="short run for rocprofv3 --pmc: tune, a marker copy, a few steps, a marker copy")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_JSON"),
+                    help="write the HBM-traffic summary of two --pmc runs of --pmc-probe (markdown, stdout)")
     return ap.parse_args()
+
+
+# ----------------------------------------------------------------- HBM traffic
+# The roofline's "traffic" entry comes from two rocprofv3 counter runs of
+# --pmc-probe (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).  Each counter is
+# scaled by what it reads for a plain elementwise copy of known size (the
+# marker), and the result is stored with a hash of the kernel sources and the
+# FFT tile choice; it is reported only while both still match.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_sweep_64x32cubed_dp45.md")
+MARKER_ELEMS = 1 << 26          # float32 elements of the marker copy (256 MiB read + 256 MiB written)
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2603_03706_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(src, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    with open(os.path.join(ROOT, "paper_2603_03706_amd", "build.py"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def tile_key(tuning):
+    if not tuning:
+        return None
+    return [{k: t.get(k) for k in ("grid", "Wx", "path", "Wy", "TW", "TK")} for t in tuning]
+
+
+def profile_name(kernel):
+    """Name used by the library's launch profiler for a demangled kernel name."""
+    import re
+    k = kernel.split("(")[0].replace("void ", "").strip()
+    m = re.match(r"mmk::k_(stage|final)<(\d+), (\d+)>", k)
+    if m:
+        return f"{m.group(1)}_{'rk4' if m.group(2) == '0' else 'dp45'}_{m.group(3)}" \
+            if not (m.group(1) == "stage" and m.group(2) == "0" and m.group(3) == "0") else "stage_rk4_start"
+    table = {"mmk::k_fft_yz": "fft_yz_convolve", "mmk::k_fft_zc": "fft_z_convolve",
+             "mmk::k_fft_y<-1>": "fft_y_forward", "mmk::k_fft_y<1>": "fft_y_inverse"}
+    if k in table:
+        return table[k]
+    if k.startswith("mmk::k_fft_xf"):
+        return "fft_x_forward"
+    if k.startswith("mmk::k_fft_xi"):
+        return "fft_x_inverse"
+    return None
+
+
+def pmc_probe(args):
+    import torch
+    insts, ctxs, batch = build_batch(args.instances, args.tol)
+    tuning = None if args.no_tune else batch.tune()
+    batch.step(3, args.tol)
+    src = torch.ones(MARKER_ELEMS, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    batch.step(args.profile_steps, args.tol)
+    torch.cuda.synchronize()
+    torch.mul(src, 2.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"tiles": tile_key(tuning), "sources": source_hash(), "steps": args.profile_steps,
+                      "marker_bytes": 4 * MARKER_ELEMS}))
+
+
+def read_counters(path):
+    import csv
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    marks = [i for i, (d, k, c, v) in enumerate(rows) if "MulFunctor" in k]
+    if len(marks) < 2:
+        raise SystemExit(f"{path}: expected two marker dispatches, found {len(marks)}")
+    lo, hi = marks[0], marks[-1]
+    per = {}
+    for d, k, c, v in rows[lo + 1:hi]:
+        per.setdefault(k, []).append(v)
+    return rows[lo][3], rows[hi][3], per
+
+
+def summarize_pmc(fetch_csv, write_csv, probe_json):
+    with open(probe_json) as f:
+        probe = json.loads(f.read().strip().splitlines()[-1])
+    mb = probe["marker_bytes"]
+    f0, f1, fetch = read_counters(fetch_csv)
+    w0, w1, write = read_counters(write_csv)
+    ff = mb / (0.5 * (f0 + f1) * 1024.0)
+    fw = mb / (0.5 * (w0 + w1) * 1024.0)
+    print("# HBM traffic per launch: field sweep, 64 x 32^3 spheres, FFT demag on 64^3, DP45 tol 1e-6\n")
+    print("Commands (from the repository root, one MI355X; each counter in a run of its own):\n")
+    print("```")
+    print("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --pmc-probe > gpurun_out/probe.json")
+    print("rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- python3 bench.py --pmc-probe")
+    print("python3 bench.py --summarize-pmc gpurun_out/pmc_fetch/fetch_counter_collection.csv "
+          "gpurun_out/pmc_write/write_counter_collection.csv gpurun_out/probe.json")
+    print("```\n")
+    print(f"Calibration: an elementwise float32 copy of {mb} bytes (read {mb}, write {mb}) reads "
+          f"FETCH_SIZE {f0:.0f} / {f1:.0f} KiB and WRITE_SIZE {w0:.0f} / {w1:.0f} KiB; scale factors "
+          f"{ff:.4f} (fetch) and {fw:.4f} (write).\n")
+    print(f"Kernels between the two markers ({probe['steps']} DP45 steps of the batch), per dispatch:\n")
+    print("| kernel | dispatches | FETCH KiB | WRITE KiB | HBM bytes (scaled) |")
+    print("|---|---|---|---|---|")
+    out = {}
+    for k in sorted(fetch, key=lambda k: -sum(fetch[k])):
+        name = profile_name(k)
+        fv = sum(fetch[k]) / len(fetch[k])
+        wv = sum(write.get(k, [0.0])) / max(1, len(write.get(k, [])))
+        b = fv * 1024.0 * ff + wv * 1024.0 * fw
+        print(f"| `{k.split('(')[0]}` | {len(fetch[k])} | {fv:.0f} | {wv:.0f} | {b:.4g} |")
+        if name:
+            out[name] = b
+    print("\nMachine-readable (kernel sources, FFT tiles, scaled bytes per launch):\n")
+    print("```")
+    print("traffic-json: " + json.dumps({"sources": probe["sources"], "tiles": probe["tiles"], "bytes": out}))
+    print("```")
+
+
+def stored_traffic(kernel, tiles):
+    """Scaled HBM bytes per launch of `kernel` from the stored counter summary,
+    or None when the kernel sources or the tile choice changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.startswith("traffic-json: "):
+                    rec = json.loads(line[len("traffic-json: "):])
+                    if rec["sources"] == source_hash() and rec["tiles"] == tiles:
+                        return rec["bytes"].get(kernel)
+    except OSError:
+        pass
+    return None
 
 
 def build_batch(n, tol):
@@ -176,6 +315,9 @@ def cpu_baseline(inst, seconds, tol):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
               "the batched form would shard instances across GPUs, which is not built here.", file=sys.stderr)
@@ -184,6 +326,9 @@ def main():
     from paper_2603_03706_amd import mmcav
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.pmc_probe:
+        pmc_probe(args)
+        return
 
     insts, ctxs, batch = build_batch(args.instances, args.tol)
     cells = sum(i.cells for i in insts)
@@ -212,8 +357,10 @@ def main():
                             "GBps": gbs})
         kernels.sort(key=lambda k: -k["total_ms"])
         top = kernels[0]
+        traffic = stored_traffic(top["name"], tile_key(tuning))
         roof = {"bound": "hbm", "achieved": round(top["GBps"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(top["GBps"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": top["name"],
+                "frac": round(top["GBps"] / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic), "kernel": top["name"],
                 "avg_us": round(top["avg_us"], 2), "bytes_per_launch": top["bytes_per_launch"]}
         print(f"[bench] profile: {json.dumps(kernels)}", file=sys.stderr, flush=True)
 
@@ -259,8 +406,7 @@ def main():
                                f"FFT demag on 64^3, 1 uniform mode, DP45 tol {args.tol:g}, batched",
                    "instances": len(insts), "grid": [32, 32, 32], "method": "dp45", "tol": args.tol,
                    "accepted_fraction": acc / (args.steps * len(insts)),
-                   "fft_tiles": None if tuning is None else [{k: t[k] for k in ("grid", "Wx", "path", "Wy", "TW")}
-                                                            for t in tuning]},
+                   "fft_tiles": tile_key(tuning)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched_vs_plain": speedup,

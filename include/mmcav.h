@@ -185,6 +185,20 @@ mm_status mm_batch_destroy(mm_batch* b);
  * of the timings and choices is written to report (may be NULL). */
 mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len);
 
+/* Demag y-z strategy for every FFT grid shape in the batch (mm_batch_tune
+ * chooses one per shape by timing; before that the register strategy is used
+ * where it applies, else the fused one where it fits, else the split one):
+ *   MM_YZ_FUSED     y and z lines transformed in LDS by one workgroup per
+ *                   (instance, kx), z in tiles of ky columns;
+ *   MM_YZ_REGISTER  one workgroup per (instance, kx), each line split over
+ *                   four lanes that hold it in registers; padded y of 16..128
+ *                   and padded z of 16..64 cells only;
+ *   MM_YZ_SPLIT     separate y and z passes through device memory.
+ * All three compute the same convolution (agreement to FP32 rounding).
+ * Returns MM_ERR_ARG, changing nothing, if some shape cannot use `path`. */
+enum { MM_YZ_FUSED = 0, MM_YZ_REGISTER = 1, MM_YZ_SPLIT = 2 };
+mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path);
+
 /* Per-kernel timing: run `steps` steps eagerly, timing each launch with HIP
  * events on the library stream.  Fills up to `cap` entries: names (each
  * char[48]), launches, total milliseconds, algorithmic bytes per launch

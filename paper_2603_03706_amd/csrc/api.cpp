@@ -124,6 +124,22 @@ int fused_tile(int ny, int nz, int py, int pz) {
 
 bool fused_fits(int ny, int nz, int py, int pz) { return fused_tile(ny, nz, py, pz) > 0; }
 
+// fused y-z with lines in registers: padded y in {16..128}, padded z in {16..64}
+size_t reg_lds(int nz, int py, int pz) {
+  (void)nz;
+  return sizeof(float2) * ((size_t)3 * (pz / 2) * (py + 1) + py + pz + 32) +
+         sizeof(float) * 6 * (size_t)(pz / 2 + 1) * (py / 2 + 1);
+}
+bool reg_fits(int ny, int nz, int py, int pz) {
+  (void)ny;
+  const bool y_ok = py == 16 || py == 32 || py == 64 || py == 128;
+  const bool z_ok = pz == 16 || pz == 32 || pz == 64;
+  return y_ok && z_ok && reg_lds(nz, py, pz) <= 160 * 1024;
+}
+
+enum { PATH_FUSED = MM_YZ_FUSED, PATH_REG = MM_YZ_REGISTER, PATH_SPLIT = MM_YZ_SPLIT };
+const char* path_name(int p) { return p == PATH_REG ? "reg" : p == PATH_SPLIT ? "split" : "fused"; }
+
 Layout make_layout(const mm_params& p, int n_modes) {
   Layout L{};
   L.ncell = p.nx * p.ny * p.nz;
@@ -249,7 +265,7 @@ struct mm_batch {
   std::vector<unsigned> versions;
   struct Group {
     int nx, ny, nz, px, py, pz, kx;
-    bool split;
+    int path;
     int Wx, Wy, TW, TK = 1;
     WorkItem *xf = nullptr, *yz = nullptr, *y = nullptr, *zc = nullptr;
     int n_xf = 0, n_yz = 0, n_y = 0, n_zc = 0;
@@ -421,7 +437,7 @@ mm_status build_group(mm_batch::Group& g) {
   const int ky_tiles = (g.py + g.TW - 1) / g.TW;
   for (int m : g.members) {
     for (int t = 0; t < tiles_x; ++t) xf.push_back({m, t});
-    if (!g.split) {
+    if (g.path != PATH_SPLIT) {
       for (int k = 0; k < g.kx; ++k) yz.push_back({m, k});
     } else {
       for (int t = 0; t < tiles_y; ++t) yy.push_back({m, t});
@@ -441,7 +457,7 @@ mm_status build_group(mm_batch::Group& g) {
   if (mm_status s = up(zc, &g.zc, &g.n_zc)) return s;
   g.lds_xf = sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + g.px);
   g.lds_xi = sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + (size_t)g.kx * 2 * g.Wx + g.px);
-  g.lds_yz = fused_lds(g.ny, g.nz, g.py, g.pz, g.TK);
+  g.lds_yz = g.path == PATH_REG ? reg_lds(g.nz, g.py, g.pz) : fused_lds(g.ny, g.nz, g.py, g.pz, g.TK);
   g.lds_y = sizeof(float2) * ((size_t)g.py * (g.Wy + 1) + g.py);
   g.lds_zc = sizeof(float2) * ((size_t)g.pz * 3 * g.TW + g.pz);
   return MM_OK;
@@ -477,7 +493,7 @@ mm_status batch_build(mm_batch* b) {
       g = &b->groups.back();
       g->nx = c->p.nx; g->ny = c->p.ny; g->nz = c->p.nz;
       g->px = c->L.px; g->py = c->L.py; g->pz = c->L.pz; g->kx = c->L.kx;
-      g->split = c->L.split;
+      g->path = reg_fits(g->ny, g->nz, g->py, g->pz) ? PATH_REG : c->L.split ? PATH_SPLIT : PATH_FUSED;
     }
     g->members.push_back(i);
   }
@@ -540,7 +556,12 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1) {
           return mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, method, stage, g_twiddle, b->stream);
         }))
       return s;
-    if (!g.split) {
+    if (g.path == PATH_REG) {
+      if (mm_status s = launch(b, "fft_yz_convolve", [&] {
+            return mmk_launch_fft_yzr(g.py / 4, g.pz / 4, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
+          }))
+        return s;
+    } else if (g.path == PATH_FUSED) {
       if (mm_status s = launch(b, "fft_yz_convolve", [&] {
             return mmk_launch_fft_yz(g.TK, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
           }))
@@ -1365,6 +1386,28 @@ mm_status mm_batch_step(mm_batch* b, int64_t steps, double tol) {
   return end_run(b, wall);
 }
 
+mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path) {
+  if (!b) return fail(MM_ERR_ARG, "batch is NULL");
+  if (path != PATH_FUSED && path != PATH_REG && path != PATH_SPLIT) return fail(MM_ERR_ARG, "unknown y-z path");
+  for (auto& g : b->groups) {
+    if (path == PATH_REG && !reg_fits(g.ny, g.nz, g.py, g.pz))
+      return fail(MM_ERR_ARG, "register y-z path needs padded y in 16..128 and padded z in 16..64");
+    if (path == PATH_FUSED && !fused_fits(g.ny, g.nz, g.py, g.pz))
+      return fail(MM_ERR_ARG, "fused y-z path does not fit in LDS for this grid");
+  }
+  MM_HIP(hipStreamSynchronize(b->stream));
+  for (auto& g : b->groups) {
+    g.path = path;
+    if (path == PATH_FUSED) g.TK = std::max(1, fused_tile(g.ny, g.nz, g.py, g.pz));
+    if (mm_status s = build_group(g)) return s;
+  }
+  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+  if (b->exec_rev) { hipGraphExecDestroy(b->exec_rev); b->exec_rev = nullptr; }
+  if (b->graph_rev) { hipGraphDestroy(b->graph_rev); b->graph_rev = nullptr; }
+  return MM_OK;
+}
+
 mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, char* names, int64_t* launches,
                            double* total_ms, double* bytes_per_launch, int32_t* n) {
   if (!b || !n || steps < 0 || cap < 0) return fail(MM_ERR_ARG, "bad arguments");
@@ -1455,28 +1498,39 @@ mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
     }
     g.Wx = bestW;
     // y-z passes: fused vs split with tile widths
-    bool bestSplit = g.split;
+    int bestPath = g.path;
     int bestWy = g.Wy, bestTW = g.TW;
     double bestYZ = 1e30;
     std::string yrep;
     int bestTK = g.TK;
     for (int tk = std::min(16, g.py); tk >= 1 && fused_fits(g.ny, g.nz, g.py, g.pz); tk /= 2) {
       if (fused_lds(g.ny, g.nz, g.py, g.pz, tk) > 160 * 1024) continue;
-      g.split = false;
+      g.path = PATH_FUSED;
       g.TK = tk;
       if (mm_status s = build_group(g)) return s;
       double us;
       if (mm_status s = timed([&] { return mmk_launch_fft_yz(g.TK, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream); }, &us))
         return s;
       yrep += (yrep.empty() ? "" : ", ") + std::string("\"fused_") + std::to_string(tk) + "\": " + std::to_string(us);
-      if (us < bestYZ) { bestYZ = us; bestSplit = false; bestTK = tk; }
+      if (us < bestYZ) { bestYZ = us; bestPath = PATH_FUSED; bestTK = tk; }
       if (tk <= 2) break;
+    }
+    if (reg_fits(g.ny, g.nz, g.py, g.pz)) {
+      g.path = PATH_REG;
+      if (mm_status s = build_group(g)) return s;
+      double us;
+      if (mm_status s = timed([&] {
+            return mmk_launch_fft_yzr(g.py / 4, g.pz / 4, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
+          }, &us))
+        return s;
+      yrep += (yrep.empty() ? "" : ", ") + std::string("\"reg\": ") + std::to_string(us);
+      if (us < bestYZ) { bestYZ = us; bestPath = PATH_REG; }
     }
     for (int Wy = 4; Wy <= 64; Wy *= 2) {
       if (sizeof(float2) * ((size_t)g.py * (Wy + 1) + g.py) > lds_cap) continue;
       for (int TW = 1; TW <= 16; TW *= 2) {
         if (sizeof(float2) * ((size_t)g.pz * 3 * TW + g.pz) > lds_cap) continue;
-        g.split = true;
+        g.path = PATH_SPLIT;
         g.Wy = Wy;
         g.TW = TW;
         if (mm_status s = build_group(g)) return s;
@@ -1491,17 +1545,17 @@ mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
           return s;
         yrep += (yrep.empty() ? "" : ", ") + std::string("\"split_") + std::to_string(Wy) + "_" +
                 std::to_string(TW) + "\": " + std::to_string(us);
-        if (us < bestYZ) { bestYZ = us; bestSplit = true; bestWy = Wy; bestTW = TW; }
+        if (us < bestYZ) { bestYZ = us; bestPath = PATH_SPLIT; bestWy = Wy; bestTW = TW; }
       }
     }
-    g.split = bestSplit;
+    g.path = bestPath;
     g.Wy = bestWy;
     g.TW = bestTW;
     g.TK = bestTK;
     if (mm_status s = build_group(g)) return s;
     rep += (gi ? ", " : "") + std::string("{\"grid\": [") + std::to_string(g.nx) + ", " + std::to_string(g.ny) + ", " +
            std::to_string(g.nz) + "], \"instances\": " + std::to_string(g.members.size()) + ", \"Wx\": " +
-           std::to_string(g.Wx) + ", \"path\": \"" + (g.split ? "split" : "fused") + "\", \"Wy\": " +
+           std::to_string(g.Wx) + ", \"path\": \"" + path_name(g.path) + "\", \"Wy\": " +
            std::to_string(g.Wy) + ", \"TW\": " + std::to_string(g.TW) + ", \"TK\": " + std::to_string(g.TK) + ", \"x_us\": {" + xrep +
            "}, \"yz_us\": {" + yrep + "}}";
   }

@@ -129,6 +129,28 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Every buffer reached through the descriptor table lives in global memory.
+// Stating the address space lets the compiler emit global loads and stores
+// (scalar base + 32-bit offset, vector-memory counter only) instead of flat
+// ones, which carry 64-bit addresses and also wait on the LDS counter.
+#define MMG __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ MMG T* gbl(T* p) {
+  return (MMG T*)p;
+}
+
+// float2 through global pointers (the vector type's operators do not take
+// address-space qualified operands)
+__device__ __forceinline__ float2 gld2(const MMG float2* p) {
+  const MMG float* q = (const MMG float*)p;
+  return make_float2(q[0], q[1]);
+}
+__device__ __forceinline__ void gst2(MMG float2* p, float2 v) {
+  MMG float* q = (MMG float*)p;
+  q[0] = v.x;
+  q[1] = v.y;
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

@@ -198,11 +198,28 @@ __device__ __forceinline__ void kernel_mul(const InstDesc& D, int kx, int ky, in
   float sy = 1.f, sz = 1.f;
   if (ky > hy) { ky2 = D.py - ky; sy = -1.f; }
   if (kz > hz) { kz2 = D.pz - kz; sz = -1.f; }
-  const size_t plane = (size_t)(hz + 1) * (hy + 1) * D.kx;
-  const size_t o = ((size_t)kz2 * (hy + 1) + ky2) * D.kx + kx;
-  const float* K = D.kern;
+  const int plane = (hz + 1) * (hy + 1);
+  const int o = kz2 * (hy + 1) + ky2;
+  const MMG float* K = gbl(D.kern) + (size_t)kx * 6 * plane;
   const float nxx = K[o], nyy = K[plane + o], nzz = K[2 * plane + o];
   const float nxy = sy * K[3 * plane + o], nxz = sz * K[4 * plane + o], nyz = sy * sz * K[5 * plane + o];
+  const float2 a = mx, b = my, c = mz;
+  mx = make_float2(nxx * a.x + nxy * b.x + nxz * c.x, nxx * a.y + nxy * b.y + nxz * c.y);
+  my = make_float2(nxy * a.x + nyy * b.x + nyz * c.x, nxy * a.y + nyy * b.y + nyz * c.y);
+  mz = make_float2(nxz * a.x + nyz * b.x + nzz * c.x, nxz * a.y + nyz * b.y + nzz * c.y);
+}
+
+// the same multiply with the kernel slice of one kx staged in LDS as [6][PZ/2+1][PY/2+1]
+template <int PY, int PZ>
+__device__ __forceinline__ void kernel_mul_lds(const float* Ks, int ky, int kz, float2& mx, float2& my, float2& mz) {
+  constexpr int HY = PY / 2, HZ = PZ / 2, PL = (HZ + 1) * (HY + 1);
+  int ky2 = ky, kz2 = kz;
+  float sy = 1.f, sz = 1.f;
+  if (ky > HY) { ky2 = PY - ky; sy = -1.f; }
+  if (kz > HZ) { kz2 = PZ - kz; sz = -1.f; }
+  const float* K = Ks + kz2 * (HY + 1) + ky2;
+  const float nxx = K[0], nyy = K[PL], nzz = K[2 * PL];
+  const float nxy = sy * K[3 * PL], nxz = sz * K[4 * PL], nyz = sy * sz * K[5 * PL];
   const float2 a = mx, b = my, c = mz;
   mx = make_float2(nxx * a.x + nxy * b.x + nxz * c.x, nxx * a.y + nxy * b.y + nxz * c.y);
   my = make_float2(nxy * a.x + nyy * b.x + nyz * c.x, nxy * a.y + nyy * b.y + nyz * c.y);
@@ -403,6 +420,248 @@ __global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__
   }
 }
 
+// ------------------------------------------- fused y-z, lines in registers
+// A padded line of length P = 4M whose inputs vanish from index 2M on is
+// split by the residue r = k mod 4 of the frequency index k = 4k' + r:
+//   X[4k' + r] = sum_j W_M^{k'j} f_r[j],  f_r[j] = W_P^{rj} (x[j] + (-i)^r x[j+M]),
+// an M-point DFT of a folded sequence.  The inverse, cropped to outputs
+// y = y0 + M jj < 2M, is the 4-point inverse DFT over r of
+//   w_r[y0] = W_P^{-r y0} (M-point inverse DFT of X[4k' + r] over k')[y0].
+// Each lane keeps one residue of one line (M points) in registers; the four
+// residues of a line sit in adjacent lanes of one wavefront, which combine
+// the inverse with two quad permutations.  One workgroup per (instance, kx):
+//   load X -> LDS rows [3][nz][Py+1];  forward y per row (in place);
+//   per ky column: forward z, kernel multiply, inverse z (in place);
+//   inverse y per row (in place);  store X.
+// Lines are read and written by the four lanes of one quad in program order,
+// so only the three phase changes need workgroup barriers.
+#define MM_YZR_T 256
+
+__host__ __device__ constexpr int brevc(int p, int lg) {
+  int r = 0;
+  for (int b = 0; b < lg; ++b) r |= ((p >> b) & 1) << (lg - 1 - b);
+  return r;
+}
+__host__ __device__ constexpr int ilog2c(int m) { return m <= 1 ? 0 : 1 + ilog2c(m >> 1); }
+
+// cos(2 pi j / 16)
+__device__ __forceinline__ constexpr float cos16(int j) {
+  j &= 15;
+  switch (j) {
+    case 0: return 1.0f;
+    case 1: case 15: return 0.92387953251128674f;
+    case 2: case 14: return 0.70710678118654752f;
+    case 3: case 13: return 0.38268343236508977f;
+    case 4: case 12: return 0.0f;
+    case 5: case 11: return -0.38268343236508977f;
+    case 6: case 10: return -0.70710678118654752f;
+    case 7: case 9: return -0.92387953251128674f;
+    default: return -1.0f;
+  }
+}
+
+// d * W_M^{k} (forward, W_M = e^{-2 pi i / M}) or d * W_M^{-k} (inverse), 0 <= k < M/2, M <= 16
+template <int M, bool INV>
+__device__ __forceinline__ float2 twc(float2 d, int k) {
+  if (k == 0) return d;
+  const int j = k * (16 / M);
+  if (j == 4) return rot<INV>(d);
+  const float c = cos16(j), sn = INV ? cos16(j - 4) : -cos16(j - 4);
+  return make_float2(d.x * c - d.y * sn, d.x * sn + d.y * c);
+}
+// d * W_M^{+-k} for M = 32 (angles on the 32-point circle)
+template <bool INV>
+__device__ __forceinline__ float2 twc32(float2 d, int k, const float2* tw32) {
+  if ((k & 1) == 0) return twc<16, INV>(d, k >> 1);
+  const float2 w = tw32[k];
+  const float sn = INV ? -w.y : w.y;
+  return make_float2(d.x * w.x - d.y * sn, d.x * sn + d.y * w.x);
+}
+
+// In-register radix-2 DIF DFT of length M: natural order in, bit-reversed out.
+template <int M, bool INV>
+__device__ __forceinline__ void reg_dft(float2 (&v)[M], const float2* tw32) {
+#pragma unroll
+  for (int h = M / 2; h >= 1; h >>= 1) {
+#pragma unroll
+    for (int g = 0; g < M; g += 2 * h) {
+#pragma unroll
+      for (int i = 0; i < h; ++i) {
+        const float2 a = v[g + i], b = v[g + i + h];
+        v[g + i] = cadd(a, b);
+        const float2 d = csub(a, b);
+        const int k = i * (M / (2 * h));
+        if constexpr (M <= 16) v[g + i + h] = twc<M, INV>(d, k);
+        else v[g + i + h] = twc32<INV>(d, k, tw32);
+      }
+    }
+  }
+}
+
+// quad_perm lane exchange: XOR 1 and XOR 2 within each group of four lanes
+__device__ __forceinline__ float dpp_x1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float dpp_x2(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float2 quad_x1(float2 v) { return make_float2(dpp_x1(v.x), dpp_x1(v.y)); }
+__device__ __forceinline__ float2 quad_x2(float2 v) { return make_float2(dpp_x2(v.x), dpp_x2(v.y)); }
+
+// Inverse 4-point DFT across the residue lanes r of a quad, keeping the
+// outputs jj = 0, 1: lane r returns h[y0 + M (r & 1)] for y0 = i + (M/2)(r >> 1),
+// i < M/2, where h[y0 + M jj] = sum_r i^{r jj} w_r[y0].
+template <int M>
+__device__ __forceinline__ void quad_inverse(const float2 (&w)[M], int r, float2 (&out)[M / 2]) {
+  const bool hi = r & 2, odd = r & 1;
+#pragma unroll
+  for (int i = 0; i < M / 2; ++i) {
+    const float2 mine = hi ? w[i + M / 2] : w[i];
+    const float2 recv = quad_x2(hi ? w[i] : w[i + M / 2]);
+    const float2 sm = cadd(mine, recv);
+    const float2 df = hi ? csub(recv, mine) : csub(mine, recv);
+    const float2 got = quad_x1(odd ? sm : df);
+    out[i] = odd ? cadd(got, rot<true>(df)) : cadd(sm, got);
+  }
+}
+
+// LDS element or zero: the (always in-bounds) load is unconditional and the
+// zero is selected afterwards, so no branch splits the batch of loads
+__device__ __forceinline__ float2 lds_or0(const float2* p, bool in) {
+  const float2 v = *p;
+  return make_float2(in ? v.x : 0.f, in ? v.y : 0.f);
+}
+
+// fold for residue r: f[j] = W_P^{rj} (x0 + (-i)^r x1)
+__device__ __forceinline__ float2 fold(float2 x0, float2 x1, int r, float2 w) {
+  if (r & 1) x1 = make_float2(x1.y, -x1.x);
+  if (r & 2) x1 = make_float2(-x1.x, -x1.y);
+  return cmul(cadd(x0, x1), w);
+}
+
+template <int MY, int MZ>
+__global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restrict__ descs,
+                                                         const WorkItem* __restrict__ work,
+                                                         const float2* __restrict__ tw) {
+  // LDS rows [3][2 MZ][RS]: row (c, z) holds y samples, zero beyond (nz, ny),
+  // so every line read below is unconditional with compile-time offsets
+  constexpr int PY = 4 * MY, PZ = 4 * MZ, RS = PY + 1, ZR = 2 * MZ, YR = 2 * MY;
+  constexpr int lgMY = ilog2c(MY), lgMZ = ilog2c(MZ), lgPY = lgMY + 2;
+  extern __shared__ float2 lds[];
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (D.ctl->done) return;
+  const int kx = wi.item;
+  const int ny = D.ny, nz = D.nz;
+  const int nrow = 3 * nz;
+  float2* B = lds;
+  float2* twy = B + 3 * ZR * RS;
+  float2* twz = twy + PY;
+  float2* tw32 = twz + PZ;
+  float* Ks = reinterpret_cast<float*>(tw32 + 32);   // kernel slice of this kx: [6][PZ/2+1][PY/2+1]
+  constexpr int HY1 = PY / 2 + 1, KPL = (PZ / 2 + 1) * HY1;
+  {
+    const MMG float* K = gbl(D.kern) + (size_t)kx * 6 * KPL;
+    for (int e = threadIdx.x; e < 6 * KPL; e += MM_YZR_T) Ks[e] = K[e];
+  }
+  load_twiddles(twy, PY, tw, MM_YZR_T);
+  load_twiddles(twz, PZ, tw, MM_YZR_T);
+  load_twiddles(tw32, 32, tw, MM_YZR_T);
+  MMG float2* X = gbl(D.fx) + (size_t)kx * nrow * ny;
+  // rows z >= nz are read by the z pass at every ky: clear them over the full padded width
+  for (int e = threadIdx.x; e < 3 * ZR * PY; e += MM_YZR_T) {
+    const int row = e >> lgPY, y = e & (PY - 1);
+    const int c = row / ZR, z = row - c * ZR;
+    if (z < nz && y >= YR) continue;
+    float2 v = make_float2(0.f, 0.f);
+    if (z < nz && y < ny) v = gld2(X + (c * nz + z) * ny + y);
+    B[row * RS + y] = v;
+  }
+  __syncthreads();
+  // forward y, one residue of one row (c, z < nz) per lane
+#pragma unroll 1
+  for (int t = threadIdx.x; t < 4 * nrow; t += MM_YZR_T) {
+    const int l = t >> 2, r = t & 3;
+    const int c = l / nz, z = l - c * nz;
+    float2* line = B + (c * ZR + z) * RS;
+    float2 f[MY];
+#pragma unroll
+    for (int j = 0; j < MY; ++j) f[j] = fold(line[j], line[j + MY], r, twy[r * j]);
+    reg_dft<MY, false>(f, tw32);
+#pragma unroll
+    for (int p = 0; p < MY; ++p) line[4 * brevc(p, lgMY) + r] = f[p];
+  }
+  __syncthreads();
+  // z per ky column: forward, kernel multiply, inverse
+#pragma unroll 1
+  for (int t = threadIdx.x; t < 4 * PY; t += MM_YZR_T) {
+    const int ky = t >> 2, r = t & 3;
+    float2 fx[MZ], fy[MZ], fz[MZ];
+    const float2* col = B + ky;
+#pragma unroll
+    for (int j = 0; j < MZ; ++j) fx[j] = fold(col[j * RS], col[(j + MZ) * RS], r, twz[r * j]);
+    reg_dft<MZ, false>(fx, tw32);
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int j = 0; j < MZ; ++j) fy[j] = fold(col[(ZR + j) * RS], col[(ZR + j + MZ) * RS], r, twz[r * j]);
+    reg_dft<MZ, false>(fy, tw32);
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int j = 0; j < MZ; ++j) fz[j] = fold(col[(2 * ZR + j) * RS], col[(2 * ZR + j + MZ) * RS], r, twz[r * j]);
+    reg_dft<MZ, false>(fz, tw32);
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int p = 0; p < MZ; ++p) {
+      kernel_mul_lds<PY, PZ>(Ks, ky, 4 * brevc(p, lgMZ) + r, fx[p], fy[p], fz[p]);
+      asm volatile("" ::: "memory");
+    }
+    const int z0 = (MZ / 2) * (r >> 1) + MZ * (r & 1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float2 g[MZ];
+#pragma unroll
+      for (int k = 0; k < MZ; ++k) g[k] = c == 0 ? fx[brevc(k, lgMZ)] : c == 1 ? fy[brevc(k, lgMZ)] : fz[brevc(k, lgMZ)];
+      reg_dft<MZ, true>(g, tw32);
+      float2 v[MZ];
+#pragma unroll
+      for (int y0 = 0; y0 < MZ; ++y0) v[y0] = cmul(g[brevc(y0, lgMZ)], twid<true>(twz, r * y0));
+      float2 o[MZ / 2];
+      quad_inverse<MZ>(v, r, o);
+      float2* out = B + (c * ZR + z0) * RS + ky;
+#pragma unroll
+      for (int i = 0; i < MZ / 2; ++i)
+        if (z0 + i < nz) out[i * RS] = o[i];
+      asm volatile("" ::: "memory");
+    }
+  }
+  __syncthreads();
+  // inverse y, one residue of one row (c, z < nz) per lane
+#pragma unroll 1
+  for (int t = threadIdx.x; t < 4 * nrow; t += MM_YZR_T) {
+    const int l = t >> 2, r = t & 3;
+    const int c = l / nz, z = l - c * nz;
+    float2* line = B + (c * ZR + z) * RS;
+    float2 g[MY];
+#pragma unroll
+    for (int k = 0; k < MY; ++k) g[k] = line[4 * k + r];
+    reg_dft<MY, true>(g, tw32);
+    float2 v[MY];
+#pragma unroll
+    for (int y0 = 0; y0 < MY; ++y0) v[y0] = cmul(g[brevc(y0, lgMY)], twid<true>(twy, r * y0));
+    float2 o[MY / 2];
+    quad_inverse<MY>(v, r, o);
+    const int y0 = (MY / 2) * (r >> 1) + MY * (r & 1);
+#pragma unroll
+    for (int i = 0; i < MY / 2; ++i) line[y0 + i] = o[i];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nrow * ny; e += MM_YZR_T) {
+    const int l = e / ny, y = e - l * ny;
+    const int c = l / nz, z = l - c * nz;
+    gst2(X + e, B[(c * ZR + z) * RS + y]);
+  }
+}
+
 // --------------------------------------------------------- split y passes
 // work item = tile of W lines (kx, c, z) of one instance; LDS [Py][W]
 template <int DIR>
@@ -529,6 +788,19 @@ hipError_t mmk_launch_fft_yz(int TK, int nblocks, size_t lds, const InstDesc* d,
   return hipGetLastError();
 }
 
+#define MM_YZR_CASE(A, B)                                                                        \
+  if (MY == A && MZ == B) {                                                                      \
+    hipLaunchKernelGGL((mmk::k_fft_yzr<A, B>), dim3(nblocks), dim3(MM_YZR_T), lds, s, d, w, tw); \
+    return hipGetLastError();                                                                    \
+  }
+hipError_t mmk_launch_fft_yzr(int MY, int MZ, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                              const float2* tw, hipStream_t s) {
+  MM_YZR_CASE(4, 4) MM_YZR_CASE(8, 4) MM_YZR_CASE(16, 4) MM_YZR_CASE(32, 4)
+  MM_YZR_CASE(4, 8) MM_YZR_CASE(8, 8) MM_YZR_CASE(16, 8) MM_YZR_CASE(32, 8)
+  MM_YZR_CASE(4, 16) MM_YZR_CASE(8, 16) MM_YZR_CASE(16, 16) MM_YZR_CASE(32, 16)
+  return hipErrorInvalidValue;
+}
+
 hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstDesc* d,
                             const WorkItem* w, const float2* tw, hipStream_t s) {
   if (dir < 0) hipLaunchKernelGGL(mmk::k_fft_y<-1>, dim3(nblocks), dim3(256), lds, s, d, w, W, tw);
@@ -545,5 +817,12 @@ hipError_t mmk_launch_fft_zc(int TW, int nblocks, size_t lds, const InstDesc* d,
 hipError_t mmk_set_lds_limits() {
   hipError_t e = hipFuncSetAttribute((const void*)mmk::k_fft_yz,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+#define MM_YZR_ATTR(A, B)                                                                         \
+  if (e == hipSuccess)                                                                            \
+    e = hipFuncSetAttribute((const void*)mmk::k_fft_yzr<A, B>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            160 * 1024);
+  MM_YZR_ATTR(4, 4) MM_YZR_ATTR(8, 4) MM_YZR_ATTR(16, 4) MM_YZR_ATTR(32, 4)
+  MM_YZR_ATTR(4, 8) MM_YZR_ATTR(8, 8) MM_YZR_ATTR(16, 8) MM_YZR_ATTR(32, 8)
+  MM_YZR_ATTR(4, 16) MM_YZR_ATTR(8, 16) MM_YZR_ATTR(16, 16) MM_YZR_ATTR(32, 16)
   return e;
 }

@@ -209,7 +209,8 @@ int padded(int n) {
   return p;
 }
 
-// Octant kernel spectrum: out[6][Pz/2+1][Py/2+1][Px/2+1] (float).
+// Octant kernel spectrum: out[Px/2+1][6][Pz/2+1][Py/2+1] (float), kx-major so that
+// one kx plane of all six components is contiguous.
 void kernel_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, std::vector<float>& out) {
   const int px = padded(nx), py = padded(ny), pz = padded(nz);
   const int hx = px / 2 + 1, hy = py / 2 + 1, hz = pz / 2 + 1;
@@ -263,7 +264,7 @@ void kernel_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, st
     for (int k = 0; k < kzn; ++k)
       for (int j = 0; j < kyn; ++j)
         for (int i = 0; i < kxn; ++i)
-          out[(((size_t)c * kzn + k) * kyn + j) * kxn + i] =
+          out[(((size_t)i * 6 + c) * kzn + k) * kyn + j] =
               (float)buf[((size_t)k * py + j) * px + i].real();
   }
 }

@@ -72,6 +72,7 @@ _SIGS = {
     "mm_batch_profile": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P,
                                         ctypes.POINTER(ctypes.c_int32)]),
     "mm_batch_tune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
+    "mm_batch_set_fft_path": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_run_record": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32]),
     "mm_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "mm_demag_tensor": (ctypes.c_int, [ctypes.c_double] * 6 + [_P]),
@@ -288,6 +289,12 @@ class Batch:
         buf = ctypes.create_string_buffer(65536)
         _check(self._lib.mm_batch_tune(self.h, buf, len(buf)))
         return json.loads(buf.value.decode())
+
+    YZ_PATHS = {"fused": 0, "reg": 1, "split": 2}
+
+    def set_fft_path(self, path):
+        """Force the demag y-z strategy ("fused", "reg" or "split") for every grid shape."""
+        _check(self._lib.mm_batch_set_fft_path(self.h, self.YZ_PATHS[path]))
 
     def profile(self, steps, tol=0.0, cap=32):
         names = ctypes.create_string_buffer(48 * cap)

@@ -303,7 +303,7 @@ def test_tuned_batch_keeps_parity():
     ctxs = [gpu_for(i) for i in insts]
     b1 = mmcav.Batch(ctxs)
     rep = b1.tune()
-    assert len(rep) == 1 and rep[0]["path"] in ("fused", "split")
+    assert len(rep) == 1 and rep[0]["path"] in ("fused", "reg", "split")
     assert all(c.stats()["accepted"] == 0 for c in ctxs)
     b1.run(20e-12)
     for c, r in zip(ctxs, ref):
@@ -313,3 +313,52 @@ def test_tuned_batch_keeps_parity():
     assert m_err(ctxs[1].get_m(), st) <= 2e-5
     b0.close()
     b1.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [(12, 12, 12), (10, 6, 5)])
+def test_fft_yz_paths_agree(shape):
+    """The three y-z strategies of the demag convolution (LDS-fused, register
+    lines, split passes) give the same trajectory to FP32 rounding, and the
+    oracle's within the parity bound, on a sphere and on a ragged box."""
+    from paper_2603_03706_amd import mmcav
+    if shape == (12, 12, 12):
+        inst = variant(W.sweep_sphere(5, count=8, n=12), method="rk4", dt0=0.2e-12)
+    else:
+        inst = W.Instance(grid=shape, cell=(5e-9, 4e-9, 3e-9), Ms=140e3, Aex=3.65e-12, alpha=0.01,
+                          B0=(0.01, 0.0, 0.15), demag=W.DEMAG_FFT,
+                          omega=np.array([TWO_PI * 5e9]), kappa=np.array([TWO_PI * 2e6]),
+                          g=np.array([TWO_PI * 80e6]), m0=_random_state(shape, 17),
+                          a0=np.array([0.05 + 0.02j]), method="rk4", dt0=0.2e-12)
+    st = oracle_for(inst)
+    run_oracle(st, 20e-12)
+    out = {}
+    for path in ("fused", "reg", "split"):
+        c = gpu_for(inst)
+        b = mmcav.Batch([c])
+        b.set_fft_path(path)
+        b.run(20e-12)
+        out[path] = c.get_m()
+        assert m_err(out[path], st) <= 2e-5, path
+        b.close()
+        c.close()
+    assert np.abs(out["reg"] - out["fused"]).max() <= 2e-6
+    assert np.abs(out["split"] - out["fused"]).max() <= 2e-6
+
+
+@pytest.mark.gpu
+def test_fft_path_rejects_unfit_shape():
+    """A shape outside the register strategy's sizes is refused without change."""
+    from paper_2603_03706_amd import mmcav
+    grid = (8, 3, 2)
+    inst = W.Instance(grid=grid, cell=(5e-9,) * 3, Ms=140e3, Aex=3.65e-12, alpha=0.01,
+                      B0=(0.0, 0.0, 0.2), demag=W.DEMAG_FFT,
+                      omega=np.array([TWO_PI * 5e9]), kappa=np.array([TWO_PI * 1e6]), g=np.array([TWO_PI * 50e6]),
+                      m0=_random_state(grid, 3), a0=np.array([0.01 + 0j]), method="rk4", dt0=0.1e-12)
+    c = gpu_for(inst)
+    b = mmcav.Batch([c])
+    with pytest.raises(mmcav.MMError):
+        b.set_fft_path("reg")
+    b.set_fft_path("split")
+    b.close()
+    c.close()
