@@ -89,6 +89,8 @@ def profile_name(kernel):
     if m:
         return f"{m.group(1)}_{'rk4' if m.group(2) == '0' else 'dp45'}_{m.group(3)}" \
             if not (m.group(1) == "stage" and m.group(2) == "0" and m.group(3) == "0") else "stage_rk4_start"
+    if k.startswith("mmk::k_fft_yzr<"):
+        return "fft_yz_convolve"
     table = {"mmk::k_fft_yz": "fft_yz_convolve", "mmk::k_fft_zc": "fft_z_convolve",
              "mmk::k_fft_y<-1>": "fft_y_forward", "mmk::k_fft_y<1>": "fft_y_inverse"}
     if k in table:

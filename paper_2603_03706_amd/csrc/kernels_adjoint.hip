@@ -45,33 +45,36 @@ __device__ __forceinline__ void cross3(const float* a, const float* b, float* o)
 __global__ __launch_bounds__(MMI_WG) void k_adj_start(const InstDesc* __restrict__ descs,
                                                       const int* __restrict__ wg_inst) {
   const InstDesc& D = descs[wg_inst[blockIdx.x]];
-  const InstCtl* C = D.ctl;
+  const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
   const int nc = D.ncell, S = D.S;
   const int i = (blockIdx.x - D.wg0) * MMI_WG + threadIdx.x;
   if (i >= nc) return;
-  const bool mag = !D.has_geom || D.geom[i];
+  const bool mag = !D.has_geom || gbl(D.geom)[i];
   const size_t vec = (size_t)3 * S * nc;
   const int ri = C->rec_index;
-  const float* Yn = D.rec_m + ((size_t)(ri + 1) * 4) * vec;      // state after the step
+  const MMG float* Yn = gbl(D.rec_m) + ((size_t)(ri + 1) * 4) * vec;      // state after the step
+  MMG float* const lam_y = gbl(D.lam_y);
+  MMG float* const lam_z = gbl(D.lam_z);
+  MMG float* const lam_k = gbl(D.lam_k);
   const float c6 = (float)(C->adj_h / 6.0);
   for (int s = 0; s < S; ++s) {
     float l[3], y[3];
     for (int c = 0; c < 3; ++c) {
-      l[c] = D.lam_y[(s * 3 + c) * nc + i];
+      l[c] = lam_y[(s * 3 + c) * nc + i];
       y[c] = Yn[(s * 3 + c) * nc + i];
     }
     float z[3] = {0.f, 0.f, 0.f};
     if (mag) {
-      const float inv = 1.0f / D.rec_norm[(size_t)ri * S * nc + s * nc + i];
+      const float inv = 1.0f / gbl(D.rec_norm)[(size_t)ri * S * nc + s * nc + i];
       const float d = l[0] * y[0] + l[1] * y[1] + l[2] * y[2];
       for (int c = 0; c < 3; ++c) z[c] = (l[c] - y[c] * d) * inv;
     }
     for (int c = 0; c < 3; ++c) {
       const int idx = (s * 3 + c) * nc + i;
-      D.lam_z[idx] = z[c];
-      D.lam_y[idx] = z[c];
-      D.lam_k[idx] = c6 * z[c];
+      lam_z[idx] = z[c];
+      lam_y[idx] = z[c];
+      lam_k[idx] = c6 * z[c];
     }
   }
 }
@@ -82,16 +85,18 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
                                                   const int* __restrict__ wg_inst) {
   __shared__ double sh[4];
   const InstDesc& D = descs[wg_inst[blockIdx.x]];
-  const InstCtl* C = D.ctl;
+  const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
   const int lw = blockIdx.x - D.wg0;
   const int nc = D.ncell, S = D.S, N = D.N;
   const int i = lw * MMI_WG + threadIdx.x;
   const bool valid = i < nc;
-  const bool mag = valid && (!D.has_geom || D.geom[i]);
+  const bool mag = valid && (!D.has_geom || gbl(D.geom)[i]);
   const int ri = C->rec_index;
   const Src src = stage_src(D, C, MMI_ADJ, ST);
-  const double* as = D.rec_a + ((size_t)ri * 4 + (ST - 1)) * N * 2;
+  const MMG double* as = gbl(D.rec_a) + ((size_t)ri * 4 + (ST - 1)) * N * 2;
+  const MMG float* const u_ = gbl(D.u);
+  MMG float* const lam_B = gbl(D.lam_B);
   const int x = valid ? i % D.nx : 0;
   const int yz = valid ? i / D.nx : 0;
   const int yy = yz % D.ny, zz = yz / D.ny;
@@ -109,7 +114,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
   if (mag)
     for (int n = 0; n < N; ++n) {
       const float b = (float)(D.h0[n] * (D.cphi[n] * as[2 * n] + D.sphi[n] * as[2 * n + 1]));
-      fb = fmaf(b, D.profiled ? D.u[(size_t)n * nc + i] : 1.f, fb);
+      fb = fmaf(b, D.profiled ? u_[(size_t)n * nc + i] : 1.f, fb);
     }
   const float gl = D.gl, al = D.alpha;
   const float dga = 2.f * al / (1.f + al * al);   // -d ln(gamma')/d alpha
@@ -125,7 +130,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
       field_at(D, src, i, x, yy, zz, m, s, fb, D.demag == 2, B);
       const float* ms = m[s];
       float l[3];
-      for (int c = 0; c < 3; ++c) l[c] = D.lam_k[(s * 3 + c) * nc + i];
+      for (int c = 0; c < 3; ++c) l[c] = gbl(D.lam_k)[(s * 3 + c) * nc + i];
       float P[3], Q[3], lm[3], t1[3], t2[3], t3[3], lB[3];
       cross3(ms, B, P);
       cross3(ms, P, Q);
@@ -147,15 +152,15 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
       gb0y += lB[1];
       gb0z += lB[2];
       lbx[s] = lB[0];
-      for (int c = 0; c < 3; ++c) D.lam_B[(s * 3 + c) * nc + i] = lB[c];
+      for (int c = 0; c < 3; ++c) lam_B[(s * 3 + c) * nc + i] = lB[c];
     }
   } else if (valid) {
     for (int s = 0; s < S; ++s)
-      for (int c = 0; c < 3; ++c) D.lam_B[(s * 3 + c) * nc + i] = 0.f;
+      for (int c = 0; c < 3; ++c) lam_B[(s * 3 + c) * nc + i] = 0.f;
   }
   // m^- transpose and the gradient of the mode profiles
   for (int n = 0; n < N; ++n) {
-    const float u = D.profiled ? (valid ? D.u[(size_t)n * nc + i] : 0.f) : 1.f;
+    const float u = D.profiled ? (valid ? u_[(size_t)n * nc + i] : 0.f) : 1.f;
     const float lr = (float)C->lmm[n][0], li = (float)C->lmm[n][1];
     double fbn = 0.0, mr = 0.0, mi = 0.0, gu = 0.0;
     if (mag) {
@@ -172,13 +177,13 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
         mi -= (double)(cs * m[s][1] * u);
         gu += (double)(cs * (lbx[s] * fbw + wmm * (lr * m[s][0] - li * m[s][1])));
       }
-      if (D.grad_u) D.grad_u[(size_t)n * nc + i] += gu;
+      if (D.grad_u) gbl(D.grad_u)[(size_t)n * nc + i] += gu;
     }
     const double s0 = block_sum(fbn, sh);
     const double s1 = block_sum(mr, sh);
     const double s2 = block_sum(mi, sh);
     if (threadIdx.x == 0) {
-      double* rec = D.partials + (size_t)lw * MMI_PSTRIDE;
+      MMG double* rec = gbl(D.partials) + (size_t)lw * MMI_PSTRIDE;
       rec[MMI_ASLOT_FB + n] = s0;
       rec[MMI_ASLOT_MM + 2 * n] = s1;
       rec[MMI_ASLOT_MM + 2 * n + 1] = s2;
@@ -189,13 +194,13 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
     for (int s = 0; s < 2; ++s)
       if (s < S)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) D.mu[(s * 3 + c) * nc + i] = mux[s][c];
+        for (int c = 0; c < 3; ++c) gbl(D.mu)[(s * 3 + c) * nc + i] = mux[s][c];
   const double r0 = block_sum(galpha, sh);
   const double r1 = block_sum(gb0x, sh);
   const double r2 = block_sum(gb0y, sh);
   const double r3 = block_sum(gb0z, sh);
   if (threadIdx.x == 0) {
-    double* rec = D.partials + (size_t)lw * MMI_PSTRIDE;
+    MMG double* rec = gbl(D.partials) + (size_t)lw * MMI_PSTRIDE;
     rec[MMI_ASLOT_ALPHA] = r0;
     rec[MMI_ASLOT_B0] = r1;
     rec[MMI_ASLOT_B0 + 1] = r2;
@@ -208,16 +213,19 @@ template <int ST>
 __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ descs,
                                                   const int* __restrict__ wg_inst) {
   const InstDesc& D = descs[wg_inst[blockIdx.x]];
-  const InstCtl* C = D.ctl;
+  const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
   const int nc = D.ncell, S = D.S;
   const int i = (blockIdx.x - D.wg0) * MMI_WG + threadIdx.x;
   if (i >= nc) return;
-  const bool mag = !D.has_geom || D.geom[i];
+  const bool mag = !D.has_geom || gbl(D.geom)[i];
   const int nx = D.nx, ny = D.ny, nz = D.nz;
   const int x = i % nx, yz = i / nx, y = yz % ny, z = yz / ny;
-  const float* L = D.lam_B;
-  const uint8_t* G = D.has_geom ? D.geom : nullptr;
+  const MMG float* L = gbl(D.lam_B);
+  const MMG uint8_t* G = D.has_geom ? gbl(D.geom) : nullptr;
+  MMG float* const lam_y = gbl(D.lam_y);
+  MMG float* const lam_z = gbl(D.lam_z);
+  MMG float* const lam_k = gbl(D.lam_k);
   const double h = C->adj_h;
   // coefficient of k_(ST-1) in y_ST and RK4 weight of k_(ST-1)
   const float cst = (float)(ST == 4 ? h : 0.5 * h);
@@ -227,7 +235,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ d
     for (int c = 0; c < 3; ++c) lb[s][c] = L[(s * 3 + c) * nc + i];
   for (int s = 0; s < S; ++s) {
     float mu[3];
-    for (int c = 0; c < 3; ++c) mu[c] = D.mu[(s * 3 + c) * nc + i];
+    for (int c = 0; c < 3; ++c) mu[c] = gbl(D.mu)[(s * 3 + c) * nc + i];
     if (mag) {
       // exchange (a symmetric graph Laplacian over magnetic pairs)
       const int base = s * 3 * nc;
@@ -257,7 +265,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ d
           if (S == 2) t += lb[1][c];
           v += nl[c] * t;
         } else if (D.demag == 2) {
-          v += D.bd[c * nc + i];
+          v += gbl(D.bd)[c * nc + i];
         }
         if (S == 2) v -= D.BE * lb[1 - s][c];
         mu[c] = v;
@@ -267,8 +275,8 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ d
     }
     for (int c = 0; c < 3; ++c) {
       const int idx = (s * 3 + c) * nc + i;
-      D.lam_y[idx] += mu[c];
-      if (ST > 1) D.lam_k[idx] = fmaf(wprev, D.lam_z[idx], cst * mu[c]);
+      lam_y[idx] += mu[c];
+      if (ST > 1) lam_k[idx] = fmaf(wprev, lam_z[idx], cst * mu[c]);
     }
   }
 }
@@ -291,7 +299,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__
                         (q >= MMI_ASLOT_ALPHA && q < MMI_ASLOT_B0 + 3);
       if (!used) continue;
       double v = 0.0;
-      for (int w = threadIdx.x; w < D.nwg; w += MMI_WG) v += D.partials[(size_t)w * MMI_PSTRIDE + q];
+      for (int w = threadIdx.x; w < D.nwg; w += MMI_WG) v += gbl(D.partials)[(size_t)w * MMI_PSTRIDE + q];
       v = block_sum(v, sh);
       if (threadIdx.x == 0) tot[q] = v;
     }

@@ -5,10 +5,32 @@
 
 namespace mmk {
 
+// Every buffer reached through the descriptor table lives in global memory.
+// Stating the address space lets the compiler emit global loads and stores
+// (scalar base + 32-bit offset, vector-memory counter only) instead of flat
+// ones, which carry 64-bit addresses and also wait on the LDS counter.
+#define MMG __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ MMG T* gbl(T* p) {
+  return (MMG T*)p;
+}
+
+// float2 through global pointers (the vector type's operators do not take
+// address-space qualified operands)
+__device__ __forceinline__ float2 gld2(const MMG float2* p) {
+  const MMG float* q = (const MMG float*)p;
+  return make_float2(q[0], q[1]);
+}
+__device__ __forceinline__ void gst2(MMG float2* p, float2 v) {
+  MMG float* q = (MMG float*)p;
+  q[0] = v.x;
+  q[1] = v.y;
+}
+
 // Stage input m = p0 + c1 * p1 (p1 optional), component-major per instance.
 struct Src {
-  const float* p0;
-  const float* p1;
+  const MMG float* p0;
+  const MMG float* p1;
   float c1;
   __device__ __forceinline__ float ld(int idx) const {
     float v = p0[idx];
@@ -20,7 +42,8 @@ struct Src {
 // Where the input of stage `stage` lives.  RK4: 0/1 state, 2 and 4 buffer
 // A, 3 buffer B.  DP45: 1 state, 2 state + h a21 k1 (not stored), 3 and 5
 // buffer A, 4 and 6 buffer B, 7 the normalised candidate.
-__device__ __forceinline__ Src stage_src(const InstDesc& D, const InstCtl* C, int method, int stage) {
+template <class CtlPtr>
+__device__ __forceinline__ Src stage_src(const InstDesc& D, CtlPtr C, int method, int stage) {
   Src s;
   s.p1 = nullptr;
   s.c1 = 0.f;
@@ -28,22 +51,22 @@ __device__ __forceinline__ Src stage_src(const InstDesc& D, const InstCtl* C, in
   if (method == MMI_ADJ) {
     // adjoint: stage 1..4 -> recorded stage input of the current step, 5 -> lambda_B
     const size_t vec = (size_t)3 * D.S * D.ncell;
-    s.p0 = (stage == 5) ? D.lam_B : D.rec_m + ((size_t)C->rec_index * 4 + (stage - 1)) * vec;
+    s.p0 = gbl((stage == 5) ? D.lam_B : D.rec_m + ((size_t)C->rec_index * 4 + (stage - 1)) * vec);
     return s;
   }
   if (method == MMI_RK4) {
-    s.p0 = (stage <= 1) ? D.y[cur] : (stage == 3 ? D.st[1] : D.st[0]);
+    s.p0 = gbl((stage <= 1) ? D.y[cur] : (stage == 3 ? D.st[1] : D.st[0]));
   } else {
     switch (stage) {
-      case 1: s.p0 = D.y[cur]; break;
+      case 1: s.p0 = gbl(D.y[cur]); break;
       case 2:
-        s.p0 = D.y[cur];
-        s.p1 = D.k[C->slot[0]];
+        s.p0 = gbl(D.y[cur]);
+        s.p1 = gbl(D.k[C->slot[0]]);
         s.c1 = (float)(C->h * DPCoef::a21);
         break;
-      case 3: case 5: s.p0 = D.st[0]; break;
-      case 4: case 6: s.p0 = D.st[1]; break;
-      default: s.p0 = D.y[1 - cur]; break;
+      case 3: case 5: s.p0 = gbl(D.st[0]); break;
+      case 4: case 6: s.p0 = gbl(D.st[1]); break;
+      default: s.p0 = gbl(D.y[1 - cur]); break;
     }
   }
   return s;
@@ -61,24 +84,37 @@ __device__ __forceinline__ void field_at(const InstDesc& D, const Src& src, int 
   const int base = s * 3 * nc;
   const float m0 = m[s][0], m1 = m[s][1], m2 = m[s][2];
   float bx = D.B0x, by = D.B0y, bz = D.B0z;
-  const uint8_t* G = D.has_geom ? D.geom : nullptr;
-  float sx = 0.f, sy = 0.f, sz = 0.f;
-#define MM_NBR(cond, off, coef)                                                     \
-  if (cond) {                                                                       \
-    const int j = i + (off);                                                        \
-    if (!G || G[j]) {                                                               \
-      sx = fmaf(coef, src.ld(base + j) - m0, sx);                                   \
-      sy = fmaf(coef, src.ld(base + nc + j) - m1, sy);                              \
-      sz = fmaf(coef, src.ld(base + 2 * nc + j) - m2, sz);                          \
-    }                                                                               \
+  // Neighbour indices: a missing or non-magnetic neighbour is replaced by the
+  // cell itself, whose difference m_j - m_i is then exactly zero, so every
+  // load below is unconditional and all of them are in flight together.
+  const int off[6] = {-1, 1, -nx, nx, -nx * ny, nx * ny};
+  const bool has[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0, z < nz - 1};
+  int jn[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) jn[q] = has[q] ? i + off[q] : i;
+  if (D.has_geom) {
+    const MMG uint8_t* G = gbl(D.geom);
+    uint8_t g[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) g[q] = G[jn[q]];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) jn[q] = g[q] ? jn[q] : i;
   }
-  MM_NBR(x > 0, -1, D.cex_x)
-  MM_NBR(x < nx - 1, 1, D.cex_x)
-  MM_NBR(y > 0, -nx, D.cex_y)
-  MM_NBR(y < ny - 1, nx, D.cex_y)
-  MM_NBR(z > 0, -nx * ny, D.cex_z)
-  MM_NBR(z < nz - 1, nx * ny, D.cex_z)
-#undef MM_NBR
+  float nb[6][3];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    nb[q][0] = src.ld(base + jn[q]);
+    nb[q][1] = src.ld(base + nc + jn[q]);
+    nb[q][2] = src.ld(base + 2 * nc + jn[q]);
+  }
+  const float cq[6] = {D.cex_x, D.cex_x, D.cex_y, D.cex_y, D.cex_z, D.cex_z};
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    sx = fmaf(cq[q], nb[q][0] - m0, sx);
+    sy = fmaf(cq[q], nb[q][1] - m1, sy);
+    sz = fmaf(cq[q], nb[q][2] - m2, sz);
+  }
   bx += sx;
   by += sy;
   bz += sz;
@@ -94,9 +130,10 @@ __device__ __forceinline__ void field_at(const InstDesc& D, const Src& src, int 
     by = fmaf(D.nly, ty, by);
     bz = fmaf(D.nlz, tz, bz);
   } else if (has_bd) {
-    bx += D.bd[i];
-    by += D.bd[nc + i];
-    bz += D.bd[2 * nc + i];
+    const MMG float* bd = gbl(D.bd);
+    bx += bd[i];
+    by += bd[nc + i];
+    bz += bd[2 * nc + i];
   }
   bx = fmaf(D.csign[s], fb, bx);
   if (D.S == 2) {
@@ -127,28 +164,6 @@ __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = nan_max(v, __shfl_xor(v, o, 64));
   return v;
-}
-
-// Every buffer reached through the descriptor table lives in global memory.
-// Stating the address space lets the compiler emit global loads and stores
-// (scalar base + 32-bit offset, vector-memory counter only) instead of flat
-// ones, which carry 64-bit addresses and also wait on the LDS counter.
-#define MMG __attribute__((address_space(1)))
-template <class T>
-__device__ __forceinline__ MMG T* gbl(T* p) {
-  return (MMG T*)p;
-}
-
-// float2 through global pointers (the vector type's operators do not take
-// address-space qualified operands)
-__device__ __forceinline__ float2 gld2(const MMG float2* p) {
-  const MMG float* q = (const MMG float*)p;
-  return make_float2(q[0], q[1]);
-}
-__device__ __forceinline__ void gst2(MMG float2* p, float2 v) {
-  MMG float* q = (MMG float*)p;
-  q[0] = v.x;
-  q[1] = v.y;
 }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_fft_xf(const InstDesc* __restrict__ des
   extern __shared__ float2 lds[];
   const WorkItem wi = work[blockIdx.x];
   const InstDesc& D = descs[wi.inst];
-  const InstCtl* C = D.ctl;
+  const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
   const int Px = D.px, nx = D.nx, ny = D.ny, nz = D.nz, nc = D.ncell;
   const int nyz = ny * nz, rows = 3 * nyz;
@@ -246,16 +246,39 @@ __global__ __launch_bounds__(256) void k_fft_xf(const InstDesc* __restrict__ des
   float2* twl = lds + Px * WP;
   load_twiddles(twl, Px, tw, 256);
   const int lgx = ilog2(Px);
-  for (int e = threadIdx.x; e < 2 * W * Px; e += 256) {
-    const int rr = e >> lgx, x = e & (Px - 1);
-    const int r = r0 + rr;
-    float v = 0.f;
-    if (x < nx && r < rows) {
-      const int c = r / nyz, yz = r - c * nyz;
-      v = src.ld(c * nc + yz * nx + x);
+  // batches of 8 loads per thread in flight (clamped addresses, padding selected afterwards)
+  const bool two = src.p1 != nullptr;
+  for (int e0 = 0; e0 < 2 * W * Px; e0 += 8 * 256) {
+    float v[8];
+    int idx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256 + threadIdx.x;
+      const int rr = e >> lgx, x = e & (Px - 1);
+      const int rc = min(r0 + rr, rows - 1);
+      const int c = rc / nyz, yz = rc - c * nyz;
+      idx[u] = c * nc + yz * nx + min(x, nx - 1);
+      v[u] = src.p0[idx[u]];
     }
-    float* p = reinterpret_cast<float*>(&buf[x * WP + (rr >> 1)]);
-    p[rr & 1] = v;
+    if (two) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = fmaf(src.c1, src.p1[idx[u]], v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256 + threadIdx.x;
+      const int rr = e >> lgx, x = e & (Px - 1);
+      if (!(e < 2 * W * Px && x < nx && r0 + rr < rows)) v[u] = 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256 + threadIdx.x;
+      if (e < 2 * W * Px) {
+        const int rr = e >> lgx, x = e & (Px - 1);
+        float* p = reinterpret_cast<float*>(&buf[x * WP + (rr >> 1)]);
+        p[rr & 1] = v[u];
+      }
+    }
   }
   __syncthreads();
   fft_cols<256, false>(buf, Px, lgx, 1, ilog2(W), 0, WP, twl);
@@ -271,7 +294,7 @@ __global__ __launch_bounds__(256) void k_fft_xf(const InstDesc* __restrict__ des
     if ((rr & 1) == 0) X = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
     else X = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
     const int c = r / nyz, yz = r - c * nyz;
-    D.fx[((size_t)kx * 3 + c) * nyz + yz] = X;
+    gst2(gbl(D.fx) + ((size_t)kx * 3 + c) * nyz + yz, X);
   }
 }
 
@@ -283,7 +306,7 @@ __global__ __launch_bounds__(256) void k_fft_xi(const InstDesc* __restrict__ des
   extern __shared__ float2 lds[];
   const WorkItem wi = work[blockIdx.x];
   const InstDesc& D = descs[wi.inst];
-  if (D.ctl->done) return;
+  if (gbl(D.ctl)->done) return;
   const int Px = D.px, nx = D.nx, ny = D.ny, nz = D.nz, nc = D.ncell;
   const int nyz = ny * nz, rows = 3 * nyz;
   const int r0 = wi.item * 2 * W;
@@ -293,15 +316,26 @@ __global__ __launch_bounds__(256) void k_fft_xi(const InstDesc* __restrict__ des
   float2* stg = lds + Px * WP;          // [Kx][2W]
   float2* twl = stg + Kx * 2 * W;
   load_twiddles(twl, Px, tw, 256);
-  for (int e = threadIdx.x; e < Kx * 2 * W; e += 256) {
-    const int kx = e / (2 * W), rr = e - kx * 2 * W;
-    const int r = r0 + rr;
-    float2 X = make_float2(0.f, 0.f);
-    if (r < rows) {
-      const int c = r / nyz, yz = r - c * nyz;
-      X = D.fx[((size_t)kx * 3 + c) * nyz + yz];
+  // batches of 8 loads per thread in flight (clamped addresses, padding selected afterwards)
+  const MMG float2* fx = gbl(D.fx);
+  for (int e0 = 0; e0 < Kx * 2 * W; e0 += 8 * 256) {
+    float2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256 + threadIdx.x;
+      const int kx = min(e / (2 * W), Kx - 1), rr = e - (e / (2 * W)) * 2 * W;
+      const int r = r0 + rr;
+      const bool in = e < Kx * 2 * W && r < rows;
+      const int rc = min(r, rows - 1);
+      const int c = rc / nyz, yz = rc - c * nyz;
+      const float2 t = gld2(fx + ((size_t)kx * 3 + c) * nyz + yz);
+      v[u] = make_float2(in ? t.x : 0.f, in ? t.y : 0.f);
     }
-    stg[kx * 2 * W + rr] = X;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + u * 256 + threadIdx.x;
+      if (e < Kx * 2 * W) stg[e] = v[u];
+    }
   }
   __syncthreads();
   const int half = Px / 2;
@@ -329,7 +363,7 @@ __global__ __launch_bounds__(256) void k_fft_xi(const InstDesc* __restrict__ des
     if (r >= rows) continue;
     const float2 Z = buf[x * WP + (rr >> 1)];
     const int c = r / nyz, yz = r - c * nyz;
-    D.bd[c * nc + yz * nx + x] = sc * ((rr & 1) ? Z.y : Z.x);
+    gbl(D.bd)[c * nc + yz * nx + x] = sc * ((rr & 1) ? Z.y : Z.x);
   }
 }
 
@@ -347,7 +381,7 @@ __global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__
   extern __shared__ float2 lds[];
   const WorkItem wi = work[blockIdx.x];
   const InstDesc& D = descs[wi.inst];
-  if (D.ctl->done) return;
+  if (gbl(D.ctl)->done) return;
   const int kx = wi.item;
   const int ny = D.ny, nz = D.nz, Py = D.py, Pz = D.pz;
   const int RP = Py + 1;
@@ -363,11 +397,11 @@ __global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__
   for (int l = threadIdx.x; l < 3 * nz; l += MM_YZ_T) ytab[l] = l * RP;
   const int lgy = ilog2(Py), lgz = ilog2(Pz), lgT = ilog2(TK);
   const int nyz = ny * nz;
-  float2* X = D.fx + (size_t)kx * 3 * nyz;
+  MMG float2* X = gbl(D.fx) + (size_t)kx * 3 * nyz;
   // load rows, zero-padded in y
   for (int e = threadIdx.x; e < 3 * nz * Py; e += MM_YZ_T) {
     const int l = e >> lgy, y = e & (Py - 1);
-    ybuf[l * RP + y] = (y < ny) ? X[l * ny + y] : make_float2(0.f, 0.f);
+    ybuf[l * RP + y] = (y < ny) ? gld2(X + l * ny + y) : make_float2(0.f, 0.f);
   }
   __syncthreads();
   fft_rows<MM_YZ_T, false>(ybuf, Py, lgy, 3 * nz, ytab, twy);
@@ -416,7 +450,7 @@ __global__ __launch_bounds__(MM_YZ_T) void k_fft_yz(const InstDesc* __restrict__
   fft_rows<MM_YZ_T, true>(ybuf, Py, lgy, 3 * nz, ytab, twy);
   for (int e = threadIdx.x; e < 3 * nz * Py; e += MM_YZ_T) {
     const int l = e >> lgy, y = e & (Py - 1);
-    if (y < ny) X[l * ny + y] = ybuf[l * RP + y];
+    if (y < ny) gst2(X + l * ny + y, ybuf[l * RP + y]);
   }
 }
 
@@ -550,7 +584,7 @@ __global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restr
   extern __shared__ float2 lds[];
   const WorkItem wi = work[blockIdx.x];
   const InstDesc& D = descs[wi.inst];
-  if (D.ctl->done) return;
+  if (gbl(D.ctl)->done) return;
   const int kx = wi.item;
   const int ny = D.ny, nz = D.nz;
   const int nrow = 3 * nz;
@@ -560,23 +594,46 @@ __global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restr
   float2* tw32 = twz + PZ;
   float* Ks = reinterpret_cast<float*>(tw32 + 32);   // kernel slice of this kx: [6][PZ/2+1][PY/2+1]
   constexpr int HY1 = PY / 2 + 1, KPL = (PZ / 2 + 1) * HY1;
+  MMG float2* X = gbl(D.fx) + (size_t)kx * nrow * ny;
   {
+    // all global loads of the prologue are issued before the first wait
+    constexpr int NK = (6 * KPL + MM_YZR_T - 1) / MM_YZR_T, NXE = 3 * ZR * PY;
+    constexpr int NX = (NXE + MM_YZR_T - 1) / MM_YZR_T;
     const MMG float* K = gbl(D.kern) + (size_t)kx * 6 * KPL;
-    for (int e = threadIdx.x; e < 6 * KPL; e += MM_YZR_T) Ks[e] = K[e];
+    float kv[NK];
+    float2 xv[NX];
+#pragma unroll
+    for (int it = 0; it < NK; ++it) {
+      const int e = it * MM_YZR_T + threadIdx.x;
+      kv[it] = e < 6 * KPL ? K[e] : 0.f;
+    }
+#pragma unroll
+    for (int it = 0; it < NX; ++it) {
+      // rows z >= nz are read by the z pass at every ky: they are cleared over the full padded width
+      const int e = it * MM_YZR_T + threadIdx.x;
+      const int row = e >> lgPY, y = e & (PY - 1);
+      const int c = row / ZR, z = row - c * ZR;
+      // clamped (in-bounds) address, padding selected afterwards: no branch between the loads
+      const bool in = e < NXE && z < nz && y < ny;
+      const float2 v = gld2(X + (min(c, 2) * nz + min(z, nz - 1)) * ny + min(y, ny - 1));
+      xv[it] = make_float2(in ? v.x : 0.f, in ? v.y : 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < NK; ++it) {
+      const int e = it * MM_YZR_T + threadIdx.x;
+      if (e < 6 * KPL) Ks[e] = kv[it];
+    }
+#pragma unroll
+    for (int it = 0; it < NX; ++it) {
+      const int e = it * MM_YZR_T + threadIdx.x;
+      const int row = e >> lgPY, y = e & (PY - 1);
+      const int z = row % ZR;
+      if (e < NXE && (z >= nz || y < YR)) B[row * RS + y] = xv[it];
+    }
   }
   load_twiddles(twy, PY, tw, MM_YZR_T);
   load_twiddles(twz, PZ, tw, MM_YZR_T);
   load_twiddles(tw32, 32, tw, MM_YZR_T);
-  MMG float2* X = gbl(D.fx) + (size_t)kx * nrow * ny;
-  // rows z >= nz are read by the z pass at every ky: clear them over the full padded width
-  for (int e = threadIdx.x; e < 3 * ZR * PY; e += MM_YZR_T) {
-    const int row = e >> lgPY, y = e & (PY - 1);
-    const int c = row / ZR, z = row - c * ZR;
-    if (z < nz && y >= YR) continue;
-    float2 v = make_float2(0.f, 0.f);
-    if (z < nz && y < ny) v = gld2(X + (c * nz + z) * ny + y);
-    B[row * RS + y] = v;
-  }
   __syncthreads();
   // forward y, one residue of one row (c, z < nz) per lane
 #pragma unroll 1
@@ -671,7 +728,7 @@ __global__ __launch_bounds__(256) void k_fft_y(const InstDesc* __restrict__ desc
   extern __shared__ float2 lds[];
   const WorkItem wi = work[blockIdx.x];
   const InstDesc& D = descs[wi.inst];
-  if (D.ctl->done) return;
+  if (gbl(D.ctl)->done) return;
   const int ny = D.ny, Py = D.py;
   const int nlines = D.kx * 3 * D.nz;
   const int l0 = wi.item * W;
@@ -685,7 +742,7 @@ __global__ __launch_bounds__(256) void k_fft_y(const InstDesc* __restrict__ desc
     const int ll = e >> lgy, y = e & (Py - 1);
     const int l = l0 + ll;
     float2 v = make_float2(0.f, 0.f);
-    if (l < nlines && y < nin) v = (DIR < 0) ? D.fx[(size_t)l * ny + y] : D.fy[(size_t)l * Py + y];
+    if (l < nlines && y < nin) v = (DIR < 0) ? gld2(gbl(D.fx) + (size_t)l * ny + y) : gld2(gbl(D.fy) + (size_t)l * Py + y);
     // forward: natural order in; inverse: bit-reversed order in
     buf[((DIR < 0) ? y : brev(y, lgy)) * WP + ll] = v;
   }
@@ -698,8 +755,8 @@ __global__ __launch_bounds__(256) void k_fft_y(const InstDesc* __restrict__ desc
     const int l = l0 + ll;
     if (l >= nlines) continue;
     const float2 v = buf[((DIR < 0) ? brev(y, lgy) : y) * WP + ll];
-    if (DIR < 0) D.fy[(size_t)l * Py + y] = v;
-    else D.fx[(size_t)l * ny + y] = v;
+    if (DIR < 0) gst2(gbl(D.fy) + (size_t)l * Py + y, v);
+    else gst2(gbl(D.fx) + (size_t)l * ny + y, v);
   }
 }
 
@@ -711,7 +768,7 @@ __global__ __launch_bounds__(256) void k_fft_zc(const InstDesc* __restrict__ des
   extern __shared__ float2 lds[];
   const WorkItem wi = work[blockIdx.x];
   const InstDesc& D = descs[wi.inst];
-  if (D.ctl->done) return;
+  if (gbl(D.ctl)->done) return;
   const int nz = D.nz, Py = D.py, Pz = D.pz;
   const int tiles = (Py + TW - 1) / TW;
   const int kx = wi.item / tiles;
@@ -725,7 +782,7 @@ __global__ __launch_bounds__(256) void k_fft_zc(const InstDesc* __restrict__ des
     const int c = l / TW, t = l - c * TW;
     const int ky = ky0 + t;
     float2 v = make_float2(0.f, 0.f);
-    if (z < nz && ky < Py) v = D.fy[(((size_t)kx * 3 + c) * nz + z) * Py + ky];
+    if (z < nz && ky < Py) v = gld2(gbl(D.fy) + (((size_t)kx * 3 + c) * nz + z) * Py + ky);
     buf[e] = v;
   }
   __syncthreads();
@@ -747,7 +804,7 @@ __global__ __launch_bounds__(256) void k_fft_zc(const InstDesc* __restrict__ des
     const int z = e / NL, l = e - z * NL;
     const int c = l / TW, t = l - c * TW;
     const int ky = ky0 + t;
-    if (ky < Py) D.fy[(((size_t)kx * 3 + c) * nz + z) * Py + ky] = buf[e];
+    if (ky < Py) gst2(gbl(D.fy) + (((size_t)kx * 3 + c) * nz + z) * Py + ky, buf[e]);
   }
 }
 

@@ -57,11 +57,11 @@ __device__ __forceinline__ double block_reduce(double v, double* sh) {
 // Reduce the per-thread mode sums of a vector field v (complex weight
 // sum_s c_s (v_x - i v_y) u_n) and store them in the partial record.
 __device__ __forceinline__ void reduce_modes(const InstDesc& D, int i, bool mag, float vr, float vi,
-                                             double* rec, int slot, double* sh) {
+                                             MMG double* rec, int slot, double* sh) {
   for (int n = 0; n < D.N; ++n) {
     double wr = 0.0, wi = 0.0;
     if (mag) {
-      const double u = D.profiled ? (double)D.u[(size_t)n * D.ncell + i] : 1.0;
+      const double u = D.profiled ? (double)gbl(D.u)[(size_t)n * D.ncell + i] : 1.0;
       wr = u * (double)vr;
       wi = u * (double)vi;
     }
@@ -80,7 +80,7 @@ template <bool MAX>
 __device__ __forceinline__ double gather_slot(const InstDesc& D, int slot, double* sh) {
   double v = MAX ? 0.0 : 0.0;
   for (int w = threadIdx.x; w < D.nwg; w += MMI_WG) {
-    const double p = D.partials[(size_t)w * MMI_PSTRIDE + slot];
+    const double p = gbl(D.partials)[(size_t)w * MMI_PSTRIDE + slot];
     v = MAX ? nan_max(v, p) : v + p;
   }
   return block_reduce<MAX>(v, sh);
@@ -92,12 +92,14 @@ __device__ __forceinline__ void record_sample(const InstDesc& D, InstCtl* C, dou
                                               const double (*a)[2], const double (*mm)[2]) {
   const long long n = C->trace_n;
   if (n >= C->trace_max) return;
-  D.trace_t[n] = t;
+  gbl(D.trace_t)[n] = t;
+  MMG double* ta = gbl(D.trace_a);
+  MMG double* tm = gbl(D.trace_m);
   for (int q = 0; q < D.N; ++q) {
-    D.trace_a[(n * D.N + q) * 2] = a[q][0];
-    D.trace_a[(n * D.N + q) * 2 + 1] = a[q][1];
-    D.trace_m[(n * D.N + q) * 2] = mm[q][0];
-    D.trace_m[(n * D.N + q) * 2 + 1] = mm[q][1];
+    ta[(n * D.N + q) * 2] = a[q][0];
+    ta[(n * D.N + q) * 2 + 1] = a[q][1];
+    tm[(n * D.N + q) * 2] = mm[q][0];
+    tm[(n * D.N + q) * 2 + 1] = mm[q][1];
   }
   C->trace_n = n + 1;
 }
@@ -132,7 +134,7 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   // m^- of the stage input written by this kernel
   const double(*mmv)[2] = reinterpret_cast<const double(*)[2]>(tot + MMI_SLOT_MM);
   if (METHOD == MMI_RK4 && ST >= 1 && C->rec_index >= 0) {
-    double* ra = D.rec_a + ((size_t)C->rec_index * 4 + (ST - 1)) * N * 2;
+    MMG double* ra = gbl(D.rec_a) + ((size_t)C->rec_index * 4 + (ST - 1)) * N * 2;
     for (int n = 0; n < N; ++n) {
       ra[2 * n] = C->as[n][0];
       ra[2 * n + 1] = C->as[n][1];
@@ -350,21 +352,24 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
                                                   const int* __restrict__ wg_inst) {
   __shared__ double sh[4];
   const InstDesc& D = descs[wg_inst[blockIdx.x]];
-  InstCtl* C = D.ctl;
+  // the control block is only read here (the finalisation kernel writes it)
+  const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
   const int lw = blockIdx.x - D.wg0;
   const int nc = D.ncell;
   const int i = lw * MMI_WG + threadIdx.x;
   const bool valid = i < nc;
-  const bool mag = valid && (!D.has_geom || D.geom[i]);
+  const bool mag = valid && (!D.has_geom || gbl(D.geom)[i]);
   const int cur = C->cur;
   const double h = C->h;
   const int S = D.S;
   using P = DPCoef;
   // control values used below, read once (global stores cannot alias them)
-  float* K[7];
+  MMG float* K[7];
 #pragma unroll
-  for (int j = 0; j < 7; ++j) K[j] = D.k[(METHOD == MMI_DP45) ? C->slot[j] : j];
+  for (int j = 0; j < 7; ++j) K[j] = gbl(D.k[(METHOD == MMI_DP45) ? C->slot[j] : j]);
+  MMG float* const st0 = gbl(D.st[0]);
+  MMG float* const st1 = gbl(D.st[1]);
   float fbc[MMI_MAX_MODES];
   const int NM = D.N;
   for (int n = 0; n < MMI_MAX_MODES; ++n)
@@ -388,7 +393,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   // recording for the discrete adjoint: keep every stage input of the step
   const int ri = (METHOD == MMI_RK4 && ST >= 1) ? C->rec_index : -1;
   if (METHOD == MMI_RK4 && ST >= 1 && ri >= 0 && valid) {
-    float* R = D.rec_m + ((size_t)ri * 4 + (ST - 1)) * (size_t)(3 * S * nc);
+    MMG float* R = gbl(D.rec_m) + ((size_t)ri * 4 + (ST - 1)) * (size_t)(3 * S * nc);
 #pragma unroll
     for (int s = 0; s < 2; ++s)
       if (s < S)
@@ -400,7 +405,8 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
     // cavity feedback sum_n h0_n u_n Re[e^{-i Phi_n} a_n]
     float fb = 0.f;
     if (D.profiled) {
-      for (int n = 0; n < NM; ++n) fb = fmaf(fbc[n], D.u[(size_t)n * nc + i], fb);
+      const MMG float* u = gbl(D.u);
+      for (int n = 0; n < NM; ++n) fb = fmaf(fbc[n], u[(size_t)n * nc + i], fb);
     } else {
       for (int n = 0; n < NM; ++n) fb += fbc[n];
     }
@@ -417,7 +423,28 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   bool bad = false;
   bool has_next = true;
   if (valid) {
-    const float* Y = D.y[cur];
+    const MMG float* Y = gbl(D.y[cur]);
+    // every earlier-stage value this stage combines is loaded before any store,
+    // so the loads of all components are in flight together
+    constexpr bool dp = METHOD == MMI_DP45;
+    constexpr bool needY = dp ? (ST >= 2 && ST <= 6) : (ST >= 2);
+    constexpr unsigned usedK = dp ? (ST == 2 ? 0x1u : ST == 3 ? 0x3u : ST == 4 ? 0x7u : ST == 5 ? 0xFu
+                                     : ST == 6 ? 0x1Du : ST == 7 ? 0x3Du : 0u)
+                                  : (ST >= 2 ? 0x1u : 0u);
+    float yv[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float kl[6][2][3];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      if (s >= S) continue;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int idx = (s * 3 + c) * nc + i;
+        if (needY) yv[s][c] = Y[idx];
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+          if (usedK & (1u << j)) kl[j][s][c] = K[j][idx];
+      }
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       if (s >= S) continue;
@@ -431,60 +458,59 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
           } else if (ST == 1) {
             K[0][idx] = kk;
             nx_[s][c] = fmaf((float)(0.5 * h), kk, m[s][c]);
-            D.st[0][idx] = nx_[s][c];
+            st0[idx] = nx_[s][c];
           } else if (ST == 2 || ST == 3) {
-            const float acc = fmaf(2.f, kk, K[0][idx]);
+            const float acc = fmaf(2.f, kk, kl[0][s][c]);
             K[0][idx] = acc;
             const float cc = (float)(ST == 3 ? h : 0.5 * h);
-            nx_[s][c] = fmaf(cc, kk, Y[idx]);
-            D.st[ST == 2 ? 1 : 0][idx] = nx_[s][c];
+            nx_[s][c] = fmaf(cc, kk, yv[s][c]);
+            (ST == 2 ? st1 : st0)[idx] = nx_[s][c];
           } else {  // ST == 4
-            nx_[s][c] = fmaf((float)(h / 6.0), K[0][idx] + kk, Y[idx]);
+            nx_[s][c] = fmaf((float)(h / 6.0), kl[0][s][c] + kk, yv[s][c]);
           }
         } else {
-          const float* K0 = K[0];
           if (ST == 1) {
             K[0][idx] = kk;
             nx_[s][c] = m[s][c];
           } else if (ST == 2) {
             K[1][idx] = kk;
             aux[s][c] = m[s][c];
-            nx_[s][c] = Y[idx] + ((float)(h * P::a31) * K0[idx] + (float)(h * P::a32) * kk);
-            D.st[0][idx] = nx_[s][c];
+            nx_[s][c] = yv[s][c] + ((float)(h * P::a31) * kl[0][s][c] + (float)(h * P::a32) * kk);
+            st0[idx] = nx_[s][c];
           } else if (ST == 3) {
             K[2][idx] = kk;
-            nx_[s][c] = Y[idx] + ((float)(h * P::a41) * K0[idx] +
-                                  (float)(h * P::a42) * K[1][idx] +
+            nx_[s][c] = yv[s][c] + ((float)(h * P::a41) * kl[0][s][c] +
+                                  (float)(h * P::a42) * kl[1][s][c] +
                                   (float)(h * P::a43) * kk);
-            D.st[1][idx] = nx_[s][c];
+            st1[idx] = nx_[s][c];
           } else if (ST == 4) {
             K[3][idx] = kk;
-            nx_[s][c] = Y[idx] + ((float)(h * P::a51) * K0[idx] +
-                                  (float)(h * P::a52) * K[1][idx] +
-                                  (float)(h * P::a53) * K[2][idx] +
+            nx_[s][c] = yv[s][c] + ((float)(h * P::a51) * kl[0][s][c] +
+                                  (float)(h * P::a52) * kl[1][s][c] +
+                                  (float)(h * P::a53) * kl[2][s][c] +
                                   (float)(h * P::a54) * kk);
-            D.st[0][idx] = nx_[s][c];
+            st0[idx] = nx_[s][c];
           } else if (ST == 5) {
             K[4][idx] = kk;
-            nx_[s][c] = Y[idx] + ((float)(h * P::a61) * K0[idx] +
-                                  (float)(h * P::a62) * K[1][idx] +
-                                  (float)(h * P::a63) * K[2][idx] +
-                                  (float)(h * P::a64) * K[3][idx] +
+            nx_[s][c] = yv[s][c] + ((float)(h * P::a61) * kl[0][s][c] +
+                                  (float)(h * P::a62) * kl[1][s][c] +
+                                  (float)(h * P::a63) * kl[2][s][c] +
+                                  (float)(h * P::a64) * kl[3][s][c] +
                                   (float)(h * P::a65) * kk);
-            D.st[1][idx] = nx_[s][c];
+            st1[idx] = nx_[s][c];
           } else if (ST == 6) {
             K[5][idx] = kk;
-            nx_[s][c] = Y[idx] + ((float)(h * P::b1) * K0[idx] +
-                                  (float)(h * P::b3) * K[2][idx] +
-                                  (float)(h * P::b4) * K[3][idx] +
-                                  (float)(h * P::b5) * K[4][idx] +
+            nx_[s][c] = yv[s][c] + ((float)(h * P::b1) * kl[0][s][c] +
+                                  (float)(h * P::b3) * kl[2][s][c] +
+                                  (float)(h * P::b4) * kl[3][s][c] +
+                                  (float)(h * P::b5) * kl[4][s][c] +
                                   (float)(h * P::b6) * kk);
           } else {  // ST == 7
             K[6][idx] = kk;
-            const float e = (float)P::e1 * K0[idx] + (float)P::e3 * K[2][idx] +
-                            (float)P::e4 * K[3][idx] +
-                            (float)P::e5 * K[4][idx] +
-                            (float)P::e6 * K[5][idx] + (float)P::e7 * kk;
+            const float e = (float)P::e1 * kl[0][s][c] + (float)P::e3 * kl[2][s][c] +
+                            (float)P::e4 * kl[3][s][c] +
+                            (float)P::e5 * kl[4][s][c] +
+                            (float)P::e6 * kl[5][s][c] + (float)P::e7 * kk;
             const float ae = fabsf(e);
             errm = (ae != ae || errm != errm) ? ae + errm : fmaxf(errm, ae);
           }
@@ -496,7 +522,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
         float v0 = nx_[s][0], v1 = nx_[s][1], v2 = nx_[s][2];
         if (mag) {
           const float nrm = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
-          if (METHOD == MMI_RK4 && ri >= 0) D.rec_norm[(size_t)ri * S * nc + s * nc + i] = nrm;
+          if (METHOD == MMI_RK4 && ri >= 0) gbl(D.rec_norm)[(size_t)ri * S * nc + s * nc + i] = nrm;
           const float inv = 1.0f / nrm;
           v0 *= inv;
           v1 *= inv;
@@ -506,7 +532,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
         nx_[s][0] = v0;
         nx_[s][1] = v1;
         nx_[s][2] = v2;
-        float* Yn = D.y[1 - cur];
+        MMG float* Yn = gbl(D.y[1 - cur]);
         Yn[(s * 3 + 0) * nc + i] = v0;
         Yn[(s * 3 + 1) * nc + i] = v1;
         Yn[(s * 3 + 2) * nc + i] = v2;
@@ -516,7 +542,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   if (METHOD == MMI_DP45 && ST == 7) has_next = false;
 
   // ---- per-workgroup partials
-  double* rec = D.partials + (size_t)lw * MMI_PSTRIDE;
+  MMG double* rec = gbl(D.partials) + (size_t)lw * MMI_PSTRIDE;
   if (has_next) {
     float vr = 0.f, vi = 0.f;
 #pragma unroll
