@@ -199,6 +199,14 @@ mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len);
 enum { MM_YZ_FUSED = 0, MM_YZ_REGISTER = 1, MM_YZ_SPLIT = 2 };
 mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path);
 
+/* Strategy of the x passes (R2C forward, C2R inverse) for every FFT grid
+ * shape: MM_X_REGISTER holds each pair of real rows as one complex line split
+ * over four lanes in registers (padded x of 16..128 cells only; the default
+ * where it applies), MM_X_LDS transforms tiles of rows in LDS.  Same results
+ * to FP32 rounding.  MM_ERR_ARG, changing nothing, if a shape cannot use it. */
+enum { MM_X_LDS = 0, MM_X_REGISTER = 1 };
+mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path);
+
 /* Per-kernel timing: run `steps` steps eagerly, timing each launch with HIP
  * events on the library stream.  Fills up to `cap` entries: names (each
  * char[48]), launches, total milliseconds, algorithmic bytes per launch

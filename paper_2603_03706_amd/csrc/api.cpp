@@ -138,6 +138,10 @@ bool reg_fits(int ny, int nz, int py, int pz) {
 }
 
 enum { PATH_FUSED = MM_YZ_FUSED, PATH_REG = MM_YZ_REGISTER, PATH_SPLIT = MM_YZ_SPLIT };
+
+// x passes with lines in registers (selected by a tile width Wx of 0): padded x of 16..128
+bool xreg_fits(int px) { return px == 16 || px == 32 || px == 64 || px == 128; }
+constexpr int XR_ROWS = 128;
 const char* path_name(int p) { return p == PATH_REG ? "reg" : p == PATH_SPLIT ? "split" : "fused"; }
 
 Layout make_layout(const mm_params& p, int n_modes) {
@@ -430,7 +434,7 @@ mm_status build_group(mm_batch::Group& g) {
       *p = nullptr;
     }
   const int rows = 3 * g.ny * g.nz;
-  const int tiles_x = (rows + 2 * g.Wx - 1) / (2 * g.Wx);
+  const int tiles_x = g.Wx == 0 ? (rows + XR_ROWS - 1) / XR_ROWS : (rows + 2 * g.Wx - 1) / (2 * g.Wx);
   std::vector<WorkItem> xf, yz, yy, zc;
   const int ylines = g.kx * 3 * g.nz;
   const int tiles_y = (ylines + g.Wy - 1) / g.Wy;
@@ -455,8 +459,8 @@ mm_status build_group(mm_batch::Group& g) {
   if (mm_status s = up(yz, &g.yz, &g.n_yz)) return s;
   if (mm_status s = up(yy, &g.y, &g.n_y)) return s;
   if (mm_status s = up(zc, &g.zc, &g.n_zc)) return s;
-  g.lds_xf = sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + g.px);
-  g.lds_xi = sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + (size_t)g.kx * 2 * g.Wx + g.px);
+  g.lds_xf = g.Wx == 0 ? 0 : sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + g.px);
+  g.lds_xi = g.Wx == 0 ? 0 : sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + (size_t)g.kx * 2 * g.Wx + g.px);
   g.lds_yz = g.path == PATH_REG ? reg_lds(g.nz, g.py, g.pz) : fused_lds(g.ny, g.nz, g.py, g.pz, g.TK);
   g.lds_y = sizeof(float2) * ((size_t)g.py * (g.Wy + 1) + g.py);
   g.lds_zc = sizeof(float2) * ((size_t)g.pz * 3 * g.TW + g.pz);
@@ -498,7 +502,7 @@ mm_status batch_build(mm_batch* b) {
     g->members.push_back(i);
   }
   for (auto& g : b->groups) {
-    g.Wx = std::max(1, std::min(32, 2048 / g.px));
+    g.Wx = xreg_fits(g.px) ? 0 : std::max(1, std::min(32, 2048 / g.px));
     g.Wy = std::max(1, std::min(64, 2048 / g.py));
     int tw = 1;
     while (tw * 2 <= 16 && 3 * (tw * 2) * g.pz <= 2048) tw *= 2;
@@ -553,6 +557,8 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1) {
   if (method < 0) method = b->method;
   for (auto& g : b->groups) {
     if (mm_status s = launch(b, "fft_x_forward", [&] {
+          if (g.Wx == 0)
+            return mmk_launch_fft_xr(1, g.px / 4, g.n_xf, b->d_desc, g.xf, method, stage, g_twiddle, b->stream);
           return mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, method, stage, g_twiddle, b->stream);
         }))
       return s;
@@ -581,6 +587,7 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1) {
         return s;
     }
     if (mm_status s = launch(b, "fft_x_inverse", [&] {
+          if (g.Wx == 0) return mmk_launch_fft_xr(-1, g.px / 4, g.n_xf, b->d_desc, g.xf, 0, 0, g_twiddle, b->stream);
           return mmk_launch_fft_xi(g.Wx, g.n_xf, g.lds_xi, b->d_desc, g.xf, g_twiddle, b->stream);
         }))
       return s;
@@ -1408,6 +1415,24 @@ mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path) {
   return MM_OK;
 }
 
+mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path) {
+  if (!b) return fail(MM_ERR_ARG, "batch is NULL");
+  if (path != MM_X_LDS && path != MM_X_REGISTER) return fail(MM_ERR_ARG, "unknown x path");
+  for (auto& g : b->groups)
+    if (path == MM_X_REGISTER && !xreg_fits(g.px))
+      return fail(MM_ERR_ARG, "register x path needs a padded x of 16..128 cells");
+  MM_HIP(hipStreamSynchronize(b->stream));
+  for (auto& g : b->groups) {
+    g.Wx = path == MM_X_REGISTER ? 0 : std::max(1, std::min(32, 2048 / g.px));
+    if (mm_status s = build_group(g)) return s;
+  }
+  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+  if (b->exec_rev) { hipGraphExecDestroy(b->exec_rev); b->exec_rev = nullptr; }
+  if (b->graph_rev) { hipGraphDestroy(b->graph_rev); b->graph_rev = nullptr; }
+  return MM_OK;
+}
+
 mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, char* names, int64_t* launches,
                            double* total_ms, double* bytes_per_launch, int32_t* n) {
   if (!b || !n || steps < 0 || cap < 0) return fail(MM_ERR_ARG, "bad arguments");
@@ -1482,18 +1507,24 @@ mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
     int bestW = g.Wx;
     double bestT = 1e30;
     std::string xrep;
-    for (int W = 2; W <= 32; W *= 2) {
-      if (sizeof(float2) * ((size_t)g.px * (W + 1) + (size_t)g.kx * 2 * W + g.px) > lds_cap) continue;
+    for (int W = xreg_fits(g.px) ? 0 : 2; W <= 32; W = W ? 2 * W : 2) {
+      if (W && sizeof(float2) * ((size_t)g.px * (W + 1) + (size_t)g.kx * 2 * W + g.px) > lds_cap) continue;
       g.Wx = W;
       if (mm_status s = build_group(g)) return s;
       double us;
       if (mm_status s = timed([&] {
+            if (g.Wx == 0) {
+              hipError_t e = mmk_launch_fft_xr(1, g.px / 4, g.n_xf, b->d_desc, g.xf, b->method, 1, g_twiddle, b->stream);
+              if (e != hipSuccess) return e;
+              return mmk_launch_fft_xr(-1, g.px / 4, g.n_xf, b->d_desc, g.xf, 0, 0, g_twiddle, b->stream);
+            }
             hipError_t e = mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, b->method, 1, g_twiddle, b->stream);
             if (e != hipSuccess) return e;
             return mmk_launch_fft_xi(g.Wx, g.n_xf, g.lds_xi, b->d_desc, g.xf, g_twiddle, b->stream);
           }, &us))
         return s;
-      xrep += (xrep.empty() ? "" : ", ") + std::string("\"") + std::to_string(W) + "\": " + std::to_string(us);
+      xrep += (xrep.empty() ? "" : ", ") + std::string("\"") + (W ? std::to_string(W) : std::string("reg")) + "\": " +
+              std::to_string(us);
       if (us < bestT) { bestT = us; bestW = W; }
     }
     g.Wx = bestW;

@@ -635,12 +635,11 @@ __global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restr
   load_twiddles(twz, PZ, tw, MM_YZR_T);
   load_twiddles(tw32, 32, tw, MM_YZR_T);
   __syncthreads();
-  // forward y, one residue of one row (c, z < nz) per lane
+  // forward y, one residue of one row per lane (rows z >= nz hold zeros and stay zero)
 #pragma unroll 1
-  for (int t = threadIdx.x; t < 4 * nrow; t += MM_YZR_T) {
-    const int l = t >> 2, r = t & 3;
-    const int c = l / nz, z = l - c * nz;
-    float2* line = B + (c * ZR + z) * RS;
+  for (int t = threadIdx.x; t < 4 * 3 * ZR; t += MM_YZR_T) {
+    const int r = t & 3;
+    float2* line = B + (t >> 2) * RS;
     float2 f[MY];
 #pragma unroll
     for (int j = 0; j < MY; ++j) f[j] = fold(line[j], line[j + MY], r, twy[r * j]);
@@ -692,12 +691,11 @@ __global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restr
     }
   }
   __syncthreads();
-  // inverse y, one residue of one row (c, z < nz) per lane
+  // inverse y, one residue of one row per lane
 #pragma unroll 1
-  for (int t = threadIdx.x; t < 4 * nrow; t += MM_YZR_T) {
-    const int l = t >> 2, r = t & 3;
-    const int c = l / nz, z = l - c * nz;
-    float2* line = B + (c * ZR + z) * RS;
+  for (int t = threadIdx.x; t < 4 * 3 * ZR; t += MM_YZR_T) {
+    const int r = t & 3;
+    float2* line = B + (t >> 2) * RS;
     float2 g[MY];
 #pragma unroll
     for (int k = 0; k < MY; ++k) g[k] = line[4 * k + r];
@@ -712,10 +710,148 @@ __global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restr
     for (int i = 0; i < MY / 2; ++i) line[y0 + i] = o[i];
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < nrow * ny; e += MM_YZR_T) {
-    const int l = e / ny, y = e - l * ny;
-    const int c = l / nz, z = l - c * nz;
-    gst2(X + e, B[(c * ZR + z) * RS + y]);
+#pragma unroll 4
+  for (int e = threadIdx.x; e < 3 * ZR * YR; e += MM_YZR_T) {
+    const int row = e >> (lgMY + 1), y = e & (YR - 1);
+    const int c = row / ZR, z = row & (ZR - 1);
+    if (z < nz && y < ny) gst2(X + (c * nz + z) * ny + y, B[row * RS + y]);
+  }
+}
+
+// --------------------------------------------------- x passes, lines in registers
+// Work item = 128 consecutive real rows (64 complex lines) of one instance.
+// A line packs two real rows (real and imaginary part) and is split over four
+// adjacent lanes by frequency residue, as in the fused y-z kernel above.
+#define MM_XR_T 256
+#define MM_XR_ROWS 128
+
+// forward: rows of the stage input -> X[kx][row] for kx <= Px/2
+template <int MX>
+__global__ __launch_bounds__(MM_XR_T) void k_fft_xfr(const InstDesc* __restrict__ descs,
+                                                     const WorkItem* __restrict__ work, int method,
+                                                     int stage, const float2* __restrict__ tw) {
+  constexpr int PX = 4 * MX, NXP = 2 * MX, RSX = NXP + 1, lgM = ilog2c(MX), lgN = lgM + 1;
+  __shared__ float rowbuf[MM_XR_ROWS * RSX];
+  __shared__ float2 twx[PX + 32];
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  const MMG InstCtl* __restrict__ C = gbl(D.ctl);
+  if (C->done) return;
+  const int nx = D.nx, rows = 3 * D.ny * D.nz;
+  const int r0 = wi.item * MM_XR_ROWS;
+  const Src src = stage_src(D, C, method, stage);
+  float2* tw32 = twx + PX;
+  load_twiddles(twx, PX, tw, MM_XR_T);
+  load_twiddles(tw32, 32, tw, MM_XR_T);
+  {
+    // rows are contiguous x-lines: element (row, x) of the stage input is at row * nx + x
+    constexpr int NE = MM_XR_ROWS * NXP, NB = NE / MM_XR_T;
+    float v[NB];
+    int idx[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = u * MM_XR_T + threadIdx.x;
+      const int rr = e >> lgN, x = e & (NXP - 1);
+      idx[u] = min(r0 + rr, rows - 1) * nx + min(x, nx - 1);
+      v[u] = src.p0[idx[u]];
+    }
+    if (src.p1) {
+#pragma unroll
+      for (int u = 0; u < NB; ++u) v[u] = fmaf(src.c1, src.p1[idx[u]], v[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = u * MM_XR_T + threadIdx.x;
+      const int rr = e >> lgN, x = e & (NXP - 1);
+      rowbuf[rr * RSX + x] = (x < nx && r0 + rr < rows) ? v[u] : 0.f;
+    }
+  }
+  __syncthreads();
+  const int l = threadIdx.x >> 2, r = threadIdx.x & 3;
+  const float* ra = rowbuf + (2 * l) * RSX;
+  const float* rb = ra + RSX;
+  float2 f[MX];
+#pragma unroll
+  for (int j = 0; j < MX; ++j)
+    f[j] = fold(make_float2(ra[j], rb[j]), make_float2(ra[j + MX], rb[j + MX]), r, twx[r * j]);
+  reg_dft<MX, false>(f, tw32);
+  // f[brev(k)] = Z[4k + r].  R2C split with the partner Z[Px - kx]: the same
+  // lane for r = 0, 2, the lane r ^ 2 for r = 1, 3 (register of k' = MX-1-k).
+  MMG float2* X = gbl(D.fx);
+  const size_t kstride = (size_t)rows;
+  const int ra_row = r0 + 2 * l;
+#pragma unroll
+  for (int k = 0; k <= MX / 2; ++k) {
+    const float2 z = f[brevc(k % MX, lgM)];
+    const float2 recv = quad_x2(f[brevc(MX - 1 - k < 0 ? 0 : MX - 1 - k, lgM)]);
+    const float2 zm = r == 0 ? f[brevc((MX - k) % MX, lgM)] : r == 2 ? f[brevc(MX - 1 - k < 0 ? 0 : MX - 1 - k, lgM)] : recv;
+    const int kx = 4 * k + r;
+    if (kx <= NXP) {
+      const float2 xa = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+      const float2 xb = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
+      MMG float2* o = X + (size_t)kx * kstride + ra_row;
+      if (ra_row < rows) gst2(o, xa);
+      if (ra_row + 1 < rows) gst2(o + 1, xb);
+    }
+  }
+}
+
+// inverse: X[kx][row] -> B_d rows (crop x < nx, scale), C2R of two rows per line
+template <int MX>
+__global__ __launch_bounds__(MM_XR_T) void k_fft_xir(const InstDesc* __restrict__ descs,
+                                                     const WorkItem* __restrict__ work,
+                                                     const float2* __restrict__ tw) {
+  constexpr int PX = 4 * MX, NXP = 2 * MX, RSX = NXP + 1, lgM = ilog2c(MX), lgN = lgM + 1;
+  __shared__ float rowbuf[MM_XR_ROWS * RSX];
+  __shared__ float2 twx[PX + 32];
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (gbl(D.ctl)->done) return;
+  const int nx = D.nx, rows = 3 * D.ny * D.nz;
+  const int r0 = wi.item * MM_XR_ROWS;
+  float2* tw32 = twx + PX;
+  load_twiddles(twx, PX, tw, MM_XR_T);
+  load_twiddles(tw32, 32, tw, MM_XR_T);
+  const int l = threadIdx.x >> 2, r = threadIdx.x & 3;
+  const int ra_row = min(r0 + 2 * l, rows - 1), rb_row = min(r0 + 2 * l + 1, rows - 1);
+  const bool b_in = r0 + 2 * l + 1 < rows;
+  const MMG float2* X = gbl(D.fx);
+  const size_t kstride = (size_t)rows;
+  // Z[kx] = Xa[kx] + i Xb[kx] for kx <= Px/2, conj(Xa[Px-kx]) + i conj(Xb[Px-kx]) above
+  float2 g[MX];
+#pragma unroll
+  for (int k = 0; k < MX; ++k) {
+    const int kx = 4 * k + r;
+    const bool lo = kx <= NXP;
+    const int kk = lo ? kx : PX - kx;
+    float2 a = gld2(X + (size_t)kk * kstride + ra_row);
+    float2 b = gld2(X + (size_t)kk * kstride + rb_row);
+    if (!b_in) b = make_float2(0.f, 0.f);
+    if (kx == 0 || kx == NXP) { a.y = 0.f; b.y = 0.f; }
+    g[k] = lo ? make_float2(a.x - b.y, a.y + b.x) : make_float2(a.x + b.y, b.x - a.y);
+  }
+  __syncthreads();   // twiddles
+  reg_dft<MX, true>(g, tw32);
+  float2 w[MX];
+#pragma unroll
+  for (int y0 = 0; y0 < MX; ++y0) w[y0] = cmul(g[brevc(y0, lgM)], twid<true>(twx, r * y0));
+  float2 o[MX / 2];
+  quad_inverse<MX>(w, r, o);
+  const int x0 = (MX / 2) * (r >> 1) + MX * (r & 1);
+  float* pa = rowbuf + (2 * l) * RSX;
+#pragma unroll
+  for (int i = 0; i < MX / 2; ++i) {
+    pa[x0 + i] = o[i].x;
+    pa[RSX + x0 + i] = o[i].y;
+  }
+  __syncthreads();
+  const float sc = D.bd_scale;
+  MMG float* bd = gbl(D.bd);
+  constexpr int NE = MM_XR_ROWS * NXP;
+#pragma unroll 4
+  for (int e = threadIdx.x; e < NE; e += MM_XR_T) {
+    const int rr = e >> lgN, x = e & (NXP - 1);
+    if (x < nx && r0 + rr < rows) bd[(r0 + rr) * nx + x] = sc * rowbuf[rr * RSX + x];
   }
 }
 
@@ -856,6 +992,22 @@ hipError_t mmk_launch_fft_yzr(int MY, int MZ, int nblocks, size_t lds, const Ins
   MM_YZR_CASE(4, 8) MM_YZR_CASE(8, 8) MM_YZR_CASE(16, 8) MM_YZR_CASE(32, 8)
   MM_YZR_CASE(4, 16) MM_YZR_CASE(8, 16) MM_YZR_CASE(16, 16) MM_YZR_CASE(32, 16)
   return hipErrorInvalidValue;
+}
+
+hipError_t mmk_launch_fft_xr(int dir, int MX, int nblocks, const InstDesc* d, const WorkItem* w, int method,
+                             int stage, const float2* tw, hipStream_t s) {
+  switch (MX * dir) {
+    case 4: hipLaunchKernelGGL(mmk::k_fft_xfr<4>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
+    case 8: hipLaunchKernelGGL(mmk::k_fft_xfr<8>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
+    case 16: hipLaunchKernelGGL(mmk::k_fft_xfr<16>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
+    case 32: hipLaunchKernelGGL(mmk::k_fft_xfr<32>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
+    case -4: hipLaunchKernelGGL(mmk::k_fft_xir<4>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
+    case -8: hipLaunchKernelGGL(mmk::k_fft_xir<8>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
+    case -16: hipLaunchKernelGGL(mmk::k_fft_xir<16>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
+    case -32: hipLaunchKernelGGL(mmk::k_fft_xir<32>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstDesc* d,

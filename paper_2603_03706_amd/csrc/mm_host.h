@@ -13,6 +13,10 @@ void kernel_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, st
 
 hipError_t mmk_launch_stage(int method, int stage, bool final_pass, int nblocks, int count,
                             const InstDesc* descs, const int* wg, hipStream_t stream);
+// x passes with lines in registers: Px = 4 MX, MX in {4, 8, 16, 32}; dir +1 forward (method,
+// stage select the stage input), -1 inverse; work items are tiles of 128 rows
+hipError_t mmk_launch_fft_xr(int dir, int MX, int nblocks, const InstDesc* d, const WorkItem* w, int method,
+                             int stage, const float2* tw, hipStream_t s);
 hipError_t mmk_launch_fft_xf(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              int method, int stage, const float2* tw, hipStream_t s);
 hipError_t mmk_launch_fft_xi(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,

@@ -73,6 +73,7 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_int32)]),
     "mm_batch_tune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
     "mm_batch_set_fft_path": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "mm_batch_set_fft_x": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_run_record": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32]),
     "mm_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "mm_demag_tensor": (ctypes.c_int, [ctypes.c_double] * 6 + [_P]),
@@ -295,6 +296,10 @@ class Batch:
     def set_fft_path(self, path):
         """Force the demag y-z strategy ("fused", "reg" or "split") for every grid shape."""
         _check(self._lib.mm_batch_set_fft_path(self.h, self.YZ_PATHS[path]))
+
+    def set_fft_x(self, path):
+        """Force the x-pass strategy ("lds" or "reg") for every grid shape."""
+        _check(self._lib.mm_batch_set_fft_x(self.h, {"lds": 0, "reg": 1}[path]))
 
     def profile(self, steps, tol=0.0, cap=32):
         names = ctypes.create_string_buffer(48 * cap)

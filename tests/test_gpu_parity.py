@@ -318,9 +318,10 @@ def test_tuned_batch_keeps_parity():
 @pytest.mark.gpu
 @pytest.mark.parametrize("shape", [(12, 12, 12), (10, 6, 5)])
 def test_fft_yz_paths_agree(shape):
-    """The three y-z strategies of the demag convolution (LDS-fused, register
-    lines, split passes) give the same trajectory to FP32 rounding, and the
-    oracle's within the parity bound, on a sphere and on a ragged box."""
+    """The y-z strategies of the demag convolution (LDS-fused, register lines,
+    split passes) and the two x-pass strategies (LDS tiles, register lines)
+    give the same trajectory to FP32 rounding, and the oracle's within the
+    parity bound, on a sphere and on a ragged box."""
     from paper_2603_03706_amd import mmcav
     if shape == (12, 12, 12):
         inst = variant(W.sweep_sphere(5, count=8, n=12), method="rk4", dt0=0.2e-12)
@@ -333,24 +334,26 @@ def test_fft_yz_paths_agree(shape):
     st = oracle_for(inst)
     run_oracle(st, 20e-12)
     out = {}
-    for path in ("fused", "reg", "split"):
+    for path, xpath in (("fused", "lds"), ("reg", "reg"), ("split", "lds"), ("fused", "reg")):
         c = gpu_for(inst)
         b = mmcav.Batch([c])
         b.set_fft_path(path)
+        b.set_fft_x(xpath)
         b.run(20e-12)
-        out[path] = c.get_m()
-        assert m_err(out[path], st) <= 2e-5, path
+        out[path, xpath] = c.get_m()
+        assert m_err(out[path, xpath], st) <= 2e-5, (path, xpath)
         b.close()
         c.close()
-    assert np.abs(out["reg"] - out["fused"]).max() <= 2e-6
-    assert np.abs(out["split"] - out["fused"]).max() <= 2e-6
+    ref = out["fused", "lds"]
+    for key, m in out.items():
+        assert np.abs(m - ref).max() <= 2e-6, key
 
 
 @pytest.mark.gpu
 def test_fft_path_rejects_unfit_shape():
-    """A shape outside the register strategy's sizes is refused without change."""
+    """A shape outside the register strategies' sizes is refused without change."""
     from paper_2603_03706_amd import mmcav
-    grid = (8, 3, 2)
+    grid = (100, 3, 2)       # padded (256, 8, 4): outside both register strategies
     inst = W.Instance(grid=grid, cell=(5e-9,) * 3, Ms=140e3, Aex=3.65e-12, alpha=0.01,
                       B0=(0.0, 0.0, 0.2), demag=W.DEMAG_FFT,
                       omega=np.array([TWO_PI * 5e9]), kappa=np.array([TWO_PI * 1e6]), g=np.array([TWO_PI * 50e6]),
@@ -359,6 +362,9 @@ def test_fft_path_rejects_unfit_shape():
     b = mmcav.Batch([c])
     with pytest.raises(mmcav.MMError):
         b.set_fft_path("reg")
+    with pytest.raises(mmcav.MMError):
+        b.set_fft_x("reg")
     b.set_fft_path("split")
+    b.set_fft_x("lds")
     b.close()
     c.close()
