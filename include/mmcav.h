@@ -201,8 +201,8 @@ mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path);
 
 /* Strategy of the x passes (R2C forward, C2R inverse) for every FFT grid
  * shape: MM_X_REGISTER holds each pair of real rows as one complex line split
- * over four lanes in registers (padded x of 16..128 cells only; the default
- * where it applies), MM_X_LDS transforms tiles of rows in LDS.  Same results
+ * over four lanes in registers (padded x of 16..128 cells only), MM_X_LDS
+ * (the default) transforms tiles of rows in LDS.  Same results
  * to FP32 rounding.  MM_ERR_ARG, changing nothing, if a shape cannot use it. */
 enum { MM_X_LDS = 0, MM_X_REGISTER = 1 };
 mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path);

@@ -37,6 +37,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // ------------------------------------------------------------ device state
 float2* g_twiddle = nullptr;  // e^{-2 pi i m / 1024}, m < 1024
+int g_cus = 256;               // compute units of the device (set with the twiddles)
 std::mutex g_mu;
 
 struct Spectrum {
@@ -59,6 +60,9 @@ mm_status ensure_twiddles() {
   MM_HIP(hipMalloc(&g_twiddle, sizeof(float2) * MMI_TW_LEN));
   MM_HIP(hipMemcpy(g_twiddle, h.data(), sizeof(float2) * MMI_TW_LEN, hipMemcpyHostToDevice));
   MM_HIP(mmk_set_lds_limits());
+  int dev = 0;
+  MM_HIP(hipGetDevice(&dev));
+  MM_HIP(hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev));
   return MM_OK;
 }
 
@@ -502,7 +506,7 @@ mm_status batch_build(mm_batch* b) {
     g->members.push_back(i);
   }
   for (auto& g : b->groups) {
-    g.Wx = xreg_fits(g.px) ? 0 : std::max(1, std::min(32, 2048 / g.px));
+    g.Wx = std::max(1, std::min(16, 1024 / g.px));
     g.Wy = std::max(1, std::min(64, 2048 / g.py));
     int tw = 1;
     while (tw * 2 <= 16 && 3 * (tw * 2) * g.pz <= 2048) tw *= 2;
@@ -1423,7 +1427,7 @@ mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path) {
       return fail(MM_ERR_ARG, "register x path needs a padded x of 16..128 cells");
   MM_HIP(hipStreamSynchronize(b->stream));
   for (auto& g : b->groups) {
-    g.Wx = path == MM_X_REGISTER ? 0 : std::max(1, std::min(32, 2048 / g.px));
+    g.Wx = path == MM_X_REGISTER ? 0 : std::max(1, std::min(16, 1024 / g.px));
     if (mm_status s = build_group(g)) return s;
   }
   if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }

@@ -293,8 +293,8 @@ __global__ __launch_bounds__(256) void k_fft_xf(const InstDesc* __restrict__ des
     float2 X;
     if ((rr & 1) == 0) X = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
     else X = make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
-    const int c = r / nyz, yz = r - c * nyz;
-    gst2(gbl(D.fx) + ((size_t)kx * 3 + c) * nyz + yz, X);
+    // X[kx][c][z][y] with row r = (c, z, y): offset kx * rows + r
+    gst2(gbl(D.fx) + (size_t)kx * rows + r, X);
   }
 }
 
@@ -326,9 +326,7 @@ __global__ __launch_bounds__(256) void k_fft_xi(const InstDesc* __restrict__ des
       const int kx = min(e / (2 * W), Kx - 1), rr = e - (e / (2 * W)) * 2 * W;
       const int r = r0 + rr;
       const bool in = e < Kx * 2 * W && r < rows;
-      const int rc = min(r, rows - 1);
-      const int c = rc / nyz, yz = rc - c * nyz;
-      const float2 t = gld2(fx + ((size_t)kx * 3 + c) * nyz + yz);
+      const float2 t = gld2(fx + (size_t)kx * rows + min(r, rows - 1));
       v[u] = make_float2(in ? t.x : 0.f, in ? t.y : 0.f);
     }
 #pragma unroll
@@ -362,8 +360,7 @@ __global__ __launch_bounds__(256) void k_fft_xi(const InstDesc* __restrict__ des
     const int r = r0 + rr;
     if (r >= rows) continue;
     const float2 Z = buf[x * WP + (rr >> 1)];
-    const int c = r / nyz, yz = r - c * nyz;
-    gbl(D.bd)[c * nc + yz * nx + x] = sc * ((rr & 1) ? Z.y : Z.x);
+    gbl(D.bd)[r * nx + x] = sc * ((rr & 1) ? Z.y : Z.x);
   }
 }
 
@@ -582,38 +579,38 @@ __global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restr
   constexpr int PY = 4 * MY, PZ = 4 * MZ, RS = PY + 1, ZR = 2 * MZ, YR = 2 * MY;
   constexpr int lgMY = ilog2c(MY), lgMZ = ilog2c(MZ), lgPY = lgMY + 2;
   extern __shared__ float2 lds[];
-  const WorkItem wi = work[blockIdx.x];
-  const InstDesc& D = descs[wi.inst];
-  if (gbl(D.ctl)->done) return;
-  const int kx = wi.item;
-  const int ny = D.ny, nz = D.nz;
-  const int nrow = 3 * nz;
   float2* B = lds;
   float2* twy = B + 3 * ZR * RS;
   float2* twz = twy + PY;
   float2* tw32 = twz + PZ;
   float* Ks = reinterpret_cast<float*>(tw32 + 32);   // kernel slice of this kx: [6][PZ/2+1][PY/2+1]
   constexpr int HY1 = PY / 2 + 1, KPL = (PZ / 2 + 1) * HY1;
+  constexpr int NK = (6 * KPL + MM_YZR_T - 1) / MM_YZR_T, NXE = 3 * ZR * PY;
+  constexpr int NX = (NXE + MM_YZR_T - 1) / MM_YZR_T;
+  load_twiddles(twy, PY, tw, MM_YZR_T);
+  load_twiddles(twz, PZ, tw, MM_YZR_T);
+  load_twiddles(tw32, 32, tw, MM_YZR_T);
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (gbl(D.ctl)->done) return;
+  const int kx = wi.item;
+  const int ny = D.ny, nz = D.nz;
+  const int nrow = 3 * nz;
   MMG float2* X = gbl(D.fx) + (size_t)kx * nrow * ny;
   {
     // all global loads of the prologue are issued before the first wait
-    constexpr int NK = (6 * KPL + MM_YZR_T - 1) / MM_YZR_T, NXE = 3 * ZR * PY;
-    constexpr int NX = (NXE + MM_YZR_T - 1) / MM_YZR_T;
     const MMG float* K = gbl(D.kern) + (size_t)kx * 6 * KPL;
     float kv[NK];
     float2 xv[NX];
 #pragma unroll
-    for (int it = 0; it < NK; ++it) {
-      const int e = it * MM_YZR_T + threadIdx.x;
-      kv[it] = e < 6 * KPL ? K[e] : 0.f;
-    }
+    for (int it = 0; it < NK; ++it) kv[it] = K[min(it * MM_YZR_T + (int)threadIdx.x, 6 * KPL - 1)];
 #pragma unroll
     for (int it = 0; it < NX; ++it) {
-      // rows z >= nz are read by the z pass at every ky: they are cleared over the full padded width
+      // rows z >= nz are read by the z pass at every ky: they are cleared over the full padded width;
+      // clamped (in-bounds) address, padding selected afterwards: no branch between the loads
       const int e = it * MM_YZR_T + threadIdx.x;
       const int row = e >> lgPY, y = e & (PY - 1);
       const int c = row / ZR, z = row - c * ZR;
-      // clamped (in-bounds) address, padding selected afterwards: no branch between the loads
       const bool in = e < NXE && z < nz && y < ny;
       const float2 v = gld2(X + (min(c, 2) * nz + min(z, nz - 1)) * ny + min(y, ny - 1));
       xv[it] = make_float2(in ? v.x : 0.f, in ? v.y : 0.f);
@@ -631,21 +628,36 @@ __global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restr
       if (e < NXE && (z >= nz || y < YR)) B[row * RS + y] = xv[it];
     }
   }
-  load_twiddles(twy, PY, tw, MM_YZR_T);
-  load_twiddles(twz, PZ, tw, MM_YZR_T);
-  load_twiddles(tw32, 32, tw, MM_YZR_T);
   __syncthreads();
-  // forward y, one residue of one row per lane (rows z >= nz hold zeros and stay zero)
+  {
+  // forward y.  Up to 64-point rows: two residue lanes per row, 2 MY points
+  // each; the upper half of a padded row is zero, so the fold reduces to the
+  // twiddle W^{rj}.  Longer rows: four residue lanes as in the z pass.
+  if constexpr (MY <= 16) {
+    constexpr int M2 = 2 * MY, lg2 = lgMY + 1;
 #pragma unroll 1
-  for (int t = threadIdx.x; t < 4 * 3 * ZR; t += MM_YZR_T) {
-    const int r = t & 3;
-    float2* line = B + (t >> 2) * RS;
-    float2 f[MY];
+    for (int t = threadIdx.x; t < 2 * 3 * ZR; t += MM_YZR_T) {
+      const int r = t & 1;
+      float2* line = B + (t >> 1) * RS;
+      float2 f[M2];
 #pragma unroll
-    for (int j = 0; j < MY; ++j) f[j] = fold(line[j], line[j + MY], r, twy[r * j]);
-    reg_dft<MY, false>(f, tw32);
+      for (int j = 0; j < M2; ++j) f[j] = cmul(line[j], twy[r * j]);
+      reg_dft<M2, false>(f, tw32);
 #pragma unroll
-    for (int p = 0; p < MY; ++p) line[4 * brevc(p, lgMY) + r] = f[p];
+      for (int p = 0; p < M2; ++p) line[2 * brevc(p, lg2) + r] = f[p];
+    }
+  } else {
+#pragma unroll 1
+    for (int t = threadIdx.x; t < 4 * 3 * ZR; t += MM_YZR_T) {
+      const int r = t & 3;
+      float2* line = B + (t >> 2) * RS;
+      float2 f[MY];
+#pragma unroll
+      for (int j = 0; j < MY; ++j) f[j] = fold(line[j], line[j + MY], r, twy[r * j]);
+      reg_dft<MY, false>(f, tw32);
+#pragma unroll
+      for (int p = 0; p < MY; ++p) line[4 * brevc(p, lgMY) + r] = f[p];
+    }
   }
   __syncthreads();
   // z per ky column: forward, kernel multiply, inverse
@@ -691,23 +703,46 @@ __global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restr
     }
   }
   __syncthreads();
-  // inverse y, one residue of one row per lane
+  }
+  {
+  // inverse y (cropped to y < 2 MY), the same lane split as the forward pass
+  if constexpr (MY <= 16) {
+    constexpr int M2 = 2 * MY, lg2 = lgMY + 1;
 #pragma unroll 1
-  for (int t = threadIdx.x; t < 4 * 3 * ZR; t += MM_YZR_T) {
-    const int r = t & 3;
-    float2* line = B + (t >> 2) * RS;
-    float2 g[MY];
+    for (int t = threadIdx.x; t < 2 * 3 * ZR; t += MM_YZR_T) {
+      const int r = t & 1;
+      float2* line = B + (t >> 1) * RS;
+      float2 g[M2];
 #pragma unroll
-    for (int k = 0; k < MY; ++k) g[k] = line[4 * k + r];
-    reg_dft<MY, true>(g, tw32);
-    float2 v[MY];
+      for (int k = 0; k < M2; ++k) g[k] = line[2 * k + r];
+      reg_dft<M2, true>(g, tw32);
+      // h[y0] = w_0[y0] + w_1[y0]; lane r keeps y0 in [r MY, (r + 1) MY)
 #pragma unroll
-    for (int y0 = 0; y0 < MY; ++y0) v[y0] = cmul(g[brevc(y0, lgMY)], twid<true>(twy, r * y0));
-    float2 o[MY / 2];
-    quad_inverse<MY>(v, r, o);
-    const int y0 = (MY / 2) * (r >> 1) + MY * (r & 1);
+      for (int i = 0; i < MY; ++i) {
+        const float2 w0 = cmul(g[brevc(i, lg2)], twid<true>(twy, r * i));
+        const float2 w1 = cmul(g[brevc(i + MY, lg2)], twid<true>(twy, r * (i + MY)));
+        const float2 got = make_float2(dpp_x1(r ? w0.x : w1.x), dpp_x1(r ? w0.y : w1.y));
+        line[r * MY + i] = cadd(r ? w1 : w0, got);
+      }
+    }
+  } else {
+#pragma unroll 1
+    for (int t = threadIdx.x; t < 4 * 3 * ZR; t += MM_YZR_T) {
+      const int r = t & 3;
+      float2* line = B + (t >> 2) * RS;
+      float2 g[MY];
 #pragma unroll
-    for (int i = 0; i < MY / 2; ++i) line[y0 + i] = o[i];
+      for (int k = 0; k < MY; ++k) g[k] = line[4 * k + r];
+      reg_dft<MY, true>(g, tw32);
+      float2 v[MY];
+#pragma unroll
+      for (int y0 = 0; y0 < MY; ++y0) v[y0] = cmul(g[brevc(y0, lgMY)], twid<true>(twy, r * y0));
+      float2 o[MY / 2];
+      quad_inverse<MY>(v, r, o);
+      const int y0 = (MY / 2) * (r >> 1) + MY * (r & 1);
+#pragma unroll
+      for (int i = 0; i < MY / 2; ++i) line[y0 + i] = o[i];
+    }
   }
   __syncthreads();
 #pragma unroll 4
@@ -715,6 +750,7 @@ __global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restr
     const int row = e >> (lgMY + 1), y = e & (YR - 1);
     const int c = row / ZR, z = row & (ZR - 1);
     if (z < nz && y < ny) gst2(X + (c * nz + z) * ny + y, B[row * RS + y]);
+  }
   }
 }
 
@@ -986,8 +1022,8 @@ hipError_t mmk_launch_fft_yz(int TK, int nblocks, size_t lds, const InstDesc* d,
     hipLaunchKernelGGL((mmk::k_fft_yzr<A, B>), dim3(nblocks), dim3(MM_YZR_T), lds, s, d, w, tw); \
     return hipGetLastError();                                                                    \
   }
-hipError_t mmk_launch_fft_yzr(int MY, int MZ, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
-                              const float2* tw, hipStream_t s) {
+hipError_t mmk_launch_fft_yzr(int MY, int MZ, int nblocks, size_t lds, const InstDesc* d,
+                              const WorkItem* w, const float2* tw, hipStream_t s) {
   MM_YZR_CASE(4, 4) MM_YZR_CASE(8, 4) MM_YZR_CASE(16, 4) MM_YZR_CASE(32, 4)
   MM_YZR_CASE(4, 8) MM_YZR_CASE(8, 8) MM_YZR_CASE(16, 8) MM_YZR_CASE(32, 8)
   MM_YZR_CASE(4, 16) MM_YZR_CASE(8, 16) MM_YZR_CASE(16, 16) MM_YZR_CASE(32, 16)
