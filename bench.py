@@ -174,15 +174,38 @@ def summarize_pmc(fetch_csv, write_csv, probe_json):
     print("```")
 
 
+def tile_fields(kernel, tiles):
+    """The part of the FFT tile choice that shapes `kernel`'s launches."""
+    if tiles is None:
+        return None
+    if kernel.startswith("fft_x_"):
+        keys = ("grid", "Wx")
+    elif kernel.startswith("fft_"):
+        keys = ("grid", "path", "TK", "Wy", "TW")
+    else:
+        return []
+    out = []
+    for t in tiles:
+        d = {k: t.get(k) for k in keys}
+        if kernel.startswith("fft_") and not kernel.startswith("fft_x_"):
+            if d["path"] != "fused":
+                d.pop("TK")
+            if d["path"] != "split":
+                d.pop("Wy"), d.pop("TW")
+        out.append(d)
+    return out
+
+
 def stored_traffic(kernel, tiles):
     """Scaled HBM bytes per launch of `kernel` from the stored counter summary,
-    or None when the kernel sources or the tile choice changed since."""
+    or None when the kernel sources, or the tiles of that kernel, changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
             for line in f:
                 if line.startswith("traffic-json: "):
                     rec = json.loads(line[len("traffic-json: "):])
-                    if rec["sources"] == source_hash() and rec["tiles"] == tiles:
+                    if rec["sources"] == source_hash() and \
+                            tile_fields(kernel, rec["tiles"]) == tile_fields(kernel, tiles):
                         return rec["bytes"].get(kernel)
     except OSError:
         pass
