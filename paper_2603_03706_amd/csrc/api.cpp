@@ -286,10 +286,6 @@ struct mm_batch {
   hipGraphExec_t exec_rev = nullptr;
   hipGraph_t graph_rev = nullptr;
   hipEvent_t ev = nullptr;
-  // side stream for the per-instance finalisation kernels that overlap the
-  // next stage's demag convolution (default priority, like the main stream)
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // profiling
   bool profiling = false;
   struct Prof { std::string name; long long launches = 0; double ms = 0.0; double bytes = 0.0; };
@@ -520,9 +516,6 @@ mm_status batch_build(mm_batch* b) {
   }
   MM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   MM_HIP(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
-  MM_HIP(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
-  MM_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
-  MM_HIP(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
   return MM_OK;
 }
 
@@ -541,8 +534,7 @@ mm_status refresh_descs(mm_batch* b) {
 
 // Launch wrapper that times the launch when profiling.
 template <class F>
-mm_status launch(mm_batch* b, const char* name, F&& f, hipStream_t on = nullptr) {
-  if (!on) on = b->stream;
+mm_status launch(mm_batch* b, const char* name, F&& f) {
   size_t idx = 0;
   if (b->profiling) {
     for (; idx < b->prof.size(); ++idx)
@@ -554,9 +546,9 @@ mm_status launch(mm_batch* b, const char* name, F&& f, hipStream_t on = nullptr)
     hipEvent_t e0, e1;
     MM_HIP(hipEventCreate(&e0));
     MM_HIP(hipEventCreate(&e1));
-    MM_HIP(hipEventRecord(e0, on));
+    MM_HIP(hipEventRecord(e0, b->stream));
     MM_HIP(f());
-    MM_HIP(hipEventRecord(e1, on));
+    MM_HIP(hipEventRecord(e1, b->stream));
     b->pending.push_back({e0, e1});
     b->pending_idx.push_back((int)idx);
     return MM_OK;
@@ -638,41 +630,12 @@ mm_status enqueue_start(mm_batch* b) {
   return enqueue_stage(b, 1);
 }
 
-// One step.  For DP45 stages 3..7 the demag convolution of the stage input
-// depends only on the previous stage kernel, not on the previous
-// finalisation (which updates the cavity stage values read by the next stage
-// kernel), so that finalisation runs on the side stream, overlapped with the
-// convolution, and is joined before the next stage kernel.
 mm_status enqueue_step(mm_batch* b) {
   const int s0 = b->method == MM_RK4 ? 1 : 2;
   const int s1 = b->method == MM_RK4 ? 4 : 7;
-  const int n = (int)b->ctxs.size();
-  const bool overlap = b->method == MM_DP45 && !b->groups.empty();
   for (int st = s0; st <= s1; ++st) {
-    const bool fork = overlap && st < s1;   // this stage's finalisation overlaps the next demag
-    // with overlap, the demag of stages after the first is enqueued in the fork below
-    if (!(overlap && st > s0))
-      if (mm_status s = enqueue_demag(b, st)) return s;
-    if (mm_status s = launch(b, stage_name(b->method, st), [&] {
-          return mmk_launch_stage(b->method, st, false, b->total_wg, n, b->d_desc, b->d_wg, b->stream);
-        }))
-      return s;
-    if (fork) {
-      MM_HIP(hipEventRecord(b->ev_fork, b->stream));
-      MM_HIP(hipStreamWaitEvent(b->side, b->ev_fork, 0));
-      if (mm_status s = launch(b, final_name(b->method, st), [&] {
-            return mmk_launch_stage(b->method, st, true, b->total_wg, n, b->d_desc, b->d_wg, b->side);
-          }, b->side))
-        return s;
-      MM_HIP(hipEventRecord(b->ev_join, b->side));
-      if (mm_status s = enqueue_demag(b, st + 1)) return s;
-      MM_HIP(hipStreamWaitEvent(b->stream, b->ev_join, 0));
-    } else {
-      if (mm_status s = launch(b, final_name(b->method, st), [&] {
-            return mmk_launch_stage(b->method, st, true, b->total_wg, n, b->d_desc, b->d_wg, b->stream);
-          }))
-        return s;
-    }
+    if (mm_status s = enqueue_demag(b, st)) return s;
+    if (mm_status s = enqueue_stage(b, st)) return s;
   }
   return MM_OK;
 }
@@ -1665,9 +1628,6 @@ mm_status mm_batch_destroy(mm_batch* b) {
   if (b->d_flags) hipFree(b->d_flags);
   if (b->h_flags) hipHostFree(b->h_flags);
   if (b->ev) hipEventDestroy(b->ev);
-  if (b->ev_fork) hipEventDestroy(b->ev_fork);
-  if (b->ev_join) hipEventDestroy(b->ev_join);
-  if (b->side) hipStreamDestroy(b->side);
   if (b->stream) hipStreamDestroy(b->stream);
   delete b;
   return MM_OK;
