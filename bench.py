@@ -78,7 +78,7 @@ def source_hash():
 def tile_key(tuning):
     if not tuning:
         return None
-    return [{k: t.get(k) for k in ("grid", "Wx", "path", "Wy", "TW", "TK")} for t in tuning]
+    return [{k: t.get(k) for k in ("grid", "Wx", "x_stage", "path", "Wy", "TW", "TK")} for t in tuning]
 
 
 def profile_name(kernel):
@@ -179,11 +179,11 @@ def tile_fields(kernel, tiles):
     if tiles is None:
         return None
     if kernel.startswith("fft_x_"):
-        keys = ("grid", "Wx")
+        keys = ("grid", "Wx", "x_stage")
     elif kernel.startswith("fft_"):
         keys = ("grid", "path", "TK", "Wy", "TW")
     else:
-        return []
+        keys = ("grid", "x_stage")
     out = []
     for t in tiles:
         d = {k: t.get(k) for k in keys}

@@ -200,11 +200,15 @@ enum { MM_YZ_FUSED = 0, MM_YZ_REGISTER = 1, MM_YZ_SPLIT = 2 };
 mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path);
 
 /* Strategy of the x passes (R2C forward, C2R inverse) for every FFT grid
- * shape: MM_X_REGISTER holds each pair of real rows as one complex line split
- * over four lanes in registers (padded x of 16..128 cells only), MM_X_LDS
- * (the default) transforms tiles of rows in LDS.  Same results
- * to FP32 rounding.  MM_ERR_ARG, changing nothing, if a shape cannot use it. */
-enum { MM_X_LDS = 0, MM_X_REGISTER = 1 };
+ * shape: MM_X_STAGE (the default where it applies: nx a power of two from 2
+ * to 128, one sublattice) does them inside the stage kernels, each workgroup
+ * for its own whole x-rows, so the demag field never goes through device
+ * memory and the next stage input is transformed where it is computed;
+ * MM_X_LDS transforms tiles of rows in separate kernels; MM_X_REGISTER does
+ * so with each pair of real rows as one complex line over four lanes in
+ * registers (padded x of 16..128 cells only).  Same results to FP32
+ * rounding.  MM_ERR_ARG, changing nothing, if a shape cannot use `path`. */
+enum { MM_X_LDS = 0, MM_X_REGISTER = 1, MM_X_STAGE = 2 };
 mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path);
 
 /* Per-kernel timing: run `steps` steps eagerly, timing each launch with HIP

@@ -146,6 +146,14 @@ enum { PATH_FUSED = MM_YZ_FUSED, PATH_REG = MM_YZ_REGISTER, PATH_SPLIT = MM_YZ_S
 // x passes with lines in registers (selected by a tile width Wx of 0): padded x of 16..128
 bool xreg_fits(int px) { return px == 16 || px == 32 || px == 64 || px == 128; }
 constexpr int XR_ROWS = 128;
+
+// x passes inside the stage kernels: a 256-cell workgroup must hold whole
+// x-rows, so nx is a power of two from 2 to 128
+bool xfuse_fits(int nx) { return nx >= 2 && nx <= 128 && (nx & (nx - 1)) == 0; }
+size_t xfuse_lds(int nx) {
+  const int R = 256 / nx, J = R / 2, Px = 2 * nx, Kx = nx + 1;
+  return sizeof(float2) * ((size_t)3 * Px * (J + 1) + (size_t)Kx * 4 * R + Px);
+}
 const char* path_name(int p) { return p == PATH_REG ? "reg" : p == PATH_SPLIT ? "split" : "fused"; }
 
 Layout make_layout(const mm_params& p, int n_modes) {
@@ -274,6 +282,7 @@ struct mm_batch {
   struct Group {
     int nx, ny, nz, px, py, pz, kx;
     int path;
+    bool xfused = false;   // x passes inside the stage kernels
     int Wx, Wy, TW, TK = 1;
     WorkItem *xf = nullptr, *yz = nullptr, *y = nullptr, *zc = nullptr;
     int n_xf = 0, n_yz = 0, n_y = 0, n_zc = 0;
@@ -286,6 +295,8 @@ struct mm_batch {
   hipGraphExec_t exec_rev = nullptr;
   hipGraph_t graph_rev = nullptr;
   hipEvent_t ev = nullptr;
+  std::vector<int> xfused;     // per instance: x passes inside the stage kernels
+  size_t stage_lds = 0;        // dynamic LDS of the stage kernels (x passes), 0 if none
   // profiling
   bool profiling = false;
   struct Prof { std::string name; long long launches = 0; double ms = 0.0; double bytes = 0.0; };
@@ -471,24 +482,47 @@ mm_status build_group(mm_batch::Group& g) {
   return MM_OK;
 }
 
-mm_status batch_build(mm_batch* b) {
+// Per-instance x-pass placement and the stage kernels' LDS, from the groups.
+void batch_xfused(mm_batch* b) {
+  b->xfused.assign(b->ctxs.size(), 0);
+  b->stage_lds = 0;
+  for (auto& g : b->groups)
+    if (g.xfused) {
+      for (int m : g.members) b->xfused[m] = 1;
+      b->stage_lds = std::max(b->stage_lds, xfuse_lds(g.nx));
+    }
+}
+
+InstDesc batch_desc(const mm_batch* b, int i) {
+  InstDesc d = b->ctxs[i]->desc;
+  int wg0 = 0;
+  for (int j = 0; j < i; ++j) wg0 += b->ctxs[j]->desc.nwg;
+  d.wg0 = wg0;
+  d.xfused = b->xfused.empty() ? 0 : b->xfused[i];
+  return d;
+}
+
+mm_status upload_batch_descs(mm_batch* b) {
   const int n = (int)b->ctxs.size();
   std::vector<InstDesc> descs(n);
+  for (int i = 0; i < n; ++i) descs[i] = batch_desc(b, i);
+  MM_HIP(hipMemcpy(b->d_desc, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
+  for (int i = 0; i < n; ++i) b->versions[i] = b->ctxs[i]->version;
+  return MM_OK;
+}
+
+mm_status batch_build(mm_batch* b) {
+  const int n = (int)b->ctxs.size();
   std::vector<int> wg;
-  for (int i = 0; i < n; ++i) {
-    descs[i] = b->ctxs[i]->desc;
-    descs[i].wg0 = (int)wg.size();
-    for (int w = 0; w < descs[i].nwg; ++w) wg.push_back(i);
-  }
+  for (int i = 0; i < n; ++i)
+    for (int w = 0; w < b->ctxs[i]->desc.nwg; ++w) wg.push_back(i);
   b->total_wg = (int)wg.size();
   MM_HIP(hipMalloc(&b->d_desc, sizeof(InstDesc) * n));
-  MM_HIP(hipMemcpy(b->d_desc, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
   MM_HIP(hipMalloc(&b->d_wg, sizeof(int) * wg.size()));
   MM_HIP(hipMemcpy(b->d_wg, wg.data(), sizeof(int) * wg.size(), hipMemcpyHostToDevice));
   MM_HIP(hipMalloc(&b->d_flags, sizeof(int) * 2 * n));
   MM_HIP(hipHostMalloc((void**)&b->h_flags, sizeof(int) * 2 * n, hipHostMallocDefault));
   b->versions.resize(n);
-  for (int i = 0; i < n; ++i) b->versions[i] = b->ctxs[i]->version;
   // FFT groups by grid shape
   for (int i = 0; i < n; ++i) {
     const mm_ctx* c = b->ctxs[i];
@@ -512,8 +546,13 @@ mm_status batch_build(mm_batch* b) {
     while (tw * 2 <= 16 && 3 * (tw * 2) * g.pz <= 2048) tw *= 2;
     g.TW = tw;
     g.TK = std::max(1, fused_tile(g.ny, g.nz, g.py, g.pz));
+    g.xfused = xfuse_fits(g.nx);
+    for (int m : g.members)
+      if (b->ctxs[m]->p.sublattices != 1) g.xfused = false;
     if (mm_status s = build_group(g)) return s;
   }
+  batch_xfused(b);
+  if (mm_status s = upload_batch_descs(b)) return s;
   MM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   MM_HIP(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
   return MM_OK;
@@ -522,10 +561,7 @@ mm_status batch_build(mm_batch* b) {
 mm_status refresh_descs(mm_batch* b) {
   for (size_t i = 0; i < b->ctxs.size(); ++i) {
     if (b->versions[i] == b->ctxs[i]->version) continue;
-    InstDesc d = b->ctxs[i]->desc;
-    int wg0 = 0;
-    for (size_t j = 0; j < i; ++j) wg0 += b->ctxs[j]->desc.nwg;
-    d.wg0 = wg0;
+    const InstDesc d = batch_desc(b, (int)i);
     MM_HIP(hipMemcpy(b->d_desc + i, &d, sizeof(InstDesc), hipMemcpyHostToDevice));
     b->versions[i] = b->ctxs[i]->version;
   }
@@ -557,9 +593,14 @@ mm_status launch(mm_batch* b, const char* name, F&& f) {
   return MM_OK;
 }
 
-mm_status enqueue_demag(mm_batch* b, int stage, int method = -1) {
+// Demag convolution of the given stage's input.  For groups whose x passes
+// run inside the stage kernels, the x-forward pass is enqueued only when
+// `fwd` (the input was not produced by a stage kernel) and the x-inverse
+// pass only when `inv` (the consuming kernel does not transform itself).
+mm_status enqueue_demag(mm_batch* b, int stage, int method = -1, bool fwd = true, bool inv = true) {
   if (method < 0) method = b->method;
   for (auto& g : b->groups) {
+    if (!g.xfused || fwd)
     if (mm_status s = launch(b, "fft_x_forward", [&] {
           if (g.Wx == 0)
             return mmk_launch_fft_xr(1, g.px / 4, g.n_xf, b->d_desc, g.xf, method, stage, g_twiddle, b->stream);
@@ -590,6 +631,7 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1) {
           }))
         return s;
     }
+    if (!g.xfused || inv)
     if (mm_status s = launch(b, "fft_x_inverse", [&] {
           if (g.Wx == 0) return mmk_launch_fft_xr(-1, g.px / 4, g.n_xf, b->d_desc, g.xf, 0, 0, g_twiddle, b->stream);
           return mmk_launch_fft_xi(g.Wx, g.n_xf, g.lds_xi, b->d_desc, g.xf, g_twiddle, b->stream);
@@ -616,25 +658,50 @@ const char* final_name(int method, int st) {
 mm_status enqueue_stage(mm_batch* b, int st) {
   const int n = (int)b->ctxs.size();
   if (mm_status s = launch(b, stage_name(b->method, st), [&] {
-        return mmk_launch_stage(b->method, st, false, b->total_wg, n, b->d_desc, b->d_wg, b->stream);
+        return mmk_launch_stage(b->method, st, false, b->total_wg, n, b->d_desc, b->d_wg, g_twiddle,
+                                b->stage_lds, b->stream);
       }))
     return s;
   return launch(b, final_name(b->method, st), [&] {
-    return mmk_launch_stage(b->method, st, true, b->total_wg, n, b->d_desc, b->d_wg, b->stream);
+    return mmk_launch_stage(b->method, st, true, b->total_wg, n, b->d_desc, b->d_wg, g_twiddle, 0, b->stream);
   });
 }
 
+// x-forward pass of the state for groups whose x passes run in the stage kernels
+mm_status enqueue_x_forward(mm_batch* b, int stage) {
+  for (auto& g : b->groups) {
+    if (!g.xfused) continue;
+    if (mm_status s = launch(b, "fft_x_forward", [&] {
+          if (g.Wx == 0)
+            return mmk_launch_fft_xr(1, g.px / 4, g.n_xf, b->d_desc, g.xf, b->method, stage, g_twiddle, b->stream);
+          return mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, b->method, stage, g_twiddle, b->stream);
+        }))
+      return s;
+  }
+  return MM_OK;
+}
+
+// Run start.  RK4: reductions of the state (and, for groups with x passes in
+// the stage kernels, the X rows of the state for the first stage).  DP45:
+// the full first derivative, whose kernel reads the demag field from memory.
 mm_status enqueue_start(mm_batch* b) {
-  if (b->method == MM_RK4) return enqueue_stage(b, 0);
+  if (b->method == MM_RK4) {
+    if (mm_status s = enqueue_x_forward(b, 1)) return s;
+    return enqueue_stage(b, 0);
+  }
   if (mm_status s = enqueue_demag(b, 1)) return s;
   return enqueue_stage(b, 1);
 }
 
+// One step.  Where the stage kernels do the x passes, each stage's input is
+// already in X (written by the previous stage kernel) except the DP45 stage
+// 2 input, which depends on the step size chosen after stage 7.
 mm_status enqueue_step(mm_batch* b) {
   const int s0 = b->method == MM_RK4 ? 1 : 2;
   const int s1 = b->method == MM_RK4 ? 4 : 7;
   for (int st = s0; st <= s1; ++st) {
-    if (mm_status s = enqueue_demag(b, st)) return s;
+    const bool fwd = b->method == MM_DP45 && st == 2;
+    if (mm_status s = enqueue_demag(b, st, -1, fwd, false)) return s;
     if (mm_status s = enqueue_stage(b, st)) return s;
   }
   return MM_OK;
@@ -808,7 +875,8 @@ double algorithmic_bytes(const mm_batch* b, const std::string& name) {
   if (is_stage) st = name.back() - '0';
   for (size_t gi = 0; gi < b->groups.size() || is_stage; ++gi) {
     if (is_stage) {
-      for (const mm_ctx* c : b->ctxs) {
+      for (size_t ci = 0; ci < b->ctxs.size(); ++ci) {
+        const mm_ctx* c = b->ctxs[ci];
         const double cells = (double)c->L.ncell * c->p.sublattices;
         double rd = 0, wr = 0;
         if (b->method == MM_RK4) {
@@ -822,8 +890,19 @@ double algorithmic_bytes(const mm_batch* b, const std::string& name) {
           rd = R[st];
           wr = Wt[st];
         }
-        double extra = (double)c->L.ncell * ((c->p.geometry ? 1.0 : 0.0) + (c->profiled ? 4.0 * c->N : 0.0) +
-                                             (c->p.demag == MM_DEMAG_FFT && name != "stage_rk4_start" ? 12.0 : 0.0));
+        const bool fft = c->p.demag == MM_DEMAG_FFT && name != "stage_rk4_start";
+        const bool xin = !b->xfused.empty() && b->xfused[ci];
+        // demag field: B_d read, or with the x passes inside, the X rows read
+        // (C2R) and the next input's X rows written (R2C)
+        double demag = 0.0;
+        if (fft && !xin) demag = 12.0;
+        if (fft && xin) {
+          const bool c2r = b->method == MM_RK4 ? st >= 1 : st >= 2;
+          const bool r2c = b->method == MM_RK4 ? st >= 1 : (st >= 2 && st <= 6);
+          const double xrow = 24.0 * c->L.kx / c->p.nx;   // X bytes per cell
+          demag = (c2r ? xrow : 0.0) + (r2c ? xrow : 0.0);
+        }
+        double extra = (double)c->L.ncell * ((c->p.geometry ? 1.0 : 0.0) + (c->profiled ? 4.0 * c->N : 0.0) + demag);
         total += cells * (rd + wr) + extra;
       }
       break;
@@ -1421,15 +1500,24 @@ mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path) {
 
 mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path) {
   if (!b) return fail(MM_ERR_ARG, "batch is NULL");
-  if (path != MM_X_LDS && path != MM_X_REGISTER) return fail(MM_ERR_ARG, "unknown x path");
-  for (auto& g : b->groups)
+  if (path != MM_X_LDS && path != MM_X_REGISTER && path != MM_X_STAGE) return fail(MM_ERR_ARG, "unknown x path");
+  for (auto& g : b->groups) {
     if (path == MM_X_REGISTER && !xreg_fits(g.px))
       return fail(MM_ERR_ARG, "register x path needs a padded x of 16..128 cells");
+    if (path == MM_X_STAGE && !g.xfused && !xfuse_fits(g.nx))
+      return fail(MM_ERR_ARG, "x passes in the stage kernels need nx a power of two from 2 to 128");
+    if (path == MM_X_STAGE)
+      for (int m : g.members)
+        if (b->ctxs[m]->p.sublattices != 1) return fail(MM_ERR_ARG, "x passes in the stage kernels need one sublattice");
+  }
   MM_HIP(hipStreamSynchronize(b->stream));
   for (auto& g : b->groups) {
+    g.xfused = path == MM_X_STAGE;
     g.Wx = path == MM_X_REGISTER ? 0 : std::max(1, std::min(16, 1024 / g.px));
     if (mm_status s = build_group(g)) return s;
   }
+  batch_xfused(b);
+  if (mm_status s = upload_batch_descs(b)) return s;
   if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
   if (b->exec_rev) { hipGraphExecDestroy(b->exec_rev); b->exec_rev = nullptr; }
@@ -1590,7 +1678,7 @@ mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
     if (mm_status s = build_group(g)) return s;
     rep += (gi ? ", " : "") + std::string("{\"grid\": [") + std::to_string(g.nx) + ", " + std::to_string(g.ny) + ", " +
            std::to_string(g.nz) + "], \"instances\": " + std::to_string(g.members.size()) + ", \"Wx\": " +
-           std::to_string(g.Wx) + ", \"path\": \"" + path_name(g.path) + "\", \"Wy\": " +
+           std::to_string(g.Wx) + ", \"x_stage\": " + std::string(g.xfused ? "true" : "false") + ", \"path\": \"" + path_name(g.path) + "\", \"Wy\": " +
            std::to_string(g.Wy) + ", \"TW\": " + std::to_string(g.TW) + ", \"TK\": " + std::to_string(g.TK) + ", \"x_us\": {" + xrep +
            "}, \"yz_us\": {" + yrep + "}}";
   }

@@ -78,7 +78,7 @@ __device__ __forceinline__ Src stage_src(const InstDesc& D, CtlPtr C, int method
 // x + intersublattice -B_E m_{s'}.  m holds the cell's own stage input.
 __device__ __forceinline__ void field_at(const InstDesc& D, const Src& src, int i, int x, int y,
                                          int z, const float (&m)[2][3], int s, float fb,
-                                         bool has_bd, float (&B)[3]) {
+                                         bool has_bd, float (&B)[3], const float* bdv = nullptr) {
   const int nc = D.ncell;
   const int nx = D.nx, ny = D.ny, nz = D.nz;
   const int base = s * 3 * nc;
@@ -129,6 +129,10 @@ __device__ __forceinline__ void field_at(const InstDesc& D, const Src& src, int 
     bx = fmaf(D.nlx, tx, bx);
     by = fmaf(D.nly, ty, by);
     bz = fmaf(D.nlz, tz, bz);
+  } else if (bdv) {
+    bx += bdv[0];
+    by += bdv[1];
+    bz += bdv[2];
   } else if (has_bd) {
     const MMG float* bd = gbl(D.bd);
     bx += bd[i];

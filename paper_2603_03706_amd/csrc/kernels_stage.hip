@@ -3,6 +3,7 @@
 // step-size controller done by the last workgroup of each instance.
 #include "mm_internal.h"
 #include "kernels_common.h"
+#include "fft_lds.h"
 
 namespace mmk {
 
@@ -18,9 +19,9 @@ __device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double ar, dou
 // LL torque on sublattice s at cell i from its effective field.
 __device__ __forceinline__ void torque_at(const InstDesc& D, const Src& src, int i, int x, int y,
                                           int z, const float (&m)[2][3], int s, float fb,
-                                          bool has_bd, float (&k)[3]) {
+                                          bool has_bd, float (&k)[3], const float* bdv = nullptr) {
   float B[3];
-  field_at(D, src, i, x, y, z, m, s, fb, has_bd, B);
+  field_at(D, src, i, x, y, z, m, s, fb, has_bd, B, bdv);
   const float m0 = m[s][0], m1 = m[s][1], m2 = m[s][2];
   // -gl [m x B + alpha m x (m x B)]
   const float cx = m1 * B[2] - m2 * B[1];
@@ -344,13 +345,116 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   }
 }
 
+// ------------------------------------------- x passes inside the stage kernel
+// With D.xfused (FFT demag, one sublattice, nx a power of two from 2 to 128),
+// a 256-cell workgroup holds R = 256/nx whole x-rows of each component.  It
+// transforms them itself: the C2R of the convolved X rows gives the demag
+// field of its cells in LDS (no B_d round trip), and the R2C of the next
+// stage input it computes writes the X rows of the next convolution (no
+// separate x-forward pass).  Rows (c, 2j) and (c, 2j+1) share one complex
+// line; lines are transformed by the LDS line FFTs in place.
+struct XRows {
+  int nx, lgnx, R, lgR, J, lgJ, Px, lgx, Kx, es, cs, nyz, rows, yz0, nrow;
+  float2 *zb, *stg, *twl;
+};
+
+__device__ __forceinline__ XRows xrows_setup(const InstDesc& D, int lw, float2* lds) {
+  XRows q;
+  q.nx = D.nx;
+  q.lgnx = ilog2(q.nx);
+  q.lgR = 8 - q.lgnx;
+  q.R = 1 << q.lgR;
+  q.lgJ = q.lgR - 1;
+  q.J = 1 << q.lgJ;
+  q.Px = D.px;
+  q.lgx = q.lgnx + 1;
+  q.Kx = D.kx;
+  q.es = q.J + 1;
+  q.cs = q.Px * q.es;
+  q.nyz = D.ny * D.nz;
+  q.rows = 3 * q.nyz;
+  q.yz0 = lw * q.R;
+  q.nrow = min(q.R, q.nyz - q.yz0);     // rows of this workgroup (the last one may hold fewer)
+  q.zb = lds;                            // [3][Px][J + 1] lines
+  q.stg = lds + 3 * q.cs;                // [Kx][4R] staged X rows
+  q.twl = q.stg + q.Kx * 4 * q.R;        // [Px]
+  return q;
+}
+
+// demag field [T] of this thread's cell from the convolved X rows
+__device__ __forceinline__ void xrows_c2r(const InstDesc& D, const XRows& q, float (&bdv)[3]) {
+  const MMG float2* X = gbl(D.fx);
+  const int lg4R = q.lgR + 2;
+  for (int e = threadIdx.x; e < q.Kx * 4 * q.R; e += MMI_WG) {
+    const int k = e >> lg4R, qq = e & (4 * q.R - 1);
+    const int c = qq >> q.lgR, j = qq & (q.R - 1);
+    float2 v = make_float2(0.f, 0.f);
+    if (c < 3 && j < q.nrow) v = gld2(X + (size_t)k * q.rows + c * q.nyz + q.yz0 + j);
+    q.stg[e] = v;
+  }
+  __syncthreads();
+  const int half = q.Px >> 1;
+  for (int e = threadIdx.x; e < 3 * q.Px * q.J; e += MMI_WG) {
+    const int j2 = e & (q.J - 1), rest = e >> q.lgJ;
+    const int p = rest & (q.Px - 1), c = rest >> q.lgx;
+    const int kk = p <= half ? p : q.Px - p;
+    const float2* row = q.stg + (kk << lg4R) + c * q.R + 2 * j2;
+    float2 a = row[0], b = row[1];
+    if (p == 0 || p == half) { a.y = 0.f; b.y = 0.f; }
+    const float2 Z = p <= half ? make_float2(a.x - b.y, a.y + b.x) : make_float2(a.x + b.y, b.x - a.y);
+    q.zb[c * q.cs + brev(p, q.lgx) * q.es + j2] = Z;
+  }
+  __syncthreads();
+  fft_cols<MMI_WG, true>(q.zb, q.Px, q.lgx, 3, q.lgJ, q.cs, q.es, q.twl);
+  const int j = threadIdx.x >> q.lgnx, x = threadIdx.x & (q.nx - 1);
+  const float sc = D.bd_scale;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float2 z = q.zb[c * q.cs + x * q.es + (j >> 1)];
+    bdv[c] = sc * ((j & 1) ? z.y : z.x);
+  }
+}
+
+// X rows of the next stage input v (this thread's cell; zero for cells
+// outside the grid)
+__device__ __forceinline__ void xrows_r2c(const InstDesc& D, const XRows& q, const float (&v)[3]) {
+  __syncthreads();   // every thread is done with the lines of the C2R
+  for (int e = threadIdx.x; e < 3 * q.cs; e += MMI_WG) q.zb[e] = make_float2(0.f, 0.f);
+  __syncthreads();
+  {
+    const int j = threadIdx.x >> q.lgnx, x = threadIdx.x & (q.nx - 1);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float* p = reinterpret_cast<float*>(q.zb + c * q.cs + x * q.es + (j >> 1));
+      p[j & 1] = v[c];
+    }
+  }
+  __syncthreads();
+  fft_cols<MMI_WG, false>(q.zb, q.Px, q.lgx, 3, q.lgJ, q.cs, q.es, q.twl);
+  MMG float2* X = gbl(D.fx);
+  const int lg4R = q.lgR + 2;
+  for (int e = threadIdx.x; e < q.Kx * 4 * q.R; e += MMI_WG) {
+    const int k = e >> lg4R, qq = e & (4 * q.R - 1);
+    const int c = qq >> q.lgR, j = qq & (q.R - 1);
+    if (c >= 3 || j >= q.nrow) continue;
+    const float2* zc = q.zb + c * q.cs + (j >> 1);
+    const float2 Z = zc[brev(k & (q.Px - 1), q.lgx) * q.es];
+    const float2 Zm = zc[brev((q.Px - k) & (q.Px - 1), q.lgx) * q.es];
+    const float2 o = (j & 1) == 0 ? make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y))
+                                  : make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
+    gst2(X + (size_t)k * q.rows + c * q.nyz + q.yz0 + j, o);
+  }
+}
+
 // --------------------------------------------------------------- the kernel
 // METHOD RK4: ST = 0 run start (reductions only), 1..4 stages.
 // METHOD DP45: ST = 1 run start (k1), 2..7 stages.
 template <int METHOD, int ST>
 __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ descs,
-                                                  const int* __restrict__ wg_inst) {
+                                                  const int* __restrict__ wg_inst,
+                                                  const float2* __restrict__ tw) {
   __shared__ double sh[4];
+  extern __shared__ float2 xl[];
   const InstDesc& D = descs[wg_inst[blockIdx.x]];
   // the control block is only read here (the finalisation kernel writes it)
   const MMG InstCtl* __restrict__ C = gbl(D.ctl);
@@ -376,6 +480,20 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
     fbc[n] = n < NM ? (float)(D.h0[n] * (D.cphi[n] * C->as[n][0] + D.sphi[n] * C->as[n][1])) : 0.f;
 
   const Src src = stage_src(D, C, METHOD, ST);
+
+  // x passes done here: the C2R of this stage's convolved rows, and (below)
+  // the R2C of the next stage input
+  constexpr bool kC2R = (METHOD == MMI_RK4) ? (ST >= 1) : (ST >= 2);
+  constexpr bool kR2C = (METHOD == MMI_RK4) ? (ST >= 1) : (ST >= 2 && ST <= 6);
+  const bool xf = (kC2R || kR2C) && D.xfused;
+  XRows xq;
+  float bdv[3] = {0.f, 0.f, 0.f};
+  if (xf) {
+    xq = xrows_setup(D, lw, xl);
+    load_twiddles(xq.twl, xq.Px, tw, MMI_WG);
+    __syncthreads();
+    if (kC2R) xrows_c2r(D, xq, bdv);
+  }
 
   const int x = valid ? i % D.nx : 0;
   const int yz = valid ? i / D.nx : 0;
@@ -413,7 +531,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
     const bool has_bd = D.demag == 2;
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      if (s < S) torque_at(D, src, i, x, yy, zz, m, s, fb, has_bd, k[s]);
+      if (s < S) torque_at(D, src, i, x, yy, zz, m, s, fb, has_bd, k[s], (kC2R && xf) ? bdv : nullptr);
   }
 
   // combination and outputs
@@ -581,7 +699,10 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
     const double r = block_reduce<true>(bad ? 1.0 : 0.0, sh);
     if (threadIdx.x == 0) rec[MMI_SLOT_BAD] = r;
   }
-
+  if (kR2C && xf) {
+    const float v[3] = {valid ? nx_[0][0] : 0.f, valid ? nx_[0][1] : 0.f, valid ? nx_[0][2] : 0.f};
+    xrows_r2c(D, xq, v);
+  }
 }
 
 // One workgroup per instance: gather the partial records of the stage
@@ -627,13 +748,14 @@ __global__ __launch_bounds__(MMI_WG) void k_final(const InstDesc* __restrict__ d
     if (final_pass)                                                                             \
       hipLaunchKernelGGL((mmk::k_final<M, S>), dim3(count), dim3(MMI_WG), 0, stream, descs, count); \
     else                                                                                        \
-      hipLaunchKernelGGL((mmk::k_stage<M, S>), dim3(nblocks), dim3(MMI_WG), 0, stream, descs, wg); \
+      hipLaunchKernelGGL((mmk::k_stage<M, S>), dim3(nblocks), dim3(MMI_WG), lds, stream, descs, wg, tw); \
     break;
 
 // final_pass = false: the cell kernel of a stage; true: its per-instance
 // finalisation (count instances).
 hipError_t mmk_launch_stage(int method, int stage, bool final_pass, int nblocks, int count,
-                            const InstDesc* descs, const int* wg, hipStream_t stream) {
+                            const InstDesc* descs, const int* wg, const float2* tw, size_t lds,
+                            hipStream_t stream) {
   if (method == MMI_RK4) {
     switch (stage) {
       MM_STAGE_LAUNCH(MMI_RK4, 0)

@@ -12,7 +12,8 @@ void kernel_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, st
 }  // namespace mmh
 
 hipError_t mmk_launch_stage(int method, int stage, bool final_pass, int nblocks, int count,
-                            const InstDesc* descs, const int* wg, hipStream_t stream);
+                            const InstDesc* descs, const int* wg, const float2* tw, size_t lds,
+                            hipStream_t stream);
 // x passes with lines in registers: Px = 4 MX, MX in {4, 8, 16, 32}; dir +1 forward (method,
 // stage select the stage input), -1 inverse; work items are tiles of 128 rows
 hipError_t mmk_launch_fft_xr(int dir, int MX, int nblocks, const InstDesc* d, const WorkItem* w, int method,

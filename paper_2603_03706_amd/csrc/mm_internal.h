@@ -84,8 +84,9 @@ struct InstDesc {
   // FFT demag
   float2* fx;                         // [Kx][3][nz][ny]
   float2* fy;                         // [Kx][3][nz][Py] (split path)
-  const float* kern;                  // [6][Pz/2+1][Py/2+1][Kx]
+  const float* kern;                  // [Kx][6][Pz/2+1][Py/2+1]
   int px, py, pz, kx;
+  int xfused;                         // x passes done inside the stage kernels (see k_stage)
   // discrete adjoint (RK4): recorded segment and adjoint fields
   float* rec_m;                       // [K+1][4][S*3*cells] stage inputs of each recorded step
   float* rec_norm;                    // [K][S*cells] |z| before the renormalisation

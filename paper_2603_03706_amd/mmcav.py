@@ -298,8 +298,8 @@ class Batch:
         _check(self._lib.mm_batch_set_fft_path(self.h, self.YZ_PATHS[path]))
 
     def set_fft_x(self, path):
-        """Force the x-pass strategy ("lds" or "reg") for every grid shape."""
-        _check(self._lib.mm_batch_set_fft_x(self.h, {"lds": 0, "reg": 1}[path]))
+        """Force the x-pass strategy ("lds", "reg" or "stage") for every grid shape."""
+        _check(self._lib.mm_batch_set_fft_x(self.h, {"lds": 0, "reg": 1, "stage": 2}[path]))
 
     def profile(self, steps, tol=0.0, cap=32):
         names = ctypes.create_string_buffer(48 * cap)

@@ -316,12 +316,12 @@ def test_tuned_batch_keeps_parity():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("shape", [(12, 12, 12), (10, 6, 5)])
+@pytest.mark.parametrize("shape", [(12, 12, 12), (10, 6, 5), (16, 6, 5)])
 def test_fft_yz_paths_agree(shape):
     """The y-z strategies of the demag convolution (LDS-fused, register lines,
-    split passes) and the two x-pass strategies (LDS tiles, register lines)
-    give the same trajectory to FP32 rounding, and the oracle's within the
-    parity bound, on a sphere and on a ragged box."""
+    split passes) and the x-pass strategies (LDS tiles, register lines, inside
+    the stage kernels) give the same trajectory to FP32 rounding, and the
+    oracle's within the parity bound, on a sphere and on ragged boxes."""
     from paper_2603_03706_amd import mmcav
     if shape == (12, 12, 12):
         inst = variant(W.sweep_sphere(5, count=8, n=12), method="rk4", dt0=0.2e-12)
@@ -334,7 +334,10 @@ def test_fft_yz_paths_agree(shape):
     st = oracle_for(inst)
     run_oracle(st, 20e-12)
     out = {}
-    for path, xpath in (("fused", "lds"), ("reg", "reg"), ("split", "lds"), ("fused", "reg")):
+    combos = [("fused", "lds"), ("reg", "reg"), ("split", "lds"), ("fused", "reg")]
+    if shape[0] & (shape[0] - 1) == 0:       # x passes inside the stage kernels need nx = 2^k
+        combos += [("reg", "stage"), ("split", "stage")]
+    for path, xpath in combos:
         c = gpu_for(inst)
         b = mmcav.Batch([c])
         b.set_fft_path(path)
@@ -364,6 +367,8 @@ def test_fft_path_rejects_unfit_shape():
         b.set_fft_path("reg")
     with pytest.raises(mmcav.MMError):
         b.set_fft_x("reg")
+    with pytest.raises(mmcav.MMError):
+        b.set_fft_x("stage")
     b.set_fft_path("split")
     b.set_fft_x("lds")
     b.close()
