@@ -151,12 +151,7 @@ constexpr int XR_ROWS = 128;
 // x-rows, so nx is a power of two from 2 to 128
 bool xfuse_fits(int nx) { return nx >= 2 && nx <= 128 && (nx & (nx - 1)) == 0; }
 size_t xfuse_lds(int nx) {
-  const int Px = 2 * nx, Kx = nx + 1;
-  if (nx <= 32) {   // one region per wavefront (four per workgroup)
-    const int Rw = 64 / nx, Lw = Rw / 2;
-    return 4 * sizeof(float2) * ((size_t)3 * Px * Lw + (size_t)Kx * 4 * Rw + Px);
-  }
-  const int R = 256 / nx, J = R / 2;
+  const int R = 256 / nx, J = R / 2, Px = 2 * nx, Kx = nx + 1;
   return sizeof(float2) * ((size_t)3 * Px * (J + 1) + (size_t)Kx * 4 * R + Px);
 }
 const char* path_name(int p) { return p == PATH_REG ? "reg" : p == PATH_SPLIT ? "split" : "fused"; }

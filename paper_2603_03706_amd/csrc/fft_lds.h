@@ -117,15 +117,10 @@ __device__ void fft_rows(float2* lds, int L, int lg, int NL, const int* tab, con
 // Lines along a strided axis: line (c, j) of NC groups of 2^lgJ adjacent
 // lines, element stride es, group stride cs.  Consecutive threads take
 // adjacent lines.
-// WAVE: the lines belong to one wavefront (T = 64), which works through the
-// passes alone.  A wavefront's LDS instructions complete in program order and
-// each pass reads and writes disjoint elements, so the passes only need to
-// stay in program order (a wave barrier, no workgroup barrier).
-template <int T, bool DIT, bool WAVE = false>
+template <int T, bool DIT>
 __device__ void fft_cols(float2* lds, int L, int lg, int NC, int lgJ, int cs, int es, const float2* twl,
                          int s0 = 0, int tmax = -1) {
   if (lg == 0) return;
-  const int tid = WAVE ? (int)(threadIdx.x & 63) : (int)threadIdx.x;
   const int J = 1 << lgJ;
   if (!DIT) {
     // DIF stages s0 .. lg-1 (stage s has span L >> (s + 1))
@@ -133,22 +128,22 @@ __device__ void fft_cols(float2* lds, int L, int lg, int NC, int lgJ, int cs, in
     for (; s + 2 <= lg; s += 2) {
       const int h = L >> (s + 1), q = h >> 1, lq = lg - s - 2, lgQ = lg - 2;
       const int NB = (NC << lgQ) << lgJ;
-      for (int idx = tid; idx < NB; idx += T) {
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
         const int j = idx & (J - 1), rest = idx >> lgJ;
         const int r = rest & ((1 << lgQ) - 1), c = rest >> lgQ;
         const int g = r >> lq, i = r & (q - 1);
         dif4(lds, c * cs + j + (g * 2 * h + i) * es, q * es, h * es, twl[i << s], twl[i << (s + 1)]);
       }
-      if (WAVE) __builtin_amdgcn_wave_barrier(); else __syncthreads();
+      __syncthreads();
     }
     if (s < lg) {
       const int NB = (NC << (lg - 1)) << lgJ;
-      for (int idx = tid; idx < NB; idx += T) {
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
         const int j = idx & (J - 1), rest = idx >> lgJ;
         const int m = rest & ((1 << (lg - 1)) - 1), c = rest >> (lg - 1);
         bf2(lds, c * cs + j + 2 * m * es, es);
       }
-      if (WAVE) __builtin_amdgcn_wave_barrier(); else __syncthreads();
+      __syncthreads();
     }
   } else {
     // DIT stages 0 .. tmax-1 (stage t has span 1 << t)
@@ -156,25 +151,25 @@ __device__ void fft_cols(float2* lds, int L, int lg, int NC, int lgJ, int cs, in
     int t = 0;
     if (tmax & 1) {
       const int NB = (NC << (lg - 1)) << lgJ;
-      for (int idx = tid; idx < NB; idx += T) {
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
         const int j = idx & (J - 1), rest = idx >> lgJ;
         const int m = rest & ((1 << (lg - 1)) - 1), c = rest >> (lg - 1);
         bf2(lds, c * cs + j + 2 * m * es, es);
       }
-      if (WAVE) __builtin_amdgcn_wave_barrier(); else __syncthreads();
+      __syncthreads();
       t = 1;
     }
     for (; t + 2 <= tmax; t += 2) {
       const int q = 1 << t, lgQ = lg - 2;
       const int NB = (NC << lgQ) << lgJ;
-      for (int idx = tid; idx < NB; idx += T) {
+      for (int idx = threadIdx.x; idx < NB; idx += T) {
         const int j = idx & (J - 1), rest = idx >> lgJ;
         const int r = rest & ((1 << lgQ) - 1), c = rest >> lgQ;
         const int g = r >> t, i = r & (q - 1);
         dit4(lds, c * cs + j + (g * 4 * q + i) * es, q * es, twid<true>(twl, i << (lg - t - 1)),
              twid<true>(twl, i << (lg - t - 2)));
       }
-      if (WAVE) __builtin_amdgcn_wave_barrier(); else __syncthreads();
+      __syncthreads();
     }
   }
 }

@@ -446,108 +446,6 @@ __device__ __forceinline__ void xrows_r2c(const InstDesc& D, const XRows& q, con
   }
 }
 
-// Rows of up to 32 cells: a wavefront holds Rw = 64/nx whole rows of each
-// component and transforms them on its own, in its own LDS region, with no
-// workgroup barrier.
-struct XWave {
-  int nx, lgnx, Rw, lgRw, Lw, lgLw, Px, lgx, Kx, cs, nyz, rows, row0, nrow, lane;
-  float2 *zb, *stg, *twl;
-};
-
-__device__ __forceinline__ size_t xwave_region(int nx) {
-  const int Rw = 64 / nx, Lw = Rw / 2, Px = 2 * nx, Kx = nx + 1;
-  return (size_t)3 * Px * Lw + (size_t)Kx * 4 * Rw + Px;
-}
-
-__device__ __forceinline__ XWave xwave_setup(const InstDesc& D, int lw, float2* lds, const float2* tw) {
-  XWave q;
-  q.nx = D.nx;
-  q.lgnx = ilog2(q.nx);
-  q.lgRw = 6 - q.lgnx;
-  q.Rw = 1 << q.lgRw;
-  q.lgLw = q.lgRw - 1;
-  q.Lw = 1 << q.lgLw;
-  q.Px = D.px;
-  q.lgx = q.lgnx + 1;
-  q.Kx = D.kx;
-  q.cs = q.Px * q.Lw;
-  q.nyz = D.ny * D.nz;
-  q.rows = 3 * q.nyz;
-  const int w = threadIdx.x >> 6;
-  q.lane = threadIdx.x & 63;
-  q.row0 = lw * (4 * q.Rw) + w * q.Rw;
-  q.nrow = max(0, min(q.Rw, q.nyz - q.row0));
-  float2* region = lds + (size_t)w * xwave_region(q.nx);
-  q.zb = region;                          // [3][Px][Lw] lines (rows 2l, 2l+1 of a component)
-  q.stg = region + 3 * q.cs;              // [Kx][4 Rw] staged X rows
-  q.twl = q.stg + q.Kx * 4 * q.Rw;        // [Px]
-  for (int m = q.lane; m < q.Px; m += 64) q.twl[m] = tw[m * (MMI_TW_LEN / q.Px)];
-  __builtin_amdgcn_wave_barrier();
-  return q;
-}
-
-__device__ __forceinline__ void xwave_c2r(const InstDesc& D, const XWave& q, float (&bdv)[3]) {
-  const MMG float2* X = gbl(D.fx);
-  const int lg4R = q.lgRw + 2;
-  for (int e = q.lane; e < q.Kx * 4 * q.Rw; e += 64) {
-    const int k = e >> lg4R, qq = e & (4 * q.Rw - 1);
-    const int c = qq >> q.lgRw, j = qq & (q.Rw - 1);
-    const bool in = c < 3 && j < q.nrow;
-    const float2 v = gld2(X + (size_t)k * q.rows + min(c, 2) * q.nyz + min(q.row0 + j, q.nyz - 1));
-    q.stg[e] = in ? v : make_float2(0.f, 0.f);
-  }
-  __builtin_amdgcn_wave_barrier();
-  const int half = q.Px >> 1;
-  for (int e = q.lane; e < 3 * q.Px * q.Lw; e += 64) {
-    const int l = e & (q.Lw - 1), rest = e >> q.lgLw;
-    const int p = rest & (q.Px - 1), c = rest >> q.lgx;
-    const int kk = p <= half ? p : q.Px - p;
-    const float2* row = q.stg + (kk << lg4R) + c * q.Rw + 2 * l;
-    float2 a = row[0], b = row[1];
-    if (p == 0 || p == half) { a.y = 0.f; b.y = 0.f; }
-    const float2 Z = p <= half ? make_float2(a.x - b.y, a.y + b.x) : make_float2(a.x + b.y, b.x - a.y);
-    q.zb[c * q.cs + brev(p, q.lgx) * q.Lw + l] = Z;
-  }
-  __builtin_amdgcn_wave_barrier();
-  fft_cols<64, true, true>(q.zb, q.Px, q.lgx, 3, q.lgLw, q.cs, q.Lw, q.twl);
-  const int j = q.lane >> q.lgnx, x = q.lane & (q.nx - 1);
-  const float sc = D.bd_scale;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const float2 z = q.zb[c * q.cs + x * q.Lw + (j >> 1)];
-    bdv[c] = sc * ((j & 1) ? z.y : z.x);
-  }
-}
-
-__device__ __forceinline__ void xwave_r2c(const InstDesc& D, const XWave& q, const float (&v)[3]) {
-  __builtin_amdgcn_wave_barrier();
-  for (int e = q.lane; e < 3 * q.cs; e += 64) q.zb[e] = make_float2(0.f, 0.f);
-  __builtin_amdgcn_wave_barrier();
-  {
-    const int j = q.lane >> q.lgnx, x = q.lane & (q.nx - 1);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float* p = reinterpret_cast<float*>(q.zb + c * q.cs + x * q.Lw + (j >> 1));
-      p[j & 1] = v[c];
-    }
-  }
-  __builtin_amdgcn_wave_barrier();
-  fft_cols<64, false, true>(q.zb, q.Px, q.lgx, 3, q.lgLw, q.cs, q.Lw, q.twl);
-  MMG float2* X = gbl(D.fx);
-  const int lg4R = q.lgRw + 2;
-  for (int e = q.lane; e < q.Kx * 4 * q.Rw; e += 64) {
-    const int k = e >> lg4R, qq = e & (4 * q.Rw - 1);
-    const int c = qq >> q.lgRw, j = qq & (q.Rw - 1);
-    if (c >= 3 || j >= q.nrow) continue;
-    const float2* zc = q.zb + c * q.cs + (j >> 1);
-    const float2 Z = zc[brev(k & (q.Px - 1), q.lgx) * q.Lw];
-    const float2 Zm = zc[brev((q.Px - k) & (q.Px - 1), q.lgx) * q.Lw];
-    const float2 o = (j & 1) == 0 ? make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y))
-                                  : make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
-    gst2(X + (size_t)k * q.rows + c * q.nyz + q.row0 + j, o);
-  }
-}
-
 // --------------------------------------------------------------- the kernel
 // METHOD RK4: ST = 0 run start (reductions only), 1..4 stages.
 // METHOD DP45: ST = 1 run start (k1), 2..7 stages.
@@ -588,14 +486,9 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   constexpr bool kC2R = (METHOD == MMI_RK4) ? (ST >= 1) : (ST >= 2);
   constexpr bool kR2C = (METHOD == MMI_RK4) ? (ST >= 1) : (ST >= 2 && ST <= 6);
   const bool xf = (kC2R || kR2C) && D.xfused;
-  const bool xwave = xf && D.nx <= 32;    // rows of a wavefront, no workgroup barriers
   XRows xq;
-  XWave xw;
   float bdv[3] = {0.f, 0.f, 0.f};
-  if (xwave) {
-    xw = xwave_setup(D, lw, xl, tw);
-    if (kC2R) xwave_c2r(D, xw, bdv);
-  } else if (xf) {
+  if (xf) {
     xq = xrows_setup(D, lw, xl);
     load_twiddles(xq.twl, xq.Px, tw, MMI_WG);
     __syncthreads();
@@ -808,8 +701,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   }
   if (kR2C && xf) {
     const float v[3] = {valid ? nx_[0][0] : 0.f, valid ? nx_[0][1] : 0.f, valid ? nx_[0][2] : 0.f};
-    if (xwave) xwave_r2c(D, xw, v);
-    else xrows_r2c(D, xq, v);
+    xrows_r2c(D, xq, v);
   }
 }
 
