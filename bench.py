@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-afm", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=512)
     ap.add_argument("--afm-steps", type=int, default=20)
+    ap.add_argument("--no-film", action="store_true")
+    ap.add_argument("--film-steps", type=int, default=100)
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for rocprofv3 --pmc: tune, a marker copy, a few steps, a marker copy")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_JSON"),
@@ -318,6 +320,25 @@ def afm_batch(steps, tol):
             "batched_vs_plain": plain / dt, "batched_cell_updates_per_s": cells * acc / len(insts) / dt}
 
 
+def film_rate(steps, tol):
+    """Multimode film: 128 x 128 x 32 cells at 5 nm (524,288), FFT demag on
+    256 x 256 x 64, four profiled modes, DP45 at tol, from m = +z with
+    a_1(0) = 1: cell-updates/s of one instance."""
+    import torch
+    from paper_2603_03706_amd import mmcav, workloads as W
+    inst = W.multimode_film()
+    c = mmcav.Context.from_instance(inst)
+    b = mmcav.Batch([c])
+    b.tune()
+    b.step(20, tol)
+    dt, acc = timed_steps(b, [c], steps, tol)
+    b.close()
+    c.close()
+    return {"workload": "multimode film 128x128x32 at 5 nm, FFT demag on 256x256x64, 4 profiled modes, "
+                        f"DP45 tol {tol:g}", "cells": inst.cells, "steps": steps, "accepted": acc,
+            "ms_per_step": dt / steps * 1e3, "cell_updates_per_s": inst.cells * acc / dt}
+
+
 def cpu_baseline(inst, seconds, tol):
     """The oracle, as it stands, on the host cores: one sweep instance,
     DP45 from the same initial state, for about `seconds` of CPU work."""
@@ -410,6 +431,12 @@ def main():
         afm = afm_batch(args.afm_steps, args.tol)
         print(f"[bench] afm: {json.dumps(afm)}", file=sys.stderr, flush=True)
 
+    film = None
+    if not args.no_film:
+        print("[bench] film leg", file=sys.stderr, flush=True)
+        film = film_rate(args.film_steps, args.tol)
+        print(f"[bench] film: {json.dumps(film)}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(insts[0], args.cpu_seconds, args.tol)
@@ -438,6 +465,7 @@ def main():
         "adjoint_over_forward": None if adj is None else adj["adjoint_over_forward"],
         "adjoint": adj,
         "afm_batch": afm,
+        "film": film,
         "kernels": kernels,
     }
     print(json.dumps(out))
