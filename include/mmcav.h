@@ -193,10 +193,12 @@ mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len);
  *   MM_YZ_REGISTER  one workgroup per (instance, kx), each line split over
  *                   four lanes that hold it in registers; padded y of 16..128
  *                   and padded z of 16..64 cells only;
- *   MM_YZ_SPLIT     separate y and z passes through device memory.
- * All three compute the same convolution (agreement to FP32 rounding).
+ *   MM_YZ_SPLIT     separate y and z passes through device memory;
+ *   MM_YZ_REGISTER8 as MM_YZ_REGISTER with each z line over eight lanes
+ *                   (half the registers per lane); padded z of 32 or 64.
+ * All of them compute the same convolution (agreement to FP32 rounding).
  * Returns MM_ERR_ARG, changing nothing, if some shape cannot use `path`. */
-enum { MM_YZ_FUSED = 0, MM_YZ_REGISTER = 1, MM_YZ_SPLIT = 2 };
+enum { MM_YZ_FUSED = 0, MM_YZ_REGISTER = 1, MM_YZ_SPLIT = 2, MM_YZ_REGISTER8 = 3 };
 mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path);
 
 /* Strategy of the x passes (R2C forward, C2R inverse) for every FFT grid

@@ -141,7 +141,9 @@ bool reg_fits(int ny, int nz, int py, int pz) {
   return y_ok && z_ok && reg_lds(nz, py, pz) <= 160 * 1024;
 }
 
-enum { PATH_FUSED = MM_YZ_FUSED, PATH_REG = MM_YZ_REGISTER, PATH_SPLIT = MM_YZ_SPLIT };
+enum { PATH_FUSED = MM_YZ_FUSED, PATH_REG = MM_YZ_REGISTER, PATH_SPLIT = MM_YZ_SPLIT, PATH_REG8 = MM_YZ_REGISTER8 };
+// eight lanes per z column: padded z of 32 or 64
+bool reg8_fits(int ny, int nz, int py, int pz) { return reg_fits(ny, nz, py, pz) && (pz == 32 || pz == 64); }
 
 // x passes with lines in registers (selected by a tile width Wx of 0): padded x of 16..128
 bool xreg_fits(int px) { return px == 16 || px == 32 || px == 64 || px == 128; }
@@ -154,7 +156,9 @@ size_t xfuse_lds(int nx) {
   const int R = 256 / nx, J = R / 2, Px = 2 * nx, Kx = nx + 1;
   return sizeof(float2) * ((size_t)3 * Px * (J + 1) + (size_t)Kx * 4 * R + Px);
 }
-const char* path_name(int p) { return p == PATH_REG ? "reg" : p == PATH_SPLIT ? "split" : "fused"; }
+const char* path_name(int p) {
+  return p == PATH_REG ? "reg" : p == PATH_REG8 ? "reg8" : p == PATH_SPLIT ? "split" : "fused";
+}
 
 Layout make_layout(const mm_params& p, int n_modes) {
   Layout L{};
@@ -476,7 +480,8 @@ mm_status build_group(mm_batch::Group& g) {
   if (mm_status s = up(zc, &g.zc, &g.n_zc)) return s;
   g.lds_xf = g.Wx == 0 ? 0 : sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + g.px);
   g.lds_xi = g.Wx == 0 ? 0 : sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + (size_t)g.kx * 2 * g.Wx + g.px);
-  g.lds_yz = g.path == PATH_REG ? reg_lds(g.nz, g.py, g.pz) : fused_lds(g.ny, g.nz, g.py, g.pz, g.TK);
+  g.lds_yz = (g.path == PATH_REG || g.path == PATH_REG8) ? reg_lds(g.nz, g.py, g.pz)
+                                                         : fused_lds(g.ny, g.nz, g.py, g.pz, g.TK);
   g.lds_y = sizeof(float2) * ((size_t)g.py * (g.Wy + 1) + g.py);
   g.lds_zc = sizeof(float2) * ((size_t)g.pz * 3 * g.TW + g.pz);
   return MM_OK;
@@ -607,7 +612,12 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1, bool fwd = true
           return mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, method, stage, g_twiddle, b->stream);
         }))
       return s;
-    if (g.path == PATH_REG) {
+    if (g.path == PATH_REG8) {
+      if (mm_status s = launch(b, "fft_yz_convolve", [&] {
+            return mmk_launch_fft_yz8(g.py / 4, g.pz / 4, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
+          }))
+        return s;
+    } else if (g.path == PATH_REG) {
       if (mm_status s = launch(b, "fft_yz_convolve", [&] {
             return mmk_launch_fft_yzr(g.py / 4, g.pz / 4, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
           }))
@@ -1478,10 +1488,13 @@ mm_status mm_batch_step(mm_batch* b, int64_t steps, double tol) {
 
 mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path) {
   if (!b) return fail(MM_ERR_ARG, "batch is NULL");
-  if (path != PATH_FUSED && path != PATH_REG && path != PATH_SPLIT) return fail(MM_ERR_ARG, "unknown y-z path");
+  if (path != PATH_FUSED && path != PATH_REG && path != PATH_SPLIT && path != PATH_REG8)
+    return fail(MM_ERR_ARG, "unknown y-z path");
   for (auto& g : b->groups) {
     if (path == PATH_REG && !reg_fits(g.ny, g.nz, g.py, g.pz))
       return fail(MM_ERR_ARG, "register y-z path needs padded y in 16..128 and padded z in 16..64");
+    if (path == PATH_REG8 && !reg8_fits(g.ny, g.nz, g.py, g.pz))
+      return fail(MM_ERR_ARG, "eight-lane register y-z path needs padded y in 16..128 and padded z of 32 or 64");
     if (path == PATH_FUSED && !fused_fits(g.ny, g.nz, g.py, g.pz))
       return fail(MM_ERR_ARG, "fused y-z path does not fit in LDS for this grid");
   }
@@ -1648,6 +1661,17 @@ mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
         return s;
       yrep += (yrep.empty() ? "" : ", ") + std::string("\"reg\": ") + std::to_string(us);
       if (us < bestYZ) { bestYZ = us; bestPath = PATH_REG; }
+    }
+    if (reg8_fits(g.ny, g.nz, g.py, g.pz)) {
+      g.path = PATH_REG8;
+      if (mm_status s = build_group(g)) return s;
+      double us;
+      if (mm_status s = timed([&] {
+            return mmk_launch_fft_yz8(g.py / 4, g.pz / 4, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
+          }, &us))
+        return s;
+      yrep += (yrep.empty() ? "" : ", ") + std::string("\"reg8\": ") + std::to_string(us);
+      if (us < bestYZ) { bestYZ = us; bestPath = PATH_REG8; }
     }
     for (int Wy = 4; Wy <= 64; Wy *= 2) {
       if (sizeof(float2) * ((size_t)g.py * (Wy + 1) + g.py) > lds_cap) continue;

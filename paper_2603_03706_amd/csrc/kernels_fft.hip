@@ -586,6 +586,190 @@ __global__ __launch_bounds__(MM_YZR_T, 2) void k_fft_yzr(const InstDesc* __restr
   }
 }
 
+// ------------------------------ fused y-z, eight lanes per z column (T = 512)
+// The same transform as k_fft_yzr, with each residue's z line split again
+// over two lanes (h = 0, 1) by one radix-2 stage: the even and odd outputs of
+// the residue DFT are (M/2)-point DFTs of f[j] + f[j+M/2] and
+// (f[j] - f[j+M/2]) W_M^j, and its inverse recombines the two half-length
+// inverses the same way.  Lane l = 2r + h of a group of eight: the half
+// exchange is a DPP swap of adjacent lanes, residue pairs r^1 are two lanes
+// apart (DPP), r^2 four lanes apart (swizzle).  Half the registers per lane
+// of k_fft_yzr, so twice the wavefronts per SIMD; y rows use four lanes.
+#define MM_YZ8_T 512
+
+__device__ __forceinline__ float swz_x4(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
+}
+__device__ __forceinline__ float2 lane_x4(float2 v) { return make_float2(swz_x4(v.x), swz_x4(v.y)); }
+__device__ __forceinline__ float2 lane_x2(float2 v) { return make_float2(dpp_x2(v.x), dpp_x2(v.y)); }
+__device__ __forceinline__ float2 lane_x1(float2 v) { return make_float2(dpp_x1(v.x), dpp_x1(v.y)); }
+
+// quad_inverse with residue r^2 four lanes and r^1 two lanes apart
+template <int M>
+__device__ __forceinline__ void quad_inverse8(const float2 (&w)[M], int r, float2 (&out)[M / 2]) {
+  const bool hi = r & 2, odd = r & 1;
+#pragma unroll
+  for (int i = 0; i < M / 2; ++i) {
+    const float2 mine = hi ? w[i + M / 2] : w[i];
+    const float2 recv = lane_x4(hi ? w[i] : w[i + M / 2]);
+    const float2 sm = cadd(mine, recv);
+    const float2 df = hi ? csub(recv, mine) : csub(mine, recv);
+    const float2 got = lane_x2(odd ? sm : df);
+    out[i] = odd ? cadd(got, rot<true>(df)) : cadd(sm, got);
+  }
+}
+
+template <int MY, int MZ>
+__global__ __launch_bounds__(MM_YZ8_T) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_fft_yz8(const InstDesc* __restrict__ descs,
+                                                         const WorkItem* __restrict__ work,
+                                                         const float2* __restrict__ tw) {
+  constexpr int PY = 4 * MY, PZ = 4 * MZ, RS = PY + 1, ZR = 2 * MZ, YR = 2 * MY, MH = MZ / 2;
+  constexpr int lgMY = ilog2c(MY), lgMZ = ilog2c(MZ), lgMH = lgMZ - 1, lgPY = lgMY + 2;
+  extern __shared__ float2 lds[];
+  float2* B = lds;
+  float2* twy = B + 3 * ZR * RS;
+  float2* twz = twy + PY;
+  float2* tw32 = twz + PZ;
+  float* Ks = reinterpret_cast<float*>(tw32 + 32);
+  constexpr int HY1 = PY / 2 + 1, KPL = (PZ / 2 + 1) * HY1;
+  constexpr int NK = (6 * KPL + MM_YZ8_T - 1) / MM_YZ8_T, NXE = 3 * ZR * PY;
+  constexpr int NX = (NXE + MM_YZ8_T - 1) / MM_YZ8_T;
+  load_twiddles(twy, PY, tw, MM_YZ8_T);
+  load_twiddles(twz, PZ, tw, MM_YZ8_T);
+  load_twiddles(tw32, 32, tw, MM_YZ8_T);
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (gbl(D.ctl)->done) return;
+  const int kx = wi.item;
+  const int ny = D.ny, nz = D.nz;
+  const int nrow = 3 * nz;
+  MMG float2* X = gbl(D.fx) + (size_t)kx * nrow * ny;
+  {
+    const MMG float* K = gbl(D.kern) + (size_t)kx * 6 * KPL;
+    float kv[NK];
+    float2 xv[NX];
+#pragma unroll
+    for (int it = 0; it < NK; ++it) kv[it] = K[min(it * MM_YZ8_T + (int)threadIdx.x, 6 * KPL - 1)];
+#pragma unroll
+    for (int it = 0; it < NX; ++it) {
+      const int e = it * MM_YZ8_T + threadIdx.x;
+      const int row = e >> lgPY, y = e & (PY - 1);
+      const int c = row / ZR, z = row - c * ZR;
+      const bool in = e < NXE && z < nz && y < ny;
+      const float2 v = gld2(X + (min(c, 2) * nz + min(z, nz - 1)) * ny + min(y, ny - 1));
+      xv[it] = make_float2(in ? v.x : 0.f, in ? v.y : 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < NK; ++it) {
+      const int e = it * MM_YZ8_T + threadIdx.x;
+      if (e < 6 * KPL) Ks[e] = kv[it];
+    }
+#pragma unroll
+    for (int it = 0; it < NX; ++it) {
+      const int e = it * MM_YZ8_T + threadIdx.x;
+      const int row = e >> lgPY, y = e & (PY - 1);
+      const int z = row % ZR;
+      if (e < NXE && (z >= nz || y < YR)) B[row * RS + y] = xv[it];
+    }
+  }
+  __syncthreads();
+  // forward y, four residue lanes per row
+#pragma unroll 1
+  for (int t = threadIdx.x; t < 4 * 3 * ZR; t += MM_YZ8_T) {
+    const int r = t & 3;
+    float2* line = B + (t >> 2) * RS;
+    float2 f[MY];
+#pragma unroll
+    for (int j = 0; j < MY; ++j) f[j] = fold(line[j], line[j + MY], r, twy[r * j]);
+    reg_dft<MY, false>(f, tw32);
+#pragma unroll
+    for (int p = 0; p < MY; ++p) line[4 * brevc(p, lgMY) + r] = f[p];
+  }
+  __syncthreads();
+  // z per ky column: eight lanes (residue r, half h)
+#pragma unroll 1
+  for (int t = threadIdx.x; t < 8 * PY; t += MM_YZ8_T) {
+    const int ky = t >> 3, h = t & 1, r = (t >> 1) & 3;
+    const float2* col = B + ky;
+    float2 fc[3][MH];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      // fold of this half, then the radix-2 stage across the two halves
+#pragma unroll
+      for (int jj = 0; jj < MH; ++jj) {
+        const int j = h * MH + jj;
+        fc[c][jj] = fold(col[(c * ZR + j) * RS], col[(c * ZR + j + MZ) * RS], r, twz[r * j]);
+      }
+#pragma unroll
+      for (int jj = 0; jj < MH; ++jj) {
+        const float2 own = fc[c][jj];
+        const float2 recv = lane_x1(own);
+        const float2 hi = twc<MZ, false>(csub(recv, own), jj);
+        fc[c][jj] = h ? hi : cadd(own, recv);
+      }
+      reg_dft<MH, false>(fc[c], tw32);
+      asm volatile("" ::: "memory");
+    }
+    // fc[c][p] = X_r[2 brev(p) + h]
+#pragma unroll
+    for (int p = 0; p < MH; ++p) {
+      kernel_mul_lds<PY, PZ>(Ks, ky, 4 * (2 * brevc(p, lgMH) + h) + r, fc[0][p], fc[1][p], fc[2][p]);
+      asm volatile("" ::: "memory");
+    }
+    const int zb = h * MH;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float2 g[MH];
+#pragma unroll
+      for (int k = 0; k < MH; ++k) g[k] = fc[c][brevc(k, lgMH)];
+      reg_dft<MH, true>(g, tw32);
+      // recombine the halves: x[z'] = g0 + W^{-z'} g1, x[z' + MH] = g0 - W^{-z'} g1
+      float2 w[MH];
+#pragma unroll
+      for (int zz = 0; zz < MH; ++zz) {
+        const float2 own = g[brevc(zz, lgMH)];
+        const float2 t1 = twc<MZ, true>(own, zz);
+        const float2 recv = lane_x1(h ? t1 : own);
+        const float2 x = h ? csub(recv, t1) : cadd(own, recv);
+        w[zz] = cmul(x, twid<true>(twz, r * (zb + zz)));
+      }
+      float2 o[MH / 2];
+      quad_inverse8<MH>(w, r, o);
+      const int z0 = zb + (MH / 2) * (r >> 1) + MZ * (r & 1);
+#pragma unroll
+      for (int i = 0; i < MH / 2; ++i)
+        if (z0 + i < nz) B[(c * ZR + z0 + i) * RS + ky] = o[i];
+      asm volatile("" ::: "memory");
+    }
+  }
+  __syncthreads();
+  // inverse y, four residue lanes per row
+#pragma unroll 1
+  for (int t = threadIdx.x; t < 4 * 3 * ZR; t += MM_YZ8_T) {
+    const int r = t & 3;
+    float2* line = B + (t >> 2) * RS;
+    float2 g[MY];
+#pragma unroll
+    for (int k = 0; k < MY; ++k) g[k] = line[4 * k + r];
+    reg_dft<MY, true>(g, tw32);
+    float2 v[MY];
+#pragma unroll
+    for (int y0 = 0; y0 < MY; ++y0) v[y0] = cmul(g[brevc(y0, lgMY)], twid<true>(twy, r * y0));
+    float2 o[MY / 2];
+    quad_inverse<MY>(v, r, o);
+    const int y0 = (MY / 2) * (r >> 1) + MY * (r & 1);
+#pragma unroll
+    for (int i = 0; i < MY / 2; ++i) line[y0 + i] = o[i];
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int e = threadIdx.x; e < 3 * ZR * YR; e += MM_YZ8_T) {
+    const int row = e >> (lgMY + 1), y = e & (YR - 1);
+    const int c = row / ZR, z = row & (ZR - 1);
+    if (z < nz && y < ny) gst2(X + (c * nz + z) * ny + y, B[row * RS + y]);
+  }
+}
+
 // --------------------------------------------------- x passes, lines in registers
 // Work item = 128 consecutive real rows (64 complex lines) of one instance.
 // A line packs two real rows (real and imaginary part) and is split over four
@@ -878,6 +1062,18 @@ hipError_t mmk_launch_fft_xr(int dir, int MX, int nblocks, const InstDesc* d, co
   return hipGetLastError();
 }
 
+#define MM_YZ8_CASE(A, B)                                                                        \
+  if (MY == A && MZ == B) {                                                                      \
+    hipLaunchKernelGGL((mmk::k_fft_yz8<A, B>), dim3(nblocks), dim3(MM_YZ8_T), lds, s, d, w, tw); \
+    return hipGetLastError();                                                                    \
+  }
+hipError_t mmk_launch_fft_yz8(int MY, int MZ, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                              const float2* tw, hipStream_t s) {
+  MM_YZ8_CASE(4, 8) MM_YZ8_CASE(8, 8) MM_YZ8_CASE(16, 8) MM_YZ8_CASE(32, 8)
+  MM_YZ8_CASE(4, 16) MM_YZ8_CASE(8, 16) MM_YZ8_CASE(16, 16) MM_YZ8_CASE(32, 16)
+  return hipErrorInvalidValue;
+}
+
 hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstDesc* d,
                             const WorkItem* w, const float2* tw, hipStream_t s) {
   if (dir < 0) hipLaunchKernelGGL(mmk::k_fft_y<-1>, dim3(nblocks), dim3(256), lds, s, d, w, W, tw);
@@ -901,5 +1097,11 @@ hipError_t mmk_set_lds_limits() {
   MM_YZR_ATTR(4, 4) MM_YZR_ATTR(8, 4) MM_YZR_ATTR(16, 4) MM_YZR_ATTR(32, 4)
   MM_YZR_ATTR(4, 8) MM_YZR_ATTR(8, 8) MM_YZR_ATTR(16, 8) MM_YZR_ATTR(32, 8)
   MM_YZR_ATTR(4, 16) MM_YZR_ATTR(8, 16) MM_YZR_ATTR(16, 16) MM_YZR_ATTR(32, 16)
+#define MM_YZ8_ATTR(A, B)                                                                         \
+  if (e == hipSuccess)                                                                            \
+    e = hipFuncSetAttribute((const void*)mmk::k_fft_yz8<A, B>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            160 * 1024);
+  MM_YZ8_ATTR(4, 8) MM_YZ8_ATTR(8, 8) MM_YZ8_ATTR(16, 8) MM_YZ8_ATTR(32, 8)
+  MM_YZ8_ATTR(4, 16) MM_YZ8_ATTR(8, 16) MM_YZ8_ATTR(16, 16) MM_YZ8_ATTR(32, 16)
   return e;
 }

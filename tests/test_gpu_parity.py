@@ -316,7 +316,7 @@ def test_tuned_batch_keeps_parity():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("shape", [(12, 12, 12), (10, 6, 5), (16, 6, 5)])
+@pytest.mark.parametrize("shape", [(12, 12, 12), (10, 6, 5), (16, 6, 5), (16, 12, 9)])
 def test_fft_yz_paths_agree(shape):
     """The y-z strategies of the demag convolution (LDS-fused, register lines,
     split passes) and the x-pass strategies (LDS tiles, register lines, inside
@@ -337,6 +337,8 @@ def test_fft_yz_paths_agree(shape):
     combos = [("fused", "lds"), ("reg", "reg"), ("split", "lds"), ("fused", "reg")]
     if shape[0] & (shape[0] - 1) == 0:       # x passes inside the stage kernels need nx = 2^k
         combos += [("reg", "stage"), ("split", "stage")]
+    if shape[2] > 8:                         # eight lanes per z column need a padded z of 32 or 64
+        combos += [("reg8", "lds")] + ([("reg8", "stage")] if shape[0] & (shape[0] - 1) == 0 else [])
     for path, xpath in combos:
         c = gpu_for(inst)
         b = mmcav.Batch([c])
@@ -365,6 +367,8 @@ def test_fft_path_rejects_unfit_shape():
     b = mmcav.Batch([c])
     with pytest.raises(mmcav.MMError):
         b.set_fft_path("reg")
+    with pytest.raises(mmcav.MMError):
+        b.set_fft_path("reg8")
     with pytest.raises(mmcav.MMError):
         b.set_fft_x("reg")
     with pytest.raises(mmcav.MMError):
