@@ -303,7 +303,7 @@ def test_tuned_batch_keeps_parity():
     ctxs = [gpu_for(i) for i in insts]
     b1 = mmcav.Batch(ctxs)
     rep = b1.tune()
-    assert len(rep) == 1 and rep[0]["path"] in ("fused", "reg", "split")
+    assert len(rep) == 1 and rep[0]["path"] in ("fused", "reg", "reg8", "split")
     assert all(c.stats()["accepted"] == 0 for c in ctxs)
     b1.run(20e-12)
     for c, r in zip(ctxs, ref):
