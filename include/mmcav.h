@@ -186,8 +186,9 @@ mm_status mm_batch_destroy(mm_batch* b);
 mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len);
 
 /* Demag y-z strategy for every FFT grid shape in the batch (mm_batch_tune
- * chooses one per shape by timing; before that the register strategy is used
- * where it applies, else the fused one where it fits, else the split one):
+ * chooses one per shape by timing; before that the eight-lane register
+ * strategy is used where it applies, else the register one, else the fused
+ * one where it fits, else the split one):
  *   MM_YZ_FUSED     y and z lines transformed in LDS by one workgroup per
  *                   (instance, kx), z in tiles of ky columns;
  *   MM_YZ_REGISTER  one workgroup per (instance, kx), each line split over

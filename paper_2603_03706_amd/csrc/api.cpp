@@ -540,7 +540,10 @@ mm_status batch_build(mm_batch* b) {
       g = &b->groups.back();
       g->nx = c->p.nx; g->ny = c->p.ny; g->nz = c->p.nz;
       g->px = c->L.px; g->py = c->L.py; g->pz = c->L.pz; g->kx = c->L.kx;
-      g->path = reg_fits(g->ny, g->nz, g->py, g->pz) ? PATH_REG : c->L.split ? PATH_SPLIT : PATH_FUSED;
+      g->path = reg8_fits(g->ny, g->nz, g->py, g->pz) ? PATH_REG8
+                : reg_fits(g->ny, g->nz, g->py, g->pz) ? PATH_REG
+                : c->L.split                           ? PATH_SPLIT
+                                                       : PATH_FUSED;
     }
     g->members.push_back(i);
   }
