@@ -153,10 +153,6 @@ constexpr int XR_ROWS = 128;
 // x-rows, so nx is a power of two from 2 to 128
 bool xfuse_fits(int nx) { return nx >= 2 && nx <= 128 && (nx & (nx - 1)) == 0; }
 size_t xfuse_lds(int nx) {
-  if (nx == 16 || nx == 32) {   // register lines: staged X rows, twiddles, real rows
-    const int R = 256 / nx, Kx = nx + 1, Px = 2 * nx;
-    return sizeof(float2) * ((size_t)Kx * 4 * R + Px + 32) + sizeof(float) * 3 * 256;
-  }
   const int R = 256 / nx, J = R / 2, Px = 2 * nx, Kx = nx + 1;
   return sizeof(float2) * ((size_t)3 * Px * (J + 1) + (size_t)Kx * 4 * R + Px);
 }

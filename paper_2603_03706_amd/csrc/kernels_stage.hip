@@ -4,7 +4,6 @@
 #include "mm_internal.h"
 #include "kernels_common.h"
 #include "fft_lds.h"
-#include "fft_reg.h"
 
 namespace mmk {
 
@@ -447,119 +446,6 @@ __device__ __forceinline__ void xrows_r2c(const InstDesc& D, const XRows& q, con
   }
 }
 
-// Rows of 16 or 32 cells: each complex line (rows 2p and 2p+1 of a component)
-// is held by four adjacent lanes in registers, one residue of the frequency
-// index each (as in the register FFT kernels); the workgroup's rows pass
-// through LDS once in each direction, with two workgroup barriers per pass.
-template <int MX>
-struct XLanes {
-  static constexpr int NX = 2 * MX, PX = 4 * MX, KX = NX + 1, R = 256 / NX, LG_R = ilog2c(R);
-  static constexpr int L = 3 * R / 2;                 // lines of the workgroup
-  static constexpr int SQ = 4 * R;                    // staged row stride (>= 3R, a power of two)
-  static constexpr size_t lds_bytes() {
-    return sizeof(float2) * ((size_t)KX * SQ + PX + 32) + sizeof(float) * 3 * 256;
-  }
-  int nyz, rows, yz0, nrow;
-  float2 *stg, *twx, *tw32;
-  float* rowbuf;                                      // [3][R][NX] real rows
-
-  __device__ __forceinline__ void setup(const InstDesc& D, int lw, float2* lds, const float2* tw) {
-    nyz = D.ny * D.nz;
-    rows = 3 * nyz;
-    yz0 = lw * R;
-    nrow = min(R, nyz - yz0);
-    stg = lds;
-    twx = stg + KX * SQ;
-    tw32 = twx + PX;
-    rowbuf = reinterpret_cast<float*>(tw32 + 32);
-    load_twiddles(twx, PX, tw, MMI_WG);
-    load_twiddles(tw32, 32, tw, MMI_WG);
-  }
-
-  // demag field of this thread's cell from the convolved X rows
-  __device__ __forceinline__ void c2r(const InstDesc& D, float (&bdv)[3]) {
-    const MMG float2* X = gbl(D.fx);
-    for (int e = threadIdx.x; e < KX * SQ; e += MMI_WG) {
-      const int k = e >> (LG_R + 2), q = e & (SQ - 1);
-      const int c = q >> LG_R, j = q & (R - 1);
-      const bool in = c < 3 && j < nrow;
-      const float2 v = gld2(X + (size_t)k * rows + min(c, 2) * nyz + min(yz0 + j, nyz - 1));
-      stg[e] = in ? v : make_float2(0.f, 0.f);
-    }
-    __syncthreads();   // staged rows and twiddles
-    const int t = threadIdx.x;
-    if (t < 4 * L) {
-      const int l = t >> 2, r = t & 3;
-      const int c = l / (R / 2), p = l - c * (R / 2);
-      const int qa = c * R + 2 * p;
-      float2 g[MX];
-#pragma unroll
-      for (int k = 0; k < MX; ++k) {
-        const int kx = 4 * k + r;
-        const bool lo = kx <= NX;
-        const int kk = lo ? kx : PX - kx;
-        float2 a = stg[kk * SQ + qa], b = stg[kk * SQ + qa + 1];
-        if (kx == 0 || kx == NX) { a.y = 0.f; b.y = 0.f; }
-        g[k] = lo ? make_float2(a.x - b.y, a.y + b.x) : make_float2(a.x + b.y, b.x - a.y);
-      }
-      reg_dft<MX, true>(g, tw32);
-      float2 w[MX];
-#pragma unroll
-      for (int y0 = 0; y0 < MX; ++y0) w[y0] = cmul(g[brevc(y0, ilog2c(MX))], twid<true>(twx, r * y0));
-      float2 o[MX / 2];
-      quad_inverse<MX>(w, r, o);
-      const int x0 = (MX / 2) * (r >> 1) + MX * (r & 1);
-      const float sc = D.bd_scale;
-      float* ra = rowbuf + (c * R + 2 * p) * NX;
-#pragma unroll
-      for (int i = 0; i < MX / 2; ++i) {
-        ra[x0 + i] = sc * o[i].x;
-        ra[NX + x0 + i] = sc * o[i].y;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 3; ++c) bdv[c] = rowbuf[c * 256 + threadIdx.x];
-  }
-
-  // X rows of the next stage input v of this thread's cell (zero outside the grid)
-  __device__ __forceinline__ void r2c(const InstDesc& D, const float (&v)[3]) {
-    __syncthreads();   // every thread has read its demag field from rowbuf
-#pragma unroll
-    for (int c = 0; c < 3; ++c) rowbuf[c * 256 + threadIdx.x] = v[c];
-    __syncthreads();
-    const int t = threadIdx.x;
-    if (t >= 4 * L) return;
-    const int l = t >> 2, r = t & 3;
-    const int c = l / (R / 2), p = l - c * (R / 2);
-    const float* ra = rowbuf + (c * R + 2 * p) * NX;
-    const float* rb = ra + NX;
-    float2 f[MX];
-#pragma unroll
-    for (int j = 0; j < MX; ++j)
-      f[j] = fold(make_float2(ra[j], rb[j]), make_float2(ra[j + MX], rb[j + MX]), r, twx[r * j]);
-    reg_dft<MX, false>(f, tw32);
-    // f[brev(k)] = Z[4k + r]; the partner Z[Px - kx] is in this lane for
-    // r = 0, 2 and in the lane r ^ 2 for r = 1, 3
-    constexpr int lgM = ilog2c(MX);
-    MMG float2* X = gbl(D.fx);
-    const int row = c * nyz + yz0 + 2 * p;
-    const bool in_a = 2 * p < nrow, in_b = 2 * p + 1 < nrow;
-#pragma unroll
-    for (int k = 0; k <= MX / 2; ++k) {
-      const float2 z = f[brevc(k % MX, lgM)];
-      const float2 recv = quad_x2(f[brevc(MX - 1 - k, lgM)]);
-      const float2 zm = r == 0 ? f[brevc((MX - k) % MX, lgM)] : r == 2 ? f[brevc(MX - 1 - k, lgM)] : recv;
-      const int kx = 4 * k + r;
-      if (kx <= NX) {
-        MMG float2* o = X + (size_t)kx * rows + row;
-        if (in_a) gst2(o, make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y)));
-        if (in_b) gst2(o + 1, make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x)));
-      }
-    }
-  }
-};
-
 // --------------------------------------------------------------- the kernel
 // METHOD RK4: ST = 0 run start (reductions only), 1..4 stages.
 // METHOD DP45: ST = 1 run start (k1), 2..7 stages.
@@ -600,18 +486,9 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   constexpr bool kC2R = (METHOD == MMI_RK4) ? (ST >= 1) : (ST >= 2);
   constexpr bool kR2C = (METHOD == MMI_RK4) ? (ST >= 1) : (ST >= 2 && ST <= 6);
   const bool xf = (kC2R || kR2C) && D.xfused;
-  const int xmode = !xf ? 0 : D.nx == 32 ? 32 : D.nx == 16 ? 16 : 1;   // register lines for 16 / 32
   XRows xq;
-  XLanes<16> x16;
-  XLanes<8> x8;
   float bdv[3] = {0.f, 0.f, 0.f};
-  if (xmode == 32) {
-    x16.setup(D, lw, xl, tw);
-    if (kC2R) x16.c2r(D, bdv);
-  } else if (xmode == 16) {
-    x8.setup(D, lw, xl, tw);
-    if (kC2R) x8.c2r(D, bdv);
-  } else if (xmode == 1) {
+  if (xf) {
     xq = xrows_setup(D, lw, xl);
     load_twiddles(xq.twl, xq.Px, tw, MMI_WG);
     __syncthreads();
@@ -824,9 +701,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   }
   if (kR2C && xf) {
     const float v[3] = {valid ? nx_[0][0] : 0.f, valid ? nx_[0][1] : 0.f, valid ? nx_[0][2] : 0.f};
-    if (xmode == 32) x16.r2c(D, v);
-    else if (xmode == 16) x8.r2c(D, v);
-    else xrows_r2c(D, xq, v);
+    xrows_r2c(D, xq, v);
   }
 }
 
