@@ -204,7 +204,7 @@ mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path);
 
 /* Strategy of the x passes (R2C forward, C2R inverse) for every FFT grid
  * shape: MM_X_STAGE (the default where it applies: nx a power of two from 2
- * to 128, one sublattice) does them inside the stage kernels, each workgroup
+ * to 256, one sublattice) does them inside the stage kernels, each workgroup
  * for its own whole x-rows, so the demag field never goes through device
  * memory and the next stage input is transformed where it is computed;
  * MM_X_LDS transforms tiles of rows in separate kernels; MM_X_REGISTER does

@@ -149,11 +149,11 @@ bool reg8_fits(int ny, int nz, int py, int pz) { return reg_fits(ny, nz, py, pz)
 bool xreg_fits(int px) { return px == 16 || px == 32 || px == 64 || px == 128; }
 constexpr int XR_ROWS = 128;
 
-// x passes inside the stage kernels: a 256-cell workgroup must hold whole
-// x-rows, so nx is a power of two from 2 to 128
-bool xfuse_fits(int nx) { return nx >= 2 && nx <= 128 && (nx & (nx - 1)) == 0; }
+// x passes inside the stage kernels: a workgroup must hold at least two whole
+// x-rows of each component, so nx is a power of two from 2 to MMI_WG / 2
+bool xfuse_fits(int nx) { return nx >= 2 && nx <= MMI_WG / 2 && (nx & (nx - 1)) == 0; }
 size_t xfuse_lds(int nx) {
-  const int R = 256 / nx, J = R / 2, Px = 2 * nx, Kx = nx + 1;
+  const int R = MMI_WG / nx, J = R / 2, Px = 2 * nx, Kx = nx + 1;
   return sizeof(float2) * ((size_t)3 * Px * (J + 1) + (size_t)Kx * 4 * R + Px);
 }
 const char* path_name(int p) {
@@ -1521,7 +1521,7 @@ mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path) {
     if (path == MM_X_REGISTER && !xreg_fits(g.px))
       return fail(MM_ERR_ARG, "register x path needs a padded x of 16..128 cells");
     if (path == MM_X_STAGE && !g.xfused && !xfuse_fits(g.nx))
-      return fail(MM_ERR_ARG, "x passes in the stage kernels need nx a power of two from 2 to 128");
+      return fail(MM_ERR_ARG, "x passes in the stage kernels need nx a power of two from 2 to 256");
     if (path == MM_X_STAGE)
       for (int m : g.members)
         if (b->ctxs[m]->p.sublattices != 1) return fail(MM_ERR_ARG, "x passes in the stage kernels need one sublattice");

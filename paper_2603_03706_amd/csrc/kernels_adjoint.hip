@@ -30,7 +30,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   __syncthreads();
   if (lane == 0) sh[wv] = v;
   __syncthreads();
-  return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  double r = sh[0];
+#pragma unroll
+  for (int w = 1; w < MMI_WG / 64; ++w) r += sh[w];
+  return r;
 }
 
 __device__ __forceinline__ void cross3(const float* a, const float* b, float* o) {
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_start(const InstDesc* __restrict
 template <int ST>
 __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ descs,
                                                   const int* __restrict__ wg_inst) {
-  __shared__ double sh[4];
+  __shared__ double sh[MMI_WG / 64];
   const InstDesc& D = descs[wg_inst[blockIdx.x]];
   const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ d
 // ST = 5: step start.  ST = 4..1: after the stage kernels of that stage.
 template <int ST>
 __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__ descs, int count) {
-  __shared__ double sh[4];
+  __shared__ double sh[MMI_WG / 64];
   __shared__ double tot[MMI_PSTRIDE];
   if ((int)blockIdx.x >= count) return;
   const InstDesc& D = descs[blockIdx.x];

@@ -36,22 +36,19 @@ __device__ __forceinline__ void torque_at(const InstDesc& D, const Src& src, int
   k[2] = gl * fmaf(a, dz, cz);
 }
 
-// Block-wide reduction over 256 threads, result valid in thread 0.
+// Block-wide reduction over the workgroup in a fixed order, result valid in
+// thread 0.
 template <bool MAX>
 __device__ __forceinline__ double block_reduce(double v, double* sh) {
+  constexpr int NW = MMI_WG / 64;
   v = MAX ? wave_max(v) : wave_sum(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) sh[wv] = v;
   __syncthreads();
   double r = sh[0];
-  if (MAX) {
-    r = nan_max(r, sh[1]);
-    r = nan_max(r, sh[2]);
-    r = nan_max(r, sh[3]);
-  } else {
-    r = ((r + sh[1]) + sh[2]) + sh[3];
-  }
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r = MAX ? nan_max(r, sh[w]) : r + sh[w];
   return r;
 }
 
@@ -346,8 +343,8 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
 }
 
 // ------------------------------------------- x passes inside the stage kernel
-// With D.xfused (FFT demag, one sublattice, nx a power of two from 2 to 128),
-// a 256-cell workgroup holds R = 256/nx whole x-rows of each component.  It
+// With D.xfused (FFT demag, one sublattice, nx a power of two from 2 to MMI_WG/2),
+// a workgroup of MMI_WG cells holds R = MMI_WG/nx whole x-rows of each component.  It
 // transforms them itself: the C2R of the convolved X rows gives the demag
 // field of its cells in LDS (no B_d round trip), and the R2C of the next
 // stage input it computes writes the X rows of the next convolution (no
@@ -362,7 +359,7 @@ __device__ __forceinline__ XRows xrows_setup(const InstDesc& D, int lw, float2* 
   XRows q;
   q.nx = D.nx;
   q.lgnx = ilog2(q.nx);
-  q.lgR = 8 - q.lgnx;
+  q.lgR = MMI_LG_WG - q.lgnx;
   q.R = 1 << q.lgR;
   q.lgJ = q.lgR - 1;
   q.J = 1 << q.lgJ;
@@ -453,7 +450,7 @@ template <int METHOD, int ST>
 __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ descs,
                                                   const int* __restrict__ wg_inst,
                                                   const float2* __restrict__ tw) {
-  __shared__ double sh[4];
+  __shared__ double sh[MMI_WG / 64];
   extern __shared__ float2 xl[];
   const InstDesc& D = descs[wg_inst[blockIdx.x]];
   // the control block is only read here (the finalisation kernel writes it)
@@ -709,7 +706,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
 // kernel in a fixed order and run the FP64 cavity step / controller.
 template <int METHOD, int ST>
 __global__ __launch_bounds__(MMI_WG) void k_final(const InstDesc* __restrict__ descs, int count) {
-  __shared__ double sh[4];
+  __shared__ double sh[MMI_WG / 64];
   __shared__ double tot[MMI_PSTRIDE];
   if ((int)blockIdx.x >= count) return;
   const InstDesc& D = descs[blockIdx.x];

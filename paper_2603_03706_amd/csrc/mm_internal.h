@@ -4,7 +4,8 @@
 #include <stdint.h>
 
 #define MMI_MAX_MODES 16
-#define MMI_WG 256                 // stage-kernel workgroup size (4 wave64)
+#define MMI_WG 512                    // threads (= cells) per workgroup of the cell kernels
+#define MMI_LG_WG 9
 #define MMI_PSTRIDE 72             // doubles per workgroup partial record
 #define MMI_TW_LEN 1024            // length of the twiddle table (max FFT length)
 
