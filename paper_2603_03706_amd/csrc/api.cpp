@@ -605,9 +605,14 @@ mm_status launch(mm_batch* b, const char* name, F&& f) {
 // run inside the stage kernels, the x-forward pass is enqueued only when
 // `fwd` (the input was not produced by a stage kernel) and the x-inverse
 // pass only when `inv` (the consuming kernel does not transform itself).
-mm_status enqueue_demag(mm_batch* b, int stage, int method = -1, bool fwd = true, bool inv = true) {
+// final_st >= 0: the finalisation of that stage of the batch's method rides
+// on the first group's y-z launch (eight-lane path only, see merge_final).
+mm_status enqueue_demag(mm_batch* b, int stage, int method = -1, bool fwd = true, bool inv = true,
+                        int final_st = -1) {
   if (method < 0) method = b->method;
+  const int nfinal = final_st >= 0 ? (int)b->ctxs.size() : 0;
   for (auto& g : b->groups) {
+    const bool first = &g == &b->groups[0];
     if (!g.xfused || fwd)
     if (mm_status s = launch(b, "fft_x_forward", [&] {
           if (g.Wx == 0)
@@ -617,7 +622,8 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1, bool fwd = true
       return s;
     if (g.path == PATH_REG8) {
       if (mm_status s = launch(b, "fft_yz_convolve", [&] {
-            return mmk_launch_fft_yz8(g.py / 4, g.pz / 4, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
+            return mmk_launch_fft_yz8(g.py / 4, g.pz / 4, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream,
+                                      first ? nfinal : 0, b->method, final_st);
           }))
         return s;
     } else if (g.path == PATH_REG) {
@@ -668,13 +674,15 @@ const char* final_name(int method, int st) {
   return method == MM_RK4 ? rk[st] : dp[st];
 }
 
-mm_status enqueue_stage(mm_batch* b, int st) {
+// Stage kernel, then (unless the next y-z launch carries it) its finalisation.
+mm_status enqueue_stage(mm_batch* b, int st, bool with_final = true) {
   const int n = (int)b->ctxs.size();
   if (mm_status s = launch(b, stage_name(b->method, st), [&] {
         return mmk_launch_stage(b->method, st, false, b->total_wg, n, b->d_desc, b->d_wg, g_twiddle,
                                 b->stage_lds, b->stream);
       }))
     return s;
+  if (!with_final) return MM_OK;
   return launch(b, final_name(b->method, st), [&] {
     return mmk_launch_stage(b->method, st, true, b->total_wg, n, b->d_desc, b->d_wg, g_twiddle, 0, b->stream);
   });
@@ -709,13 +717,22 @@ mm_status enqueue_start(mm_batch* b) {
 // One step.  Where the stage kernels do the x passes, each stage's input is
 // already in X (written by the previous stage kernel) except the DP45 stage
 // 2 input, which depends on the step size chosen after stage 7.
+// The finalisation of a stage other than the last of the step runs as extra
+// workgroups of the next stage's first y-z launch when that launch is the
+// eight-lane kernel: the transform reads only X, which the finalisation does
+// not touch, and the next stage kernel comes after both in stream order.
+bool merge_final(const mm_batch* b) { return !b->groups.empty() && b->groups[0].path == PATH_REG8; }
+
 mm_status enqueue_step(mm_batch* b) {
   const int s0 = b->method == MM_RK4 ? 1 : 2;
   const int s1 = b->method == MM_RK4 ? 4 : 7;
+  int pending = -1;
   for (int st = s0; st <= s1; ++st) {
     const bool fwd = b->method == MM_DP45 && st == 2;
-    if (mm_status s = enqueue_demag(b, st, -1, fwd, false)) return s;
-    if (mm_status s = enqueue_stage(b, st)) return s;
+    if (mm_status s = enqueue_demag(b, st, -1, fwd, false, pending)) return s;
+    const bool merge = st < s1 && merge_final(b);
+    if (mm_status s = enqueue_stage(b, st, !merge)) return s;
+    pending = merge ? st : -1;
   }
   return MM_OK;
 }

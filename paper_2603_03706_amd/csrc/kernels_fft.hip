@@ -19,6 +19,7 @@
 #include "mm_internal.h"
 #include "kernels_common.h"
 #include "fft_lds.h"
+#include "stage_final.h"
 
 namespace mmk {
 
@@ -619,13 +620,27 @@ __device__ __forceinline__ void quad_inverse8(const float2 (&w)[M], int r, float
   }
 }
 
+// Workgroups nyz .. nyz + nfinal - 1 of the launch do not transform: each
+// runs the finalisation of stage fstage (method fmethod) for instance
+// blockIdx.x - nyz.  That work reads only the partial records and control
+// blocks of the previous stage kernel, which the transform never touches, so
+// the two share one launch and the finalisation fills the last, partly empty
+// round of transform workgroups.
+static_assert(MM_YZ8_T == MMI_WG, "the finalisation body assumes MMI_WG threads");
+
 template <int MY, int MZ>
 __global__ __launch_bounds__(MM_YZ8_T) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_fft_yz8(const InstDesc* __restrict__ descs,
                                                          const WorkItem* __restrict__ work,
-                                                         const float2* __restrict__ tw) {
+                                                         const float2* __restrict__ tw, int nyz,
+                                                         int fmethod, int fstage) {
   constexpr int PY = 4 * MY, PZ = 4 * MZ, RS = PY + 1, ZR = 2 * MZ, YR = 2 * MY, MH = MZ / 2;
   constexpr int lgMY = ilog2c(MY), lgMZ = ilog2c(MZ), lgMH = lgMZ - 1, lgPY = lgMY + 2;
   extern __shared__ float2 lds[];
+  if ((int)blockIdx.x >= nyz) {
+    double* sh = reinterpret_cast<double*>(lds);
+    final_any(fmethod, fstage, descs, (int)blockIdx.x - nyz, sh, sh + MMI_WG / 64);
+    return;
+  }
   float2* B = lds;
   float2* twy = B + 3 * ZR * RS;
   float2* twz = twy + PY;
@@ -1064,11 +1079,13 @@ hipError_t mmk_launch_fft_xr(int dir, int MX, int nblocks, const InstDesc* d, co
 
 #define MM_YZ8_CASE(A, B)                                                                        \
   if (MY == A && MZ == B) {                                                                      \
-    hipLaunchKernelGGL((mmk::k_fft_yz8<A, B>), dim3(nblocks), dim3(MM_YZ8_T), lds, s, d, w, tw); \
+    hipLaunchKernelGGL((mmk::k_fft_yz8<A, B>), dim3(nblocks + nfinal), dim3(MM_YZ8_T), lds, s, d, w, tw, \
+                       nblocks, fmethod, fstage);                                                \
     return hipGetLastError();                                                                    \
   }
 hipError_t mmk_launch_fft_yz8(int MY, int MZ, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
-                              const float2* tw, hipStream_t s) {
+                              const float2* tw, hipStream_t s, int nfinal, int fmethod, int fstage) {
+  if (nfinal < 0 || (nfinal > 0 && lds < (MMI_WG / 64 + MMI_PSTRIDE) * sizeof(double))) return hipErrorInvalidValue;
   MM_YZ8_CASE(4, 8) MM_YZ8_CASE(8, 8) MM_YZ8_CASE(16, 8) MM_YZ8_CASE(32, 8)
   MM_YZ8_CASE(4, 16) MM_YZ8_CASE(8, 16) MM_YZ8_CASE(16, 16) MM_YZ8_CASE(32, 16)
   return hipErrorInvalidValue;

@@ -25,9 +25,12 @@ hipError_t mmk_launch_fft_xi(int W, int nblocks, size_t lds, const InstDesc* d, 
 // fused y-z with lines in registers: Py = 4 MY, Pz = 4 MZ, MY in {4,8,16,32}, MZ in {4,8,16}
 hipError_t mmk_launch_fft_yzr(int MY, int MZ, int nblocks, size_t lds, const InstDesc* d,
                               const WorkItem* w, const float2* tw, hipStream_t s);
-// the same with eight lanes per z column (512 threads): MY in {4,8,16,32}, MZ in {8,16}
+// the same with eight lanes per z column (512 threads): MY in {4,8,16,32}, MZ in {8,16}.
+// nfinal > 0 appends that many workgroups that run the finalisation of stage
+// fstage of method fmethod for instances 0 .. nfinal - 1.
 hipError_t mmk_launch_fft_yz8(int MY, int MZ, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
-                              const float2* tw, hipStream_t s);
+                              const float2* tw, hipStream_t s, int nfinal = 0, int fmethod = 0,
+                              int fstage = 0);
 hipError_t mmk_launch_fft_yz(int TK, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              const float2* tw, hipStream_t s);
 hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstDesc* d,

@@ -1,0 +1,365 @@
+// Per-instance finalisation of a stage, shared by the stage kernels' own
+// finalisation launch and by the FFT kernels that carry it as extra
+// workgroups: gather the partial records of the stage kernel in a fixed
+// order and run the FP64 cavity step / step-size controller in thread 0.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "mm_internal.h"
+#include "kernels_common.h"
+
+namespace mmk {
+
+__device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double ar, double ai, double mr,
+                                        double mi, double& fr, double& fi) {
+  // (-i w - kappa) a + i g e^{-i Phi} m^-
+  const double w = D.omega[n], kp = D.kappa[n], g = D.g[n], c = D.cphi[n], s = D.sphi[n];
+  fr = -kp * ar + w * ai + g * (s * mr - c * mi);
+  fi = -w * ar - kp * ai + g * (s * mi + c * mr);
+}
+
+// Block-wide reduction over the workgroup in a fixed order, result valid in
+// thread 0.
+template <bool MAX>
+__device__ __forceinline__ double block_reduce(double v, double* sh) {
+  constexpr int NW = MMI_WG / 64;
+  v = MAX ? wave_max(v) : wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double r = sh[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r = MAX ? nan_max(r, sh[w]) : r + sh[w];
+  return r;
+}
+
+// Sum (or max) one slot of the partial records over all workgroups of an
+// instance in a fixed order; result in thread 0.
+template <bool MAX>
+__device__ __forceinline__ double gather_slot(const InstDesc& D, int slot, double* sh) {
+  double v = MAX ? 0.0 : 0.0;
+  for (int w = threadIdx.x; w < D.nwg; w += MMI_WG) {
+    const double p = gbl(D.partials)[(size_t)w * MMI_PSTRIDE + slot];
+    v = MAX ? nan_max(v, p) : v + p;
+  }
+  return block_reduce<MAX>(v, sh);
+}
+
+// Append one trace sample (time, a, m^-) from values held in the control
+// block / the gathered sums.
+__device__ __forceinline__ void record_sample(const InstDesc& D, InstCtl* C, double t,
+                                              const double (*a)[2], const double (*mm)[2]) {
+  const long long n = C->trace_n;
+  if (n >= C->trace_max) return;
+  gbl(D.trace_t)[n] = t;
+  MMG double* ta = gbl(D.trace_a);
+  MMG double* tm = gbl(D.trace_m);
+  for (int q = 0; q < D.N; ++q) {
+    ta[(n * D.N + q) * 2] = a[q][0];
+    ta[(n * D.N + q) * 2 + 1] = a[q][1];
+    tm[(n * D.N + q) * 2] = mm[q][0];
+    tm[(n * D.N + q) * 2 + 1] = mm[q][1];
+  }
+  C->trace_n = n + 1;
+}
+
+__device__ __forceinline__ double hermite(double th, double h, double y0, double f0, double y1,
+                                          double f1) {
+  const double t2 = th * th, t3 = t2 * th;
+  return (2 * t3 - 3 * t2 + 1) * y0 + (t3 - 2 * t2 + th) * h * f0 + (-2 * t3 + 3 * t2) * y1 +
+         (t3 - t2) * h * f1;
+}
+
+// next attempted step: min(dt, t_end - t), clipped to land on t_end
+__device__ __forceinline__ void plan_step(InstCtl* C, double dt) {
+  const double rem = C->t_end - C->t;
+  double h = dt;
+  int clipped = 0;
+  if (h * (1.0 + 1e-9) >= rem) {
+    h = rem;
+    clipped = 1;
+  }
+  C->h = h;
+  C->clipped = clipped;
+}
+
+// ------------------------------------------------------------ finalisation
+// Runs in thread 0 of the last workgroup of an instance, with the gathered
+// sums in tot[] (mode sums already scaled by 1/(S N_geo)).
+template <int METHOD, int ST>
+__device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
+  const int N = D.N;
+  const double h = C->h;
+  // m^- of the stage input written by this kernel
+  const double(*mmv)[2] = reinterpret_cast<const double(*)[2]>(tot + MMI_SLOT_MM);
+  if (METHOD == MMI_RK4 && ST >= 1 && C->rec_index >= 0) {
+    MMG double* ra = gbl(D.rec_a) + ((size_t)C->rec_index * 4 + (ST - 1)) * N * 2;
+    for (int n = 0; n < N; ++n) {
+      ra[2 * n] = C->as[n][0];
+      ra[2 * n + 1] = C->as[n][1];
+    }
+  }
+  if (METHOD == MMI_RK4) {
+    if (ST == 0) {  // run start: m^- of y, first derivative, first step
+      for (int n = 0; n < N; ++n) {
+        cav_rhs(D, n, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+        C->mm1[n][0] = mmv[n][0];
+        C->mm1[n][1] = mmv[n][1];
+        C->as[n][0] = C->a[n][0];
+        C->as[n][1] = C->a[n][1];
+      }
+      if (C->trace_on && !C->trace_started) {
+        C->trace_started = 1;
+        C->trace_t0 = C->t;
+        record_sample(D, C, C->t, C->a, C->mm1);
+      }
+      plan_step(C, C->dt_fixed);
+      return;
+    }
+    if (ST <= 3) {
+      const double c = (ST == 3) ? h : 0.5 * h;
+      for (int n = 0; n < N; ++n) {
+        const double ar = C->a[n][0] + c * C->ka[ST - 1][n][0];
+        const double ai = C->a[n][1] + c * C->ka[ST - 1][n][1];
+        cav_rhs(D, n, ar, ai, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
+        C->as[n][0] = ar;
+        C->as[n][1] = ai;
+      }
+      return;
+    }
+    // ST == 4: step end; the new amplitudes go to C->as first
+    bool bad = tot[MMI_SLOT_BAD] != 0.0;
+    const double c6 = h / 6.0;
+    for (int n = 0; n < N; ++n) {
+      for (int r = 0; r < 2; ++r) {
+        const double v = C->a[n][r] + c6 * (C->ka[0][n][r] + 2.0 * C->ka[1][n][r] +
+                                            2.0 * C->ka[2][n][r] + C->ka[3][n][r]);
+        if (!isfinite(v)) bad = true;
+        C->as[n][r] = v;
+      }
+    }
+    if (bad) {
+      for (int n = 0; n < N; ++n) {
+        C->as[n][0] = C->a[n][0];
+        C->as[n][1] = C->a[n][1];
+      }
+      C->status = -6;
+      C->done = 1;
+      return;
+    }
+    C->cur ^= 1;
+    C->t = C->clipped ? C->t_end : C->t + h;
+    C->accepted += 1;
+    if (C->rec_index >= 0) C->rec_index += 1;
+    C->dt_min_seen = fmin(C->dt_min_seen, h);
+    C->dt_max_seen = fmax(C->dt_max_seen, h);
+    for (int n = 0; n < N; ++n) {
+      C->a[n][0] = C->as[n][0];
+      C->a[n][1] = C->as[n][1];
+      cav_rhs(D, n, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+      C->mm1[n][0] = mmv[n][0];
+      C->mm1[n][1] = mmv[n][1];
+    }
+    if (C->trace_on) {
+      C->trace_steps += 1;
+      if (C->trace_steps % C->trace_stride == 0) record_sample(D, C, C->t, C->a, C->mm1);
+    }
+    if (C->t >= C->t_end) {
+      C->done = 1;
+      return;
+    }
+    plan_step(C, C->dt_fixed);
+    return;
+  }
+  // ------------------------------------------------------------- DP45
+  using P = DPCoef;
+  if (ST == 1) {  // run start (k1 written by the kernel)
+    for (int n = 0; n < N; ++n) {
+      cav_rhs(D, n, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+      C->mm1[n][0] = mmv[n][0];
+      C->mm1[n][1] = mmv[n][1];
+      C->dmm1[n][0] = tot[MMI_SLOT_DMM + 2 * n];
+      C->dmm1[n][1] = tot[MMI_SLOT_DMM + 2 * n + 1];
+    }
+    if (C->trace_on && !C->trace_started) {
+      C->trace_started = 1;
+      C->trace_t0 = C->t;
+      record_sample(D, C, C->t, C->a, C->mm1);
+    }
+    plan_step(C, C->dt);
+    const double hh = C->h;
+    for (int n = 0; n < N; ++n) {
+      C->as[n][0] = C->a[n][0] + hh * P::a21 * C->ka[0][n][0];
+      C->as[n][1] = C->a[n][1] + hh * P::a21 * C->ka[0][n][1];
+    }
+    return;
+  }
+  if (ST == 2) {
+    // ka2 at (a2, m^-(m2)) [m2 sums in the DMM slot], then ka3 at (a3, m^-(m3))
+    for (int n = 0; n < N; ++n)
+      cav_rhs(D, n, C->as[n][0], C->as[n][1], tot[MMI_SLOT_DMM + 2 * n],
+              tot[MMI_SLOT_DMM + 2 * n + 1], C->ka[1][n][0], C->ka[1][n][1]);
+  }
+  if (ST >= 2 && ST <= 6) {
+    // a_{ST+1} = a + h sum_j A[ST+1][j] ka_j
+    double A[6];
+    if (ST == 2) { A[0] = P::a31; A[1] = P::a32; }
+    if (ST == 3) { A[0] = P::a41; A[1] = P::a42; A[2] = P::a43; }
+    if (ST == 4) { A[0] = P::a51; A[1] = P::a52; A[2] = P::a53; A[3] = P::a54; }
+    if (ST == 5) { A[0] = P::a61; A[1] = P::a62; A[2] = P::a63; A[3] = P::a64; A[4] = P::a65; }
+    if (ST == 6) { A[0] = P::b1; A[1] = 0.0; A[2] = P::b3; A[3] = P::b4; A[4] = P::b5; A[5] = P::b6; }
+    for (int n = 0; n < N; ++n) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int j = 0; j < ST; ++j) {
+        s0 += A[j] * C->ka[j][n][0];
+        s1 += A[j] * C->ka[j][n][1];
+      }
+      const double ar = C->a[n][0] + h * s0;
+      const double ai = C->a[n][1] + h * s1;
+      cav_rhs(D, n, ar, ai, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
+      C->as[n][0] = ar;
+      C->as[n][1] = ai;
+      if (ST == 6) {
+        C->mm7[n][0] = mmv[n][0];
+        C->mm7[n][1] = mmv[n][1];
+      }
+    }
+    return;
+  }
+  // ST == 7: error norm, accept / reject, next step
+  double err = tot[MMI_SLOT_ERR];
+  const double E[7] = {P::e1, 0.0, P::e3, P::e4, P::e5, P::e6, P::e7};
+  for (int n = 0; n < N; ++n) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int j = 0; j < 7; ++j) {
+      s0 += E[j] * C->ka[j][n][0];
+      s1 += E[j] * C->ka[j][n][1];
+    }
+    err = nan_max(err, fabs(h * s0));
+    err = nan_max(err, fabs(h * s1));
+  }
+  const double eps = err / C->tol;
+  const bool finite = isfinite(eps);
+  double fac;
+  if (finite && eps <= 1.0) {
+    // trace: samples in (t, t + h]
+    if (C->trace_on) {
+      const double t0 = C->t;
+      while (C->trace_n < C->trace_max) {
+        const double tk = C->trace_t0 + (double)C->trace_n * C->trace_dt;
+        if (tk > t0 + h * (1.0 + 1e-12) || tk <= t0) break;
+        const double th = (tk - t0) / h;
+        const long long q = C->trace_n;
+        D.trace_t[q] = tk;
+        for (int n = 0; n < N; ++n)
+          for (int r = 0; r < 2; ++r) {
+            D.trace_a[(q * N + n) * 2 + r] =
+                hermite(th, h, C->a[n][r], C->ka[0][n][r], C->as[n][r], C->ka[6][n][r]);
+            D.trace_m[(q * N + n) * 2 + r] = hermite(th, h, C->mm1[n][r], C->dmm1[n][r], C->mm7[n][r],
+                                                     tot[MMI_SLOT_DMM + 2 * n + r]);
+          }
+        C->trace_n = q + 1;
+      }
+    }
+    C->t = C->clipped ? C->t_end : C->t + h;
+    C->accepted += 1;
+    C->dt_min_seen = fmin(C->dt_min_seen, h);
+    C->dt_max_seen = fmax(C->dt_max_seen, h);
+    for (int n = 0; n < N; ++n)
+      for (int r = 0; r < 2; ++r) {
+        C->a[n][r] = C->as[n][r];          // a_7
+        C->ka[0][n][r] = C->ka[6][n][r];   // FSAL
+        C->mm1[n][r] = C->mm7[n][r];
+        C->dmm1[n][r] = tot[MMI_SLOT_DMM + 2 * n + r];
+      }
+    C->cur ^= 1;
+    const int s0 = C->slot[0];
+    C->slot[0] = C->slot[6];
+    C->slot[6] = s0;
+    const double fmx = C->last_rejected ? 1.0 : 5.0;
+    fac = (eps == 0.0) ? 5.0 : 0.9 * pow(eps, -0.2);
+    fac = fmin(fmx, fmax(0.2, fac));
+    C->last_rejected = 0;
+  } else {
+    C->rejected += 1;
+    fac = finite ? fmax(0.2, 0.9 * pow(eps, -0.2)) : 0.2;
+    fac = fmin(1.0, fac);
+    C->last_rejected = 1;
+  }
+  double dtn = h * fac;
+  if (C->dt_max > 0.0) dtn = fmin(dtn, C->dt_max);
+  C->dt = dtn;
+  if (C->t >= C->t_end) {
+    C->done = 1;
+  } else if (dtn < C->dt_min) {
+    C->status = finite ? -5 : -6;
+    C->done = 1;
+  }
+  plan_step(C, dtn);
+  const double hh = C->h;
+  for (int n = 0; n < N; ++n) {
+    C->as[n][0] = C->a[n][0] + hh * P::a21 * C->ka[0][n][0];
+    C->as[n][1] = C->a[n][1] + hh * P::a21 * C->ka[0][n][1];
+  }
+}
+
+// Body of the finalisation of stage ST of instance `inst` (all MMI_WG
+// threads of the workgroup; sh: MMI_WG / 64 doubles, tot: MMI_PSTRIDE
+// doubles of LDS).
+template <int METHOD, int ST>
+__device__ void final_body(const InstDesc* __restrict__ descs, int inst, double* sh, double* tot) {
+  const InstDesc& D = descs[inst];
+  InstCtl* C = D.ctl;
+  if (C->done) return;
+  const bool has_next = !(METHOD == MMI_DP45 && ST == 7);
+  const double scale = D.inv_ngeo / (double)D.S;
+  if (has_next) {
+    for (int q = 0; q < 2 * D.N; ++q) {
+      const double v = gather_slot<false>(D, MMI_SLOT_MM + q, sh);
+      if (threadIdx.x == 0) tot[MMI_SLOT_MM + q] = v * scale;
+    }
+  }
+  if (METHOD == MMI_DP45 && (ST == 1 || ST == 2 || ST == 7)) {
+    for (int q = 0; q < 2 * D.N; ++q) {
+      const double v = gather_slot<false>(D, MMI_SLOT_DMM + q, sh);
+      if (threadIdx.x == 0) tot[MMI_SLOT_DMM + q] = v * scale;
+    }
+  }
+  if (METHOD == MMI_DP45 && ST == 7) {
+    const double v = gather_slot<true>(D, MMI_SLOT_ERR, sh);
+    if (threadIdx.x == 0) tot[MMI_SLOT_ERR] = v;
+  }
+  if (METHOD == MMI_RK4 && ST == 4) {
+    const double v = gather_slot<true>(D, MMI_SLOT_BAD, sh);
+    if (threadIdx.x == 0) tot[MMI_SLOT_BAD] = v;
+  }
+  if (threadIdx.x == 0) finalize<METHOD, ST>(D, C, tot);
+}
+
+// the same with the method and stage chosen at run time
+__device__ __forceinline__ void final_any(int method, int st, const InstDesc* __restrict__ descs, int inst,
+                                          double* sh, double* tot) {
+  if (method == MMI_RK4) {
+    switch (st) {
+      case 0: final_body<MMI_RK4, 0>(descs, inst, sh, tot); break;
+      case 1: final_body<MMI_RK4, 1>(descs, inst, sh, tot); break;
+      case 2: final_body<MMI_RK4, 2>(descs, inst, sh, tot); break;
+      case 3: final_body<MMI_RK4, 3>(descs, inst, sh, tot); break;
+      case 4: final_body<MMI_RK4, 4>(descs, inst, sh, tot); break;
+      default: break;
+    }
+  } else {
+    switch (st) {
+      case 1: final_body<MMI_DP45, 1>(descs, inst, sh, tot); break;
+      case 2: final_body<MMI_DP45, 2>(descs, inst, sh, tot); break;
+      case 3: final_body<MMI_DP45, 3>(descs, inst, sh, tot); break;
+      case 4: final_body<MMI_DP45, 4>(descs, inst, sh, tot); break;
+      case 5: final_body<MMI_DP45, 5>(descs, inst, sh, tot); break;
+      case 6: final_body<MMI_DP45, 6>(descs, inst, sh, tot); break;
+      case 7: final_body<MMI_DP45, 7>(descs, inst, sh, tot); break;
+      default: break;
+    }
+  }
+}
+
+}  // namespace mmk
