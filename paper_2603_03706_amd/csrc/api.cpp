@@ -153,8 +153,8 @@ constexpr int XR_ROWS = 128;
 // x-rows of each component, so nx is a power of two from 2 to MMI_WG / 2
 bool xfuse_fits(int nx) { return nx >= 2 && nx <= MMI_WG / 2 && (nx & (nx - 1)) == 0; }
 size_t xfuse_lds(int nx) {
-  const int R = MMI_WG / nx, J = R / 2, Px = 2 * nx, Kx = nx + 1;
-  return sizeof(float2) * ((size_t)3 * Px * (J + 1) + (size_t)Kx * 4 * R + Px);
+  const int R = MMI_WG / nx, J = R / 2, Px = 2 * nx;
+  return sizeof(float2) * ((size_t)3 * Px * (J + 1) + Px);
 }
 const char* path_name(int p) {
   return p == PATH_REG ? "reg" : p == PATH_REG8 ? "reg8" : p == PATH_SPLIT ? "split" : "fused";

@@ -42,8 +42,24 @@ __device__ __forceinline__ void reduce_modes(const InstDesc& D, int i, bool mag,
       wr = u * (double)vr;
       wi = u * (double)vi;
     }
-    const double sr = block_reduce<false>(wr, sh);
-    const double si = block_reduce<false>(wi, sh);
+    // both sums in one pass over the waves (same order of additions as two
+    // separate block sums)
+    constexpr int NW = MMI_WG / 64;
+    wr = wave_sum(wr);
+    wi = wave_sum(wi);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+      sh[wv] = wr;
+      sh[NW + wv] = wi;
+    }
+    __syncthreads();
+    double sr = sh[0], si = sh[NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      sr += sh[w];
+      si += sh[NW + w];
+    }
     if (threadIdx.x == 0) {
       rec[slot + 2 * n] = sr;
       rec[slot + 2 * n + 1] = si;
@@ -61,7 +77,7 @@ __device__ __forceinline__ void reduce_modes(const InstDesc& D, int i, bool mag,
 // line; lines are transformed by the LDS line FFTs in place.
 struct XRows {
   int nx, lgnx, R, lgR, J, lgJ, Px, lgx, Kx, es, cs, nyz, rows, yz0, nrow;
-  float2 *zb, *stg, *twl;
+  float2 *zb, *twl;
 };
 
 __device__ __forceinline__ XRows xrows_setup(const InstDesc& D, int lw, float2* lds) {
@@ -82,33 +98,31 @@ __device__ __forceinline__ XRows xrows_setup(const InstDesc& D, int lw, float2* 
   q.yz0 = lw * q.R;
   q.nrow = min(q.R, q.nyz - q.yz0);     // rows of this workgroup (the last one may hold fewer)
   q.zb = lds;                            // [3][Px][J + 1] lines
-  q.stg = lds + 3 * q.cs;                // [Kx][4R] staged X rows
-  q.twl = q.stg + q.Kx * 4 * q.R;        // [Px]
+  q.twl = lds + 3 * q.cs;                // [Px]
   return q;
 }
 
 // demag field [T] of this thread's cell from the convolved X rows
 __device__ __forceinline__ void xrows_c2r(const InstDesc& D, const XRows& q, float (&bdv)[3]) {
   const MMG float2* X = gbl(D.fx);
-  const int lg4R = q.lgR + 2;
-  for (int e = threadIdx.x; e < q.Kx * 4 * q.R; e += MMI_WG) {
-    const int k = e >> lg4R, qq = e & (4 * q.R - 1);
-    const int c = qq >> q.lgR, j = qq & (q.R - 1);
-    float2 v = make_float2(0.f, 0.f);
-    if (c < 3 && j < q.nrow) v = gld2(X + (size_t)k * q.rows + c * q.nyz + q.yz0 + j);
-    q.stg[e] = v;
-  }
-  __syncthreads();
   const int half = q.Px >> 1;
-  for (int e = threadIdx.x; e < 3 * q.Px * q.J; e += MMI_WG) {
+  // Item (k, c, j2), k <= Px/2: the X values a, b of rows 2 j2 and 2 j2 + 1
+  // give line entries Z[k] = a + i b and, by Hermitian symmetry,
+  // Z[Px - k] = conj(a) + i conj(b); both go to their bit-reversed slots.
+  const int n = q.Kx * 3 * q.J;
+  for (int e = threadIdx.x; e < n; e += MMI_WG) {
     const int j2 = e & (q.J - 1), rest = e >> q.lgJ;
-    const int p = rest & (q.Px - 1), c = rest >> q.lgx;
-    const int kk = p <= half ? p : q.Px - p;
-    const float2* row = q.stg + (kk << lg4R) + c * q.R + 2 * j2;
-    float2 a = row[0], b = row[1];
-    if (p == 0 || p == half) { a.y = 0.f; b.y = 0.f; }
-    const float2 Z = p <= half ? make_float2(a.x - b.y, a.y + b.x) : make_float2(a.x + b.y, b.x - a.y);
-    q.zb[c * q.cs + brev(p, q.lgx) * q.es + j2] = Z;
+    const int k = rest / 3, c = rest - 3 * k;
+    const int j = 2 * j2;
+    const MMG float2* row = X + (size_t)k * q.rows + c * q.nyz + q.yz0;
+    float2 a = gld2(row + min(j, q.nrow - 1)), b = gld2(row + min(j + 1, q.nrow - 1));
+    if (j >= q.nrow) a = make_float2(0.f, 0.f);
+    if (j + 1 >= q.nrow) b = make_float2(0.f, 0.f);
+    const bool edge = k == 0 || k == half;
+    if (edge) { a.y = 0.f; b.y = 0.f; }
+    float2* line = q.zb + c * q.cs + j2;
+    line[brev(k, q.lgx) * q.es] = make_float2(a.x - b.y, a.y + b.x);
+    if (!edge) line[brev(q.Px - k, q.lgx) * q.es] = make_float2(a.x + b.y, b.x - a.y);
   }
   __syncthreads();
   fft_cols<MMI_WG, true>(q.zb, q.Px, q.lgx, 3, q.lgJ, q.cs, q.es, q.twl);
@@ -122,33 +136,41 @@ __device__ __forceinline__ void xrows_c2r(const InstDesc& D, const XRows& q, flo
 }
 
 // X rows of the next stage input v (this thread's cell; zero for cells
-// outside the grid)
-__device__ __forceinline__ void xrows_r2c(const InstDesc& D, const XRows& q, const float (&v)[3]) {
-  __syncthreads();   // every thread is done with the lines of the C2R
-  for (int e = threadIdx.x; e < 3 * q.cs; e += MMI_WG) q.zb[e] = make_float2(0.f, 0.f);
-  __syncthreads();
+// outside the grid).  `synced`: a workgroup barrier already separates the
+// C2R's last reads of the lines from here.
+__device__ __forceinline__ void xrows_r2c(const InstDesc& D, const XRows& q, const float (&v)[3], bool synced) {
+  if (!synced) __syncthreads();
   {
+    // line entries x < nx hold the cells, x >= nx the zero padding
     const int j = threadIdx.x >> q.lgnx, x = threadIdx.x & (q.nx - 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float* p = reinterpret_cast<float*>(q.zb + c * q.cs + x * q.es + (j >> 1));
       p[j & 1] = v[c];
     }
+    const int pad = q.nx * q.es;
+    for (int e = threadIdx.x; e < 3 * pad; e += MMI_WG) {
+      const int c = (e >= pad) + (e >= 2 * pad);
+      q.zb[c * q.cs + pad + (e - c * pad)] = make_float2(0.f, 0.f);
+    }
   }
   __syncthreads();
   fft_cols<MMI_WG, false>(q.zb, q.Px, q.lgx, 3, q.lgJ, q.cs, q.es, q.twl);
   MMG float2* X = gbl(D.fx);
-  const int lg4R = q.lgR + 2;
-  for (int e = threadIdx.x; e < q.Kx * 4 * q.R; e += MMI_WG) {
-    const int k = e >> lg4R, qq = e & (4 * q.R - 1);
-    const int c = qq >> q.lgR, j = qq & (q.R - 1);
-    if (c >= 3 || j >= q.nrow) continue;
-    const float2* zc = q.zb + c * q.cs + (j >> 1);
+  // Item (k, c, j2): Z[k] and Z[Px - k] of line j2 separate into the X values
+  // of rows 2 j2 (even part) and 2 j2 + 1 (odd part).
+  const int n = q.Kx * 3 * q.J;
+  for (int e = threadIdx.x; e < n; e += MMI_WG) {
+    const int j2 = e & (q.J - 1), rest = e >> q.lgJ;
+    const int k = rest / 3, c = rest - 3 * k;
+    const int j = 2 * j2;
+    if (j >= q.nrow) continue;
+    const float2* zc = q.zb + c * q.cs + j2;
     const float2 Z = zc[brev(k & (q.Px - 1), q.lgx) * q.es];
     const float2 Zm = zc[brev((q.Px - k) & (q.Px - 1), q.lgx) * q.es];
-    const float2 o = (j & 1) == 0 ? make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y))
-                                  : make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x));
-    gst2(X + (size_t)k * q.rows + c * q.nyz + q.yz0 + j, o);
+    MMG float2* row = X + (size_t)k * q.rows + c * q.nyz + q.yz0 + j;
+    gst2(row, make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y)));
+    if (j + 1 < q.nrow) gst2(row + 1, make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x)));
   }
 }
 
@@ -159,7 +181,7 @@ template <int METHOD, int ST>
 __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ descs,
                                                   const int* __restrict__ wg_inst,
                                                   const float2* __restrict__ tw) {
-  __shared__ double sh[MMI_WG / 64];
+  __shared__ double sh[2 * (MMI_WG / 64)];
   extern __shared__ float2 xl[];
   const InstDesc& D = descs[wg_inst[blockIdx.x]];
   // the control block is only read here (the finalisation kernel writes it)
@@ -196,8 +218,8 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   float bdv[3] = {0.f, 0.f, 0.f};
   if (xf) {
     xq = xrows_setup(D, lw, xl);
+    // the barriers inside the passes order these stores before the line FFTs
     load_twiddles(xq.twl, xq.Px, tw, MMI_WG);
-    __syncthreads();
     if (kC2R) xrows_c2r(D, xq, bdv);
   }
 
@@ -407,7 +429,8 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   }
   if (kR2C && xf) {
     const float v[3] = {valid ? nx_[0][0] : 0.f, valid ? nx_[0][1] : 0.f, valid ? nx_[0][2] : 0.f};
-    xrows_r2c(D, xq, v);
+    // the mode reductions above end with workgroup barriers
+    xrows_r2c(D, xq, v, has_next && NM > 0);
   }
 }
 

@@ -316,12 +316,14 @@ def test_tuned_batch_keeps_parity():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("shape", [(12, 12, 12), (10, 6, 5), (16, 6, 5), (16, 12, 9)])
+@pytest.mark.parametrize("shape", [(12, 12, 12), (10, 6, 5), (16, 6, 5), (16, 12, 9), (16, 5, 7), (32, 7, 9)])
 def test_fft_yz_paths_agree(shape):
     """The y-z strategies of the demag convolution (LDS-fused, register lines,
     split passes) and the x-pass strategies (LDS tiles, register lines, inside
     the stage kernels) give the same trajectory to FP32 rounding, and the
-    oracle's within the parity bound, on a sphere and on ragged boxes."""
+    oracle's within the parity bound, on a sphere and on ragged boxes (odd
+    row counts per workgroup among them: 16 x 5 x 7 and 32 x 7 x 9 leave 3
+    and 15 x-rows in the last workgroup of 512 cells)."""
     from paper_2603_03706_amd import mmcav
     if shape == (12, 12, 12):
         inst = variant(W.sweep_sphere(5, count=8, n=12), method="rk4", dt0=0.2e-12)
