@@ -48,7 +48,9 @@ def parse():
     ap.add_argument("--no-film", action="store_true")
     ap.add_argument("--film-steps", type=int, default=100)
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="short run for rocprofv3 --pmc: tune, a marker copy, a few steps, a marker copy")
+                    help="short run for rocprofv3 --pmc: tune, a marker copy, the per-kernel profile phase, a marker copy")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON", "COMMAND"),
+                    help="write the per-phase kernel time summary of a rocprofv3 --kernel-trace run (markdown)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_JSON"),
                     help="write the HBM-traffic summary of two --pmc runs of --pmc-probe (markdown, stdout)")
     return ap.parse_args()
@@ -80,7 +82,9 @@ def source_hash():
 def tile_key(tuning):
     if not tuning:
         return None
-    return [{k: t.get(k) for k in ("grid", "Wx", "x_stage", "path", "Wy", "TW", "TK")} for t in tuning]
+    # the per-kernel profile runs the whole batch with the first part's choices
+    return [{k: t.get(k) for k in ("grid", "Wx", "x_stage", "path", "Wy", "TW", "TK")}
+            for t in tuning if t.get("part", 0) == 0]
 
 
 def profile_name(kernel):
@@ -91,7 +95,7 @@ def profile_name(kernel):
     if m:
         return f"{m.group(1)}_{'rk4' if m.group(2) == '0' else 'dp45'}_{m.group(3)}" \
             if not (m.group(1) == "stage" and m.group(2) == "0" and m.group(3) == "0") else "stage_rk4_start"
-    if k.startswith("mmk::k_fft_yzr<"):
+    if k.startswith("mmk::k_fft_yzr<") or k.startswith("mmk::k_fft_yz8<"):
         return "fft_yz_convolve"
     table = {"mmk::k_fft_yz": "fft_yz_convolve", "mmk::k_fft_zc": "fft_z_convolve",
              "mmk::k_fft_y<-1>": "fft_y_forward", "mmk::k_fft_y<1>": "fft_y_inverse"}
@@ -104,7 +108,67 @@ def profile_name(kernel):
     return None
 
 
+def mark():
+    """A tiny elementwise kernel between two synchronisations: marks phase
+    boundaries (timed steps, per-kernel profile) in a kernel trace."""
+    import torch
+    torch.cuda.synchronize()
+    torch.mul(torch.ones(1024, device="cuda"), 2.0)
+    torch.cuda.synchronize()
+
+
+def summarize_trace(trace_csv, bench_json, command):
+    """Per-kernel durations of a rocprofv3 kernel trace of the benchmark,
+    split by the phase markers: the timed steps and the profile phase (whose
+    averages are the ones the JSON line's kernels and roofline use)."""
+    import csv
+    rows = []
+    with open(trace_csv) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+    marks = [i for i, r in enumerate(rows) if "MulFunctor" in r[2]]
+    if len(marks) < 4:
+        raise SystemExit(f"{trace_csv}: expected four phase markers, found {len(marks)}")
+    with open(bench_json) as f:
+        out = json.loads(f.read().strip().splitlines()[-1])
+    bench_us = {k["name"]: k["avg_us"] for k in out.get("kernels", [])}
+
+    def table(lo, hi, with_bench):
+        per = {}
+        for s0, s1, k in rows[lo + 1:hi]:
+            per.setdefault(k.split("(")[0], []).append((s1 - s0) / 1e3)
+        tot = sum(sum(v) for v in per.values())
+        extra = " avg us in the JSON line |" if with_bench else ""
+        print("| kernel | calls | avg us | total ms | % of phase kernel time |" + extra)
+        print("|---|---|---|---|---|" + ("---|" if with_bench else ""))
+        for k in sorted(per, key=lambda k: -sum(per[k])):
+            v = per[k]
+            b = bench_us.get(profile_name(k) or "", None)
+            col = (f" {'' if b is None else f'{b:.1f}'} |") if with_bench else ""
+            print(f"| `{k}` | {len(v)} | {sum(v) / len(v):.1f} | {sum(v) / 1e3:.3f} | {100 * sum(v) / tot:.1f} |" + col)
+        span = (rows[hi][0] - rows[lo][1]) / 1e3
+        print(f"\nPhase wall time between the markers: {span / 1e3:.2f} ms; summed kernel time {tot / 1e3:.2f} ms.\n")
+
+    print("# Kernel time: field sweep, 64 x 32^3 spheres, FFT demag on 64^3, DP45 tol 1e-6\n")
+    print("Command (from the repository root, one MI355X):\n")
+    print("```\n" + command + "\n```\n")
+    print(f"Bench line of this run: {out['ms_per_step']:.4f} ms per step, value {out['value']:.4g} "
+          f"{out['unit']}, {out['config'].get('streams')} concurrent sub-batches, FFT tiles "
+          f"{json.dumps(out['config'].get('fft_tiles'))}.\n")
+    print(f"## Timed steps ({out['steps']} DP45 steps of the batch, graphs on the sub-batch streams)\n")
+    print("Kernels of different sub-batches overlap here, so a kernel's duration includes the "
+          "time it shares the device.\n")
+    table(marks[0], marks[1], False)
+    print(f"## Per-kernel profile phase (whole batch, eager launches, one kernel at a time)\n")
+    print("The JSON line's kernel table and roofline are measured in this phase with HIP events on the "
+          "library stream; the last column repeats them.\n")
+    table(marks[2], marks[3], True)
+
+
 def pmc_probe(args):
+    """Between two marker copies: the per-kernel profile phase of the
+    benchmark (the whole batch, eager launches, the tuned FFT choices)."""
     import torch
     insts, ctxs, batch = build_batch(args.instances, args.tol)
     tuning = None if args.no_tune else batch.tune()
@@ -114,7 +178,7 @@ def pmc_probe(args):
     torch.cuda.synchronize()
     torch.mul(src, 2.0, out=dst)
     torch.cuda.synchronize()
-    batch.step(args.profile_steps, args.tol)
+    batch.profile(args.profile_steps, args.tol)
     torch.cuda.synchronize()
     torch.mul(src, 2.0, out=dst)
     torch.cuda.synchronize()
@@ -158,7 +222,8 @@ def summarize_pmc(fetch_csv, write_csv, probe_json):
     print(f"Calibration: an elementwise float32 copy of {mb} bytes (read {mb}, write {mb}) reads "
           f"FETCH_SIZE {f0:.0f} / {f1:.0f} KiB and WRITE_SIZE {w0:.0f} / {w1:.0f} KiB; scale factors "
           f"{ff:.4f} (fetch) and {fw:.4f} (write).\n")
-    print(f"Kernels between the two markers ({probe['steps']} DP45 steps of the batch), per dispatch:\n")
+    print(f"Kernels between the two markers (the per-kernel profile phase: {probe['steps']} eager DP45 steps "
+          "of the whole batch), per dispatch:\n")
     print("| kernel | dispatches | FETCH KiB | WRITE KiB | HBM bytes (scaled) |")
     print("|---|---|---|---|---|")
     out = {}
@@ -302,6 +367,8 @@ def afm_batch(steps, tol):
     insts = [W.afm_instance(k) for k in range(32)]
     ctxs = [mmcav.Context.from_instance(i) for i in insts]
     b = mmcav.Batch(ctxs)
+    b.tune()
+    streams = b.streams()
     b.step(10, tol)
     dt, acc = timed_steps(b, ctxs, steps, tol)
     cells = sum(i.cells * 2 for i in insts)
@@ -316,7 +383,7 @@ def afm_batch(steps, tol):
     for c in ctxs:
         c.close()
     return {"workload": "AFM batch: 32 instances, 64^2x16 .. 256^2x16, 2 sublattices, 2 nm, DP45 tol 1e-6",
-            "sublattice_cells": cells, "batched_s": dt, "plain_sequential_s": plain,
+            "sublattice_cells": cells, "streams": streams, "batched_s": dt, "plain_sequential_s": plain,
             "batched_vs_plain": plain / dt, "batched_cell_updates_per_s": cells * acc / len(insts) / dt}
 
 
@@ -361,6 +428,9 @@ def cpu_baseline(inst, seconds, tol):
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return
@@ -386,7 +456,9 @@ def main():
     batch.step(args.warmup, args.tol)
     torch.cuda.synchronize()
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    mark()
     dt, acc = timed_steps(batch, ctxs, args.steps, args.tol)
+    mark()
     rate = cells / len(insts) * acc / dt
     st0 = ctxs[0].stats()
     print(f"[bench] {dt:.3f} s, {acc} accepted instance-steps, dt now {st0['dt']:.3e} s", file=sys.stderr, flush=True)
@@ -394,7 +466,9 @@ def main():
     roof = None
     kernels = []
     if not args.no_profile:
+        mark()
         prof = batch.profile(args.profile_steps, args.tol)
+        mark()
         for p in prof:
             avg_ms = p["total_ms"] / max(1, p["launches"])
             gbs = p["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
@@ -458,6 +532,7 @@ def main():
                                f"FFT demag on 64^3, 1 uniform mode, DP45 tol {args.tol:g}, batched",
                    "instances": len(insts), "grid": [32, 32, 32], "method": "dp45", "tol": args.tol,
                    "accepted_fraction": acc / (args.steps * len(insts)),
+                   "streams": batch.streams(),
                    "fft_tiles": tile_key(tuning)},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -168,8 +168,20 @@ mm_status mm_set_state(mm_ctx* ctx, const void* blob, size_t bytes);
 /* Group count >= 1 contexts (all with modes set and the same method).  The
  * contexts stay owned by the caller and must outlive the batch.  Each
  * instance keeps its own t, dt, status and trace; one launch sequence
- * (captured in a HIP graph) advances all of them. */
+ * (captured in a HIP graph) advances all of them.  The batch may instead
+ * run as sub-batches of about equal cell count, each with its own stream and
+ * graphs, whose launch sequences the device runs concurrently, so that the
+ * last, partly filled round of workgroups of one kernel overlaps another
+ * part's next kernel (mm_batch_set_streams, or chosen by timing in
+ * mm_batch_tune).  An instance's arithmetic does not depend on the split. */
 mm_status mm_batch_create(mm_ctx* const* ctxs, int32_t count, mm_batch** out);
+/* Re-split the batch into `parts` sub-batches (1..8, at most the instance
+ * count; 1 = one launch sequence for all).  Waits for the batch's streams;
+ * FFT strategy choices (mm_batch_tune, mm_batch_set_fft_*) return to their
+ * defaults.  The handle stays valid.  MM_ERR_ARG for parts out of range. */
+mm_status mm_batch_set_streams(mm_batch* b, int32_t parts);
+/* Number of sub-batches the batch runs as. */
+mm_status mm_batch_get_streams(const mm_batch* b, int32_t* parts);
 /* Advance every instance by T (tol as in mm_run).  Returns the first
  * non-OK instance status, or MM_OK; per-instance status in mm_get_stats. */
 mm_status mm_batch_run(mm_batch* b, double T, double tol);
@@ -178,11 +190,15 @@ mm_status mm_batch_run(mm_batch* b, double T, double tol);
 mm_status mm_batch_step(mm_batch* b, int64_t steps, double tol);
 mm_status mm_batch_destroy(mm_batch* b);
 
-/* Autotune the demag FFT of every grid shape in the batch: times the x
- * passes for each tile width and the y-z work either fused in one LDS-resident
- * kernel or split into y / z passes for each tile shape, on the current
- * state, and keeps the fastest.  The state is not advanced.  A JSON summary
- * of the timings and choices is written to report (may be NULL). */
+/* Autotune the batch.  With two or more instances it first times whole
+ * steps (32 + 2 x 64 attempted steps) of the batch run as 1, 2 and 3
+ * concurrent sub-batches (mm_batch_set_streams) and keeps the fastest; then,
+ * in every sub-batch, the demag FFT of every grid shape: the x passes for
+ * each tile width and the y-z work either fused in one LDS-resident kernel or
+ * split into y / z passes for each tile shape, keeping the fastest.  Every
+ * instance's state (and trace, counters, statistics) is left as it was.  A
+ * JSON list of the choices and timings, one entry per grid shape and
+ * sub-batch ("part": its index), is written to report (may be NULL). */
 mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len);
 
 /* Demag y-z strategy for every FFT grid shape in the batch (mm_batch_tune
@@ -215,7 +231,9 @@ enum { MM_X_LDS = 0, MM_X_REGISTER = 1, MM_X_STAGE = 2 };
 mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path);
 
 /* Per-kernel timing: run `steps` steps eagerly, timing each launch with HIP
- * events on the library stream.  Fills up to `cap` entries: names (each
+ * events on the library stream (for a split batch: the whole batch as one
+ * launch sequence with the FFT strategies of its first part, each kernel
+ * alone on the device).  Fills up to `cap` entries: names (each
  * char[48]), launches, total milliseconds, algorithmic bytes per launch
  * (the bytes a launch must read and write; see the kernel notes).  *n is
  * set to the number of kernel kinds. */

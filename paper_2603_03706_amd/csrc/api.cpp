@@ -31,6 +31,9 @@ mm_status fail(mm_status s, const std::string& msg) {
 
 constexpr double kMu0 = 4e-7 * M_PI;
 constexpr int kStepsPerGraph = 32;
+// Sub-batches (streams) a new batch runs as; mm_batch_tune may choose more.
+constexpr int kDefaultParts = 1;
+constexpr int kMaxTunedParts = 3;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -307,6 +310,10 @@ struct mm_batch {
   std::vector<Prof> prof;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<int> pending_idx;
+  // Non-empty: this batch only dispatches to sub-batches over disjoint sets
+  // of its instances, each with its own stream, tables and graphs, whose
+  // launch sequences the device runs concurrently.
+  std::vector<mm_batch*> parts;
 };
 
 namespace {
@@ -893,6 +900,123 @@ mm_status new_batch(mm_ctx* const* ctxs, int count, mm_batch** out) {
   return MM_OK;
 }
 
+// Work of one instance for the partition below: cells times sublattices.
+double inst_cells(const mm_ctx* c) { return (double)c->L.ncell * c->p.sublattices; }
+
+// A batch of `parts` sub-batches (parts >= 2) whose cell counts are as even
+// as a greedy assignment (largest instance first, to the lightest part) makes
+// them; each part keeps the instances in batch order.
+mm_status new_split_batch(mm_ctx* const* ctxs, int count, int parts, mm_batch** out) {
+  auto* b = new mm_batch();
+  b->ctxs.assign(ctxs, ctxs + count);
+  b->method = ctxs[0]->method;
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int c) { return inst_cells(ctxs[a]) > inst_cells(ctxs[c]); });
+  std::vector<double> load(parts, 0.0);
+  std::vector<std::vector<int>> sets(parts);
+  for (int i : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    sets[k].push_back(i);
+    load[k] += inst_cells(ctxs[i]);
+  }
+  for (auto& set : sets) {
+    std::sort(set.begin(), set.end());
+    std::vector<mm_ctx*> sub;
+    for (int i : set) sub.push_back(ctxs[i]);
+    mm_batch* part = nullptr;
+    if (mm_status s = new_batch(sub.data(), (int)sub.size(), &part)) {
+      mm_batch_destroy(b);
+      return s;
+    }
+    b->parts.push_back(part);
+  }
+  *out = b;
+  return MM_OK;
+}
+
+mm_status make_batch(mm_ctx* const* ctxs, int count, int parts, mm_batch** out) {
+  parts = std::min(parts, count);
+  return parts <= 1 ? new_batch(ctxs, count, out) : new_split_batch(ctxs, count, parts, out);
+}
+
+// Run every part to its end time (T as in batch_run), the parts' graphs
+// launched round-robin so that their streams overlap.
+mm_status parts_run(mm_batch* b, double T, double tol) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (mm_batch* p : b->parts) {
+    if (mm_status s = begin_run(p, T, tol)) return s;
+    if (mm_status s = ensure_graph(p)) return s;
+  }
+  std::vector<mm_batch*> active = b->parts;
+  while (!active.empty()) {
+    for (mm_batch* p : active) {
+      const int n = (int)p->ctxs.size();
+      MM_HIP(hipGraphLaunch(p->exec, p->stream));
+      MM_HIP(mmk_launch_gather_done(n, p->d_desc, p->d_flags, p->stream));
+      MM_HIP(hipMemcpyAsync(p->h_flags, p->d_flags, sizeof(int) * 2 * n, hipMemcpyDeviceToHost, p->stream));
+    }
+    std::vector<mm_batch*> still;
+    for (mm_batch* p : active) {
+      MM_HIP(hipStreamSynchronize(p->stream));
+      bool all = true;
+      for (size_t i = 0; i < p->ctxs.size(); ++i) all = all && p->h_flags[2 * i] != 0;
+      if (!all) still.push_back(p);
+    }
+    active.swap(still);
+  }
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  mm_status first = MM_OK;
+  for (mm_batch* p : b->parts) {
+    const mm_status s = end_run(p, wall);
+    if (s != MM_OK && first == MM_OK) first = s;
+  }
+  return first;
+}
+
+// Exactly `steps` attempted steps of every part, interleaved per graph.
+mm_status parts_step(mm_batch* b, int64_t steps, double tol) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (mm_batch* p : b->parts) {
+    if (mm_status s = begin_run(p, -1.0, tol)) return s;
+    if (mm_status s = ensure_graph(p)) return s;
+  }
+  int64_t left = steps;
+  for (; left >= kStepsPerGraph; left -= kStepsPerGraph)
+    for (mm_batch* p : b->parts) MM_HIP(hipGraphLaunch(p->exec, p->stream));
+  for (; left > 0; --left)
+    for (mm_batch* p : b->parts)
+      if (mm_status s = enqueue_step(p)) return s;
+  for (mm_batch* p : b->parts) MM_HIP(hipStreamSynchronize(p->stream));
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  mm_status first = MM_OK;
+  for (mm_batch* p : b->parts) {
+    const mm_status s = end_run(p, wall);
+    if (s != MM_OK && first == MM_OK) first = s;
+  }
+  return first;
+}
+
+// FFT strategy of `src`'s groups copied to the groups of `dst` with the same
+// grid shape (and the work tables rebuilt).
+mm_status copy_fft_settings(mm_batch* dst, const mm_batch* src) {
+  for (auto& g : dst->groups)
+    for (const auto& h : src->groups)
+      if (g.nx == h.nx && g.ny == h.ny && g.nz == h.nz && g.px == h.px && g.py == h.py && g.pz == h.pz) {
+        g.path = h.path;
+        g.xfused = h.xfused;
+        g.Wx = h.Wx;
+        g.Wy = h.Wy;
+        g.TW = h.TW;
+        g.TK = h.TK;
+        if (mm_status s = build_group(g)) return s;
+        break;
+      }
+  batch_xfused(dst);
+  return upload_batch_descs(dst);
+}
+
 double algorithmic_bytes(const mm_batch* b, const std::string& name) {
   double total = 0.0;
   if (name.rfind("final_", 0) == 0) {
@@ -1474,7 +1598,26 @@ mm_status mm_batch_create(mm_ctx* const* ctxs, int32_t count, mm_batch** out) {
       if (ctxs[j] == ctxs[i]) return fail(MM_ERR_ARG, "a context appears twice in the batch");
   }
   if (mm_status s = set_device(ctxs[0])) return s;
-  return new_batch(ctxs, count, out);
+  return make_batch(ctxs, count, kDefaultParts, out);
+}
+
+mm_status mm_batch_set_streams(mm_batch* b, int32_t parts) {
+  if (!b) return fail(MM_ERR_ARG, "batch is NULL");
+  if (parts < 1 || parts > 8) return fail(MM_ERR_ARG, "parts must be 1..8");
+  if (mm_status s = set_device(b->ctxs[0])) return s;
+  for (mm_batch* p : b->parts) MM_HIP(hipStreamSynchronize(p->stream));
+  if (b->stream) MM_HIP(hipStreamSynchronize(b->stream));
+  mm_batch* nb = nullptr;
+  if (mm_status s = make_batch(b->ctxs.data(), (int)b->ctxs.size(), parts, &nb)) return s;
+  // the handle stays valid: it takes the new contents, the old ones are freed
+  std::swap(*b, *nb);
+  return mm_batch_destroy(nb);
+}
+
+mm_status mm_batch_get_streams(const mm_batch* b, int32_t* parts) {
+  if (!b || !parts) return fail(MM_ERR_ARG, "bad arguments");
+  *parts = b->parts.empty() ? 1 : (int32_t)b->parts.size();
+  return MM_OK;
 }
 
 mm_status mm_batch_run(mm_batch* b, double T, double tol) {
@@ -1484,6 +1627,7 @@ mm_status mm_batch_run(mm_batch* b, double T, double tol) {
   for (mm_ctx* c : b->ctxs)
     if (c->method != b->method) return fail(MM_ERR_STATE, "instance method changed after batch creation");
   if (mm_status s = set_device(b->ctxs[0])) return s;
+  if (!b->parts.empty()) return parts_run(b, T, tol);
   return batch_run(b, T, tol);
 }
 
@@ -1491,6 +1635,7 @@ mm_status mm_batch_step(mm_batch* b, int64_t steps, double tol) {
   if (!b || steps < 0) return fail(MM_ERR_ARG, "bad arguments");
   if (mm_status s = validate_tol(b, tol)) return s;
   if (mm_status s = set_device(b->ctxs[0])) return s;
+  if (!b->parts.empty()) return parts_step(b, steps, tol);
   const auto t0 = std::chrono::steady_clock::now();
   if (mm_status s = begin_run(b, -1.0, tol)) return s;
   if (mm_status s = ensure_graph(b)) return s;
@@ -1506,10 +1651,11 @@ mm_status mm_batch_step(mm_batch* b, int64_t steps, double tol) {
   return end_run(b, wall);
 }
 
-mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path) {
-  if (!b) return fail(MM_ERR_ARG, "batch is NULL");
+static mm_status check_fft_path(const mm_batch* b, int32_t path) {
   if (path != PATH_FUSED && path != PATH_REG && path != PATH_SPLIT && path != PATH_REG8)
     return fail(MM_ERR_ARG, "unknown y-z path");
+  for (const mm_batch* p : b->parts)
+    if (mm_status s = check_fft_path(p, path)) return s;
   for (auto& g : b->groups) {
     if (path == PATH_REG && !reg_fits(g.ny, g.nz, g.py, g.pz))
       return fail(MM_ERR_ARG, "register y-z path needs padded y in 16..128 and padded z in 16..64");
@@ -1518,6 +1664,15 @@ mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path) {
     if (path == PATH_FUSED && !fused_fits(g.ny, g.nz, g.py, g.pz))
       return fail(MM_ERR_ARG, "fused y-z path does not fit in LDS for this grid");
   }
+  return MM_OK;
+}
+
+mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path) {
+  if (!b) return fail(MM_ERR_ARG, "batch is NULL");
+  if (mm_status s = check_fft_path(b, path)) return s;
+  for (mm_batch* p : b->parts)
+    if (mm_status s = mm_batch_set_fft_path(p, path)) return s;
+  if (!b->parts.empty()) return MM_OK;
   MM_HIP(hipStreamSynchronize(b->stream));
   for (auto& g : b->groups) {
     g.path = path;
@@ -1531,9 +1686,10 @@ mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path) {
   return MM_OK;
 }
 
-mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path) {
-  if (!b) return fail(MM_ERR_ARG, "batch is NULL");
+static mm_status check_fft_x(const mm_batch* b, int32_t path) {
   if (path != MM_X_LDS && path != MM_X_REGISTER && path != MM_X_STAGE) return fail(MM_ERR_ARG, "unknown x path");
+  for (const mm_batch* p : b->parts)
+    if (mm_status s = check_fft_x(p, path)) return s;
   for (auto& g : b->groups) {
     if (path == MM_X_REGISTER && !xreg_fits(g.px))
       return fail(MM_ERR_ARG, "register x path needs a padded x of 16..128 cells");
@@ -1543,6 +1699,15 @@ mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path) {
       for (int m : g.members)
         if (b->ctxs[m]->p.sublattices != 1) return fail(MM_ERR_ARG, "x passes in the stage kernels need one sublattice");
   }
+  return MM_OK;
+}
+
+mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path) {
+  if (!b) return fail(MM_ERR_ARG, "batch is NULL");
+  if (mm_status s = check_fft_x(b, path)) return s;
+  for (mm_batch* p : b->parts)
+    if (mm_status s = mm_batch_set_fft_x(p, path)) return s;
+  if (!b->parts.empty()) return MM_OK;
   MM_HIP(hipStreamSynchronize(b->stream));
   for (auto& g : b->groups) {
     g.xfused = path == MM_X_STAGE;
@@ -1563,6 +1728,18 @@ mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, 
   if (!b || !n || steps < 0 || cap < 0) return fail(MM_ERR_ARG, "bad arguments");
   if (mm_status s = validate_tol(b, tol)) return s;
   if (mm_status s = set_device(b->ctxs[0])) return s;
+  if (!b->parts.empty()) {
+    // kernels of the whole batch as one launch sequence, one at a time, with
+    // the FFT strategies the parts use
+    for (mm_batch* p : b->parts) MM_HIP(hipStreamSynchronize(p->stream));
+    mm_batch* whole = nullptr;
+    if (mm_status s = new_batch(b->ctxs.data(), (int)b->ctxs.size(), &whole)) return s;
+    mm_status s = copy_fft_settings(whole, b->parts[0]);
+    if (s == MM_OK)
+      s = mm_batch_profile(whole, steps, tol, cap, names, launches, total_ms, bytes_per_launch, n);
+    mm_batch_destroy(whole);
+    return s;
+  }
   b->prof.clear();
   if (mm_status s = begin_run(b, -1.0, tol)) return s;
   MM_HIP(hipStreamSynchronize(b->stream));
@@ -1598,9 +1775,125 @@ mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, 
   return MM_OK;
 }
 
+// Insert `fields` (JSON members) at the start of every top-level object of
+// the JSON list `list`.
+static std::string add_to_entries(const std::string& list, const std::string& fields) {
+  std::string out;
+  int depth = 0;
+  for (char ch : list) {
+    out += ch;
+    if (ch == '{') {
+      if (depth == 1) out += fields + ", ";
+      ++depth;
+    } else if (ch == '[') {
+      ++depth;
+    } else if (ch == ']' || ch == '}') {
+      --depth;
+    }
+  }
+  return out;
+}
+
+// Everything of a context that a timed run changes: the control block, the
+// state vector it points to and the host-side run bookkeeping.
+struct SavedRun {
+  InstCtl h;
+  std::vector<char> y;
+  mm_stats stats;
+  bool sampling_changed;
+  int record_next;
+};
+
+static mm_status save_run(mm_ctx* c, SavedRun& sv) {
+  if (mm_status s = ctl_pull(c, sv.h)) return s;
+  sv.y.resize(sizeof(float) * 3 * c->p.sublattices * (size_t)c->L.ncell);
+  MM_HIP(hipMemcpy(sv.y.data(), c->ws + c->L.y[sv.h.cur], sv.y.size(), hipMemcpyDeviceToHost));
+  sv.stats = c->stats;
+  sv.sampling_changed = c->sampling_changed;
+  sv.record_next = c->record_next;
+  return MM_OK;
+}
+
+static mm_status restore_run(mm_ctx* c, const SavedRun& sv) {
+  if (mm_status s = ctl_push(c, sv.h)) return s;
+  MM_HIP(hipMemcpy(c->ws + c->L.y[sv.h.cur], sv.y.data(), sv.y.size(), hipMemcpyHostToDevice));
+  c->stats = sv.stats;
+  c->sampling_changed = sv.sampling_changed;
+  c->record_next = sv.record_next;
+  return MM_OK;
+}
+
+// Choose how many concurrent sub-batches (1 .. kMaxTunedParts) the batch
+// runs as by timing whole steps of each candidate partition; the fastest one
+// (the very object timed, so its streams stay as measured) replaces b's
+// contents.  Every instance's state is restored afterwards.
+static mm_status tune_streams(mm_batch* b, std::string& rep) {
+  const int count = (int)b->ctxs.size();
+  std::vector<SavedRun> saved(count);
+  for (int i = 0; i < count; ++i)
+    if (mm_status s = save_run(b->ctxs[i], saved[i])) return s;
+  const double tol = saved[0].h.tol > 0 ? saved[0].h.tol : 1e-6;
+  std::vector<mm_batch*> cand;
+  std::vector<double> ms;
+  mm_status st = MM_OK;
+  for (int parts = 1; parts <= std::min(kMaxTunedParts, count) && st == MM_OK; ++parts) {
+    mm_batch* c = nullptr;
+    st = make_batch(b->ctxs.data(), count, parts, &c);
+    if (st != MM_OK) break;
+    cand.push_back(c);
+    double best = 1e300;
+    st = mm_batch_step(c, kStepsPerGraph, tol);    // captures the graphs
+    for (int rep_i = 0; rep_i < 2 && st == MM_OK; ++rep_i) {
+      const auto t0 = std::chrono::steady_clock::now();
+      st = mm_batch_step(c, 2 * kStepsPerGraph, tol);
+      best = std::min(best, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    }
+    ms.push_back(best * 1e3 / (2 * kStepsPerGraph));
+    for (int i = 0; i < count && st == MM_OK; ++i) st = restore_run(b->ctxs[i], saved[i]);
+  }
+  if (st == MM_OK) {
+    const int k = (int)(std::min_element(ms.begin(), ms.end()) - ms.begin());
+    std::swap(*b, *cand[k]);
+    rep = "\"streams_ms_per_step\": [";
+    for (size_t i = 0; i < ms.size(); ++i) rep += (i ? ", " : "") + std::to_string(ms[i]);
+    rep += "], \"streams\": " + std::to_string(k + 1);
+  }
+  for (mm_batch* c : cand) mm_batch_destroy(c);   // the chosen slot now holds b's old contents
+  if (st != MM_OK)
+    for (int i = 0; i < count; ++i) restore_run(b->ctxs[i], saved[i]);
+  return st;
+}
+
+static mm_status tune_fft(mm_batch* b, std::string& rep);
+
 mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
   if (!b) return fail(MM_ERR_ARG, "NULL batch");
   if (mm_status s = set_device(b->ctxs[0])) return s;
+  std::string srep;
+  if (b->ctxs.size() >= 2)
+    if (mm_status s = tune_streams(b, srep)) return s;
+  // each part tunes its own launches; the reports are joined into one list
+  std::string all;
+  std::vector<mm_batch*> leaves = b->parts;
+  if (leaves.empty()) leaves.push_back(b);
+  for (size_t k = 0; k < leaves.size(); ++k) {
+    std::string r;
+    if (mm_status s = tune_fft(leaves[k], r)) return s;
+    r = add_to_entries(r, "\"part\": " + std::to_string(k));
+    if (r.size() >= 2) r = r.substr(1, r.size() - 2);
+    if (!r.empty()) all += (all.empty() ? "" : ", ") + r;
+  }
+  all = "[" + all + "]";
+  if (!srep.empty()) all = add_to_entries(all, srep);
+  if (report && report_len) {
+    std::strncpy(report, all.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return MM_OK;
+}
+
+// FFT tiles and paths of one launch sequence (a batch without parts).
+static mm_status tune_fft(mm_batch* b, std::string& out) {
   // make every instance runnable without touching its state
   for (mm_ctx* c : b->ctxs) {
     InstCtl h;
@@ -1735,16 +2028,14 @@ mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
   if (b->exec_rev) { hipGraphExecDestroy(b->exec_rev); b->exec_rev = nullptr; }
   if (b->graph_rev) { hipGraphDestroy(b->graph_rev); b->graph_rev = nullptr; }
   MM_HIP(hipStreamSynchronize(b->stream));
-  if (report && report_len) {
-    std::strncpy(report, rep.c_str(), report_len - 1);
-    report[report_len - 1] = 0;
-  }
+  out = rep;
   return MM_OK;
 }
 
 mm_status mm_batch_destroy(mm_batch* b) {
   if (!b) return MM_OK;
   if (!b->ctxs.empty()) hipSetDevice(b->ctxs[0]->dev);
+  for (mm_batch* p : b->parts) mm_batch_destroy(p);
   if (b->exec) hipGraphExecDestroy(b->exec);
   if (b->graph) hipGraphDestroy(b->graph);
   if (b->exec_rev) hipGraphExecDestroy(b->exec_rev);

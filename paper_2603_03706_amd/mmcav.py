@@ -74,6 +74,8 @@ _SIGS = {
     "mm_batch_tune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
     "mm_batch_set_fft_path": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_batch_set_fft_x": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "mm_batch_set_streams": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "mm_batch_get_streams": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "mm_run_record": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32]),
     "mm_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "mm_demag_tensor": (ctypes.c_int, [ctypes.c_double] * 6 + [_P]),
@@ -300,6 +302,15 @@ class Batch:
     def set_fft_x(self, path):
         """Force the x-pass strategy ("lds", "reg" or "stage") for every grid shape."""
         _check(self._lib.mm_batch_set_fft_x(self.h, {"lds": 0, "reg": 1, "stage": 2}[path]))
+
+    def set_streams(self, parts):
+        """Run the batch as `parts` concurrent sub-batches (1 = one launch sequence)."""
+        _check(self._lib.mm_batch_set_streams(self.h, int(parts)))
+
+    def streams(self):
+        n = ctypes.c_int32()
+        _check(self._lib.mm_batch_get_streams(self.h, ctypes.byref(n)))
+        return n.value
 
     def profile(self, steps, tol=0.0, cap=32):
         names = ctypes.create_string_buffer(48 * cap)

@@ -226,6 +226,41 @@ def test_batched_equals_plain_bitwise():
     b.close()
 
 
+def test_batch_streams_bitwise():
+    """Splitting a batch into concurrent sub-batches (streams) changes no
+    instance's arithmetic: states, amplitudes and traces are bit-identical
+    for 1, 2 and 3 parts, on a batch mixing two grid shapes."""
+    from paper_2603_03706_amd import mmcav
+    insts = [W.sweep_sphere(k, count=5, n=8 if k % 2 else 12) for k in range(5)]
+    out = {}
+    for parts in (1, 2, 3):
+        ctxs = [gpu_for(inst) for inst in insts]
+        for c in ctxs:
+            c.set_sampling(10e-12, 1000)
+        b = mmcav.Batch(ctxs)
+        assert b.streams() == 1
+        b.set_streams(parts)
+        assert b.streams() == parts
+        b.run(0.2e-9, 1e-6)
+        b.step(3, 1e-6)
+        out[parts] = [(c.get_m(), c.get_a(), c.get_trace(1000), c.stats()["accepted"]) for c in ctxs]
+        b.close()
+        for c in ctxs:
+            c.close()
+    for parts in (2, 3):
+        for (m, a, tr, acc), (m1, a1, tr1, acc1) in zip(out[parts], out[1]):
+            assert acc == acc1
+            assert np.array_equal(m, m1) and np.array_equal(a, a1)
+            assert all(np.array_equal(x, y) for x, y in zip(tr, tr1))
+    c = gpu_for(insts[0])
+    b = mmcav.Batch([c])
+    assert b.streams() == 1
+    for bad in (0, 9):
+        with pytest.raises(mmcav.MMError):
+            b.set_streams(bad)
+    b.close()
+
+
 def test_deterministic_and_resume_bitwise():
     inst = W.sweep_sphere(10, count=16, n=8)
     runs = []
@@ -299,15 +334,25 @@ def test_tuned_batch_keeps_parity():
         inst.method, inst.dt0 = "rk4", 0.2e-12
     ref = [gpu_for(i) for i in insts]
     b0 = mmcav.Batch(ref)
-    b0.run(20e-12)
     ctxs = [gpu_for(i) for i in insts]
+    for c in ctxs + ref:
+        c.set_sampling(5e-12, 100)
+    b0.run(20e-12)
     b1 = mmcav.Batch(ctxs)
+    m0 = [c.get_m() for c in ctxs]
     rep = b1.tune()
-    assert len(rep) == 1 and rep[0]["path"] in ("fused", "reg", "reg8", "split")
-    assert all(c.stats()["accepted"] == 0 for c in ctxs)
+    assert len(rep) == b1.streams() and all(r["path"] in ("fused", "reg", "reg8", "split") for r in rep)
+    assert all(r["streams"] == b1.streams() and len(r["streams_ms_per_step"]) == 3 for r in rep)
+    # the timed steps of the tuner leave no trace: state, counters, samples
+    assert all(c.stats()["accepted"] == 0 and c.stats()["t"] == 0.0 for c in ctxs)
+    assert all(np.array_equal(c.get_m(), m) for c, m in zip(ctxs, m0))
+    assert all(len(c.get_trace(100)[0]) == 0 for c in ctxs)
     b1.run(20e-12)
     for c, r in zip(ctxs, ref):
         assert np.abs(c.get_m() - r.get_m()).max() <= 2e-6
+        t1, a1, _ = c.get_trace(100)
+        t0, a0, _ = r.get_trace(100)
+        assert np.array_equal(t1, t0) and np.abs(a1 - a0).max() <= 1e-5 * np.abs(a0).max()
     st = oracle_for(insts[1])
     run_oracle(st, 20e-12)
     assert m_err(ctxs[1].get_m(), st) <= 2e-5
