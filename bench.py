@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="run the sweep batch as this many concurrent sub-batches instead of timing 1..3 "
+                         "in the tuner (profiler runs use it to keep the plain run's choice)")
     ap.add_argument("--no-afm", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=512)
     ap.add_argument("--afm-steps", type=int, default=20)
@@ -171,7 +174,9 @@ def pmc_probe(args):
     benchmark (the whole batch, eager launches, the tuned FFT choices)."""
     import torch
     insts, ctxs, batch = build_batch(args.instances, args.tol)
-    tuning = None if args.no_tune else batch.tune()
+    if args.streams:
+        batch.set_streams(args.streams)
+    tuning = None if args.no_tune else batch.tune(streams=not args.streams)
     batch.step(3, args.tol)
     src = torch.ones(MARKER_ELEMS, device="cuda")
     dst = torch.empty_like(src)
@@ -449,8 +454,10 @@ def main():
     insts, ctxs, batch = build_batch(args.instances, args.tol)
     cells = sum(i.cells for i in insts)
     tuning = None
+    if args.streams:
+        batch.set_streams(args.streams)
     if not args.no_tune:
-        tuning = batch.tune()
+        tuning = batch.tune(streams=not args.streams)
         print(f"[bench] fft tuning: {json.dumps(tuning)}", file=sys.stderr, flush=True)
     print(f"[bench] {len(insts)} instances, {cells} cells; warmup {args.warmup} steps", file=sys.stderr, flush=True)
     batch.step(args.warmup, args.tol)

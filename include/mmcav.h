@@ -200,6 +200,8 @@ mm_status mm_batch_destroy(mm_batch* b);
  * JSON list of the choices and timings, one entry per grid shape and
  * sub-batch ("part": its index), is written to report (may be NULL). */
 mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len);
+/* The FFT part of mm_batch_tune only: the batch keeps its sub-batch count. */
+mm_status mm_batch_tune_fft(mm_batch* b, char* report, size_t report_len);
 
 /* Demag y-z strategy for every FFT grid shape in the batch (mm_batch_tune
  * chooses one per shape by timing; before that the eight-lane register

@@ -12,7 +12,13 @@
 #include <vector>
 
 #include "mm_host.h"
+#include "launch.h"
 #include "mmcav.h"
+
+hipEvent_t* mm_launch_events() {
+  thread_local hipEvent_t ev[2] = {nullptr, nullptr};
+  return ev;
+}
 
 namespace {
 
@@ -30,6 +36,7 @@ mm_status fail(mm_status s, const std::string& msg) {
   } while (0)
 
 constexpr double kMu0 = 4e-7 * M_PI;
+
 constexpr int kStepsPerGraph = 32;
 // Sub-batches (streams) a new batch runs as; mm_batch_tune may choose more.
 constexpr int kDefaultParts = 1;
@@ -595,11 +602,16 @@ mm_status launch(mm_batch* b, const char* name, F&& f) {
       b->prof.back().bytes = algorithmic_bytes(b, name);
     }
     hipEvent_t e0, e1;
-    MM_HIP(hipEventCreate(&e0));
-    MM_HIP(hipEventCreate(&e1));
-    MM_HIP(hipEventRecord(e0, b->stream));
-    MM_HIP(f());
-    MM_HIP(hipEventRecord(e1, b->stream));
+    MM_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+    MM_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+    // recorded by the runtime at the kernel's own start and end
+    hipEvent_t* ev = mm_launch_events();
+    ev[0] = e0;
+    ev[1] = e1;
+    const hipError_t err = f();
+    ev[0] = nullptr;
+    ev[1] = nullptr;
+    MM_HIP(err);
     b->pending.push_back({e0, e1});
     b->pending_idx.push_back((int)idx);
     return MM_OK;
@@ -1866,12 +1878,24 @@ static mm_status tune_streams(mm_batch* b, std::string& rep) {
 
 static mm_status tune_fft(mm_batch* b, std::string& rep);
 
+static mm_status tune_all_fft(mm_batch* b, const std::string& srep, char* report, size_t report_len);
+
 mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
   if (!b) return fail(MM_ERR_ARG, "NULL batch");
   if (mm_status s = set_device(b->ctxs[0])) return s;
   std::string srep;
   if (b->ctxs.size() >= 2)
     if (mm_status s = tune_streams(b, srep)) return s;
+  return tune_all_fft(b, srep, report, report_len);
+}
+
+mm_status mm_batch_tune_fft(mm_batch* b, char* report, size_t report_len) {
+  if (!b) return fail(MM_ERR_ARG, "NULL batch");
+  if (mm_status s = set_device(b->ctxs[0])) return s;
+  return tune_all_fft(b, "", report, report_len);
+}
+
+static mm_status tune_all_fft(mm_batch* b, const std::string& srep, char* report, size_t report_len) {
   // each part tunes its own launches; the reports are joined into one list
   std::string all;
   std::vector<mm_batch*> leaves = b->parts;

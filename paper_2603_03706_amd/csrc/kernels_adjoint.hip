@@ -21,6 +21,7 @@
 //      to lambda_B, then the RK bookkeeping above.
 #include "mm_internal.h"
 #include "kernels_common.h"
+#include "launch.h"
 
 namespace mmk {
 
@@ -47,11 +48,12 @@ __device__ __forceinline__ void cross3(const float* a, const float* b, float* o)
 // lambda_k4 = h/6 lambda_z.
 __global__ __launch_bounds__(MMI_WG) void k_adj_start(const InstDesc* __restrict__ descs,
                                                       const int* __restrict__ wg_inst) {
-  const InstDesc& D = descs[wg_inst[blockIdx.x]];
+  const int lblk = xcd_block();
+  const InstDesc& D = descs[wg_inst[lblk]];
   const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
   const int nc = D.ncell, S = D.S;
-  const int i = (blockIdx.x - D.wg0) * MMI_WG + threadIdx.x;
+  const int i = (lblk - D.wg0) * MMI_WG + threadIdx.x;
   if (i >= nc) return;
   const bool mag = !D.has_geom || gbl(D.geom)[i];
   const size_t vec = (size_t)3 * S * nc;
@@ -87,10 +89,11 @@ template <int ST>
 __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ descs,
                                                   const int* __restrict__ wg_inst) {
   __shared__ double sh[MMI_WG / 64];
-  const InstDesc& D = descs[wg_inst[blockIdx.x]];
+  const int lblk = xcd_block();
+  const InstDesc& D = descs[wg_inst[lblk]];
   const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
-  const int lw = blockIdx.x - D.wg0;
+  const int lw = lblk - D.wg0;
   const int nc = D.ncell, S = D.S, N = D.N;
   const int i = lw * MMI_WG + threadIdx.x;
   const bool valid = i < nc;
@@ -215,11 +218,12 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
 template <int ST>
 __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ descs,
                                                   const int* __restrict__ wg_inst) {
-  const InstDesc& D = descs[wg_inst[blockIdx.x]];
+  const int lblk = xcd_block();
+  const InstDesc& D = descs[wg_inst[lblk]];
   const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
   const int nc = D.ncell, S = D.S;
-  const int i = (blockIdx.x - D.wg0) * MMI_WG + threadIdx.x;
+  const int i = (lblk - D.wg0) * MMI_WG + threadIdx.x;
   if (i >= nc) return;
   const bool mag = !D.has_geom || gbl(D.geom)[i];
   const int nx = D.nx, ny = D.ny, nz = D.nz;
@@ -360,13 +364,13 @@ hipError_t mmk_launch_adj(int kind, int stage, int nblocks, int count, const Ins
                           hipStream_t s) {
   // kind 0: start, 1: A, 2: B, 3: cavity
   if (kind == 0) {
-    hipLaunchKernelGGL(mmk::k_adj_start, dim3(nblocks), dim3(MMI_WG), 0, s, d, wg);
+    MM_LAUNCH(mmk::k_adj_start, dim3(nblocks), dim3(MMI_WG), 0, s, d, wg);
     return hipGetLastError();
   }
 #define MM_ADJ(K, ST)                                                                                  \
   if (kind == K && stage == ST) {                                                                      \
-    if (K == 1) hipLaunchKernelGGL(mmk::k_adj_a<ST>, dim3(nblocks), dim3(MMI_WG), 0, s, d, wg);        \
-    if (K == 2) hipLaunchKernelGGL(mmk::k_adj_b<ST>, dim3(nblocks), dim3(MMI_WG), 0, s, d, wg);        \
+    if (K == 1) MM_LAUNCH(mmk::k_adj_a<ST>, dim3(nblocks), dim3(MMI_WG), 0, s, d, wg);        \
+    if (K == 2) MM_LAUNCH(mmk::k_adj_b<ST>, dim3(nblocks), dim3(MMI_WG), 0, s, d, wg);        \
     return hipGetLastError();                                                                          \
   }
   MM_ADJ(1, 1) MM_ADJ(1, 2) MM_ADJ(1, 3) MM_ADJ(1, 4)
@@ -374,11 +378,11 @@ hipError_t mmk_launch_adj(int kind, int stage, int nblocks, int count, const Ins
 #undef MM_ADJ
   if (kind == 3) {
     switch (stage) {
-      case 1: hipLaunchKernelGGL(mmk::k_adj_cav<1>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
-      case 2: hipLaunchKernelGGL(mmk::k_adj_cav<2>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
-      case 3: hipLaunchKernelGGL(mmk::k_adj_cav<3>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
-      case 4: hipLaunchKernelGGL(mmk::k_adj_cav<4>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
-      case 5: hipLaunchKernelGGL(mmk::k_adj_cav<5>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 1: MM_LAUNCH(mmk::k_adj_cav<1>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 2: MM_LAUNCH(mmk::k_adj_cav<2>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 3: MM_LAUNCH(mmk::k_adj_cav<3>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 4: MM_LAUNCH(mmk::k_adj_cav<4>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 5: MM_LAUNCH(mmk::k_adj_cav<5>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -151,6 +151,18 @@ __device__ __forceinline__ void field_at(const InstDesc& D, const Src& src, int 
   B[2] = bz;
 }
 
+// The workgroups of one dispatch are placed on the eight XCDs round-robin
+// (block b on XCD b mod 8) and every XCD has its own L2.  This maps the
+// hardware block index to a logical one (a bijection on [0, gridDim.x)) so
+// that each XCD works through one contiguous range of logical blocks: cells
+// that are neighbours in z, two 512-cell workgroups apart, are then read
+// through the same L2 instead of being fetched again by another XCD.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 // max that propagates NaN (a NaN anywhere makes the result NaN)
 __device__ __forceinline__ double nan_max(double a, double b) {
   return (a != a || b != b) ? (a + b) : fmax(a, b);

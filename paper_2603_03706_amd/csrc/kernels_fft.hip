@@ -18,6 +18,7 @@
 // pass is needed between them.
 #include "mm_internal.h"
 #include "kernels_common.h"
+#include "launch.h"
 #include "fft_lds.h"
 #include "stage_final.h"
 
@@ -1017,12 +1018,12 @@ __global__ __launch_bounds__(256) void k_fft_zc(const InstDesc* __restrict__ des
 hipError_t mmk_launch_fft_xf(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              int method, int stage, const float2* tw, hipStream_t s) {
   switch (W) {
-    case 1: hipLaunchKernelGGL(mmk::k_fft_xf<1>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
-    case 2: hipLaunchKernelGGL(mmk::k_fft_xf<2>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
-    case 4: hipLaunchKernelGGL(mmk::k_fft_xf<4>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
-    case 8: hipLaunchKernelGGL(mmk::k_fft_xf<8>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
-    case 16: hipLaunchKernelGGL(mmk::k_fft_xf<16>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
-    case 32: hipLaunchKernelGGL(mmk::k_fft_xf<32>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 1: MM_LAUNCH(mmk::k_fft_xf<1>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 2: MM_LAUNCH(mmk::k_fft_xf<2>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 4: MM_LAUNCH(mmk::k_fft_xf<4>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 8: MM_LAUNCH(mmk::k_fft_xf<8>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 16: MM_LAUNCH(mmk::k_fft_xf<16>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
+    case 32: MM_LAUNCH(mmk::k_fft_xf<32>, dim3(nblocks), dim3(256), lds, s, d, w, method, stage, tw); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1031,12 +1032,12 @@ hipError_t mmk_launch_fft_xf(int W, int nblocks, size_t lds, const InstDesc* d, 
 hipError_t mmk_launch_fft_xi(int W, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              const float2* tw, hipStream_t s) {
   switch (W) {
-    case 1: hipLaunchKernelGGL(mmk::k_fft_xi<1>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
-    case 2: hipLaunchKernelGGL(mmk::k_fft_xi<2>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
-    case 4: hipLaunchKernelGGL(mmk::k_fft_xi<4>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
-    case 8: hipLaunchKernelGGL(mmk::k_fft_xi<8>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
-    case 16: hipLaunchKernelGGL(mmk::k_fft_xi<16>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
-    case 32: hipLaunchKernelGGL(mmk::k_fft_xi<32>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 1: MM_LAUNCH(mmk::k_fft_xi<1>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 2: MM_LAUNCH(mmk::k_fft_xi<2>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 4: MM_LAUNCH(mmk::k_fft_xi<4>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 8: MM_LAUNCH(mmk::k_fft_xi<8>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 16: MM_LAUNCH(mmk::k_fft_xi<16>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
+    case 32: MM_LAUNCH(mmk::k_fft_xi<32>, dim3(nblocks), dim3(256), lds, s, d, w, tw); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1044,13 +1045,13 @@ hipError_t mmk_launch_fft_xi(int W, int nblocks, size_t lds, const InstDesc* d, 
 
 hipError_t mmk_launch_fft_yz(int TK, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              const float2* tw, hipStream_t s) {
-  hipLaunchKernelGGL(mmk::k_fft_yz, dim3(nblocks), dim3(MM_YZ_T), lds, s, d, w, tw, TK);
+  MM_LAUNCH(mmk::k_fft_yz, dim3(nblocks), dim3(MM_YZ_T), lds, s, d, w, tw, TK);
   return hipGetLastError();
 }
 
 #define MM_YZR_CASE(A, B)                                                                        \
   if (MY == A && MZ == B) {                                                                      \
-    hipLaunchKernelGGL((mmk::k_fft_yzr<A, B>), dim3(nblocks), dim3(MM_YZR_T), lds, s, d, w, tw); \
+    MM_LAUNCH((mmk::k_fft_yzr<A, B>), dim3(nblocks), dim3(MM_YZR_T), lds, s, d, w, tw); \
     return hipGetLastError();                                                                    \
   }
 hipError_t mmk_launch_fft_yzr(int MY, int MZ, int nblocks, size_t lds, const InstDesc* d,
@@ -1064,14 +1065,14 @@ hipError_t mmk_launch_fft_yzr(int MY, int MZ, int nblocks, size_t lds, const Ins
 hipError_t mmk_launch_fft_xr(int dir, int MX, int nblocks, const InstDesc* d, const WorkItem* w, int method,
                              int stage, const float2* tw, hipStream_t s) {
   switch (MX * dir) {
-    case 4: hipLaunchKernelGGL(mmk::k_fft_xfr<4>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
-    case 8: hipLaunchKernelGGL(mmk::k_fft_xfr<8>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
-    case 16: hipLaunchKernelGGL(mmk::k_fft_xfr<16>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
-    case 32: hipLaunchKernelGGL(mmk::k_fft_xfr<32>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
-    case -4: hipLaunchKernelGGL(mmk::k_fft_xir<4>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
-    case -8: hipLaunchKernelGGL(mmk::k_fft_xir<8>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
-    case -16: hipLaunchKernelGGL(mmk::k_fft_xir<16>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
-    case -32: hipLaunchKernelGGL(mmk::k_fft_xir<32>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
+    case 4: MM_LAUNCH(mmk::k_fft_xfr<4>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
+    case 8: MM_LAUNCH(mmk::k_fft_xfr<8>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
+    case 16: MM_LAUNCH(mmk::k_fft_xfr<16>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
+    case 32: MM_LAUNCH(mmk::k_fft_xfr<32>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, method, stage, tw); break;
+    case -4: MM_LAUNCH(mmk::k_fft_xir<4>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
+    case -8: MM_LAUNCH(mmk::k_fft_xir<8>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
+    case -16: MM_LAUNCH(mmk::k_fft_xir<16>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
+    case -32: MM_LAUNCH(mmk::k_fft_xir<32>, dim3(nblocks), dim3(MM_XR_T), 0, s, d, w, tw); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1079,7 +1080,7 @@ hipError_t mmk_launch_fft_xr(int dir, int MX, int nblocks, const InstDesc* d, co
 
 #define MM_YZ8_CASE(A, B)                                                                        \
   if (MY == A && MZ == B) {                                                                      \
-    hipLaunchKernelGGL((mmk::k_fft_yz8<A, B>), dim3(nblocks + nfinal), dim3(MM_YZ8_T), lds, s, d, w, tw, \
+    MM_LAUNCH((mmk::k_fft_yz8<A, B>), dim3(nblocks + nfinal), dim3(MM_YZ8_T), lds, s, d, w, tw, \
                        nblocks, fmethod, fstage);                                                \
     return hipGetLastError();                                                                    \
   }
@@ -1093,14 +1094,14 @@ hipError_t mmk_launch_fft_yz8(int MY, int MZ, int nblocks, size_t lds, const Ins
 
 hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstDesc* d,
                             const WorkItem* w, const float2* tw, hipStream_t s) {
-  if (dir < 0) hipLaunchKernelGGL(mmk::k_fft_y<-1>, dim3(nblocks), dim3(256), lds, s, d, w, W, tw);
-  else hipLaunchKernelGGL(mmk::k_fft_y<1>, dim3(nblocks), dim3(256), lds, s, d, w, W, tw);
+  if (dir < 0) MM_LAUNCH(mmk::k_fft_y<-1>, dim3(nblocks), dim3(256), lds, s, d, w, W, tw);
+  else MM_LAUNCH(mmk::k_fft_y<1>, dim3(nblocks), dim3(256), lds, s, d, w, W, tw);
   return hipGetLastError();
 }
 
 hipError_t mmk_launch_fft_zc(int TW, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              const float2* tw, hipStream_t s) {
-  hipLaunchKernelGGL(mmk::k_fft_zc, dim3(nblocks), dim3(256), lds, s, d, w, TW, tw);
+  MM_LAUNCH(mmk::k_fft_zc, dim3(nblocks), dim3(256), lds, s, d, w, TW, tw);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 // step-size controller done by the last workgroup of each instance.
 #include "mm_internal.h"
 #include "kernels_common.h"
+#include "launch.h"
 #include "fft_lds.h"
 #include "stage_final.h"
 
@@ -183,11 +184,12 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
                                                   const float2* __restrict__ tw) {
   __shared__ double sh[2 * (MMI_WG / 64)];
   extern __shared__ float2 xl[];
-  const InstDesc& D = descs[wg_inst[blockIdx.x]];
+  const int lblk = xcd_block();
+  const InstDesc& D = descs[wg_inst[lblk]];
   // the control block is only read here (the finalisation kernel writes it)
   const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
-  const int lw = blockIdx.x - D.wg0;
+  const int lw = lblk - D.wg0;
   const int nc = D.ncell;
   const int i = lw * MMI_WG + threadIdx.x;
   const bool valid = i < nc;
@@ -450,9 +452,9 @@ __global__ __launch_bounds__(MMI_WG) void k_final(const InstDesc* __restrict__ d
 #define MM_STAGE_LAUNCH(M, S)                                                                   \
   case S:                                                                                       \
     if (final_pass)                                                                             \
-      hipLaunchKernelGGL((mmk::k_final<M, S>), dim3(count), dim3(MMI_WG), 0, stream, descs, count); \
+      MM_LAUNCH((mmk::k_final<M, S>), dim3(count), dim3(MMI_WG), 0, stream, descs, count); \
     else                                                                                        \
-      hipLaunchKernelGGL((mmk::k_stage<M, S>), dim3(nblocks), dim3(MMI_WG), lds, stream, descs, wg, tw); \
+      MM_LAUNCH((mmk::k_stage<M, S>), dim3(nblocks), dim3(MMI_WG), lds, stream, descs, wg, tw); \
     break;
 
 // final_pass = false: the cell kernel of a stage; true: its per-instance
@@ -496,6 +498,6 @@ __global__ void k_gather_done(const InstDesc* __restrict__ d, int count, int* __
 }  // namespace mmk
 
 hipError_t mmk_launch_gather_done(int count, const InstDesc* d, int* out, hipStream_t s) {
-  hipLaunchKernelGGL(mmk::k_gather_done, dim3((count + 63) / 64), dim3(64), 0, s, d, count, out);
+  MM_LAUNCH(mmk::k_gather_done, dim3((count + 63) / 64), dim3(64), 0, s, d, count, out);
   return hipGetLastError();
 }

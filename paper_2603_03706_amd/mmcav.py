@@ -75,6 +75,7 @@ _SIGS = {
     "mm_batch_set_fft_path": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_batch_set_fft_x": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_batch_set_streams": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "mm_batch_tune_fft": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
     "mm_batch_get_streams": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "mm_run_record": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32]),
     "mm_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
@@ -286,11 +287,13 @@ class Batch:
     def step(self, steps, tol=0.0):
         _check(self._lib.mm_batch_step(self.h, int(steps), float(tol)))
 
-    def tune(self):
-        """Autotune the FFT tiles / path per grid shape; returns the report."""
+    def tune(self, streams=True):
+        """Autotune the sub-batch count (unless streams=False) and the FFT
+        tiles / path per grid shape; returns the report."""
         import json
         buf = ctypes.create_string_buffer(65536)
-        _check(self._lib.mm_batch_tune(self.h, buf, len(buf)))
+        fn = self._lib.mm_batch_tune if streams else self._lib.mm_batch_tune_fft
+        _check(fn(self.h, buf, len(buf)))
         return json.loads(buf.value.decode())
 
     YZ_PATHS = {"fused": 0, "reg": 1, "split": 2, "reg8": 3}
