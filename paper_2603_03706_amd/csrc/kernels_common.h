@@ -39,6 +39,21 @@ struct Src {
   }
 };
 
+// The same with the presence of p1 fixed at compile time, so that every
+// load of a stencil (both fields when TWO) is issued without a test.
+template <bool TWO>
+struct SrcFixed {
+  const MMG float* p0;
+  const MMG float* p1;
+  float c1;
+  __device__ __forceinline__ explicit SrcFixed(const Src& s) : p0(s.p0), p1(s.p1), c1(s.c1) {}
+  __device__ __forceinline__ float ld(int idx) const {
+    float v = p0[idx];
+    if (TWO) v = fmaf(c1, p1[idx], v);
+    return v;
+  }
+};
+
 // Where the input of stage `stage` lives.  RK4: 0/1 state, 2 and 4 buffer
 // A, 3 buffer B.  DP45: 1 state, 2 state + h a21 k1 (not stored), 3 and 5
 // buffer A, 4 and 6 buffer B, 7 the normalised candidate.
@@ -76,7 +91,8 @@ __device__ __forceinline__ Src stage_src(const InstDesc& D, CtlPtr C, int method
 // Zeeman + exchange over magnetic neighbour pairs + uniaxial anisotropy +
 // demag (local diagonal, or the FFT result in D.bd) + feedback c_s fb along
 // x + intersublattice -B_E m_{s'}.  m holds the cell's own stage input.
-__device__ __forceinline__ void field_at(const InstDesc& D, const Src& src, int i, int x, int y,
+template <class SRC>
+__device__ __forceinline__ void field_at(const InstDesc& D, const SRC& src, int i, int x, int y,
                                          int z, const float (&m)[2][3], int s, float fb,
                                          bool has_bd, float (&B)[3], const float* bdv = nullptr) {
   const int nc = D.ncell;

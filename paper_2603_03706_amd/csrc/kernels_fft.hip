@@ -638,8 +638,7 @@ __global__ __launch_bounds__(MM_YZ8_T) __attribute__((amdgpu_waves_per_eu(4, 4))
   constexpr int lgMY = ilog2c(MY), lgMZ = ilog2c(MZ), lgMH = lgMZ - 1, lgPY = lgMY + 2;
   extern __shared__ float2 lds[];
   if ((int)blockIdx.x >= nyz) {
-    double* sh = reinterpret_cast<double*>(lds);
-    final_any(fmethod, fstage, descs, (int)blockIdx.x - nyz, sh, sh + MMI_WG / 64);
+    final_any(fmethod, fstage, descs, (int)blockIdx.x - nyz, reinterpret_cast<double*>(lds));
     return;
   }
   float2* B = lds;
@@ -1086,7 +1085,7 @@ hipError_t mmk_launch_fft_xr(int dir, int MX, int nblocks, const InstDesc* d, co
   }
 hipError_t mmk_launch_fft_yz8(int MY, int MZ, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                               const float2* tw, hipStream_t s, int nfinal, int fmethod, int fstage) {
-  if (nfinal < 0 || (nfinal > 0 && lds < (MMI_WG / 64 + MMI_PSTRIDE) * sizeof(double))) return hipErrorInvalidValue;
+  if (nfinal < 0 || (nfinal > 0 && lds < MMI_PSTRIDE * sizeof(double))) return hipErrorInvalidValue;
   MM_YZ8_CASE(4, 8) MM_YZ8_CASE(8, 8) MM_YZ8_CASE(16, 8) MM_YZ8_CASE(32, 8)
   MM_YZ8_CASE(4, 16) MM_YZ8_CASE(8, 16) MM_YZ8_CASE(16, 16) MM_YZ8_CASE(32, 16)
   return hipErrorInvalidValue;

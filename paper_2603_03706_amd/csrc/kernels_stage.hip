@@ -12,7 +12,8 @@ namespace mmk {
 // ---------------------------------------------------------------- helpers
 
 // LL torque on sublattice s at cell i from its effective field.
-__device__ __forceinline__ void torque_at(const InstDesc& D, const Src& src, int i, int x, int y,
+template <class SRC>
+__device__ __forceinline__ void torque_at(const InstDesc& D, const SRC& src, int i, int x, int y,
                                           int z, const float (&m)[2][3], int s, float fb,
                                           bool has_bd, float (&k)[3], const float* bdv = nullptr) {
   float B[3];
@@ -209,7 +210,8 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   for (int n = 0; n < MMI_MAX_MODES; ++n)
     fbc[n] = n < NM ? (float)(D.h0[n] * (D.cphi[n] * C->as[n][0] + D.sphi[n] * C->as[n][1])) : 0.f;
 
-  const Src src = stage_src(D, C, METHOD, ST);
+  // only the DP45 stage-2 input is formed on the fly from two fields
+  const SrcFixed<METHOD == MMI_DP45 && ST == 2> src(stage_src(D, C, METHOD, ST));
 
   // x passes done here: the C2R of this stage's convolved rows, and (below)
   // the R2C of the next stage input
@@ -440,10 +442,9 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
 // kernel in a fixed order and run the FP64 cavity step / controller.
 template <int METHOD, int ST>
 __global__ __launch_bounds__(MMI_WG) void k_final(const InstDesc* __restrict__ descs, int count) {
-  __shared__ double sh[MMI_WG / 64];
   __shared__ double tot[MMI_PSTRIDE];
   if ((int)blockIdx.x >= count) return;
-  final_body<METHOD, ST>(descs, blockIdx.x, sh, tot);
+  final_body<METHOD, ST>(descs, blockIdx.x, tot);
 }
 
 }  // namespace mmk

@@ -33,16 +33,25 @@ __device__ __forceinline__ double block_reduce(double v, double* sh) {
   return r;
 }
 
-// Sum (or max) one slot of the partial records over all workgroups of an
-// instance in a fixed order; result in thread 0.
+// Sum (or, with MAX, the NaN-propagating max of) slots s0 .. s0+n-1 of the
+// partial records over all workgroups of an instance, every slot in a fixed
+// order: wave w of the workgroup takes slots w, w + 8, ...; its lanes stride
+// over the workgroups (lane l: records l, l + 64, ...) and a butterfly joins
+// the lanes.  Results (sums times `scale`) go to tot[slot] in LDS; the caller
+// synchronises before reading them.
 template <bool MAX>
-__device__ __forceinline__ double gather_slot(const InstDesc& D, int slot, double* sh) {
-  double v = MAX ? 0.0 : 0.0;
-  for (int w = threadIdx.x; w < D.nwg; w += MMI_WG) {
-    const double p = gbl(D.partials)[(size_t)w * MMI_PSTRIDE + slot];
-    v = MAX ? nan_max(v, p) : v + p;
+__device__ __forceinline__ void gather_slots(const InstDesc& D, int s0, int n, double scale, double* tot) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const MMG double* P = gbl(D.partials);
+  for (int k = wv; k < n; k += MMI_WG / 64) {
+    double v = 0.0;
+    for (int w = lane; w < D.nwg; w += 64) {
+      const double p = P[(size_t)w * MMI_PSTRIDE + s0 + k];
+      v = MAX ? nan_max(v, p) : v + p;
+    }
+    v = MAX ? wave_max(v) : wave_sum(v);
+    if (lane == 0) tot[s0 + k] = MAX ? v : v * scale;
   }
-  return block_reduce<MAX>(v, sh);
 }
 
 // Append one trace sample (time, a, m^-) from values held in the control
@@ -304,59 +313,43 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
 }
 
 // Body of the finalisation of stage ST of instance `inst` (all MMI_WG
-// threads of the workgroup; sh: MMI_WG / 64 doubles, tot: MMI_PSTRIDE
-// doubles of LDS).
+// threads of the workgroup; tot: MMI_PSTRIDE doubles of LDS).
 template <int METHOD, int ST>
-__device__ void final_body(const InstDesc* __restrict__ descs, int inst, double* sh, double* tot) {
+__device__ void final_body(const InstDesc* __restrict__ descs, int inst, double* tot) {
   const InstDesc& D = descs[inst];
   InstCtl* C = D.ctl;
   if (C->done) return;
   const bool has_next = !(METHOD == MMI_DP45 && ST == 7);
   const double scale = D.inv_ngeo / (double)D.S;
-  if (has_next) {
-    for (int q = 0; q < 2 * D.N; ++q) {
-      const double v = gather_slot<false>(D, MMI_SLOT_MM + q, sh);
-      if (threadIdx.x == 0) tot[MMI_SLOT_MM + q] = v * scale;
-    }
-  }
-  if (METHOD == MMI_DP45 && (ST == 1 || ST == 2 || ST == 7)) {
-    for (int q = 0; q < 2 * D.N; ++q) {
-      const double v = gather_slot<false>(D, MMI_SLOT_DMM + q, sh);
-      if (threadIdx.x == 0) tot[MMI_SLOT_DMM + q] = v * scale;
-    }
-  }
-  if (METHOD == MMI_DP45 && ST == 7) {
-    const double v = gather_slot<true>(D, MMI_SLOT_ERR, sh);
-    if (threadIdx.x == 0) tot[MMI_SLOT_ERR] = v;
-  }
-  if (METHOD == MMI_RK4 && ST == 4) {
-    const double v = gather_slot<true>(D, MMI_SLOT_BAD, sh);
-    if (threadIdx.x == 0) tot[MMI_SLOT_BAD] = v;
-  }
+  if (has_next) gather_slots<false>(D, MMI_SLOT_MM, 2 * D.N, scale, tot);
+  if (METHOD == MMI_DP45 && (ST == 1 || ST == 2 || ST == 7)) gather_slots<false>(D, MMI_SLOT_DMM, 2 * D.N, scale, tot);
+  if (METHOD == MMI_DP45 && ST == 7) gather_slots<true>(D, MMI_SLOT_ERR, 1, 1.0, tot);
+  if (METHOD == MMI_RK4 && ST == 4) gather_slots<true>(D, MMI_SLOT_BAD, 1, 1.0, tot);
+  __syncthreads();
   if (threadIdx.x == 0) finalize<METHOD, ST>(D, C, tot);
 }
 
 // the same with the method and stage chosen at run time
 __device__ __forceinline__ void final_any(int method, int st, const InstDesc* __restrict__ descs, int inst,
-                                          double* sh, double* tot) {
+                                          double* tot) {
   if (method == MMI_RK4) {
     switch (st) {
-      case 0: final_body<MMI_RK4, 0>(descs, inst, sh, tot); break;
-      case 1: final_body<MMI_RK4, 1>(descs, inst, sh, tot); break;
-      case 2: final_body<MMI_RK4, 2>(descs, inst, sh, tot); break;
-      case 3: final_body<MMI_RK4, 3>(descs, inst, sh, tot); break;
-      case 4: final_body<MMI_RK4, 4>(descs, inst, sh, tot); break;
+      case 0: final_body<MMI_RK4, 0>(descs, inst, tot); break;
+      case 1: final_body<MMI_RK4, 1>(descs, inst, tot); break;
+      case 2: final_body<MMI_RK4, 2>(descs, inst, tot); break;
+      case 3: final_body<MMI_RK4, 3>(descs, inst, tot); break;
+      case 4: final_body<MMI_RK4, 4>(descs, inst, tot); break;
       default: break;
     }
   } else {
     switch (st) {
-      case 1: final_body<MMI_DP45, 1>(descs, inst, sh, tot); break;
-      case 2: final_body<MMI_DP45, 2>(descs, inst, sh, tot); break;
-      case 3: final_body<MMI_DP45, 3>(descs, inst, sh, tot); break;
-      case 4: final_body<MMI_DP45, 4>(descs, inst, sh, tot); break;
-      case 5: final_body<MMI_DP45, 5>(descs, inst, sh, tot); break;
-      case 6: final_body<MMI_DP45, 6>(descs, inst, sh, tot); break;
-      case 7: final_body<MMI_DP45, 7>(descs, inst, sh, tot); break;
+      case 1: final_body<MMI_DP45, 1>(descs, inst, tot); break;
+      case 2: final_body<MMI_DP45, 2>(descs, inst, tot); break;
+      case 3: final_body<MMI_DP45, 3>(descs, inst, tot); break;
+      case 4: final_body<MMI_DP45, 4>(descs, inst, tot); break;
+      case 5: final_body<MMI_DP45, 5>(descs, inst, tot); break;
+      case 6: final_body<MMI_DP45, 6>(descs, inst, tot); break;
+      case 7: final_body<MMI_DP45, 7>(descs, inst, tot); break;
       default: break;
     }
   }
