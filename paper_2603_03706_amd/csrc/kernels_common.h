@@ -87,6 +87,9 @@ __device__ __forceinline__ Src stage_src(const InstDesc& D, CtlPtr C, int method
   return s;
 }
 
+// bdv: this cell's demag field already at hand (used when use_bdv; pass a
+// pointer fixed at compile time, never one chosen at run time, so that the
+// array stays in registers).
 // Effective field [T] on sublattice s at cell i (x, y, z its coordinates):
 // Zeeman + exchange over magnetic neighbour pairs + uniaxial anisotropy +
 // demag (local diagonal, or the FFT result in D.bd) + feedback c_s fb along
@@ -94,7 +97,8 @@ __device__ __forceinline__ Src stage_src(const InstDesc& D, CtlPtr C, int method
 template <class SRC>
 __device__ __forceinline__ void field_at(const InstDesc& D, const SRC& src, int i, int x, int y,
                                          int z, const float (&m)[2][3], int s, float fb,
-                                         bool has_bd, float (&B)[3], const float* bdv = nullptr) {
+                                         bool has_bd, float (&B)[3], const float* bdv = nullptr,
+                                         bool use_bdv = true) {
   const int nc = D.ncell;
   const int nx = D.nx, ny = D.ny, nz = D.nz;
   const int base = s * 3 * nc;
@@ -145,7 +149,7 @@ __device__ __forceinline__ void field_at(const InstDesc& D, const SRC& src, int 
     bx = fmaf(D.nlx, tx, bx);
     by = fmaf(D.nly, ty, by);
     bz = fmaf(D.nlz, tz, bz);
-  } else if (bdv) {
+  } else if (bdv && use_bdv) {
     bx += bdv[0];
     by += bdv[1];
     bz += bdv[2];

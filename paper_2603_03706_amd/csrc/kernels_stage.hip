@@ -15,9 +15,10 @@ namespace mmk {
 template <class SRC>
 __device__ __forceinline__ void torque_at(const InstDesc& D, const SRC& src, int i, int x, int y,
                                           int z, const float (&m)[2][3], int s, float fb,
-                                          bool has_bd, float (&k)[3], const float* bdv = nullptr) {
+                                          bool has_bd, float (&k)[3], const float* bdv = nullptr,
+                                          bool use_bdv = true) {
   float B[3];
-  field_at(D, src, i, x, y, z, m, s, fb, has_bd, B, bdv);
+  field_at(D, src, i, x, y, z, m, s, fb, has_bd, B, bdv, use_bdv);
   const float m0 = m[s][0], m1 = m[s][1], m2 = m[s][2];
   // -gl [m x B + alpha m x (m x B)]
   const float cx = m1 * B[2] - m2 * B[1];
@@ -263,7 +264,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
     const bool has_bd = D.demag == 2;
 #pragma unroll
     for (int s = 0; s < 2; ++s)
-      if (s < S) torque_at(D, src, i, x, yy, zz, m, s, fb, has_bd, k[s], (kC2R && xf) ? bdv : nullptr);
+      if (s < S) torque_at(D, src, i, x, yy, zz, m, s, fb, has_bd, k[s], kC2R ? bdv : nullptr, xf);
   }
 
   // combination and outputs
