@@ -188,7 +188,9 @@ def summarize_trace(trace_csv, bench_json, command):
     table(marks[0], marks[1], False)
     print(f"## Per-kernel profile phase (whole batch, eager launches, one kernel at a time)\n")
     print("The JSON line's kernel table and roofline are measured in this phase with HIP events on the "
-          "library stream; the last column repeats them.\n")
+          "library stream; the last column repeats them. The event pair around a launch adds a few "
+          "microseconds of dispatch overhead to each figure, so the JSON line's durations are the "
+          "larger ones and its achieved rates the smaller ones.\n")
     table(marks[2], marks[3], True)
 
 

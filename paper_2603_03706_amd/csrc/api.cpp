@@ -602,8 +602,10 @@ mm_status launch(mm_batch* b, const char* name, F&& f) {
       b->prof.back().bytes = algorithmic_bytes(b, name);
     }
     hipEvent_t e0, e1;
-    MM_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
-    MM_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
+    // default events: the system-scope release at the end of the kernel
+    // writes its dirty lines back, so per-dispatch write counters see them
+    MM_HIP(hipEventCreate(&e0));
+    MM_HIP(hipEventCreate(&e1));
     // recorded by the runtime at the kernel's own start and end
     hipEvent_t* ev = mm_launch_events();
     ev[0] = e0;

@@ -1,8 +1,8 @@
 // Kernel launches of the library.  The per-kernel profiler sets the two
 // events of the calling thread around one launch; the runtime then records
-// them at that kernel's own start and end (no gap before or after it), so
-// the profiled durations are the kernels' own.  Outside the profiler both
-// are null and the launch is an ordinary one.
+// them together with that kernel's dispatch instead of as separate markers
+// (a few microseconds of dispatch overhead remain in each figure).  Outside
+// the profiler both are null and the launch is an ordinary one.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
