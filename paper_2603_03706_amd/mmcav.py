@@ -342,6 +342,51 @@ class Batch:
             pass
 
 
+class RecordedRunFunction(torch.autograd.Function):
+    """Differentiable fixed-step RK4 run of one instance: the forward pass
+    records the run on the GPU (mm_run_record: checkpoints every
+    `checkpoint_every` steps), the backward pass is the library's discrete
+    adjoint (mm_adjoint).  Inputs that carry gradients: the mode profiles u
+    (float32 [N][nz][ny][nx]), the couplings g (float64 [N], rad/s), the
+    damping alpha (float64 scalar) and the bias field B0 (float64 [3], T).
+    Outputs: a(T) as float64 [N][2] (real, imaginary part) and m(T) as float32
+    [S][3][nz][ny][nx].  The other parameters come from `inst`
+    (workloads.Instance, method rk4).  Arguments and results are only
+    marshalled here; both passes run in the library's kernels."""
+
+    @staticmethod
+    def forward(fctx, u, g, alpha, B0, inst, T, checkpoint_every):
+        import dataclasses
+        run = dataclasses.replace(inst, u=u.detach().cpu().numpy().astype(np.float32),
+                                  g=g.detach().cpu().numpy().astype(np.float64),
+                                  alpha=float(alpha.detach().cpu()),
+                                  B0=tuple(float(v) for v in B0.detach().cpu()))
+        if run.method != "rk4":
+            raise ValueError("the discrete adjoint is built for fixed-step RK4 runs")
+        c = Context.from_instance(run)
+        c.run_record(T, checkpoint_every)
+        a = c.get_a()
+        fctx.context = c
+        return (torch.from_numpy(np.stack([a.real, a.imag], axis=-1)), torch.from_numpy(c.get_m()))
+
+    @staticmethod
+    def backward(fctx, grad_a, grad_m):
+        c = fctx.context
+        ga = np.zeros((c.N, 2)) if grad_a is None else grad_a.detach().cpu().numpy().astype(np.float64)
+        gm = None if grad_m is None else grad_m.detach().cpu().numpy().astype(np.float32)
+        g = c.adjoint(ga[:, 0] + 1j * ga[:, 1], gm)
+        c.close()
+        fctx.context = None
+        return (torch.from_numpy(g["u"]), torch.from_numpy(g["g"]), torch.tensor(g["alpha"], dtype=torch.float64),
+                torch.from_numpy(np.asarray(g["B0"], np.float64)), None, None, None)
+
+
+def recorded_run(inst, T, u, g, alpha, B0, checkpoint_every=256):
+    """a(T) [N][2] and m(T) of `inst` run for T with the given u, g, alpha and
+    B0 (tensors; gradients flow through the GPU discrete adjoint)."""
+    return RecordedRunFunction.apply(u, g, alpha, B0, inst, T, checkpoint_every)
+
+
 def exported_symbols():
     """Names declared in include/mmcav.h."""
     return list(_SIGS)
