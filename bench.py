@@ -436,24 +436,39 @@ def film_rate(steps, tol):
             "ms_per_step": dt / steps * 1e3, "cell_updates_per_s": inst.cells * acc / dt}
 
 
-def cpu_baseline(inst, seconds, tol):
-    """The oracle, as it stands, on the host cores: one sweep instance,
-    DP45 from the same initial state, for about `seconds` of CPU work."""
+def oracle_rate(inst, seconds, tol):
+    """Accepted steps of the oracle on one instance, DP45 from its initial
+    state, in about `seconds` of host time: (accepted, rejected, seconds)."""
     import torch
     from tests.helpers import oracle_for
     st = oracle_for(inst)
-    cores = torch.get_num_threads()
     t0 = time.perf_counter()
     with torch.no_grad():
         st._dp_first()
         # advance in small slices until the time budget is used
         while time.perf_counter() - t0 < seconds:
             st.run(5e-13, tol)
-    dt = time.perf_counter() - t0
+    return st.accepted, st.rejected, time.perf_counter() - t0
+
+
+def cpu_baseline(inst, seconds, tol):
+    """The oracle, as it stands, on the host cores: one sweep instance for
+    about `seconds` with every host thread torch uses, then for a third of
+    that on one thread."""
+    import torch
+    cores = torch.get_num_threads()
+    acc, rej, dt = oracle_rate(inst, seconds, tol)
+    torch.set_num_threads(1)
+    try:
+        acc1, _, dt1 = oracle_rate(inst, seconds / 3.0, tol)
+    finally:
+        torch.set_num_threads(cores)
     cells = inst.cells
-    return {"value": cells * st.accepted / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+    return {"value": cells * acc / dt, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"one 32^3 sphere instance (17,256 magnetic cells, FFT demag on 64^3), DP45 tol {tol:g}, "
-                      f"{st.accepted} accepted steps ({st.rejected} rejected) in {dt:.1f} s from t = 0"}
+                      f"{acc} accepted steps ({rej} rejected) in {dt:.1f} s from t = 0",
+            "one_core": {"value": cells * acc1 / dt1, "cores": 1,
+                         "sample": f"the same instance, {acc1} accepted steps in {dt1:.1f} s on one thread"}}
 
 
 def main():
