@@ -292,11 +292,13 @@ def test_library_owned_workspace_matches_torch_workspace():
 # -------------------------------------------------------- full-size checks
 def test_sweep_batch_full_size_first_step():
     """The 64-instance sweep (32^3 spheres, FFT on 64^3) batched as the
-    benchmark runs it: one DP45 step, sampled instances against the oracle."""
+    benchmark runs it (tuned: sub-batch count and FFT strategies): one DP45
+    step, sampled instances against the oracle."""
     from paper_2603_03706_amd import mmcav
     insts = [W.sweep_sphere(k) for k in range(64)]
     ctxs = [gpu_for(inst) for inst in insts]
     b = mmcav.Batch(ctxs)
+    b.tune()
     b.step(1, 1e-6)
     for k in (0, 31, 63):
         st = oracle_for(insts[k])
