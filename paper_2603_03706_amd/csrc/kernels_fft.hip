@@ -939,27 +939,63 @@ __global__ __launch_bounds__(256) void k_fft_y(const InstDesc* __restrict__ desc
   float2* buf = lds;
   float2* twl = lds + Py * WP;
   load_twiddles(twl, Py, tw, 256);
-  const int nin = (DIR < 0) ? ny : Py;
-  const int lgy = ilog2(Py);
-  for (int e = threadIdx.x; e < W * Py; e += 256) {
-    const int ll = e >> lgy, y = e & (Py - 1);
-    const int l = l0 + ll;
-    float2 v = make_float2(0.f, 0.f);
-    if (l < nlines && y < nin) v = (DIR < 0) ? gld2(gbl(D.fx) + (size_t)l * ny + y) : gld2(gbl(D.fy) + (size_t)l * Py + y);
-    // forward: natural order in; inverse: bit-reversed order in
-    buf[((DIR < 0) ? y : brev(y, lgy)) * WP + ll] = v;
-  }
-  __syncthreads();
-  if (DIR < 0) fft_cols<256, false>(buf, Py, lgy, 1, ilog2(W), 0, WP, twl);
-  else fft_cols<256, true>(buf, Py, lgy, 1, ilog2(W), 0, WP, twl);
-  const int nout = (DIR < 0) ? Py : ny;
-  for (int e = threadIdx.x; e < W * nout; e += 256) {
-    const int ll = e / nout, y = e - ll * nout;
-    const int l = l0 + ll;
-    if (l >= nlines) continue;
-    const float2 v = buf[((DIR < 0) ? brev(y, lgy) : y) * WP + ll];
-    if (DIR < 0) gst2(gbl(D.fy) + (size_t)l * Py + y, v);
-    else gst2(gbl(D.fx) + (size_t)l * ny + y, v);
+  __syncthreads();   // the pruned forward stage below reads the table
+  const int lgy = ilog2(Py), lgW = ilog2(W);
+  if (DIR < 0) {
+    // The inputs vanish for y >= ny, and ny <= Py/2: the first radix-2^2 DIF
+    // stage (span Py/2) reads only x0 = x[y] and x1 = x[y + Py/4] and is done
+    // here with the same arithmetic as the full stage (x2 = x3 = 0).
+    const int q = Py >> 2;
+    if (q == 0) {
+      // lines of one or two points: no stage to skip
+      for (int e = threadIdx.x; e < W * Py; e += 256) {
+        const int ll = e >> lgy, y = e & (Py - 1);
+        const int l = l0 + ll;
+        float2 v = make_float2(0.f, 0.f);
+        if (l < nlines && y < ny) v = gld2(gbl(D.fx) + (size_t)l * ny + y);
+        buf[y * WP + ll] = v;
+      }
+    }
+    for (int e = threadIdx.x; e < W * q; e += 256) {
+      const int y = e & (q - 1), ll = e >> (lgy - 2);   // consecutive threads: consecutive y
+      const int l = l0 + ll;
+      const MMG float2* row = gbl(D.fx) + (size_t)min(l, nlines - 1) * ny;
+      float2 x0 = gld2(row + min(y, ny - 1)), x1 = gld2(row + min(y + q, ny - 1));
+      if (l >= nlines || y >= ny) x0 = make_float2(0.f, 0.f);
+      if (l >= nlines || y + q >= ny) x1 = make_float2(0.f, 0.f);
+      const float2 z = make_float2(0.f, 0.f);
+      const float2 w1 = twl[y], w2 = twl[2 * y];
+      const float2 a0 = cadd(x0, z), a1 = cadd(x1, z);
+      const float2 a2 = cmul(csub(x0, z), w1);
+      const float2 a3 = rot<false>(cmul(csub(x1, z), w1));
+      buf[y * WP + ll] = cadd(a0, a1);
+      buf[(y + q) * WP + ll] = cmul(csub(a0, a1), w2);
+      buf[(y + 2 * q) * WP + ll] = cadd(a2, a3);
+      buf[(y + 3 * q) * WP + ll] = cmul(csub(a2, a3), w2);
+    }
+    __syncthreads();
+    fft_cols<256, false>(buf, Py, lgy, 1, lgW, 0, WP, twl, q == 0 ? 0 : 2);
+    for (int e = threadIdx.x; e < W * Py; e += 256) {
+      const int ll = e >> lgy, y = e & (Py - 1);
+      const int l = l0 + ll;
+      if (l < nlines) gst2(gbl(D.fy) + (size_t)l * Py + y, buf[brev(y, lgy) * WP + ll]);
+    }
+  } else {
+    // bit-reversed order in, natural order out, cropped to y < ny
+    for (int e = threadIdx.x; e < W * Py; e += 256) {
+      const int ll = e >> lgy, y = e & (Py - 1);
+      const int l = l0 + ll;
+      float2 v = make_float2(0.f, 0.f);
+      if (l < nlines) v = gld2(gbl(D.fy) + (size_t)l * Py + y);
+      buf[brev(y, lgy) * WP + ll] = v;
+    }
+    __syncthreads();
+    fft_cols<256, true>(buf, Py, lgy, 1, lgW, 0, WP, twl);
+    for (int e = threadIdx.x; e < W * Py; e += 256) {
+      const int ll = e >> lgy, y = e & (Py - 1);
+      const int l = l0 + ll;
+      if (l < nlines && y < ny) gst2(gbl(D.fx) + (size_t)l * ny + y, buf[y * WP + ll]);
+    }
   }
 }
 
@@ -980,19 +1016,46 @@ __global__ __launch_bounds__(256) void k_fft_zc(const InstDesc* __restrict__ des
   float2* buf = lds;
   float2* twl = lds + Pz * NL;
   load_twiddles(twl, Pz, tw, 256);
-  for (int e = threadIdx.x; e < Pz * NL; e += 256) {
-    const int z = e / NL, l = e - z * NL;
-    const int c = l / TW, t = l - c * TW;
-    const int ky = ky0 + t;
-    float2 v = make_float2(0.f, 0.f);
-    if (z < nz && ky < Py) v = gld2(gbl(D.fy) + (((size_t)kx * 3 + c) * nz + z) * Py + ky);
-    buf[e] = v;
-  }
   __syncthreads();
   const int lgz = ilog2(Pz), lgT = ilog2(TW);
-  fft_cols<256, false>(buf, Pz, lgz, 3, lgT, TW, NL, twl);
+  const MMG float2* Yk = gbl(D.fy) + (size_t)kx * 3 * nz * Py;
+  // The inputs vanish for z >= nz, and nz <= Pz/2: the first radix-2^2 DIF
+  // stage (span Pz/2) reads only x0 = x[z] and x1 = x[z + Pz/4] and is done
+  // here with the same arithmetic as the full stage (x2 = x3 = 0).
+  const int q = Pz >> 2;
+  if (q == 0) {
+    for (int e = threadIdx.x; e < Pz * NL; e += 256) {
+      const int t = e & (TW - 1), zc = e >> lgT;
+      const int z = zc / 3, c = zc - 3 * z;
+      const int ky = ky0 + t;
+      float2 v = make_float2(0.f, 0.f);
+      if (z < nz && ky < Py) v = gld2(Yk + ((size_t)c * nz + z) * Py + ky);
+      buf[z * NL + c * TW + t] = v;
+    }
+  }
+  for (int e = threadIdx.x; e < q * NL; e += 256) {
+    const int t = e & (TW - 1), zc = e >> lgT;
+    const int z = zc / 3, c = zc - 3 * z;
+    const int ky = min(ky0 + t, Py - 1);
+    const MMG float2* col = Yk + (size_t)c * nz * Py + ky;
+    float2 x0 = gld2(col + (size_t)min(z, nz - 1) * Py), x1 = gld2(col + (size_t)min(z + q, nz - 1) * Py);
+    if (z >= nz) x0 = make_float2(0.f, 0.f);
+    if (z + q >= nz) x1 = make_float2(0.f, 0.f);
+    const float2 zero = make_float2(0.f, 0.f);
+    const float2 w1 = twl[z], w2 = twl[2 * z];
+    const float2 a0 = cadd(x0, zero), a1 = cadd(x1, zero);
+    const float2 a2 = cmul(csub(x0, zero), w1);
+    const float2 a3 = rot<false>(cmul(csub(x1, zero), w1));
+    float2* line = buf + c * TW + t;
+    line[z * NL] = cadd(a0, a1);
+    line[(z + q) * NL] = cmul(csub(a0, a1), w2);
+    line[(z + 2 * q) * NL] = cadd(a2, a3);
+    line[(z + 3 * q) * NL] = cmul(csub(a2, a3), w2);
+  }
+  __syncthreads();
+  fft_cols<256, false>(buf, Pz, lgz, 3, lgT, TW, NL, twl, q == 0 ? 0 : 2);
   for (int e = threadIdx.x; e < Pz * TW; e += 256) {
-    const int pz_ = e / TW, t = e - pz_ * TW;
+    const int pz_ = e >> lgT, t = e & (TW - 1);
     const int ky = ky0 + t;
     if (ky >= Py) continue;
     float2 mx = buf[pz_ * NL + t], my = buf[pz_ * NL + TW + t], mz = buf[pz_ * NL + 2 * TW + t];
@@ -1004,10 +1067,10 @@ __global__ __launch_bounds__(256) void k_fft_zc(const InstDesc* __restrict__ des
   __syncthreads();
   fft_cols<256, true>(buf, Pz, lgz, 3, lgT, TW, NL, twl);
   for (int e = threadIdx.x; e < nz * NL; e += 256) {
-    const int z = e / NL, l = e - z * NL;
-    const int c = l / TW, t = l - c * TW;
+    const int t = e & (TW - 1), zc = e >> lgT;
+    const int z = zc / 3, c = zc - 3 * z;
     const int ky = ky0 + t;
-    if (ky < Py) gst2(gbl(D.fy) + (((size_t)kx * 3 + c) * nz + z) * Py + ky, buf[e]);
+    if (ky < Py) gst2(gbl(D.fy) + (((size_t)kx * 3 + c) * nz + z) * Py + ky, buf[z * NL + c * TW + t]);
   }
 }
 
