@@ -990,11 +990,32 @@ __global__ __launch_bounds__(256) void k_fft_y(const InstDesc* __restrict__ desc
       buf[brev(y, lgy) * WP + ll] = v;
     }
     __syncthreads();
-    fft_cols<256, true>(buf, Py, lgy, 1, lgW, 0, WP, twl);
-    for (int e = threadIdx.x; e < W * Py; e += 256) {
-      const int ll = e >> lgy, y = e & (Py - 1);
-      const int l = l0 + ll;
-      if (l < nlines && y < ny) gst2(gbl(D.fx) + (size_t)l * ny + y, buf[y * WP + ll]);
+    const int q = Py >> 2;
+    if (q == 0) {
+      fft_cols<256, true>(buf, Py, lgy, 1, lgW, 0, WP, twl);
+      for (int e = threadIdx.x; e < W * Py; e += 256) {
+        const int ll = e >> lgy, y = e & (Py - 1);
+        const int l = l0 + ll;
+        if (l < nlines && y < ny) gst2(gbl(D.fx) + (size_t)l * ny + y, buf[y * WP + ll]);
+      }
+    } else {
+      // all DIT stages but the last radix-2^2 one (span Py/4); that one is
+      // done here for the outputs y < Py/2 only (ny <= Py/2), with the same
+      // arithmetic as the full stage
+      fft_cols<256, true>(buf, Py, lgy, 1, lgW, 0, WP, twl, 0, lgy - 2);
+      for (int e = threadIdx.x; e < W * q; e += 256) {
+        const int i = e & (q - 1), ll = e >> (lgy - 2);
+        const int l = l0 + ll;
+        const float2* x = buf + i * WP + ll;
+        const float2 wA = twid<true>(twl, i << 1), wB = twid<true>(twl, i);
+        const float2 t1 = cmul(x[q * WP], wA), t3 = cmul(x[3 * q * WP], wA);
+        const float2 a0 = cadd(x[0], t1), a1 = csub(x[0], t1), a2 = cadd(x[2 * q * WP], t3),
+                     a3 = csub(x[2 * q * WP], t3);
+        const float2 u = cmul(a2, wB), v = rot<true>(cmul(a3, wB));
+        MMG float2* out = gbl(D.fx) + (size_t)l * ny;
+        if (l < nlines && i < ny) gst2(out + i, cadd(a0, u));
+        if (l < nlines && i + q < ny) gst2(out + i + q, cadd(a1, v));
+      }
     }
   }
 }
@@ -1065,12 +1086,33 @@ __global__ __launch_bounds__(256) void k_fft_zc(const InstDesc* __restrict__ des
     buf[pz_ * NL + 2 * TW + t] = mz;
   }
   __syncthreads();
-  fft_cols<256, true>(buf, Pz, lgz, 3, lgT, TW, NL, twl);
-  for (int e = threadIdx.x; e < nz * NL; e += 256) {
+  if (q == 0) {
+    fft_cols<256, true>(buf, Pz, lgz, 3, lgT, TW, NL, twl);
+    for (int e = threadIdx.x; e < nz * NL; e += 256) {
+      const int t = e & (TW - 1), zc = e >> lgT;
+      const int z = zc / 3, c = zc - 3 * z;
+      const int ky = ky0 + t;
+      if (ky < Py) gst2(gbl(D.fy) + (((size_t)kx * 3 + c) * nz + z) * Py + ky, buf[z * NL + c * TW + t]);
+    }
+    return;
+  }
+  // all DIT stages but the last radix-2^2 one (span Pz/4); that one is done
+  // here for the outputs z < Pz/2 only (nz <= Pz/2), with the same arithmetic
+  // as the full stage
+  fft_cols<256, true>(buf, Pz, lgz, 3, lgT, TW, NL, twl, 0, lgz - 2);
+  for (int e = threadIdx.x; e < q * NL; e += 256) {
     const int t = e & (TW - 1), zc = e >> lgT;
-    const int z = zc / 3, c = zc - 3 * z;
+    const int i = zc / 3, c = zc - 3 * i;
     const int ky = ky0 + t;
-    if (ky < Py) gst2(gbl(D.fy) + (((size_t)kx * 3 + c) * nz + z) * Py + ky, buf[z * NL + c * TW + t]);
+    const float2* x = buf + i * NL + c * TW + t;
+    const float2 wA = twid<true>(twl, i << 1), wB = twid<true>(twl, i);
+    const float2 t1 = cmul(x[q * NL], wA), t3 = cmul(x[3 * q * NL], wA);
+    const float2 a0 = cadd(x[0], t1), a1 = csub(x[0], t1), a2 = cadd(x[2 * q * NL], t3),
+                 a3 = csub(x[2 * q * NL], t3);
+    const float2 u = cmul(a2, wB), v = rot<true>(cmul(a3, wB));
+    MMG float2* out = gbl(D.fy) + (((size_t)kx * 3 + c) * nz) * Py + ky;
+    if (ky < Py && i < nz) gst2(out + (size_t)i * Py, cadd(a0, u));
+    if (ky < Py && i + q < nz) gst2(out + (size_t)(i + q) * Py, cadd(a1, v));
   }
 }
 
