@@ -36,38 +36,64 @@ __device__ __forceinline__ void torque_at(const InstDesc& D, const SRC& src, int
 
 // Reduce the per-thread mode sums of a vector field v (complex weight
 // sum_s c_s (v_x - i v_y) u_n) and store them in the partial record.
-__device__ __forceinline__ void reduce_modes(const InstDesc& D, int i, bool mag, float vr, float vi,
-                                             MMG double* rec, int slot, double* sh) {
-  for (int n = 0; n < D.N; ++n) {
-    double wr = 0.0, wi = 0.0;
-    if (mag) {
-      const double u = D.profiled ? (double)gbl(D.u)[(size_t)n * D.ncell + i] : 1.0;
-      wr = u * (double)vr;
-      wi = u * (double)vi;
+// Modes are reduced CH at a time: the wave sums of up to 2 CH values, one
+// exchange through LDS (two barriers), and thread 0 adds the waves' sums in
+// wave order (the same order of additions for every value as one block sum
+// per value).  sh: MODE_CHUNK * 2 * (MMI_WG / 64) doubles.
+#define MODE_CHUNK 4
+template <int CH>
+__device__ __forceinline__ void reduce_modes_by(const InstDesc& D, int i, bool mag, float vr, float vi,
+                                                MMG double* rec, int slot, double* sh) {
+  constexpr int NW = MMI_WG / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int NM = D.N;
+  for (int n0 = 0; n0 < NM; n0 += CH) {
+    double wr[CH], wi[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      wr[q] = 0.0;
+      wi[q] = 0.0;
+      if (n0 + q < NM) {
+        if (mag) {
+          const double u = D.profiled ? (double)gbl(D.u)[(size_t)(n0 + q) * D.ncell + i] : 1.0;
+          wr[q] = u * (double)vr;
+          wi[q] = u * (double)vi;
+        }
+        wr[q] = wave_sum(wr[q]);
+        wi[q] = wave_sum(wi[q]);
+      }
     }
-    // both sums in one pass over the waves (same order of additions as two
-    // separate block sums)
-    constexpr int NW = MMI_WG / 64;
-    wr = wave_sum(wr);
-    wi = wave_sum(wi);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) {
-      sh[wv] = wr;
-      sh[NW + wv] = wi;
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        sh[(2 * q) * NW + wv] = wr[q];
+        sh[(2 * q + 1) * NW + wv] = wi[q];
+      }
     }
     __syncthreads();
-    double sr = sh[0], si = sh[NW];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) {
-      sr += sh[w];
-      si += sh[NW + w];
-    }
     if (threadIdx.x == 0) {
-      rec[slot + 2 * n] = sr;
-      rec[slot + 2 * n + 1] = si;
+#pragma unroll
+      for (int q = 0; q < CH; ++q) {
+        if (n0 + q >= NM) break;
+        double sr = sh[(2 * q) * NW], si = sh[(2 * q + 1) * NW];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+          sr += sh[(2 * q) * NW + w];
+          si += sh[(2 * q + 1) * NW + w];
+        }
+        rec[slot + 2 * (n0 + q)] = sr;
+        rec[slot + 2 * (n0 + q) + 1] = si;
+      }
     }
   }
+}
+
+// one mode: one value pair per exchange; more: MODE_CHUNK modes per exchange
+__device__ __forceinline__ void reduce_modes(const InstDesc& D, int i, bool mag, float vr, float vi,
+                                             MMG double* rec, int slot, double* sh) {
+  if (D.N <= 1) reduce_modes_by<1>(D, i, mag, vr, vi, rec, slot, sh);
+  else reduce_modes_by<MODE_CHUNK>(D, i, mag, vr, vi, rec, slot, sh);
 }
 
 // ------------------------------------------- x passes inside the stage kernel
@@ -184,7 +210,7 @@ template <int METHOD, int ST>
 __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ descs,
                                                   const int* __restrict__ wg_inst,
                                                   const float2* __restrict__ tw) {
-  __shared__ double sh[2 * (MMI_WG / 64)];
+  __shared__ double sh[MODE_CHUNK * 2 * (MMI_WG / 64)];
   extern __shared__ float2 xl[];
   const int lblk = xcd_block();
   const InstDesc& D = descs[wg_inst[lblk]];

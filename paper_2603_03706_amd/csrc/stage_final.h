@@ -45,7 +45,16 @@ __device__ __forceinline__ void gather_slots(const InstDesc& D, int s0, int n, d
   const MMG double* P = gbl(D.partials);
   for (int k = wv; k < n; k += MMI_WG / 64) {
     double v = 0.0;
-    for (int w = lane; w < D.nwg; w += 64) {
+    int w = lane;
+    // eight records in flight at a time, combined in the same order
+    for (; w + 7 * 64 < D.nwg; w += 8 * 64) {
+      double p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] = P[(size_t)(w + u * 64) * MMI_PSTRIDE + s0 + k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v = MAX ? nan_max(v, p[u]) : v + p[u];
+    }
+    for (; w < D.nwg; w += 64) {
       const double p = P[(size_t)w * MMI_PSTRIDE + s0 + k];
       v = MAX ? nan_max(v, p) : v + p;
     }
