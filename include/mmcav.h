@@ -251,15 +251,16 @@ mm_status mm_run_record(mm_ctx* ctx, double T, int32_t checkpoint_every);
 
 /* Gradients of a scalar loss L(m(T), a(T)) of the recorded run, by the
  * discrete adjoint of the recorded step sequence (each segment between
- * checkpoints is recomputed with its stage inputs kept on the device, then
- * reversed stage by stage).  Inputs: dL_da [n][2] = (dL/dRe a_n, dL/dIm a_n)
+ * checkpoints is recomputed with its stage inputs, and with FFT demag their
+ * demag fields, kept on the device, then reversed stage by stage).  Inputs: dL_da [n][2] = (dL/dRe a_n, dL/dIm a_n)
  * at T (required); dL_dm [S][3][nz][ny][nx] at T or NULL (zero).  Outputs
  * (each may be NULL): grad_u [n][nz][ny][nx] (d L / d u_n(r), also for
  * modes set without a profile, i.e. at u = 1), grad_g [n], grad_alpha [1],
  * grad_B0 [3], grad_a0 [n][2] and grad_m0 [S][3][nz][ny][nx] (with respect
  * to the normalised initial state).  The context's state is left at the end
- * of the recorded run.  Device memory: 4 (K+1) + 5 state-sized buffers for
- * K = checkpoint_every, plus the checkpoints. */
+ * of the recorded run.  Device memory: 4 (K+1) + 5 state-sized buffers
+ * (plus 4 K field-sized ones with FFT demag) for K = checkpoint_every, plus
+ * the checkpoints. */
 mm_status mm_adjoint(mm_ctx* ctx, const double* dL_da, const float* dL_dm, float* grad_u, double* grad_g,
                      double* grad_alpha, double* grad_B0, double* grad_a0, float* grad_m0);
 

@@ -448,7 +448,8 @@ mm_status upload_desc(mm_ctx* c) {
     d.lam_k = f; f += vec;
     d.lam_z = f; f += vec;
     d.mu = f; f += vec;
-    d.lam_B = f;
+    d.lam_B = f; f += vec;
+    d.rec_bd = L.fft ? f : nullptr;
     d.rec_a = c->adj_d;
     d.grad_u = c->adj_d + (size_t)K * 4 * std::max(1, c->N) * 2;
   }
@@ -782,8 +783,12 @@ mm_status enqueue_reverse_step(mm_batch* b) {
     return s;
   if (mm_status s = launch(b, "adj_cavity", [&] { return mmk_launch_adj(3, 5, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
     return s;
+  // with the demag fields of the stage inputs recorded, only the convolution
+  // of the field adjoint remains per stage
+  const bool bd_recorded = b->ctxs.size() == 1 && b->ctxs[0]->desc.rec_bd;
   for (int st = 4; st >= 1; --st) {
-    if (mm_status s = enqueue_demag(b, st, MMI_ADJ)) return s;
+    if (!bd_recorded)
+      if (mm_status s = enqueue_demag(b, st, MMI_ADJ)) return s;
     if (mm_status s = launch(b, "adj_stage_a", [&] { return mmk_launch_adj(1, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
       return s;
     if (mm_status s = enqueue_demag(b, 5, MMI_ADJ)) return s;
@@ -1516,7 +1521,11 @@ mm_status mm_adjoint(mm_ctx* c, const double* dL_da, const float* dL_dm, float* 
     if (c->adj_d) hipFree(c->adj_d);
     c->adj_f = nullptr;
     c->adj_d = nullptr;
-    const size_t nf = (size_t)(K + 1) * 4 * vec + (size_t)K * S * nc + 5 * vec;
+    // stage inputs, norms, five adjoint vectors and, with FFT demag, the demag
+    // field of every recorded stage input (the reverse pass then needs one
+    // convolution per stage instead of two)
+    const size_t nf = (size_t)(K + 1) * 4 * vec + (size_t)K * S * nc + 5 * vec +
+                      (c->L.fft ? (size_t)K * 4 * 3 * nc : 0);
     const size_t nd = (size_t)K * 4 * std::max(1, N) * 2 + (size_t)std::max(1, N) * nc;
     if (hipMalloc(&c->adj_f, sizeof(float) * nf) != hipSuccess) return fail(MM_ERR_OOM, "adjoint allocation failed");
     if (hipMalloc(&c->adj_d, sizeof(double) * nd) != hipSuccess) return fail(MM_ERR_OOM, "adjoint allocation failed");

@@ -128,12 +128,21 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
   double galpha = 0.0, gb0x = 0.0, gb0y = 0.0, gb0z = 0.0;
   float lbx[2] = {0.f, 0.f};
   float mux[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  // demag field of this stage input: recorded during the segment recompute,
+  // else from the convolution just enqueued
+  float bdv[3] = {0.f, 0.f, 0.f};
+  const bool bd_recorded = D.rec_bd != nullptr;
+  if (bd_recorded && valid) {
+    const MMG float* RB = gbl(D.rec_bd) + ((size_t)ri * 4 + (ST - 1)) * (size_t)(3 * nc);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bdv[c] = RB[c * nc + i];
+  }
   if (mag) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       if (s >= S) continue;
       float B[3];
-      field_at(D, src, i, x, yy, zz, m, s, fb, D.demag == 2, B);
+      field_at(D, src, i, x, yy, zz, m, s, fb, D.demag == 2, B, bdv, bd_recorded);
       const float* ms = m[s];
       float l[3];
       for (int c = 0; c < 3; ++c) l[c] = gbl(D.lam_k)[(s * 3 + c) * nc + i];

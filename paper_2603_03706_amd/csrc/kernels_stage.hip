@@ -276,6 +276,13 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
       if (s < S)
 #pragma unroll
         for (int c = 0; c < 3; ++c) R[(s * 3 + c) * nc + i] = m[s][c];
+    // and the demag field of this stage input (FFT demag: one sublattice)
+    if (D.rec_bd) {
+      MMG float* RB = gbl(D.rec_bd) + ((size_t)ri * 4 + (ST - 1)) * (size_t)(3 * nc);
+      const MMG float* bd = gbl(D.bd);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) RB[c * nc + i] = (kC2R && xf) ? bdv[c] : bd[c * nc + i];
+    }
   }
   const bool need_torque = !(METHOD == MMI_RK4 && ST == 0);
   if (need_torque && mag) {

@@ -91,6 +91,7 @@ struct InstDesc {
   // discrete adjoint (RK4): recorded segment and adjoint fields
   float* rec_m;                       // [K+1][4][S*3*cells] stage inputs of each recorded step
   float* rec_norm;                    // [K][S*cells] |z| before the renormalisation
+  float* rec_bd;                      // [K][4][3*cells] demag field of each recorded stage input (FFT demag), or null
   double* rec_a;                      // [K][4][N][2] cavity stage inputs
   float* lam_y;                       // adjoint of the step start state
   float* lam_k;                       // adjoint of the current stage derivative
