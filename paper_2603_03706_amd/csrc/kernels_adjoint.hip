@@ -37,6 +37,28 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
+// K block sums with one exchange through LDS (sh: K * MMI_WG / 64 doubles);
+// every value is added in the same order as by block_sum.
+template <int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double* sh) {
+  constexpr int NW = MMI_WG / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[k * NW + wv] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double r = sh[k * NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) r += sh[k * NW + w];
+    v[k] = r;
+  }
+}
+
 __device__ __forceinline__ void cross3(const float* a, const float* b, float* o) {
   o[0] = a[1] * b[2] - a[2] * b[1];
   o[1] = a[2] * b[0] - a[0] * b[2];
@@ -88,7 +110,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_start(const InstDesc* __restrict
 template <int ST>
 __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ descs,
                                                   const int* __restrict__ wg_inst) {
-  __shared__ double sh[MMI_WG / 64];
+  __shared__ double sh[4 * (MMI_WG / 64)];
   const int lblk = xcd_block();
   const InstDesc& D = descs[wg_inst[lblk]];
   const MMG InstCtl* __restrict__ C = gbl(D.ctl);
@@ -194,14 +216,13 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
       }
       if (D.grad_u) gbl(D.grad_u)[(size_t)n * nc + i] += gu;
     }
-    const double s0 = block_sum(fbn, sh);
-    const double s1 = block_sum(mr, sh);
-    const double s2 = block_sum(mi, sh);
+    double sums[3] = {fbn, mr, mi};
+    block_sums<3>(sums, sh);
     if (threadIdx.x == 0) {
       MMG double* rec = gbl(D.partials) + (size_t)lw * MMI_PSTRIDE;
-      rec[MMI_ASLOT_FB + n] = s0;
-      rec[MMI_ASLOT_MM + 2 * n] = s1;
-      rec[MMI_ASLOT_MM + 2 * n + 1] = s2;
+      rec[MMI_ASLOT_FB + n] = sums[0];
+      rec[MMI_ASLOT_MM + 2 * n] = sums[1];
+      rec[MMI_ASLOT_MM + 2 * n + 1] = sums[2];
     }
   }
   if (valid)
@@ -210,16 +231,14 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
       if (s < S)
 #pragma unroll
         for (int c = 0; c < 3; ++c) gbl(D.mu)[(s * 3 + c) * nc + i] = mux[s][c];
-  const double r0 = block_sum(galpha, sh);
-  const double r1 = block_sum(gb0x, sh);
-  const double r2 = block_sum(gb0y, sh);
-  const double r3 = block_sum(gb0z, sh);
+  double r[4] = {galpha, gb0x, gb0y, gb0z};
+  block_sums<4>(r, sh);
   if (threadIdx.x == 0) {
     MMG double* rec = gbl(D.partials) + (size_t)lw * MMI_PSTRIDE;
-    rec[MMI_ASLOT_ALPHA] = r0;
-    rec[MMI_ASLOT_B0] = r1;
-    rec[MMI_ASLOT_B0 + 1] = r2;
-    rec[MMI_ASLOT_B0 + 2] = r3;
+    rec[MMI_ASLOT_ALPHA] = r[0];
+    rec[MMI_ASLOT_B0] = r[1];
+    rec[MMI_ASLOT_B0 + 1] = r[2];
+    rec[MMI_ASLOT_B0 + 2] = r[3];
   }
 }
 
