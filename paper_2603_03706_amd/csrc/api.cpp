@@ -789,10 +789,16 @@ mm_status enqueue_reverse_step(mm_batch* b) {
   for (int st = 4; st >= 1; --st) {
     if (!bd_recorded)
       if (mm_status s = enqueue_demag(b, st, MMI_ADJ)) return s;
-    if (mm_status s = launch(b, "adj_stage_a", [&] { return mmk_launch_adj(1, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
+    // for groups with x passes in the cell kernels, the adjoint stage kernels
+    // transform the field adjoint themselves (R2C in A, C2R in B)
+    if (mm_status s = launch(b, "adj_stage_a", [&] {
+          return mmk_launch_adj(1, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream, g_twiddle, b->stage_lds);
+        }))
       return s;
-    if (mm_status s = enqueue_demag(b, 5, MMI_ADJ)) return s;
-    if (mm_status s = launch(b, "adj_stage_b", [&] { return mmk_launch_adj(2, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
+    if (mm_status s = enqueue_demag(b, 5, MMI_ADJ, false, false)) return s;
+    if (mm_status s = launch(b, "adj_stage_b", [&] {
+          return mmk_launch_adj(2, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream, g_twiddle, b->stage_lds);
+        }))
       return s;
     if (mm_status s = launch(b, "adj_cavity", [&] { return mmk_launch_adj(3, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
       return s;

@@ -22,6 +22,7 @@
 #include "mm_internal.h"
 #include "kernels_common.h"
 #include "launch.h"
+#include "xrows.h"
 
 namespace mmk {
 
@@ -109,8 +110,10 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_start(const InstDesc* __restrict
 // ------------------------------------------------------------ stage A
 template <int ST>
 __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ descs,
-                                                  const int* __restrict__ wg_inst) {
+                                                  const int* __restrict__ wg_inst,
+                                                  const float2* __restrict__ tw) {
   __shared__ double sh[4 * (MMI_WG / 64)];
+  extern __shared__ float2 xl[];
   const int lblk = xcd_block();
   const InstDesc& D = descs[wg_inst[lblk]];
   const MMG InstCtl* __restrict__ C = gbl(D.ctl);
@@ -149,6 +152,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
   const float wmm = (float)(D.inv_ngeo / (double)S);
   double galpha = 0.0, gb0x = 0.0, gb0y = 0.0, gb0z = 0.0;
   float lbx[2] = {0.f, 0.f};
+  float lb0[3] = {0.f, 0.f, 0.f};   // field adjoint of sublattice 0 (the R2C input)
   float mux[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
   // demag field of this stage input: recorded during the segment recompute,
   // else from the convolution just enqueued
@@ -190,6 +194,8 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
       gb0z += lB[2];
       lbx[s] = lB[0];
       for (int c = 0; c < 3; ++c) lam_B[(s * 3 + c) * nc + i] = lB[c];
+      if (s == 0)
+        for (int c = 0; c < 3; ++c) lb0[c] = lB[c];
     }
   } else if (valid) {
     for (int s = 0; s < S; ++s)
@@ -240,19 +246,37 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
     rec[MMI_ASLOT_B0 + 1] = r[2];
     rec[MMI_ASLOT_B0 + 2] = r[3];
   }
+  if (D.xfused) {
+    // R2C of the field adjoint of this workgroup's x-rows: the X rows of its
+    // convolution (no separate x-forward pass)
+    const XRows xq = xrows_setup(D, lw, xl);
+    load_twiddles(xq.twl, xq.Px, tw, MMI_WG);
+    xrows_r2c(D, xq, lb0, false);
+  }
 }
 
 // ------------------------------------------------------------ stage B
 template <int ST>
 __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ descs,
-                                                  const int* __restrict__ wg_inst) {
+                                                  const int* __restrict__ wg_inst,
+                                                  const float2* __restrict__ tw) {
+  extern __shared__ float2 xl[];
   const int lblk = xcd_block();
   const InstDesc& D = descs[wg_inst[lblk]];
   const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
   const int nc = D.ncell, S = D.S;
-  const int i = (lblk - D.wg0) * MMI_WG + threadIdx.x;
-  if (i >= nc) return;
+  const int lw = lblk - D.wg0;
+  // convolved field adjoint of this cell: C2R of the workgroup's X rows, or
+  // the x-inverse pass's output
+  float bdv[3] = {0.f, 0.f, 0.f};
+  if (D.xfused) {
+    const XRows xq = xrows_setup(D, lw, xl);
+    load_twiddles(xq.twl, xq.Px, tw, MMI_WG);
+    xrows_c2r(D, xq, bdv);
+  }
+  const int i = lw * MMI_WG + threadIdx.x;
+  if (i >= nc) return;   // no barrier below
   const bool mag = !D.has_geom || gbl(D.geom)[i];
   const int nx = D.nx, ny = D.ny, nz = D.nz;
   const int x = i % nx, yz = i / nx, y = yz % ny, z = yz / ny;
@@ -300,7 +324,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ d
           if (S == 2) t += lb[1][c];
           v += nl[c] * t;
         } else if (D.demag == 2) {
-          v += gbl(D.bd)[c * nc + i];
+          v += D.xfused ? bdv[c] : gbl(D.bd)[c * nc + i];
         }
         if (S == 2) v -= D.BE * lb[1 - s][c];
         mu[c] = v;
@@ -389,7 +413,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__
 }  // namespace mmk
 
 hipError_t mmk_launch_adj(int kind, int stage, int nblocks, int count, const InstDesc* d, const int* wg,
-                          hipStream_t s) {
+                          hipStream_t s, const float2* tw, size_t lds) {
   // kind 0: start, 1: A, 2: B, 3: cavity
   if (kind == 0) {
     MM_LAUNCH(mmk::k_adj_start, dim3(nblocks), dim3(MMI_WG), 0, s, d, wg);
@@ -397,8 +421,8 @@ hipError_t mmk_launch_adj(int kind, int stage, int nblocks, int count, const Ins
   }
 #define MM_ADJ(K, ST)                                                                                  \
   if (kind == K && stage == ST) {                                                                      \
-    if (K == 1) MM_LAUNCH(mmk::k_adj_a<ST>, dim3(nblocks), dim3(MMI_WG), 0, s, d, wg);        \
-    if (K == 2) MM_LAUNCH(mmk::k_adj_b<ST>, dim3(nblocks), dim3(MMI_WG), 0, s, d, wg);        \
+    if (K == 1) MM_LAUNCH(mmk::k_adj_a<ST>, dim3(nblocks), dim3(MMI_WG), lds, s, d, wg, tw);  \
+    if (K == 2) MM_LAUNCH(mmk::k_adj_b<ST>, dim3(nblocks), dim3(MMI_WG), lds, s, d, wg, tw);  \
     return hipGetLastError();                                                                          \
   }
   MM_ADJ(1, 1) MM_ADJ(1, 2) MM_ADJ(1, 3) MM_ADJ(1, 4)

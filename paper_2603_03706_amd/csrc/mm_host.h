@@ -39,5 +39,5 @@ hipError_t mmk_launch_fft_zc(int TW, int nblocks, size_t lds, const InstDesc* d,
                              const float2* tw, hipStream_t s);
 hipError_t mmk_set_lds_limits();
 hipError_t mmk_launch_adj(int kind, int stage, int nblocks, int count, const InstDesc* d, const int* wg,
-                          hipStream_t s);
+                          hipStream_t s, const float2* tw = nullptr, size_t lds = 0);
 hipError_t mmk_launch_gather_done(int count, const InstDesc* d, int* out, hipStream_t s);
