@@ -80,15 +80,20 @@ __global__ __launch_bounds__(256) void k_fft_xf(const InstDesc* __restrict__ des
   float2* twl = lds + Px * WP;
   load_twiddles(twl, Px, tw, 256);
   const int lgx = ilog2(Px);
+  // Entries x >= Px/2 are zero padding (nx <= Px/2): with lines of four or
+  // more points only the lower half is stored here and the first DIF stage
+  // below reads just the two nonzero quarters.
+  const bool pruned = Px >= 4;
+  const int nl = pruned ? Px >> 1 : Px, lgl = pruned ? lgx - 1 : lgx;
   // batches of 8 loads per thread in flight (clamped addresses, padding selected afterwards)
   const bool two = src.p1 != nullptr;
-  for (int e0 = 0; e0 < 2 * W * Px; e0 += 8 * 256) {
+  for (int e0 = 0; e0 < 2 * W * nl; e0 += 8 * 256) {
     float v[8];
     int idx[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * 256 + threadIdx.x;
-      const int rr = e >> lgx, x = e & (Px - 1);
+      const int rr = e >> lgl, x = e & (nl - 1);
       const int rc = min(r0 + rr, rows - 1);
       const int c = rc / nyz, yz = rc - c * nyz;
       idx[u] = c * nc + yz * nx + min(x, nx - 1);
@@ -101,21 +106,41 @@ __global__ __launch_bounds__(256) void k_fft_xf(const InstDesc* __restrict__ des
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * 256 + threadIdx.x;
-      const int rr = e >> lgx, x = e & (Px - 1);
-      if (!(e < 2 * W * Px && x < nx && r0 + rr < rows)) v[u] = 0.f;
+      const int rr = e >> lgl, x = e & (nl - 1);
+      if (!(e < 2 * W * nl && x < nx && r0 + rr < rows)) v[u] = 0.f;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int e = e0 + u * 256 + threadIdx.x;
-      if (e < 2 * W * Px) {
-        const int rr = e >> lgx, x = e & (Px - 1);
+      if (e < 2 * W * nl) {
+        const int rr = e >> lgl, x = e & (nl - 1);
         float* p = reinterpret_cast<float*>(&buf[x * WP + (rr >> 1)]);
         p[rr & 1] = v[u];
       }
     }
   }
   __syncthreads();
-  fft_cols<256, false>(buf, Px, lgx, 1, ilog2(W), 0, WP, twl);
+  if (pruned) {
+    // first radix-2^2 DIF stage (span Px/2) with the arithmetic of the full
+    // stage, zeros for its inputs x2, x3
+    const int q = Px >> 2;
+    const float2 zero = make_float2(0.f, 0.f);
+    for (int e = threadIdx.x; e < W * q; e += 256) {
+      const int ll = e & (W - 1), i = e / W;
+      float2* line = buf + ll;
+      const float2 x0 = line[i * WP], x1 = line[(i + q) * WP];
+      const float2 w1 = twl[i], w2 = twl[2 * i];
+      const float2 a0 = cadd(x0, zero), a1 = cadd(x1, zero);
+      const float2 a2 = cmul(csub(x0, zero), w1);
+      const float2 a3 = rot<false>(cmul(csub(x1, zero), w1));
+      line[i * WP] = cadd(a0, a1);
+      line[(i + q) * WP] = cmul(csub(a0, a1), w2);
+      line[(i + 2 * q) * WP] = cadd(a2, a3);
+      line[(i + 3 * q) * WP] = cmul(csub(a2, a3), w2);
+    }
+    __syncthreads();
+  }
+  fft_cols<256, false>(buf, Px, lgx, 1, ilog2(W), 0, WP, twl, pruned ? 2 : 0);
   const int Kx = D.kx;
   for (int e = threadIdx.x; e < Kx * 2 * W; e += 256) {
     const int kx = e / (2 * W), rr = e - kx * 2 * W;

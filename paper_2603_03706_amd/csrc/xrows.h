@@ -83,21 +83,38 @@ __device__ __forceinline__ void xrows_c2r(const InstDesc& D, const XRows& q, flo
 __device__ __forceinline__ void xrows_r2c(const InstDesc& D, const XRows& q, const float (&v)[3], bool synced) {
   if (!synced) __syncthreads();
   {
-    // line entries x < nx hold the cells, x >= nx the zero padding
+    // line entries x < nx hold the cells; the padding x >= nx is never stored
     const int j = threadIdx.x >> q.lgnx, x = threadIdx.x & (q.nx - 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float* p = reinterpret_cast<float*>(q.zb + c * q.cs + x * q.es + (j >> 1));
       p[j & 1] = v[c];
     }
-    const int pad = q.nx * q.es;
-    for (int e = threadIdx.x; e < 3 * pad; e += MMI_WG) {
-      const int c = (e >= pad) + (e >= 2 * pad);
-      q.zb[c * q.cs + pad + (e - c * pad)] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  {
+    // first radix-2^2 DIF stage (span Px/2): its inputs x2, x3 are the zero
+    // padding, so it reads only x0 = Z[i] and x1 = Z[i + Px/4] and is done
+    // with the arithmetic of the full stage (zeros for x2, x3)
+    const int qq = q.Px >> 2, lgq = q.lgx - 2;
+    const float2 zero = make_float2(0.f, 0.f);
+    for (int e = threadIdx.x; e < 3 * q.J * qq; e += MMI_WG) {
+      const int j2 = e & (q.J - 1), rest = e >> q.lgJ;
+      const int i = rest & (qq - 1), c = rest >> lgq;
+      float2* line = q.zb + c * q.cs + j2;
+      const float2 x0 = line[i * q.es], x1 = line[(i + qq) * q.es];
+      const float2 w1 = q.twl[i], w2 = q.twl[2 * i];
+      const float2 a0 = cadd(x0, zero), a1 = cadd(x1, zero);
+      const float2 a2 = cmul(csub(x0, zero), w1);
+      const float2 a3 = rot<false>(cmul(csub(x1, zero), w1));
+      line[i * q.es] = cadd(a0, a1);
+      line[(i + qq) * q.es] = cmul(csub(a0, a1), w2);
+      line[(i + 2 * qq) * q.es] = cadd(a2, a3);
+      line[(i + 3 * qq) * q.es] = cmul(csub(a2, a3), w2);
     }
   }
   __syncthreads();
-  fft_cols<MMI_WG, false>(q.zb, q.Px, q.lgx, 3, q.lgJ, q.cs, q.es, q.twl);
+  fft_cols<MMI_WG, false>(q.zb, q.Px, q.lgx, 3, q.lgJ, q.cs, q.es, q.twl, 2);
   MMG float2* X = gbl(D.fx);
   // Item (k, c, j2): Z[k] and Z[Px - k] of line j2 separate into the X values
   // of rows 2 j2 (even part) and 2 j2 + 1 (odd part).
