@@ -60,6 +60,21 @@ def test_adjoint_film_fft_demag_profiled_modes():
     _check(inst, steps=30, every=7)
 
 
+def test_adjoint_fft_demag_x_kernels():
+    """FFT demag on a grid whose x size is not a power of two: the x passes
+    run as separate kernels (not inside the stage kernels), in the recompute
+    and in the reverse pass, and the recorded demag fields come from the
+    x-inverse output."""
+    inst = W.multimode_film(6, 5, 3)
+    rng = np.random.default_rng(21)
+    m0 = inst.m0.astype(np.float64).copy()
+    m0[0, 0] += 0.05 * rng.normal(size=m0.shape[2:])
+    m0[0, 1] += 0.05 * rng.normal(size=m0.shape[2:])
+    inst = variant(inst, method="rk4", dt0=0.5e-12, alpha=0.01, m0=m0.astype(np.float32),
+                   a0=np.array([0.8, 0.3j, 0.0, 0.1]))
+    _check(inst, steps=20, every=6)
+
+
 def test_adjoint_afm_neel_coupling():
     inst = W.afm_instance(2, size=8, nz=3)      # phase pi/2, signs (+1, -1)
     m0 = inst.m0.astype(np.float64).copy()
