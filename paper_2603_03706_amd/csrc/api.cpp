@@ -387,6 +387,13 @@ mm_status upload_desc(mm_ctx* c) {
   const mm_params& p = c->p;
   const Layout& L = c->L;
   d.nx = p.nx; d.ny = p.ny; d.nz = p.nz; d.ncell = L.ncell;
+  auto lg_pow2 = [](int n) {
+    int l = 0;
+    while ((1 << l) < n) ++l;
+    return (1 << l) == n ? l : -1;
+  };
+  d.lgnx = lg_pow2(p.nx);
+  d.lgny = lg_pow2(p.ny);
   d.S = p.sublattices; d.N = c->N; d.profiled = c->profiled ? 1 : 0; d.has_geom = p.geometry ? 1 : 0;
   d.demag = p.demag; d.method = c->method; d.nwg = L.nwg; d.wg0 = 0;
   const double cex = 2.0 * p.Aex / p.Ms;

@@ -128,9 +128,8 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
   const MMG double* as = gbl(D.rec_a) + ((size_t)ri * 4 + (ST - 1)) * N * 2;
   const MMG float* const u_ = gbl(D.u);
   MMG float* const lam_B = gbl(D.lam_B);
-  const int x = valid ? i % D.nx : 0;
-  const int yz = valid ? i / D.nx : 0;
-  const int yy = yz % D.ny, zz = yz / D.ny;
+  int x = 0, yy = 0, zz = 0;
+  if (valid) cell_xyz(D, i, x, yy, zz);
 
   float m[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
   if (valid)
@@ -279,7 +278,8 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ d
   if (i >= nc) return;   // no barrier below
   const bool mag = !D.has_geom || gbl(D.geom)[i];
   const int nx = D.nx, ny = D.ny, nz = D.nz;
-  const int x = i % nx, yz = i / nx, y = yz % ny, z = yz / ny;
+  int x, y, z;
+  cell_xyz(D, i, x, y, z);
   const MMG float* L = gbl(D.lam_B);
   const MMG uint8_t* G = D.has_geom ? gbl(D.geom) : nullptr;
   MMG float* const lam_y = gbl(D.lam_y);

@@ -183,6 +183,22 @@ __device__ __forceinline__ int xcd_block() {
   return x * q + min(x, r) + (b >> 3);
 }
 
+// Coordinates of cell i = (z ny + y) nx + x: shifts and masks when nx and ny
+// are powers of two, integer divisions otherwise.
+__device__ __forceinline__ void cell_xyz(const InstDesc& D, int i, int& x, int& y, int& z) {
+  if (D.lgnx >= 0 && D.lgny >= 0) {
+    x = i & (D.nx - 1);
+    const int yz = i >> D.lgnx;
+    y = yz & (D.ny - 1);
+    z = yz >> D.lgny;
+  } else {
+    const int yz = i / D.nx;
+    x = i - yz * D.nx;
+    z = yz / D.ny;
+    y = yz - z * D.ny;
+  }
+}
+
 // max that propagates NaN (a NaN anywhere makes the result NaN)
 __device__ __forceinline__ double nan_max(double a, double b) {
   return (a != a || b != b) ? (a + b) : fmax(a, b);

@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_fft_xf(const InstDesc* __restrict__ des
       const int e = e0 + u * 256 + threadIdx.x;
       const int rr = e >> lgl, x = e & (nl - 1);
       const int rc = min(r0 + rr, rows - 1);
-      const int c = rc / nyz, yz = rc - c * nyz;
+      const int c = (rc >= nyz) + (rc >= 2 * nyz), yz = rc - c * nyz;
       idx[u] = c * nc + yz * nx + min(x, nx - 1);
       v[u] = src.p0[idx[u]];
     }

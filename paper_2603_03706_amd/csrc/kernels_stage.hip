@@ -148,9 +148,8 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
     if (kC2R) xrows_c2r(D, xq, bdv);
   }
 
-  const int x = valid ? i % D.nx : 0;
-  const int yz = valid ? i / D.nx : 0;
-  const int yy = yz % D.ny, zz = yz / D.ny;
+  int x = 0, yy = 0, zz = 0;
+  if (valid) cell_xyz(D, i, x, yy, zz);
 
   float m[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
   float k[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};

@@ -57,6 +57,7 @@ struct InstCtl {
 // Read-only per-instance descriptor (device memory).
 struct InstDesc {
   int nx, ny, nz, ncell;
+  int lgnx, lgny;                     // log2 of nx, ny when powers of two, else -1
   int S, N, profiled, has_geom;
   int demag, method, nwg, wg0;
   float cex_x, cex_y, cex_z;          // (2A/Ms)/d^2 per axis
