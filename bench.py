@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--no-film", action="store_true")
     ap.add_argument("--film-steps", type=int, default=100)
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="short run for rocprofv3 --pmc: tune, a marker copy, the per-kernel profile phase, a marker copy")
+                    help="short run for rocprofv3 --pmc: a marker copy, the per-kernel profile phase, a marker copy")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON", "COMMAND"),
                     help="write the per-phase kernel time summary of a rocprofv3 --kernel-trace run (markdown)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_JSON"),
@@ -196,12 +196,17 @@ def summarize_trace(trace_csv, bench_json, command):
 
 def pmc_probe(args):
     """Between two marker copies: the per-kernel profile phase of the
-    benchmark (the whole batch, eager launches, the tuned FFT choices)."""
+    benchmark (the whole batch, eager launches).  The FFT strategy is fixed
+    to the one the tuner picks on this workload (eight-lane y-z kernel, x
+    passes in the stage kernels) rather than timed again, since counter
+    collection distorts the tuner's timings."""
     import torch
     insts, ctxs, batch = build_batch(args.instances, args.tol)
-    if args.streams:
-        batch.set_streams(args.streams)
-    tuning = None if args.no_tune else batch.tune(streams=not args.streams)
+    batch.set_fft_path("reg8")
+    batch.set_fft_x("stage")
+    nx = insts[0].grid[0]
+    tuning = [{"grid": list(insts[0].grid), "Wx": max(1, min(16, 1024 // padded(nx))), "x_stage": True,
+               "path": "reg8", "Wy": None, "TW": None, "TK": None}]
     batch.step(3, args.tol)
     src = torch.ones(MARKER_ELEMS, device="cuda")
     dst = torch.empty_like(src)
