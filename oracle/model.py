@@ -9,7 +9,10 @@ sublattices), zero on non-magnetic cells; a, complex, shape (N,).
 Equations (SI units, fields in tesla, rates in rad/s):
   * cavity modes, Sec. II A Eq. (1) and Sec. II E Eq. (12), with the
     dissipative phase of Sec. IV H Eq. (19) written as g e^{-i Phi}:
-        da_n/dt = (-i w_n - k_n) a_n + i g_n e^{-i Phi_n} m^-_n
+        da_n/dt = (-i w_n - k_n) a_n + i g_n e^{-i Phi_n} m^-_n + eta_n(t)
+    with the external microwave drive eta_n(t) of Eq. (1) / Eq. (12) taken as
+    the Gaussian pulse of Sec. IV A, eta_n(t) = A_n exp(-(t - t0_n)^2 / (2 sigma_n^2))
+    with a complex amplitude A_n [1/s] (zero when no drive is set)
   * co-rotating average, Eq. (2) weighted by the mode profile as in Eq. (18):
         m^-_n = 1/N_geo sum_i G_i u_n(r_i) (1/S) sum_s c_s (m_sx - i m_sy)
   * RF feedback along x, Eq. (3) and Eq. (13), h0_n = 2 g_n / gamma (Eq. (5)):
@@ -55,6 +58,10 @@ class Problem:
     u: Optional[np.ndarray] = None           # (N, nz, ny, nx); None = uniform
     phi: Optional[Sequence[float]] = None    # (N,); None = 0
     csign: Optional[Sequence[float]] = None  # (S,); None = +1
+    # Gaussian cavity drive eta_n(t); None = undriven
+    drive_amp: Optional[Sequence[complex]] = None   # (N,) complex amplitude [1/s]
+    drive_t0: Optional[Sequence[float]] = None      # (N,) pulse centre [s]
+    drive_sigma: Optional[Sequence[float]] = None   # (N,) pulse width [s], > 0
 
     @property
     def n_modes(self):
@@ -102,6 +109,11 @@ class Model:
             self.u = torch.ones((N,) + self.shape, dtype=torch.float64)
         else:
             self.u = torch.tensor(np.asarray(p.u, float).reshape((N,) + self.shape))
+        self.drive_on = p.drive_amp is not None
+        if self.drive_on:
+            self.drive_amp = torch.tensor(np.asarray(p.drive_amp, complex))
+            self.drive_t0 = torch.tensor(np.asarray(p.drive_t0, float))
+            self.drive_sigma = torch.tensor(np.asarray(p.drive_sigma, float))
         cs = np.ones(self.S) if p.csign is None else np.asarray(p.csign, float)
         self.csign = torch.tensor(cs)
         self.spectrum = None
@@ -184,15 +196,25 @@ class Model:
         mm = (self.csign.view(-1, 1, 1, 1) * (m[:, 0] - 1j * m[:, 1])).sum(0) / self.S
         return (self.u * (self.G * mm)).sum(dim=(1, 2, 3)) / self.n_geo
 
-    def cavity_rhs(self, a, mminus):
-        return (-1j * self.omega - self.kappa) * a + 1j * self.g * torch.exp(-1j * self.phi) * mminus
+    def drive(self, t):
+        """eta_n(t), complex (N,): the Gaussian pulse of Sec. IV A."""
+        x = (t - self.drive_t0) / self.drive_sigma
+        return self.drive_amp * torch.exp(-0.5 * x * x)
 
-    def rhs(self, m, a):
-        """(dm/dt, da/dt, m^-) at state (m, a)."""
+    def cavity_rhs(self, a, mminus, t=0.0):
+        """Eq. (12) with the dissipative phase of Eq. (19); the drive enters
+        only when one is set, at the time t of the stage."""
+        f = (-1j * self.omega - self.kappa) * a + 1j * self.g * torch.exp(-1j * self.phi) * mminus
+        if self.drive_on:
+            f = f + self.drive(t)
+        return f
+
+    def rhs(self, m, a, t=0.0):
+        """(dm/dt, da/dt, m^-) at state (m, a) and time t."""
         B = self.field(m, a)
         km = self.torque(m, B)
         mm = self.m_minus(m)
-        return km, self.cavity_rhs(a, mm), mm
+        return km, self.cavity_rhs(a, mm, t), mm
 
     def normalize(self, m):
         """m / |m| on magnetic cells, unchanged (zero) elsewhere.  The norm is

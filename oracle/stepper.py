@@ -17,6 +17,9 @@ adaptive RK45 step as the LLG equation), with no operator splitting.
     follows a rejection.  The stage-7 point is the normalised candidate.
   * after every accepted step m <- m/|m| on magnetic cells.
   * the last step is clipped so that the run ends exactly on t0 + T.
+  * stage s of a step from t with size h is evaluated at t + c_s h (RK4:
+    c = 0, 1/2, 1/2, 1; DP45: the c column of the tableau), which matters
+    only for the time-dependent cavity drive.
 
 Status values: 0 ok, -5 step size below dt_min, -6 non-finite state.
 """
@@ -96,17 +99,18 @@ class Stepper:
     def _rk4_step(self, h):
         M = self.model
         y, a = self.m, self.a
-        k1, ka1, _ = M.rhs(y, a)
-        k2, ka2, _ = M.rhs(y + 0.5 * h * k1, a + 0.5 * h * ka1)
-        k3, ka3, _ = M.rhs(y + 0.5 * h * k2, a + 0.5 * h * ka2)
-        k4, ka4, _ = M.rhs(y + h * k3, a + h * ka3)
+        t = self.t
+        k1, ka1, _ = M.rhs(y, a, t)
+        k2, ka2, _ = M.rhs(y + 0.5 * h * k1, a + 0.5 * h * ka1, t + 0.5 * h)
+        k3, ka3, _ = M.rhs(y + 0.5 * h * k2, a + 0.5 * h * ka2, t + 0.5 * h)
+        k4, ka4, _ = M.rhs(y + h * k3, a + h * ka3, t + h)
         y_new = M.normalize(y + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4))
         a_new = a + h / 6.0 * (ka1 + 2 * ka2 + 2 * ka3 + ka4)
         return y_new, a_new
 
     def _dp_first(self):
         M = self.model
-        k1, ka1, mm1 = M.rhs(self.m, self.a)
+        k1, ka1, mm1 = M.rhs(self.m, self.a, self.t)
         self.fsal = (k1, ka1, mm1, self.m_minus_rate(k1))
 
     def _dp_step(self, h):
@@ -125,7 +129,7 @@ class Stepper:
             if s == 6:
                 ys = M.normalize(ys)
                 y_cand, a_cand = ys, as_
-            k, ka, mm = M.rhs(ys, as_)
+            k, ka, mm = M.rhs(ys, as_, self.t + DP_C[s] * h)
             ks.append(k)
             kas.append(ka)
         Em = torch.zeros_like(y)

@@ -48,6 +48,9 @@ class Instance:
     u: Optional[np.ndarray] = None             # float32 (N, nz, ny, nx)
     phi: Optional[np.ndarray] = None
     csign: Optional[np.ndarray] = None         # int8 (S,)
+    drive_amp: Optional[np.ndarray] = None     # complex128 (N,) Gaussian drive amplitude [1/s]
+    drive_t0: Optional[np.ndarray] = None      # (N,) pulse centre [s]
+    drive_sigma: Optional[np.ndarray] = None   # (N,) pulse width [s]
     m0: Optional[np.ndarray] = None            # float32 (S, 3, nz, ny, nx)
     a0: Optional[np.ndarray] = None            # complex128 (N,)
     method: str = "rk4"
@@ -71,7 +74,10 @@ class Instance:
                     omega=list(self.omega), kappa=list(self.kappa), g=list(self.g),
                     u=None if self.u is None else self.u.astype(np.float64),
                     phi=None if self.phi is None else list(self.phi),
-                    csign=None if self.csign is None else list(self.csign.astype(float)))
+                    csign=None if self.csign is None else list(self.csign.astype(float)),
+                    drive_amp=None if self.drive_amp is None else list(self.drive_amp),
+                    drive_t0=None if self.drive_t0 is None else list(self.drive_t0),
+                    drive_sigma=None if self.drive_sigma is None else list(self.drive_sigma))
 
 
 def tilted(grid, theta_deg, azimuth, sublattices=1):
@@ -120,6 +126,28 @@ def plain_tiny():
                     omega=np.array([w]), kappa=np.array([TWO_PI * 1e6]), g=np.array([TWO_PI * 50e6]),
                     m0=tilted(grid, 1.0, az), a0=np.zeros(1, complex),
                     method="rk4", dt0=1e-12, tol=0.0, T=20e-9, dt_sample=10e-12)
+
+
+def paper_sim1(B0=None, g=None, kappa=None, T=16e-9, drive_amp=2e8):
+    """Benchmark geometry of Sec. IV and Sim 1 of Table I: an 8x8x1 grid of
+    10 nm cells, Ms = 140 kA/m, A = 3.5 pJ/m, alpha = 3e-4, no demag, m(0) =
+    +z, one uniform mode at 5 GHz with Q = 5000 (kappa = w_c / 2Q) and
+    g/2pi = 50 MHz, B0 at the resonance w_c / gamma unless given [T].  The
+    cavity starts empty and is excited by the Gaussian pulse of Sec. IV A
+    (sigma = 20 ps, t0 = 0.1 ns); the paper gives no amplitude, the default
+    keeps |a| near 1e-2 (linear regime).  RK4 at 1 ps for 16 ns."""
+    grid = (8, 8, 1)
+    wc = TWO_PI * 5.0e9
+    kp = wc / (2 * 5000) if kappa is None else kappa
+    gg = TWO_PI * 50e6 if g is None else g
+    b = wc / GAMMA if B0 is None else B0
+    return Instance(grid=grid, cell=(10e-9,) * 3, Ms=140e3, Aex=3.5e-12, alpha=3e-4,
+                    B0=(0.0, 0.0, b), demag=DEMAG_NONE,
+                    omega=np.array([wc]), kappa=np.array([kp]), g=np.array([gg]),
+                    drive_amp=np.array([complex(drive_amp)]), drive_t0=np.array([0.1e-9]),
+                    drive_sigma=np.array([20e-12]),
+                    m0=tilted(grid, 0.0, 0.0), a0=np.zeros(1, complex),
+                    method="rk4", dt0=1e-12, tol=0.0, T=T, dt_sample=1e-12)
 
 
 def sweep_sphere(k, count=64, n=32):

@@ -625,3 +625,79 @@ def test_dp_trace_matches_fine_rk4():
     # cubic Hermite on steps of a few ps at 5 GHz: O((w h)^4 / 384) ~ 1e-5
     assert np.abs((aa - ab).numpy()).max() < 3e-5 * np.abs(ab.numpy()).max()
     assert np.abs((ma - mb).numpy()).max() < 3e-5 * np.abs(mb.numpy()).max()
+
+
+# ------------------------------------------------ P15 Gaussian cavity drive
+def driven_cavity(t, A, w, kappa, t0, sigma):
+    """a(t) for da/dt = (-i w - kappa) a + A exp(-(t - t0)^2 / (2 sigma^2)),
+    a(0) = 0: the convolution of the pulse with e^{lambda t}, lambda =
+    -i w - kappa, done by completing the square in the exponent, which leaves
+    a difference of error functions of complex argument."""
+    from scipy.special import erf
+    lam = -1j * w - kappa
+    r = math.sqrt(2.0) * sigma
+    z1 = (t - t0 + sigma * sigma * lam) / r
+    z0 = (-t0 + sigma * sigma * lam) / r
+    return (A * sigma * math.sqrt(math.pi / 2) * np.exp(lam * (t - t0) + 0.5 * (sigma * lam) ** 2)
+            * (erf(z1) - erf(z0)))
+
+
+@pytest.mark.parametrize("method,dt,tol,bound", [("rk4", 0.5e-12, 0.0, 5e-8), ("dp45", 1e-12, 1e-12, 5e-7)])
+def test_p15_gaussian_drive_closed_form(method, dt, tol, bound):
+    """g = 0: the driven cavity of Eq. (1) / Eq. (12) with the Gaussian pulse
+    of Sec. IV A against the closed-form response, over the pulse and after
+    it.  Evaluating every stage at the step-start time, a sign or a factor of
+    two in the exponent each miss this bound by orders of magnitude."""
+    w, kp, A, t0, sg = TWO_PI * 5e9, TWO_PI * 0.5e6, (1 + 0.5j) * 2e8, 0.1e-9, 20e-12
+    M = macrospin(omega=[w], kappa=[kp], g=[0.0], drive_amp=[A], drive_t0=[t0], drive_sigma=[sg])
+    st = Stepper(M, state(0, 0), np.zeros(1, complex), method=method, dt0=dt)
+    st.set_sampling(10e-12, 1000)
+    with torch.no_grad():
+        assert st.run(0.4e-9, tol) == OK
+    t, a, _ = st.trace_arrays()
+    want = driven_cavity(t.numpy(), A, w, kp, t0, sg)
+    assert len(t) == 41
+    assert np.abs(a.numpy()[:, 0] - want).max() / np.abs(want).max() < bound
+
+
+def test_p15_drive_off_is_undriven():
+    """No drive set and a drive of zero amplitude give the same run."""
+    kw = dict(omega=[TWO_PI * 5e9], kappa=[TWO_PI * 1e6], g=[TWO_PI * 50e6], B0=(0, 0, 0.17))
+    outs = []
+    for extra in ({}, dict(drive_amp=[0j], drive_t0=[0.1e-9], drive_sigma=[20e-12])):
+        st = Stepper(macrospin(**kw, **extra), state(1, 0.3), np.array([0.01 + 0j]), dt0=1e-12)
+        with torch.no_grad():
+            st.run(0.2e-9)
+        outs.append((st.m.clone(), st.a.clone()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_p15_paper_sim1_splitting():
+    """Sim 1 of Table I at resonance with the protocol of Sec. IV A: the pulse
+    excites both polaritons and the peaks of |FFT m^-|^2 + |FFT a|^2 sit at the
+    branches of Eq. (6), w_c +- g, within 2 MHz (the paper reports an RMSE of
+    17 MHz over its sweep)."""
+    P = GOLD["anticrossing_protocol"]
+    inst = W.paper_sim1()
+    assert inst.grid == tuple(P["geometry"]["grid"]) and inst.cell[0] == P["geometry"]["cell_nm"] * 1e-9
+    assert inst.Ms == P["geometry"]["Ms_kA_per_m"] * 1e3 and inst.Aex == P["geometry"]["Aex_pJ_per_m"] * 1e-12
+    assert inst.alpha == P["geometry"]["alpha"]
+    assert math.isclose(inst.drive_sigma[0], P["sigma_ps"] * 1e-12) and math.isclose(inst.drive_t0[0], P["t0_ns"] * 1e-9)
+    assert math.isclose(inst.dt0, P["dt_ps"] * 1e-12) and round(inst.T / inst.dt0) == P["steps"] == P["T_ns"] * 1000
+    assert math.isclose(inst.kappa[0], inst.omega[0] / (2 * P["Q"]))
+    st = Stepper(Model(Problem(**inst.oracle_kwargs())), inst.m0.astype(np.float64), inst.a0, dt0=inst.dt0)
+    st.set_sampling(inst.dt_sample, 100000)
+    with torch.no_grad():
+        assert st.run(inst.T) == OK
+    t, a, mm = st.trace_arrays()
+    # the samples t_k = k dt, k = 0 .. steps (rounding of t can add one last
+    # step of a few zeptoseconds, and its sample, under the clip rule)
+    n = P["steps"] + 1
+    assert len(t) >= n and abs(float(t[n - 1]) - inst.T) < 1e-18
+    assert math.isclose(1.0 / (P["steps"] * inst.dt_sample), P["df_MHz"] * 1e6, rel_tol=1e-9)
+    f, Sa = spectrum(a.numpy()[:n, 0], inst.dt_sample)
+    _, Sm = spectrum(mm.numpy()[:n, 0], inst.dt_sample)
+    got = sorted(peaks(f, Sa + Sm, count=2, fmin=4.8e9, fmax=5.2e9))
+    lo, hi = theory.polariton(inst.omega[0], GAMMA * inst.B0[2], inst.g[0])
+    assert abs(got[0] - lo / TWO_PI) < 2e6 and abs(got[1] - hi / TWO_PI) < 2e6
+    assert abs((got[1] - got[0]) - 2 * P["g_MHz"] * 1e6) < 2e6
