@@ -123,6 +123,16 @@ mm_status mm_set_modes(mm_ctx* ctx, int32_t n, const double* omega, const double
                        const double* g, const float* u, const double* phi,
                        const int8_t* sublattice_sign);
 
+/* External cavity drive eta_n(t) of Eq. (1) / Eq. (12), as the Gaussian
+ * pulse of Sec. IV A: eta_n(t) = A_n exp(-((t - t0_n) / sigma_n)^2 / 2),
+ * added to da_n/dt at the time of every stage (t + c_s h).  amp: host [n][2]
+ * complex amplitude (re, im) [1/s]; t0: pulse centres [s]; sigma: widths
+ * [s], > 0, all finite; n must equal the mode count.  n = 0 or amp = NULL
+ * switches the drive off.  mm_set_modes also switches it off.  Takes effect
+ * from the next run, batched runs included. */
+mm_status mm_set_drive(mm_ctx* ctx, int32_t n, const double* amp, const double* t0,
+                       const double* sigma);
+
 /* Magnetisation, host [S][3][nz][ny][nx].  Normalised per cell on entry;
  * non-magnetic cells are set to 0.  A magnetic cell with |m| = 0 or a
  * non-finite value is rejected with MM_ERR_ARG. */

@@ -246,6 +246,8 @@ struct mm_ctx {
   bool profiled = false;
   std::vector<double> omega, kappa, g, phi;
   int8_t cs[2] = {1, 1};
+  bool drive_on = false;          // Gaussian cavity drive per mode
+  std::vector<double> drive_re, drive_im, drive_t0, drive_sigma;
   // stepper
   int method = MM_RK4;
   double dt0 = 1e-13, dt_min = 1e-18, dt_max = 0.0;
@@ -426,6 +428,14 @@ mm_status upload_desc(mm_ctx* c) {
     d.sphi[n] = std::sin(c->phi[n]);
     d.h0[n] = 2.0 * c->g[n] / p.gamma;
   }
+  d.drive_on = c->drive_on ? 1 : 0;
+  if (c->drive_on)
+    for (int n = 0; n < c->N; ++n) {
+      d.eta_re[n] = c->drive_re[n];
+      d.eta_im[n] = c->drive_im[n];
+      d.eta_t0[n] = c->drive_t0[n];
+      d.eta_sigma[n] = c->drive_sigma[n];
+    }
   char* w = c->ws;
   for (int i = 0; i < 2; ++i) d.y[i] = (float*)(w + L.y[i]);
   for (int i = 0; i < 7; ++i) d.k[i] = (float*)(w + L.k[i]);
@@ -1211,6 +1221,7 @@ mm_status mm_set_modes(mm_ctx* c, int32_t n, const double* omega, const double* 
   if (c->ws_bound && u && n > c->u_cap) return fail(MM_ERR_ARG, "bound workspace has no room for the mode profiles");
   if (mm_status s = ensure_device(c)) return s;
   c->N = n;
+  c->drive_on = false;
   c->omega.assign(omega, omega + n);
   c->kappa.assign(kappa, kappa + n);
   c->g.assign(g, g + n);
@@ -1250,6 +1261,32 @@ mm_status mm_set_modes(mm_ctx* c, int32_t n, const double* omega, const double* 
       c->sampling_changed = true;
     }
   }
+  return upload_desc(c);
+}
+
+mm_status mm_set_drive(mm_ctx* c, int32_t n, const double* amp, const double* t0, const double* sigma) {
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  if (!c->modes_set) return fail(MM_ERR_STATE, "modes not set (mm_set_modes)");
+  if (n == 0 || !amp) {
+    c->drive_on = false;
+    return upload_desc(c);
+  }
+  if (n != c->N) return fail(MM_ERR_ARG, "drive count must equal the mode count");
+  if (!t0 || !sigma) return fail(MM_ERR_ARG, "t0 and sigma are required with an amplitude");
+  for (int i = 0; i < n; ++i) {
+    if (!std::isfinite(amp[2 * i]) || !std::isfinite(amp[2 * i + 1]) || !std::isfinite(t0[i]))
+      return fail(MM_ERR_ARG, "drive parameters must be finite");
+    if (!(sigma[i] > 0) || !std::isfinite(sigma[i])) return fail(MM_ERR_ARG, "drive width sigma must be > 0");
+  }
+  c->drive_re.assign(n, 0.0);
+  c->drive_im.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    c->drive_re[i] = amp[2 * i];
+    c->drive_im[i] = amp[2 * i + 1];
+  }
+  c->drive_t0.assign(t0, t0 + n);
+  c->drive_sigma.assign(sigma, sigma + n);
+  c->drive_on = true;
   return upload_desc(c);
 }
 

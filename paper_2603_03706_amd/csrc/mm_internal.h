@@ -71,6 +71,10 @@ struct InstDesc {
   double gamma;                       // gyromagnetic ratio [rad/(s T)]
   double omega[MMI_MAX_MODES], kappa[MMI_MAX_MODES], g[MMI_MAX_MODES];
   double cphi[MMI_MAX_MODES], sphi[MMI_MAX_MODES], h0[MMI_MAX_MODES];
+  // Gaussian cavity drive eta_n(t) = A_n exp(-((t - t0_n) / sigma_n)^2 / 2)
+  int drive_on, pad_drive;
+  double eta_re[MMI_MAX_MODES], eta_im[MMI_MAX_MODES];
+  double eta_t0[MMI_MAX_MODES], eta_sigma[MMI_MAX_MODES];
   // device buffers
   float* y[2];                        // state [S][3][cells]
   float* k[7];                        // stage derivatives (RK4 uses k[0] as the running sum)
@@ -110,6 +114,7 @@ struct InstDesc {
 
 // Dormand-Prince 5(4) coefficients.
 struct DPCoef {
+  static constexpr double c2 = 1.0 / 5, c3 = 3.0 / 10, c4 = 4.0 / 5, c5 = 8.0 / 9;
   static constexpr double a21 = 1.0 / 5;
   static constexpr double a31 = 3.0 / 40, a32 = 9.0 / 40;
   static constexpr double a41 = 44.0 / 45, a42 = -56.0 / 15, a43 = 32.0 / 9;

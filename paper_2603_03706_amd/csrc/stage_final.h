@@ -9,12 +9,20 @@
 
 namespace mmk {
 
-__device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double ar, double ai, double mr,
-                                        double mi, double& fr, double& fi) {
-  // (-i w - kappa) a + i g e^{-i Phi} m^-
+// Cavity right-hand side of mode n at stage time t: (-i w - kappa) a +
+// i g e^{-i Phi} m^- (Eq. (12) with the phase of Eq. (19)), plus the Gaussian
+// drive eta_n(t) of Eq. (1) when one is set.
+__device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double t, double ar, double ai,
+                                        double mr, double mi, double& fr, double& fi) {
   const double w = D.omega[n], kp = D.kappa[n], g = D.g[n], c = D.cphi[n], s = D.sphi[n];
   fr = -kp * ar + w * ai + g * (s * mr - c * mi);
   fi = -w * ar - kp * ai + g * (s * mi + c * mr);
+  if (D.drive_on) {
+    const double x = (t - D.eta_t0[n]) / D.eta_sigma[n];
+    const double e = exp(-0.5 * x * x);
+    fr += D.eta_re[n] * e;
+    fi += D.eta_im[n] * e;
+  }
 }
 
 // Block-wide reduction over the workgroup in a fixed order, result valid in
@@ -120,7 +128,7 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   if (METHOD == MMI_RK4) {
     if (ST == 0) {  // run start: m^- of y, first derivative, first step
       for (int n = 0; n < N; ++n) {
-        cav_rhs(D, n, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+        cav_rhs(D, n, C->t, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
         C->mm1[n][0] = mmv[n][0];
         C->mm1[n][1] = mmv[n][1];
         C->as[n][0] = C->a[n][0];
@@ -139,7 +147,8 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
       for (int n = 0; n < N; ++n) {
         const double ar = C->a[n][0] + c * C->ka[ST - 1][n][0];
         const double ai = C->a[n][1] + c * C->ka[ST - 1][n][1];
-        cav_rhs(D, n, ar, ai, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
+        // stage ST + 1 sits at t + c (c = h/2, h/2, h)
+        cav_rhs(D, n, C->t + c, ar, ai, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
         C->as[n][0] = ar;
         C->as[n][1] = ai;
       }
@@ -174,7 +183,7 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
     for (int n = 0; n < N; ++n) {
       C->a[n][0] = C->as[n][0];
       C->a[n][1] = C->as[n][1];
-      cav_rhs(D, n, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+      cav_rhs(D, n, C->t, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
       C->mm1[n][0] = mmv[n][0];
       C->mm1[n][1] = mmv[n][1];
     }
@@ -193,7 +202,7 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   using P = DPCoef;
   if (ST == 1) {  // run start (k1 written by the kernel)
     for (int n = 0; n < N; ++n) {
-      cav_rhs(D, n, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+      cav_rhs(D, n, C->t, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
       C->mm1[n][0] = mmv[n][0];
       C->mm1[n][1] = mmv[n][1];
       C->dmm1[n][0] = tot[MMI_SLOT_DMM + 2 * n];
@@ -215,12 +224,14 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   if (ST == 2) {
     // ka2 at (a2, m^-(m2)) [m2 sums in the DMM slot], then ka3 at (a3, m^-(m3))
     for (int n = 0; n < N; ++n)
-      cav_rhs(D, n, C->as[n][0], C->as[n][1], tot[MMI_SLOT_DMM + 2 * n],
+      cav_rhs(D, n, C->t + P::c2 * h, C->as[n][0], C->as[n][1], tot[MMI_SLOT_DMM + 2 * n],
               tot[MMI_SLOT_DMM + 2 * n + 1], C->ka[1][n][0], C->ka[1][n][1]);
   }
   if (ST >= 2 && ST <= 6) {
     // a_{ST+1} = a + h sum_j A[ST+1][j] ka_j
     double A[6];
+    // node of stage ST + 1
+    const double cn = ST == 2 ? P::c3 : ST == 3 ? P::c4 : ST == 4 ? P::c5 : 1.0;
     if (ST == 2) { A[0] = P::a31; A[1] = P::a32; }
     if (ST == 3) { A[0] = P::a41; A[1] = P::a42; A[2] = P::a43; }
     if (ST == 4) { A[0] = P::a51; A[1] = P::a52; A[2] = P::a53; A[3] = P::a54; }
@@ -234,7 +245,7 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
       }
       const double ar = C->a[n][0] + h * s0;
       const double ai = C->a[n][1] + h * s1;
-      cav_rhs(D, n, ar, ai, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
+      cav_rhs(D, n, C->t + cn * h, ar, ai, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
       C->as[n][0] = ar;
       C->as[n][1] = ai;
       if (ST == 6) {

@@ -56,6 +56,7 @@ _SIGS = {
     "mm_set_modes": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P]),
     "mm_set_m": (ctypes.c_int, [_P, _P]),
     "mm_set_a": (ctypes.c_int, [_P, _P]),
+    "mm_set_drive": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "mm_set_stepper": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "mm_set_sampling": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64]),
     "mm_run": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
@@ -167,6 +168,8 @@ class Context:
                 demag=inst.demag, n_local=inst.n_local, geometry=inst.geometry,
                 sublattices=inst.sublattices, B_E=inst.B_E)
         c.set_modes(inst.omega, inst.kappa, inst.g, u=inst.u, phi=inst.phi, csign=inst.csign)
+        if getattr(inst, "drive_amp", None) is not None:
+            c.set_drive(inst.drive_amp, inst.drive_t0, inst.drive_sigma)
         c.set_m(inst.m0)
         c.set_a(inst.a0)
         c.set_stepper(RK4 if inst.method == "rk4" else DP45, inst.dt0)
@@ -182,6 +185,18 @@ class Context:
         cs = None if csign is None else np.ascontiguousarray(csign, np.int8)
         _check(self._lib.mm_set_modes(self.h, n, _ptr(om), _ptr(ka), _ptr(gg), _ptr(uu), _ptr(ph), _ptr(cs)))
         self.N = n
+
+    def set_drive(self, amp=None, t0=None, sigma=None):
+        """Gaussian cavity drive A_n exp(-((t - t0_n)/sigma_n)^2 / 2) per mode
+        (complex amplitudes [1/s]); amp=None switches it off."""
+        if amp is None:
+            _check(self._lib.mm_set_drive(self.h, 0, None, None, None))
+            return
+        a = np.asarray(amp, np.complex128)
+        buf = np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1).reshape(-1))
+        t = np.ascontiguousarray(t0, np.float64)
+        sg = np.ascontiguousarray(sigma, np.float64)
+        _check(self._lib.mm_set_drive(self.h, len(a), _ptr(buf), _ptr(t), _ptr(sg)))
 
     def set_m(self, m):
         mm = np.ascontiguousarray(m, np.float32)

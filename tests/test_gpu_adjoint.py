@@ -147,3 +147,12 @@ def test_autograd_function_matches_adjoint_and_differences():
     fd = (f(1.0) - f(-1.0)) / 2.0
     pred = float(g.grad.numpy() @ dg + al.grad.item() * dal + b0.grad.numpy() @ db)
     assert abs(fd - pred) <= 2e-2 * abs(pred), (fd, pred)
+
+
+def test_adjoint_with_cavity_drive():
+    """Sim 1 geometry of Table I over the Gaussian pulse of Sec. IV A (150
+    steps of 1 ps, segments of 64 and a ragged 22): the drive is additive and
+    independent of the state, so the reverse pass is that of the undriven
+    map while the recompute must reproduce the driven stages."""
+    inst = variant(W.paper_sim1(), a0=np.array([0.002 + 0.001j]))
+    _check(inst, steps=150, every=64, mode=0)
