@@ -13,6 +13,10 @@ Equations (SI units, fields in tesla, rates in rad/s):
     with the external microwave drive eta_n(t) of Eq. (1) / Eq. (12) taken as
     the Gaussian pulse of Sec. IV A, eta_n(t) = A_n exp(-(t - t0_n)^2 / (2 sigma_n^2))
     with a complex amplitude A_n [1/s] (zero when no drive is set)
+  * cavity-model variants of Sec. II A and Sec. V (optional, per mode):
+    nonreciprocal coupling, g_n (= g_f) in the cavity equation and
+    h0_n = 2 g_b,n / gamma in the feedback; a self-Kerr term
+    -i K_n |a_n|^2 a_n added to da_n/dt
   * co-rotating average, Eq. (2) weighted by the mode profile as in Eq. (18):
         m^-_n = 1/N_geo sum_i G_i u_n(r_i) (1/S) sum_s c_s (m_sx - i m_sy)
   * RF feedback along x, Eq. (3) and Eq. (13), h0_n = 2 g_n / gamma (Eq. (5)):
@@ -58,6 +62,8 @@ class Problem:
     u: Optional[np.ndarray] = None           # (N, nz, ny, nx); None = uniform
     phi: Optional[Sequence[float]] = None    # (N,); None = 0
     csign: Optional[Sequence[float]] = None  # (S,); None = +1
+    g_back: Optional[Sequence[float]] = None   # (N,) backward coupling g_b [rad/s]; None = g
+    kerr: Optional[Sequence[float]] = None     # (N,) self-Kerr K [rad/s]; None = 0
     # Gaussian cavity drive eta_n(t); None = undriven
     drive_amp: Optional[Sequence[complex]] = None   # (N,) complex amplitude [1/s]
     drive_t0: Optional[Sequence[float]] = None      # (N,) pulse centre [s]
@@ -102,7 +108,11 @@ class Model:
         self.kappa = torch.tensor(np.asarray(p.kappa, float))
         self.g = leaves["g"] if "g" in leaves else torch.tensor(np.asarray(p.g, float))
         self.phi = torch.tensor(np.zeros(N) if p.phi is None else np.asarray(p.phi, float))
-        self.h0 = 2.0 * self.g / p.gamma                             # Eq. (5)
+        if p.g_back is None:
+            self.h0 = 2.0 * self.g / p.gamma                         # Eq. (5)
+        else:
+            self.h0 = 2.0 * torch.tensor(np.asarray(p.g_back, float)) / p.gamma
+        self.kerr = None if p.kerr is None else torch.tensor(np.asarray(p.kerr, float))
         if "u" in leaves:
             self.u = leaves["u"]
         elif p.u is None:
@@ -202,9 +212,11 @@ class Model:
         return self.drive_amp * torch.exp(-0.5 * x * x)
 
     def cavity_rhs(self, a, mminus, t=0.0):
-        """Eq. (12) with the dissipative phase of Eq. (19); the drive enters
-        only when one is set, at the time t of the stage."""
+        """Eq. (12) with the dissipative phase of Eq. (19); the Kerr term and
+        the drive enter only when set, the drive at the time t of the stage."""
         f = (-1j * self.omega - self.kappa) * a + 1j * self.g * torch.exp(-1j * self.phi) * mminus
+        if self.kerr is not None:
+            f = f - 1j * self.kerr * (a.real * a.real + a.imag * a.imag) * a
         if self.drive_on:
             f = f + self.drive(t)
         return f

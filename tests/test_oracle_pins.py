@@ -701,3 +701,35 @@ def test_p15_paper_sim1_splitting():
     lo, hi = theory.polariton(inst.omega[0], GAMMA * inst.B0[2], inst.g[0])
     assert abs(got[0] - lo / TWO_PI) < 2e6 and abs(got[1] - hi / TWO_PI) < 2e6
     assert abs((got[1] - got[0]) - 2 * P["g_MHz"] * 1e6) < 2e6
+
+
+# ------------------------------------- P16 cavity-model variants (Sec. II A, V)
+@pytest.mark.parametrize("method", ["rk4", "dp45"])
+def test_p16_kerr_closed_form(method):
+    """g = 0, da/dt = (-i w - kappa) a - i K |a|^2 a: |a| decays as e^{-kappa t}
+    and the phase advances by w t + K |a0|^2 (1 - e^{-2 kappa t}) / (2 kappa)."""
+    w, kp, K, a0 = TWO_PI * 5e9, TWO_PI * 20e6, TWO_PI * 2e9, 0.3 + 0.1j
+    M = macrospin(omega=[w], kappa=[kp], g=[0.0], kerr=[K])
+    st = Stepper(M, state(0, 0), np.array([a0]), method=method, dt0=0.5e-12)
+    st.set_sampling(10e-12, 1000)
+    with torch.no_grad():
+        assert st.run(2e-9, 1e-12) == OK
+    t, a, _ = st.trace_arrays()
+    t = t.numpy()
+    want = a0 * np.exp((-1j * w - kp) * t) * np.exp(-1j * K * abs(a0) ** 2 * (1 - np.exp(-2 * kp * t)) / (2 * kp))
+    assert np.abs(a.numpy()[:, 0] - want).max() / abs(a0) < (2e-7 if method == "rk4" else 2e-8)
+
+
+def test_p16_nonreciprocal_splitting():
+    """g_f != g_b at resonance: (w - w_c)(w - w_m) = g_f g_b, so the branches
+    sit at w_c +- sqrt(g_f g_b) (the reciprocal splitting 2g with g^2 -> g_f g_b)."""
+    wc, gf, gb = TWO_PI * 5e9, TWO_PI * 50e6, TWO_PI * 12.5e6
+    kw = dict(alpha=1e-4, B0=(0, 0, wc / GAMMA), omega=[wc], kappa=[TWO_PI * 1e6])
+    wm = -co_rotating_rates(macrospin(g=[0.0], **kw), state(0.5, 0), np.zeros(1, complex), T=2e-9,
+                            count=1, channels="m")[0].imag
+    M = macrospin(g=[gf], g_back=[gb], **kw)
+    s = co_rotating_rates(M, state(0, 0), np.array([0.01 + 0j]), T=10e-9)
+    got = sorted(-s.imag)
+    mid, half = 0.5 * (wc + wm), math.sqrt(0.25 * (wc - wm) ** 2 + gf * gb)
+    assert abs(got[0] - (mid - half)) / TWO_PI < 1e6 and abs(got[1] - (mid + half)) / TWO_PI < 1e6
+    assert abs((got[1] - got[0]) / TWO_PI - 2 * 25e6) < 2e6
