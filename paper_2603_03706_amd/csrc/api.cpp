@@ -246,6 +246,9 @@ struct mm_ctx {
   bool profiled = false;
   std::vector<double> omega, kappa, g, phi;
   int8_t cs[2] = {1, 1};
+  bool nonrecip = false;          // backward coupling g_b set (h0 = 2 g_b / gamma)
+  bool kerr_on = false;           // self-Kerr term set
+  std::vector<double> g_back, kerr;
   bool drive_on = false;          // Gaussian cavity drive per mode
   std::vector<double> drive_re, drive_im, drive_t0, drive_sigma;
   // stepper
@@ -426,8 +429,11 @@ mm_status upload_desc(mm_ctx* c) {
     d.g[n] = c->g[n];
     d.cphi[n] = std::cos(c->phi[n]);
     d.sphi[n] = std::sin(c->phi[n]);
-    d.h0[n] = 2.0 * c->g[n] / p.gamma;
+    d.h0[n] = 2.0 * (c->nonrecip ? c->g_back[n] : c->g[n]) / p.gamma;
   }
+  d.kerr_on = c->kerr_on ? 1 : 0;
+  if (c->kerr_on)
+    for (int n = 0; n < c->N; ++n) d.kerr[n] = c->kerr[n];
   d.drive_on = c->drive_on ? 1 : 0;
   if (c->drive_on)
     for (int n = 0; n < c->N; ++n) {
@@ -1222,6 +1228,8 @@ mm_status mm_set_modes(mm_ctx* c, int32_t n, const double* omega, const double* 
   if (mm_status s = ensure_device(c)) return s;
   c->N = n;
   c->drive_on = false;
+  c->nonrecip = false;
+  c->kerr_on = false;
   c->omega.assign(omega, omega + n);
   c->kappa.assign(kappa, kappa + n);
   c->g.assign(g, g + n);
@@ -1261,6 +1269,21 @@ mm_status mm_set_modes(mm_ctx* c, int32_t n, const double* omega, const double* 
       c->sampling_changed = true;
     }
   }
+  return upload_desc(c);
+}
+
+mm_status mm_set_cavity_model(mm_ctx* c, int32_t n, const double* g_back, const double* kerr) {
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  if (!c->modes_set) return fail(MM_ERR_STATE, "modes not set (mm_set_modes)");
+  if (n != 0 && n != c->N) return fail(MM_ERR_ARG, "count must equal the mode count");
+  if (n == 0) g_back = kerr = nullptr;
+  for (int i = 0; i < n; ++i)
+    if ((g_back && !std::isfinite(g_back[i])) || (kerr && !std::isfinite(kerr[i])))
+      return fail(MM_ERR_ARG, "cavity-model parameters must be finite");
+  c->nonrecip = g_back != nullptr;
+  c->kerr_on = kerr != nullptr;
+  if (g_back) c->g_back.assign(g_back, g_back + n);
+  if (kerr) c->kerr.assign(kerr, kerr + n);
   return upload_desc(c);
 }
 
@@ -1524,6 +1547,8 @@ void restore_forward(InstCtl& dst, const InstCtl& ck) {
 mm_status mm_run_record(mm_ctx* c, double T, int32_t every) {
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (c->method != MM_RK4) return fail(MM_ERR_STATE, "recording needs the fixed-step RK4 method");
+  if (c->nonrecip || c->kerr_on)
+    return fail(MM_ERR_STATE, "the adjoint covers reciprocal coupling without a Kerr term");
   if (!(T > 0) || !std::isfinite(T) || every < 1) return fail(MM_ERR_ARG, "need T > 0 and checkpoint_every >= 1");
   if (mm_status s = check_ready(c)) return s;
   const double r = T / c->dt0;
@@ -1560,6 +1585,8 @@ mm_status mm_adjoint(mm_ctx* c, const double* dL_da, const float* dL_dm, float* 
                      double* grad_alpha, double* grad_B0, double* grad_a0, float* grad_m0) {
   if (!c || !dL_da) return fail(MM_ERR_ARG, "NULL context or dL_da");
   if (!c->rec_have) return fail(MM_ERR_STATE, "no recorded run (mm_run_record)");
+  if (c->nonrecip || c->kerr_on)
+    return fail(MM_ERR_STATE, "the adjoint covers reciprocal coupling without a Kerr term");
   if (mm_status s = set_device(c)) return s;
   const int N = c->N, S = c->p.sublattices, K = c->rec_K;
   const size_t nc = (size_t)c->L.ncell, vec = (size_t)3 * S * nc;

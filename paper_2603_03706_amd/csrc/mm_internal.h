@@ -71,6 +71,9 @@ struct InstDesc {
   double gamma;                       // gyromagnetic ratio [rad/(s T)]
   double omega[MMI_MAX_MODES], kappa[MMI_MAX_MODES], g[MMI_MAX_MODES];
   double cphi[MMI_MAX_MODES], sphi[MMI_MAX_MODES], h0[MMI_MAX_MODES];
+  // self-Kerr term -i K_n |a_n|^2 a_n of the cavity equation
+  int kerr_on, pad_kerr;
+  double kerr[MMI_MAX_MODES];
   // Gaussian cavity drive eta_n(t) = A_n exp(-((t - t0_n) / sigma_n)^2 / 2)
   int drive_on, pad_drive;
   double eta_re[MMI_MAX_MODES], eta_im[MMI_MAX_MODES];

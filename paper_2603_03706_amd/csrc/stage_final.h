@@ -10,13 +10,18 @@
 namespace mmk {
 
 // Cavity right-hand side of mode n at stage time t: (-i w - kappa) a +
-// i g e^{-i Phi} m^- (Eq. (12) with the phase of Eq. (19)), plus the Gaussian
-// drive eta_n(t) of Eq. (1) when one is set.
+// i g e^{-i Phi} m^- (Eq. (12) with the phase of Eq. (19)), plus, when set,
+// the self-Kerr term -i K |a|^2 a and the Gaussian drive eta_n(t) of Eq. (1).
 __device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double t, double ar, double ai,
                                         double mr, double mi, double& fr, double& fi) {
   const double w = D.omega[n], kp = D.kappa[n], g = D.g[n], c = D.cphi[n], s = D.sphi[n];
   fr = -kp * ar + w * ai + g * (s * mr - c * mi);
   fi = -w * ar - kp * ai + g * (s * mi + c * mr);
+  if (D.kerr_on) {
+    const double q = D.kerr[n] * (ar * ar + ai * ai);
+    fr += q * ai;
+    fi -= q * ar;
+  }
   if (D.drive_on) {
     const double x = (t - D.eta_t0[n]) / D.eta_sigma[n];
     const double e = exp(-0.5 * x * x);
