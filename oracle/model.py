@@ -17,6 +17,9 @@ Equations (SI units, fields in tesla, rates in rad/s):
     nonreciprocal coupling, g_n (= g_f) in the cavity equation and
     h0_n = 2 g_b,n / gamma in the feedback; a self-Kerr term
     -i K_n |a_n|^2 a_n added to da_n/dt
+  * direct photon-photon coupling (the H_13 entry of the Sec. II F
+    Hamiltonian, Eq. (9)): da_n/dt gains -i sum_m J_nm a_m with J real
+    symmetric and zero on the diagonal
   * co-rotating average, Eq. (2) weighted by the mode profile as in Eq. (18):
         m^-_n = 1/N_geo sum_i G_i u_n(r_i) (1/S) sum_s c_s (m_sx - i m_sy)
   * RF feedback along x, Eq. (3) and Eq. (13), h0_n = 2 g_n / gamma (Eq. (5)):
@@ -64,6 +67,7 @@ class Problem:
     csign: Optional[Sequence[float]] = None  # (S,); None = +1
     g_back: Optional[Sequence[float]] = None   # (N,) backward coupling g_b [rad/s]; None = g
     kerr: Optional[Sequence[float]] = None     # (N,) self-Kerr K [rad/s]; None = 0
+    photon_coupling: Optional[np.ndarray] = None  # (N, N) J [rad/s], symmetric, zero diagonal; None = 0
     # Gaussian cavity drive eta_n(t); None = undriven
     drive_amp: Optional[Sequence[complex]] = None   # (N,) complex amplitude [1/s]
     drive_t0: Optional[Sequence[float]] = None      # (N,) pulse centre [s]
@@ -113,6 +117,7 @@ class Model:
         else:
             self.h0 = 2.0 * torch.tensor(np.asarray(p.g_back, float)) / p.gamma
         self.kerr = None if p.kerr is None else torch.tensor(np.asarray(p.kerr, float))
+        self.J = None if p.photon_coupling is None else torch.tensor(np.asarray(p.photon_coupling, float))
         if "u" in leaves:
             self.u = leaves["u"]
         elif p.u is None:
@@ -217,6 +222,8 @@ class Model:
         f = (-1j * self.omega - self.kappa) * a + 1j * self.g * torch.exp(-1j * self.phi) * mminus
         if self.kerr is not None:
             f = f - 1j * self.kerr * (a.real * a.real + a.imag * a.imag) * a
+        if self.J is not None:
+            f = f - 1j * (self.J.to(a.dtype) @ a)
         if self.drive_on:
             f = f + self.drive(t)
         return f

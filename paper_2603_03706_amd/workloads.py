@@ -50,6 +50,7 @@ class Instance:
     csign: Optional[np.ndarray] = None         # int8 (S,)
     g_back: Optional[np.ndarray] = None        # (N,) backward coupling g_b [rad/s] (None: g)
     kerr: Optional[np.ndarray] = None          # (N,) self-Kerr coefficient [rad/s] (None: 0)
+    photon_coupling: Optional[np.ndarray] = None  # (N, N) direct mode coupling J [rad/s] (None: 0)
     drive_amp: Optional[np.ndarray] = None     # complex128 (N,) Gaussian drive amplitude [1/s]
     drive_t0: Optional[np.ndarray] = None      # (N,) pulse centre [s]
     drive_sigma: Optional[np.ndarray] = None   # (N,) pulse width [s]
@@ -79,6 +80,7 @@ class Instance:
                     csign=None if self.csign is None else list(self.csign.astype(float)),
                     g_back=None if self.g_back is None else list(self.g_back),
                     kerr=None if self.kerr is None else list(self.kerr),
+                    photon_coupling=None if self.photon_coupling is None else np.asarray(self.photon_coupling, float),
                     drive_amp=None if self.drive_amp is None else list(self.drive_amp),
                     drive_t0=None if self.drive_t0 is None else list(self.drive_t0),
                     drive_sigma=None if self.drive_sigma is None else list(self.drive_sigma))

@@ -733,3 +733,40 @@ def test_p16_nonreciprocal_splitting():
     mid, half = 0.5 * (wc + wm), math.sqrt(0.25 * (wc - wm) ** 2 + gf * gb)
     assert abs(got[0] - (mid - half)) / TWO_PI < 1e6 and abs(got[1] - (mid + half)) / TWO_PI < 1e6
     assert abs((got[1] - got[0]) / TWO_PI - 2 * 25e6) < 2e6
+
+
+@pytest.mark.parametrize("method", ["rk4", "dp45"])
+def test_p16_photon_coupling_two_cavities(method):
+    """g = 0, two equal cavities joined by J (the H_13 entry of Eq. (9)):
+    a_1 = e^{(-i w - kappa) t} (a_1(0) cos Jt - i a_2(0) sin Jt), and the
+    same with 1 and 2 swapped."""
+    w, kp, J = TWO_PI * 5e9, TWO_PI * 3e6, TWO_PI * 80e6
+    a0 = np.array([0.02 + 0.01j, -0.005j])
+    M = macrospin(omega=[w, w], kappa=[kp, kp], g=[0.0, 0.0], photon_coupling=np.array([[0.0, J], [J, 0.0]]))
+    st = Stepper(M, state(0, 0), a0, method=method, dt0=0.5e-12)
+    st.set_sampling(10e-12, 1000)
+    with torch.no_grad():
+        assert st.run(3e-9, 1e-14) == OK
+    t, a, _ = st.trace_arrays()
+    t = t.numpy()[:, None]
+    e = np.exp((-1j * w - kp) * t)
+    want = e * np.stack([a0[0] * np.cos(J * t[:, 0]) - 1j * a0[1] * np.sin(J * t[:, 0]),
+                         a0[1] * np.cos(J * t[:, 0]) - 1j * a0[0] * np.sin(J * t[:, 0])], axis=1)
+    assert np.abs(a.numpy() - want).max() / np.abs(a0).max() < (2e-7 if method == "rk4" else 1e-9)
+
+
+def test_p16_three_mode_with_direct_coupling():
+    """Eq. (9) with a nonzero H_13 = J: the rates of the coupled run are the
+    eigenvalues of the 3x3 Hermitian matrix (numpy eigvalsh), and the dark
+    state of the J = 0 case is no longer an eigenvector."""
+    g, J = TWO_PI * 50e6, TWO_PI * 30e6
+    wm = TWO_PI * 5e9
+    w1, w2 = wm - g, wm + g
+    H = np.array([[w1, g, J], [g, wm, g], [J, g, w2]])
+    want = np.linalg.eigvalsh(H)
+    M = macrospin(alpha=1e-4, B0=(0, 0, wm / GAMMA), omega=[w1, w2], kappa=[TWO_PI * 1e6] * 2, g=[g, g],
+                  photon_coupling=np.array([[0.0, J], [J, 0.0]]))
+    s = co_rotating_rates(M, state(0, 0), np.array([0.01 + 0j, 0]), T=10e-9, count=6)
+    got = np.sort(-s.imag)
+    assert got.size == 3 and np.abs(got - want).max() / TWO_PI < 1e6
+    assert np.abs(want - (wm + np.array([-math.sqrt(3) * g, 0, math.sqrt(3) * g]))).max() / TWO_PI > 5e6
