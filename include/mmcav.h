@@ -124,15 +124,20 @@ mm_status mm_set_modes(mm_ctx* ctx, int32_t n, const double* omega, const double
                        const int8_t* sublattice_sign);
 
 /* Cavity-model variants, per mode (n must equal the mode count; n = 0
- * switches both off, as does mm_set_modes):
+ * switches all of them off, as does mm_set_modes):
  *   g_back: backward (cavity-to-magnon) coupling g_b [rad/s] of Sec. II A,
  *     so that the feedback uses h0_n = 2 g_b,n / gamma while the cavity
  *     equation keeps g_n (= g_f); NULL = reciprocal (g_b = g).
  *   kerr: self-Kerr coefficient K_n [rad/s] (Sec. V names Kerr terms as a
  *     cavity-model variant): da_n/dt gains -i K_n |a_n|^2 a_n; NULL = none.
+ *   coupling: host [n][n] direct photon-photon coupling J [rad/s], the
+ *     H_13 entry of the Sec. II F Hamiltonian (Eq. (9)) for any mode pair:
+ *     da_n/dt gains -i sum_m J_nm a_m; symmetric with a zero diagonal
+ *     (else MM_ERR_ARG); NULL = none.
  * Host arrays, finite values.  mm_run_record and mm_adjoint return
- * MM_ERR_STATE while either variant is set. */
-mm_status mm_set_cavity_model(mm_ctx* ctx, int32_t n, const double* g_back, const double* kerr);
+ * MM_ERR_STATE while any variant is set. */
+mm_status mm_set_cavity_model(mm_ctx* ctx, int32_t n, const double* g_back, const double* kerr,
+                              const double* coupling);
 
 /* External cavity drive eta_n(t) of Eq. (1) / Eq. (12), as the Gaussian
  * pulse of Sec. IV A: eta_n(t) = A_n exp(-((t - t0_n) / sigma_n)^2 / 2),

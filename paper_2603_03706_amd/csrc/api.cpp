@@ -248,7 +248,8 @@ struct mm_ctx {
   int8_t cs[2] = {1, 1};
   bool nonrecip = false;          // backward coupling g_b set (h0 = 2 g_b / gamma)
   bool kerr_on = false;           // self-Kerr term set
-  std::vector<double> g_back, kerr;
+  bool jcpl_on = false;           // direct mode coupling set
+  std::vector<double> g_back, kerr, jcpl;
   bool drive_on = false;          // Gaussian cavity drive per mode
   std::vector<double> drive_re, drive_im, drive_t0, drive_sigma;
   // stepper
@@ -434,6 +435,10 @@ mm_status upload_desc(mm_ctx* c) {
   d.kerr_on = c->kerr_on ? 1 : 0;
   if (c->kerr_on)
     for (int n = 0; n < c->N; ++n) d.kerr[n] = c->kerr[n];
+  d.jcpl_on = c->jcpl_on ? 1 : 0;
+  if (c->jcpl_on)
+    for (int n = 0; n < c->N; ++n)
+      for (int m = 0; m < c->N; ++m) d.jcpl[n][m] = c->jcpl[(size_t)n * c->N + m];
   d.drive_on = c->drive_on ? 1 : 0;
   if (c->drive_on)
     for (int n = 0; n < c->N; ++n) {
@@ -1230,6 +1235,7 @@ mm_status mm_set_modes(mm_ctx* c, int32_t n, const double* omega, const double* 
   c->drive_on = false;
   c->nonrecip = false;
   c->kerr_on = false;
+  c->jcpl_on = false;
   c->omega.assign(omega, omega + n);
   c->kappa.assign(kappa, kappa + n);
   c->g.assign(g, g + n);
@@ -1272,18 +1278,29 @@ mm_status mm_set_modes(mm_ctx* c, int32_t n, const double* omega, const double* 
   return upload_desc(c);
 }
 
-mm_status mm_set_cavity_model(mm_ctx* c, int32_t n, const double* g_back, const double* kerr) {
+mm_status mm_set_cavity_model(mm_ctx* c, int32_t n, const double* g_back, const double* kerr,
+                              const double* coupling) {
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (!c->modes_set) return fail(MM_ERR_STATE, "modes not set (mm_set_modes)");
   if (n != 0 && n != c->N) return fail(MM_ERR_ARG, "count must equal the mode count");
-  if (n == 0) g_back = kerr = nullptr;
+  if (n == 0) g_back = kerr = coupling = nullptr;
   for (int i = 0; i < n; ++i)
     if ((g_back && !std::isfinite(g_back[i])) || (kerr && !std::isfinite(kerr[i])))
       return fail(MM_ERR_ARG, "cavity-model parameters must be finite");
+  if (coupling)
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double v = coupling[(size_t)i * n + j];
+        if (!std::isfinite(v)) return fail(MM_ERR_ARG, "cavity-model parameters must be finite");
+        if (i == j && v != 0.0) return fail(MM_ERR_ARG, "mode coupling must be zero on the diagonal");
+        if (v != coupling[(size_t)j * n + i]) return fail(MM_ERR_ARG, "mode coupling must be symmetric");
+      }
   c->nonrecip = g_back != nullptr;
   c->kerr_on = kerr != nullptr;
+  c->jcpl_on = coupling != nullptr;
   if (g_back) c->g_back.assign(g_back, g_back + n);
   if (kerr) c->kerr.assign(kerr, kerr + n);
+  if (coupling) c->jcpl.assign(coupling, coupling + (size_t)n * n);
   return upload_desc(c);
 }
 
@@ -1547,8 +1564,8 @@ void restore_forward(InstCtl& dst, const InstCtl& ck) {
 mm_status mm_run_record(mm_ctx* c, double T, int32_t every) {
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (c->method != MM_RK4) return fail(MM_ERR_STATE, "recording needs the fixed-step RK4 method");
-  if (c->nonrecip || c->kerr_on)
-    return fail(MM_ERR_STATE, "the adjoint covers reciprocal coupling without a Kerr term");
+  if (c->nonrecip || c->kerr_on || c->jcpl_on)
+    return fail(MM_ERR_STATE, "the adjoint covers the reciprocal, linear cavity without mode coupling");
   if (!(T > 0) || !std::isfinite(T) || every < 1) return fail(MM_ERR_ARG, "need T > 0 and checkpoint_every >= 1");
   if (mm_status s = check_ready(c)) return s;
   const double r = T / c->dt0;
@@ -1585,8 +1602,8 @@ mm_status mm_adjoint(mm_ctx* c, const double* dL_da, const float* dL_dm, float* 
                      double* grad_alpha, double* grad_B0, double* grad_a0, float* grad_m0) {
   if (!c || !dL_da) return fail(MM_ERR_ARG, "NULL context or dL_da");
   if (!c->rec_have) return fail(MM_ERR_STATE, "no recorded run (mm_run_record)");
-  if (c->nonrecip || c->kerr_on)
-    return fail(MM_ERR_STATE, "the adjoint covers reciprocal coupling without a Kerr term");
+  if (c->nonrecip || c->kerr_on || c->jcpl_on)
+    return fail(MM_ERR_STATE, "the adjoint covers the reciprocal, linear cavity without mode coupling");
   if (mm_status s = set_device(c)) return s;
   const int N = c->N, S = c->p.sublattices, K = c->rec_K;
   const size_t nc = (size_t)c->L.ncell, vec = (size_t)3 * S * nc;

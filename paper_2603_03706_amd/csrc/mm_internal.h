@@ -74,6 +74,9 @@ struct InstDesc {
   // self-Kerr term -i K_n |a_n|^2 a_n of the cavity equation
   int kerr_on, pad_kerr;
   double kerr[MMI_MAX_MODES];
+  // direct mode coupling -i sum_m J_nm a_m (J symmetric, zero diagonal)
+  int jcpl_on, pad_jcpl;
+  double jcpl[MMI_MAX_MODES][MMI_MAX_MODES];
   // Gaussian cavity drive eta_n(t) = A_n exp(-((t - t0_n) / sigma_n)^2 / 2)
   int drive_on, pad_drive;
   double eta_re[MMI_MAX_MODES], eta_im[MMI_MAX_MODES];

@@ -9,11 +9,14 @@
 
 namespace mmk {
 
-// Cavity right-hand side of mode n at stage time t: (-i w - kappa) a +
-// i g e^{-i Phi} m^- (Eq. (12) with the phase of Eq. (19)), plus, when set,
-// the self-Kerr term -i K |a|^2 a and the Gaussian drive eta_n(t) of Eq. (1).
-__device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double t, double ar, double ai,
+// Cavity right-hand side of mode n at stage time t, with the stage
+// amplitudes of all modes in A: (-i w - kappa) a + i g e^{-i Phi} m^-
+// (Eq. (12) with the phase of Eq. (19)), plus, when set, the self-Kerr term
+// -i K |a|^2 a, the direct mode coupling -i sum_m J_nm a_m (the H_13 entry of
+// Eq. (9)) and the Gaussian drive eta_n(t) of Eq. (1).
+__device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double t, const double (*A)[2],
                                         double mr, double mi, double& fr, double& fi) {
+  const double ar = A[n][0], ai = A[n][1];
   const double w = D.omega[n], kp = D.kappa[n], g = D.g[n], c = D.cphi[n], s = D.sphi[n];
   fr = -kp * ar + w * ai + g * (s * mr - c * mi);
   fi = -w * ar - kp * ai + g * (s * mi + c * mr);
@@ -21,6 +24,15 @@ __device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double t, doub
     const double q = D.kerr[n] * (ar * ar + ai * ai);
     fr += q * ai;
     fi -= q * ar;
+  }
+  if (D.jcpl_on) {
+    double jr = 0.0, ji = 0.0;
+    for (int m = 0; m < D.N; ++m) {
+      jr += D.jcpl[n][m] * A[m][0];
+      ji += D.jcpl[n][m] * A[m][1];
+    }
+    fr += ji;
+    fi -= jr;
   }
   if (D.drive_on) {
     const double x = (t - D.eta_t0[n]) / D.eta_sigma[n];
@@ -133,7 +145,7 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   if (METHOD == MMI_RK4) {
     if (ST == 0) {  // run start: m^- of y, first derivative, first step
       for (int n = 0; n < N; ++n) {
-        cav_rhs(D, n, C->t, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+        cav_rhs(D, n, C->t, C->a, mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
         C->mm1[n][0] = mmv[n][0];
         C->mm1[n][1] = mmv[n][1];
         C->as[n][0] = C->a[n][0];
@@ -150,13 +162,12 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
     if (ST <= 3) {
       const double c = (ST == 3) ? h : 0.5 * h;
       for (int n = 0; n < N; ++n) {
-        const double ar = C->a[n][0] + c * C->ka[ST - 1][n][0];
-        const double ai = C->a[n][1] + c * C->ka[ST - 1][n][1];
-        // stage ST + 1 sits at t + c (c = h/2, h/2, h)
-        cav_rhs(D, n, C->t + c, ar, ai, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
-        C->as[n][0] = ar;
-        C->as[n][1] = ai;
+        C->as[n][0] = C->a[n][0] + c * C->ka[ST - 1][n][0];
+        C->as[n][1] = C->a[n][1] + c * C->ka[ST - 1][n][1];
       }
+      // stage ST + 1 sits at t + c (c = h/2, h/2, h)
+      for (int n = 0; n < N; ++n)
+        cav_rhs(D, n, C->t + c, C->as, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
       return;
     }
     // ST == 4: step end; the new amplitudes go to C->as first
@@ -188,7 +199,9 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
     for (int n = 0; n < N; ++n) {
       C->a[n][0] = C->as[n][0];
       C->a[n][1] = C->as[n][1];
-      cav_rhs(D, n, C->t, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+    }
+    for (int n = 0; n < N; ++n) {
+      cav_rhs(D, n, C->t, C->a, mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
       C->mm1[n][0] = mmv[n][0];
       C->mm1[n][1] = mmv[n][1];
     }
@@ -207,7 +220,7 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   using P = DPCoef;
   if (ST == 1) {  // run start (k1 written by the kernel)
     for (int n = 0; n < N; ++n) {
-      cav_rhs(D, n, C->t, C->a[n][0], C->a[n][1], mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+      cav_rhs(D, n, C->t, C->a, mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
       C->mm1[n][0] = mmv[n][0];
       C->mm1[n][1] = mmv[n][1];
       C->dmm1[n][0] = tot[MMI_SLOT_DMM + 2 * n];
@@ -229,7 +242,7 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   if (ST == 2) {
     // ka2 at (a2, m^-(m2)) [m2 sums in the DMM slot], then ka3 at (a3, m^-(m3))
     for (int n = 0; n < N; ++n)
-      cav_rhs(D, n, C->t + P::c2 * h, C->as[n][0], C->as[n][1], tot[MMI_SLOT_DMM + 2 * n],
+      cav_rhs(D, n, C->t + P::c2 * h, C->as, tot[MMI_SLOT_DMM + 2 * n],
               tot[MMI_SLOT_DMM + 2 * n + 1], C->ka[1][n][0], C->ka[1][n][1]);
   }
   if (ST >= 2 && ST <= 6) {
@@ -248,11 +261,11 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
         s0 += A[j] * C->ka[j][n][0];
         s1 += A[j] * C->ka[j][n][1];
       }
-      const double ar = C->a[n][0] + h * s0;
-      const double ai = C->a[n][1] + h * s1;
-      cav_rhs(D, n, C->t + cn * h, ar, ai, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
-      C->as[n][0] = ar;
-      C->as[n][1] = ai;
+      C->as[n][0] = C->a[n][0] + h * s0;
+      C->as[n][1] = C->a[n][1] + h * s1;
+    }
+    for (int n = 0; n < N; ++n) {
+      cav_rhs(D, n, C->t + cn * h, C->as, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
       if (ST == 6) {
         C->mm7[n][0] = mmv[n][0];
         C->mm7[n][1] = mmv[n][1];

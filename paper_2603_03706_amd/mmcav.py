@@ -57,7 +57,7 @@ _SIGS = {
     "mm_set_m": (ctypes.c_int, [_P, _P]),
     "mm_set_a": (ctypes.c_int, [_P, _P]),
     "mm_set_drive": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
-    "mm_set_cavity_model": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "mm_set_cavity_model": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "mm_set_stepper": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "mm_set_sampling": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64]),
     "mm_run": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
@@ -169,8 +169,8 @@ class Context:
                 demag=inst.demag, n_local=inst.n_local, geometry=inst.geometry,
                 sublattices=inst.sublattices, B_E=inst.B_E)
         c.set_modes(inst.omega, inst.kappa, inst.g, u=inst.u, phi=inst.phi, csign=inst.csign)
-        if getattr(inst, "g_back", None) is not None or getattr(inst, "kerr", None) is not None:
-            c.set_cavity_model(inst.g_back, inst.kerr)
+        if any(getattr(inst, k, None) is not None for k in ("g_back", "kerr", "photon_coupling")):
+            c.set_cavity_model(inst.g_back, inst.kerr, inst.photon_coupling)
         if getattr(inst, "drive_amp", None) is not None:
             c.set_drive(inst.drive_amp, inst.drive_t0, inst.drive_sigma)
         c.set_m(inst.m0)
@@ -189,13 +189,15 @@ class Context:
         _check(self._lib.mm_set_modes(self.h, n, _ptr(om), _ptr(ka), _ptr(gg), _ptr(uu), _ptr(ph), _ptr(cs)))
         self.N = n
 
-    def set_cavity_model(self, g_back=None, kerr=None):
-        """Nonreciprocal backward coupling g_b and self-Kerr K per mode
-        [rad/s]; None leaves that variant off (both None: reciprocal, linear)."""
+    def set_cavity_model(self, g_back=None, kerr=None, coupling=None):
+        """Nonreciprocal backward coupling g_b and self-Kerr K per mode, and
+        the direct mode coupling J [N][N] (all rad/s); None leaves that
+        variant off (all None: reciprocal, linear, uncoupled modes)."""
         gb = None if g_back is None else np.ascontiguousarray(g_back, np.float64)
         kr = None if kerr is None else np.ascontiguousarray(kerr, np.float64)
-        n = 0 if gb is None and kr is None else self.N
-        _check(self._lib.mm_set_cavity_model(self.h, n, _ptr(gb), _ptr(kr)))
+        jc = None if coupling is None else np.ascontiguousarray(coupling, np.float64)
+        n = 0 if gb is None and kr is None and jc is None else self.N
+        _check(self._lib.mm_set_cavity_model(self.h, n, _ptr(gb), _ptr(kr), _ptr(jc)))
 
     def set_drive(self, amp=None, t0=None, sigma=None):
         """Gaussian cavity drive A_n exp(-((t - t0_n)/sigma_n)^2 / 2) per mode

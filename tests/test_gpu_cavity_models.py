@@ -79,7 +79,7 @@ def test_cavity_model_arguments_and_adjoint_gate():
     from paper_2603_03706_amd import mmcav
     ctx = gpu_for(W.paper_sim1(T=0.1e-9))
     with pytest.raises(mmcav.MMError) as e:
-        mmcav._check(ctx._lib.mm_set_cavity_model(ctx.h, 2, None, None))
+        mmcav._check(ctx._lib.mm_set_cavity_model(ctx.h, 2, None, None, None))
     assert e.value.status == mmcav.MM_ERR_ARG
     with pytest.raises(mmcav.MMError) as e:
         ctx.set_cavity_model(kerr=[float("inf")])
@@ -90,3 +90,65 @@ def test_cavity_model_arguments_and_adjoint_gate():
     assert e.value.status == mmcav.MM_ERR_STATE
     ctx.set_cavity_model()
     ctx.run_record(10e-12, 4)
+
+
+def _two_mode(w1, w2, g, J, **kw):
+    inst = W.paper_sim1(g=0.0)
+    return variant(inst, drive_amp=None, omega=np.array([w1, w2]), kappa=np.array([TWO_PI * 1e6] * 2),
+                   g=np.array([g, g]), photon_coupling=np.array([[0.0, J], [J, 0.0]]), **kw)
+
+
+@pytest.mark.parametrize("method", ["rk4", "dp45"])
+def test_photon_coupling_two_cavities(method):
+    """g = 0, two equal cavities joined by J: device against the oracle
+    (FP64 cavity step on both sides) and the exact beat solution."""
+    w, J = TWO_PI * 5e9, TWO_PI * 80e6
+    a0 = np.array([0.02 + 0.01j, -0.005j])
+    inst = _two_mode(w, w, 0.0, J, a0=a0, method=method, dt0=0.5e-12)
+    st, ctx = _pair(inst, 3e-9, tol=1e-14, cap=1000)
+    _, a_o, _ = st.trace_arrays()
+    t, a, _ = ctx.get_trace(1000)
+    assert len(t) == 301 and rel_a_err(a, a_o.numpy()) <= 1e-12
+    e = np.exp((-1j * w - inst.kappa[0]) * t)
+    want = np.stack([e * (a0[0] * np.cos(J * t) - 1j * a0[1] * np.sin(J * t)),
+                     e * (a0[1] * np.cos(J * t) - 1j * a0[0] * np.sin(J * t))], axis=1)
+    assert np.abs(a - want).max() / np.abs(a0).max() < (2e-7 if method == "rk4" else 1e-9)
+
+
+def test_three_mode_direct_coupling():
+    """Two cavities at w_m -+ g, both coupled to the 8x8x1 film and to each
+    other by J (Eq. (9) with H_13 = J): parity with the oracle over 1 ns, then
+    the rates of a 10 ns run at the eigenvalues of the 3x3 matrix (1 MHz)."""
+    g, J = TWO_PI * 50e6, TWO_PI * 30e6
+    wm = TWO_PI * 5e9
+    inst = _two_mode(wm - g, wm + g, g, J, a0=np.array([0.01 + 0j, 0j]))
+    inst = variant(inst, B0=(0.0, 0.0, wm / W.GAMMA))
+    st, ctx = _pair(inst, 1e-9)
+    _, a_o, mm_o = st.trace_arrays()
+    _, a, mm = ctx.get_trace(2000)
+    assert rel_a_err(a, a_o.numpy()) <= 1e-5 and rel_a_err(mm, mm_o.numpy()) <= 1e-5
+    ctx = gpu_for(inst)
+    ctx.set_sampling(10e-12, 2000)
+    ctx.run(10e-9)
+    _, a, mm = ctx.get_trace(2000)
+    # the fit uses the cavity channels: m^- carries the FP32 rounding of the
+    # state, which a sixth-order fit over three channels absorbs as a
+    # spurious rate and a bias of a few MHz
+    s = prony(np.stack([a[:, 0], a[:, 1]]), 10e-12, 6)
+    got = np.sort(-s[s.imag < 0].imag)
+    got = got[(got > TWO_PI * 4e9) & (got < TWO_PI * 6e9)]
+    want = np.linalg.eigvalsh(np.array([[wm - g, g, J], [g, wm, g], [J, g, wm + g]]))
+    assert got.size == 3 and np.abs(got - want).max() / TWO_PI < 1e6
+
+
+def test_photon_coupling_arguments():
+    from paper_2603_03706_amd import mmcav
+    w = TWO_PI * 5e9
+    ctx = gpu_for(_two_mode(w, w, 0.0, TWO_PI * 10e6, a0=np.zeros(2, complex)))
+    for J in ([[0.0, 1e6], [2e6, 0.0]], [[1e6, 1e6], [1e6, 0.0]], [[0.0, np.nan], [np.nan, 0.0]]):
+        with pytest.raises(mmcav.MMError) as e:
+            ctx.set_cavity_model(coupling=J)
+        assert e.value.status == mmcav.MM_ERR_ARG
+    with pytest.raises(mmcav.MMError) as e:
+        ctx.run_record(10e-12, 4)
+    assert e.value.status == mmcav.MM_ERR_STATE
