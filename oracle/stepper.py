@@ -8,6 +8,10 @@ Runge-Kutta step (Sec. III A: the cavity ODEs are integrated in the same
 adaptive RK45 step as the LLG equation), with no operator splitting.
 
   * fixed step: classical RK4;
+  * operator-split (the co-simulation scheme of Sec. III B, kept as an
+    accuracy baseline): per step, one RK4 step of the cavity ODE with m^-
+    held at its step-start value, then one RK4 step of the LLG with the
+    feedback field of the new amplitudes held over the whole step;
   * adaptive: Dormand-Prince 5(4) (Dormand & Prince, J. Comput. Appl. Math. 6,
     19 (1980)), first-same-as-last, advancing with the 5th-order weights.
     Error  eps = max(|E_m| over magnetic cells, components and sublattices,
@@ -108,6 +112,24 @@ class Stepper:
         a_new = a + h / 6.0 * (ka1 + 2 * ka2 + 2 * ka3 + ka4)
         return y_new, a_new
 
+    def _split_step(self, h):
+        M = self.model
+        y, a, t = self.m, self.a, self.t
+        mm = M.m_minus(y)
+        k1 = M.cavity_rhs(a, mm, t)
+        k2 = M.cavity_rhs(a + 0.5 * h * k1, mm, t + 0.5 * h)
+        k3 = M.cavity_rhs(a + 0.5 * h * k2, mm, t + 0.5 * h)
+        k4 = M.cavity_rhs(a + h * k3, mm, t + h)
+        a_new = a + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+
+        def f(m):
+            return M.torque(m, M.field(m, a_new))
+        q1 = f(y)
+        q2 = f(y + 0.5 * h * q1)
+        q3 = f(y + 0.5 * h * q2)
+        q4 = f(y + h * q3)
+        return M.normalize(y + h / 6.0 * (q1 + 2 * q2 + 2 * q3 + q4)), a_new
+
     def _dp_first(self):
         M = self.model
         k1, ka1, mm1 = M.rhs(self.m, self.a, self.t)
@@ -165,7 +187,7 @@ class Stepper:
             if clipped:
                 h = remaining
             if not adaptive:
-                y_new, a_new = self._rk4_step(h)
+                y_new, a_new = self._split_step(h) if self.method == "split" else self._rk4_step(h)
                 if not (bool(torch.isfinite(y_new).all()) and bool(torch.isfinite(a_new.real).all())
                         and bool(torch.isfinite(a_new.imag).all())):
                     status = NONFINITE

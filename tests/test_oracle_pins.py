@@ -770,3 +770,43 @@ def test_p16_three_mode_with_direct_coupling():
     got = np.sort(-s.imag)
     assert got.size == 3 and np.abs(got - want).max() / TWO_PI < 1e6
     assert np.abs(want - (wm + np.array([-math.sqrt(3) * g, 0, math.sqrt(3) * g]))).max() / TWO_PI > 5e6
+
+
+# ------------------------------------- P17 operator-split scheme (Sec. III B)
+def test_p17_split_equals_joint_when_uncoupled():
+    """g = 0: the cavity and the magnet do not talk, so holding m^- or the
+    feedback over a step changes nothing and the split run is the joint RK4
+    run bit for bit."""
+    kw = dict(omega=[TWO_PI * 5e9], kappa=[TWO_PI * 1e6], g=[0.0], B0=(0, 0, 0.17),
+              drive_amp=[1e8j], drive_t0=[0.05e-9], drive_sigma=[20e-12])
+    outs = []
+    for method in ("rk4", "split"):
+        st = Stepper(macrospin(**kw), state(3, 0.2), np.array([0.01 + 0j]), method=method, dt0=1e-12)
+        with torch.no_grad():
+            st.run(0.2e-9)
+        outs.append((st.m, st.a))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_p17_split_error_is_first_order():
+    """Vacuum Rabi exchange at resonance (g/2pi = 50 MHz, 1 ns): against a
+    quarter-step joint RK4 reference, halving dt halves the split scheme's
+    error (first order, the O(g w T dt) splitting error) and divides the
+    joint stepper's by 16 (fourth order); at 1 ps the split error is more
+    than 100 times the joint one."""
+    wc, g = TWO_PI * 5e9, TWO_PI * 50e6
+    kw = dict(alpha=1e-4, B0=(0, 0, wc / GAMMA), omega=[wc], kappa=[TWO_PI * 1e6], g=[g])
+
+    def trace(method, dt):
+        st = Stepper(macrospin(**kw), state(0, 0), np.array([0.01 + 0j]), method=method, dt0=dt)
+        st.set_sampling(20e-12, 1000)
+        with torch.no_grad():
+            st.run(1e-9)
+        return st.trace_arrays()[1].numpy()[:, 0]
+
+    ref = trace("rk4", 0.25e-12)
+    es = [np.abs(trace("split", dt) - ref).max() for dt in (1e-12, 0.5e-12)]
+    ej = [np.abs(trace("rk4", dt) - ref).max() for dt in (1e-12, 0.5e-12)]
+    assert 1.8 < es[0] / es[1] < 2.3
+    assert 13 < ej[0] / ej[1] < 19
+    assert es[0] > 100 * ej[0]
