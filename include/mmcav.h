@@ -61,7 +61,7 @@ typedef enum {
 } mm_status;
 
 enum { MM_DEMAG_NONE = 0, MM_DEMAG_LOCAL = 1, MM_DEMAG_FFT = 2 };
-enum { MM_RK4 = 0, MM_DP45 = 1 };
+enum { MM_RK4 = 0, MM_DP45 = 1, MM_RK4_SPLIT = 2 };
 enum { MM_MAX_MODES = 16 };
 
 typedef struct {
@@ -159,7 +159,12 @@ mm_status mm_set_a(mm_ctx* ctx, const double* a);
 
 /* Stepper: method MM_RK4 (fixed step dt0) or MM_DP45 (adaptive, first trial
  * step dt0); dt_min (> 0) ends an adaptive run with MM_ERR_DT_UNDERFLOW when
- * the step would fall below it; dt_max caps the step (<= 0: no cap). */
+ * the step would fall below it; dt_max caps the step (<= 0: no cap).
+ * MM_RK4_SPLIT is the operator-split co-simulation scheme of Sec. III B, as
+ * an accuracy baseline for the joint stepper: per step of dt0 the cavity
+ * takes one RK4 step with m^- held at its step-start value, then the LLG
+ * takes one RK4 step with the feedback of the new amplitudes held.  It
+ * samples like MM_RK4 and has no adjoint (mm_run_record: MM_ERR_STATE). */
 mm_status mm_set_stepper(mm_ctx* ctx, int32_t method, double dt0, double dt_min, double dt_max);
 
 /* Record a(t_k) and m^-(t_k) at t_k = t_start + k dt_sample into a device

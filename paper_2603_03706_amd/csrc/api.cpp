@@ -254,6 +254,7 @@ struct mm_ctx {
   std::vector<double> drive_re, drive_im, drive_t0, drive_sigma;
   // stepper
   int method = MM_RK4;
+  bool split = false;             // MM_RK4_SPLIT: RK4 kernels in the operator-split scheme
   double dt0 = 1e-13, dt_min = 1e-18, dt_max = 0.0;
   // sampling
   double dt_sample = 0.0;
@@ -402,6 +403,7 @@ mm_status upload_desc(mm_ctx* c) {
   d.lgny = lg_pow2(p.ny);
   d.S = p.sublattices; d.N = c->N; d.profiled = c->profiled ? 1 : 0; d.has_geom = p.geometry ? 1 : 0;
   d.demag = p.demag; d.method = c->method; d.nwg = L.nwg; d.wg0 = 0;
+  d.split = c->split ? 1 : 0;
   const double cex = 2.0 * p.Aex / p.Ms;
   d.cex_x = p.nx > 1 ? (float)(cex / (p.dx * p.dx)) : 0.f;
   d.cex_y = p.ny > 1 ? (float)(cex / (p.dy * p.dy)) : 0.f;
@@ -1372,7 +1374,9 @@ mm_status mm_set_a(mm_ctx* c, const double* a) {
 
 mm_status mm_set_stepper(mm_ctx* c, int32_t method, double dt0, double dt_min, double dt_max) {
   if (!c) return fail(MM_ERR_ARG, "NULL context");
-  if (method != MM_RK4 && method != MM_DP45) return fail(MM_ERR_ARG, "unknown method");
+  if (method != MM_RK4 && method != MM_DP45 && method != MM_RK4_SPLIT) return fail(MM_ERR_ARG, "unknown method");
+  const bool split = method == MM_RK4_SPLIT;
+  if (split) method = MM_RK4;
   if (!(dt0 > 0) || !std::isfinite(dt0)) return fail(MM_ERR_ARG, "dt0 must be > 0");
   if (!(dt_min > 0) || !std::isfinite(dt_min) || dt_min > dt0) return fail(MM_ERR_ARG, "need 0 < dt_min <= dt0");
   if (!std::isfinite(dt_max)) return fail(MM_ERR_ARG, "dt_max must be finite");
@@ -1381,6 +1385,7 @@ mm_status mm_set_stepper(mm_ctx* c, int32_t method, double dt0, double dt_min, d
     c->solo = nullptr;
   }
   c->method = method;
+  c->split = split;
   c->dt0 = dt0;
   c->dt_min = dt_min;
   c->dt_max = dt_max;
@@ -1392,6 +1397,7 @@ mm_status mm_set_stepper(mm_ctx* c, int32_t method, double dt0, double dt_min, d
     h.last_rejected = 0;
     if (mm_status s = ctl_push(c, h)) return s;
     c->desc.method = method;
+    c->desc.split = split ? 1 : 0;
     c->version++;
   }
   return MM_OK;
@@ -1563,7 +1569,7 @@ void restore_forward(InstCtl& dst, const InstCtl& ck) {
 
 mm_status mm_run_record(mm_ctx* c, double T, int32_t every) {
   if (!c) return fail(MM_ERR_ARG, "NULL context");
-  if (c->method != MM_RK4) return fail(MM_ERR_STATE, "recording needs the fixed-step RK4 method");
+  if (c->method != MM_RK4 || c->split) return fail(MM_ERR_STATE, "recording needs the fixed-step RK4 method");
   if (c->nonrecip || c->kerr_on || c->jcpl_on)
     return fail(MM_ERR_STATE, "the adjoint covers the reciprocal, linear cavity without mode coupling");
   if (!(T > 0) || !std::isfinite(T) || every < 1) return fail(MM_ERR_ARG, "need T > 0 and checkpoint_every >= 1");

@@ -60,6 +60,7 @@ struct InstDesc {
   int lgnx, lgny;                     // log2 of nx, ny when powers of two, else -1
   int S, N, profiled, has_geom;
   int demag, method, nwg, wg0;
+  int split, pad_split;               // RK4 in the operator-split scheme (cavity first, m^- held)
   float cex_x, cex_y, cex_z;          // (2A/Ms)/d^2 per axis
   float cK, ex, ey, ez;               // 2K/Ms and the unit axis
   float B0x, B0y, B0z;

@@ -126,6 +126,31 @@ __device__ __forceinline__ void plan_step(InstCtl* C, double dt) {
   C->clipped = clipped;
 }
 
+// Operator-split cavity step (the co-simulation scheme of Sec. III B): one
+// RK4 step of the cavity ODE over C->h from C->a with m^- held at mh, into
+// C->as, which then feeds every LLG stage of the step.  The stage
+// derivatives go to C->ka[0..3].
+__device__ __forceinline__ void split_cavity(const InstDesc& D, InstCtl* C, const double (*mh)[2]) {
+  const int N = D.N;
+  const double h = C->h, t = C->t;
+  for (int n = 0; n < N; ++n)
+    cav_rhs(D, n, t, C->a, mh[n][0], mh[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+  for (int s = 1; s <= 3; ++s) {
+    const double c = (s == 3) ? h : 0.5 * h;
+    for (int n = 0; n < N; ++n) {
+      C->as[n][0] = C->a[n][0] + c * C->ka[s - 1][n][0];
+      C->as[n][1] = C->a[n][1] + c * C->ka[s - 1][n][1];
+    }
+    for (int n = 0; n < N; ++n)
+      cav_rhs(D, n, t + c, C->as, mh[n][0], mh[n][1], C->ka[s][n][0], C->ka[s][n][1]);
+  }
+  const double c6 = h / 6.0;
+  for (int n = 0; n < N; ++n)
+    for (int r = 0; r < 2; ++r)
+      C->as[n][r] = C->a[n][r] + c6 * (C->ka[0][n][r] + 2.0 * C->ka[1][n][r] + 2.0 * C->ka[2][n][r] +
+                                       C->ka[3][n][r]);
+}
+
 // ------------------------------------------------------------ finalisation
 // Runs in thread 0 of the last workgroup of an instance, with the gathered
 // sums in tot[] (mode sums already scaled by 1/(S N_geo)).
@@ -145,7 +170,8 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   if (METHOD == MMI_RK4) {
     if (ST == 0) {  // run start: m^- of y, first derivative, first step
       for (int n = 0; n < N; ++n) {
-        cav_rhs(D, n, C->t, C->a, mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+        if (!D.split)
+          cav_rhs(D, n, C->t, C->a, mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
         C->mm1[n][0] = mmv[n][0];
         C->mm1[n][1] = mmv[n][1];
         C->as[n][0] = C->a[n][0];
@@ -157,8 +183,10 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
         record_sample(D, C, C->t, C->a, C->mm1);
       }
       plan_step(C, C->dt_fixed);
+      if (D.split) split_cavity(D, C, mmv);
       return;
     }
+    if (D.split && ST <= 3) return;  // the LLG stages keep the new amplitudes
     if (ST <= 3) {
       const double c = (ST == 3) ? h : 0.5 * h;
       for (int n = 0; n < N; ++n) {
@@ -170,13 +198,15 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
         cav_rhs(D, n, C->t + c, C->as, mmv[n][0], mmv[n][1], C->ka[ST][n][0], C->ka[ST][n][1]);
       return;
     }
-    // ST == 4: step end; the new amplitudes go to C->as first
+    // ST == 4: step end; the new amplitudes go to C->as first (the split
+    // scheme has them there since the step start)
     bool bad = tot[MMI_SLOT_BAD] != 0.0;
     const double c6 = h / 6.0;
     for (int n = 0; n < N; ++n) {
       for (int r = 0; r < 2; ++r) {
-        const double v = C->a[n][r] + c6 * (C->ka[0][n][r] + 2.0 * C->ka[1][n][r] +
-                                            2.0 * C->ka[2][n][r] + C->ka[3][n][r]);
+        const double v = D.split ? C->as[n][r]
+                                 : C->a[n][r] + c6 * (C->ka[0][n][r] + 2.0 * C->ka[1][n][r] +
+                                                      2.0 * C->ka[2][n][r] + C->ka[3][n][r]);
         if (!isfinite(v)) bad = true;
         C->as[n][r] = v;
       }
@@ -201,7 +231,8 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
       C->a[n][1] = C->as[n][1];
     }
     for (int n = 0; n < N; ++n) {
-      cav_rhs(D, n, C->t, C->a, mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+      if (!D.split)
+        cav_rhs(D, n, C->t, C->a, mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
       C->mm1[n][0] = mmv[n][0];
       C->mm1[n][1] = mmv[n][1];
     }
@@ -214,13 +245,15 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
       return;
     }
     plan_step(C, C->dt_fixed);
+    if (D.split) split_cavity(D, C, mmv);
     return;
   }
   // ------------------------------------------------------------- DP45
   using P = DPCoef;
   if (ST == 1) {  // run start (k1 written by the kernel)
     for (int n = 0; n < N; ++n) {
-      cav_rhs(D, n, C->t, C->a, mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
+      if (!D.split)
+        cav_rhs(D, n, C->t, C->a, mmv[n][0], mmv[n][1], C->ka[0][n][0], C->ka[0][n][1]);
       C->mm1[n][0] = mmv[n][0];
       C->mm1[n][1] = mmv[n][1];
       C->dmm1[n][0] = tot[MMI_SLOT_DMM + 2 * n];

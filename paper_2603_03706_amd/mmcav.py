@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmmcav.so
 
 MM_OK, MM_ERR_ARG, MM_ERR_HIP, MM_ERR_OOM, MM_ERR_STATE, MM_ERR_DT_UNDERFLOW, MM_ERR_NONFINITE = 0, -1, -2, -3, -4, -5, -6
 DEMAG_NONE, DEMAG_LOCAL, DEMAG_FFT = 0, 1, 2
-RK4, DP45 = 0, 1
+RK4, DP45, RK4_SPLIT = 0, 1, 2
 MAX_MODES = 16
 
 _STATUS_NAMES = {0: "MM_OK", -1: "MM_ERR_ARG", -2: "MM_ERR_HIP", -3: "MM_ERR_OOM", -4: "MM_ERR_STATE",
@@ -175,7 +175,7 @@ class Context:
             c.set_drive(inst.drive_amp, inst.drive_t0, inst.drive_sigma)
         c.set_m(inst.m0)
         c.set_a(inst.a0)
-        c.set_stepper(RK4 if inst.method == "rk4" else DP45, inst.dt0)
+        c.set_stepper({"rk4": RK4, "dp45": DP45, "split": RK4_SPLIT}[inst.method], inst.dt0)
         return c
 
     def set_modes(self, omega, kappa, g, u=None, phi=None, csign=None):
