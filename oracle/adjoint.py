@@ -12,10 +12,12 @@ from .model import Model, Problem
 from .stepper import Stepper
 
 
-def run_with_grad(problem: Problem, m0, a0, dt, T, loss_fn, method="rk4"):
+def run_with_grad(problem: Problem, m0, a0, dt, T, loss_fn, method="rk4", trace_loss=None):
     """Return (loss, grads) where grads has d loss / d u (N, nz, ny, nx),
     d g (N,), d alpha, d B0 (3,), d a0 (N complex, as d/dRe + i d/dIm) and
-    d m0 (S, 3, nz, ny, nx, taken with respect to the normalised state)."""
+    d m0 (S, 3, nz, ny, nx, taken with respect to the normalised state).
+    With trace_loss, the loss also has trace_loss(A) for A the complex
+    amplitudes at the start and every step end, shape (steps + 1, N)."""
     N = len(problem.omega)
     nx, ny, nz = problem.grid
     u0 = np.ones((N, nz, ny, nx)) if problem.u is None else np.asarray(problem.u, float).reshape(N, nz, ny, nx)
@@ -32,8 +34,12 @@ def run_with_grad(problem: Problem, m0, a0, dt, T, loss_fn, method="rk4"):
     m_start = st.m.detach().clone().requires_grad_(True)
     st.m = m_start
     st.a = torch.complex(ar, ai)
+    if trace_loss is not None:
+        st.set_sampling(dt, 1 << 30)
     status = st.run(T)
     loss = loss_fn(st.m, st.a)
+    if trace_loss is not None:
+        loss = loss + trace_loss(torch.stack(st.trace["a"]))
     loss.backward()
     grads = {
         "u": leaves["u"].grad.numpy(),
