@@ -295,6 +295,19 @@ mm_status mm_run_record(mm_ctx* ctx, double T, int32_t checkpoint_every);
 mm_status mm_adjoint(mm_ctx* ctx, const double* dL_da, const float* dL_dm, float* grad_u, double* grad_g,
                      double* grad_alpha, double* grad_B0, double* grad_a0, float* grad_m0);
 
+/* As mm_adjoint, for a loss that also depends on the cavity trace of the
+ * recorded run, L(a(t_0), a(t_1), ..., a(t_K), m(T)) with t_k = t_0 + k dt
+ * the step ends (spectral objectives such as |sum_k a(t_k) e^{i w t_k}|^2,
+ * the observable of Sec. IV).  dL_dtrace: host [count][n][2] =
+ * (dL/dRe a_n(t_k), dL/dIm a_n(t_k)), count = recorded steps + 1 (else
+ * MM_ERR_ARG); each entry is added to the cavity adjoint when the reverse
+ * pass reaches its step end, entry 0 to grad_a0.  dL_da (a further
+ * derivative at T) may be NULL.  The buffer is copied to the device for the
+ * call (count * n * 16 bytes) and freed before it returns. */
+mm_status mm_adjoint_trace(mm_ctx* ctx, const double* dL_dtrace, int64_t count, const double* dL_da,
+                           const float* dL_dm, float* grad_u, double* grad_g, double* grad_alpha,
+                           double* grad_B0, double* grad_a0, float* grad_m0);
+
 /* ---- host-side checks (no GPU needed) ------------------------------------ */
 /* Cell-averaged demag tensor (xx, yy, zz, xy, xz, yz) at displacement
  * (X, Y, Z) [m] for cells dx*dy*dz, as the library's setup computes it. */

@@ -288,6 +288,7 @@ struct mm_ctx {
   double* adj_d = nullptr;         // rec_a, grad_u
   int adj_K = -1, adj_N = -1;
   bool adj_on = false;             // descriptor carries the adjoint pointers
+  double* dla_dev = nullptr;       // dL/da at every step end (mm_adjoint_trace), during the call only
 };
 
 struct mm_batch {
@@ -482,6 +483,7 @@ mm_status upload_desc(mm_ctx* c) {
     d.rec_bd = L.fft ? f : nullptr;
     d.rec_a = c->adj_d;
     d.grad_u = c->adj_d + (size_t)K * 4 * std::max(1, c->N) * 2;
+    d.dla_trace = c->dla_dev;
   }
   c->version++;
   return MM_OK;
@@ -1604,8 +1606,50 @@ mm_status mm_run_record(mm_ctx* c, double T, int32_t every) {
   return MM_OK;
 }
 
+static mm_status adjoint_impl(mm_ctx* c, const double* dL_da, const float* dL_dm, const double* dL_dtrace,
+                              float* grad_u, double* grad_g, double* grad_alpha, double* grad_B0,
+                              double* grad_a0, float* grad_m0);
+
 mm_status mm_adjoint(mm_ctx* c, const double* dL_da, const float* dL_dm, float* grad_u, double* grad_g,
                      double* grad_alpha, double* grad_B0, double* grad_a0, float* grad_m0) {
+  return adjoint_impl(c, dL_da, dL_dm, nullptr, grad_u, grad_g, grad_alpha, grad_B0, grad_a0, grad_m0);
+}
+
+mm_status mm_adjoint_trace(mm_ctx* c, const double* dL_dtrace, int64_t count, const double* dL_da,
+                           const float* dL_dm, float* grad_u, double* grad_g, double* grad_alpha,
+                           double* grad_B0, double* grad_a0, float* grad_m0) {
+  if (!c || !dL_dtrace) return fail(MM_ERR_ARG, "NULL context or dL_dtrace");
+  if (!c->rec_have) return fail(MM_ERR_STATE, "no recorded run (mm_run_record)");
+  if (count != c->rec_steps + 1) return fail(MM_ERR_ARG, "dL_dtrace needs one entry per step end and the start");
+  const size_t n = (size_t)count * 2 * std::max(1, c->N);
+  for (size_t i = 0; i < (size_t)count * 2 * c->N; ++i)
+    if (!std::isfinite(dL_dtrace[i])) return fail(MM_ERR_ARG, "non-finite dL_dtrace");
+  if (mm_status s = set_device(c)) return s;
+  // the layout [count][N][2] as given, padded to at least one mode
+  std::vector<double> hbuf(n, 0.0);
+  for (int64_t k = 0; k < count; ++k)
+    for (int q = 0; q < 2 * c->N; ++q) hbuf[(size_t)k * 2 * std::max(1, c->N) + q] = dL_dtrace[(size_t)k * 2 * c->N + q];
+  double* dev = nullptr;
+  if (hipMalloc(&dev, sizeof(double) * n) != hipSuccess) return fail(MM_ERR_OOM, "trace adjoint allocation failed");
+  mm_status st = MM_OK;
+  if (hipMemcpy(dev, hbuf.data(), sizeof(double) * n, hipMemcpyHostToDevice) != hipSuccess) {
+    st = fail(MM_ERR_HIP, "trace adjoint copy failed");
+  } else {
+    std::vector<double> zero(2 * std::max(1, c->N), 0.0);
+    c->dla_dev = dev;
+    st = adjoint_impl(c, dL_da ? dL_da : zero.data(), dL_dm, dL_dtrace, grad_u, grad_g, grad_alpha, grad_B0,
+                      grad_a0, grad_m0);
+    c->dla_dev = nullptr;
+    const mm_status s2 = upload_desc(c);
+    if (st == MM_OK) st = s2;
+  }
+  hipFree(dev);
+  return st;
+}
+
+static mm_status adjoint_impl(mm_ctx* c, const double* dL_da, const float* dL_dm, const double* dL_dtrace,
+                              float* grad_u, double* grad_g, double* grad_alpha, double* grad_B0,
+                              double* grad_a0, float* grad_m0) {
   if (!c || !dL_da) return fail(MM_ERR_ARG, "NULL context or dL_da");
   if (!c->rec_have) return fail(MM_ERR_STATE, "no recorded run (mm_run_record)");
   if (c->nonrecip || c->kerr_on || c->jcpl_on)
@@ -1676,6 +1720,7 @@ mm_status mm_adjoint(mm_ctx* c, const double* dL_da, const float* dL_dm, float* 
                      hipMemcpyDeviceToDevice));
     // reverse the segment
     h.rec_index = (int)steps - 1;
+    h.adj_base = (long long)k * K;
     h.done = 0;
     h.adj_h = c->rec_h;
     if (mm_status s = ctl_push(c, h)) return s;
@@ -1689,7 +1734,12 @@ mm_status mm_adjoint(mm_ctx* c, const double* dL_da, const float* dL_dm, float* 
   if (grad_g) for (int n = 0; n < N; ++n) grad_g[n] = h.grad_g[n];
   if (grad_alpha) *grad_alpha = h.grad_alpha;
   if (grad_B0) for (int q = 0; q < 3; ++q) grad_B0[q] = h.grad_B0[q];
-  if (grad_a0) for (int n = 0; n < N; ++n) { grad_a0[2 * n] = h.la[n][0]; grad_a0[2 * n + 1] = h.la[n][1]; }
+  // the trace loss at the start acts on a0 directly
+  if (grad_a0)
+    for (int n = 0; n < N; ++n) {
+      grad_a0[2 * n] = h.la[n][0] + (dL_dtrace ? dL_dtrace[2 * n] : 0.0);
+      grad_a0[2 * n + 1] = h.la[n][1] + (dL_dtrace ? dL_dtrace[2 * n + 1] : 0.0);
+    }
   if (grad_m0) MM_HIP(hipMemcpy(grad_m0, c->desc.lam_y, sizeof(float) * vec, hipMemcpyDeviceToHost));
   if (grad_u && N > 0) {
     std::vector<double> gu((size_t)N * nc);

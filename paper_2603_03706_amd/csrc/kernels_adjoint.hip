@@ -365,6 +365,14 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__
   }
   if (threadIdx.x != 0) return;
   if (ST == 5) {
+    // a loss on the trace: its derivative at the end of the step being reversed
+    if (D.dla_trace) {
+      const double* q = D.dla_trace + (size_t)(C->adj_base + C->rec_index + 1) * N * 2;
+      for (int n = 0; n < N; ++n) {
+        C->la[n][0] += q[2 * n];
+        C->la[n][1] += q[2 * n + 1];
+      }
+    }
     for (int n = 0; n < N; ++n)
       for (int r = 0; r < 2; ++r) {
         C->lza[n][r] = C->la[n][r];

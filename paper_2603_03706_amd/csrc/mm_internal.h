@@ -44,7 +44,7 @@ struct InstCtl {
   int rec_index;                      // recorded step within the segment (-1: not recording)
   int pad1;
   double adj_h;                       // step of the recorded run
-  double rec_a_pad;
+  long long adj_base;                 // recorded-run index of the first step of the segment being reversed
   double la[MMI_MAX_MODES][2];        // adjoint of a at the step start (accumulator)
   double lza[MMI_MAX_MODES][2];       // adjoint of a after the step
   double lka[MMI_MAX_MODES][2];       // adjoint of the current stage derivative of a
@@ -111,6 +111,7 @@ struct InstDesc {
   float* mu;                          // direct part of the stage VJP
   float* lam_B;                       // adjoint of the effective field
   double* grad_u;                     // [N][cells] accumulator (null: not requested)
+  const double* dla_trace;            // [steps+1][N][2] dL/da at every step end of the recorded run, or null
 };
 
 // adjoint partial-record slots (doubles), reusing the forward partials

@@ -58,6 +58,7 @@ _SIGS = {
     "mm_set_a": (ctypes.c_int, [_P, _P]),
     "mm_set_drive": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "mm_set_cavity_model": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "mm_adjoint_trace": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "mm_set_stepper": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "mm_set_sampling": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64]),
     "mm_run": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
@@ -232,10 +233,12 @@ class Context:
     def run_record(self, T, checkpoint_every=256):
         _check(self._lib.mm_run_record(self.h, float(T), int(checkpoint_every)))
 
-    def adjoint(self, dL_da, dL_dm=None):
-        """Gradients of the loss of the recorded run; dL_da complex (N,)."""
+    def adjoint(self, dL_da, dL_dm=None, dL_dtrace=None):
+        """Gradients of the loss of the recorded run; dL_da complex (N,) at T
+        (may be None with dL_dtrace), dL_dtrace complex (steps + 1, N): the
+        derivative with respect to a at every step end and the start."""
         nx, ny, nz = self.grid
-        dl = np.asarray(dL_da, np.complex128)
+        dl = np.zeros(self.N, np.complex128) if dL_da is None else np.asarray(dL_da, np.complex128)
         buf = np.ascontiguousarray(np.stack([dl.real, dl.imag], axis=-1).reshape(-1))
         dm = None if dL_dm is None else np.ascontiguousarray(dL_dm, np.float32)
         gu = np.zeros((max(self.N, 1), nz, ny, nx), np.float32)
@@ -244,8 +247,14 @@ class Context:
         gb = np.zeros(3)
         ga0 = np.zeros(2 * max(self.N, 1))
         gm0 = np.zeros((self.S, 3, nz, ny, nx), np.float32)
-        _check(self._lib.mm_adjoint(self.h, _ptr(buf), _ptr(dm), _ptr(gu), _ptr(gg), _ptr(ga), _ptr(gb),
-                                    _ptr(ga0), _ptr(gm0)))
+        if dL_dtrace is None:
+            _check(self._lib.mm_adjoint(self.h, _ptr(buf), _ptr(dm), _ptr(gu), _ptr(gg), _ptr(ga), _ptr(gb),
+                                        _ptr(ga0), _ptr(gm0)))
+        else:
+            dt = np.asarray(dL_dtrace, np.complex128).reshape(-1, self.N)
+            tb = np.ascontiguousarray(np.stack([dt.real, dt.imag], axis=-1).reshape(-1))
+            _check(self._lib.mm_adjoint_trace(self.h, _ptr(tb), dt.shape[0], _ptr(buf), _ptr(dm), _ptr(gu),
+                                              _ptr(gg), _ptr(ga), _ptr(gb), _ptr(ga0), _ptr(gm0)))
         return {"u": gu[:self.N], "g": gg[:self.N], "alpha": float(ga[0]), "B0": gb,
                 "a0": ga0[0:2 * self.N:2] + 1j * ga0[1:2 * self.N:2], "m0": gm0}
 
@@ -374,16 +383,19 @@ class RecordedRunFunction(torch.autograd.Function):
     """Differentiable fixed-step RK4 run of one instance: the forward pass
     records the run on the GPU (mm_run_record: checkpoints every
     `checkpoint_every` steps), the backward pass is the library's discrete
-    adjoint (mm_adjoint).  Inputs that carry gradients: the mode profiles u
-    (float32 [N][nz][ny][nx]), the couplings g (float64 [N], rad/s), the
-    damping alpha (float64 scalar) and the bias field B0 (float64 [3], T).
-    Outputs: a(T) as float64 [N][2] (real, imaginary part) and m(T) as float32
-    [S][3][nz][ny][nx].  The other parameters come from `inst`
-    (workloads.Instance, method rk4).  Arguments and results are only
+    adjoint (mm_adjoint, or mm_adjoint_trace when the trace output carries
+    a gradient).  Inputs that carry gradients: the mode profiles u (float32
+    [N][nz][ny][nx]), the couplings g (float64 [N], rad/s), the damping alpha
+    (float64 scalar) and the bias field B0 (float64 [3], T).  Outputs: a(T)
+    as float64 [N][2] (real, imaginary part), m(T) as float32
+    [S][3][nz][ny][nx] and, with `with_trace`, a at the start and every step
+    end as float64 [steps + 1][N][2] (else an empty tensor), so that losses
+    on the trace (spectra) differentiate too.  The other parameters come from
+    `inst` (workloads.Instance, method rk4).  Arguments and results are only
     marshalled here; both passes run in the library's kernels."""
 
     @staticmethod
-    def forward(fctx, u, g, alpha, B0, inst, T, checkpoint_every):
+    def forward(fctx, u, g, alpha, B0, inst, T, checkpoint_every, with_trace=False):
         import dataclasses
         run = dataclasses.replace(inst, u=u.detach().cpu().numpy().astype(np.float32),
                                   g=g.detach().cpu().numpy().astype(np.float64),
@@ -392,27 +404,42 @@ class RecordedRunFunction(torch.autograd.Function):
         if run.method != "rk4":
             raise ValueError("the discrete adjoint is built for fixed-step RK4 runs")
         c = Context.from_instance(run)
+        steps = int(round(T / run.dt0))
+        if with_trace:
+            c.set_sampling(run.dt0, steps + 1)
         c.run_record(T, checkpoint_every)
         a = c.get_a()
+        tr = torch.zeros(0, dtype=torch.float64)
+        if with_trace:
+            _, at, _ = c.get_trace(steps + 1)
+            if at.shape[0] != steps + 1:
+                raise RuntimeError("trace of the recorded run has %d samples, expected %d" % (at.shape[0], steps + 1))
+            tr = torch.from_numpy(np.stack([at.real, at.imag], axis=-1))
         fctx.context = c
-        return (torch.from_numpy(np.stack([a.real, a.imag], axis=-1)), torch.from_numpy(c.get_m()))
+        return (torch.from_numpy(np.stack([a.real, a.imag], axis=-1)), torch.from_numpy(c.get_m()), tr)
 
     @staticmethod
-    def backward(fctx, grad_a, grad_m):
+    def backward(fctx, grad_a, grad_m, grad_trace):
         c = fctx.context
         ga = np.zeros((c.N, 2)) if grad_a is None else grad_a.detach().cpu().numpy().astype(np.float64)
         gm = None if grad_m is None else grad_m.detach().cpu().numpy().astype(np.float32)
-        g = c.adjoint(ga[:, 0] + 1j * ga[:, 1], gm)
+        gt = None
+        if grad_trace is not None and grad_trace.numel() > 0:
+            q = grad_trace.detach().cpu().numpy().astype(np.float64)
+            gt = q[..., 0] + 1j * q[..., 1]
+        g = c.adjoint(ga[:, 0] + 1j * ga[:, 1], gm, gt)
         c.close()
         fctx.context = None
         return (torch.from_numpy(g["u"]), torch.from_numpy(g["g"]), torch.tensor(g["alpha"], dtype=torch.float64),
-                torch.from_numpy(np.asarray(g["B0"], np.float64)), None, None, None)
+                torch.from_numpy(np.asarray(g["B0"], np.float64)), None, None, None, None)
 
 
-def recorded_run(inst, T, u, g, alpha, B0, checkpoint_every=256):
+def recorded_run(inst, T, u, g, alpha, B0, checkpoint_every=256, with_trace=False):
     """a(T) [N][2] and m(T) of `inst` run for T with the given u, g, alpha and
-    B0 (tensors; gradients flow through the GPU discrete adjoint)."""
-    return RecordedRunFunction.apply(u, g, alpha, B0, inst, T, checkpoint_every)
+    B0 (tensors; gradients flow through the GPU discrete adjoint), and with
+    `with_trace` also a at the start and every step end, [steps + 1][N][2]."""
+    a, m, tr = RecordedRunFunction.apply(u, g, alpha, B0, inst, T, checkpoint_every, with_trace)
+    return (a, m, tr) if with_trace else (a, m)
 
 
 def exported_symbols():
