@@ -134,8 +134,9 @@ mm_status mm_set_modes(mm_ctx* ctx, int32_t n, const double* omega, const double
  *     H_13 entry of the Sec. II F Hamiltonian (Eq. (9)) for any mode pair:
  *     da_n/dt gains -i sum_m J_nm a_m; symmetric with a zero diagonal
  *     (else MM_ERR_ARG); NULL = none.
- * Host arrays, finite values.  mm_run_record and mm_adjoint return
- * MM_ERR_STATE while any variant is set. */
+ * Host arrays, finite values.  The adjoint covers the Kerr term and the
+ * mode coupling; mm_run_record and mm_adjoint return MM_ERR_STATE while a
+ * backward coupling is set. */
 mm_status mm_set_cavity_model(mm_ctx* ctx, int32_t n, const double* g_back, const double* kerr,
                               const double* coupling);
 

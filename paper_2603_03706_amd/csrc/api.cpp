@@ -1572,8 +1572,8 @@ void restore_forward(InstCtl& dst, const InstCtl& ck) {
 mm_status mm_run_record(mm_ctx* c, double T, int32_t every) {
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (c->method != MM_RK4 || c->split) return fail(MM_ERR_STATE, "recording needs the fixed-step RK4 method");
-  if (c->nonrecip || c->kerr_on || c->jcpl_on)
-    return fail(MM_ERR_STATE, "the adjoint covers the reciprocal, linear cavity without mode coupling");
+  if (c->nonrecip)
+    return fail(MM_ERR_STATE, "the adjoint covers reciprocal coupling (g_b = g)");
   if (!(T > 0) || !std::isfinite(T) || every < 1) return fail(MM_ERR_ARG, "need T > 0 and checkpoint_every >= 1");
   if (mm_status s = check_ready(c)) return s;
   const double r = T / c->dt0;
@@ -1652,8 +1652,8 @@ static mm_status adjoint_impl(mm_ctx* c, const double* dL_da, const float* dL_dm
                               double* grad_a0, float* grad_m0) {
   if (!c || !dL_da) return fail(MM_ERR_ARG, "NULL context or dL_da");
   if (!c->rec_have) return fail(MM_ERR_STATE, "no recorded run (mm_run_record)");
-  if (c->nonrecip || c->kerr_on || c->jcpl_on)
-    return fail(MM_ERR_STATE, "the adjoint covers the reciprocal, linear cavity without mode coupling");
+  if (c->nonrecip)
+    return fail(MM_ERR_STATE, "the adjoint covers reciprocal coupling (g_b = g)");
   if (mm_status s = set_device(c)) return s;
   const int N = c->N, S = c->p.sublattices, K = c->rec_K;
   const size_t nc = (size_t)c->L.ncell, vec = (size_t)3 * S * nc;

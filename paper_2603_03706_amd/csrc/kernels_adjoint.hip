@@ -385,6 +385,9 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__
     for (int c = 0; c < 3; ++c) C->grad_B0[c] += tot[MMI_ASLOT_B0 + c];
     const double cst = (ST == 4) ? h : 0.5 * h;
     const double wprev = h * (ST == 2 ? 1.0 : 2.0) / 6.0;
+    // mu_a of every mode first: with direct mode coupling it reads the
+    // lambda_ka of all modes, which the update below overwrites
+    double mu[MMI_MAX_MODES][2];
     for (int n = 0; n < N; ++n) {
       const double c = D.cphi[n], s = D.sphi[n], g = D.g[n];
       const double lr = C->lka[n][0], li = C->lka[n][1];
@@ -395,13 +398,30 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__
       C->grad_g[n] += lr * fr + li * fi + fb * (2.0 / D.gamma) * (c * as[2 * n] + s * as[2 * n + 1]);
       // mu_a = conj(-kappa - i w) lambda_ka + h0 fb (c, s)
       const double w = D.omega[n], kp = D.kappa[n];
-      const double mur = -kp * lr - w * li + D.h0[n] * fb * c;
-      const double mui = w * lr - kp * li + D.h0[n] * fb * s;
-      C->la[n][0] += mur;
-      C->la[n][1] += mui;
+      double mur = -kp * lr - w * li + D.h0[n] * fb * c;
+      double mui = w * lr - kp * li + D.h0[n] * fb * s;
+      if (D.kerr_on) {
+        // transpose of the Jacobian of -i K |a|^2 a at the stage amplitude
+        const double ar = as[2 * n], ai = as[2 * n + 1], K = D.kerr[n];
+        const double q = K * (ar * ar + ai * ai), x = 2.0 * K * ar * ai;
+        mur += lr * x - li * (q + 2.0 * K * ar * ar);
+        mui += lr * (q + 2.0 * K * ai * ai) - li * x;
+      }
+      if (D.jcpl_on)
+        for (int q = 0; q < N; ++q) {
+          // -i sum_q J_qn a_n in the equation of mode q, J symmetric
+          mur -= D.jcpl[q][n] * C->lka[q][1];
+          mui += D.jcpl[q][n] * C->lka[q][0];
+        }
+      mu[n][0] = mur;
+      mu[n][1] = mui;
+    }
+    for (int n = 0; n < N; ++n) {
+      C->la[n][0] += mu[n][0];
+      C->la[n][1] += mu[n][1];
       if (ST > 1) {
-        C->lka[n][0] = wprev * C->lza[n][0] + cst * mur;
-        C->lka[n][1] = wprev * C->lza[n][1] + cst * mui;
+        C->lka[n][0] = wprev * C->lza[n][0] + cst * mu[n][0];
+        C->lka[n][1] = wprev * C->lza[n][1] + cst * mu[n][1];
       }
     }
     if (ST == 1) C->rec_index -= 1;

@@ -206,3 +206,20 @@ def test_adjoint_spectral_objective():
     # none), so the two agree to the FP32 state, not bit for bit
     assert _rel(u.grad.numpy(), g["u"]) <= 1e-5 and _rel(gg.grad.numpy(), g["g"]) <= 1e-5
     assert _rel(b0.grad.numpy(), g["B0"]) <= 1e-5
+
+
+def test_adjoint_kerr_and_mode_coupling():
+    """Two modes at 5 GHz -+ 30 MHz joined by J/2pi = 50 MHz, each with a
+    self-Kerr term (K |a|^2 / 2pi up to 180 MHz at the start), coupled to the
+    Sim 1 film and driven on mode 0 by the pulse (150 steps of 1 ps, segments
+    64, 64 and a ragged 22): the cavity VJP with the Kerr and coupling
+    Jacobians against the oracle's autograd gradient."""
+    wc, g = TWO_PI * 5e9, TWO_PI * 50e6
+    J = TWO_PI * 50e6
+    inst = variant(W.paper_sim1(), omega=np.array([wc - TWO_PI * 30e6, wc + TWO_PI * 30e6]),
+                   kappa=np.array([TWO_PI * 1e6] * 2), g=np.array([g, 0.8 * g]),
+                   kerr=np.array([TWO_PI * 2e9, TWO_PI * 1e9]),
+                   photon_coupling=np.array([[0.0, J], [J, 0.0]]),
+                   drive_amp=np.array([2e8 + 0j, 0j]), drive_t0=np.array([0.1e-9] * 2),
+                   drive_sigma=np.array([20e-12] * 2), a0=np.array([0.3 + 0j, 0.1j]))
+    _check(inst, steps=150, every=64, mode=0)

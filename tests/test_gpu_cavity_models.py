@@ -149,6 +149,6 @@ def test_photon_coupling_arguments():
         with pytest.raises(mmcav.MMError) as e:
             ctx.set_cavity_model(coupling=J)
         assert e.value.status == mmcav.MM_ERR_ARG
-    with pytest.raises(mmcav.MMError) as e:
-        ctx.run_record(10e-12, 4)
-    assert e.value.status == mmcav.MM_ERR_STATE
+    # the adjoint covers the mode coupling (its gradient is checked with the
+    # adjoint tests); only a backward coupling is refused
+    ctx.run_record(10e-12, 4)
