@@ -152,3 +152,35 @@ def test_photon_coupling_arguments():
     # the adjoint covers the mode coupling (its gradient is checked with the
     # adjoint tests); only a backward coupling is refused
     ctx.run_record(10e-12, 4)
+
+
+def test_batch_mixing_variants_equals_plain_bitwise():
+    """One batch whose instances carry different cavity options (the pulse,
+    a Kerr term, a backward coupling, two modes joined by J, the split
+    scheme) gives each instance exactly its plain run: every option lives
+    in the instance's own descriptor."""
+    from paper_2603_03706_amd import mmcav
+    w = TWO_PI * 5e9
+    base = W.paper_sim1(T=0.5e-9)
+    insts = [base,
+             variant(base, drive_amp=None, kerr=np.array([TWO_PI * 1e9]), a0=np.array([0.1 + 0j])),
+             variant(base, g_back=np.array([TWO_PI * 20e6])),
+             _two_mode(w - TWO_PI * 30e6, w + TWO_PI * 30e6, TWO_PI * 50e6, TWO_PI * 40e6,
+                       a0=np.array([0.01 + 0j, 0j]), T=0.5e-9),
+             variant(base, method="split")]
+    plain = []
+    for inst in insts:
+        c = gpu_for(inst)
+        c.set_sampling(10e-12, 100)
+        c.run(base.T)
+        plain.append((c.get_m(), c.get_a(), c.get_trace(100)))
+    ctxs = [gpu_for(inst) for inst in insts]
+    for c in ctxs:
+        c.set_sampling(10e-12, 100)
+    b = mmcav.Batch(ctxs)
+    b.run(base.T)
+    for c, (m, a, tr) in zip(ctxs, plain):
+        assert np.array_equal(c.get_m(), m) and np.array_equal(c.get_a(), a)
+        t2 = c.get_trace(100)
+        assert all(np.array_equal(x, y) for x, y in zip(t2, tr))
+    b.close()
