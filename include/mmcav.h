@@ -278,7 +278,11 @@ mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, 
 /* Advance by T (a whole number of RK4 steps of dt0, relative slack 1e-9)
  * from the current state and keep a checkpoint (m, a, t) every
  * `checkpoint_every` steps (device memory) for a later mm_adjoint.  The
- * context must use MM_RK4.  Replaces any earlier recording. */
+ * context must use MM_RK4 (not MM_RK4_SPLIT) and reciprocal coupling (no
+ * g_back from mm_set_cavity_model), else MM_ERR_STATE; the drive, the Kerr
+ * term and the mode coupling are covered.  Replaces any earlier recording.
+ * With sampling set (dt_sample = dt0), the trace of the recorded run gives
+ * a at every step end for mm_adjoint_trace. */
 mm_status mm_run_record(mm_ctx* ctx, double T, int32_t checkpoint_every);
 
 /* Gradients of a scalar loss L(m(T), a(T)) of the recorded run, by the
