@@ -737,7 +737,7 @@ def test_p16_nonreciprocal_splitting():
 
 @pytest.mark.parametrize("method", ["rk4", "dp45"])
 def test_p16_photon_coupling_two_cavities(method):
-    """g = 0, two equal cavities joined by J (the H_13 entry of Eq. (9)):
+    """g = 0, two equal cavities joined by J (the H_13 entry of Eq. (14)):
     a_1 = e^{(-i w - kappa) t} (a_1(0) cos Jt - i a_2(0) sin Jt), and the
     same with 1 and 2 swapped."""
     w, kp, J = TWO_PI * 5e9, TWO_PI * 3e6, TWO_PI * 80e6
@@ -756,7 +756,7 @@ def test_p16_photon_coupling_two_cavities(method):
 
 
 def test_p16_three_mode_with_direct_coupling():
-    """Eq. (9) with a nonzero H_13 = J: the rates of the coupled run are the
+    """Eq. (14) with a nonzero H_13 = J: the rates of the coupled run are the
     eigenvalues of the 3x3 Hermitian matrix (numpy eigvalsh), and the dark
     state of the J = 0 case is no longer an eigenvector."""
     g, J = TWO_PI * 50e6, TWO_PI * 30e6
@@ -810,3 +810,104 @@ def test_p17_split_error_is_first_order():
     assert 1.8 < es[0] / es[1] < 2.3
     assert 13 < ej[0] / ej[1] < 19
     assert es[0] > 100 * ej[0]
+
+
+# ------------------------------------- m^- normalisation on a masked geometry
+def masked_sphere_rabi(n=12, gMHz=50.0):
+    """Staircase sphere of diameter n cells on an n^3 grid (about half of the
+    cells magnetic), isotropic local demag N = 1/3 (no shift of the Kittel
+    mode), uniform profile, at resonance with the cavity: the uniform state
+    precesses as one macrospin."""
+    w = TWO_PI * 5e9
+    mask = W.sphere_mask(n, n / 2.0)
+    inst = W.Instance(grid=(n, n, n), cell=(5e-9,) * 3, **W.YIG, B0=(0.0, 0.0, w / GAMMA),
+                      demag=DEMAG_LOCAL, n_local=(1 / 3, 1 / 3, 1 / 3), geometry=mask,
+                      omega=np.array([w]), kappa=np.array([TWO_PI * 1e6]), g=np.array([TWO_PI * gMHz * 1e6]),
+                      m0=W.tilted((n, n, n), 0.0, 0.0) * mask[None, None], a0=np.array([0.01 + 0j]),
+                      method="rk4", dt0=1e-12, dt_sample=10e-12)
+    return inst
+
+
+def test_masked_sphere_splitting_is_2g():
+    """Eq. (2) weighted as in Eq. (18) averages over the N_geo magnetic cells
+    only: on a masked sphere the polariton splitting at resonance is 2g
+    (Eq. (6) with Delta = 0).  Dividing by the grid's cell count instead
+    would scale the cavity's drive by N_geo/N_cells (0.52 here) and give a
+    splitting of about 1.44 g."""
+    inst = masked_sphere_rabi()
+    n_geo = int(inst.geometry.sum())
+    assert n_geo / inst.cells < 0.6
+    M = Model(Problem(**inst.oracle_kwargs()))
+    assert M.n_geo == n_geo
+    s = co_rotating_rates(M, inst.m0, inst.a0, T=4e-9, dt=1e-12, sample=10e-12)
+    split = abs(s[0].imag - s[1].imag)
+    g = inst.g[0]
+    assert abs(split - 2 * g) <= 2e-3 * 2 * g, (split / TWO_PI / 1e6, 2 * g / TWO_PI / 1e6)
+
+
+# ------------------------------------------ DP45 step-size law, by hand
+def _controller_by_hand(lam, a0, tol, h0, T, expo=-0.2, cap_after_reject=True):
+    """The accept/reject sequence of Dormand-Prince 5(4) on da/dt = lam a,
+    written out from the controller law alone: eps = max(|Re E|, |Im E|)/tol
+    with E = (R5 - R4)(lam h) a, the local error of the embedded pair
+    (closed-form polynomials pinned in P1); accept iff eps <= 1; the next
+    step is h min(fmax, max(0.2, 0.9 eps^expo)), fmax = 5, or 1 on the step
+    after a rejection; the last step is clipped onto T."""
+    t, a, dt, last_rej = 0.0, complex(a0), float(h0), False
+    acc = rej = capped = 0
+    while t < T:
+        rem = T - t
+        h = dt
+        clipped = h * (1.0 + 1e-9) >= rem
+        if clipped:
+            h = rem
+        z = lam * h
+        E = theory.dp_error_polynomial(z) * a
+        eps = max(abs(E.real), abs(E.imag)) / tol
+        if eps <= 1.0:
+            a = a * theory.dp5_stability(z)
+            t = T if clipped else t + h
+            acc += 1
+            raw = 5.0 if eps == 0.0 else 0.9 * eps ** expo
+            fmax = 1.0 if (last_rej and cap_after_reject) else 5.0
+            if last_rej and raw > 1.0:
+                capped += 1
+            f = min(fmax, max(0.2, raw))
+            last_rej = False
+        else:
+            rej += 1
+            f = min(1.0, max(0.2, 0.9 * eps ** expo))
+            last_rej = True
+        dt = h * f
+    return dict(accepted=acc, rejected=rej, dt=dt, a=a, capped=capped)
+
+
+CONTROLLER_CASE = dict(w=TWO_PI * 5e9, k=TWO_PI * 30e6, a0=0.3 - 0.4j, tol=1e-6, h0=100e-12, T=400e-12)
+
+
+def test_controller_law_by_hand():
+    """With g = 0 and the magnetisation static (m along B0) the DP45 error is
+    that of the linear cavity alone, so the whole step-size sequence follows
+    from the controller law: counts, final proposal and amplitude match the
+    hand computation; the run includes rejections, a post-rejection cap and
+    a clipped last step.  A wrong exponent or a missing cap changes the
+    sequence, so either would fail here."""
+    c = CONTROLLER_CASE
+    lam = -1j * c["w"] - c["k"]
+    ref = _controller_by_hand(lam, c["a0"], c["tol"], c["h0"], c["T"])
+    assert ref["rejected"] >= 2 and ref["capped"] >= 1 and ref["accepted"] >= 10
+    for alt in (_controller_by_hand(lam, c["a0"], c["tol"], c["h0"], c["T"], expo=-0.25),
+                _controller_by_hand(lam, c["a0"], c["tol"], c["h0"], c["T"], cap_after_reject=False)):
+        assert (alt["accepted"], alt["rejected"]) != (ref["accepted"], ref["rejected"]) or \
+            abs(alt["dt"] - ref["dt"]) > 1e-6 * ref["dt"]
+    M = macrospin(B0=(0, 0, 0.1), omega=[c["w"]], kappa=[c["k"]], g=[0.0])
+    st = Stepper(M, state(0, 0), np.array([c["a0"]]), method="dp45", dt0=c["h0"])
+    with torch.no_grad():
+        status = st.run(c["T"], tol=c["tol"])
+    assert status == OK and st.t == c["T"]
+    assert (st.accepted, st.rejected) == (ref["accepted"], ref["rejected"])
+    # the embedded error is a difference of O(1) stage sums that cancel to
+    # O(|lam h|^5) ~ 1e-6, so the two evaluations of eps agree to ~1e-10
+    # relative, and the step sizes (eps^(-1/5)) to better than 1e-8
+    assert abs(st.dt - ref["dt"]) <= 1e-8 * ref["dt"]
+    assert abs(complex(st.a[0]) - ref["a"]) <= 1e-12 * abs(c["a0"])
