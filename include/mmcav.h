@@ -4,7 +4,7 @@
  * (arXiv 2603.03706, "Multimode cavity magnonics in mumax+").
  *
  * What one step computes (all on the GPU, no host round trip per step):
- *   - cavity modes (Sec. II A Eq. (1), Sec. II E Eq. (12); dissipative part
+ *   - cavity modes (Sec. II A Eq. (1), Sec. II F Eq. (12); dissipative part
  *     of Sec. IV H Eq. (19) written as a phase Phi_n):
  *         da_n/dt = (-i w_n - k_n) a_n + i g_n e^{-i Phi_n} m^-_n
  *   - mode-weighted co-rotating average (Eq. (2) weighted as in Eq. (18)):
@@ -114,7 +114,7 @@ mm_status mm_bind_workspace(mm_ctx* ctx, void* device_ptr, size_t bytes);
  * the stream and has finished when the call returns. */
 mm_status mm_set_stream(mm_ctx* ctx, void* hip_stream);
 
-/* Cavity modes (Sec. II E): n in [0, MM_MAX_MODES]; omega, kappa, g [rad/s]
+/* Cavity modes (Sec. II F): n in [0, MM_MAX_MODES]; omega, kappa, g [rad/s]
  * (kappa >= 0); u: host [n][nz][ny][nx] mode profiles, or NULL for u = 1;
  * phi: dissipative phase per mode [rad] or NULL for 0; sublattice_sign:
  * c_s per sublattice (+1/-1) or NULL for +1.  h0_n = 2 g_n / gamma is
@@ -131,7 +131,7 @@ mm_status mm_set_modes(mm_ctx* ctx, int32_t n, const double* omega, const double
  *   kerr: self-Kerr coefficient K_n [rad/s] (Sec. V names Kerr terms as a
  *     cavity-model variant): da_n/dt gains -i K_n |a_n|^2 a_n; NULL = none.
  *   coupling: host [n][n] direct photon-photon coupling J [rad/s], the
- *     H_13 entry of the Sec. II F Hamiltonian (Eq. (9)) for any mode pair:
+ *     H_13 entry of the Sec. II F coupling matrix (Eq. (14)) for any mode pair:
  *     da_n/dt gains -i sum_m J_nm a_m; symmetric with a zero diagonal
  *     (else MM_ERR_ARG); NULL = none.
  * Host arrays, finite values.  The adjoint covers the Kerr term and the
@@ -319,7 +319,11 @@ mm_status mm_adjoint_trace(mm_ctx* ctx, const double* dL_dtrace, int64_t count, 
 mm_status mm_demag_tensor(double X, double Y, double Z, double dx, double dy, double dz,
                           double* out6);
 
-/* Description of the last error on this thread (never NULL). */
+/* Description of the last error on this thread (never NULL).  The error
+ * text is kept per calling thread rather than per context: every entry point
+ * (including mm_create, which has no context yet, and the batch calls, which
+ * span several) records its failure in the same place, and with one context
+ * per thread at a time the two are the same. */
 const char* mm_last_error(void);
 
 #ifdef __cplusplus

@@ -7,7 +7,7 @@ State: m with shape (S, 3, nz, ny, nx) (S = 1 ferromagnet, 2 antiferromagnet
 sublattices), zero on non-magnetic cells; a, complex, shape (N,).
 
 Equations (SI units, fields in tesla, rates in rad/s):
-  * cavity modes, Sec. II A Eq. (1) and Sec. II E Eq. (12), with the
+  * cavity modes, Sec. II A Eq. (1) and Sec. II F Eq. (12), with the
     dissipative phase of Sec. IV H Eq. (19) written as g e^{-i Phi}:
         da_n/dt = (-i w_n - k_n) a_n + i g_n e^{-i Phi_n} m^-_n + eta_n(t)
     with the external microwave drive eta_n(t) of Eq. (1) / Eq. (12) taken as
@@ -18,7 +18,7 @@ Equations (SI units, fields in tesla, rates in rad/s):
     h0_n = 2 g_b,n / gamma in the feedback; a self-Kerr term
     -i K_n |a_n|^2 a_n added to da_n/dt
   * direct photon-photon coupling (the H_13 entry of the Sec. II F
-    Hamiltonian, Eq. (9)): da_n/dt gains -i sum_m J_nm a_m with J real
+    coupling matrix, Eq. (14)): da_n/dt gains -i sum_m J_nm a_m with J real
     symmetric and zero on the diagonal
   * co-rotating average, Eq. (2) weighted by the mode profile as in Eq. (18):
         m^-_n = 1/N_geo sum_i G_i u_n(r_i) (1/S) sum_s c_s (m_sx - i m_sy)

@@ -44,20 +44,20 @@ def rabi_period(g):
 
 
 def three_mode(w1, wm, w2, g1, g2):
-    """Eigenvalues and eigenvectors of the 3x3 matrix of Sec. II E Eq. (14),
+    """Eigenvalues and eigenvectors of the 3x3 matrix of Sec. II F Eq. (14),
     basis (|1>, |m>, |2>)."""
     H = np.array([[w1, g1, 0.0], [g1, wm, g2], [0.0, g2, w2]])
     return np.linalg.eigh(H)
 
 
 def afmr(BE, BA, gamma=1.76e11):
-    """Zero-field AFM resonance gamma sqrt(2 B_E B_A + B_A^2), Sec. II F
+    """Zero-field AFM resonance gamma sqrt(2 B_E B_A + B_A^2), Sec. II G
     Eq. (15), fields in tesla (B = mu0 H)."""
     return gamma * np.sqrt(2.0 * BE * BA + BA * BA)
 
 
 def afm_split(BE, BA, B, gamma=1.76e11):
-    """Field-split AFM branches w_AFMR -+ gamma B, Sec. II F Eq. (16)."""
+    """Field-split AFM branches w_AFMR -+ gamma B, Sec. II G Eq. (16)."""
     w0 = afmr(BE, BA, gamma)
     return w0 - gamma * B, w0 + gamma * B
 

@@ -881,6 +881,14 @@ mm_status begin_run(mm_batch* b, double T, double tol) {
     h.dt_max = c->dt_max;
     h.done = 0;
     h.status = 0;
+    // the run-start stage kernel evaluates the feedback from the stage
+    // amplitude: it must be the amplitude of the state the run starts from
+    // (a previous run leaves the next stage input there, mm_set_a and
+    // mm_set_state set a alone)
+    for (int n = 0; n < MMI_MAX_MODES; ++n) {
+      h.as[n][0] = h.a[n][0];
+      h.as[n][1] = h.a[n][1];
+    }
     h.rec_index = c->record_next;
     c->record_next = -1;
     if (c->sampling_changed) {

@@ -13,7 +13,7 @@ namespace mmk {
 // amplitudes of all modes in A: (-i w - kappa) a + i g e^{-i Phi} m^-
 // (Eq. (12) with the phase of Eq. (19)), plus, when set, the self-Kerr term
 // -i K |a|^2 a, the direct mode coupling -i sum_m J_nm a_m (the H_13 entry of
-// Eq. (9)) and the Gaussian drive eta_n(t) of Eq. (1).
+// Eq. (14)) and the Gaussian drive eta_n(t) of Eq. (1).
 __device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double t, const double (*A)[2],
                                         double mr, double mi, double& fr, double& fi) {
   const double ar = A[n][0], ai = A[n][1];

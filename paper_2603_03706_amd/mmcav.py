@@ -416,7 +416,12 @@ class RecordedRunFunction(torch.autograd.Function):
                 raise RuntimeError("trace of the recorded run has %d samples, expected %d" % (at.shape[0], steps + 1))
             tr = torch.from_numpy(np.stack([at.real, at.imag], axis=-1))
         fctx.context = c
-        return (torch.from_numpy(np.stack([a.real, a.imag], axis=-1)), torch.from_numpy(c.get_m()), tr)
+        # outputs on the device of u; gradients go back on each input's own
+        # device and dtype
+        fctx.like = [(x.device, x.dtype) for x in (u, g, alpha, B0)]
+        dev = u.device
+        return (torch.from_numpy(np.stack([a.real, a.imag], axis=-1)).to(dev), torch.from_numpy(c.get_m()).to(dev),
+                tr.to(dev))
 
     @staticmethod
     def backward(fctx, grad_a, grad_m, grad_trace):
@@ -430,8 +435,10 @@ class RecordedRunFunction(torch.autograd.Function):
         g = c.adjoint(ga[:, 0] + 1j * ga[:, 1], gm, gt)
         c.close()
         fctx.context = None
-        return (torch.from_numpy(g["u"]), torch.from_numpy(g["g"]), torch.tensor(g["alpha"], dtype=torch.float64),
-                torch.from_numpy(np.asarray(g["B0"], np.float64)), None, None, None, None)
+        grads = (torch.from_numpy(g["u"]), torch.from_numpy(g["g"]), torch.tensor(g["alpha"], dtype=torch.float64),
+                 torch.from_numpy(np.asarray(g["B0"], np.float64)))
+        grads = tuple(x.to(device=d, dtype=t) for x, (d, t) in zip(grads, fctx.like))
+        return grads + (None, None, None, None)
 
 
 def recorded_run(inst, T, u, g, alpha, B0, checkpoint_every=256, with_trace=False):

@@ -202,7 +202,7 @@ def afm_instance(k, size=None, nz=16):
     s = afm_size(k) if size is None else size
     grid = (s, s, nz)
     BA = 2.0 * AFM["Ku"] / AFM["Ms"]
-    wc = GAMMA * math.sqrt(2.0 * AFM["B_E"] * BA + BA * BA)      # resonance of Sec. II F
+    wc = GAMMA * math.sqrt(2.0 * AFM["B_E"] * BA + BA * BA)      # resonance of Sec. II G, Eq. (15)
     az = TWO_PI * np.random.default_rng(4).uniform()
     return Instance(grid=grid, cell=(2e-9,) * 3, Ms=AFM["Ms"], Aex=AFM["Aex"], alpha=AFM["alpha"],
                     Ku=AFM["Ku"], ku_axis=(0.0, 0.0, 1.0), B0=(0.0, 0.0, 0.0), demag=DEMAG_NONE,

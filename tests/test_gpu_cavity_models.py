@@ -117,7 +117,7 @@ def test_photon_coupling_two_cavities(method):
 
 def test_three_mode_direct_coupling():
     """Two cavities at w_m -+ g, both coupled to the 8x8x1 film and to each
-    other by J (Eq. (9) with H_13 = J): parity with the oracle over 1 ns, then
+    other by J (Eq. (14) with H_13 = J): parity with the oracle over 1 ns, then
     the rates of a 10 ns run at the eigenvalues of the 3x3 matrix (1 MHz)."""
     g, J = TWO_PI * 50e6, TWO_PI * 30e6
     wm = TWO_PI * 5e9
