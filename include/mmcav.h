@@ -218,9 +218,33 @@ mm_status mm_batch_get_streams(const mm_batch* b, int32_t* parts);
  * non-OK instance status, or MM_OK; per-instance status in mm_get_stats. */
 mm_status mm_batch_run(mm_batch* b, double T, double tol);
 /* Advance every unfinished instance by exactly `steps` attempted steps from
- * its current state (t_end = +inf), for throughput measurement. */
+ * its current state (t_end = +inf), for throughput measurement.  The run
+ * starts by evaluating the first derivative at the current state (as every
+ * run does) and ends by reading each instance's statistics back; the steps
+ * run as captured graphs (32-step graphs, then graphs of 16, 8, 4, 2 and 1
+ * steps for the remainder). */
 mm_status mm_batch_step(mm_batch* b, int64_t steps, double tol);
 mm_status mm_batch_destroy(mm_batch* b);
+
+/* Open-ended stepping in three calls, so that a caller can time or stream
+ * steps without the per-run set-up and read-back (Sec. III A: the RK45 loop
+ * stays on the device with no per-step host transfer):
+ *  - mm_batch_begin sets every instance's run parameters (no end time, tol
+ *    as in mm_run), enqueues the run-start derivative and captures every
+ *    step graph; it returns without waiting for the device.
+ *  - mm_batch_advance enqueues exactly `steps` further attempted steps of
+ *    every unfinished instance as graph launches on the batch's streams and
+ *    returns at once; consecutive calls continue one run (FSAL, dt and the
+ *    trace carry over), bit for bit as one mm_batch_step of the summed count.
+ *  - mm_batch_end waits for the device, reads every instance's statistics
+ *    (mm_get_stats) and returns the first non-OK instance status.
+ * Between begin and end, any call on the batch or on one of its contexts
+ * other than advance, end and mm_batch_destroy (which waits and closes the
+ * run) returns MM_ERR_STATE; so does begin on a batch with an open run or
+ * with an instance in another open run, and advance/end with none. */
+mm_status mm_batch_begin(mm_batch* b, double tol);
+mm_status mm_batch_advance(mm_batch* b, int64_t steps);
+mm_status mm_batch_end(mm_batch* b);
 
 /* Autotune the batch.  With two or more instances it first times whole
  * steps (32 + 2 x 64 attempted steps) of the batch run as 1, 2 and 3

@@ -37,6 +37,9 @@ mm_status fail(mm_status s, const std::string& msg) {
 
 constexpr double kMu0 = 4e-7 * M_PI;
 
+// Error of a context call made while the context is in an open batch run.
+mm_status open_error() { return fail(MM_ERR_STATE, "the instance is in an open batch run (mm_batch_end first)"); }
+
 constexpr int kStepsPerGraph = 32;
 // Sub-batches (streams) a new batch runs as; mm_batch_tune may choose more.
 constexpr int kDefaultParts = 1;
@@ -273,6 +276,7 @@ struct mm_ctx {
   bool m_set = false;
   hipStream_t user_stream = nullptr;
   mm_batch* solo = nullptr;      // batch of one for mm_run
+  mm_batch* open_in = nullptr;   // batch with an open run (mm_batch_begin .. mm_batch_end)
   unsigned version = 1;          // bumps when the descriptor changes
   mm_stats stats{};
   InstDesc desc{};
@@ -314,6 +318,10 @@ struct mm_batch {
   std::vector<Group> groups;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  hipGraphExec_t exec_pow[5] = {};   // 1, 2, 4, 8 and 16 steps (step counts below kStepsPerGraph)
+  hipGraph_t graph_pow[5] = {};
+  bool open = false;                 // between mm_batch_begin and mm_batch_end
+  std::chrono::steady_clock::time_point open_t0{};
   hipGraphExec_t exec_rev = nullptr;
   hipGraph_t graph_rev = nullptr;
   hipEvent_t ev = nullptr;
@@ -332,6 +340,15 @@ struct mm_batch {
 };
 
 namespace {
+
+// A batch is busy while it, one of its parts or one of its instances has an
+// open run.
+bool batch_busy(const mm_batch* b) {
+  if (b->open) return true;
+  for (const mm_ctx* c : b->ctxs)
+    if (c->open_in) return true;
+  return false;
+}
 
 mm_status upload_desc(mm_ctx* c);
 
@@ -791,11 +808,11 @@ mm_status enqueue_step(mm_batch* b) {
   return MM_OK;
 }
 
-mm_status ensure_graph(mm_batch* b) {
-  if (b->exec) return MM_OK;
+// Capture `steps` consecutive steps of the batch into one executable graph.
+mm_status capture_steps(mm_batch* b, int steps, hipGraph_t* graph, hipGraphExec_t* exec) {
   MM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   mm_status st = MM_OK;
-  for (int k = 0; k < kStepsPerGraph && st == MM_OK; ++k) st = enqueue_step(b);
+  for (int k = 0; k < steps && st == MM_OK; ++k) st = enqueue_step(b);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(b->stream, &g);
   if (st != MM_OK) {
@@ -803,8 +820,52 @@ mm_status ensure_graph(mm_batch* b) {
     return st;
   }
   if (e != hipSuccess) return fail(MM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-  b->graph = g;
-  MM_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  *graph = g;
+  MM_HIP(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
+  return MM_OK;
+}
+
+mm_status ensure_graph(mm_batch* b) {
+  if (b->exec) return MM_OK;
+  return capture_steps(b, kStepsPerGraph, &b->graph, &b->exec);
+}
+
+// Graph of 2^lg steps (lg 0..4).
+mm_status ensure_graph_pow(mm_batch* b, int lg) {
+  if (b->exec_pow[lg]) return MM_OK;
+  return capture_steps(b, 1 << lg, &b->graph_pow[lg], &b->exec_pow[lg]);
+}
+
+// Every captured graph of the batch (after a change of work tables or
+// strategy they no longer match the launches the batch would make).
+void drop_graphs(mm_batch* b) {
+  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
+  for (int i = 0; i < 5; ++i) {
+    if (b->exec_pow[i]) { hipGraphExecDestroy(b->exec_pow[i]); b->exec_pow[i] = nullptr; }
+    if (b->graph_pow[i]) { hipGraphDestroy(b->graph_pow[i]); b->graph_pow[i] = nullptr; }
+  }
+  if (b->exec_rev) { hipGraphExecDestroy(b->exec_rev); b->exec_rev = nullptr; }
+  if (b->graph_rev) { hipGraphDestroy(b->graph_rev); b->graph_rev = nullptr; }
+}
+
+// Graph launches for exactly `steps` steps on every part (or the batch
+// itself): whole 32-step graphs, then the binary digits of the remainder.
+// Graphs are captured on first use.
+mm_status launch_steps(mm_batch* b, int64_t steps) {
+  std::vector<mm_batch*> seq = b->parts;
+  if (seq.empty()) seq.push_back(b);
+  for (mm_batch* p : seq) {
+    if (mm_status s = ensure_graph(p)) return s;
+    for (int lg = 0; lg < 5; ++lg)
+      if ((steps % kStepsPerGraph) >> lg & 1)
+        if (mm_status s = ensure_graph_pow(p, lg)) return s;
+  }
+  for (int64_t left = steps; left >= kStepsPerGraph; left -= kStepsPerGraph)
+    for (mm_batch* p : seq) MM_HIP(hipGraphLaunch(p->exec, p->stream));
+  for (int lg = 4; lg >= 0; --lg)
+    if ((steps % kStepsPerGraph) >> lg & 1)
+      for (mm_batch* p : seq) MM_HIP(hipGraphLaunch(p->exec_pow[lg], p->stream));
   return MM_OK;
 }
 
@@ -856,7 +917,7 @@ mm_status ensure_reverse_graph(mm_batch* b) {
 
 mm_status wait_user_streams(mm_batch* b) {
   for (mm_ctx* c : b->ctxs)
-    if (c->user_stream) {
+    if (c->user_stream && c->user_stream != b->stream) {
       MM_HIP(hipEventRecord(b->ev, c->user_stream));
       MM_HIP(hipStreamWaitEvent(b->stream, b->ev, 0));
     }
@@ -1040,23 +1101,22 @@ mm_status parts_run(mm_batch* b, double T, double tol) {
   return first;
 }
 
-// Exactly `steps` attempted steps of every part, interleaved per graph.
-mm_status parts_step(mm_batch* b, int64_t steps, double tol) {
-  const auto t0 = std::chrono::steady_clock::now();
-  for (mm_batch* p : b->parts) {
+// Begin an open-ended run of every part (or of the batch itself).
+mm_status open_run(mm_batch* b, double tol) {
+  std::vector<mm_batch*> seq = b->parts;
+  if (seq.empty()) seq.push_back(b);
+  for (mm_batch* p : seq)
     if (mm_status s = begin_run(p, -1.0, tol)) return s;
-    if (mm_status s = ensure_graph(p)) return s;
-  }
-  int64_t left = steps;
-  for (; left >= kStepsPerGraph; left -= kStepsPerGraph)
-    for (mm_batch* p : b->parts) MM_HIP(hipGraphLaunch(p->exec, p->stream));
-  for (; left > 0; --left)
-    for (mm_batch* p : b->parts)
-      if (mm_status s = enqueue_step(p)) return s;
-  for (mm_batch* p : b->parts) MM_HIP(hipStreamSynchronize(p->stream));
-  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return MM_OK;
+}
+
+// Wait for every part and pull the statistics of its instances.
+mm_status close_run(mm_batch* b, double wall) {
+  std::vector<mm_batch*> seq = b->parts;
+  if (seq.empty()) seq.push_back(b);
+  for (mm_batch* p : seq) MM_HIP(hipStreamSynchronize(p->stream));
   mm_status first = MM_OK;
-  for (mm_batch* p : b->parts) {
+  for (mm_batch* p : seq) {
     const mm_status s = end_run(p, wall);
     if (s != MM_OK && first == MM_OK) first = s;
   }
@@ -1181,6 +1241,7 @@ mm_status mm_create(const mm_params* p, mm_ctx** out) {
 }
 
 mm_status mm_destroy(mm_ctx* c) {
+  if (c && c->open_in) return open_error();
   if (!c) return MM_OK;
   if (c->solo) mm_batch_destroy(c->solo);
   if (c->dev_ready || c->ws) hipSetDevice(c->dev);
@@ -1204,6 +1265,7 @@ mm_status mm_workspace_bytes(const mm_params* p, int32_t n_modes, size_t* bytes)
 }
 
 mm_status mm_bind_workspace(mm_ctx* c, void* ptr, size_t bytes) {
+  if (c && c->open_in) return open_error();
   if (!c || !ptr) return fail(MM_ERR_ARG, "NULL context or pointer");
   if (c->dev_ready) return fail(MM_ERR_STATE, "device memory already in use; bind before mm_set_modes");
   if (((uintptr_t)ptr) % kAlign) return fail(MM_ERR_ARG, "workspace must be 256-byte aligned");
@@ -1218,6 +1280,7 @@ mm_status mm_bind_workspace(mm_ctx* c, void* ptr, size_t bytes) {
 }
 
 mm_status mm_set_stream(mm_ctx* c, void* stream) {
+  if (c && c->open_in) return open_error();
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   c->user_stream = (hipStream_t)stream;
   return MM_OK;
@@ -1225,6 +1288,7 @@ mm_status mm_set_stream(mm_ctx* c, void* stream) {
 
 mm_status mm_set_modes(mm_ctx* c, int32_t n, const double* omega, const double* kappa, const double* g,
                        const float* u, const double* phi, const int8_t* sign) {
+  if (c && c->open_in) return open_error();
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (n < 0 || n > MM_MAX_MODES) return fail(MM_ERR_ARG, "mode count out of range");
   if (n > 0 && (!omega || !kappa || !g)) return fail(MM_ERR_ARG, "omega, kappa and g are required");
@@ -1292,6 +1356,7 @@ mm_status mm_set_modes(mm_ctx* c, int32_t n, const double* omega, const double* 
 
 mm_status mm_set_cavity_model(mm_ctx* c, int32_t n, const double* g_back, const double* kerr,
                               const double* coupling) {
+  if (c && c->open_in) return open_error();
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (!c->modes_set) return fail(MM_ERR_STATE, "modes not set (mm_set_modes)");
   if (n != 0 && n != c->N) return fail(MM_ERR_ARG, "count must equal the mode count");
@@ -1317,6 +1382,7 @@ mm_status mm_set_cavity_model(mm_ctx* c, int32_t n, const double* g_back, const 
 }
 
 mm_status mm_set_drive(mm_ctx* c, int32_t n, const double* amp, const double* t0, const double* sigma) {
+  if (c && c->open_in) return open_error();
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (!c->modes_set) return fail(MM_ERR_STATE, "modes not set (mm_set_modes)");
   if (n == 0 || !amp) {
@@ -1343,6 +1409,7 @@ mm_status mm_set_drive(mm_ctx* c, int32_t n, const double* amp, const double* t0
 }
 
 mm_status mm_set_m(mm_ctx* c, const float* m) {
+  if (c && c->open_in) return open_error();
   if (!c || !m) return fail(MM_ERR_ARG, "NULL argument");
   const size_t nc = (size_t)c->L.ncell;
   const int S = c->p.sublattices;
@@ -1369,6 +1436,7 @@ mm_status mm_set_m(mm_ctx* c, const float* m) {
 }
 
 mm_status mm_set_a(mm_ctx* c, const double* a) {
+  if (c && c->open_in) return open_error();
   if (!c || !a) return fail(MM_ERR_ARG, "NULL argument");
   if (!c->modes_set) return fail(MM_ERR_STATE, "modes not set");
   for (int i = 0; i < 2 * c->N; ++i)
@@ -1383,6 +1451,7 @@ mm_status mm_set_a(mm_ctx* c, const double* a) {
 }
 
 mm_status mm_set_stepper(mm_ctx* c, int32_t method, double dt0, double dt_min, double dt_max) {
+  if (c && c->open_in) return open_error();
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (method != MM_RK4 && method != MM_DP45 && method != MM_RK4_SPLIT) return fail(MM_ERR_ARG, "unknown method");
   const bool split = method == MM_RK4_SPLIT;
@@ -1414,6 +1483,7 @@ mm_status mm_set_stepper(mm_ctx* c, int32_t method, double dt0, double dt_min, d
 }
 
 mm_status mm_set_sampling(mm_ctx* c, double dt_sample, int64_t max_samples) {
+  if (c && c->open_in) return open_error();
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (max_samples < 0) return fail(MM_ERR_ARG, "max_samples must be >= 0");
   if (max_samples > 0 && !(dt_sample > 0 && std::isfinite(dt_sample))) return fail(MM_ERR_ARG, "dt_sample must be > 0");
@@ -1438,6 +1508,7 @@ mm_status mm_set_sampling(mm_ctx* c, double dt_sample, int64_t max_samples) {
 }
 
 mm_status mm_run(mm_ctx* c, double T, double tol) {
+  if (c && c->open_in) return open_error();
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (!(T > 0) || !std::isfinite(T)) return fail(MM_ERR_ARG, "T must be finite and > 0");
   if (mm_status s = check_ready(c)) return s;
@@ -1451,6 +1522,7 @@ mm_status mm_run(mm_ctx* c, double T, double tol) {
 }
 
 mm_status mm_get_m(const mm_ctx* c, float* out) {
+  if (c && c->open_in) return open_error();
   if (!c || !out) return fail(MM_ERR_ARG, "NULL argument");
   if (!c->dev_ready || !c->m_set) return fail(MM_ERR_STATE, "no state on the device");
   InstCtl h;
@@ -1461,6 +1533,7 @@ mm_status mm_get_m(const mm_ctx* c, float* out) {
 }
 
 mm_status mm_get_a(const mm_ctx* c, double* out) {
+  if (c && c->open_in) return open_error();
   if (!c || !out) return fail(MM_ERR_ARG, "NULL argument");
   if (!c->dev_ready) return fail(MM_ERR_STATE, "no state on the device");
   InstCtl h;
@@ -1473,6 +1546,7 @@ mm_status mm_get_a(const mm_ctx* c, double* out) {
 }
 
 mm_status mm_get_trace(const mm_ctx* c, double* t, double* a, double* mminus, int64_t* n) {
+  if (c && c->open_in) return open_error();
   if (!c || !n) return fail(MM_ERR_ARG, "NULL argument");
   if (!c->dev_ready) return fail(MM_ERR_STATE, "no state on the device");
   InstCtl h;
@@ -1493,6 +1567,7 @@ mm_status mm_get_trace(const mm_ctx* c, double* t, double* a, double* mminus, in
 }
 
 mm_status mm_get_stats(const mm_ctx* c, mm_stats* out) {
+  if (c && c->open_in) return open_error();
   if (!c || !out) return fail(MM_ERR_ARG, "NULL argument");
   *out = c->stats;
   return MM_OK;
@@ -1508,6 +1583,7 @@ constexpr uint64_t kMagic = 0x6d6d636176310001ULL;
 }  // namespace
 
 mm_status mm_get_state(const mm_ctx* c, void* blob, size_t* bytes) {
+  if (c && c->open_in) return open_error();
   if (!c || !bytes) return fail(MM_ERR_ARG, "NULL argument");
   const size_t mb = sizeof(float) * 3 * c->p.sublattices * (size_t)c->L.ncell;
   const size_t need = sizeof(StateHeader) + sizeof(InstCtl) + mb;
@@ -1529,6 +1605,7 @@ mm_status mm_get_state(const mm_ctx* c, void* blob, size_t* bytes) {
 }
 
 mm_status mm_set_state(mm_ctx* c, const void* blob, size_t bytes) {
+  if (c && c->open_in) return open_error();
   if (!c || !blob) return fail(MM_ERR_ARG, "NULL argument");
   if (bytes < sizeof(StateHeader)) return fail(MM_ERR_ARG, "state blob too small");
   StateHeader hd;
@@ -1578,6 +1655,7 @@ void restore_forward(InstCtl& dst, const InstCtl& ck) {
 }  // namespace
 
 mm_status mm_run_record(mm_ctx* c, double T, int32_t every) {
+  if (c && c->open_in) return open_error();
   if (!c) return fail(MM_ERR_ARG, "NULL context");
   if (c->method != MM_RK4 || c->split) return fail(MM_ERR_STATE, "recording needs the fixed-step RK4 method");
   if (c->nonrecip)
@@ -1620,6 +1698,7 @@ static mm_status adjoint_impl(mm_ctx* c, const double* dL_da, const float* dL_dm
 
 mm_status mm_adjoint(mm_ctx* c, const double* dL_da, const float* dL_dm, float* grad_u, double* grad_g,
                      double* grad_alpha, double* grad_B0, double* grad_a0, float* grad_m0) {
+  if (c && c->open_in) return open_error();
   return adjoint_impl(c, dL_da, dL_dm, nullptr, grad_u, grad_g, grad_alpha, grad_B0, grad_a0, grad_m0);
 }
 
@@ -1772,6 +1851,7 @@ mm_status mm_batch_create(mm_ctx* const* ctxs, int32_t count, mm_batch** out) {
   if (!ctxs || !out || count < 1) return fail(MM_ERR_ARG, "need count >= 1 contexts and an output");
   for (int i = 0; i < count; ++i) {
     if (!ctxs[i]) return fail(MM_ERR_ARG, "NULL context in batch");
+    if (ctxs[i]->open_in) return open_error();
     if (mm_status s = check_ready(ctxs[i])) return s;
     if (ctxs[i]->method != ctxs[0]->method) return fail(MM_ERR_ARG, "all instances need the same method");
     if (ctxs[i]->dev != ctxs[0]->dev) return fail(MM_ERR_ARG, "all instances need the same device");
@@ -1783,6 +1863,7 @@ mm_status mm_batch_create(mm_ctx* const* ctxs, int32_t count, mm_batch** out) {
 }
 
 mm_status mm_batch_set_streams(mm_batch* b, int32_t parts) {
+  if (b && batch_busy(b)) return open_error();
   if (!b) return fail(MM_ERR_ARG, "batch is NULL");
   if (parts < 1 || parts > 8) return fail(MM_ERR_ARG, "parts must be 1..8");
   if (mm_status s = set_device(b->ctxs[0])) return s;
@@ -1802,6 +1883,7 @@ mm_status mm_batch_get_streams(const mm_batch* b, int32_t* parts) {
 }
 
 mm_status mm_batch_run(mm_batch* b, double T, double tol) {
+  if (b && batch_busy(b)) return open_error();
   if (!b) return fail(MM_ERR_ARG, "NULL batch");
   if (!(T > 0) || !std::isfinite(T)) return fail(MM_ERR_ARG, "T must be finite and > 0");
   if (mm_status s = validate_tol(b, tol)) return s;
@@ -1814,22 +1896,57 @@ mm_status mm_batch_run(mm_batch* b, double T, double tol) {
 
 mm_status mm_batch_step(mm_batch* b, int64_t steps, double tol) {
   if (!b || steps < 0) return fail(MM_ERR_ARG, "bad arguments");
+  if (b->open) return fail(MM_ERR_STATE, "the batch has an open run (mm_batch_end first)");
   if (mm_status s = validate_tol(b, tol)) return s;
   if (mm_status s = set_device(b->ctxs[0])) return s;
-  if (!b->parts.empty()) return parts_step(b, steps, tol);
   const auto t0 = std::chrono::steady_clock::now();
-  if (mm_status s = begin_run(b, -1.0, tol)) return s;
-  if (mm_status s = ensure_graph(b)) return s;
-  int64_t left = steps;
-  while (left >= kStepsPerGraph) {
-    MM_HIP(hipGraphLaunch(b->exec, b->stream));
-    left -= kStepsPerGraph;
-  }
-  for (; left > 0; --left)
-    if (mm_status s = enqueue_step(b)) return s;
+  if (mm_status s = open_run(b, tol)) return s;
+  if (mm_status s = launch_steps(b, steps)) return s;
+  for (mm_batch* p : b->parts) MM_HIP(hipStreamSynchronize(p->stream));
   MM_HIP(hipStreamSynchronize(b->stream));
   const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  return end_run(b, wall);
+  return close_run(b, wall);
+}
+
+mm_status mm_batch_begin(mm_batch* b, double tol) {
+  if (!b) return fail(MM_ERR_ARG, "batch is NULL");
+  if (b->open) return fail(MM_ERR_STATE, "the batch already has an open run");
+  if (mm_status s = validate_tol(b, tol)) return s;
+  for (mm_ctx* c : b->ctxs) {
+    if (c->method != b->method) return fail(MM_ERR_STATE, "instance method changed after batch creation");
+    if (c->open_in) return fail(MM_ERR_STATE, "an instance of the batch is in another open run");
+  }
+  if (mm_status s = set_device(b->ctxs[0])) return s;
+  if (mm_status s = open_run(b, tol)) return s;
+  // capture every step graph now, so that mm_batch_advance only launches
+  std::vector<mm_batch*> seq = b->parts;
+  if (seq.empty()) seq.push_back(b);
+  for (mm_batch* p : seq) {
+    if (mm_status s = ensure_graph(p)) return s;
+    for (int lg = 0; lg < 5; ++lg)
+      if (mm_status s = ensure_graph_pow(p, lg)) return s;
+  }
+  b->open = true;
+  b->open_t0 = std::chrono::steady_clock::now();
+  for (mm_ctx* c : b->ctxs) c->open_in = b;
+  return MM_OK;
+}
+
+mm_status mm_batch_advance(mm_batch* b, int64_t steps) {
+  if (!b || steps < 0) return fail(MM_ERR_ARG, "bad arguments");
+  if (!b->open) return fail(MM_ERR_STATE, "no open run (mm_batch_begin first)");
+  if (mm_status s = set_device(b->ctxs[0])) return s;
+  return launch_steps(b, steps);
+}
+
+mm_status mm_batch_end(mm_batch* b) {
+  if (!b) return fail(MM_ERR_ARG, "batch is NULL");
+  if (!b->open) return fail(MM_ERR_STATE, "no open run (mm_batch_begin first)");
+  if (mm_status s = set_device(b->ctxs[0])) return s;
+  b->open = false;
+  for (mm_ctx* c : b->ctxs) c->open_in = nullptr;
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - b->open_t0).count();
+  return close_run(b, wall);
 }
 
 static mm_status check_fft_path(const mm_batch* b, int32_t path) {
@@ -1849,6 +1966,7 @@ static mm_status check_fft_path(const mm_batch* b, int32_t path) {
 }
 
 mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path) {
+  if (b && batch_busy(b)) return open_error();
   if (!b) return fail(MM_ERR_ARG, "batch is NULL");
   if (mm_status s = check_fft_path(b, path)) return s;
   for (mm_batch* p : b->parts)
@@ -1860,10 +1978,7 @@ mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path) {
     if (path == PATH_FUSED) g.TK = std::max(1, fused_tile(g.ny, g.nz, g.py, g.pz));
     if (mm_status s = build_group(g)) return s;
   }
-  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
-  if (b->exec_rev) { hipGraphExecDestroy(b->exec_rev); b->exec_rev = nullptr; }
-  if (b->graph_rev) { hipGraphDestroy(b->graph_rev); b->graph_rev = nullptr; }
+  drop_graphs(b);
   return MM_OK;
 }
 
@@ -1884,6 +1999,7 @@ static mm_status check_fft_x(const mm_batch* b, int32_t path) {
 }
 
 mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path) {
+  if (b && batch_busy(b)) return open_error();
   if (!b) return fail(MM_ERR_ARG, "batch is NULL");
   if (mm_status s = check_fft_x(b, path)) return s;
   for (mm_batch* p : b->parts)
@@ -1897,15 +2013,13 @@ mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path) {
   }
   batch_xfused(b);
   if (mm_status s = upload_batch_descs(b)) return s;
-  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
-  if (b->exec_rev) { hipGraphExecDestroy(b->exec_rev); b->exec_rev = nullptr; }
-  if (b->graph_rev) { hipGraphDestroy(b->graph_rev); b->graph_rev = nullptr; }
+  drop_graphs(b);
   return MM_OK;
 }
 
 mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, char* names, int64_t* launches,
                            double* total_ms, double* bytes_per_launch, int32_t* n) {
+  if (b && batch_busy(b)) return open_error();
   if (!b || !n || steps < 0 || cap < 0) return fail(MM_ERR_ARG, "bad arguments");
   if (mm_status s = validate_tol(b, tol)) return s;
   if (mm_status s = set_device(b->ctxs[0])) return s;
@@ -2050,6 +2164,7 @@ static mm_status tune_fft(mm_batch* b, std::string& rep);
 static mm_status tune_all_fft(mm_batch* b, const std::string& srep, char* report, size_t report_len);
 
 mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
+  if (b && batch_busy(b)) return open_error();
   if (!b) return fail(MM_ERR_ARG, "NULL batch");
   if (mm_status s = set_device(b->ctxs[0])) return s;
   std::string srep;
@@ -2059,6 +2174,7 @@ mm_status mm_batch_tune(mm_batch* b, char* report, size_t report_len) {
 }
 
 mm_status mm_batch_tune_fft(mm_batch* b, char* report, size_t report_len) {
+  if (b && batch_busy(b)) return open_error();
   if (!b) return fail(MM_ERR_ARG, "NULL batch");
   if (mm_status s = set_device(b->ctxs[0])) return s;
   return tune_all_fft(b, "", report, report_len);
@@ -2216,10 +2332,7 @@ static mm_status tune_fft(mm_batch* b, std::string& out) {
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   // launch sequences changed: recapture on next use
-  if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-  if (b->graph) { hipGraphDestroy(b->graph); b->graph = nullptr; }
-  if (b->exec_rev) { hipGraphExecDestroy(b->exec_rev); b->exec_rev = nullptr; }
-  if (b->graph_rev) { hipGraphDestroy(b->graph_rev); b->graph_rev = nullptr; }
+  drop_graphs(b);
   MM_HIP(hipStreamSynchronize(b->stream));
   out = rep;
   return MM_OK;
@@ -2229,10 +2342,11 @@ mm_status mm_batch_destroy(mm_batch* b) {
   if (!b) return MM_OK;
   if (!b->ctxs.empty()) hipSetDevice(b->ctxs[0]->dev);
   for (mm_batch* p : b->parts) mm_batch_destroy(p);
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  if (b->exec_rev) hipGraphExecDestroy(b->exec_rev);
-  if (b->graph_rev) hipGraphDestroy(b->graph_rev);
+  if (b->open) {
+    hipStreamSynchronize(b->stream);
+    for (mm_ctx* c : b->ctxs) c->open_in = nullptr;
+  }
+  drop_graphs(b);
   for (auto& g : b->groups) {
     if (g.xf) hipFree(g.xf);
     if (g.yz) hipFree(g.yz);

@@ -71,6 +71,9 @@ _SIGS = {
     "mm_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(_P)]),
     "mm_batch_run": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
     "mm_batch_step": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double]),
+    "mm_batch_begin": (ctypes.c_int, [_P, ctypes.c_double]),
+    "mm_batch_advance": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "mm_batch_end": (ctypes.c_int, [_P]),
     "mm_batch_destroy": (ctypes.c_int, [_P]),
     "mm_batch_profile": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P,
                                         ctypes.POINTER(ctypes.c_int32)]),
@@ -323,6 +326,18 @@ class Batch:
 
     def step(self, steps, tol=0.0):
         _check(self._lib.mm_batch_step(self.h, int(steps), float(tol)))
+
+    def begin(self, tol=0.0):
+        """Open an unbounded run (run-start derivative, graph capture); returns without waiting."""
+        _check(self._lib.mm_batch_begin(self.h, float(tol)))
+
+    def advance(self, steps):
+        """Enqueue exactly `steps` more attempted steps of the open run; returns without waiting."""
+        _check(self._lib.mm_batch_advance(self.h, int(steps)))
+
+    def end(self):
+        """Wait for the open run and read every instance's statistics back."""
+        _check(self._lib.mm_batch_end(self.h))
 
     def tune(self, streams=True):
         """Autotune the sub-batch count (unless streams=False) and the FFT
