@@ -181,6 +181,28 @@ mm_status mm_set_sampling(mm_ctx* ctx, double dt_sample, int64_t max_samples);
  * step), or an argument/HIP error. */
 mm_status mm_run(mm_ctx* ctx, double T, double tol);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mm_run with
+ * the same arguments, semantics and arithmetic (bit for bit the result of
+ * mm_run with its default FFT choices), whose per-run scratch -- stage
+ * derivatives and inputs, workgroup partial records, the demag field and
+ * spectra, the instance descriptor, work tables and done flags -- lives in a
+ * fixed static device array of MM_NOALLOC_SCRATCH_BYTES (every GPU the
+ * library runs on holds its own copy until the process ends) instead of
+ * memory the library allocates.  The call makes no hipMalloc, hipFree, pinned-memory or
+ * stream/graph creation call; it launches eagerly on the context's stream
+ * (mm_set_stream; the null stream if none) and waits for the run.  The
+ * context must be set up (mm_set_modes and mm_set_m, which allocate its
+ * state).  MM_ERR_ARG if the instance's scratch exceeds the array (about
+ * 108 B per cell and sublattice plus, with FFT demag, 12 B per cell and the
+ * x-transformed rows: e.g. a 64^3 grid with FFT demag fits, a 128x128x32 one
+ * does not).  The array is cleared where it must start at zero at every
+ * call.  Runs of one process on one GPU share its array and are serialised
+ * by a lock; runs on one GPU that overlap from two processes each have their
+ * own array. */
+#define MM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+mm_status mm_run_noalloc(mm_ctx* ctx, double T, double tol);
+
 /* Copy out m [S][3][nz][ny][nx] (FP32) and a [n][2] (FP64). */
 mm_status mm_get_m(const mm_ctx* ctx, float* out);
 mm_status mm_get_a(const mm_ctx* ctx, double* out);

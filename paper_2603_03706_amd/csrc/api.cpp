@@ -304,6 +304,20 @@ struct mm_batch {
   int total_wg = 0;
   int* d_flags = nullptr;
   int* h_flags = nullptr;
+  int h_flags_local[2] = {0, 0};   // host flags of a batch without pinned memory (no-allocation run)
+  bool arena = false;              // tables and run buffers carved from a fixed region: nothing to free
+  // per-run buffers that replace the context's own (no-allocation run)
+  struct RunBufs {
+    bool on = false;
+    float* k[7] = {};
+    float* st[2] = {};
+    double* partials = nullptr;
+    float* bd = nullptr;
+    float2* fx = nullptr;
+    float2* fy = nullptr;
+    char* lo = nullptr;            // byte range to clear before the run
+    size_t bytes = 0;
+  } rb;
   std::vector<unsigned> versions;
   struct Group {
     int nx, ny, nz, px, py, pz, kx;
@@ -509,13 +523,46 @@ mm_status upload_desc(mm_ctx* c) {
 // ------------------------------------------------------------- batches
 double algorithmic_bytes(const mm_batch* b, const std::string& name);
 
-// Work tables and LDS sizes of one FFT group for its current tile choice.
-mm_status build_group(mm_batch::Group& g) {
-  for (WorkItem** p : {&g.xf, &g.yz, &g.y, &g.zc})
-    if (*p) {
-      hipFree(*p);
-      *p = nullptr;
+// Device memory for a batch's tables and per-run buffers: hipMalloc
+// (MALLOC), carved in order from a fixed region (CARVE: the no-allocation
+// run), or only counted (COUNT: the bytes a carve would take).
+struct DevArena {
+  enum Mode { MALLOC, CARVE, COUNT } mode = MALLOC;
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  mm_status take(size_t bytes, void** out) {
+    if (mode == MALLOC) {
+      if (hipMalloc(out, bytes) != hipSuccess) return fail(MM_ERR_OOM, "device allocation failed");
+      return MM_OK;
     }
+    const size_t o = (off + 255) & ~(size_t)255;
+    off = o + bytes;
+    if (mode == COUNT) {
+      *out = (void*)(uintptr_t)256;          // never dereferenced
+      return MM_OK;
+    }
+    if (off > cap) return fail(MM_ERR_ARG, "instance does not fit the no-allocation scratch");
+    *out = base + o;
+    return MM_OK;
+  }
+  // take `bytes` and copy `src` there (host to device, synchronous)
+  mm_status upload(void** dst, const void* src, size_t bytes) {
+    if (mm_status s = take(bytes, dst)) return s;
+    if (mode != COUNT) MM_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return MM_OK;
+  }
+};
+
+// Work tables and LDS sizes of one FFT group for its current tile choice.
+mm_status build_group(mm_batch::Group& g, DevArena* arena = nullptr) {
+  DevArena heap;
+  if (!arena) arena = &heap;
+  if (arena->mode == DevArena::MALLOC)
+    for (WorkItem** p : {&g.xf, &g.yz, &g.y, &g.zc})
+      if (*p) {
+        hipFree(*p);
+        *p = nullptr;
+      }
   const int rows = 3 * g.ny * g.nz;
   const int tiles_x = g.Wx == 0 ? (rows + XR_ROWS - 1) / XR_ROWS : (rows + 2 * g.Wx - 1) / (2 * g.Wx);
   std::vector<WorkItem> xf, yz, yy, zc;
@@ -534,9 +581,7 @@ mm_status build_group(mm_batch::Group& g) {
   auto up = [&](std::vector<WorkItem>& v, WorkItem** dst, int* cnt) -> mm_status {
     *cnt = (int)v.size();
     if (v.empty()) return MM_OK;
-    MM_HIP(hipMalloc(dst, sizeof(WorkItem) * v.size()));
-    MM_HIP(hipMemcpy(*dst, v.data(), sizeof(WorkItem) * v.size(), hipMemcpyHostToDevice));
-    return MM_OK;
+    return arena->upload((void**)dst, v.data(), sizeof(WorkItem) * v.size());
   };
   if (mm_status s = up(xf, &g.xf, &g.n_xf)) return s;
   if (mm_status s = up(yz, &g.yz, &g.n_yz)) return s;
@@ -568,29 +613,74 @@ InstDesc batch_desc(const mm_batch* b, int i) {
   for (int j = 0; j < i; ++j) wg0 += b->ctxs[j]->desc.nwg;
   d.wg0 = wg0;
   d.xfused = b->xfused.empty() ? 0 : b->xfused[i];
+  if (b->rb.on) {
+    for (int j = 0; j < 7; ++j) d.k[j] = b->rb.k[j];
+    for (int j = 0; j < 2; ++j) d.st[j] = b->rb.st[j];
+    d.partials = b->rb.partials;
+    if (d.bd) d.bd = b->rb.bd;
+    if (d.fx) d.fx = b->rb.fx;
+    if (d.fy) d.fy = b->rb.fy;
+  }
   return d;
 }
 
-mm_status upload_batch_descs(mm_batch* b) {
+mm_status upload_batch_descs(mm_batch* b, bool count_only = false) {
   const int n = (int)b->ctxs.size();
   std::vector<InstDesc> descs(n);
   for (int i = 0; i < n; ++i) descs[i] = batch_desc(b, i);
-  MM_HIP(hipMemcpy(b->d_desc, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
+  if (!count_only) MM_HIP(hipMemcpy(b->d_desc, descs.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice));
   for (int i = 0; i < n; ++i) b->versions[i] = b->ctxs[i]->version;
   return MM_OK;
 }
 
-mm_status batch_build(mm_batch* b) {
+// Per-run buffers of the batch's single instance (stage derivatives, stage
+// inputs, workgroup partials and, with FFT demag, the demag field and the
+// spectra) carved from the arena instead of the context's workspace.
+mm_status carve_run_buffers(mm_batch* b, DevArena* ar) {
+  const mm_ctx* c = b->ctxs[0];
+  const Layout& L = c->L;
+  const size_t vec = sizeof(float) * 3 * L.S * (size_t)L.ncell;
+  mm_batch::RunBufs& r = b->rb;
+  const size_t start = ar->off;
+  for (int j = 0; j < 7; ++j)
+    if (mm_status s = ar->take(vec, (void**)&r.k[j])) return s;
+  for (int j = 0; j < 2; ++j)
+    if (mm_status s = ar->take(vec, (void**)&r.st[j])) return s;
+  if (mm_status s = ar->take(sizeof(double) * MMI_PSTRIDE * (size_t)L.nwg, (void**)&r.partials)) return s;
+  if (L.fft) {
+    const mm_params& p = c->p;
+    if (mm_status s = ar->take(sizeof(float) * 3 * (size_t)L.ncell, (void**)&r.bd)) return s;
+    if (mm_status s = ar->take(sizeof(float2) * (size_t)L.kx * 3 * p.nz * p.ny, (void**)&r.fx)) return s;
+    // the spectra of the y pass exist only on the split y-z path
+    if (!b->groups.empty() && b->groups[0].path == PATH_SPLIT)
+      if (mm_status s = ar->take(sizeof(float2) * (size_t)L.kx * 3 * p.nz * L.py, (void**)&r.fy)) return s;
+  }
+  r.on = true;
+  r.lo = (char*)r.k[0];
+  r.bytes = ar->off - ((start + 255) & ~(size_t)255);
+  return MM_OK;
+}
+
+// Tables, descriptors and streams of a batch.  With an arena (one instance
+// only), every device buffer, the per-run buffers included, is carved from it
+// and no stream or event is created: the caller sets b->stream.
+mm_status batch_build(mm_batch* b, DevArena* arena = nullptr) {
+  DevArena heap;
+  DevArena* ar = arena ? arena : &heap;
+  const bool counting = ar->mode == DevArena::COUNT;
   const int n = (int)b->ctxs.size();
   std::vector<int> wg;
   for (int i = 0; i < n; ++i)
     for (int w = 0; w < b->ctxs[i]->desc.nwg; ++w) wg.push_back(i);
   b->total_wg = (int)wg.size();
-  MM_HIP(hipMalloc(&b->d_desc, sizeof(InstDesc) * n));
-  MM_HIP(hipMalloc(&b->d_wg, sizeof(int) * wg.size()));
-  MM_HIP(hipMemcpy(b->d_wg, wg.data(), sizeof(int) * wg.size(), hipMemcpyHostToDevice));
-  MM_HIP(hipMalloc(&b->d_flags, sizeof(int) * 2 * n));
-  MM_HIP(hipHostMalloc((void**)&b->h_flags, sizeof(int) * 2 * n, hipHostMallocDefault));
+  b->arena = arena != nullptr;
+  if (mm_status s = ar->take(sizeof(InstDesc) * n, (void**)&b->d_desc)) return s;
+  if (mm_status s = ar->upload((void**)&b->d_wg, wg.data(), sizeof(int) * wg.size())) return s;
+  if (mm_status s = ar->take(sizeof(int) * 2 * n, (void**)&b->d_flags)) return s;
+  if (arena)
+    b->h_flags = b->h_flags_local;
+  else
+    MM_HIP(hipHostMalloc((void**)&b->h_flags, sizeof(int) * 2 * n, hipHostMallocDefault));
   b->versions.resize(n);
   // FFT groups by grid shape
   for (int i = 0; i < n; ++i) {
@@ -621,10 +711,13 @@ mm_status batch_build(mm_batch* b) {
     g.xfused = xfuse_fits(g.nx);
     for (int m : g.members)
       if (b->ctxs[m]->p.sublattices != 1) g.xfused = false;
-    if (mm_status s = build_group(g)) return s;
+    if (mm_status s = build_group(g, ar)) return s;
   }
   batch_xfused(b);
-  if (mm_status s = upload_batch_descs(b)) return s;
+  if (arena)
+    if (mm_status s = carve_run_buffers(b, ar)) return s;
+  if (mm_status s = upload_batch_descs(b, counting)) return s;
+  if (arena) return MM_OK;
   MM_HIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
   MM_HIP(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
   return MM_OK;
@@ -1519,6 +1612,58 @@ mm_status mm_run(mm_ctx* c, double T, double tol) {
   if (mm_status s = validate_tol(c->solo, tol)) return s;
   if (mm_status s = set_device(c)) return s;
   return batch_run(c->solo, T, tol);
+}
+
+mm_status mm_run_noalloc(mm_ctx* c, double T, double tol) {
+  if (c && c->open_in) return open_error();
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  if (!(T > 0) || !std::isfinite(T)) return fail(MM_ERR_ARG, "T must be finite and > 0");
+  if (mm_status s = check_ready(c)) return s;
+  if (!c->dev_ready) return fail(MM_ERR_STATE, "device state not set up");
+  if (c->method == MM_DP45 && !(tol > 0 && std::isfinite(tol)))
+    return fail(MM_ERR_ARG, "DP45 needs a finite tol > 0");
+  if (mm_status s = set_device(c)) return s;
+  void* base = nullptr;
+  size_t cap = 0;
+  MM_HIP(mmk_noalloc_scratch(c->dev, &base, &cap));
+  mm_ctx* one[1] = {c};
+  {
+    // bytes the tables and run buffers take, with the same choices as mm_run
+    mm_batch probe;
+    probe.ctxs.assign(one, one + 1);
+    probe.method = c->method;
+    DevArena cnt;
+    cnt.mode = DevArena::COUNT;
+    if (mm_status s = batch_build(&probe, &cnt)) return s;
+    if (cnt.off > cap)
+      return fail(MM_ERR_ARG, "the instance needs " + std::to_string(cnt.off) + " bytes of scratch; mm_run_noalloc has " +
+                                  std::to_string(cap));
+  }
+  std::lock_guard<std::mutex> lk(mmk_noalloc_lock(c->dev));
+  const auto t0 = std::chrono::steady_clock::now();
+  mm_batch b;
+  b.ctxs.assign(one, one + 1);
+  b.method = c->method;
+  b.stream = c->user_stream;
+  DevArena ar;
+  ar.mode = DevArena::CARVE;
+  ar.base = (char*)base;
+  ar.cap = cap;
+  if (mm_status s = batch_build(&b, &ar)) return s;
+  // the array keeps the previous call's contents: start from zeros, as the
+  // context's own buffers did
+  MM_HIP(mmk_launch_fill_zero(b.rb.lo, b.rb.bytes, b.stream));
+  if (mm_status s = begin_run(&b, T, tol)) return s;
+  for (;;) {
+    for (int k = 0; k < kStepsPerGraph; ++k)
+      if (mm_status s = enqueue_step(&b)) return s;
+    MM_HIP(mmk_launch_gather_done(1, b.d_desc, b.d_flags, b.stream));
+    MM_HIP(hipMemcpyAsync(b.h_flags, b.d_flags, sizeof(int) * 2, hipMemcpyDeviceToHost, b.stream));
+    MM_HIP(hipStreamSynchronize(b.stream));
+    if (b.h_flags[0] != 0) break;
+  }
+  const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return end_run(&b, wall);
 }
 
 mm_status mm_get_m(const mm_ctx* c, float* out) {

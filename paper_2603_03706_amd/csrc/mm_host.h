@@ -1,6 +1,7 @@
 // Host-side helpers of the library (setup and launch wrappers).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <mutex>
 #include <vector>
 
 #include "mm_internal.h"
@@ -41,3 +42,8 @@ hipError_t mmk_set_lds_limits();
 hipError_t mmk_launch_adj(int kind, int stage, int nblocks, int count, const InstDesc* d, const int* wg,
                           hipStream_t s, const float2* tw = nullptr, size_t lds = 0);
 hipError_t mmk_launch_gather_done(int count, const InstDesc* d, int* out, hipStream_t s);
+// the no-allocation run: this device's fixed scratch (address and size), the
+// per-device lock that serialises such runs, and a zero-fill kernel
+hipError_t mmk_noalloc_scratch(int dev, void** ptr, size_t* bytes);
+std::mutex& mmk_noalloc_lock(int dev);
+hipError_t mmk_launch_fill_zero(void* p, size_t bytes, hipStream_t s);

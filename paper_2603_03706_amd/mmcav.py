@@ -62,6 +62,7 @@ _SIGS = {
     "mm_set_stepper": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
     "mm_set_sampling": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int64]),
     "mm_run": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
+    "mm_run_noalloc": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double]),
     "mm_get_m": (ctypes.c_int, [_P, _P]),
     "mm_get_a": (ctypes.c_int, [_P, _P]),
     "mm_get_trace": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(ctypes.c_int64)]),
@@ -232,6 +233,10 @@ class Context:
 
     def run(self, T, tol=0.0):
         _check(self._lib.mm_run(self.h, float(T), float(tol)))
+
+    def run_noalloc(self, T, tol=0.0):
+        """mm_run whose per-run scratch is the library's fixed device array (no device allocation)."""
+        _check(self._lib.mm_run_noalloc(self.h, float(T), float(tol)))
 
     def run_record(self, T, checkpoint_every=256):
         _check(self._lib.mm_run_record(self.h, float(T), int(checkpoint_every)))
