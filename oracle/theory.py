@@ -88,3 +88,33 @@ def dp4_stability(z):
 def dp_error_polynomial(z):
     """dp5_stability - dp4_stability written out, free of cancellation."""
     return -97 / 120000 * z ** 5 + 39 / 120000 * z ** 6 - z ** 7 / 24000
+
+
+def _prism_dz(a, b, c):
+    """Magnetometric demagnetizing factor along z of a rectangular prism
+    of half-sides a, b, c (along x, y, z): A. Aharoni, J. Appl. Phys. 83,
+    3432 (1998), Eq. (1)."""
+    r = np.sqrt(a * a + b * b + c * c)
+    ab, bc, ac = np.sqrt(a * a + b * b), np.sqrt(b * b + c * c), np.sqrt(a * a + c * c)
+    t = ((b * b - c * c) / (2 * b * c) * np.log((r - a) / (r + a))
+         + (a * a - c * c) / (2 * a * c) * np.log((r - b) / (r + b))
+         + b / (2 * c) * np.log((ab + a) / (ab - a))
+         + a / (2 * c) * np.log((ab + b) / (ab - b))
+         + c / (2 * a) * np.log((bc - b) / (bc + b))
+         + c / (2 * b) * np.log((ac - a) / (ac + a))
+         + 2 * np.arctan(a * b / (c * r))
+         + (a ** 3 + b ** 3 - 2 * c ** 3) / (3 * a * b * c)
+         + (a * a + b * b - 2 * c * c) / (3 * a * b * c) * r
+         + c / (a * b) * (ac + bc)
+         - (ab ** 3 + bc ** 3 + ac ** 3) / (3 * a * b * c))
+    return t / np.pi
+
+
+def prism_demag_factors(lx, ly, lz):
+    """(N_xx, N_yy, N_zz) of a uniformly magnetised rectangular block of
+    edges lx, ly, lz: the volume average of its demagnetizing tensor, which
+    is also the average of the cell-pair (Newell) tensor over all cell pairs
+    of the block when it is cut into cells.  Aharoni's Eq. (1) with the
+    axes permuted."""
+    a, b, c = 0.5 * lx, 0.5 * ly, 0.5 * lz
+    return _prism_dz(b, c, a), _prism_dz(c, a, b), _prism_dz(a, b, c)

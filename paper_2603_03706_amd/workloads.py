@@ -172,14 +172,31 @@ def sweep_sphere(k, count=64, n=32):
                     method="dp45", dt0=1e-13, tol=1e-6, T=100e-9, dt_sample=10e-12)
 
 
+# Shape term N_zz - N_xx of the volume-averaged demagnetizing tensor of the
+# film blocks (cubic cells), written by tests/golden/film_shape_terms.py
+# from the oracle and checked against it by a test.
+FILM_SHAPE_TERMS = {
+    (128, 128, 32): 0.47594880860161287,
+    (16, 12, 4): 0.45608201895187317,
+    (16, 16, 4): 0.47594880860161287,
+    (8, 6, 3): 0.3260951818600196,
+    (6, 5, 3): 0.23458240488129364,
+    (6, 5, 2): 0.37251086212134954,
+    (5, 4, 2): 0.308786125759433,
+}
+
+
 def multimode_film(nx=128, ny=128, nz=32):
     """YIG film at 5 nm with FFT demag and four standing-wave modes at 4.8,
-    4.9, 5.0 and 5.1 GHz; g_n/2pi drawn from U(10, 60) MHz; a_1(0) = 1."""
+    4.9, 5.0 and 5.1 GHz; g_n/2pi drawn from U(10, 60) MHz; a_1(0) = 1.
+    Bias along z: 2 pi 5 GHz / gamma + mu0 Ms (N_zz - N_xx) with the block's
+    own volume-averaged tensor, so that its uniform mode sits at 5 GHz."""
     grid = (nx, ny, nz)
+    if grid not in FILM_SHAPE_TERMS:
+        raise ValueError(f"no stored shape term for a {grid} film")
     g = TWO_PI * 1e6 * np.random.default_rng(3).uniform(10.0, 60.0, 4)
     u = np.stack([standing_wave(grid, n, 1) for n in (1, 2, 3, 4)]).astype(np.float32)
-    # bias: 5 GHz plus the thin-film shape field mu0 Ms (N_zz - N_xx = 1)
-    B0 = TWO_PI * 5.0e9 / GAMMA + MU0 * YIG["Ms"]
+    B0 = TWO_PI * 5.0e9 / GAMMA + MU0 * YIG["Ms"] * FILM_SHAPE_TERMS[grid]
     a0 = np.array([1.0, 0.0, 0.0, 0.0], complex)
     return Instance(grid=grid, cell=(5e-9,) * 3, **YIG, B0=(0.0, 0.0, B0), demag=DEMAG_FFT,
                     omega=TWO_PI * np.array([4.8e9, 4.9e9, 5.0e9, 5.1e9]),

@@ -436,6 +436,34 @@ def test_p12_uniform_film_interior():
     assert abs(-H[2, 0, 32, 32] - 1.0) < 0.03
 
 
+@pytest.mark.parametrize("grid", [(4, 6, 2), (5, 3, 7), (8, 8, 2), (3, 3, 3)])
+def test_p12_mean_tensor_is_prism_factor(grid):
+    """The volume average of the cell-pair tensor over all cell pairs of a
+    rectangular block equals the block's magnetometric demagnetizing factors
+    (Aharoni's closed form), whose trace is 1; a cube gives 1/3."""
+    nx, ny, nz = grid
+    cell = (5e-9, 4e-9, 6e-9) if grid == (5, 3, 7) else (5e-9,) * 3
+    N = newell.mean_tensor(np.ones((nz, ny, nx), bool), cell)
+    want = theory.prism_demag_factors(nx * cell[0], ny * cell[1], nz * cell[2])
+    assert np.abs(np.diag(N) - np.array(want)).max() < 1e-10
+    assert abs(sum(want) - 1.0) < 1e-12
+    assert np.abs(N - np.diag(np.diag(N))).max() < 1e-12
+    if nx == ny == nz:
+        assert np.abs(np.array(want) - 1 / 3).max() < 1e-12
+
+
+def test_film_bias_shape_terms():
+    """The film workload's stored shape terms are the oracle's N_zz - N_xx
+    of each block, so its uniform mode sits at 5 GHz (reading of the film
+    bias: the block's own averaged tensor, not the thin-film limit 1)."""
+    for (nx, ny, nz), v in W.FILM_SHAPE_TERMS.items():
+        n_xx, _, n_zz = theory.prism_demag_factors(float(nx), float(ny), float(nz))
+        assert abs(v - (n_zz - n_xx)) < 1e-14
+    film = W.multimode_film()
+    w_uniform = GAMMA * (film.B0[2] - 4e-7 * math.pi * film.Ms * W.FILM_SHAPE_TERMS[(128, 128, 32)])
+    assert abs(w_uniform / TWO_PI - 5e9) < 1.0
+
+
 # ----------------------------------------------------------------- P13 overlap
 def test_p13_mode_overlap_selection_rule():
     vals = GOLD["overlap_nx"]["values"]
