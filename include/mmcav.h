@@ -140,6 +140,18 @@ mm_status mm_set_modes(mm_ctx* ctx, int32_t n, const double* omega, const double
 mm_status mm_set_cavity_model(mm_ctx* ctx, int32_t n, const double* g_back, const double* kerr,
                               const double* coupling);
 
+/* Degenerate parametric pump of each mode (Sec. V names parametric drives
+ * among the cavity-model variants without giving an equation): da_n/dt
+ * gains -i lam_n e^{-2 i wp_n t} conj(a_n), a pump at twice wp_n with
+ * complex strength lam_n [rad/s], evaluated at the time of every stage
+ * (t + c_s h).  In the frame rotating at wp_n = w_n one quadrature decays at
+ * kappa_n + |lam_n| and the other at kappa_n - |lam_n| (parametric gain
+ * above the threshold |lam_n| = kappa_n).  lambda: host [n][2] (re, im);
+ * omega_p: host [n] wp_n [rad/s]; finite values; n must equal the mode
+ * count.  n = 0 or lambda = NULL switches the pump off; mm_set_modes also
+ * does.  The adjoint carries the pump's Jacobian. */
+mm_status mm_set_parametric(mm_ctx* ctx, int32_t n, const double* lambda, const double* omega_p);
+
 /* External cavity drive eta_n(t) of Eq. (1) / Eq. (12), as the Gaussian
  * pulse of Sec. IV A: eta_n(t) = A_n exp(-((t - t0_n) / sigma_n)^2 / 2),
  * added to da_n/dt at the time of every stage (t + c_s h).  amp: host [n][2]

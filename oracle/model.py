@@ -20,6 +20,11 @@ Equations (SI units, fields in tesla, rates in rad/s):
   * direct photon-photon coupling (the H_13 entry of the Sec. II F
     coupling matrix, Eq. (14)): da_n/dt gains -i sum_m J_nm a_m with J real
     symmetric and zero on the diagonal
+  * a degenerate parametric pump (Sec. V names parametric drives without an
+    equation): da_n/dt gains -i lam_n e^{-2 i wp_n t} conj(a_n), a pump at
+    twice wp_n with complex strength lam_n [rad/s]; in the frame rotating
+    at wp_n at resonance one quadrature decays at kappa + |lam| and the
+    other at kappa - |lam| (gain above the threshold |lam| = kappa)
   * co-rotating average, Eq. (2) weighted by the mode profile as in Eq. (18):
         m^-_n = 1/N_geo sum_i G_i u_n(r_i) (1/S) sum_s c_s (m_sx - i m_sy)
   * RF feedback along x, Eq. (3) and Eq. (13), h0_n = 2 g_n / gamma (Eq. (5)):
@@ -72,6 +77,9 @@ class Problem:
     drive_amp: Optional[Sequence[complex]] = None   # (N,) complex amplitude [1/s]
     drive_t0: Optional[Sequence[float]] = None      # (N,) pulse centre [s]
     drive_sigma: Optional[Sequence[float]] = None   # (N,) pulse width [s], > 0
+    # degenerate parametric pump -i lam_n e^{-2 i wp_n t} conj(a_n); None = off
+    param_lambda: Optional[Sequence[complex]] = None  # (N,) complex strength [rad/s]
+    param_wp: Optional[Sequence[float]] = None        # (N,) half the pump frequency [rad/s]
 
     @property
     def n_modes(self):
@@ -124,6 +132,10 @@ class Model:
             self.u = torch.ones((N,) + self.shape, dtype=torch.float64)
         else:
             self.u = torch.tensor(np.asarray(p.u, float).reshape((N,) + self.shape))
+        self.param_on = p.param_lambda is not None
+        if self.param_on:
+            self.param_lambda = torch.tensor(np.asarray(p.param_lambda, complex))
+            self.param_wp = torch.tensor(np.asarray(p.param_wp, float))
         self.drive_on = p.drive_amp is not None
         if self.drive_on:
             self.drive_amp = torch.tensor(np.asarray(p.drive_amp, complex))
@@ -217,13 +229,16 @@ class Model:
         return self.drive_amp * torch.exp(-0.5 * x * x)
 
     def cavity_rhs(self, a, mminus, t=0.0):
-        """Eq. (12) with the dissipative phase of Eq. (19); the Kerr term and
-        the drive enter only when set, the drive at the time t of the stage."""
+        """Eq. (12) with the dissipative phase of Eq. (19); the Kerr term, the
+        mode coupling, the parametric pump and the drive enter only when set,
+        the pump and the drive at the time t of the stage."""
         f = (-1j * self.omega - self.kappa) * a + 1j * self.g * torch.exp(-1j * self.phi) * mminus
         if self.kerr is not None:
             f = f - 1j * self.kerr * (a.real * a.real + a.imag * a.imag) * a
         if self.J is not None:
             f = f - 1j * (self.J.to(a.dtype) @ a)
+        if self.param_on:
+            f = f - 1j * self.param_lambda * torch.exp(-2j * self.param_wp * t) * torch.conj(a)
         if self.drive_on:
             f = f + self.drive(t)
         return f

@@ -254,6 +254,8 @@ struct mm_ctx {
   bool jcpl_on = false;           // direct mode coupling set
   std::vector<double> g_back, kerr, jcpl;
   bool drive_on = false;          // Gaussian cavity drive per mode
+  bool param_on = false;          // degenerate parametric pump per mode
+  std::vector<double> par_re, par_im, par_wp;
   std::vector<double> drive_re, drive_im, drive_t0, drive_sigma;
   // stepper
   int method = MM_RK4;
@@ -473,6 +475,13 @@ mm_status upload_desc(mm_ctx* c) {
   if (c->jcpl_on)
     for (int n = 0; n < c->N; ++n)
       for (int m = 0; m < c->N; ++m) d.jcpl[n][m] = c->jcpl[(size_t)n * c->N + m];
+  d.param_on = c->param_on ? 1 : 0;
+  if (c->param_on)
+    for (int n = 0; n < c->N; ++n) {
+      d.par_re[n] = c->par_re[n];
+      d.par_im[n] = c->par_im[n];
+      d.par_wp[n] = c->par_wp[n];
+    }
   d.drive_on = c->drive_on ? 1 : 0;
   if (c->drive_on)
     for (int n = 0; n < c->N; ++n) {
@@ -1402,6 +1411,7 @@ mm_status mm_set_modes(mm_ctx* c, int32_t n, const double* omega, const double* 
   if (mm_status s = ensure_device(c)) return s;
   c->N = n;
   c->drive_on = false;
+  c->param_on = false;
   c->nonrecip = false;
   c->kerr_on = false;
   c->jcpl_on = false;
@@ -1498,6 +1508,30 @@ mm_status mm_set_drive(mm_ctx* c, int32_t n, const double* amp, const double* t0
   c->drive_t0.assign(t0, t0 + n);
   c->drive_sigma.assign(sigma, sigma + n);
   c->drive_on = true;
+  return upload_desc(c);
+}
+
+mm_status mm_set_parametric(mm_ctx* c, int32_t n, const double* lambda, const double* omega_p) {
+  if (c && c->open_in) return open_error();
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  if (!c->modes_set) return fail(MM_ERR_STATE, "modes not set (mm_set_modes)");
+  if (n == 0 || !lambda) {
+    c->param_on = false;
+    return upload_desc(c);
+  }
+  if (n != c->N) return fail(MM_ERR_ARG, "pump count must equal the mode count");
+  if (!omega_p) return fail(MM_ERR_ARG, "omega_p is required with a pump strength");
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(lambda[2 * i]) || !std::isfinite(lambda[2 * i + 1]) || !std::isfinite(omega_p[i]))
+      return fail(MM_ERR_ARG, "pump parameters must be finite");
+  c->par_re.assign(n, 0.0);
+  c->par_im.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    c->par_re[i] = lambda[2 * i];
+    c->par_im[i] = lambda[2 * i + 1];
+  }
+  c->par_wp.assign(omega_p, omega_p + n);
+  c->param_on = true;
   return upload_desc(c);
 }
 
@@ -1955,6 +1989,7 @@ static mm_status adjoint_impl(mm_ctx* c, const double* dL_da, const float* dL_dm
     h.adj_base = (long long)k * K;
     h.done = 0;
     h.adj_h = c->rec_h;
+    h.adj_t0 = c->ck_ctl[k].t;
     if (mm_status s = ctl_push(c, h)) return s;
     for (long long q = 0; q < steps; ++q) MM_HIP(hipGraphLaunch(b->exec_rev, b->stream));
     MM_HIP(hipStreamSynchronize(b->stream));

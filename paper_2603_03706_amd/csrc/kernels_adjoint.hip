@@ -407,6 +407,17 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__
         mur += lr * x - li * (q + 2.0 * K * ar * ar);
         mui += lr * (q + 2.0 * K * ai * ai) - li * x;
       }
+      if (D.param_on) {
+        // transpose of the Jacobian of -i Lam conj(a), Lam = lam e^{-2 i wp t}
+        // at the stage time: [[Li, -Lr], [-Lr, -Li]] (symmetric)
+        const double ts = C->adj_t0 + (double)C->rec_index * h + (ST == 1 ? 0.0 : ST == 4 ? h : 0.5 * h);
+        double sn, cs;
+        sincos(2.0 * D.par_wp[n] * ts, &sn, &cs);
+        const double Lr = D.par_re[n] * cs + D.par_im[n] * sn;
+        const double Li = D.par_im[n] * cs - D.par_re[n] * sn;
+        mur += Li * lr - Lr * li;
+        mui -= Lr * lr + Li * li;
+      }
       if (D.jcpl_on)
         for (int q = 0; q < N; ++q) {
           // -i sum_q J_qn a_n in the equation of mode q, J symmetric

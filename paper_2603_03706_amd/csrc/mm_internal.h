@@ -44,6 +44,7 @@ struct InstCtl {
   int rec_index;                      // recorded step within the segment (-1: not recording)
   int pad1;
   double adj_h;                       // step of the recorded run
+  double adj_t0;                      // time at the start of the segment being reversed
   long long adj_base;                 // recorded-run index of the first step of the segment being reversed
   double la[MMI_MAX_MODES][2];        // adjoint of a at the step start (accumulator)
   double lza[MMI_MAX_MODES][2];       // adjoint of a after the step
@@ -82,6 +83,9 @@ struct InstDesc {
   int drive_on, pad_drive;
   double eta_re[MMI_MAX_MODES], eta_im[MMI_MAX_MODES];
   double eta_t0[MMI_MAX_MODES], eta_sigma[MMI_MAX_MODES];
+  // degenerate parametric pump -i lam_n e^{-2 i wp_n t} conj(a_n)
+  int param_on, pad_param;
+  double par_re[MMI_MAX_MODES], par_im[MMI_MAX_MODES], par_wp[MMI_MAX_MODES];
   // device buffers
   float* y[2];                        // state [S][3][cells]
   float* k[7];                        // stage derivatives (RK4 uses k[0] as the running sum)

@@ -13,7 +13,8 @@ namespace mmk {
 // amplitudes of all modes in A: (-i w - kappa) a + i g e^{-i Phi} m^-
 // (Eq. (12) with the phase of Eq. (19)), plus, when set, the self-Kerr term
 // -i K |a|^2 a, the direct mode coupling -i sum_m J_nm a_m (the H_13 entry of
-// Eq. (14)) and the Gaussian drive eta_n(t) of Eq. (1).
+// Eq. (14)), the degenerate parametric pump -i lam e^{-2 i wp t} conj(a) and
+// the Gaussian drive eta_n(t) of Eq. (1).
 __device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double t, const double (*A)[2],
                                         double mr, double mi, double& fr, double& fi) {
   const double ar = A[n][0], ai = A[n][1];
@@ -33,6 +34,15 @@ __device__ __forceinline__ void cav_rhs(const InstDesc& D, int n, double t, cons
     }
     fr += ji;
     fi -= jr;
+  }
+  if (D.param_on) {
+    double sn, cs;
+    sincos(2.0 * D.par_wp[n] * t, &sn, &cs);
+    // Lam = lam e^{-2 i wp t};  -i Lam conj(a) = (Li ar - Lr ai) - i (Lr ar + Li ai)
+    const double lr = D.par_re[n] * cs + D.par_im[n] * sn;
+    const double li = D.par_im[n] * cs - D.par_re[n] * sn;
+    fr += li * ar - lr * ai;
+    fi -= lr * ar + li * ai;
   }
   if (D.drive_on) {
     const double x = (t - D.eta_t0[n]) / D.eta_sigma[n];

@@ -57,6 +57,7 @@ _SIGS = {
     "mm_set_m": (ctypes.c_int, [_P, _P]),
     "mm_set_a": (ctypes.c_int, [_P, _P]),
     "mm_set_drive": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
+    "mm_set_parametric": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     "mm_set_cavity_model": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     "mm_adjoint_trace": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "mm_set_stepper": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
@@ -178,6 +179,8 @@ class Context:
             c.set_cavity_model(inst.g_back, inst.kerr, inst.photon_coupling)
         if getattr(inst, "drive_amp", None) is not None:
             c.set_drive(inst.drive_amp, inst.drive_t0, inst.drive_sigma)
+        if getattr(inst, "param_lambda", None) is not None:
+            c.set_parametric(inst.param_lambda, inst.param_wp)
         c.set_m(inst.m0)
         c.set_a(inst.a0)
         c.set_stepper({"rk4": RK4, "dp45": DP45, "split": RK4_SPLIT}[inst.method], inst.dt0)
@@ -203,6 +206,17 @@ class Context:
         jc = None if coupling is None else np.ascontiguousarray(coupling, np.float64)
         n = 0 if gb is None and kr is None and jc is None else self.N
         _check(self._lib.mm_set_cavity_model(self.h, n, _ptr(gb), _ptr(kr), _ptr(jc)))
+
+    def set_parametric(self, lam=None, omega_p=None):
+        """Degenerate parametric pump -i lam_n e^{-2 i wp_n t} conj(a_n) per
+        mode (complex strengths [rad/s], wp [rad/s]); lam=None switches it off."""
+        if lam is None:
+            _check(self._lib.mm_set_parametric(self.h, 0, None, None))
+            return
+        la = np.asarray(lam, np.complex128)
+        buf = np.ascontiguousarray(np.stack([la.real, la.imag], axis=-1).reshape(-1))
+        wp = np.ascontiguousarray(omega_p, np.float64)
+        _check(self._lib.mm_set_parametric(self.h, len(la), _ptr(buf), _ptr(wp)))
 
     def set_drive(self, amp=None, t0=None, sigma=None):
         """Gaussian cavity drive A_n exp(-((t - t0_n)/sigma_n)^2 / 2) per mode

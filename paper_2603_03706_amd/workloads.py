@@ -54,6 +54,8 @@ class Instance:
     drive_amp: Optional[np.ndarray] = None     # complex128 (N,) Gaussian drive amplitude [1/s]
     drive_t0: Optional[np.ndarray] = None      # (N,) pulse centre [s]
     drive_sigma: Optional[np.ndarray] = None   # (N,) pulse width [s]
+    param_lambda: Optional[np.ndarray] = None  # complex128 (N,) parametric pump strength [rad/s]
+    param_wp: Optional[np.ndarray] = None      # (N,) half the pump frequency [rad/s]
     m0: Optional[np.ndarray] = None            # float32 (S, 3, nz, ny, nx)
     a0: Optional[np.ndarray] = None            # complex128 (N,)
     method: str = "rk4"
@@ -83,7 +85,9 @@ class Instance:
                     photon_coupling=None if self.photon_coupling is None else np.asarray(self.photon_coupling, float),
                     drive_amp=None if self.drive_amp is None else list(self.drive_amp),
                     drive_t0=None if self.drive_t0 is None else list(self.drive_t0),
-                    drive_sigma=None if self.drive_sigma is None else list(self.drive_sigma))
+                    drive_sigma=None if self.drive_sigma is None else list(self.drive_sigma),
+                    param_lambda=None if self.param_lambda is None else list(self.param_lambda),
+                    param_wp=None if self.param_wp is None else list(self.param_wp))
 
 
 def tilted(grid, theta_deg, azimuth, sublattices=1):

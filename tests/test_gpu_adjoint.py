@@ -223,3 +223,16 @@ def test_adjoint_kerr_and_mode_coupling():
                    drive_amp=np.array([2e8 + 0j, 0j]), drive_t0=np.array([0.1e-9] * 2),
                    drive_sigma=np.array([20e-12] * 2), a0=np.array([0.3 + 0j, 0.1j]))
     _check(inst, steps=150, every=64, mode=0)
+
+
+def test_adjoint_parametric_pump():
+    """A degenerate parametric pump on the cavity (|lam|/2pi = 30 MHz against
+    kappa/2pi = 50 MHz, pump at twice the cavity frequency) coupled to the Sim 1 film, 150 RK4
+    steps in segments of 64, 64 and 22 (each segment reverses the pump at its
+    own stage times): the cavity VJP with the pump's Jacobian against the
+    oracle's autograd gradient."""
+    base = W.paper_sim1()
+    wc = base.omega[0]
+    inst = variant(base, kappa=np.array([TWO_PI * 50e6]), param_lambda=np.array([TWO_PI * 30e6 * np.exp(0.9j)]),
+                   param_wp=np.array([wc]), a0=np.array([0.2 + 0.05j]))
+    _check(inst, steps=150, every=64, mode=0)

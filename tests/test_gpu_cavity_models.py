@@ -184,3 +184,57 @@ def test_batch_mixing_variants_equals_plain_bitwise():
         t2 = c.get_trace(100)
         assert all(np.array_equal(x, y) for x, y in zip(t2, tr))
     b.close()
+
+
+# ------------------------------------------- degenerate parametric pump
+@pytest.mark.parametrize("method", ["rk4", "dp45"])
+def test_parametric_uncoupled_closed_form(method):
+    """g = 0, pump -i lam e^{-2 i wp t} conj(a) with |lam| = 1.5 kappa at
+    20 MHz detuning: the FP64 cavity on the device follows the oracle to
+    rounding and the rotating-frame matrix exponential to the method error."""
+    from tests.test_oracle_pins import _parametric_rotating
+    wp, kp = TWO_PI * 5e9, TWO_PI * 20e6
+    lam = 1.5 * kp * np.exp(0.4j)
+    w = wp + TWO_PI * 20e6
+    a0 = 0.3 + 0.1j
+    inst = variant(W.paper_sim1(g=0.0), drive_amp=None, omega=np.array([w]), kappa=np.array([kp]),
+                   param_lambda=np.array([lam]), param_wp=np.array([wp]), a0=np.array([a0]),
+                   method=method, dt0=0.5e-12)
+    st, ctx = _pair(inst, 2e-9, tol=1e-12)
+    t_o, a_o, _ = st.trace_arrays()
+    t, a, _ = ctx.get_trace(2000)
+    assert len(t) == len(t_o) == 201
+    assert rel_a_err(a, a_o.numpy()) <= 1e-12
+    want = np.exp(-1j * wp * t) * _parametric_rotating(lam, kp, w - wp, t, a0)
+    assert np.abs(a[:, 0] - want).max() / np.abs(want).max() < (2e-7 if method == "rk4" else 2e-8)
+
+
+def test_parametric_coupled_parity():
+    """The pumped cavity (|lam| = 0.8 kappa, pump at twice the cavity
+    frequency) coupled to the 8x8x1 film of Sec. IV, RK4 at 1 ps for 1 ns,
+    and the same with the operator-split scheme: against the oracle."""
+    wc, kp = W.paper_sim1().omega[0], W.paper_sim1().kappa[0]
+    for method in ("rk4", "split"):
+        inst = variant(W.paper_sim1(), drive_amp=None, param_lambda=np.array([0.8 * kp * np.exp(-0.6j)]),
+                       param_wp=np.array([wc]), a0=np.array([0.05 + 0.02j]), method=method)
+        st, ctx = _pair(inst, 1e-9)
+        _, a_o, mm_o = st.trace_arrays()
+        _, a, mm = ctx.get_trace(2000)
+        assert rel_a_err(a, a_o.numpy()) <= 1e-5
+        assert rel_a_err(mm, mm_o.numpy()) <= 1e-5
+        assert m_err(ctx.get_m(), st) <= 1e-5
+
+
+def test_parametric_argument_checks():
+    from paper_2603_03706_amd import mmcav
+    ctx = gpu_for(W.paper_sim1(T=0.1e-9))
+    with pytest.raises(mmcav.MMError):
+        ctx.set_parametric([1e6, 2e6], [1e10, 1e10])          # count != modes
+    with pytest.raises(mmcav.MMError):
+        ctx.set_parametric([complex(np.nan)], [1e10])
+    ctx.set_parametric([1e6], [1e10])
+    ctx.set_parametric(None)                                  # off again: the plain run
+    ref = gpu_for(W.paper_sim1(T=0.1e-9))
+    ctx.run(0.1e-9)
+    ref.run(0.1e-9)
+    assert np.array_equal(ctx.get_a(), ref.get_a()) and np.array_equal(ctx.get_m(), ref.get_m())

@@ -89,3 +89,28 @@ def test_oracle_gradient_with_geometry_mask():
         vals.append(run_loss(prob, m0, np.array([1.0, 0.3j, 0.0, 0.0]), dt, T, loss_mode2, leaves=lv))
     fd = (vals[0] - vals[1]) / 2e-4
     assert abs(fd - np.sum(g["u"] * du)) <= 1e-6 * abs(fd)
+
+
+def test_oracle_gradient_with_parametric_pump():
+    """With the pump -i lam e^{-2 i wp t} conj(a) on two modes (whose
+    Jacobian mixes a and conj(a)), the autograd gradient with respect to the
+    initial amplitudes and the couplings matches central differences."""
+    prob, m0, a0 = small_film()
+    kw = dict(prob.__dict__)
+    kw["param_lambda"] = [0, 2e8 * np.exp(0.5j), 0, 1e8 * np.exp(-1.2j)]
+    kw["param_wp"] = [0.0, prob.omega[1], 0.0, prob.omega[3] + 1e8]
+    prob = Problem(**kw)
+    dt, T = 0.5e-12, 10e-12
+    L, g, status = run_with_grad(prob, m0, a0, dt, T, loss_mode2)
+    assert status == 0 and L > 0
+    rng = np.random.default_rng(6)
+    da = rng.normal(size=4) + 1j * rng.normal(size=4)
+    dg = rng.normal(size=4) * np.asarray(prob.g)
+    ad = float(np.real(np.vdot(g["a0"], da))) + float(np.dot(g["g"], dg))
+    vals = {}
+    for sgn in (+1, -1):
+        h = 1e-4 * sgn
+        lv = {"g": torch.tensor(np.asarray(prob.g, float) + h * dg)}
+        vals[sgn] = run_loss(prob, m0, a0 + h * da, dt, T, loss_mode2, leaves=lv)
+    fd = (vals[1] - vals[-1]) / 2e-4
+    assert abs(fd - ad) <= 1e-6 * abs(fd), (fd, ad)

@@ -748,6 +748,71 @@ def test_p16_kerr_closed_form(method):
     assert np.abs(a.numpy()[:, 0] - want).max() / abs(a0) < (2e-7 if method == "rk4" else 2e-8)
 
 
+def _parametric_rotating(lam, kp, delta, t, b0):
+    """Rotating-frame amplitude b(t) = a(t) e^{i wp t} of the uncoupled
+    pumped cavity db/dt = (-i delta - kappa) b - i lam conj(b): with
+    b = e^{i arg(lam)/2} (x + i y) the real pair (x, y) obeys
+    d/dt (x, y) = [[-kappa, delta - |lam|], [-delta - |lam|, -kappa]] (x, y),
+    solved by the matrix exponential."""
+    from scipy.linalg import expm
+    ph = np.exp(0.5j * np.angle(lam))
+    c0 = b0 / ph
+    A = np.array([[-kp, delta - abs(lam)], [-delta - abs(lam), -kp]])
+    out = []
+    for tk in t:
+        x, y = expm(A * tk) @ np.array([c0.real, c0.imag])
+        out.append(ph * (x + 1j * y))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("method", ["rk4", "dp45"])
+@pytest.mark.parametrize("lam_MHz,phase,detune_MHz", [(15.0, 0.7, 0.0), (30.0, 0.0, 0.0), (25.0, -1.1, 40.0)])
+def test_p18_parametric_pump(method, lam_MHz, phase, detune_MHz):
+    """Degenerate parametric pump (Sec. V; reading: -i lam e^{-2 i wp t}
+    conj(a)), g = 0: the lab-frame amplitude equals e^{-i wp t} times the
+    rotating-frame solution.  At resonance one quadrature decays at
+    kappa + |lam| and the other at kappa - |lam| (below threshold for
+    |lam| < kappa, growth above it); detuned, the rates are
+    -kappa +- sqrt(|lam|^2 - delta^2)."""
+    wp, kp = TWO_PI * 5e9, TWO_PI * 20e6
+    lam = TWO_PI * lam_MHz * 1e6 * np.exp(1j * phase)
+    w = wp + TWO_PI * detune_MHz * 1e6
+    a0 = 0.3 + 0.1j
+    M = macrospin(omega=[w], kappa=[kp], g=[0.0], param_lambda=[lam], param_wp=[wp])
+    st = Stepper(M, state(0, 0), np.array([a0]), method=method, dt0=0.5e-12)
+    st.set_sampling(10e-12, 1000)
+    with torch.no_grad():
+        assert st.run(2e-9, 1e-12) == OK
+    t, a, _ = st.trace_arrays()
+    t = t.numpy()
+    want = np.exp(-1j * wp * t) * _parametric_rotating(lam, kp, w - wp, t, a0)
+    assert np.abs(a.numpy()[:, 0] - want).max() / np.abs(want).max() < (2e-7 if method == "rk4" else 2e-8)
+    # the rotating-frame rates themselves
+    A = np.array([[-kp, (w - wp) - abs(lam)], [-(w - wp) - abs(lam), -kp]])
+    ev = np.sort_complex(np.linalg.eigvals(A))
+    root = np.sqrt(complex(abs(lam) ** 2 - (w - wp) ** 2))
+    assert np.abs(ev - np.sort_complex(np.array([-kp - root, -kp + root]))).max() < 1e-6 * kp
+
+
+def test_p18_parametric_sign_and_conjugation():
+    """Plausible slips in the pump term change the dynamics: without the
+    conjugate it is a frequency shift (no quadrature gain), with e^{+2 i wp t}
+    it is off resonance by 4 wp (no effect); the pinned form amplifies one
+    quadrature above threshold."""
+    wp, kp, lam = TWO_PI * 5e9, TWO_PI * 5e6, TWO_PI * 60e6
+    M = macrospin(omega=[wp], kappa=[kp], g=[0.0], param_lambda=[lam], param_wp=[wp])
+    st = Stepper(M, state(0, 0), np.array([0.1 + 0j]), method="rk4", dt0=2e-12)
+    with torch.no_grad():
+        st.run(10e-9)
+    grown = abs(complex(st.a[0]))
+    M0 = macrospin(omega=[wp], kappa=[kp], g=[0.0])
+    st0 = Stepper(M0, state(0, 0), np.array([0.1 + 0j]), method="rk4", dt0=2e-12)
+    with torch.no_grad():
+        st0.run(10e-9)
+    # quadrature x - y grows at lam - kappa = 2 pi 55 MHz: e^{3.5} ~ 30x
+    assert grown > 10 * 0.1 and abs(complex(st0.a[0])) < 0.1
+
+
 def test_p16_nonreciprocal_splitting():
     """g_f != g_b at resonance: (w - w_c)(w - w_m) = g_f g_b, so the branches
     sit at w_c +- sqrt(g_f g_b) (the reciprocal splitting 2g with g^2 -> g_f g_b)."""
