@@ -118,3 +118,23 @@ def prism_demag_factors(lx, ly, lz):
     axes permuted."""
     a, b, c = 0.5 * lx, 0.5 * ly, 0.5 * lz
     return _prism_dz(b, c, a), _prism_dz(c, a, b), _prism_dz(a, b, c)
+
+
+def exchange_mode_field(k, n, A, Ms, d):
+    """Exchange field per unit amplitude [T] of the Neumann standing wave
+    cos(k pi (i + 1/2) / n) along an axis of n cells of size d: the
+    eigenvalue (2A/Ms)(2/d^2)(1 - cos(k pi / n)) of the six-neighbour
+    stencil with free ends, so that the wave precesses at
+    gamma (B0 + this field) in a bias B0 along z without demag."""
+    return 2.0 * A / Ms * 2.0 / (d * d) * (1.0 - np.cos(k * np.pi / n))
+
+
+def profile_coupling(g, u, phi):
+    """Coupling of a cavity mode of profile u to the spin-wave mode of
+    profile phi (Sec. II E, Eq. (10)-(11) and Eq. (18)): the cavity sees
+    g <u m^-> and the wave is driven by g u(r) a projected on phi, so the
+    pair exchanges at g_eff = g <u phi> / sqrt(<phi^2>) (means over the
+    magnetic cells); <u> for a uniform phi."""
+    u = np.asarray(u, float)
+    phi = np.asarray(phi, float)
+    return g * np.mean(u * phi) / np.sqrt(np.mean(phi * phi))

@@ -160,6 +160,31 @@ def paper_sim1(B0=None, g=None, kappa=None, T=16e-9, drive_amp=2e8):
                     method="rk4", dt0=1e-12, tol=0.0, T=T, dt_sample=1e-12)
 
 
+# AFM material of Sim 7 (Table I notes, Sec. IV G): per sublattice
+# Ms = 200 kA/m, K = 100 J/m^3 (mu0 H_A = 2K/Ms = 1 mT), alpha = 1e-3,
+# A = 3.5 pJ/m; intersublattice field mu0 H_E = 15.9 T (from J_cell)
+AFM_PAPER = dict(Ms=200e3, Ku=100.0, alpha=1e-3, Aex=3.5e-12, B_E=15.9)
+
+
+def paper_sim7(B0=0.0, alpha=None, g=None, csign=(1, 1), m0=None, T=16e-9):
+    """Sim 7 of Table I: the two-sublattice antiferromagnet of Sec. IV G on
+    the 8x8x1 geometry at 10 nm, easy axis z, bias B0 along z [T], sublattice
+    1 along +z and 2 along -z, one uniform mode at 5 GHz with Q = 5000 and
+    g/2pi = 50 MHz coupled to the net magnetization (signs +1, +1) and
+    excited by the pulse of Sec. IV A; RK4 at 4 ps for 16 ns (4,000 steps)."""
+    grid = (8, 8, 1)
+    wc = TWO_PI * 5.0e9
+    if m0 is None:
+        m0 = tilted(grid, 0.0, 0.0, sublattices=2)
+    return Instance(grid=grid, cell=(10e-9,) * 3, Ms=AFM_PAPER["Ms"], Aex=AFM_PAPER["Aex"],
+                    alpha=AFM_PAPER["alpha"] if alpha is None else alpha, Ku=AFM_PAPER["Ku"],
+                    ku_axis=(0.0, 0.0, 1.0), B0=(0.0, 0.0, B0), demag=DEMAG_NONE, sublattices=2,
+                    B_E=AFM_PAPER["B_E"], omega=np.array([wc]), kappa=np.array([wc / (2 * 5000)]),
+                    g=np.array([TWO_PI * 50e6 if g is None else g]), csign=np.array(csign, np.int8),
+                    drive_amp=np.array([2e8 + 0j]), drive_t0=np.array([0.1e-9]), drive_sigma=np.array([20e-12]),
+                    m0=m0, a0=np.zeros(1, complex), method="rk4", dt0=4e-12, tol=0.0, T=T, dt_sample=4e-12)
+
+
 def sweep_sphere(k, count=64, n=32):
     """Instance k of the field sweep: YIG sphere of diameter n cells on an n^3
     grid at 5 nm, FFT demag, gamma B0/2pi from 4.5 to 5.5 GHz, one uniform

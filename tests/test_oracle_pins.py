@@ -1004,3 +1004,35 @@ def test_controller_law_by_hand():
     # relative, and the step sizes (eps^(-1/5)) to better than 1e-8
     assert abs(st.dt - ref["dt"]) <= 1e-8 * ref["dt"]
     assert abs(complex(st.a[0]) - ref["a"]) <= 1e-12 * abs(c["a0"])
+
+
+def test_standing_wave_coupling_closed_form():
+    """A cavity of one-node profile on the 8x8x1 film of Sec. IV couples to
+    the k = 1 standing spin wave (Sec. IV F, Eq. (18)): with the wave tuned to
+    the cavity (B0 = w_c / gamma - its exchange field), the oracle's two
+    branches sit at w_c -+ g <u phi> / sqrt<phi^2> (the lossy 2x2 of Eq. (7)
+    with that coupling) within 0.05 MHz; the same profile is blind to the
+    uniform magnon (<u> = 0)."""
+    base = W.paper_sim1(T=4e-9)
+    wc, g, kp = base.omega[0], base.g[0], base.kappa[0]
+    u = W.standing_wave(base.grid, 1).astype(np.float64)[None]
+    bk = theory.exchange_mode_field(1, 8, base.Aex, base.Ms, base.cell[0])
+    B = wc / GAMMA - bk
+    kw = base.oracle_kwargs()
+    kw.update(u=u, B0=(0.0, 0.0, B))
+    st = Stepper(Model(Problem(**kw)), base.m0, base.a0, method="rk4", dt0=1e-12)
+    st.set_sampling(10e-12, 1000)
+    with torch.no_grad():
+        assert st.run(4e-9) == OK
+    t, a, mm = st.trace_arrays()
+    k = t.numpy() > 0.3e-9
+    a, mm = a.numpy()[k, 0], mm.numpy()[k, 0]
+    s = prony(np.stack([a / np.abs(a).max(), mm / np.abs(mm).max()]), 10e-12, 6)
+    ge = theory.profile_coupling(g, u[0], u[0])
+    assert abs(ge - g / math.sqrt(2) / math.cos(math.pi / 16)) < 1e-6 * g
+    wk = GAMMA * (B + bk)
+    want = np.linalg.eigvals(np.array([[wc - 1j * kp, ge], [ge, wk - 1j * base.alpha * wk]]))
+    for w in want:
+        got = -s.imag[np.argmin(np.abs(-s.imag - w.real))]
+        assert abs(got - w.real) / TWO_PI < 0.05e6
+    assert abs(theory.overlap(u[0])) < 1e-15
