@@ -388,6 +388,16 @@ __device__ __forceinline__ void reg_dft(float2 (&v)[M], const float2* tw32) {
   }
 }
 
+// d * (1 + hf (W_M^{+-k} - 1)): the twiddle for lanes with hf = 1, the
+// identity for hf = 0 (k > 0, M <= 16)
+template <int M, bool INV>
+__device__ __forceinline__ float2 twh(float2 d, int k, float hf) {
+  const int j = k * (16 / M);
+  const float c = cos16(j), sn = INV ? cos16(j - 4) : -cos16(j - 4);
+  const float tr = fmaf(hf, c - 1.f, 1.f), ti = hf * sn;
+  return make_float2(d.x * tr - d.y * ti, d.x * ti + d.y * tr);
+}
+
 // quad_perm lane exchange: XOR 1 and XOR 2 within each group of four lanes
 __device__ __forceinline__ float dpp_x1(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
@@ -427,6 +437,20 @@ __device__ __forceinline__ float2 fold(float2 x0, float2 x1, int r, float2 w) {
   if (r & 1) x1 = make_float2(x1.y, -x1.x);
   if (r & 2) x1 = make_float2(-x1.x, -x1.y);
   return cmul(cadd(x0, x1), w);
+}
+
+// (-i)^r of a lane's residue r, as (re, im) in {0, +-1}
+struct Root4 {
+  float re, im;
+  __device__ __forceinline__ explicit Root4(int r)
+      : re((r & 1) ? 0.f : ((r & 2) ? -1.f : 1.f)), im((r & 1) ? ((r & 2) ? 1.f : -1.f) : 0.f) {}
+};
+// the same fold with the residue's root held by the lane: x0 + c x1 by two
+// fused multiply-adds per part (c has one nonzero part, so each result is
+// rounded once, as the plain sum), then the twiddle
+__device__ __forceinline__ float2 fold_c(float2 x0, float2 x1, Root4 c, float2 w) {
+  const float2 s = make_float2(fmaf(c.re, x1.x, fmaf(-c.im, x1.y, x0.x)), fmaf(c.re, x1.y, fmaf(c.im, x1.x, x0.y)));
+  return cmul(s, w);
 }
 
 template <int MY, int MZ>
@@ -717,35 +741,42 @@ __global__ __launch_bounds__(MM_YZ8_T) __attribute__((amdgpu_waves_per_eu(4, 4))
 #pragma unroll 1
   for (int t = threadIdx.x; t < 4 * 3 * ZR; t += MM_YZ8_T) {
     const int r = t & 3;
+    const Root4 cr(r);
     float2* line = B + (t >> 2) * RS;
     float2 f[MY];
 #pragma unroll
-    for (int j = 0; j < MY; ++j) f[j] = fold(line[j], line[j + MY], r, twy[r * j]);
+    for (int j = 0; j < MY; ++j) f[j] = fold_c(line[j], line[j + MY], cr, twy[r * j]);
     reg_dft<MY, false>(f, tw32);
 #pragma unroll
     for (int p = 0; p < MY; ++p) line[4 * brevc(p, lgMY) + r] = f[p];
   }
   __syncthreads();
-  // z per ky column: eight lanes (residue r, half h)
+  // z per ky column: eight lanes (residue r, half h).  The lane-dependent
+  // roles are written as arithmetic with per-lane constants instead of
+  // selects: sg = +1 / -1 for h = 0 / 1, and the half-split twiddle is
+  // 1 + hf (W - 1) with hf = h.
 #pragma unroll 1
   for (int t = threadIdx.x; t < 8 * PY; t += MM_YZ8_T) {
     const int ky = t >> 3, h = t & 1, r = (t >> 1) & 3;
+    const Root4 cr(r);
+    const float hf = (float)h, sg = 1.f - 2.f * hf;
     const float2* col = B + ky;
     float2 fc[3][MH];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      // fold of this half, then the radix-2 stage across the two halves
+      // fold of this half, then the radix-2 stage across the two halves:
+      // h = 0 keeps own + recv, h = 1 (recv - own) W_MZ^jj
 #pragma unroll
       for (int jj = 0; jj < MH; ++jj) {
         const int j = h * MH + jj;
-        fc[c][jj] = fold(col[(c * ZR + j) * RS], col[(c * ZR + j + MZ) * RS], r, twz[r * j]);
+        fc[c][jj] = fold_c(col[(c * ZR + j) * RS], col[(c * ZR + j + MZ) * RS], cr, twz[r * j]);
       }
 #pragma unroll
       for (int jj = 0; jj < MH; ++jj) {
         const float2 own = fc[c][jj];
         const float2 recv = lane_x1(own);
-        const float2 hi = twc<MZ, false>(csub(recv, own), jj);
-        fc[c][jj] = h ? hi : cadd(own, recv);
+        const float2 d = make_float2(fmaf(sg, own.x, recv.x), fmaf(sg, own.y, recv.y));
+        fc[c][jj] = jj == 0 ? d : twh<MZ, false>(d, jj, hf);
       }
       reg_dft<MH, false>(fc[c], tw32);
       asm volatile("" ::: "memory");
@@ -764,6 +795,8 @@ __global__ __launch_bounds__(MM_YZ8_T) __attribute__((amdgpu_waves_per_eu(4, 4))
       for (int k = 0; k < MH; ++k) g[k] = fc[c][brevc(k, lgMH)];
       reg_dft<MH, true>(g, tw32);
       // recombine the halves: x[z'] = g0 + W^{-z'} g1, x[z' + MH] = g0 - W^{-z'} g1
+      // (selects here: the arithmetic form needs registers this kernel does
+      // not have at four wavefronts per SIMD)
       float2 w[MH];
 #pragma unroll
       for (int zz = 0; zz < MH; ++zz) {
