@@ -57,3 +57,25 @@ def prony(x, dt, count):
     z = np.roots(np.concatenate([[1.0], -coef]))
     s = np.log(z) / dt
     return s[np.argsort(-s.imag)]
+
+
+def prony_torch(x, dt, count):
+    """prony() written with torch operations, so that autograd
+    differentiates the rates with respect to the samples: the prediction
+    coefficients by the pseudo-inverse of the linear-prediction matrix, the
+    rates from the eigenvalues of the companion matrix.  x: complex tensor
+    (n,) or (channels, n)."""
+    import torch
+    if x.dim() == 1:
+        x = x.unsqueeze(0)
+    rows, rhs = [], []
+    for ch in x:
+        for k in range(count, ch.shape[0]):
+            rows.append(torch.flip(ch[k - count:k], dims=(0,)))
+            rhs.append(ch[k])
+    A = torch.stack(rows)
+    b = torch.stack(rhs)
+    coef = torch.linalg.pinv(A) @ b
+    comp = torch.diag(torch.ones(count - 1, dtype=coef.dtype), -1)
+    comp = torch.cat([coef.unsqueeze(0), comp[1:]], dim=0)
+    return torch.log(torch.linalg.eigvals(comp)) / dt
