@@ -12,12 +12,15 @@ from .model import Model, Problem
 from .stepper import Stepper
 
 
-def run_with_grad(problem: Problem, m0, a0, dt, T, loss_fn, method="rk4", trace_loss=None):
+def run_with_grad(problem: Problem, m0, a0, dt, T, loss_fn, method="rk4", trace_loss=None, steps=None):
     """Return (loss, grads) where grads has d loss / d u (N, nz, ny, nx),
     d g (N,), d alpha, d B0 (3,), d a0 (N complex, as d/dRe + i d/dIm) and
     d m0 (S, 3, nz, ny, nx, taken with respect to the normalised state).
     With trace_loss, the loss also has trace_loss(A) for A the complex
-    amplitudes at the start and every step end, shape (steps + 1, N)."""
+    amplitudes at the start and every step end, shape (steps + 1, N).
+    With steps (a sequence of accepted Dormand-Prince step sizes, negative
+    for one clipped onto T), the run is that replayed sequence instead of a
+    fixed-step run: the adjoint of an adaptive run with its steps held."""
     N = len(problem.omega)
     nx, ny, nz = problem.grid
     u0 = np.ones((N, nz, ny, nx)) if problem.u is None else np.asarray(problem.u, float).reshape(N, nz, ny, nx)
@@ -36,7 +39,11 @@ def run_with_grad(problem: Problem, m0, a0, dt, T, loss_fn, method="rk4", trace_
     st.a = torch.complex(ar, ai)
     if trace_loss is not None:
         st.set_sampling(dt, 1 << 30)
-    status = st.run(T)
+    if steps is not None:
+        st.replay(steps, t_end=T)
+        status = 0
+    else:
+        status = st.run(T)
     loss = loss_fn(st.m, st.a)
     if trace_loss is not None:
         loss = loss + trace_loss(torch.stack(st.trace["a"]))
@@ -52,10 +59,14 @@ def run_with_grad(problem: Problem, m0, a0, dt, T, loss_fn, method="rk4", trace_
     return float(loss.detach()), grads, status
 
 
-def run_loss(problem: Problem, m0, a0, dt, T, loss_fn, method="rk4", leaves=None):
-    """Loss only (no gradient), optionally with perturbed parameter leaves."""
+def run_loss(problem: Problem, m0, a0, dt, T, loss_fn, method="rk4", leaves=None, steps=None):
+    """Loss only (no gradient), optionally with perturbed parameter leaves
+    (and, with steps, of the replayed Dormand-Prince sequence)."""
     M = Model(problem, leaves)
     st = Stepper(M, np.asarray(m0, float), np.asarray(a0, complex), method=method, dt0=dt)
     with torch.no_grad():
-        st.run(T)
+        if steps is not None:
+            st.replay(steps, t_end=T)
+        else:
+            st.run(T)
         return float(loss_fn(st.m, st.a))

@@ -23,7 +23,13 @@ adaptive RK45 step as the LLG equation), with no operator splitting.
   * the last step is clipped so that the run ends exactly on t0 + T.
   * stage s of a step from t with size h is evaluated at t + c_s h (RK4:
     c = 0, 1/2, 1/2, 1; DP45: the c column of the tableau), which matters
-    only for the time-dependent cavity drive.
+    only for the time-dependent cavity terms (drive, parametric pump).
+  * an adaptive run keeps the sizes of its accepted steps (`accepted_h`,
+    negative for a step clipped onto the end time); `replay` applies the
+    5th-order steps of such a sequence, every one accepted.  Rejected
+    attempts leave no trace in the state, so the replay reaches the adaptive
+    run's states; it is the map the adjoint of an adaptive run
+    differentiates (the step sizes held fixed).
 
 Status values: 0 ok, -5 step size below dt_min, -6 non-finite state.
 """
@@ -76,6 +82,7 @@ class Stepper:
         self.last_rejected = False
         self.fsal = None            # (k1, ka1, m^-_1, dm^-/dt_1) at the current state
         self.trace = None
+        self.accepted_h = []        # sizes of the accepted adaptive steps (negative: clipped)
 
     # ----------------------------------------------------------- observables
     def m_minus_rate(self, k):
@@ -210,6 +217,7 @@ class Stepper:
                 self.t = t_end if clipped else self.t + h
                 self.fsal = st7
                 self.accepted += 1
+                self.accepted_h.append(-h if clipped else h)
                 fmax = 1.0 if self.last_rejected else 5.0
                 fac = 5.0 if eps == 0.0 else 0.9 * eps ** (-0.2)
                 fac = min(fmax, max(0.2, fac))
@@ -224,6 +232,37 @@ class Stepper:
                 status = NONFINITE if not math.isfinite(eps) else DT_UNDERFLOW
                 break
         return status
+
+    def replay(self, steps, t_end=None):
+        """Apply accepted Dormand-Prince steps of the given sizes (negative:
+        a step that lands on t_end, the end time of the recorded run): the
+        stages of the tableau from the current state, the 5th-order
+        combination, the renormalised candidate.  Returns the number of
+        steps taken."""
+        M = self.model
+        for hs in steps:
+            h = abs(hs)
+            y, a, t = self.m, self.a, self.t
+            ks, kas = [], []
+            for s in range(6):
+                ys, as_ = y, a
+                for j, c in enumerate(DP_A[s]):
+                    if c != 0.0:
+                        ys = ys + h * c * ks[j]
+                        as_ = as_ + h * c * kas[j]
+                k, ka, _ = M.rhs(ys, as_, t + DP_C[s] * h)
+                ks.append(k)
+                kas.append(ka)
+            yn, an = y, a
+            for j, b in enumerate(DP_B[:6]):
+                if b != 0.0:
+                    yn = yn + h * b * ks[j]
+                    an = an + h * b * kas[j]
+            self.m, self.a = M.normalize(yn), an
+            self.t = t_end if (hs < 0 and t_end is not None) else t + h
+            self.accepted += 1
+        self.fsal = None
+        return len(steps)
 
     def _sample_interval(self, h, start, a1, end):
         tr = self.trace

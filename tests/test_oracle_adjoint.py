@@ -114,3 +114,33 @@ def test_oracle_gradient_with_parametric_pump():
         vals[sgn] = run_loss(prob, m0, a0 + h * da, dt, T, loss_mode2, leaves=lv)
     fd = (vals[1] - vals[-1]) / 2e-4
     assert abs(fd - ad) <= 1e-6 * abs(fd), (fd, ad)
+
+
+def test_dp45_replay_reaches_the_adaptive_states():
+    """The replay of an adaptive run's accepted steps (rejected attempts
+    leave the state untouched, FSAL is f at the new state) reaches the same
+    state bit for bit; its autograd gradient, with the steps held, matches
+    central differences of the replayed map."""
+    from oracle.model import Model
+    from oracle.stepper import Stepper
+    prob, m0, a0 = small_film()
+    st = Stepper(Model(prob), m0, a0, method="dp45", dt0=2e-12)
+    with torch.no_grad():
+        assert st.run(12e-12, 1e-7) == 0
+    hs = list(st.accepted_h)
+    assert st.rejected >= 1 and len(hs) == st.accepted and hs[-1] < 0
+    rp = Stepper(Model(prob), m0, a0, method="dp45", dt0=2e-12)
+    with torch.no_grad():
+        rp.replay(hs, t_end=12e-12)
+    assert torch.equal(rp.m, st.m) and torch.equal(rp.a, st.a) and rp.t == st.t
+    L, g, _ = run_with_grad(prob, m0, a0, 2e-12, 12e-12, loss_mode2, steps=hs)
+    rng = np.random.default_rng(8)
+    du = rng.normal(size=np.asarray(prob.u).shape)
+    dg = rng.normal(size=4) * np.asarray(prob.g)
+    ad = np.sum(g["u"] * du) + np.dot(g["g"], dg)
+    vals = []
+    for h in (1e-4, -1e-4):
+        lv = {"u": torch.tensor(np.asarray(prob.u, float) + h * du), "g": torch.tensor(np.asarray(prob.g, float) + h * dg)}
+        vals.append(run_loss(prob, m0, a0, 2e-12, 12e-12, loss_mode2, leaves=lv, steps=hs))
+    fd = (vals[0] - vals[1]) / 2e-4
+    assert abs(fd - ad) <= 1e-6 * abs(fd), (fd, ad)
