@@ -332,7 +332,7 @@ mm_status mm_batch_set_fft_x(mm_batch* b, int32_t path);
 mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, char* names,
                            int64_t* launches, double* total_ms, double* bytes_per_launch, int32_t* n);
 
-/* ---- form (3): discrete adjoint of a fixed-step RK4 run ----------------- */
+/* ---- form (3): discrete adjoint (fixed-step RK4 runs; adaptive DP45 runs by replay) */
 /* Advance by T (a whole number of RK4 steps of dt0, relative slack 1e-9)
  * from the current state and keep a checkpoint (m, a, t) every
  * `checkpoint_every` steps (device memory) for a later mm_adjoint.  The
@@ -342,6 +342,25 @@ mm_status mm_batch_profile(mm_batch* b, int64_t steps, double tol, int32_t cap, 
  * With sampling set (dt_sample = dt0), the trace of the recorded run gives
  * a at every step end for mm_adjoint_trace. */
 mm_status mm_run_record(mm_ctx* ctx, double T, int32_t checkpoint_every);
+
+/* Adjoint of adaptive runs (form (3) for the DP45 stepper): advance by T
+ * with DP45 at tolerance tol (as mm_run) from the current state, keeping the
+ * size of every accepted step, then replay the accepted steps from the
+ * start (each at its logged size, all accepted: rejected attempts leave no
+ * trace in the state, so the replay reaches the run's states bit for bit)
+ * and keep a checkpoint every `checkpoint_every` accepted steps.  A later
+ * mm_adjoint differentiates that replayed map, the step sizes held fixed --
+ * the usual adjoint of an adaptive run.  The context must use MM_DP45 and
+ * reciprocal coupling, else MM_ERR_STATE; losses on the trace
+ * (mm_adjoint_trace) are built for RK4 runs only.  The state is left at the
+ * end of the run with its own controller state, counters and trace.
+ * Device memory: the step log (8 B per accepted step) and the checkpoints;
+ * mm_adjoint then keeps six stage inputs per step of a segment. */
+mm_status mm_run_record_adaptive(mm_ctx* ctx, double T, double tol, int32_t checkpoint_every);
+/* Sizes of the accepted steps of the last mm_run_record_adaptive, negative
+ * for the last one when it was clipped onto the end time: *n is in: the
+ * capacity of h (may be 0 with h = NULL), out: the number of steps. */
+mm_status mm_get_step_log(const mm_ctx* ctx, double* h, int64_t* n);
 
 /* Gradients of a scalar loss L(m(T), a(T)) of the recorded run, by the
  * discrete adjoint of the recorded step sequence (each segment between

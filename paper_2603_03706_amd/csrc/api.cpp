@@ -292,9 +292,16 @@ struct mm_ctx {
   std::vector<InstCtl> ck_ctl;
   float* adj_f = nullptr;          // rec_m, rec_norm, lam_y, lam_k, lam_z, mu, lam_B
   double* adj_d = nullptr;         // rec_a, grad_u
-  int adj_K = -1, adj_N = -1;
+  int adj_K = -1, adj_N = -1, adj_nstg = 4;
   bool adj_on = false;             // descriptor carries the adjoint pointers
   double* dla_dev = nullptr;       // dL/da at every step end (mm_adjoint_trace), during the call only
+  // adaptive recorded runs (DP45): the accepted step sizes on the device,
+  // their host copy, and the end time of the recorded run
+  double* hlog_dev = nullptr;
+  long long hlog_cap = 0;
+  std::vector<double> rec_hs;
+  int rec_method = MM_RK4;
+  double rec_t_end = 0.0;
 };
 
 struct mm_batch {
@@ -509,11 +516,15 @@ mm_status upload_desc(mm_ctx* c) {
     d.fy = (float2*)(w + L.fy);
     d.kern = c->spec ? c->spec->dev : nullptr;
   }
+  d.hlog = c->hlog_dev;
+  d.hlog_cap = c->hlog_cap;
+  d.rec_nstg = c->method == MM_DP45 ? 6 : 4;
   if (c->adj_on) {
     const size_t vec = (size_t)3 * p.sublattices * L.ncell;
-    const int K = c->adj_K;
+    const int K = c->adj_K, ns = d.rec_nstg;
+    const bool dp = c->method == MM_DP45;
     float* f = c->adj_f;
-    d.rec_m = f; f += (size_t)(K + 1) * 4 * vec;
+    d.rec_m = f; f += (size_t)(K + 1) * ns * vec;
     d.rec_norm = f; f += (size_t)K * p.sublattices * L.ncell;
     d.lam_y = f; f += vec;
     d.lam_k = f; f += vec;
@@ -521,8 +532,11 @@ mm_status upload_desc(mm_ctx* c) {
     d.mu = f; f += vec;
     d.lam_B = f; f += vec;
     d.rec_bd = L.fft ? f : nullptr;
+    if (L.fft) f += (size_t)(K + (dp ? 1 : 0)) * ns * 3 * L.ncell;
+    d.mu_st = dp ? f : nullptr;
     d.rec_a = c->adj_d;
-    d.grad_u = c->adj_d + (size_t)K * 4 * std::max(1, c->N) * 2;
+    d.grad_u = c->adj_d + (size_t)K * ns * std::max(1, c->N) * 2;
+    d.rec_t = dp ? d.grad_u + (size_t)std::max(1, c->N) * L.ncell : nullptr;
     d.dla_trace = c->dla_dev;
   }
   c->version++;
@@ -972,7 +986,9 @@ mm_status launch_steps(mm_batch* b, int64_t steps) {
 }
 
 // One reverse step of the discrete adjoint for every instance of the batch.
+mm_status enqueue_reverse_step_dp(mm_batch* b);
 mm_status enqueue_reverse_step(mm_batch* b) {
+  if (b->method == MM_DP45) return enqueue_reverse_step_dp(b);
   const int n = (int)b->ctxs.size();
   if (mm_status s = launch(b, "adj_start", [&] { return mmk_launch_adj(0, 0, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
     return s;
@@ -990,12 +1006,39 @@ mm_status enqueue_reverse_step(mm_batch* b) {
           return mmk_launch_adj(1, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream, g_twiddle, b->stage_lds);
         }))
       return s;
-    if (mm_status s = enqueue_demag(b, 5, MMI_ADJ, false, false)) return s;
+    if (mm_status s = enqueue_demag(b, 0, MMI_ADJ, false, false)) return s;
     if (mm_status s = launch(b, "adj_stage_b", [&] {
           return mmk_launch_adj(2, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream, g_twiddle, b->stage_lds);
         }))
       return s;
     if (mm_status s = launch(b, "adj_cavity", [&] { return mmk_launch_adj(3, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
+      return s;
+  }
+  return MM_OK;
+}
+
+// The same for the replayed steps of an adaptive run: stages 6..1 of the
+// Dormand-Prince tableau (cavity part: kind 4, stage 7 = step start).
+mm_status enqueue_reverse_step_dp(mm_batch* b) {
+  const int n = (int)b->ctxs.size();
+  if (mm_status s = launch(b, "adj_start", [&] { return mmk_launch_adj(0, 0, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
+    return s;
+  if (mm_status s = launch(b, "adj_cavity", [&] { return mmk_launch_adj(4, 7, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
+    return s;
+  const bool bd_recorded = b->ctxs.size() == 1 && b->ctxs[0]->desc.rec_bd;
+  for (int st = 6; st >= 1; --st) {
+    if (!bd_recorded)
+      if (mm_status s = enqueue_demag(b, st, MMI_ADJ)) return s;
+    if (mm_status s = launch(b, "adj_stage_a", [&] {
+          return mmk_launch_adj(1, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream, g_twiddle, b->stage_lds);
+        }))
+      return s;
+    if (mm_status s = enqueue_demag(b, 0, MMI_ADJ, false, false)) return s;
+    if (mm_status s = launch(b, "adj_stage_b", [&] {
+          return mmk_launch_adj(2, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream, g_twiddle, b->stage_lds);
+        }))
+      return s;
+    if (mm_status s = launch(b, "adj_cavity", [&] { return mmk_launch_adj(4, st, b->total_wg, n, b->d_desc, b->d_wg, b->stream); }))
       return s;
   }
   return MM_OK;
@@ -1032,12 +1075,13 @@ mm_status check_ready(mm_ctx* c) {
   return MM_OK;
 }
 
-// Set run parameters of every instance; t_end = t + T (T <= 0: unbounded).
-mm_status begin_run(mm_batch* b, double T, double tol) {
+// Set run parameters of every instance; t_end = t + T (T <= 0: unbounded),
+// or t_end_abs when that is finite.
+mm_status begin_run(mm_batch* b, double T, double tol, double t_end_abs = NAN) {
   for (mm_ctx* c : b->ctxs) {
     InstCtl h;
     if (mm_status s = ctl_pull(c, h)) return s;
-    h.t_end = T > 0 ? h.t + T : 1e300;
+    h.t_end = std::isfinite(t_end_abs) ? t_end_abs : T > 0 ? h.t + T : 1e300;
     h.tol = tol;
     h.dt_fixed = c->dt0;
     h.dt_min = c->dt_min;
@@ -1071,20 +1115,25 @@ mm_status begin_run(mm_batch* b, double T, double tol) {
   return enqueue_start(b);
 }
 
+// The host copy of an instance's statistics from its control block.
+void set_stats(mm_ctx* c, const InstCtl& h, double wall) {
+  c->stats.accepted = h.accepted;
+  c->stats.rejected = h.rejected;
+  c->stats.t = h.t;
+  c->stats.dt = c->method == MM_RK4 ? h.dt_fixed : h.dt;
+  c->stats.dt_min_seen = h.dt_min_seen;
+  c->stats.dt_max_seen = h.dt_max_seen;
+  c->stats.wall_s = wall;
+  c->stats.status = h.status;
+}
+
 mm_status end_run(mm_batch* b, double wall) {
   MM_HIP(hipStreamSynchronize(b->stream));
   mm_status first = MM_OK;
   for (mm_ctx* c : b->ctxs) {
     InstCtl h;
     if (mm_status s = ctl_pull(c, h)) return s;
-    c->stats.accepted = h.accepted;
-    c->stats.rejected = h.rejected;
-    c->stats.t = h.t;
-    c->stats.dt = c->method == MM_RK4 ? h.dt_fixed : h.dt;
-    c->stats.dt_min_seen = h.dt_min_seen;
-    c->stats.dt_max_seen = h.dt_max_seen;
-    c->stats.wall_s = wall;
-    c->stats.status = h.status;
+    set_stats(c, h, wall);
     if (h.status != 0 && first == MM_OK) first = (mm_status)h.status;
   }
   if (first == MM_ERR_DT_UNDERFLOW) return fail(first, "adaptive step fell below dt_min");
@@ -1092,9 +1141,9 @@ mm_status end_run(mm_batch* b, double wall) {
   return first;
 }
 
-mm_status batch_run(mm_batch* b, double T, double tol) {
+mm_status batch_run(mm_batch* b, double T, double tol, double t_end_abs = NAN) {
   const auto t0 = std::chrono::steady_clock::now();
-  if (mm_status s = begin_run(b, T, tol)) return s;
+  if (mm_status s = begin_run(b, T, tol, t_end_abs)) return s;
   if (mm_status s = ensure_graph(b)) return s;
   const int n = (int)b->ctxs.size();
   for (;;) {
@@ -1353,6 +1402,7 @@ mm_status mm_destroy(mm_ctx* c) {
   if (c->ck_m) hipFree(c->ck_m);
   if (c->adj_f) hipFree(c->adj_f);
   if (c->adj_d) hipFree(c->adj_d);
+  if (c->hlog_dev) hipFree(c->hlog_dev);
   release_spectrum(c->spec);
   delete c;
   return MM_OK;
@@ -1836,7 +1886,8 @@ void restore_forward(InstCtl& dst, const InstCtl& ck) {
 mm_status mm_run_record(mm_ctx* c, double T, int32_t every) {
   if (c && c->open_in) return open_error();
   if (!c) return fail(MM_ERR_ARG, "NULL context");
-  if (c->method != MM_RK4 || c->split) return fail(MM_ERR_STATE, "recording needs the fixed-step RK4 method");
+  if (c->method != MM_RK4 || c->split)
+    return fail(MM_ERR_STATE, "recording needs the fixed-step RK4 method (DP45: mm_run_record_adaptive)");
   if (c->nonrecip)
     return fail(MM_ERR_STATE, "the adjoint covers reciprocal coupling (g_b = g)");
   if (!(T > 0) || !std::isfinite(T) || every < 1) return fail(MM_ERR_ARG, "need T > 0 and checkpoint_every >= 1");
@@ -1868,12 +1919,133 @@ mm_status mm_run_record(mm_ctx* c, double T, int32_t every) {
   c->rec_K = every;
   c->rec_nck = nck;
   c->rec_h = c->dt0;
+  c->rec_method = MM_RK4;
   return MM_OK;
+}
+
+// Replay the logged accepted steps idx0 .. idx_end - 1 of an adaptive
+// recorded run from the current state: each step takes its logged size and
+// is accepted, and a step logged as clipped lands on the recorded run's own
+// end time, so the replay reaches the recorded states bit for bit.
+mm_status replay_run(mm_ctx* c, long long idx0, long long idx_end) {
+  InstCtl h;
+  if (mm_status s = ctl_pull(c, h)) return s;
+  h.replay = 1;
+  h.replay_idx = idx0;
+  h.replay_end = idx_end;
+  h.hlog_on = 0;
+  h.trace_on = 0;
+  if (mm_status s = ctl_push(c, h)) return s;
+  const bool sc = c->sampling_changed;
+  c->sampling_changed = false;
+  const mm_status st = batch_run(c->solo, 0.0, 1.0, c->rec_t_end);
+  c->sampling_changed = sc;
+  if (st != MM_OK) return st;
+  if (mm_status s = ctl_pull(c, h)) return s;
+  h.replay = 0;
+  return ctl_push(c, h);
+}
+
+// (Re)allocate the step log for `cap` accepted steps.
+mm_status ensure_step_log(mm_ctx* c, long long cap) {
+  if (c->hlog_dev && c->hlog_cap >= cap) return MM_OK;
+  if (c->hlog_dev) hipFree(c->hlog_dev);
+  c->hlog_dev = nullptr;
+  c->hlog_cap = 0;
+  if (hipMalloc(&c->hlog_dev, sizeof(double) * (size_t)cap) != hipSuccess) return fail(MM_ERR_OOM, "step log allocation failed");
+  c->hlog_cap = cap;
+  if (mm_status s = upload_desc(c)) return s;
+  return refresh_descs(c->solo);
 }
 
 static mm_status adjoint_impl(mm_ctx* c, const double* dL_da, const float* dL_dm, const double* dL_dtrace,
                               float* grad_u, double* grad_g, double* grad_alpha, double* grad_B0,
                               double* grad_a0, float* grad_m0);
+
+mm_status mm_run_record_adaptive(mm_ctx* c, double T, double tol, int32_t every) {
+  if (c && c->open_in) return open_error();
+  if (!c) return fail(MM_ERR_ARG, "NULL context");
+  if (c->method != MM_DP45) return fail(MM_ERR_STATE, "adaptive recording needs the DP45 method");
+  if (c->nonrecip) return fail(MM_ERR_STATE, "the adjoint covers reciprocal coupling (g_b = g)");
+  if (!(T > 0) || !std::isfinite(T) || every < 1) return fail(MM_ERR_ARG, "need T > 0 and checkpoint_every >= 1");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(MM_ERR_ARG, "DP45 needs a finite tol > 0");
+  if (mm_status s = check_ready(c)) return s;
+  if (mm_status s = set_device(c)) return s;
+  if (mm_status s = ensure_solo(c)) return s;
+  const size_t vec = (size_t)3 * c->p.sublattices * c->L.ncell;
+  c->rec_have = false;
+  // the start state
+  InstCtl h0;
+  if (mm_status s = ctl_pull(c, h0)) return s;
+  std::vector<float> m0(vec);
+  MM_HIP(hipMemcpy(m0.data(), c->ws + c->L.y[h0.cur], sizeof(float) * vec, hipMemcpyDeviceToHost));
+  // 1. the adaptive run, logging the size of every accepted step (run again
+  //    from the start with a larger log if it fills)
+  long long cap = std::max<long long>(1024, c->hlog_cap);
+  InstCtl hend;
+  double wall_run = 0.0;
+  for (;;) {
+    if (mm_status s = ensure_step_log(c, cap)) return s;
+    InstCtl h = h0;
+    h.hlog_on = 1;
+    h.hlog_n = 0;
+    h.replay = 0;
+    if (mm_status s = ctl_push(c, h)) return s;
+    MM_HIP(hipMemcpy(c->ws + c->L.y[h0.cur], m0.data(), sizeof(float) * vec, hipMemcpyHostToDevice));
+    if (mm_status s = batch_run(c->solo, T, tol)) return s;
+    wall_run = c->stats.wall_s;
+    if (mm_status s = ctl_pull(c, hend)) return s;
+    if (hend.hlog_n <= c->hlog_cap) break;
+    cap = 2 * hend.hlog_n;
+  }
+  const long long n = hend.hlog_n;
+  if (n < 1) return fail(MM_ERR_STATE, "the run took no step");
+  c->rec_hs.assign((size_t)n, 0.0);
+  MM_HIP(hipMemcpy(c->rec_hs.data(), c->hlog_dev, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+  c->rec_t_end = hend.t_end;
+  // 2. checkpoints every `every` steps along the replay of the logged steps
+  const int nck = (int)((n + every - 1) / every);
+  if (c->ck_m) hipFree(c->ck_m);
+  c->ck_m = nullptr;
+  if (hipMalloc(&c->ck_m, sizeof(float) * vec * nck) != hipSuccess) return fail(MM_ERR_OOM, "checkpoint allocation failed");
+  c->ck_ctl.assign(nck, InstCtl{});
+  {
+    InstCtl h = h0;
+    h.hlog_on = 0;
+    if (mm_status s = ctl_push(c, h)) return s;
+    MM_HIP(hipMemcpy(c->ws + c->L.y[h0.cur], m0.data(), sizeof(float) * vec, hipMemcpyHostToDevice));
+  }
+  for (int k = 0; k < nck; ++k) {
+    InstCtl h;
+    if (mm_status s = ctl_pull(c, h)) return s;
+    c->ck_ctl[k] = h;
+    MM_HIP(hipMemcpy(c->ck_m + vec * k, c->ws + c->L.y[h.cur], sizeof(float) * vec, hipMemcpyDeviceToDevice));
+    if (mm_status s = replay_run(c, (long long)k * every, std::min<long long>((long long)(k + 1) * every, n))) return s;
+  }
+  // the replay has reached the recorded run's end state; its own control
+  // block (step-size controller, counters, trace) comes back
+  hend.hlog_on = 0;
+  hend.replay = 0;
+  if (mm_status s = ctl_push(c, hend)) return s;
+  set_stats(c, hend, wall_run);
+  c->rec_have = true;
+  c->rec_steps = n;
+  c->rec_K = every;
+  c->rec_nck = nck;
+  c->rec_h = 0.0;
+  c->rec_method = MM_DP45;
+  return MM_OK;
+}
+
+mm_status mm_get_step_log(const mm_ctx* c, double* h, int64_t* n) {
+  if (c && c->open_in) return open_error();
+  if (!c || !n) return fail(MM_ERR_ARG, "NULL argument");
+  if (!c->rec_have || c->rec_method != MM_DP45) return fail(MM_ERR_STATE, "no adaptive recorded run (mm_run_record_adaptive)");
+  const int64_t cnt = (int64_t)c->rec_hs.size();
+  if (h) std::memcpy(h, c->rec_hs.data(), sizeof(double) * (size_t)std::min<int64_t>(*n, cnt));
+  *n = cnt;
+  return MM_OK;
+}
 
 mm_status mm_adjoint(mm_ctx* c, const double* dL_da, const float* dL_dm, float* grad_u, double* grad_g,
                      double* grad_alpha, double* grad_B0, double* grad_a0, float* grad_m0) {
@@ -1926,21 +2098,28 @@ static mm_status adjoint_impl(mm_ctx* c, const double* dL_da, const float* dL_dm
   for (int i = 0; i < 2 * N; ++i)
     if (!std::isfinite(dL_da[i])) return fail(MM_ERR_ARG, "non-finite dL_da");
   // adjoint buffers for segments of K steps
-  if (c->adj_K != K || c->adj_N != N) {
+  const bool dp = c->rec_method == MM_DP45;
+  if (dp && dL_dtrace) return fail(MM_ERR_STATE, "losses on the trace are built for fixed-step RK4 runs");
+  if (dp != (c->method == MM_DP45)) return fail(MM_ERR_STATE, "the stepper changed since the run was recorded");
+  const int ns = dp ? 6 : 4;
+  if (c->adj_K != K || c->adj_N != N || c->adj_nstg != ns) {
     if (c->adj_f) hipFree(c->adj_f);
     if (c->adj_d) hipFree(c->adj_d);
     c->adj_f = nullptr;
     c->adj_d = nullptr;
+    c->adj_K = -1;
     // stage inputs, norms, five adjoint vectors and, with FFT demag, the demag
     // field of every recorded stage input (the reverse pass then needs one
-    // convolution per stage instead of two)
-    const size_t nf = (size_t)(K + 1) * 4 * vec + (size_t)K * S * nc + 5 * vec +
-                      (c->L.fft ? (size_t)K * 4 * 3 * nc : 0);
-    const size_t nd = (size_t)K * 4 * std::max(1, N) * 2 + (size_t)std::max(1, N) * nc;
+    // convolution per stage instead of two); DP45: the mu of stages 3..6 and
+    // the start time of every step
+    const size_t nf = (size_t)(K + 1) * ns * vec + (size_t)K * S * nc + 5 * vec +
+                      (c->L.fft ? (size_t)(K + (dp ? 1 : 0)) * ns * 3 * nc : 0) + (dp ? 4 * vec : 0);
+    const size_t nd = (size_t)K * ns * std::max(1, N) * 2 + (size_t)std::max(1, N) * nc + (dp ? (size_t)K : 0);
     if (hipMalloc(&c->adj_f, sizeof(float) * nf) != hipSuccess) return fail(MM_ERR_OOM, "adjoint allocation failed");
     if (hipMalloc(&c->adj_d, sizeof(double) * nd) != hipSuccess) return fail(MM_ERR_OOM, "adjoint allocation failed");
     c->adj_K = K;
     c->adj_N = N;
+    c->adj_nstg = ns;
   }
   c->adj_on = true;
   if (mm_status s = upload_desc(c)) return s;
@@ -1980,10 +2159,17 @@ static mm_status adjoint_impl(mm_ctx* c, const double* dL_da, const float* dL_dm
     if (mm_status s = ctl_push(c, h)) return s;
     MM_HIP(hipMemcpy(c->ws + c->L.y[0], c->ck_m + vec * k, sizeof(float) * vec, hipMemcpyDeviceToDevice));
     c->record_next = 0;
-    if (mm_status s = batch_run(b, (double)steps * c->rec_h, 0.0)) return s;
-    if (mm_status s = ctl_pull(c, h)) return s;
-    MM_HIP(hipMemcpy(c->desc.rec_m + (size_t)steps * 4 * vec, c->ws + c->L.y[h.cur], sizeof(float) * vec,
-                     hipMemcpyDeviceToDevice));
+    if (dp) {
+      // the replay records every stage input, the stage-7 one as the next
+      // step's first, so the state after the segment is in place too
+      if (mm_status s = replay_run(c, (long long)k * K, (long long)k * K + steps)) return s;
+      if (mm_status s = ctl_pull(c, h)) return s;
+    } else {
+      if (mm_status s = batch_run(b, (double)steps * c->rec_h, 0.0)) return s;
+      if (mm_status s = ctl_pull(c, h)) return s;
+      MM_HIP(hipMemcpy(c->desc.rec_m + (size_t)steps * 4 * vec, c->ws + c->L.y[h.cur], sizeof(float) * vec,
+                       hipMemcpyDeviceToDevice));
+    }
     // reverse the segment
     h.rec_index = (int)steps - 1;
     h.adj_base = (long long)k * K;

@@ -12,6 +12,15 @@
 // The stage inputs y_s, |z_m| and a_s were recorded by the forward kernels
 // while the segment was recomputed from its checkpoint.
 //
+// Adaptive (DP45) runs are reversed as the replay of their accepted steps
+// (the step sizes h held): z = y + h sum_{j<=6} b_j k_j with stage inputs
+// y_s = y + h sum_{j<s} a_sj k_j.  Reverse: lambda_z as above, lambda_y =
+// lambda_z, then for s = 6..1: mu_s = J_f(y_s)^T lambda_ks, lambda_y += mu_s,
+// with lambda_ks = h (b_s lambda_z + sum_{q>s} a_qs mu_q); the mu_q of
+// stages 3..6 are kept until the earlier stages have used them.
+// Stage numbering of the launches: RK4 stages 1..4 and 5 for the step
+// start; DP45 stages 1..6 and 7 for the step start.
+//
 // Per stage the VJP is split in two cell kernels around the demag
 // convolution of lambda_B (the tensor is symmetric and even, so the same
 // FFT convolution is its own transpose):
@@ -66,6 +75,13 @@ __device__ __forceinline__ void cross3(const float* a, const float* b, float* o)
   o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// size of the step being reversed: fixed (RK4) or the logged one (DP45)
+template <class CtlPtr>
+__device__ __forceinline__ double adj_step(const InstDesc& D, CtlPtr C) {
+  if (D.method != MMI_DP45) return C->adj_h;
+  return fabs(gbl(D.hlog)[C->adj_base + C->rec_index]);
+}
+
 // ---------------------------------------------------------- step start
 // lambda_z from the step-end adjoint (held in lam_y), lambda_y = lambda_z,
 // lambda_k4 = h/6 lambda_z.
@@ -81,11 +97,12 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_start(const InstDesc* __restrict
   const bool mag = !D.has_geom || gbl(D.geom)[i];
   const size_t vec = (size_t)3 * S * nc;
   const int ri = C->rec_index;
-  const MMG float* Yn = gbl(D.rec_m) + ((size_t)(ri + 1) * 4) * vec;      // state after the step
+  const MMG float* Yn = gbl(D.rec_m) + ((size_t)(ri + 1) * D.rec_nstg) * vec;   // state after the step
   MMG float* const lam_y = gbl(D.lam_y);
   MMG float* const lam_z = gbl(D.lam_z);
   MMG float* const lam_k = gbl(D.lam_k);
-  const float c6 = (float)(C->adj_h / 6.0);
+  // weight of the last stage in the step-end combination: h/6 (RK4), h b_6 (DP45)
+  const float c6 = (float)(D.method == MMI_DP45 ? adj_step(D, C) * DPCoef::b6 : C->adj_h / 6.0);
   for (int s = 0; s < S; ++s) {
     float l[3], y[3];
     for (int c = 0; c < 3; ++c) {
@@ -125,7 +142,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
   const bool mag = valid && (!D.has_geom || gbl(D.geom)[i]);
   const int ri = C->rec_index;
   const Src src = stage_src(D, C, MMI_ADJ, ST);
-  const MMG double* as = gbl(D.rec_a) + ((size_t)ri * 4 + (ST - 1)) * N * 2;
+  const MMG double* as = gbl(D.rec_a) + ((size_t)ri * D.rec_nstg + (ST - 1)) * N * 2;
   const MMG float* const u_ = gbl(D.u);
   MMG float* const lam_B = gbl(D.lam_B);
   int x = 0, yy = 0, zz = 0;
@@ -158,7 +175,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_a(const InstDesc* __restrict__ d
   float bdv[3] = {0.f, 0.f, 0.f};
   const bool bd_recorded = D.rec_bd != nullptr;
   if (bd_recorded && valid) {
-    const MMG float* RB = gbl(D.rec_bd) + ((size_t)ri * 4 + (ST - 1)) * (size_t)(3 * nc);
+    const MMG float* RB = gbl(D.rec_bd) + ((size_t)ri * D.rec_nstg + (ST - 1)) * (size_t)(3 * nc);
 #pragma unroll
     for (int c = 0; c < 3; ++c) bdv[c] = RB[c * nc + i];
   }
@@ -285,10 +302,13 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ d
   MMG float* const lam_y = gbl(D.lam_y);
   MMG float* const lam_z = gbl(D.lam_z);
   MMG float* const lam_k = gbl(D.lam_k);
-  const double h = C->adj_h;
-  // coefficient of k_(ST-1) in y_ST and RK4 weight of k_(ST-1)
+  const bool dp = D.method == MMI_DP45;
+  const double h = adj_step(D, C);
+  // RK4: coefficient of k_(ST-1) in y_ST and the weight of k_(ST-1)
   const float cst = (float)(ST == 4 ? h : 0.5 * h);
   const float wprev = (float)(h * (ST == 2 ? 1.0 : 2.0) / 6.0);
+  // DP45: lambda_k(ST-1) = h (b_(ST-1) lambda_z + sum_{q>=ST} a_(q,ST-1) mu_q)
+  const size_t vec = (size_t)3 * S * nc;
   float lb[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
   for (int s = 0; s < S; ++s)
     for (int c = 0; c < 3; ++c) lb[s][c] = L[(s * 3 + c) * nc + i];
@@ -335,24 +355,36 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_b(const InstDesc* __restrict__ d
     for (int c = 0; c < 3; ++c) {
       const int idx = (s * 3 + c) * nc + i;
       lam_y[idx] += mu[c];
-      if (ST > 1) lam_k[idx] = fmaf(wprev, lam_z[idx], cst * mu[c]);
+      if (!dp) {
+        if (ST > 1) lam_k[idx] = fmaf(wprev, lam_z[idx], cst * mu[c]);
+      } else if (ST > 1) {
+        // keep mu of stages 3..6 for the stages below
+        if (ST >= 3) gbl(D.mu_st)[(size_t)(ST - 3) * vec + idx] = mu[c];
+        float acc = (float)(DPCoef::b(ST - 1)) * lam_z[idx] + (float)DPCoef::a(ST, ST - 1) * mu[c];
+#pragma unroll
+        for (int q = ST + 1; q <= 6; ++q)
+          acc = fmaf((float)DPCoef::a(q, ST - 1), gbl(D.mu_st)[(size_t)(q - 3) * vec + idx], acc);
+        lam_k[idx] = (float)h * acc;
+      }
     }
   }
 }
 
 // --------------------------------------------------------- cavity part
-// ST = 5: step start.  ST = 4..1: after the stage kernels of that stage.
-template <int ST>
+// RK4 (DP = false): ST = 5 step start, ST = 4..1 after the stage kernels of
+// that stage.  DP45 (DP = true): ST = 7 step start, ST = 6..1.
+template <bool DP, int ST>
 __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__ descs, int count) {
   __shared__ double sh[MMI_WG / 64];
   __shared__ double tot[MMI_PSTRIDE];
+  constexpr bool kStart = DP ? ST == 7 : ST == 5;
   if ((int)blockIdx.x >= count) return;
   const InstDesc& D = descs[blockIdx.x];
   InstCtl* C = D.ctl;
   if (C->done) return;
   const int N = D.N;
-  const double h = C->adj_h;
-  if (ST <= 4) {
+  const double h = adj_step(D, C);
+  if (!kStart) {
     for (int q = 0; q < MMI_PSTRIDE; ++q) {
       const bool used = (q < N) || (q >= MMI_ASLOT_MM && q < MMI_ASLOT_MM + 2 * N) ||
                         (q >= MMI_ASLOT_ALPHA && q < MMI_ASLOT_B0 + 3);
@@ -364,22 +396,23 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__
     }
   }
   if (threadIdx.x != 0) return;
-  if (ST == 5) {
+  if (kStart) {
     // a loss on the trace: its derivative at the end of the step being reversed
-    if (D.dla_trace) {
+    if (!DP && D.dla_trace) {
       const double* q = D.dla_trace + (size_t)(C->adj_base + C->rec_index + 1) * N * 2;
       for (int n = 0; n < N; ++n) {
         C->la[n][0] += q[2 * n];
         C->la[n][1] += q[2 * n + 1];
       }
     }
+    const double wl = DP ? h * DPCoef::b6 : h / 6.0;
     for (int n = 0; n < N; ++n)
       for (int r = 0; r < 2; ++r) {
         C->lza[n][r] = C->la[n][r];
-        C->lka[n][r] = h / 6.0 * C->la[n][r];
+        C->lka[n][r] = wl * C->la[n][r];
       }
   } else {
-    const double* as = D.rec_a + ((size_t)C->rec_index * 4 + (ST - 1)) * N * 2;
+    const double* as = D.rec_a + ((size_t)C->rec_index * D.rec_nstg + (ST - 1)) * N * 2;
     const double scale = D.inv_ngeo / (double)D.S;
     C->grad_alpha += tot[MMI_ASLOT_ALPHA];
     for (int c = 0; c < 3; ++c) C->grad_B0[c] += tot[MMI_ASLOT_B0 + c];
@@ -410,7 +443,8 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__
       if (D.param_on) {
         // transpose of the Jacobian of -i Lam conj(a), Lam = lam e^{-2 i wp t}
         // at the stage time: [[Li, -Lr], [-Lr, -Li]] (symmetric)
-        const double ts = C->adj_t0 + (double)C->rec_index * h + (ST == 1 ? 0.0 : ST == 4 ? h : 0.5 * h);
+        const double ts = DP ? gbl(D.rec_t)[C->rec_index] + DPCoef::c(ST) * h
+                             : C->adj_t0 + (double)C->rec_index * h + (ST == 1 ? 0.0 : ST == 4 ? h : 0.5 * h);
         double sn, cs;
         sincos(2.0 * D.par_wp[n] * ts, &sn, &cs);
         const double Lr = D.par_re[n] * cs + D.par_im[n] * sn;
@@ -430,9 +464,19 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__
     for (int n = 0; n < N; ++n) {
       C->la[n][0] += mu[n][0];
       C->la[n][1] += mu[n][1];
-      if (ST > 1) {
-        C->lka[n][0] = wprev * C->lza[n][0] + cst * mu[n][0];
-        C->lka[n][1] = wprev * C->lza[n][1] + cst * mu[n][1];
+      if (!DP) {
+        if (ST > 1) {
+          C->lka[n][0] = wprev * C->lza[n][0] + cst * mu[n][0];
+          C->lka[n][1] = wprev * C->lza[n][1] + cst * mu[n][1];
+        }
+      } else if (ST > 1) {
+        // lambda_ka(ST-1) = h (b_(ST-1) lambda_za + sum_{q>=ST} a_(q,ST-1) mu_a,q)
+        for (int r = 0; r < 2; ++r) {
+          if (ST >= 3) C->lmua[ST - 1][n][r] = mu[n][r];
+          double acc = DPCoef::b(ST - 1) * C->lza[n][r] + DPCoef::a(ST, ST - 1) * mu[n][r];
+          for (int q = ST + 1; q <= 6; ++q) acc += DPCoef::a(q, ST - 1) * C->lmua[q - 1][n][r];
+          C->lka[n][r] = h * acc;
+        }
       }
     }
     if (ST == 1) C->rec_index -= 1;
@@ -453,7 +497,7 @@ __global__ __launch_bounds__(MMI_WG) void k_adj_cav(const InstDesc* __restrict__
 
 hipError_t mmk_launch_adj(int kind, int stage, int nblocks, int count, const InstDesc* d, const int* wg,
                           hipStream_t s, const float2* tw, size_t lds) {
-  // kind 0: start, 1: A, 2: B, 3: cavity
+  // kind 0: start, 1: A, 2: B, 3: cavity (RK4), 4: cavity (DP45)
   if (kind == 0) {
     MM_LAUNCH(mmk::k_adj_start, dim3(nblocks), dim3(MMI_WG), 0, s, d, wg);
     return hipGetLastError();
@@ -464,16 +508,29 @@ hipError_t mmk_launch_adj(int kind, int stage, int nblocks, int count, const Ins
     if (K == 2) MM_LAUNCH(mmk::k_adj_b<ST>, dim3(nblocks), dim3(MMI_WG), lds, s, d, wg, tw);  \
     return hipGetLastError();                                                                          \
   }
-  MM_ADJ(1, 1) MM_ADJ(1, 2) MM_ADJ(1, 3) MM_ADJ(1, 4)
-  MM_ADJ(2, 1) MM_ADJ(2, 2) MM_ADJ(2, 3) MM_ADJ(2, 4)
+  MM_ADJ(1, 1) MM_ADJ(1, 2) MM_ADJ(1, 3) MM_ADJ(1, 4) MM_ADJ(1, 5) MM_ADJ(1, 6)
+  MM_ADJ(2, 1) MM_ADJ(2, 2) MM_ADJ(2, 3) MM_ADJ(2, 4) MM_ADJ(2, 5) MM_ADJ(2, 6)
 #undef MM_ADJ
   if (kind == 3) {
     switch (stage) {
-      case 1: MM_LAUNCH(mmk::k_adj_cav<1>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
-      case 2: MM_LAUNCH(mmk::k_adj_cav<2>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
-      case 3: MM_LAUNCH(mmk::k_adj_cav<3>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
-      case 4: MM_LAUNCH(mmk::k_adj_cav<4>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
-      case 5: MM_LAUNCH(mmk::k_adj_cav<5>, dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 1: MM_LAUNCH((mmk::k_adj_cav<false, 1>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 2: MM_LAUNCH((mmk::k_adj_cav<false, 2>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 3: MM_LAUNCH((mmk::k_adj_cav<false, 3>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 4: MM_LAUNCH((mmk::k_adj_cav<false, 4>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 5: MM_LAUNCH((mmk::k_adj_cav<false, 5>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  if (kind == 4) {   // DP45 cavity part: stages 1..6, 7 = step start
+    switch (stage) {
+      case 1: MM_LAUNCH((mmk::k_adj_cav<true, 1>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 2: MM_LAUNCH((mmk::k_adj_cav<true, 2>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 3: MM_LAUNCH((mmk::k_adj_cav<true, 3>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 4: MM_LAUNCH((mmk::k_adj_cav<true, 4>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 5: MM_LAUNCH((mmk::k_adj_cav<true, 5>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 6: MM_LAUNCH((mmk::k_adj_cav<true, 6>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
+      case 7: MM_LAUNCH((mmk::k_adj_cav<true, 7>), dim3(count), dim3(MMI_WG), 0, s, d, count); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -64,9 +64,9 @@ __device__ __forceinline__ Src stage_src(const InstDesc& D, CtlPtr C, int method
   s.c1 = 0.f;
   const int cur = C->cur;
   if (method == MMI_ADJ) {
-    // adjoint: stage 1..4 -> recorded stage input of the current step, 5 -> lambda_B
+    // adjoint: stage 1..nstg -> recorded stage input of the current step, 0 -> lambda_B
     const size_t vec = (size_t)3 * D.S * D.ncell;
-    s.p0 = gbl((stage == 5) ? D.lam_B : D.rec_m + ((size_t)C->rec_index * 4 + (stage - 1)) * vec);
+    s.p0 = gbl((stage == 0) ? D.lam_B : D.rec_m + ((size_t)C->rec_index * D.rec_nstg + (stage - 1)) * vec);
     return s;
   }
   if (method == MMI_RK4) {

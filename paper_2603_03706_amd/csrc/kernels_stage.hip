@@ -161,17 +161,21 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
         for (int c = 0; c < 3; ++c) m[s][c] = src.ld((s * 3 + c) * nc + i);
   }
   // recording for the discrete adjoint: keep every stage input of the step
-  const int ri = (METHOD == MMI_RK4 && ST >= 1) ? C->rec_index : -1;
-  if (METHOD == MMI_RK4 && ST >= 1 && ri >= 0 && valid) {
-    MMG float* R = gbl(D.rec_m) + ((size_t)ri * 4 + (ST - 1)) * (size_t)(3 * S * nc);
+  // (RK4 stages 1..4; DP45 stages 1..6, and the stage-7 input, the
+  // normalised candidate, as stage 1 of the next step)
+  const int ri = (ST >= 1) ? C->rec_index : -1;
+  if (ST >= 1 && ri >= 0 && valid) {
+    const int slot = (METHOD == MMI_DP45 && ST == 7) ? (ri + 1) * D.rec_nstg : ri * D.rec_nstg + (ST - 1);
+    MMG float* R = gbl(D.rec_m) + (size_t)slot * (size_t)(3 * S * nc);
 #pragma unroll
     for (int s = 0; s < 2; ++s)
       if (s < S)
 #pragma unroll
         for (int c = 0; c < 3; ++c) R[(s * 3 + c) * nc + i] = m[s][c];
-    // and the demag field of this stage input (FFT demag: one sublattice)
+    // and the demag field of this stage input (FFT demag: one sublattice);
+    // with FSAL, the next step's stage-1 field is the stage-7 one
     if (D.rec_bd) {
-      MMG float* RB = gbl(D.rec_bd) + ((size_t)ri * 4 + (ST - 1)) * (size_t)(3 * nc);
+      MMG float* RB = gbl(D.rec_bd) + (size_t)slot * (size_t)(3 * nc);
       const MMG float* bd = gbl(D.bd);
 #pragma unroll
       for (int c = 0; c < 3; ++c) RB[c * nc + i] = (kC2R && xf) ? bdv[c] : bd[c * nc + i];
@@ -299,7 +303,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
         float v0 = nx_[s][0], v1 = nx_[s][1], v2 = nx_[s][2];
         if (mag) {
           const float nrm = sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
-          if (METHOD == MMI_RK4 && ri >= 0) gbl(D.rec_norm)[(size_t)ri * S * nc + s * nc + i] = nrm;
+          if (ri >= 0) gbl(D.rec_norm)[(size_t)ri * S * nc + s * nc + i] = nrm;
           const float inv = 1.0f / nrm;
           v0 *= inv;
           v1 *= inv;

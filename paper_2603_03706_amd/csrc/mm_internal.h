@@ -53,6 +53,12 @@ struct InstCtl {
   double grad_g[MMI_MAX_MODES];
   double grad_alpha;
   double grad_B0[3];
+  // adaptive (DP45) runs: log of the accepted step sizes and their replay
+  long long hlog_n;                   // accepted steps logged (beyond the capacity: overflow)
+  long long replay_idx, replay_end;   // replay: next logged step, end of the replayed range
+  int hlog_on;                        // 1: log the size of every accepted step
+  int replay;                         // 1: steps take the logged sizes and are all accepted
+  double lmua[6][MMI_MAX_MODES][2];   // DP45 adjoint: mu_a of stage s at [s - 1]
 };
 
 // Read-only per-instance descriptor (device memory).
@@ -116,6 +122,12 @@ struct InstDesc {
   float* lam_B;                       // adjoint of the effective field
   double* grad_u;                     // [N][cells] accumulator (null: not requested)
   const double* dla_trace;            // [steps+1][N][2] dL/da at every step end of the recorded run, or null
+  // adaptive runs (DP45): step log, and the adjoint's extra records
+  double* hlog;                       // [hlog_cap] accepted step sizes, negative when clipped onto t_end
+  long long hlog_cap;
+  int rec_nstg, pad_nstg;             // stage inputs recorded per step: 4 (RK4), 6 (DP45)
+  double* rec_t;                      // [K] start time of each recorded step (DP45)
+  float* mu_st;                       // [4][S*3*cells] DP45 adjoint: mu of stages 3..6
 };
 
 // adjoint partial-record slots (doubles), reusing the forward partials
@@ -138,6 +150,23 @@ struct DPCoef {
                           b5 = -2187.0 / 6784, b6 = 11.0 / 84;
   static constexpr double e1 = 71.0 / 57600, e3 = -71.0 / 16695, e4 = 71.0 / 1920,
                           e5 = -17253.0 / 339200, e6 = 22.0 / 525, e7 = -1.0 / 40;
+  // a_qj of the tableau (1-based, j < q <= 6), 0 elsewhere
+  __host__ __device__ static constexpr double a(int q, int j) {
+    return q == 2 ? (j == 1 ? a21 : 0.0)
+         : q == 3 ? (j == 1 ? a31 : j == 2 ? a32 : 0.0)
+         : q == 4 ? (j == 1 ? a41 : j == 2 ? a42 : j == 3 ? a43 : 0.0)
+         : q == 5 ? (j == 1 ? a51 : j == 2 ? a52 : j == 3 ? a53 : j == 4 ? a54 : 0.0)
+         : q == 6 ? (j == 1 ? a61 : j == 2 ? a62 : j == 3 ? a63 : j == 4 ? a64 : j == 5 ? a65 : 0.0)
+                  : 0.0;
+  }
+  // b_j of the 5th-order solution (1-based, j <= 6)
+  __host__ __device__ static constexpr double b(int j) {
+    return j == 1 ? b1 : j == 3 ? b3 : j == 4 ? b4 : j == 5 ? b5 : j == 6 ? b6 : 0.0;
+  }
+  // node c_s (1-based)
+  __host__ __device__ static constexpr double c(int s) {
+    return s == 2 ? c2 : s == 3 ? c3 : s == 4 ? c4 : s == 5 ? c5 : s >= 6 ? 1.0 : 0.0;
+  }
 };
 
 // Work item of the FFT kernels: (instance, item index within the instance).

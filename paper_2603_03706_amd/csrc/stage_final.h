@@ -136,6 +136,15 @@ __device__ __forceinline__ void plan_step(InstCtl* C, double dt) {
   C->clipped = clipped;
 }
 
+// replayed step (adaptive runs): the logged size, negative when the step
+// was clipped onto the end time; the host keeps replay_idx below the log's
+// filled length
+__device__ __forceinline__ void plan_replay(const InstDesc& D, InstCtl* C) {
+  const double hs = gbl(D.hlog)[C->replay_idx];
+  C->h = fabs(hs);
+  C->clipped = hs < 0.0 ? 1 : 0;
+}
+
 // Operator-split cavity step (the co-simulation scheme of Sec. III B): one
 // RK4 step of the cavity ODE over C->h from C->a with m^- held at mh, into
 // C->as, which then feeds every LLG stage of the step.  The stage
@@ -274,13 +283,32 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
       C->trace_t0 = C->t;
       record_sample(D, C, C->t, C->a, C->mm1);
     }
-    plan_step(C, C->dt);
+    if (C->replay) plan_replay(D, C);
+    else plan_step(C, C->dt);
     const double hh = C->h;
     for (int n = 0; n < N; ++n) {
       C->as[n][0] = C->a[n][0] + hh * P::a21 * C->ka[0][n][0];
       C->as[n][1] = C->a[n][1] + hh * P::a21 * C->ka[0][n][1];
     }
     return;
+  }
+  // recording for the adjoint: the cavity stage inputs of the step (stage 1:
+  // the step-start amplitude) and the step's start time
+  if (C->rec_index >= 0 && ST >= 2 && ST <= 6) {
+    const int ri = C->rec_index;
+    MMG double* ra = gbl(D.rec_a) + ((size_t)ri * 6 + (ST - 1)) * N * 2;
+    for (int n = 0; n < N; ++n) {
+      ra[2 * n] = C->as[n][0];
+      ra[2 * n + 1] = C->as[n][1];
+    }
+    if (ST == 2) {
+      MMG double* r1 = gbl(D.rec_a) + (size_t)ri * 6 * N * 2;
+      for (int n = 0; n < N; ++n) {
+        r1[2 * n] = C->a[n][0];
+        r1[2 * n + 1] = C->a[n][1];
+      }
+      gbl(D.rec_t)[ri] = C->t;
+    }
   }
   if (ST == 2) {
     // ka2 at (a2, m^-(m2)) [m2 sums in the DMM slot], then ka3 at (a3, m^-(m3))
@@ -330,8 +358,10 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
   }
   const double eps = err / C->tol;
   const bool finite = isfinite(eps);
-  double fac;
-  if (finite && eps <= 1.0) {
+  double fac = 1.0;
+  // a replayed step is accepted whatever its error: the logged sequence
+  // holds only accepted steps
+  if (C->replay || (finite && eps <= 1.0)) {
     // trace: samples in (t, t + h]
     if (C->trace_on) {
       const double t0 = C->t;
@@ -351,6 +381,12 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
         C->trace_n = q + 1;
       }
     }
+    if (C->hlog_on) {
+      if (C->hlog_n < D.hlog_cap) gbl(D.hlog)[C->hlog_n] = C->clipped ? -h : h;
+      C->hlog_n += 1;
+    }
+    if (C->rec_index >= 0) C->rec_index += 1;
+    if (C->replay) C->replay_idx += 1;
     C->t = C->clipped ? C->t_end : C->t + h;
     C->accepted += 1;
     C->dt_min_seen = fmin(C->dt_min_seen, h);
@@ -366,6 +402,19 @@ __device__ void finalize(const InstDesc& D, InstCtl* C, const double* tot) {
     const int s0 = C->slot[0];
     C->slot[0] = C->slot[6];
     C->slot[6] = s0;
+    if (C->replay) {
+      if (C->replay_idx >= C->replay_end || C->t >= C->t_end) {
+        C->done = 1;
+      } else {
+        plan_replay(D, C);
+        const double hh = C->h;
+        for (int n = 0; n < N; ++n) {
+          C->as[n][0] = C->a[n][0] + hh * P::a21 * C->ka[0][n][0];
+          C->as[n][1] = C->a[n][1] + hh * P::a21 * C->ka[0][n][1];
+        }
+      }
+      return;
+    }
     const double fmx = C->last_rejected ? 1.0 : 5.0;
     fac = (eps == 0.0) ? 5.0 : 0.9 * pow(eps, -0.2);
     fac = fmin(fmx, fmax(0.2, fac));

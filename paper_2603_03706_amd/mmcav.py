@@ -86,6 +86,8 @@ _SIGS = {
     "mm_batch_tune_fft": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
     "mm_batch_get_streams": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "mm_run_record": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int32]),
+    "mm_run_record_adaptive": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int32]),
+    "mm_get_step_log": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64)]),
     "mm_adjoint": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "mm_demag_tensor": (ctypes.c_int, [ctypes.c_double] * 6 + [_P]),
     "mm_last_error": (ctypes.c_char_p, []),
@@ -255,6 +257,20 @@ class Context:
     def run_record(self, T, checkpoint_every=256):
         _check(self._lib.mm_run_record(self.h, float(T), int(checkpoint_every)))
 
+    def run_record_adaptive(self, T, tol, checkpoint_every=256):
+        """DP45 run of T at tol keeping its accepted step sizes, with
+        checkpoints along their replay, for a later adjoint."""
+        _check(self._lib.mm_run_record_adaptive(self.h, float(T), float(tol), int(checkpoint_every)))
+
+    def step_log(self):
+        """Accepted step sizes of the last adaptive recorded run (negative:
+        clipped onto the end time)."""
+        n = ctypes.c_int64(0)
+        _check(self._lib.mm_get_step_log(self.h, None, ctypes.byref(n)))
+        out = np.zeros(n.value)
+        _check(self._lib.mm_get_step_log(self.h, _ptr(out), ctypes.byref(n)))
+        return out
+
     def adjoint(self, dL_da, dL_dm=None, dL_dtrace=None):
         """Gradients of the loss of the recorded run; dL_da complex (N,) at T
         (may be None with dL_dtrace), dL_dtrace complex (steps + 1, N): the
@@ -414,18 +430,20 @@ class Batch:
 
 
 class RecordedRunFunction(torch.autograd.Function):
-    """Differentiable fixed-step RK4 run of one instance: the forward pass
-    records the run on the GPU (mm_run_record: checkpoints every
-    `checkpoint_every` steps), the backward pass is the library's discrete
-    adjoint (mm_adjoint, or mm_adjoint_trace when the trace output carries
-    a gradient).  Inputs that carry gradients: the mode profiles u (float32
+    """Differentiable run of one instance: the forward pass records the run
+    on the GPU (fixed-step RK4: mm_run_record; adaptive DP45 at inst.tol:
+    mm_run_record_adaptive, whose adjoint holds the accepted step sizes;
+    checkpoints every `checkpoint_every` steps), the backward pass is the
+    library's discrete adjoint (mm_adjoint, or mm_adjoint_trace when the
+    trace output of an RK4 run carries a gradient).  Inputs that carry
+    gradients: the mode profiles u (float32
     [N][nz][ny][nx]), the couplings g (float64 [N], rad/s), the damping alpha
     (float64 scalar) and the bias field B0 (float64 [3], T).  Outputs: a(T)
     as float64 [N][2] (real, imaginary part), m(T) as float32
     [S][3][nz][ny][nx] and, with `with_trace`, a at the start and every step
     end as float64 [steps + 1][N][2] (else an empty tensor), so that losses
     on the trace (spectra) differentiate too.  The other parameters come from
-    `inst` (workloads.Instance, method rk4).  Arguments and results are only
+    `inst` (workloads.Instance, method rk4 or dp45).  Arguments and results are only
     marshalled here; both passes run in the library's kernels."""
 
     @staticmethod
@@ -435,13 +453,18 @@ class RecordedRunFunction(torch.autograd.Function):
                                   g=g.detach().cpu().numpy().astype(np.float64),
                                   alpha=float(alpha.detach().cpu()),
                                   B0=tuple(float(v) for v in B0.detach().cpu()))
-        if run.method != "rk4":
-            raise ValueError("the discrete adjoint is built for fixed-step RK4 runs")
+        if run.method not in ("rk4", "dp45"):
+            raise ValueError("the discrete adjoint is built for RK4 runs and adaptive DP45 runs")
+        if run.method == "dp45" and with_trace:
+            raise ValueError("losses on the trace are built for fixed-step RK4 runs")
         c = Context.from_instance(run)
         steps = int(round(T / run.dt0))
         if with_trace:
             c.set_sampling(run.dt0, steps + 1)
-        c.run_record(T, checkpoint_every)
+        if run.method == "dp45":
+            c.run_record_adaptive(T, run.tol, checkpoint_every)
+        else:
+            c.run_record(T, checkpoint_every)
         a = c.get_a()
         tr = torch.zeros(0, dtype=torch.float64)
         if with_trace:

@@ -303,3 +303,99 @@ def test_adjoint_polariton_peak_and_linewidth():
     assert abs(w_g - 1.0) < 0.02
     assert abs(w_b0 - W.GAMMA / 2) < 0.02 * W.GAMMA / 2
     assert abs(G_a - wc / 2) < 0.1 * wc / 2
+
+
+# ------------------------------------------------- adaptive (DP45) adjoint
+def _check_dp45(inst, T, tol, every, mode=0, bound=1e-3):
+    """mm_run_record_adaptive + mm_adjoint against the oracle's autograd of
+    the replay of the device's own accepted steps (the adjoint of an
+    adaptive run holds its step sizes); the recorded run leaves the state of
+    a plain run of the same T bit for bit."""
+    from paper_2603_03706_amd import mmcav
+    inst = variant(inst, method="dp45")
+    plain = gpu_for(inst)
+    plain.run(T, tol)
+    ctx = gpu_for(inst)
+    print(f"dp45 adjoint grid={inst.grid} S={inst.sublattices} T={T:g} every={every}", flush=True)
+    ctx.run_record_adaptive(T, tol, every)
+    hs = ctx.step_log()
+    st = ctx.stats()
+    assert len(hs) == st["accepted"] == plain.stats()["accepted"] and st["rejected"] == plain.stats()["rejected"]
+    assert abs(np.abs(hs).sum() - T) <= 1e-12 * T and np.all(hs[:-1] > 0)
+    assert np.array_equal(ctx.get_m(), plain.get_m()) and np.array_equal(ctx.get_a(), plain.get_a())
+    aT = ctx.get_a()
+    dl = np.zeros(len(inst.omega), complex)
+    dl[mode] = 2 * aT[mode]
+    g = ctx.adjoint(dl)
+    assert np.array_equal(ctx.get_a(), aT)
+    prob = Problem(**inst.oracle_kwargs())
+
+    def loss(m, a):
+        return a[mode].real ** 2 + a[mode].imag ** 2
+
+    _, ref, status = run_with_grad(prob, inst.m0.astype(np.float64), inst.a0, inst.dt0, T, loss, steps=list(hs))
+    for k in ("u", "g", "B0", "a0"):
+        assert _rel(g[k], ref[k]) <= bound, k
+    assert abs(g["alpha"] - ref["alpha"]) <= bound * abs(ref["alpha"])
+    assert _rel(g["m0"], ref["m0"]) <= 5 * bound
+    return len(hs), st["rejected"]
+
+
+def test_adjoint_dp45_film_fft_demag():
+    """Adaptive run of the 8x6x3 multimode film (FFT demag, four profiled
+    modes) from a perturbed state, 20 ps at tol 1e-6 from dt0 = 1 ps (the
+    first attempts are rejected), checkpoints every 8 accepted steps (a
+    ragged last segment): gradients for u, g, alpha, B0, a0 and m0."""
+    inst = W.multimode_film(8, 6, 3)
+    rng = np.random.default_rng(14)
+    m0 = inst.m0.astype(np.float64).copy()
+    m0[0, 0] += 0.05 * rng.normal(size=m0.shape[2:])
+    m0[0, 1] += 0.05 * rng.normal(size=m0.shape[2:])
+    m0 /= np.linalg.norm(m0, axis=1, keepdims=True)
+    inst = variant(inst, m0=m0.astype(np.float32), a0=np.array([1.0, 0.2j, 0.0, 0.1]), alpha=0.01, dt0=1e-12)
+    steps, rejected = _check_dp45(inst, 20e-12, 1e-6, 8, mode=1)
+    assert steps > 16 and rejected >= 1
+
+
+def test_adjoint_dp45_pumped_driven_cavity():
+    """The Sim 1 geometry with the pulse and a parametric pump, adaptive over
+    0.2 ns: the cavity VJP at the stage times of every replayed step (the
+    drive and the pump depend on time) against the oracle."""
+    base = W.paper_sim1()
+    inst = variant(base, kappa=np.array([2 * math.pi * 30e6]), a0=np.array([0.02 + 0.01j]),
+                   param_lambda=np.array([2 * math.pi * 20e6 * np.exp(0.4j)]), param_wp=np.array([base.omega[0]]),
+                   dt0=0.5e-12)
+    _check_dp45(inst, 0.2e-9, 1e-7, 64, mode=0)
+
+
+def test_adjoint_dp45_afm_two_sublattices():
+    """Two sublattices (the AFM batch's material and Neel coupling) on
+    8x8x2, adaptive over 2 ps from a tilted antiparallel state."""
+    inst = W.afm_instance(2, size=8, nz=2)
+    inst = variant(inst, a0=np.array([0.2 + 0.1j]), dt0=2e-14)
+    _check_dp45(inst, 2e-12, 1e-6, 16, mode=0)
+
+
+def test_autograd_function_adaptive_run():
+    """The autograd Function on an adaptive run: its gradients are those of
+    mm_run_record_adaptive + mm_adjoint, on the inputs' own devices."""
+    from paper_2603_03706_amd import mmcav
+    inst = variant(W.paper_sim1(), method="dp45", tol=1e-7, dt0=0.5e-12, a0=np.array([0.02 + 0j]))
+    T = 50e-12
+    dev = torch.device("cuda:0")
+    u = torch.ones((1, 1, 8, 8), dtype=torch.float32, device=dev, requires_grad=True)
+    gg = torch.tensor(np.asarray(inst.g), dtype=torch.float64, device=dev, requires_grad=True)
+    al = torch.tensor(inst.alpha, dtype=torch.float64, requires_grad=True)
+    b0 = torch.tensor(np.asarray(inst.B0), dtype=torch.float64, requires_grad=True)
+    a, _ = mmcav.recorded_run(inst, T, u, gg, al, b0, 16)
+    L = (a[0] ** 2).sum()
+    L.backward()
+    assert u.grad.device == dev and gg.grad.device == dev and al.grad.device.type == "cpu"
+    ctx = gpu_for(inst)
+    ctx.run_record_adaptive(T, inst.tol, 16)
+    aT = ctx.get_a()
+    g = ctx.adjoint(np.array([2 * aT[0]]))
+    assert np.allclose(a.detach().cpu().numpy()[0], [aT[0].real, aT[0].imag], rtol=0, atol=0)
+    assert _rel(u.grad.cpu().numpy(), g["u"]) <= 1e-6 and _rel(gg.grad.cpu().numpy(), g["g"]) <= 1e-12
+    assert abs(float(al.grad) - g["alpha"]) <= 1e-12 * abs(g["alpha"])
+    assert _rel(b0.grad.numpy(), g["B0"]) <= 1e-12
