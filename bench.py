@@ -82,10 +82,17 @@ def parse():
     ap.add_argument("--film-steps", type=int, default=100)
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for rocprofv3 --pmc: a marker copy, the per-kernel profile phase, a marker copy")
+    ap.add_argument("--probe", choices=("sweep", "film", "afm"), default="sweep",
+                    help="workload of --pmc-probe and --leg-trace")
+    ap.add_argument("--leg-trace", action="store_true",
+                    help="for rocprofv3 --kernel-trace: the --probe workload's timed steps and its per-kernel "
+                         "profile phase between marker kernels, one JSON line")
+    ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("KERNEL_TRACE_CSV", "BENCH_JSON", "COMMAND"),
                     help="write the per-phase kernel time summary of a rocprofv3 --kernel-trace run (markdown)")
     ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PROBE_JSON"),
                     help="write the HBM-traffic summary of two --pmc runs of --pmc-probe (markdown, stdout)")
+    ap.add_argument("--command", default=None, help="command line quoted in a summary (--summarize-pmc)")
     return ap.parse_args()
 
 
@@ -141,6 +148,71 @@ def profile_name(kernel):
     return None
 
 
+WORKLOADS = {
+    "sweep": "field sweep, 64 x 32^3 spheres, FFT demag on 64^3, DP45 tol 1e-6",
+    "film": "multimode film, 128 x 128 x 32 cells at 5 nm, FFT demag on 256 x 256 x 64, 4 profiled modes, "
+            "DP45 tol 1e-6",
+    "afm": "AFM batch, 32 instances of 64^2 x 16 .. 256^2 x 16 at 2 nm, 2 sublattices, no demag, DP45 tol 1e-6",
+}
+
+
+def leg_batch(name, tol, instances=64):
+    """Contexts and batch of one benchmark workload (see WORKLOADS)."""
+    from paper_2603_03706_amd import mmcav, workloads as W
+    if name == "sweep":
+        return build_batch(instances, tol)
+    insts = [W.multimode_film()] if name == "film" else [W.afm_instance(k) for k in range(32)]
+    ctxs = [mmcav.Context.from_instance(i) for i in insts]
+    return insts, ctxs, mmcav.Batch(ctxs)
+
+
+def leg_trace(args):
+    """The --probe workload for a kernel trace: tuned batch, warm-up, the
+    timed steps between two marker kernels, then the per-kernel profile
+    phase between two more; one JSON line with the bench fields the trace
+    summary quotes."""
+    import torch
+    insts, ctxs, batch = leg_batch(args.probe, args.tol, args.instances)
+    tuning = batch.tune()
+    cells = sum(i.cells * i.sublattices for i in insts)
+    dt, acc = timed_steps(batch, ctxs, args.steps, args.tol, args.warmup, marks=True)
+    mark()
+    prof = batch.profile(args.profile_steps, args.tol)
+    mark()
+    kernels = []
+    for p in prof:
+        avg_ms = p["total_ms"] / max(1, p["launches"])
+        kernels.append({"name": p["name"], "launches": p["launches"], "avg_us": avg_ms * 1e3,
+                        "bytes_per_launch": p["bytes_per_launch"],
+                        "GBps": p["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0})
+    kernels.sort(key=lambda k: -k["avg_us"] * k["launches"])
+    print(json.dumps({"probe": args.probe, "steps": args.steps, "ms_per_step": dt / args.steps * 1e3,
+                      "value": cells / len(insts) * acc / dt, "unit": "cell-updates/s",
+                      "config": {"streams": batch.streams(), "fft_tiles": tile_key(tuning)}, "kernels": kernels}))
+
+
+def stream_copy(gib=1.0, reps=20):
+    """Achievable HBM bandwidth: an elementwise float32 copy of `gib` GiB
+    (read + write counted), the median of `reps` timed copies."""
+    import torch
+    n = int(gib * (1 << 30) / 4)
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    times.sort()
+    t = times[len(times) // 2]
+    return {"bytes": 8 * n, "seconds": t, "GBps": 8 * n / t / 1e9}
+
+
 def mark():
     """A tiny elementwise kernel between two synchronisations: marks phase
     boundaries (timed steps, per-kernel profile) in a kernel trace."""
@@ -183,7 +255,7 @@ def summarize_trace(trace_csv, bench_json, command):
         span = (rows[hi][0] - rows[lo][1]) / 1e3
         print(f"\nPhase wall time between the markers: {span / 1e3:.2f} ms; summed kernel time {tot / 1e3:.2f} ms.\n")
 
-    print("# Kernel time: field sweep, 64 x 32^3 spheres, FFT demag on 64^3, DP45 tol 1e-6\n")
+    print(f"# Kernel time: {WORKLOADS[out.get('probe', 'sweep')]}\n")
     print("Command (from the repository root, one MI355X):\n")
     print("```\n" + command + "\n```\n")
     print(f"Bench line of this run: {out['ms_per_step']:.4f} ms per step, value {out['value']:.4g} "
@@ -208,12 +280,18 @@ def pmc_probe(args):
     passes in the stage kernels) rather than timed again, since counter
     collection distorts the tuner's timings."""
     import torch
-    insts, ctxs, batch = build_batch(args.instances, args.tol)
-    batch.set_fft_path("reg8")
-    batch.set_fft_x("stage")
-    nx = insts[0].grid[0]
-    tuning = [{"grid": list(insts[0].grid), "Wx": max(1, min(16, 1024 // padded(nx))), "x_stage": True,
-               "path": "reg8", "Wy": None, "TW": None, "TK": None}]
+    insts, ctxs, batch = leg_batch(args.probe, args.tol, args.instances)
+    if args.probe == "sweep":
+        batch.set_fft_path("reg8")
+        batch.set_fft_x("stage")
+        nx = insts[0].grid[0]
+        tuning = [{"grid": list(insts[0].grid), "Wx": max(1, min(16, 1024 // padded(nx))), "x_stage": True,
+                   "path": "reg8", "Wy": None, "TW": None, "TK": None}]
+    else:
+        # the film's and the AFM batch's choices are timed here too (their
+        # summaries are for reading, not for the JSON line's traffic)
+        tuning = tile_key(batch.tune(streams=False))
+        tuning = tuning if tuning else None
     batch.step(3, args.tol)
     src = torch.ones(MARKER_ELEMS, device="cuda")
     dst = torch.empty_like(src)
@@ -224,8 +302,8 @@ def pmc_probe(args):
     torch.cuda.synchronize()
     torch.mul(src, 2.0, out=dst)
     torch.cuda.synchronize()
-    print(json.dumps({"tiles": tile_key(tuning), "sources": source_hash(), "steps": args.profile_steps,
-                      "marker_bytes": 4 * MARKER_ELEMS}))
+    print(json.dumps({"probe": args.probe, "tiles": tile_key(tuning) if args.probe == "sweep" else tuning,
+                      "sources": source_hash(), "steps": args.profile_steps, "marker_bytes": 4 * MARKER_ELEMS}))
 
 
 def read_counters(path):
@@ -245,7 +323,7 @@ def read_counters(path):
     return rows[lo][3], rows[hi][3], per
 
 
-def summarize_pmc(fetch_csv, write_csv, probe_json):
+def summarize_pmc(fetch_csv, write_csv, probe_json, args_command=None):
     with open(probe_json) as f:
         probe = json.loads(f.read().strip().splitlines()[-1])
     mb = probe["marker_bytes"]
@@ -253,19 +331,25 @@ def summarize_pmc(fetch_csv, write_csv, probe_json):
     w0, w1, write = read_counters(write_csv)
     ff = mb / (0.5 * (f0 + f1) * 1024.0)
     fw = mb / (0.5 * (w0 + w1) * 1024.0)
-    print("# HBM traffic per launch: field sweep, 64 x 32^3 spheres, FFT demag on 64^3, DP45 tol 1e-6\n")
+    name = probe.get("probe", "sweep")
+    print(f"# HBM traffic per launch: {WORKLOADS[name]}\n")
     print("Commands (from the repository root, one MI355X; each counter in a run of its own):\n")
     print("```")
-    print("rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch -o fetch -- python3 bench.py --pmc-probe > gpurun_out/probe.json")
-    print("rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write -o write -- python3 bench.py --pmc-probe")
-    print("python3 bench.py --summarize-pmc gpurun_out/pmc_fetch/fetch_counter_collection.csv "
-          "gpurun_out/pmc_write/write_counter_collection.csv gpurun_out/probe.json")
+    if args_command:
+        print(args_command)
+    else:
+        print(f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_fetch_{name} -o fetch -- "
+              f"python3 bench.py --pmc-probe --probe {name} > gpurun_out/probe_{name}.json")
+        print(f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_write_{name} -o write -- "
+              f"python3 bench.py --pmc-probe --probe {name}")
+        print(f"python3 bench.py --summarize-pmc gpurun_out/pmc_fetch_{name}/fetch_counter_collection.csv "
+              f"gpurun_out/pmc_write_{name}/write_counter_collection.csv gpurun_out/probe_{name}.json")
     print("```\n")
     print(f"Calibration: an elementwise float32 copy of {mb} bytes (read {mb}, write {mb}) reads "
           f"FETCH_SIZE {f0:.0f} / {f1:.0f} KiB and WRITE_SIZE {w0:.0f} / {w1:.0f} KiB; scale factors "
           f"{ff:.4f} (fetch) and {fw:.4f} (write).\n")
     print(f"Kernels between the two markers (the per-kernel profile phase: {probe['steps']} eager DP45 steps "
-          "of the whole batch), per dispatch:\n")
+          f"of the whole batch; tiles {json.dumps(probe.get('tiles'))}), per dispatch:\n")
     print("| kernel | dispatches | FETCH KiB | WRITE KiB | HBM bytes (scaled) |")
     print("|---|---|---|---|---|")
     out = {}
@@ -545,7 +629,7 @@ def main():
         summarize_trace(*args.summarize_trace)
         return
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc)
+        summarize_pmc(*args.summarize_pmc, args_command=args.command)
         return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -557,6 +641,9 @@ def main():
     torch.cuda.set_device(0)
     if args.pmc_probe:
         pmc_probe(args)
+        return
+    if args.leg_trace:
+        leg_trace(args)
         return
 
     insts, ctxs, batch = build_batch(args.instances, args.tol)
@@ -607,6 +694,14 @@ def main():
         roof.update({"traffic": None if traffic is None else round(traffic), "kernel": top["name"],
                      "avg_us": round(top["avg_us"], 2), "bytes_per_launch": top["bytes_per_launch"]})
         print(f"[bench] profile: {json.dumps(kernels)}", file=sys.stderr, flush=True)
+
+    stream = None
+    if not args.no_stream:
+        # the achievable HBM bandwidth on this GPU, beside the 8 TB/s peak
+        stream = stream_copy()
+        if roof is not None:
+            roof["hbm"]["achievable"] = round(stream["GBps"], 1)
+        print(f"[bench] stream copy: {json.dumps(stream)}", file=sys.stderr, flush=True)
 
     speedup = None
     if not args.no_plain:
@@ -672,6 +767,7 @@ def main():
         "afm_batch": afm,
         "film": film,
         "paper_sweep": sweep41,
+        "stream_copy": stream,
         "kernels": kernels,
     }
     print(json.dumps(out))
