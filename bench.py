@@ -276,17 +276,17 @@ def summarize_trace(trace_csv, bench_json, command):
 def pmc_probe(args):
     """Between two marker copies: the per-kernel profile phase of the
     benchmark (the whole batch, eager launches).  The FFT strategy is fixed
-    to the one the tuner picks on this workload (eight-lane y-z kernel, x
+    to the one the tuner picks on this workload (two-pass exchange y-z kernel, x
     passes in the stage kernels) rather than timed again, since counter
     collection distorts the tuner's timings."""
     import torch
     insts, ctxs, batch = leg_batch(args.probe, args.tol, args.instances)
     if args.probe == "sweep":
-        batch.set_fft_path("reg8")
+        batch.set_fft_path("xch")
         batch.set_fft_x("stage")
         nx = insts[0].grid[0]
         tuning = [{"grid": list(insts[0].grid), "Wx": max(1, min(16, 1024 // padded(nx))), "x_stage": True,
-                   "path": "reg8", "Wy": None, "TW": None, "TK": None}]
+                   "path": "xch", "Wy": None, "TW": None, "TK": None}]
     else:
         # the film's and the AFM batch's choices are timed here too (their
         # summaries are for reading, not for the JSON line's traffic)

@@ -154,9 +154,25 @@ bool reg_fits(int ny, int nz, int py, int pz) {
   return y_ok && z_ok && reg_lds(nz, py, pz) <= 160 * 1024;
 }
 
-enum { PATH_FUSED = MM_YZ_FUSED, PATH_REG = MM_YZ_REGISTER, PATH_SPLIT = MM_YZ_SPLIT, PATH_REG8 = MM_YZ_REGISTER8 };
+enum {
+  PATH_FUSED = MM_YZ_FUSED,
+  PATH_REG = MM_YZ_REGISTER,
+  PATH_SPLIT = MM_YZ_SPLIT,
+  PATH_REG8 = MM_YZ_REGISTER8,
+  PATH_XCH = MM_YZ_EXCHANGE
+};
 // eight lanes per z column: padded z of 32 or 64
 bool reg8_fits(int ny, int nz, int py, int pz) { return reg_fits(ny, nz, py, pz) && (pz == 32 || pz == 64); }
+// two register passes per line with an LDS exchange: padded y of 16..128, padded z of 32 or 64
+size_t xch_lds(int py, int pz) {
+  return sizeof(float2) * ((size_t)3 * (pz / 2) * (py + mmk_yzx_pad()) + py + pz) +
+         sizeof(float) * 6 * (size_t)(pz / 2 + 1) * (py / 2 + 1);
+}
+bool xch_fits(int ny, int nz, int py, int pz) {
+  (void)ny, (void)nz;
+  const bool y_ok = py == 16 || py == 32 || py == 64 || py == 128;
+  return y_ok && (pz == 32 || pz == 64) && xch_lds(py, pz) <= 160 * 1024;
+}
 
 // x passes with lines in registers (selected by a tile width Wx of 0): padded x of 16..128
 bool xreg_fits(int px) { return px == 16 || px == 32 || px == 64 || px == 128; }
@@ -170,7 +186,7 @@ size_t xfuse_lds(int nx) {
   return sizeof(float2) * ((size_t)3 * Px * (J + 1) + Px);
 }
 const char* path_name(int p) {
-  return p == PATH_REG ? "reg" : p == PATH_REG8 ? "reg8" : p == PATH_SPLIT ? "split" : "fused";
+  return p == PATH_REG ? "reg" : p == PATH_REG8 ? "reg8" : p == PATH_XCH ? "xch" : p == PATH_SPLIT ? "split" : "fused";
 }
 
 Layout make_layout(const mm_params& p, int n_modes) {
@@ -612,8 +628,9 @@ mm_status build_group(mm_batch::Group& g, DevArena* arena = nullptr) {
   if (mm_status s = up(zc, &g.zc, &g.n_zc)) return s;
   g.lds_xf = g.Wx == 0 ? 0 : sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + g.px);
   g.lds_xi = g.Wx == 0 ? 0 : sizeof(float2) * ((size_t)g.px * (g.Wx + 1) + (size_t)g.kx * 2 * g.Wx + g.px);
-  g.lds_yz = (g.path == PATH_REG || g.path == PATH_REG8) ? reg_lds(g.nz, g.py, g.pz)
-                                                         : fused_lds(g.ny, g.nz, g.py, g.pz, g.TK);
+  g.lds_yz = g.path == PATH_XCH                             ? xch_lds(g.py, g.pz)
+             : (g.path == PATH_REG || g.path == PATH_REG8) ? reg_lds(g.nz, g.py, g.pz)
+                                                           : fused_lds(g.ny, g.nz, g.py, g.pz, g.TK);
   g.lds_y = sizeof(float2) * ((size_t)g.py * (g.Wy + 1) + g.py);
   g.lds_zc = sizeof(float2) * ((size_t)g.pz * 3 * g.TW + g.pz);
   return MM_OK;
@@ -717,8 +734,9 @@ mm_status batch_build(mm_batch* b, DevArena* arena = nullptr) {
       g = &b->groups.back();
       g->nx = c->p.nx; g->ny = c->p.ny; g->nz = c->p.nz;
       g->px = c->L.px; g->py = c->L.py; g->pz = c->L.pz; g->kx = c->L.kx;
-      g->path = reg8_fits(g->ny, g->nz, g->py, g->pz) ? PATH_REG8
-                : reg_fits(g->ny, g->nz, g->py, g->pz) ? PATH_REG
+      g->path = xch_fits(g->ny, g->nz, g->py, g->pz)    ? PATH_XCH
+                : reg8_fits(g->ny, g->nz, g->py, g->pz) ? PATH_REG8
+                : reg_fits(g->ny, g->nz, g->py, g->pz)  ? PATH_REG
                 : c->L.split                           ? PATH_SPLIT
                                                        : PATH_FUSED;
     }
@@ -807,10 +825,11 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1, bool fwd = true
           return mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, method, stage, g_twiddle, b->stream);
         }))
       return s;
-    if (g.path == PATH_REG8) {
+    if (g.path == PATH_REG8 || g.path == PATH_XCH) {
       if (mm_status s = launch(b, "fft_yz_convolve", [&] {
-            return mmk_launch_fft_yz8(g.py / 4, g.pz / 4, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream,
-                                      first ? nfinal : 0, b->method, final_st);
+            auto f = g.path == PATH_XCH ? mmk_launch_fft_yzx : mmk_launch_fft_yz8;
+            return f(g.py / 4, g.pz / 4, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream,
+                     first ? nfinal : 0, b->method, final_st);
           }))
         return s;
     } else if (g.path == PATH_REG) {
@@ -908,7 +927,9 @@ mm_status enqueue_start(mm_batch* b) {
 // workgroups of the next stage's first y-z launch when that launch is the
 // eight-lane kernel: the transform reads only X, which the finalisation does
 // not touch, and the next stage kernel comes after both in stream order.
-bool merge_final(const mm_batch* b) { return !b->groups.empty() && b->groups[0].path == PATH_REG8; }
+bool merge_final(const mm_batch* b) {
+  return !b->groups.empty() && (b->groups[0].path == PATH_REG8 || b->groups[0].path == PATH_XCH);
+}
 
 mm_status enqueue_step(mm_batch* b) {
   const int s0 = b->method == MM_RK4 ? 1 : 2;
@@ -2316,7 +2337,7 @@ mm_status mm_batch_end(mm_batch* b) {
 }
 
 static mm_status check_fft_path(const mm_batch* b, int32_t path) {
-  if (path != PATH_FUSED && path != PATH_REG && path != PATH_SPLIT && path != PATH_REG8)
+  if (path != PATH_FUSED && path != PATH_REG && path != PATH_SPLIT && path != PATH_REG8 && path != PATH_XCH)
     return fail(MM_ERR_ARG, "unknown y-z path");
   for (const mm_batch* p : b->parts)
     if (mm_status s = check_fft_path(p, path)) return s;
@@ -2325,6 +2346,8 @@ static mm_status check_fft_path(const mm_batch* b, int32_t path) {
       return fail(MM_ERR_ARG, "register y-z path needs padded y in 16..128 and padded z in 16..64");
     if (path == PATH_REG8 && !reg8_fits(g.ny, g.nz, g.py, g.pz))
       return fail(MM_ERR_ARG, "eight-lane register y-z path needs padded y in 16..128 and padded z of 32 or 64");
+    if (path == PATH_XCH && !xch_fits(g.ny, g.nz, g.py, g.pz))
+      return fail(MM_ERR_ARG, "exchange y-z path needs padded y in 16..128 and padded z of 32 or 64");
     if (path == PATH_FUSED && !fused_fits(g.ny, g.nz, g.py, g.pz))
       return fail(MM_ERR_ARG, "fused y-z path does not fit in LDS for this grid");
   }
@@ -2660,6 +2683,17 @@ static mm_status tune_fft(mm_batch* b, std::string& out) {
         return s;
       yrep += (yrep.empty() ? "" : ", ") + std::string("\"reg8\": ") + std::to_string(us);
       if (us < bestYZ) { bestYZ = us; bestPath = PATH_REG8; }
+    }
+    if (xch_fits(g.ny, g.nz, g.py, g.pz)) {
+      g.path = PATH_XCH;
+      if (mm_status s = build_group(g)) return s;
+      double us;
+      if (mm_status s = timed([&] {
+            return mmk_launch_fft_yzx(g.py / 4, g.pz / 4, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
+          }, &us))
+        return s;
+      yrep += (yrep.empty() ? "" : ", ") + std::string("\"xch\": ") + std::to_string(us);
+      if (us < bestYZ) { bestYZ = us; bestPath = PATH_XCH; }
     }
     for (int Wy = 4; Wy <= 64; Wy *= 2) {
       if (sizeof(float2) * ((size_t)g.py * (Wy + 1) + g.py) > lds_cap) continue;

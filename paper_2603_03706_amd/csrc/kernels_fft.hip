@@ -843,6 +843,319 @@ __global__ __launch_bounds__(MM_YZ8_T) __attribute__((amdgpu_waves_per_eu(4, 4))
   }
 }
 
+// ------------------------- fused y-z, two register passes per line (T = 512)
+// A padded line of length P = L Q whose inputs vanish from P/2 on is
+// transformed by L lanes.  With n = L n1 + lam and k = k1 + Q k2,
+//   X[k1 + Q k2] = sum_lam W_L^{lam k2} W_P^{lam k1} sum_{n1 < Q/2} x[L n1 + lam] W_Q^{n1 k1}:
+// lane lam takes the Q-point DFT of its own decimated sequence (whose upper
+// half is zero) and scales it by W_P^{lam k1}; after an exchange through LDS
+// lane mu takes the L-point DFTs of k1 = mu + L j, j < Q/L.  The inverse
+// runs the same factorisation backwards with n = n1 + L n2: L-point inverse
+// DFTs over k2 for each k1 of the lane, the conjugate scale W_P^{-n1 k1},
+// exchange, and the Q-point inverse DFTs of which only the outputs n2 < Q/2
+// (n < P/2, the cropped half) are formed.  All lanes of a line sit in one
+// wavefront, whose LDS accesses complete in program order, so the exchange
+// needs no workgroup barrier; the line's own LDS storage is the exchange
+// area (a y row holds P slots, a z column of the three components 3P/2).
+// One workgroup per (instance, kx):
+//   load X -> LDS rows [3][Pz/2][Py + pad];  forward y per row (in place);
+//   per ky column: forward z of the three components, kernel multiply,
+//   inverse z (in place);  inverse y per row (in place);  store X.
+#define MM_YZX_T 512
+
+// points per lane Q and lanes per line L of a padded length P (Q >= L):
+// y rows take up to sixteen points per lane, z columns eight
+template <int P, int QMAX>
+struct LinePass {
+  static constexpr int Q = P / 2 < QMAX ? P / 2 : QMAX, L = P / Q;
+  static constexpr int lgQ = ilog2c(Q), lgL = ilog2c(L);
+  static_assert(Q >= L && L >= 2, "unsupported padded length");
+};
+
+// radix-2 DIF stages h = H0 .. 1 of an in-register M-point DFT (M <= 16):
+// natural order in, bit-reversed out when H0 = M/2
+template <int M, bool INV, int H0>
+__device__ __forceinline__ void dif_stages(float2 (&v)[M]) {
+#pragma unroll
+  for (int h = H0; h >= 1; h >>= 1) {
+#pragma unroll
+    for (int g = 0; g < M; g += 2 * h) {
+#pragma unroll
+      for (int i = 0; i < h; ++i) {
+        const float2 a = v[g + i], b = v[g + i + h];
+        v[g + i] = cadd(a, b);
+        v[g + i + h] = twc<M, INV>(csub(a, b), i * (M / (2 * h)));
+      }
+    }
+  }
+}
+// the same DFT of a sequence whose entries M/2 .. M-1 are zero (not read):
+// the first stage has nothing to add and only scales
+template <int M, bool INV>
+__device__ __forceinline__ void dif_half(float2 (&v)[M]) {
+#pragma unroll
+  for (int i = 0; i < M / 2; ++i) v[i + M / 2] = twc<M, INV>(v[i], i);
+  if constexpr (M >= 4) dif_stages<M, INV, M / 4>(v);
+}
+
+// exchange slot of value k1 from / for lane a: groups of L slots, rotated by
+// k1 so that a write of fixed k1 and a read of fixed a both spread over L
+// groups (and so over LDS banks)
+template <int L>
+__device__ __forceinline__ int xslot(int k1, int a) {
+  return k1 * L + ((a + k1) & (L - 1));
+}
+
+// order the wavefront's LDS accesses across lanes (no instruction: a
+// wavefront's LDS operations already complete in issue order)
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+
+template <int MY, int MZ, int RPAD>
+__global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 32 ? 2 : 4, MY >= 32 ? 2 : 4))) void k_fft_yzx(
+    const InstDesc* __restrict__ descs, const WorkItem* __restrict__ work, const float2* __restrict__ tw,
+    int nyz, int fmethod, int fstage) {
+  constexpr int PY = 4 * MY, PZ = 4 * MZ, RS = PY + RPAD, ZR = 2 * MZ, YR = 2 * MY;
+  using LY = LinePass<PY, 16>;
+  using LZ = LinePass<PZ, 8>;
+  constexpr int QY = LY::Q, NY = LY::L, QZ = LZ::Q, NZ = LZ::L;
+  constexpr int lgPY = ilog2c(PY);
+  constexpr int RPW = 64 / NY;                  // y rows per wavefront
+  constexpr int NW = MM_YZX_T / 64;             // wavefronts per workgroup
+  extern __shared__ float2 lds[];
+  if ((int)blockIdx.x >= nyz) {
+    final_any(fmethod, fstage, descs, (int)blockIdx.x - nyz, reinterpret_cast<double*>(lds));
+    return;
+  }
+  float2* B = lds;
+  float2* twy = B + 3 * ZR * RS;
+  float2* twz = twy + PY;
+  float* Ks = reinterpret_cast<float*>(twz + PZ);
+  constexpr int HY1 = PY / 2 + 1, KPL = (PZ / 2 + 1) * HY1;
+  constexpr int NK = (6 * KPL + MM_YZX_T - 1) / MM_YZX_T, NXE = 3 * ZR * PY;
+  constexpr int NX = (NXE + MM_YZX_T - 1) / MM_YZX_T;
+  load_twiddles(twy, PY, tw, MM_YZX_T);
+  load_twiddles(twz, PZ, tw, MM_YZX_T);
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (gbl(D.ctl)->done) return;
+  const int kx = wi.item;
+  const int ny = D.ny, nz = D.nz;
+  const int nrow = 3 * nz;
+  MMG float2* X = gbl(D.fx) + (size_t)kx * nrow * ny;
+  {
+    const MMG float* K = gbl(D.kern) + (size_t)kx * 6 * KPL;
+    float kv[NK];
+    float2 xv[NX];
+#pragma unroll
+    for (int it = 0; it < NK; ++it) kv[it] = K[min(it * MM_YZX_T + (int)threadIdx.x, 6 * KPL - 1)];
+#pragma unroll
+    for (int it = 0; it < NX; ++it) {
+      const int e = it * MM_YZX_T + threadIdx.x;
+      const int row = e >> lgPY, y = e & (PY - 1);
+      const int c = row / ZR, z = row - c * ZR;
+      const bool in = e < NXE && z < nz && y < ny;
+      const float2 v = gld2(X + (min(c, 2) * nz + min(z, nz - 1)) * ny + min(y, ny - 1));
+      xv[it] = make_float2(in ? v.x : 0.f, in ? v.y : 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < NK; ++it) {
+      const int e = it * MM_YZX_T + threadIdx.x;
+      if (e < 6 * KPL) Ks[e] = kv[it];
+    }
+#pragma unroll
+    for (int it = 0; it < NX; ++it) {
+      const int e = it * MM_YZX_T + threadIdx.x;
+      const int row = e >> lgPY, y = e & (PY - 1);
+      const int z = row % ZR;
+      if (e < NXE && (z >= nz || y < YR)) B[row * RS + y] = xv[it];
+    }
+  }
+  __syncthreads();
+  // Bank layout (64 banks of four bytes; an eight-byte access is served 32
+  // lanes per cycle): rows are Py + 1 slots apart.  A y row has NY lanes,
+  // lane = lam * RPW + r in its wavefront, and the wavefront's rows are
+  // SY = NY / 2 apart, so the 32 lanes of a half-wavefront (NY / 2 values
+  // of lam, RPW rows) fall on distinct bank pairs; the rows of SY
+  // wavefronts interleave to fill blocks of 32 rows.  A z column has NZ
+  // consecutive lanes and the wavefront's columns are SZ apart (SZ = NZ
+  // where Py allows), for the same reason.
+  constexpr int SY = NY / 2;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ylam = lane / RPW, yrl = lane % RPW;
+  float2 wfy[QY];
+#pragma unroll
+  for (int k1 = 0; k1 < QY; ++k1) wfy[k1] = twy[ylam * k1];
+  // forward y of the rows z < nz (rows z >= nz stay zero)
+  {
+#pragma unroll 1
+    for (int g0 = wave / SY; 32 * g0 < 3 * ZR; g0 += NW / SY) {
+      const int rho = 32 * g0 + wave % SY + SY * yrl;
+      if (rho < 3 * ZR && (rho & (ZR - 1)) < nz) {
+        float2* line = B + rho * RS;
+        float2 v[QY];
+#pragma unroll
+        for (int n1 = 0; n1 < QY / 2; ++n1) v[n1] = line[NY * n1 + ylam];
+        dif_half<QY, false>(v);
+        wave_lds_order();
+#pragma unroll
+        for (int p = 0; p < QY; ++p) {
+          const int k1 = brevc(p, LY::lgQ);
+          line[xslot<NY>(k1, ylam)] = k1 ? cmul(v[p], wfy[k1]) : v[p];
+        }
+        wave_lds_order();
+        float2 u[QY / NY][NY];
+#pragma unroll
+        for (int j = 0; j < QY / NY; ++j) {
+#pragma unroll
+          for (int a = 0; a < NY; ++a) u[j][a] = line[xslot<NY>(ylam + NY * j, a)];
+          dif_stages<NY, false, NY / 2>(u[j]);
+        }
+        wave_lds_order();
+#pragma unroll
+        for (int j = 0; j < QY / NY; ++j)
+#pragma unroll
+          for (int p = 0; p < NY; ++p) line[ylam + NY * j + QY * brevc(p, LY::lgL)] = u[j][p];
+      }
+    }
+  }
+  __syncthreads();
+  // z columns: NZ consecutive lanes per column, columns SZ apart
+  {
+    constexpr int CPW = 64 / NZ, SZ = NZ < PY / CPW ? NZ : PY / CPW;
+    const int lam = threadIdx.x & (NZ - 1);
+    float2 wf[QZ], wv[QZ / NZ][NZ];
+#pragma unroll
+    for (int k1 = 0; k1 < QZ; ++k1) wf[k1] = twz[lam * k1];
+#pragma unroll
+    for (int j = 0; j < QZ / NZ; ++j)
+#pragma unroll
+      for (int n1 = 0; n1 < NZ; ++n1) wv[j][n1] = conjf2(j == 0 ? wf[n1] : twz[n1 * (lam + NZ * j)]);
+#pragma unroll 1
+    for (int t = threadIdx.x; t < NZ * PY; t += MM_YZX_T) {
+      const int wz = t >> 6, ky = wz % SZ + SZ * ((t & 63) >> LZ::lgL) + SZ * CPW * (wz / SZ);
+      float2* col = B + ky;
+      float2 xin[3][QZ / 2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int n1 = 0; n1 < QZ / 2; ++n1) xin[c][n1] = col[(c * ZR + NZ * n1 + lam) * RS];
+      float2 sp[3][QZ / NZ][NZ];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float2 v[QZ];
+#pragma unroll
+        for (int n1 = 0; n1 < QZ / 2; ++n1) v[n1] = xin[c][n1];
+        dif_half<QZ, false>(v);
+        wave_lds_order();
+#pragma unroll
+        for (int p = 0; p < QZ; ++p) {
+          const int k1 = brevc(p, LZ::lgQ);
+          col[xslot<NZ>(k1, lam) * RS] = k1 ? cmul(v[p], wf[k1]) : v[p];
+        }
+        wave_lds_order();
+#pragma unroll
+        for (int j = 0; j < QZ / NZ; ++j) {
+#pragma unroll
+          for (int a = 0; a < NZ; ++a) sp[c][j][a] = col[xslot<NZ>(lam + NZ * j, a) * RS];
+          dif_stages<NZ, false, NZ / 2>(sp[c][j]);
+        }
+        wave_lds_order();
+      }
+      // sp[c][j][p] = X_c[k1 + QZ brev(p)], k1 = lam + NZ j
+#pragma unroll
+      for (int j = 0; j < QZ / NZ; ++j)
+#pragma unroll
+        for (int p = 0; p < NZ; ++p)
+          kernel_mul_lds<PY, PZ>(Ks, ky, lam + NZ * j + QZ * brevc(p, LZ::lgL), sp[0][j][p], sp[1][j][p],
+                                 sp[2][j][p]);
+      float2 res[3][QZ / 2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int j = 0; j < QZ / NZ; ++j) {
+          float2 g[NZ];
+#pragma unroll
+          for (int k2 = 0; k2 < NZ; ++k2) g[k2] = sp[c][j][brevc(k2, LZ::lgL)];
+          dif_stages<NZ, true, NZ / 2>(g);
+          // g[p] = sum_k2 X[k1 + QZ k2] W_NZ^{-n1 k2} at n1 = brev(p)
+#pragma unroll
+          for (int n1 = 0; n1 < NZ; ++n1) {
+            const float2 zv = g[brevc(n1, LZ::lgL)];
+            col[xslot<NZ>(lam + NZ * j, n1) * RS] = n1 == 0 ? zv : cmul(zv, wv[j][n1]);
+          }
+        }
+        wave_lds_order();
+        float2 v[QZ];
+#pragma unroll
+        for (int k1 = 0; k1 < QZ; ++k1) v[k1] = col[xslot<NZ>(k1, lam) * RS];
+        dif_stages<QZ, true, QZ / 2>(v);
+#pragma unroll
+        for (int n2 = 0; n2 < QZ / 2; ++n2) res[c][n2] = v[brevc(n2, LZ::lgQ)];
+        wave_lds_order();
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int n2 = 0; n2 < QZ / 2; ++n2) {
+          const int z = lam + NZ * n2;
+          if (z < nz) col[(c * ZR + z) * RS] = res[c][n2];
+        }
+    }
+  }
+  __syncthreads();
+  // inverse y of the rows z < nz, cropped to y < Py/2
+  {
+    float2 wv[QY / NY][NY];
+#pragma unroll
+    for (int j = 0; j < QY / NY; ++j)
+#pragma unroll
+      for (int n1 = 0; n1 < NY; ++n1) wv[j][n1] = conjf2(j == 0 ? wfy[n1] : twy[n1 * (ylam + NY * j)]);
+#pragma unroll 1
+    for (int g0 = wave / SY; 32 * g0 < 3 * ZR; g0 += NW / SY) {
+      const int rho = 32 * g0 + wave % SY + SY * yrl;
+      if (rho < 3 * ZR && (rho & (ZR - 1)) < nz) {
+        float2* line = B + rho * RS;
+        float2 g[QY / NY][NY];
+#pragma unroll
+        for (int j = 0; j < QY / NY; ++j) {
+#pragma unroll
+          for (int k2 = 0; k2 < NY; ++k2) g[j][k2] = line[ylam + NY * j + QY * k2];
+          dif_stages<NY, true, NY / 2>(g[j]);
+        }
+        wave_lds_order();
+#pragma unroll
+        for (int j = 0; j < QY / NY; ++j)
+#pragma unroll
+          for (int n1 = 0; n1 < NY; ++n1) {
+            const float2 zv = g[j][brevc(n1, LY::lgL)];
+            line[xslot<NY>(ylam + NY * j, n1)] = n1 == 0 ? zv : cmul(zv, wv[j][n1]);
+          }
+        wave_lds_order();
+        float2 v[QY];
+#pragma unroll
+        for (int k1 = 0; k1 < QY; ++k1) v[k1] = line[xslot<NY>(k1, ylam)];
+        dif_stages<QY, true, QY / 2>(v);
+        wave_lds_order();
+#pragma unroll
+        for (int n2 = 0; n2 < QY / 2; ++n2) line[ylam + NY * n2] = v[brevc(n2, LY::lgQ)];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int e = threadIdx.x; e < 3 * ZR * YR; e += MM_YZX_T) {
+    const int row = e >> (ilog2c(MY) + 1), y = e & (YR - 1);
+    const int c = row / ZR, z = row & (ZR - 1);
+    if (z < nz && y < ny) gst2(X + (c * nz + z) * ny + y, B[row * RS + y]);
+  }
+}
+
 // --------------------------------------------------- x passes, lines in registers
 // Work item = 128 consecutive real rows (64 complex lines) of one instance.
 // A line packs two real rows (real and imaginary part) and is split over four
@@ -1254,6 +1567,24 @@ hipError_t mmk_launch_fft_yz8(int MY, int MZ, int nblocks, size_t lds, const Ins
   return hipErrorInvalidValue;
 }
 
+#ifndef MM_YZX_PAD
+#define MM_YZX_PAD 1
+#endif
+#define MM_YZX_CASE(A, B)                                                                          \
+  if (MY == A && MZ == B) {                                                                        \
+    MM_LAUNCH((mmk::k_fft_yzx<A, B, MM_YZX_PAD>), dim3(nblocks + nfinal), dim3(MM_YZX_T), lds, s, d, w, tw, \
+              nblocks, fmethod, fstage);                                                          \
+    return hipGetLastError();                                                                      \
+  }
+hipError_t mmk_launch_fft_yzx(int MY, int MZ, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                              const float2* tw, hipStream_t s, int nfinal, int fmethod, int fstage) {
+  if (nfinal < 0 || (nfinal > 0 && lds < MMI_PSTRIDE * sizeof(double))) return hipErrorInvalidValue;
+  MM_YZX_CASE(4, 8) MM_YZX_CASE(8, 8) MM_YZX_CASE(16, 8) MM_YZX_CASE(32, 8)
+  MM_YZX_CASE(4, 16) MM_YZX_CASE(8, 16) MM_YZX_CASE(16, 16) MM_YZX_CASE(32, 16)
+  return hipErrorInvalidValue;
+}
+int mmk_yzx_pad() { return MM_YZX_PAD; }
+
 hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstDesc* d,
                             const WorkItem* w, const float2* tw, hipStream_t s) {
   if (dir < 0) MM_LAUNCH(mmk::k_fft_y<-1>, dim3(nblocks), dim3(256), lds, s, d, w, W, tw);
@@ -1283,5 +1614,11 @@ hipError_t mmk_set_lds_limits() {
                             160 * 1024);
   MM_YZ8_ATTR(4, 8) MM_YZ8_ATTR(8, 8) MM_YZ8_ATTR(16, 8) MM_YZ8_ATTR(32, 8)
   MM_YZ8_ATTR(4, 16) MM_YZ8_ATTR(8, 16) MM_YZ8_ATTR(16, 16) MM_YZ8_ATTR(32, 16)
+#define MM_YZX_ATTR(A, B)                                                                         \
+  if (e == hipSuccess)                                                                            \
+    e = hipFuncSetAttribute((const void*)mmk::k_fft_yzx<A, B, MM_YZX_PAD>,                        \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  MM_YZX_ATTR(4, 8) MM_YZX_ATTR(8, 8) MM_YZX_ATTR(16, 8) MM_YZX_ATTR(32, 8)
+  MM_YZX_ATTR(4, 16) MM_YZX_ATTR(8, 16) MM_YZX_ATTR(16, 16) MM_YZX_ATTR(32, 16)
   return e;
 }

@@ -343,7 +343,7 @@ def test_tuned_batch_keeps_parity():
     b1 = mmcav.Batch(ctxs)
     m0 = [c.get_m() for c in ctxs]
     rep = b1.tune()
-    assert len(rep) == b1.streams() and all(r["path"] in ("fused", "reg", "reg8", "split") for r in rep)
+    assert len(rep) == b1.streams() and all(r["path"] in ("fused", "reg", "reg8", "xch", "split") for r in rep)
     assert all(r["streams"] == b1.streams() and len(r["streams_ms_per_step"]) == 3 for r in rep)
     # the timed steps of the tuner leave no trace: state, counters, samples
     assert all(c.stats()["accepted"] == 0 and c.stats()["t"] == 0.0 for c in ctxs)
@@ -363,14 +363,17 @@ def test_tuned_batch_keeps_parity():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("shape", [(12, 12, 12), (10, 6, 5), (16, 6, 5), (16, 12, 9), (16, 5, 7), (32, 7, 9)])
+@pytest.mark.parametrize("shape", [(12, 12, 12), (10, 6, 5), (16, 6, 5), (16, 12, 9), (16, 5, 7), (32, 7, 9),
+                                   (8, 20, 17), (8, 40, 20)])
 def test_fft_yz_paths_agree(shape):
     """The y-z strategies of the demag convolution (LDS-fused, register lines,
-    split passes) and the x-pass strategies (LDS tiles, register lines, inside
-    the stage kernels) give the same trajectory to FP32 rounding, and the
-    oracle's within the parity bound, on a sphere and on ragged boxes (odd
-    row counts per workgroup among them: 16 x 5 x 7 and 32 x 7 x 9 leave 3
-    and 15 x-rows in the last workgroup of 512 cells)."""
+    two-pass lines with an LDS exchange, split passes) and the x-pass
+    strategies (LDS tiles, register lines, inside the stage kernels) give the
+    same trajectory to FP32 rounding, and the oracle's within the parity
+    bound, on a sphere and on ragged boxes (odd row counts per workgroup among
+    them: 16 x 5 x 7 and 32 x 7 x 9 leave 3 and 15 x-rows in the last
+    workgroup of 512 cells; 8 x 20 x 17 and 8 x 40 x 20 pad y to 64 and 128
+    and z to 64, with z rows past nz in every column)."""
     from paper_2603_03706_amd import mmcav
     if shape == (12, 12, 12):
         inst = variant(W.sweep_sphere(5, count=8, n=12), method="rk4", dt0=0.2e-12)
@@ -387,7 +390,9 @@ def test_fft_yz_paths_agree(shape):
     if shape[0] & (shape[0] - 1) == 0:       # x passes inside the stage kernels need nx = 2^k
         combos += [("reg", "stage"), ("split", "stage")]
     if shape[2] > 8:                         # eight lanes per z column need a padded z of 32 or 64
-        combos += [("reg8", "lds")] + ([("reg8", "stage")] if shape[0] & (shape[0] - 1) == 0 else [])
+        combos += [("reg8", "lds"), ("xch", "lds")]
+        if shape[0] & (shape[0] - 1) == 0:
+            combos += [("reg8", "stage"), ("xch", "stage")]
     for path, xpath in combos:
         c = gpu_for(inst)
         b = mmcav.Batch([c])
@@ -418,6 +423,8 @@ def test_fft_path_rejects_unfit_shape():
         b.set_fft_path("reg")
     with pytest.raises(mmcav.MMError):
         b.set_fft_path("reg8")
+    with pytest.raises(mmcav.MMError):
+        b.set_fft_path("xch")
     with pytest.raises(mmcav.MMError):
         b.set_fft_x("reg")
     with pytest.raises(mmcav.MMError):
