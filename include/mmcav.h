@@ -296,7 +296,8 @@ mm_status mm_batch_tune_fft(mm_batch* b, char* report, size_t report_len);
 /* Demag y-z strategy for every FFT grid shape in the batch (mm_batch_tune
  * chooses one per shape by timing; before that the exchange strategy is used
  * where it applies, else the eight-lane register one, else the register one,
- * else the fused one where it fits, else the split one):
+ * else the fused one where it fits, else the split exchange one, else the
+ * split one):
  *   MM_YZ_FUSED     y and z lines transformed in LDS by one workgroup per
  *                   (instance, kx), z in tiles of ky columns;
  *   MM_YZ_REGISTER  one workgroup per (instance, kx), each line split over
@@ -308,9 +309,19 @@ mm_status mm_batch_tune_fft(mm_batch* b, char* report, size_t report_len);
  *   MM_YZ_EXCHANGE  one workgroup per (instance, kx), each line over 2..8
  *                   lanes in two register passes joined by one exchange
  *                   through LDS; padded y of 16..128, padded z of 32 or 64.
+ *   MM_YZ_SPLIT_EXCHANGE  the split passes with the y passes done by the
+ *                   line transforms of MM_YZ_EXCHANGE (whole rows per lane
+ *                   group) and the z pass of MM_YZ_SPLIT; padded y of 16..256.
  * All of them compute the same convolution (agreement to FP32 rounding).
  * Returns MM_ERR_ARG, changing nothing, if some shape cannot use `path`. */
-enum { MM_YZ_FUSED = 0, MM_YZ_REGISTER = 1, MM_YZ_SPLIT = 2, MM_YZ_REGISTER8 = 3, MM_YZ_EXCHANGE = 4 };
+enum {
+  MM_YZ_FUSED = 0,
+  MM_YZ_REGISTER = 1,
+  MM_YZ_SPLIT = 2,
+  MM_YZ_REGISTER8 = 3,
+  MM_YZ_EXCHANGE = 4,
+  MM_YZ_SPLIT_EXCHANGE = 5
+};
 mm_status mm_batch_set_fft_path(mm_batch* b, int32_t path);
 
 /* Strategy of the x passes (R2C forward, C2R inverse) for every FFT grid

@@ -159,7 +159,8 @@ enum {
   PATH_REG = MM_YZ_REGISTER,
   PATH_SPLIT = MM_YZ_SPLIT,
   PATH_REG8 = MM_YZ_REGISTER8,
-  PATH_XCH = MM_YZ_EXCHANGE
+  PATH_XCH = MM_YZ_EXCHANGE,
+  PATH_SPLITX = MM_YZ_SPLIT_EXCHANGE
 };
 // eight lanes per z column: padded z of 32 or 64
 bool reg8_fits(int ny, int nz, int py, int pz) { return reg_fits(ny, nz, py, pz) && (pz == 32 || pz == 64); }
@@ -168,6 +169,9 @@ size_t xch_lds(int py, int pz) {
   return sizeof(float2) * ((size_t)3 * (pz / 2) * (py + mmk_yzx_pad()) + py + pz) +
          sizeof(float) * 6 * (size_t)(pz / 2 + 1) * (py / 2 + 1);
 }
+// split passes with the two-pass y line transforms: padded y of 16..256
+bool splitx_fits(int py) { return mmk_sx_rows(py) > 0; }
+size_t splitx_lds_y(int py) { return sizeof(float2) * ((size_t)mmk_sx_rows(py) * (py + 1) + py); }
 bool xch_fits(int ny, int nz, int py, int pz) {
   (void)ny, (void)nz;
   const bool y_ok = py == 16 || py == 32 || py == 64 || py == 128;
@@ -186,7 +190,12 @@ size_t xfuse_lds(int nx) {
   return sizeof(float2) * ((size_t)3 * Px * (J + 1) + Px);
 }
 const char* path_name(int p) {
-  return p == PATH_REG ? "reg" : p == PATH_REG8 ? "reg8" : p == PATH_XCH ? "xch" : p == PATH_SPLIT ? "split" : "fused";
+  return p == PATH_REG      ? "reg"
+         : p == PATH_REG8   ? "reg8"
+         : p == PATH_XCH    ? "xch"
+         : p == PATH_SPLIT  ? "split"
+         : p == PATH_SPLITX ? "splitx"
+                            : "fused";
 }
 
 Layout make_layout(const mm_params& p, int n_modes) {
@@ -606,11 +615,13 @@ mm_status build_group(mm_batch::Group& g, DevArena* arena = nullptr) {
   const int tiles_x = g.Wx == 0 ? (rows + XR_ROWS - 1) / XR_ROWS : (rows + 2 * g.Wx - 1) / (2 * g.Wx);
   std::vector<WorkItem> xf, yz, yy, zc;
   const int ylines = g.kx * 3 * g.nz;
-  const int tiles_y = (ylines + g.Wy - 1) / g.Wy;
+  const bool sx = g.path == PATH_SPLITX;
+  const int wy = sx ? mmk_sx_rows(g.py) : g.Wy;
+  const int tiles_y = (ylines + wy - 1) / wy;
   const int ky_tiles = (g.py + g.TW - 1) / g.TW;
   for (int m : g.members) {
     for (int t = 0; t < tiles_x; ++t) xf.push_back({m, t});
-    if (g.path != PATH_SPLIT) {
+    if (g.path != PATH_SPLIT && !sx) {
       for (int k = 0; k < g.kx; ++k) yz.push_back({m, k});
     } else {
       for (int t = 0; t < tiles_y; ++t) yy.push_back({m, t});
@@ -631,7 +642,7 @@ mm_status build_group(mm_batch::Group& g, DevArena* arena = nullptr) {
   g.lds_yz = g.path == PATH_XCH                             ? xch_lds(g.py, g.pz)
              : (g.path == PATH_REG || g.path == PATH_REG8) ? reg_lds(g.nz, g.py, g.pz)
                                                            : fused_lds(g.ny, g.nz, g.py, g.pz, g.TK);
-  g.lds_y = sizeof(float2) * ((size_t)g.py * (g.Wy + 1) + g.py);
+  g.lds_y = sx ? splitx_lds_y(g.py) : sizeof(float2) * ((size_t)g.py * (g.Wy + 1) + g.py);
   g.lds_zc = sizeof(float2) * ((size_t)g.pz * 3 * g.TW + g.pz);
   return MM_OK;
 }
@@ -737,6 +748,7 @@ mm_status batch_build(mm_batch* b, DevArena* arena = nullptr) {
       g->path = xch_fits(g->ny, g->nz, g->py, g->pz)    ? PATH_XCH
                 : reg8_fits(g->ny, g->nz, g->py, g->pz) ? PATH_REG8
                 : reg_fits(g->ny, g->nz, g->py, g->pz)  ? PATH_REG
+                : c->L.split && splitx_fits(g->py)     ? PATH_SPLITX
                 : c->L.split                           ? PATH_SPLIT
                                                        : PATH_FUSED;
     }
@@ -840,6 +852,19 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1, bool fwd = true
     } else if (g.path == PATH_FUSED) {
       if (mm_status s = launch(b, "fft_yz_convolve", [&] {
             return mmk_launch_fft_yz(g.TK, g.n_yz, g.lds_yz, b->d_desc, g.yz, g_twiddle, b->stream);
+          }))
+        return s;
+    } else if (g.path == PATH_SPLITX) {
+      if (mm_status s = launch(b, "fft_y_forward", [&] {
+            return mmk_launch_fft_ysx(-1, g.py, g.n_y, g.lds_y, b->d_desc, g.y, g_twiddle, b->stream);
+          }))
+        return s;
+      if (mm_status s = launch(b, "fft_z_convolve", [&] {
+            return mmk_launch_fft_zc(g.TW, g.n_zc, g.lds_zc, b->d_desc, g.zc, g_twiddle, b->stream);
+          }))
+        return s;
+      if (mm_status s = launch(b, "fft_y_inverse", [&] {
+            return mmk_launch_fft_ysx(1, g.py, g.n_y, g.lds_y, b->d_desc, g.y, g_twiddle, b->stream);
           }))
         return s;
     } else {
@@ -2337,7 +2362,8 @@ mm_status mm_batch_end(mm_batch* b) {
 }
 
 static mm_status check_fft_path(const mm_batch* b, int32_t path) {
-  if (path != PATH_FUSED && path != PATH_REG && path != PATH_SPLIT && path != PATH_REG8 && path != PATH_XCH)
+  if (path != PATH_FUSED && path != PATH_REG && path != PATH_SPLIT && path != PATH_REG8 && path != PATH_XCH &&
+      path != PATH_SPLITX)
     return fail(MM_ERR_ARG, "unknown y-z path");
   for (const mm_batch* p : b->parts)
     if (mm_status s = check_fft_path(p, path)) return s;
@@ -2346,6 +2372,8 @@ static mm_status check_fft_path(const mm_batch* b, int32_t path) {
       return fail(MM_ERR_ARG, "register y-z path needs padded y in 16..128 and padded z in 16..64");
     if (path == PATH_REG8 && !reg8_fits(g.ny, g.nz, g.py, g.pz))
       return fail(MM_ERR_ARG, "eight-lane register y-z path needs padded y in 16..128 and padded z of 32 or 64");
+    if (path == PATH_SPLITX && !splitx_fits(g.py))
+      return fail(MM_ERR_ARG, "split exchange y-z path needs padded y in 16..256");
     if (path == PATH_XCH && !xch_fits(g.ny, g.nz, g.py, g.pz))
       return fail(MM_ERR_ARG, "exchange y-z path needs padded y in 16..128 and padded z of 32 or 64");
     if (path == PATH_FUSED && !fused_fits(g.ny, g.nz, g.py, g.pz))
@@ -2694,6 +2722,23 @@ static mm_status tune_fft(mm_batch* b, std::string& out) {
         return s;
       yrep += (yrep.empty() ? "" : ", ") + std::string("\"xch\": ") + std::to_string(us);
       if (us < bestYZ) { bestYZ = us; bestPath = PATH_XCH; }
+    }
+    for (int TW = 1; TW <= 16 && splitx_fits(g.py); TW *= 2) {
+      if (sizeof(float2) * ((size_t)g.pz * 3 * TW + g.pz) > lds_cap) continue;
+      g.path = PATH_SPLITX;
+      g.TW = TW;
+      if (mm_status s = build_group(g)) return s;
+      double us;
+      if (mm_status s = timed([&] {
+            hipError_t e = mmk_launch_fft_ysx(-1, g.py, g.n_y, g.lds_y, b->d_desc, g.y, g_twiddle, b->stream);
+            if (e != hipSuccess) return e;
+            e = mmk_launch_fft_zc(g.TW, g.n_zc, g.lds_zc, b->d_desc, g.zc, g_twiddle, b->stream);
+            if (e != hipSuccess) return e;
+            return mmk_launch_fft_ysx(1, g.py, g.n_y, g.lds_y, b->d_desc, g.y, g_twiddle, b->stream);
+          }, &us))
+        return s;
+      yrep += (yrep.empty() ? "" : ", ") + std::string("\"splitx_") + std::to_string(TW) + "\": " + std::to_string(us);
+      if (us < bestYZ) { bestYZ = us; bestPath = PATH_SPLITX; bestTW = TW; }
     }
     for (int Wy = 4; Wy <= 64; Wy *= 2) {
       if (sizeof(float2) * ((size_t)g.py * (Wy + 1) + g.py) > lds_cap) continue;

@@ -916,17 +916,200 @@ __device__ __forceinline__ void wave_lds_order() {
 
 __device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
 
+// The y transforms of one row held in LDS by N lanes (lane lam).  Forward:
+// inputs at slots [0, P/2), afterwards slot k holds X[k].  Inverse: slot k
+// holds X[k], afterwards slots [0, P/2) hold the inverse transform (no 1/P).
+// wf[k1] = W_P^{lam k1}; wv[j][n1] = W_P^{-n1 (lam + N j)}.
+template <int P>
+struct YRow {
+  using LP = LinePass<P, 16>;
+  static constexpr int Q = LP::Q, N = LP::L;
+  struct Tw {
+    float2 wf[Q], wv[Q / N][N];
+  };
+  __device__ static void twiddles(Tw& w, const float2* tw, int lam) {
+#pragma unroll
+    for (int k1 = 0; k1 < Q; ++k1) w.wf[k1] = tw[lam * k1];
+#pragma unroll
+    for (int j = 0; j < Q / N; ++j)
+#pragma unroll
+      for (int n1 = 0; n1 < N; ++n1) w.wv[j][n1] = conjf2(j == 0 ? w.wf[n1] : tw[n1 * (lam + N * j)]);
+  }
+  __device__ static void forward(float2* line, int lam, const Tw& w) {
+    float2 v[Q];
+#pragma unroll
+    for (int n1 = 0; n1 < Q / 2; ++n1) v[n1] = line[N * n1 + lam];
+    dif_half<Q, false>(v);
+    wave_lds_order();
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+      const int k1 = brevc(p, LP::lgQ);
+      line[xslot<N>(k1, lam)] = k1 ? cmul(v[p], w.wf[k1]) : v[p];
+    }
+    wave_lds_order();
+    float2 u[Q / N][N];
+#pragma unroll
+    for (int j = 0; j < Q / N; ++j) {
+#pragma unroll
+      for (int a = 0; a < N; ++a) u[j][a] = line[xslot<N>(lam + N * j, a)];
+      dif_stages<N, false, N / 2>(u[j]);
+    }
+    wave_lds_order();
+#pragma unroll
+    for (int j = 0; j < Q / N; ++j)
+#pragma unroll
+      for (int p = 0; p < N; ++p) line[lam + N * j + Q * brevc(p, LP::lgL)] = u[j][p];
+  }
+  __device__ static void inverse(float2* line, int lam, const Tw& w) {
+    float2 g[Q / N][N];
+#pragma unroll
+    for (int j = 0; j < Q / N; ++j) {
+#pragma unroll
+      for (int k2 = 0; k2 < N; ++k2) g[j][k2] = line[lam + N * j + Q * k2];
+      dif_stages<N, true, N / 2>(g[j]);
+    }
+    wave_lds_order();
+#pragma unroll
+    for (int j = 0; j < Q / N; ++j)
+#pragma unroll
+      for (int n1 = 0; n1 < N; ++n1) {
+        const float2 zv = g[j][brevc(n1, LP::lgL)];
+        line[xslot<N>(lam + N * j, n1)] = n1 == 0 ? zv : cmul(zv, w.wv[j][n1]);
+      }
+    wave_lds_order();
+    float2 v[Q];
+#pragma unroll
+    for (int k1 = 0; k1 < Q; ++k1) v[k1] = line[xslot<N>(k1, lam)];
+    dif_stages<Q, true, Q / 2>(v);
+    wave_lds_order();
+#pragma unroll
+    for (int n2 = 0; n2 < Q / 2; ++n2) line[lam + N * n2] = v[brevc(n2, LP::lgQ)];
+  }
+};
+
+// The z convolution of one column held in LDS by N lanes (lane lam): the
+// three components at rows c ZR + z (stride RS, ZR = P/2; rows nz .. ZR-1
+// zero), forward z, the kernel multiply kmul(kz, x, y, z) at every kz, the
+// inverse z; rows z < nz receive the result.  The column's 3 ZR slots serve
+// as the exchange area once its inputs are in registers.
+template <int P>
+struct ZCol {
+  using LP = LinePass<P, 8>;
+  static constexpr int Q = LP::Q, N = LP::L, ZR = P / 2;
+  struct Tw {
+    float2 wf[Q], wv[Q / N][N];
+  };
+  __device__ static void twiddles(Tw& w, const float2* tw, int lam) {
+#pragma unroll
+    for (int k1 = 0; k1 < Q; ++k1) w.wf[k1] = tw[lam * k1];
+#pragma unroll
+    for (int j = 0; j < Q / N; ++j)
+#pragma unroll
+      for (int n1 = 0; n1 < N; ++n1) w.wv[j][n1] = conjf2(j == 0 ? w.wf[n1] : tw[n1 * (lam + N * j)]);
+  }
+  template <class KMul>
+  __device__ static void convolve(float2* col, int RS, int nz, int lam, const Tw& w, KMul&& kmul) {
+    float2 xin[3][Q / 2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int n1 = 0; n1 < Q / 2; ++n1) xin[c][n1] = col[(c * ZR + N * n1 + lam) * RS];
+    float2 sp[3][Q / N][N];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float2 v[Q];
+#pragma unroll
+      for (int n1 = 0; n1 < Q / 2; ++n1) v[n1] = xin[c][n1];
+      dif_half<Q, false>(v);
+      wave_lds_order();
+#pragma unroll
+      for (int p = 0; p < Q; ++p) {
+        const int k1 = brevc(p, LP::lgQ);
+        col[xslot<N>(k1, lam) * RS] = k1 ? cmul(v[p], w.wf[k1]) : v[p];
+      }
+      wave_lds_order();
+#pragma unroll
+      for (int j = 0; j < Q / N; ++j) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) sp[c][j][a] = col[xslot<N>(lam + N * j, a) * RS];
+        dif_stages<N, false, N / 2>(sp[c][j]);
+      }
+      wave_lds_order();
+    }
+    // sp[c][j][p] = X_c[k1 + Q brev(p)], k1 = lam + N j
+#pragma unroll
+    for (int j = 0; j < Q / N; ++j)
+#pragma unroll
+      for (int p = 0; p < N; ++p) kmul(lam + N * j + Q * brevc(p, LP::lgL), sp[0][j][p], sp[1][j][p], sp[2][j][p]);
+    float2 res[3][Q / 2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int j = 0; j < Q / N; ++j) {
+        float2 g[N];
+#pragma unroll
+        for (int k2 = 0; k2 < N; ++k2) g[k2] = sp[c][j][brevc(k2, LP::lgL)];
+        dif_stages<N, true, N / 2>(g);
+        // g[p] = sum_k2 X[k1 + Q k2] W_N^{-n1 k2} at n1 = brev(p)
+#pragma unroll
+        for (int n1 = 0; n1 < N; ++n1) {
+          const float2 zv = g[brevc(n1, LP::lgL)];
+          col[xslot<N>(lam + N * j, n1) * RS] = n1 == 0 ? zv : cmul(zv, w.wv[j][n1]);
+        }
+      }
+      wave_lds_order();
+      float2 v[Q];
+#pragma unroll
+      for (int k1 = 0; k1 < Q; ++k1) v[k1] = col[xslot<N>(k1, lam) * RS];
+      dif_stages<Q, true, Q / 2>(v);
+#pragma unroll
+      for (int n2 = 0; n2 < Q / 2; ++n2) res[c][n2] = v[brevc(n2, LP::lgQ)];
+      wave_lds_order();
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int n2 = 0; n2 < Q / 2; ++n2) {
+        const int z = lam + N * n2;
+        if (z < nz) col[(c * ZR + z) * RS] = res[c][n2];
+      }
+  }
+};
+
+// LDS bank layout shared by the kernels below (64 banks of four bytes; an
+// eight-byte access is served 32 lanes per cycle).  Rows are an odd number of
+// slots apart.  A y row has N lanes, lane = lam * RPW + r in its wavefront
+// (RPW = 64 / N rows), and the wavefront's rows are SY = N / 2 apart, so the
+// 32 lanes of a half-wavefront (N / 2 values of lam, RPW rows) fall on
+// distinct bank pairs; the rows of SY wavefronts interleave to fill blocks of
+// 32 rows.  A z column has N consecutive lanes and the wavefront's columns
+// are SZ apart (SZ = N where the tile is wide enough), for the same reason.
+// Row of y-lane yrl in block g0 of wavefront `wave`:
+template <int N>
+__device__ __forceinline__ int yrow_of(int g0, int wave, int yrl) {
+  constexpr int SY = N / 2;
+  return 32 * g0 + wave % SY + SY * yrl;
+}
+// Column of thread t in a tile of NCOL columns, N lanes per column:
+template <int N, int NCOL>
+__device__ __forceinline__ int zcol_of(int t) {
+  constexpr int CPW = 64 / N, SZ = N < NCOL / CPW ? N : NCOL / CPW;
+  const int wz = t >> 6;
+  return wz % SZ + SZ * ((t & 63) / N) + SZ * CPW * (wz / SZ);
+}
+
 template <int MY, int MZ, int RPAD>
 __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 32 ? 2 : 4, MY >= 32 ? 2 : 4))) void k_fft_yzx(
     const InstDesc* __restrict__ descs, const WorkItem* __restrict__ work, const float2* __restrict__ tw,
     int nyz, int fmethod, int fstage) {
   constexpr int PY = 4 * MY, PZ = 4 * MZ, RS = PY + RPAD, ZR = 2 * MZ, YR = 2 * MY;
-  using LY = LinePass<PY, 16>;
-  using LZ = LinePass<PZ, 8>;
-  constexpr int QY = LY::Q, NY = LY::L, QZ = LZ::Q, NZ = LZ::L;
+  using YR_ = YRow<PY>;
+  using ZC = ZCol<PZ>;
+  constexpr int NY = YR_::N, NZ = ZC::N;
   constexpr int lgPY = ilog2c(PY);
   constexpr int RPW = 64 / NY;                  // y rows per wavefront
   constexpr int NW = MM_YZX_T / 64;             // wavefronts per workgroup
+  constexpr int SY = NY / 2;
   extern __shared__ float2 lds[];
   if ((int)blockIdx.x >= nyz) {
     final_any(fmethod, fstage, descs, (int)blockIdx.x - nyz, reinterpret_cast<double*>(lds));
@@ -977,175 +1160,36 @@ __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 
     }
   }
   __syncthreads();
-  // Bank layout (64 banks of four bytes; an eight-byte access is served 32
-  // lanes per cycle): rows are Py + 1 slots apart.  A y row has NY lanes,
-  // lane = lam * RPW + r in its wavefront, and the wavefront's rows are
-  // SY = NY / 2 apart, so the 32 lanes of a half-wavefront (NY / 2 values
-  // of lam, RPW rows) fall on distinct bank pairs; the rows of SY
-  // wavefronts interleave to fill blocks of 32 rows.  A z column has NZ
-  // consecutive lanes and the wavefront's columns are SZ apart (SZ = NZ
-  // where Py allows), for the same reason.
-  constexpr int SY = NY / 2;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ylam = lane / RPW, yrl = lane % RPW;
-  float2 wfy[QY];
-#pragma unroll
-  for (int k1 = 0; k1 < QY; ++k1) wfy[k1] = twy[ylam * k1];
+  typename YR_::Tw wy;
+  YR_::twiddles(wy, twy, ylam);
   // forward y of the rows z < nz (rows z >= nz stay zero)
-  {
 #pragma unroll 1
-    for (int g0 = wave / SY; 32 * g0 < 3 * ZR; g0 += NW / SY) {
-      const int rho = 32 * g0 + wave % SY + SY * yrl;
-      if (rho < 3 * ZR && (rho & (ZR - 1)) < nz) {
-        float2* line = B + rho * RS;
-        float2 v[QY];
-#pragma unroll
-        for (int n1 = 0; n1 < QY / 2; ++n1) v[n1] = line[NY * n1 + ylam];
-        dif_half<QY, false>(v);
-        wave_lds_order();
-#pragma unroll
-        for (int p = 0; p < QY; ++p) {
-          const int k1 = brevc(p, LY::lgQ);
-          line[xslot<NY>(k1, ylam)] = k1 ? cmul(v[p], wfy[k1]) : v[p];
-        }
-        wave_lds_order();
-        float2 u[QY / NY][NY];
-#pragma unroll
-        for (int j = 0; j < QY / NY; ++j) {
-#pragma unroll
-          for (int a = 0; a < NY; ++a) u[j][a] = line[xslot<NY>(ylam + NY * j, a)];
-          dif_stages<NY, false, NY / 2>(u[j]);
-        }
-        wave_lds_order();
-#pragma unroll
-        for (int j = 0; j < QY / NY; ++j)
-#pragma unroll
-          for (int p = 0; p < NY; ++p) line[ylam + NY * j + QY * brevc(p, LY::lgL)] = u[j][p];
-      }
-    }
+  for (int g0 = wave / SY; 32 * g0 < 3 * ZR; g0 += NW / SY) {
+    const int rho = yrow_of<NY>(g0, wave, yrl);
+    if (rho < 3 * ZR && (rho & (ZR - 1)) < nz) YR_::forward(B + rho * RS, ylam, wy);
   }
   __syncthreads();
-  // z columns: NZ consecutive lanes per column, columns SZ apart
+  // z columns
   {
-    constexpr int CPW = 64 / NZ, SZ = NZ < PY / CPW ? NZ : PY / CPW;
     const int lam = threadIdx.x & (NZ - 1);
-    float2 wf[QZ], wv[QZ / NZ][NZ];
-#pragma unroll
-    for (int k1 = 0; k1 < QZ; ++k1) wf[k1] = twz[lam * k1];
-#pragma unroll
-    for (int j = 0; j < QZ / NZ; ++j)
-#pragma unroll
-      for (int n1 = 0; n1 < NZ; ++n1) wv[j][n1] = conjf2(j == 0 ? wf[n1] : twz[n1 * (lam + NZ * j)]);
+    typename ZC::Tw wz;
+    ZC::twiddles(wz, twz, lam);
 #pragma unroll 1
     for (int t = threadIdx.x; t < NZ * PY; t += MM_YZX_T) {
-      const int wz = t >> 6, ky = wz % SZ + SZ * ((t & 63) >> LZ::lgL) + SZ * CPW * (wz / SZ);
-      float2* col = B + ky;
-      float2 xin[3][QZ / 2];
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int n1 = 0; n1 < QZ / 2; ++n1) xin[c][n1] = col[(c * ZR + NZ * n1 + lam) * RS];
-      float2 sp[3][QZ / NZ][NZ];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float2 v[QZ];
-#pragma unroll
-        for (int n1 = 0; n1 < QZ / 2; ++n1) v[n1] = xin[c][n1];
-        dif_half<QZ, false>(v);
-        wave_lds_order();
-#pragma unroll
-        for (int p = 0; p < QZ; ++p) {
-          const int k1 = brevc(p, LZ::lgQ);
-          col[xslot<NZ>(k1, lam) * RS] = k1 ? cmul(v[p], wf[k1]) : v[p];
-        }
-        wave_lds_order();
-#pragma unroll
-        for (int j = 0; j < QZ / NZ; ++j) {
-#pragma unroll
-          for (int a = 0; a < NZ; ++a) sp[c][j][a] = col[xslot<NZ>(lam + NZ * j, a) * RS];
-          dif_stages<NZ, false, NZ / 2>(sp[c][j]);
-        }
-        wave_lds_order();
-      }
-      // sp[c][j][p] = X_c[k1 + QZ brev(p)], k1 = lam + NZ j
-#pragma unroll
-      for (int j = 0; j < QZ / NZ; ++j)
-#pragma unroll
-        for (int p = 0; p < NZ; ++p)
-          kernel_mul_lds<PY, PZ>(Ks, ky, lam + NZ * j + QZ * brevc(p, LZ::lgL), sp[0][j][p], sp[1][j][p],
-                                 sp[2][j][p]);
-      float2 res[3][QZ / 2];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-#pragma unroll
-        for (int j = 0; j < QZ / NZ; ++j) {
-          float2 g[NZ];
-#pragma unroll
-          for (int k2 = 0; k2 < NZ; ++k2) g[k2] = sp[c][j][brevc(k2, LZ::lgL)];
-          dif_stages<NZ, true, NZ / 2>(g);
-          // g[p] = sum_k2 X[k1 + QZ k2] W_NZ^{-n1 k2} at n1 = brev(p)
-#pragma unroll
-          for (int n1 = 0; n1 < NZ; ++n1) {
-            const float2 zv = g[brevc(n1, LZ::lgL)];
-            col[xslot<NZ>(lam + NZ * j, n1) * RS] = n1 == 0 ? zv : cmul(zv, wv[j][n1]);
-          }
-        }
-        wave_lds_order();
-        float2 v[QZ];
-#pragma unroll
-        for (int k1 = 0; k1 < QZ; ++k1) v[k1] = col[xslot<NZ>(k1, lam) * RS];
-        dif_stages<QZ, true, QZ / 2>(v);
-#pragma unroll
-        for (int n2 = 0; n2 < QZ / 2; ++n2) res[c][n2] = v[brevc(n2, LZ::lgQ)];
-        wave_lds_order();
-      }
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int n2 = 0; n2 < QZ / 2; ++n2) {
-          const int z = lam + NZ * n2;
-          if (z < nz) col[(c * ZR + z) * RS] = res[c][n2];
-        }
+      const int ky = zcol_of<NZ, PY>(t);
+      ZC::convolve(B + ky, RS, nz, lam, wz, [&](int kz, float2& a, float2& b, float2& c) {
+        kernel_mul_lds<PY, PZ>(Ks, ky, kz, a, b, c);
+      });
     }
   }
   __syncthreads();
   // inverse y of the rows z < nz, cropped to y < Py/2
-  {
-    float2 wv[QY / NY][NY];
-#pragma unroll
-    for (int j = 0; j < QY / NY; ++j)
-#pragma unroll
-      for (int n1 = 0; n1 < NY; ++n1) wv[j][n1] = conjf2(j == 0 ? wfy[n1] : twy[n1 * (ylam + NY * j)]);
 #pragma unroll 1
-    for (int g0 = wave / SY; 32 * g0 < 3 * ZR; g0 += NW / SY) {
-      const int rho = 32 * g0 + wave % SY + SY * yrl;
-      if (rho < 3 * ZR && (rho & (ZR - 1)) < nz) {
-        float2* line = B + rho * RS;
-        float2 g[QY / NY][NY];
-#pragma unroll
-        for (int j = 0; j < QY / NY; ++j) {
-#pragma unroll
-          for (int k2 = 0; k2 < NY; ++k2) g[j][k2] = line[ylam + NY * j + QY * k2];
-          dif_stages<NY, true, NY / 2>(g[j]);
-        }
-        wave_lds_order();
-#pragma unroll
-        for (int j = 0; j < QY / NY; ++j)
-#pragma unroll
-          for (int n1 = 0; n1 < NY; ++n1) {
-            const float2 zv = g[j][brevc(n1, LY::lgL)];
-            line[xslot<NY>(ylam + NY * j, n1)] = n1 == 0 ? zv : cmul(zv, wv[j][n1]);
-          }
-        wave_lds_order();
-        float2 v[QY];
-#pragma unroll
-        for (int k1 = 0; k1 < QY; ++k1) v[k1] = line[xslot<NY>(k1, ylam)];
-        dif_stages<QY, true, QY / 2>(v);
-        wave_lds_order();
-#pragma unroll
-        for (int n2 = 0; n2 < QY / 2; ++n2) line[ylam + NY * n2] = v[brevc(n2, LY::lgQ)];
-      }
-    }
+  for (int g0 = wave / SY; 32 * g0 < 3 * ZR; g0 += NW / SY) {
+    const int rho = yrow_of<NY>(g0, wave, yrl);
+    if (rho < 3 * ZR && (rho & (ZR - 1)) < nz) YR_::inverse(B + rho * RS, ylam, wy);
   }
   __syncthreads();
 #pragma unroll 4
@@ -1153,6 +1197,78 @@ __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 
     const int row = e >> (ilog2c(MY) + 1), y = e & (YR - 1);
     const int c = row / ZR, z = row & (ZR - 1);
     if (z < nz && y < ny) gst2(X + (c * nz + z) * ny + y, B[row * RS + y]);
+  }
+}
+
+// ------------------------ split y passes with the same line transforms (T = 512)
+// For padded y planes too large for one workgroup's LDS: the y passes over
+// rows (kx, c, z < nz) between X[kx][c][z][y < ny] and Y[kx][c][z][ky < Py]
+// (the z pass with the kernel multiply is k_fft_zc, over tiles of ky columns).
+#define MM_SX_T 512
+
+// rows per workgroup of the split y pass
+template <int PY>
+struct SplitY {
+  static constexpr int N = YRow<PY>::N, ROWS = 32 * (MM_SX_T / 64) / (N / 2), RS = PY + 1;
+};
+
+template <int PY, int DIR>
+__global__ __launch_bounds__(MM_SX_T) void k_fft_ysx(const InstDesc* __restrict__ descs,
+                                                    const WorkItem* __restrict__ work,
+                                                    const float2* __restrict__ tw) {
+  using YR_ = YRow<PY>;
+  using S = SplitY<PY>;
+  constexpr int N = S::N, RS = S::RS, ROWS = S::ROWS, RPW = 64 / N, SY = N / 2, NW = MM_SX_T / 64;
+  constexpr int HP = PY / 2;
+  extern __shared__ float2 lds[];
+  float2* B = lds;
+  float2* twy = B + ROWS * RS;
+  load_twiddles(twy, PY, tw, MM_SX_T);
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (gbl(D.ctl)->done) return;
+  const int ny = D.ny, nlines = D.kx * 3 * D.nz;
+  const int l0 = wi.item * ROWS;
+  const int nr = min(ROWS, nlines - l0);
+  MMG float2* X = gbl(D.fx) + (size_t)l0 * ny;
+  MMG float2* Y = gbl(D.fy) + (size_t)l0 * PY;
+  if (DIR < 0) {
+    for (int e = threadIdx.x; e < ROWS * HP; e += MM_SX_T) {
+      const int r = e / HP, y = e - r * HP;
+      float2 v = make_float2(0.f, 0.f);
+      if (r < nr && y < ny) v = gld2(X + (size_t)r * ny + y);
+      B[r * RS + y] = v;
+    }
+  } else {
+    for (int e = threadIdx.x; e < ROWS * PY; e += MM_SX_T) {
+      const int r = e / PY, y = e - r * PY;
+      if (r < nr) B[r * RS + y] = gld2(Y + (size_t)r * PY + y);
+    }
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ylam = lane / RPW, yrl = lane % RPW;
+  typename YR_::Tw w;
+  YR_::twiddles(w, twy, ylam);
+#pragma unroll 1
+  for (int g0 = wave / SY; 32 * g0 < ROWS; g0 += NW / SY) {
+    const int r = yrow_of<N>(g0, wave, yrl);
+    if (r < nr) {
+      if (DIR < 0) YR_::forward(B + r * RS, ylam, w);
+      else YR_::inverse(B + r * RS, ylam, w);
+    }
+  }
+  __syncthreads();
+  if (DIR < 0) {
+    for (int e = threadIdx.x; e < ROWS * PY; e += MM_SX_T) {
+      const int r = e / PY, y = e - r * PY;
+      if (r < nr) gst2(Y + (size_t)r * PY + y, B[r * RS + y]);
+    }
+  } else {
+    for (int e = threadIdx.x; e < ROWS * HP; e += MM_SX_T) {
+      const int r = e / HP, y = e - r * HP;
+      if (r < nr && y < ny) gst2(X + (size_t)r * ny + y, B[r * RS + y]);
+    }
   }
 }
 
@@ -1585,6 +1701,29 @@ hipError_t mmk_launch_fft_yzx(int MY, int MZ, int nblocks, size_t lds, const Ins
 }
 int mmk_yzx_pad() { return MM_YZX_PAD; }
 
+hipError_t mmk_launch_fft_ysx(int dir, int py, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
+                              const float2* tw, hipStream_t s) {
+#define MM_YSX_CASE(P)                                                                                       \
+  if (py == P) {                                                                                             \
+    if (dir < 0) MM_LAUNCH((mmk::k_fft_ysx<P, -1>), dim3(nblocks), dim3(MM_SX_T), lds, s, d, w, tw);        \
+    else MM_LAUNCH((mmk::k_fft_ysx<P, 1>), dim3(nblocks), dim3(MM_SX_T), lds, s, d, w, tw);                 \
+    return hipGetLastError();                                                                                \
+  }
+  MM_YSX_CASE(16) MM_YSX_CASE(32) MM_YSX_CASE(64) MM_YSX_CASE(128) MM_YSX_CASE(256)
+  return hipErrorInvalidValue;
+}
+// rows per workgroup of the split y pass
+int mmk_sx_rows(int py) {
+  switch (py) {
+    case 16: return mmk::SplitY<16>::ROWS;
+    case 32: return mmk::SplitY<32>::ROWS;
+    case 64: return mmk::SplitY<64>::ROWS;
+    case 128: return mmk::SplitY<128>::ROWS;
+    case 256: return mmk::SplitY<256>::ROWS;
+    default: return 0;
+  }
+}
+
 hipError_t mmk_launch_fft_y(int dir, int W, int nblocks, size_t lds, const InstDesc* d,
                             const WorkItem* w, const float2* tw, hipStream_t s) {
   if (dir < 0) MM_LAUNCH(mmk::k_fft_y<-1>, dim3(nblocks), dim3(256), lds, s, d, w, W, tw);
@@ -1620,5 +1759,11 @@ hipError_t mmk_set_lds_limits() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   MM_YZX_ATTR(4, 8) MM_YZX_ATTR(8, 8) MM_YZX_ATTR(16, 8) MM_YZX_ATTR(32, 8)
   MM_YZX_ATTR(4, 16) MM_YZX_ATTR(8, 16) MM_YZX_ATTR(16, 16) MM_YZX_ATTR(32, 16)
+#define MM_SX_ATTR(K)                                                                                      \
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)K, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  MM_SX_ATTR((mmk::k_fft_ysx<16, -1>)) MM_SX_ATTR((mmk::k_fft_ysx<32, -1>)) MM_SX_ATTR((mmk::k_fft_ysx<64, -1>))
+  MM_SX_ATTR((mmk::k_fft_ysx<128, -1>)) MM_SX_ATTR((mmk::k_fft_ysx<256, -1>))
+  MM_SX_ATTR((mmk::k_fft_ysx<16, 1>)) MM_SX_ATTR((mmk::k_fft_ysx<32, 1>)) MM_SX_ATTR((mmk::k_fft_ysx<64, 1>))
+  MM_SX_ATTR((mmk::k_fft_ysx<128, 1>)) MM_SX_ATTR((mmk::k_fft_ysx<256, 1>))
   return e;
 }

@@ -383,10 +383,10 @@ class Batch:
         _check(fn(self.h, buf, len(buf)))
         return json.loads(buf.value.decode())
 
-    YZ_PATHS = {"fused": 0, "reg": 1, "split": 2, "reg8": 3, "xch": 4}
+    YZ_PATHS = {"fused": 0, "reg": 1, "split": 2, "reg8": 3, "xch": 4, "splitx": 5}
 
     def set_fft_path(self, path):
-        """Force the demag y-z strategy ("fused", "reg", "reg8", "xch" or "split") for every grid shape."""
+        """Force the demag y-z strategy ("fused", "reg", "reg8", "xch", "split" or "splitx") for every grid shape."""
         _check(self._lib.mm_batch_set_fft_path(self.h, self.YZ_PATHS[path]))
 
     def set_fft_x(self, path):

@@ -343,7 +343,7 @@ def test_tuned_batch_keeps_parity():
     b1 = mmcav.Batch(ctxs)
     m0 = [c.get_m() for c in ctxs]
     rep = b1.tune()
-    assert len(rep) == b1.streams() and all(r["path"] in ("fused", "reg", "reg8", "xch", "split") for r in rep)
+    assert len(rep) == b1.streams() and all(r["path"] in ("fused", "reg", "reg8", "xch", "split", "splitx") for r in rep)
     assert all(r["streams"] == b1.streams() and len(r["streams_ms_per_step"]) == 3 for r in rep)
     # the timed steps of the tuner leave no trace: state, counters, samples
     assert all(c.stats()["accepted"] == 0 and c.stats()["t"] == 0.0 for c in ctxs)
@@ -390,9 +390,9 @@ def test_fft_yz_paths_agree(shape):
     if shape[0] & (shape[0] - 1) == 0:       # x passes inside the stage kernels need nx = 2^k
         combos += [("reg", "stage"), ("split", "stage")]
     if shape[2] > 8:                         # eight lanes per z column need a padded z of 32 or 64
-        combos += [("reg8", "lds"), ("xch", "lds")]
+        combos += [("reg8", "lds"), ("xch", "lds"), ("splitx", "lds")]
         if shape[0] & (shape[0] - 1) == 0:
-            combos += [("reg8", "stage"), ("xch", "stage")]
+            combos += [("reg8", "stage"), ("xch", "stage"), ("splitx", "stage")]
     for path, xpath in combos:
         c = gpu_for(inst)
         b = mmcav.Batch([c])
@@ -406,6 +406,35 @@ def test_fft_yz_paths_agree(shape):
     ref = out["fused", "lds"]
     for key, m in out.items():
         assert np.abs(m - ref).max() <= 2e-6, key
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shape", [(4, 100, 20), (8, 70, 9)])
+def test_split_exchange_wide_y(shape):
+    """Padded y of 256 (wider than the one-workgroup y-z kernels take): the
+    split passes whose y passes use the two-pass line transforms agree with
+    the LDS split passes to FP32 rounding and with the oracle within the
+    parity bound, for padded z of 64 and of 32 (with z rows past nz)."""
+    from paper_2603_03706_amd import mmcav
+    inst = W.Instance(grid=shape, cell=(5e-9, 4e-9, 3e-9), Ms=140e3, Aex=3.65e-12, alpha=0.01,
+                      B0=(0.01, 0.0, 0.15), demag=W.DEMAG_FFT,
+                      omega=np.array([TWO_PI * 5e9]), kappa=np.array([TWO_PI * 2e6]),
+                      g=np.array([TWO_PI * 80e6]), m0=_random_state(shape, 23),
+                      a0=np.array([0.05 + 0.02j]), method="rk4", dt0=0.2e-12)
+    st = oracle_for(inst)
+    run_oracle(st, 20e-12)
+    out = {}
+    for path in ("split", "splitx"):
+        c = gpu_for(inst)
+        b = mmcav.Batch([c])
+        b.set_fft_path(path)
+        b.set_fft_x("lds")
+        b.run(20e-12)
+        out[path] = c.get_m()
+        assert m_err(out[path], st) <= 2e-5, path
+        b.close()
+        c.close()
+    assert np.abs(out["splitx"] - out["split"]).max() <= 2e-6
 
 
 @pytest.mark.gpu
