@@ -135,8 +135,11 @@ def profile_name(kernel):
     if m:
         return f"{m.group(1)}_{'rk4' if m.group(2) == '0' else 'dp45'}_{m.group(3)}" \
             if not (m.group(1) == "stage" and m.group(2) == "0" and m.group(3) == "0") else "stage_rk4_start"
-    if k.startswith("mmk::k_fft_yzr<") or k.startswith("mmk::k_fft_yz8<"):
+    if k.startswith(("mmk::k_fft_yzr<", "mmk::k_fft_yz8<", "mmk::k_fft_yzx<")):
         return "fft_yz_convolve"
+    m = re.match(r"mmk::k_fft_ysx<\d+, (-?\d+)>", k)
+    if m:
+        return "fft_y_forward" if m.group(1) == "-1" else "fft_y_inverse"
     table = {"mmk::k_fft_yz": "fft_yz_convolve", "mmk::k_fft_zc": "fft_z_convolve",
              "mmk::k_fft_y<-1>": "fft_y_forward", "mmk::k_fft_y<1>": "fft_y_inverse"}
     if k in table:
@@ -384,7 +387,9 @@ def tile_fields(kernel, tiles):
             if d["path"] != "fused":
                 d.pop("TK")
             if d["path"] != "split":
-                d.pop("Wy"), d.pop("TW")
+                d.pop("Wy")
+            if d["path"] not in ("split", "splitx"):
+                d.pop("TW")
         out.append(d)
     return out
 
