@@ -1131,19 +1131,30 @@ __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 
   const int ny = D.ny, nz = D.nz;
   const int nrow = 3 * nz;
   MMG float2* X = gbl(D.fx) + (size_t)kx * nrow * ny;
+  // Loads: thread t takes column y = t mod Py of rows it * RPI + t / Py.  The
+  // row's (c, z) and the X offset (c nz + z) ny + y are a per-thread part
+  // plus a part uniform over the workgroup, so each element costs a compare,
+  // a select and an add.
+  constexpr int RPI = MM_YZX_T / PY;            // rows per iteration
   {
     const MMG float* K = gbl(D.kern) + (size_t)kx * 6 * KPL;
     float kv[NK];
     float2 xv[NX];
 #pragma unroll
     for (int it = 0; it < NK; ++it) kv[it] = K[min(it * MM_YZX_T + (int)threadIdx.x, 6 * KPL - 1)];
+    const int y = threadIdx.x & (PY - 1), r0 = threadIdx.x >> lgPY;
+    const bool yin = y < ny;
+    const int tb = r0 * ny + y;
 #pragma unroll
     for (int it = 0; it < NX; ++it) {
-      const int e = it * MM_YZX_T + threadIdx.x;
-      const int row = e >> lgPY, y = e & (PY - 1);
-      const int c = row / ZR, z = row - c * ZR;
-      const bool in = e < NXE && z < nz && y < ny;
-      const float2 v = gld2(X + (min(c, 2) * nz + min(z, nz - 1)) * ny + min(y, ny - 1));
+      const int row = it * RPI + r0;
+      // when the rows of an iteration stay within a component, c and the
+      // first z are compile-time and z = z0 + r0
+      const int c = (ZR % RPI == 0) ? (it * RPI) / ZR : row / ZR;
+      const int z = (ZR % RPI == 0) ? (it * RPI) % ZR + r0 : row % ZR;
+      const bool in = row < 3 * ZR && yin && z < nz;
+      const int off = (ZR % RPI == 0) ? (c * nz + (it * RPI) % ZR) * ny + tb : (c * nz + z) * ny + y;
+      const float2 v = gld2(X + (in ? off : 0));
       xv[it] = make_float2(in ? v.x : 0.f, in ? v.y : 0.f);
     }
 #pragma unroll
@@ -1153,10 +1164,8 @@ __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 
     }
 #pragma unroll
     for (int it = 0; it < NX; ++it) {
-      const int e = it * MM_YZX_T + threadIdx.x;
-      const int row = e >> lgPY, y = e & (PY - 1);
-      const int z = row % ZR;
-      if (e < NXE && (z >= nz || y < YR)) B[row * RS + y] = xv[it];
+      const int row = it * RPI + r0, z = row % ZR;
+      if (row < 3 * ZR && (z >= nz || y < YR)) B[row * RS + y] = xv[it];
     }
   }
   __syncthreads();
@@ -1192,11 +1201,20 @@ __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 
     if (rho < 3 * ZR && (rho & (ZR - 1)) < nz) YR_::inverse(B + rho * RS, ylam, wy);
   }
   __syncthreads();
-#pragma unroll 4
-  for (int e = threadIdx.x; e < 3 * ZR * YR; e += MM_YZX_T) {
-    const int row = e >> (ilog2c(MY) + 1), y = e & (YR - 1);
-    const int c = row / ZR, z = row & (ZR - 1);
-    if (z < nz && y < ny) gst2(X + (c * nz + z) * ny + y, B[row * RS + y]);
+  {
+    // stores: thread t takes column y = t mod (Py/2) of rows it * RPO + t / (Py/2)
+    constexpr int RPO = MM_YZX_T / YR, NO = (3 * ZR + RPO - 1) / RPO;
+    const int y = threadIdx.x & (YR - 1), r0 = threadIdx.x / YR;
+    const bool yin = y < ny;
+    const int tb = r0 * ny + y;
+#pragma unroll
+    for (int it = 0; it < NO; ++it) {
+      const int row = it * RPO + r0;
+      const int c = (ZR % RPO == 0) ? (it * RPO) / ZR : row / ZR;
+      const int z = (ZR % RPO == 0) ? (it * RPO) % ZR + r0 : row % ZR;
+      const int off = (ZR % RPO == 0) ? (c * nz + (it * RPO) % ZR) * ny + tb : (c * nz + z) * ny + y;
+      if (row < 3 * ZR && z < nz && yin) gst2(X + off, B[row * RS + y]);
+    }
   }
 }
 
