@@ -100,3 +100,55 @@ def test_host_demag_tensor_matches_oracle():
         assert np.abs(got - ref).max() <= 1e-10 * scale, (r, got, ref)
     with pytest.raises(mmcav.MMError):
         mmcav.demag_tensor(0, 0, 0, 0.0, 1e-9, 1e-9)
+
+
+def test_host_demag_tensor_against_high_precision_closed_form():
+    """The library's tensor (80-bit closed form below ten cells of distance,
+    a tenth-order moment expansion of the averaged kernel beyond) against
+    Newell's closed form evaluated here in 40-digit arithmetic, on both
+    sides of the switch and far out, all six components."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+
+    def q(a, b):
+        return a / b if b != 0 else mp.mpf(0)
+
+    def f(x, y, z):
+        x, y, z = abs(x), abs(y), abs(z)
+        R = mp.sqrt(x * x + y * y + z * z)
+        out = (2 * x * x - y * y - z * z) * R / 6
+        out += y / 2 * (z * z - x * x) * mp.asinh(q(y, mp.sqrt(x * x + z * z)))
+        out += z / 2 * (y * y - x * x) * mp.asinh(q(z, mp.sqrt(x * x + y * y)))
+        out -= x * y * z * mp.atan(q(y * z, x * R))
+        return out
+
+    def g(x, y, z):
+        sg = mp.sign(x) * mp.sign(y)
+        x, y, z = abs(x), abs(y), abs(z)
+        R = mp.sqrt(x * x + y * y + z * z)
+        out = -x * y * R / 3 + x * y * z * mp.asinh(q(z, mp.sqrt(x * x + y * y)))
+        out += y / 6 * (3 * z * z - y * y) * mp.asinh(q(x, mp.sqrt(y * y + z * z)))
+        out += x / 6 * (3 * z * z - x * x) * mp.asinh(q(y, mp.sqrt(x * x + z * z)))
+        out -= z ** 3 / 6 * mp.atan(q(x * y, z * R)) + z * y * y / 2 * mp.atan(q(x * z, y * R))
+        out -= z * x * x / 2 * mp.atan(q(y * z, x * R))
+        return sg * out
+
+    def diff(fn, X, Y, Z, a, b, c):
+        w = (-1, 2, -1)
+        acc = mp.mpf(0)
+        for i in range(3):
+            for j in range(3):
+                for k in range(3):
+                    acc += w[i] * w[j] * w[k] * fn(X + (i - 1) * a, Y + (j - 1) * b, Z + (k - 1) * c)
+        return acc / (4 * mp.pi * a * b * c)
+
+    d = (5e-9, 4e-9, 3e-9)
+    D = [mp.mpf(5), mp.mpf(4), mp.mpf(3)]
+    for r in [(0, 0, 0), (1, 2, 0), (6, -5, 3), (9, 3, -2), (11, 0, 1), (20, -7, 12), (40, 25, -30)]:
+        X, Y, Z = (r[i] * D[i] for i in range(3))
+        ref = np.array([float(v) * 1.0 for v in (
+            diff(f, X, Y, Z, D[0], D[1], D[2]), diff(f, Y, X, Z, D[1], D[0], D[2]), diff(f, Z, Y, X, D[2], D[1], D[0]),
+            diff(g, X, Y, Z, D[0], D[1], D[2]), diff(g, X, Z, Y, D[0], D[2], D[1]), diff(g, Y, Z, X, D[1], D[2], D[0]))])
+        got = mmcav.demag_tensor(r[0] * d[0], r[1] * d[1], r[2] * d[2], *d)
+        # the tensor is dimensionless: cells in nm or in m give the same values
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), (r, got, ref)
