@@ -149,6 +149,49 @@ def test_autograd_function_matches_adjoint_and_differences():
     assert abs(fd - pred) <= 2e-2 * abs(pred), (fd, pred)
 
 
+def test_autograd_central_differences_sixteen_directions():
+    """Central differences of the loss along 16 seeded directions in
+    (u, g, alpha, B0), u included in every one, against the directional
+    derivative of the autograd gradients, on a reduced film.  The state is
+    FP32, so a difference quotient carries about 1e-7 / 1e-3 of rounding;
+    the bound is 1e-3 of the derivative's scale."""
+    from paper_2603_03706_amd import mmcav
+    inst = W.multimode_film(8, 6, 3)
+    inst = variant(inst, method="rk4", dt0=0.5e-12, alpha=0.01, a0=np.array([1.0, 0.2j, 0.0, 0.1]))
+    T, every, mode = 30 * inst.dt0, 7, 1
+    u0 = np.asarray(inst.u, np.float32)
+
+    def args(du=0.0, dg=0.0, dal=0.0, db=0.0, grad=False):
+        return (torch.tensor((u0 + du).astype(np.float32), requires_grad=grad),
+                torch.tensor(np.asarray(inst.g) + dg, dtype=torch.float64, requires_grad=grad),
+                torch.tensor(inst.alpha + dal, dtype=torch.float64, requires_grad=grad),
+                torch.tensor(np.asarray(inst.B0) + db, dtype=torch.float64, requires_grad=grad))
+
+    u, g, al, b0 = args(grad=True)
+    a, _ = mmcav.recorded_run(inst, T, u, g, al, b0, every)
+    (a[mode, 0] ** 2 + a[mode, 1] ** 2).backward()
+    gu, gg, gal, gb = u.grad.numpy().astype(np.float64), g.grad.numpy(), al.grad.item(), b0.grad.numpy()
+
+    def loss(du, dg, dal, db):
+        with torch.no_grad():
+            out, _ = mmcav.recorded_run(inst, T, *args(du, dg, dal, db), every)
+        return float(out[mode, 0] ** 2 + out[mode, 1] ** 2)
+
+    rng = np.random.default_rng(16)
+    h = 1e-3
+    preds, fds = [], []
+    for _ in range(16):
+        du = h * np.abs(u0).max() * rng.normal(size=u0.shape)
+        dg = h * np.asarray(inst.g) * rng.normal(size=len(inst.g))
+        dal = h * inst.alpha * rng.normal()
+        db = h * max(np.abs(inst.B0).max(), 1e-3) * rng.normal(size=3)
+        fds.append((loss(du, dg, dal, db) - loss(-du, -dg, -dal, -db)) / 2.0)
+        preds.append(float(np.sum(gu * du) + gg @ dg + gal * dal + gb @ db))
+    preds, fds = np.array(preds), np.array(fds)
+    scale = np.abs(preds).max()
+    assert np.abs(fds - preds).max() <= 1e-3 * scale, (fds, preds)
+
+
 def test_adjoint_with_cavity_drive():
     """Sim 1 geometry of Table I over the Gaussian pulse of Sec. IV A (150
     steps of 1 ps, segments of 64 and a ragged 22): the drive is additive and
