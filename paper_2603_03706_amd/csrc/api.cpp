@@ -702,8 +702,8 @@ mm_status carve_run_buffers(mm_batch* b, DevArena* ar) {
     const mm_params& p = c->p;
     if (mm_status s = ar->take(sizeof(float) * 3 * (size_t)L.ncell, (void**)&r.bd)) return s;
     if (mm_status s = ar->take(sizeof(float2) * (size_t)L.kx * 3 * p.nz * p.ny, (void**)&r.fx)) return s;
-    // the spectra of the y pass exist only on the split y-z path
-    if (!b->groups.empty() && b->groups[0].path == PATH_SPLIT)
+    // the spectra of the y pass exist only on the split y-z paths
+    if (!b->groups.empty() && (b->groups[0].path == PATH_SPLIT || b->groups[0].path == PATH_SPLITX))
       if (mm_status s = ar->take(sizeof(float2) * (size_t)L.kx * 3 * p.nz * L.py, (void**)&r.fy)) return s;
   }
   r.on = true;
@@ -823,7 +823,7 @@ mm_status launch(mm_batch* b, const char* name, F&& f) {
 // `fwd` (the input was not produced by a stage kernel) and the x-inverse
 // pass only when `inv` (the consuming kernel does not transform itself).
 // final_st >= 0: the finalisation of that stage of the batch's method rides
-// on the first group's y-z launch (eight-lane path only, see merge_final).
+// on the first group's y-z launch (see merge_final).
 mm_status enqueue_demag(mm_batch* b, int stage, int method = -1, bool fwd = true, bool inv = true,
                         int final_st = -1) {
   if (method < 0) method = b->method;
@@ -856,7 +856,8 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1, bool fwd = true
         return s;
     } else if (g.path == PATH_SPLITX) {
       if (mm_status s = launch(b, "fft_y_forward", [&] {
-            return mmk_launch_fft_ysx(-1, g.py, g.n_y, g.lds_y, b->d_desc, g.y, g_twiddle, b->stream);
+            return mmk_launch_fft_ysx(-1, g.py, g.n_y, g.lds_y, b->d_desc, g.y, g_twiddle, b->stream,
+                                      first ? nfinal : 0, b->method, final_st);
           }))
         return s;
       if (mm_status s = launch(b, "fft_z_convolve", [&] {
@@ -950,10 +951,13 @@ mm_status enqueue_start(mm_batch* b) {
 // 2 input, which depends on the step size chosen after stage 7.
 // The finalisation of a stage other than the last of the step runs as extra
 // workgroups of the next stage's first y-z launch when that launch is the
-// eight-lane kernel: the transform reads only X, which the finalisation does
-// not touch, and the next stage kernel comes after both in stream order.
+// eight-lane, the two-pass or the split two-pass y forward kernel: the
+// transform reads and writes only X (and Y), which the finalisation does not
+// touch, and the next stage kernel comes after both in stream order.
 bool merge_final(const mm_batch* b) {
-  return !b->groups.empty() && (b->groups[0].path == PATH_REG8 || b->groups[0].path == PATH_XCH);
+  if (b->groups.empty()) return false;
+  const int p = b->groups[0].path;
+  return p == PATH_REG8 || p == PATH_XCH || p == PATH_SPLITX;
 }
 
 mm_status enqueue_step(mm_batch* b) {

@@ -862,6 +862,7 @@ __global__ __launch_bounds__(MM_YZ8_T) __attribute__((amdgpu_waves_per_eu(4, 4))
 //   per ky column: forward z of the three components, kernel multiply,
 //   inverse z (in place);  inverse y per row (in place);  store X.
 #define MM_YZX_T 512
+static_assert(MM_YZX_T == MMI_WG, "the finalisation body in the extra workgroups assumes MMI_WG threads");
 
 // points per lane Q and lanes per line L of a padded length P (Q >= L):
 // y rows take up to sixteen points per lane, z columns eight
@@ -1230,15 +1231,24 @@ struct SplitY {
   static constexpr int N = YRow<PY>::N, ROWS = 32 * (MM_SX_T / 64) / (N / 2), RS = PY + 1;
 };
 
+// Workgroups nwork .. nwork + nfinal - 1 of a forward launch run the
+// finalisation of stage fstage instead (as in k_fft_yzx: the y pass reads
+// and writes only X and Y, which the finalisation does not touch).
+static_assert(MM_SX_T == MMI_WG, "the finalisation body in the extra workgroups assumes MMI_WG threads");
 template <int PY, int DIR>
 __global__ __launch_bounds__(MM_SX_T) void k_fft_ysx(const InstDesc* __restrict__ descs,
                                                     const WorkItem* __restrict__ work,
-                                                    const float2* __restrict__ tw) {
+                                                    const float2* __restrict__ tw, int nwork,
+                                                    int fmethod, int fstage) {
   using YR_ = YRow<PY>;
   using S = SplitY<PY>;
   constexpr int N = S::N, RS = S::RS, ROWS = S::ROWS, RPW = 64 / N, SY = N / 2, NW = MM_SX_T / 64;
   constexpr int HP = PY / 2;
   extern __shared__ float2 lds[];
+  if ((int)blockIdx.x >= nwork) {
+    final_any(fmethod, fstage, descs, (int)blockIdx.x - nwork, reinterpret_cast<double*>(lds));
+    return;
+  }
   float2* B = lds;
   float2* twy = B + ROWS * RS;
   load_twiddles(twy, PY, tw, MM_SX_T);
@@ -1720,11 +1730,15 @@ hipError_t mmk_launch_fft_yzx(int MY, int MZ, int nblocks, size_t lds, const Ins
 int mmk_yzx_pad() { return MM_YZX_PAD; }
 
 hipError_t mmk_launch_fft_ysx(int dir, int py, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
-                              const float2* tw, hipStream_t s) {
+                              const float2* tw, hipStream_t s, int nfinal, int fmethod, int fstage) {
+  if (nfinal < 0 || (nfinal > 0 && (dir > 0 || lds < MMI_PSTRIDE * sizeof(double)))) return hipErrorInvalidValue;
 #define MM_YSX_CASE(P)                                                                                       \
   if (py == P) {                                                                                             \
-    if (dir < 0) MM_LAUNCH((mmk::k_fft_ysx<P, -1>), dim3(nblocks), dim3(MM_SX_T), lds, s, d, w, tw);        \
-    else MM_LAUNCH((mmk::k_fft_ysx<P, 1>), dim3(nblocks), dim3(MM_SX_T), lds, s, d, w, tw);                 \
+    if (dir < 0)                                                                                             \
+      MM_LAUNCH((mmk::k_fft_ysx<P, -1>), dim3(nblocks + nfinal), dim3(MM_SX_T), lds, s, d, w, tw, nblocks,   \
+                fmethod, fstage);                                                                            \
+    else                                                                                                     \
+      MM_LAUNCH((mmk::k_fft_ysx<P, 1>), dim3(nblocks), dim3(MM_SX_T), lds, s, d, w, tw, nblocks, 0, 0);      \
     return hipGetLastError();                                                                                \
   }
   MM_YSX_CASE(16) MM_YSX_CASE(32) MM_YSX_CASE(64) MM_YSX_CASE(128) MM_YSX_CASE(256)

@@ -37,7 +37,8 @@ hipError_t mmk_launch_fft_yzx(int MY, int MZ, int nblocks, size_t lds, const Ins
                               int fstage = 0);
 int mmk_yzx_pad();
 hipError_t mmk_launch_fft_ysx(int dir, int py, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
-                              const float2* tw, hipStream_t s);
+                              const float2* tw, hipStream_t s, int nfinal = 0, int fmethod = 0,
+                              int fstage = 0);
 int mmk_sx_rows(int py);
 hipError_t mmk_launch_fft_yz(int TK, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                              const float2* tw, hipStream_t s);

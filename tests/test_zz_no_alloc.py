@@ -57,6 +57,19 @@ def test_noalloc_equals_run_two_calls_second_smaller():
     _assert_same(have, want)
 
 
+def test_noalloc_wide_y_split_path():
+    """A grid whose padded y (256) takes the split y-z passes, whose y-pass
+    spectra are carved from the scratch array too: equal to mm_run."""
+    inst = W.Instance(grid=(4, 100, 20), cell=(5e-9, 4e-9, 3e-9), Ms=140e3, Aex=3.65e-12, alpha=0.01,
+                      B0=(0.01, 0.0, 0.15), demag=W.DEMAG_FFT,
+                      omega=np.array([2 * np.pi * 5e9]), kappa=np.array([2 * np.pi * 2e6]),
+                      g=np.array([2 * np.pi * 80e6]), m0=W.tilted((4, 100, 20), 10.0, 0.3),
+                      a0=np.array([0.05 + 0.02j]), method="dp45", dt0=0.2e-12)
+    want, have = _case(inst, 20e-12, 1e-6)
+    _assert_same(have, want)
+    assert have[3][0] > 5
+
+
 def test_noalloc_rk4_local_demag_and_resume():
     inst = W.plain_tiny()
     inst.T = 0.0
