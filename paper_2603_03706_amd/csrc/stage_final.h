@@ -68,33 +68,36 @@ __device__ __forceinline__ double block_reduce(double v, double* sh) {
   return r;
 }
 
-// Sum (or, with MAX, the NaN-propagating max of) slots s0 .. s0+n-1 of the
-// partial records over all workgroups of an instance, every slot in a fixed
-// order: wave w of the workgroup takes slots w, w + 8, ...; its lanes stride
-// over the workgroups (lane l: records l, l + 64, ...) and a butterfly joins
-// the lanes.  Results (sums times `scale`) go to tot[slot] in LDS; the caller
-// synchronises before reading them.
-template <bool MAX>
-__device__ __forceinline__ void gather_slots(const InstDesc& D, int s0, int n, double scale, double* tot) {
+// The gathers of one finalisation as one list of tasks: mode sums m^-
+// (slots MMI_SLOT_MM + 0 .. nmm-1), stage-derivative sums (MMI_SLOT_DMM +
+// 0 .. ndmm-1) and, with has_max, the NaN-propagating max of one slot over
+// the workgroups; wave w takes tasks w, w + 8, ...  Every slot is combined in
+// a fixed order: lane l takes records l, l + 64, ... (eight in flight) and a
+// butterfly joins the lanes.  Results (sums times `scale`) go to tot[slot]
+// in LDS; the caller synchronises before reading them.
+__device__ __forceinline__ void gather_list(const InstDesc& D, int nmm, int ndmm, bool has_max, int max_slot,
+                                            double scale, double* tot) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const MMG double* P = gbl(D.partials);
-  for (int k = wv; k < n; k += MMI_WG / 64) {
+  const int ntask = nmm + ndmm + (has_max ? 1 : 0);
+  for (int k = wv; k < ntask; k += MMI_WG / 64) {
+    const bool mx = has_max && k == ntask - 1;
+    const int slot = mx ? max_slot : (k < nmm ? MMI_SLOT_MM + k : MMI_SLOT_DMM + (k - nmm));
     double v = 0.0;
     int w = lane;
-    // eight records in flight at a time, combined in the same order
     for (; w + 7 * 64 < D.nwg; w += 8 * 64) {
       double p[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) p[u] = P[(size_t)(w + u * 64) * MMI_PSTRIDE + s0 + k];
+      for (int u = 0; u < 8; ++u) p[u] = P[(size_t)(w + u * 64) * MMI_PSTRIDE + slot];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v = MAX ? nan_max(v, p[u]) : v + p[u];
+      for (int u = 0; u < 8; ++u) v = mx ? nan_max(v, p[u]) : v + p[u];
     }
     for (; w < D.nwg; w += 64) {
-      const double p = P[(size_t)w * MMI_PSTRIDE + s0 + k];
-      v = MAX ? nan_max(v, p) : v + p;
+      const double p = P[(size_t)w * MMI_PSTRIDE + slot];
+      v = mx ? nan_max(v, p) : v + p;
     }
-    v = MAX ? wave_max(v) : wave_sum(v);
-    if (lane == 0) tot[s0 + k] = MAX ? v : v * scale;
+    v = mx ? wave_max(v) : wave_sum(v);
+    if (lane == 0) tot[slot] = mx ? v : v * scale;
   }
 }
 
@@ -451,10 +454,13 @@ __device__ void final_body(const InstDesc* __restrict__ descs, int inst, double*
   if (C->done) return;
   const bool has_next = !(METHOD == MMI_DP45 && ST == 7);
   const double scale = D.inv_ngeo / (double)D.S;
-  if (has_next) gather_slots<false>(D, MMI_SLOT_MM, 2 * D.N, scale, tot);
-  if (METHOD == MMI_DP45 && (ST == 1 || ST == 2 || ST == 7)) gather_slots<false>(D, MMI_SLOT_DMM, 2 * D.N, scale, tot);
-  if (METHOD == MMI_DP45 && ST == 7) gather_slots<true>(D, MMI_SLOT_ERR, 1, 1.0, tot);
-  if (METHOD == MMI_RK4 && ST == 4) gather_slots<true>(D, MMI_SLOT_BAD, 1, 1.0, tot);
+  // the slots this stage needs, dealt to the waves as one list so that the
+  // error (or non-finite) slot runs beside the mode sums, not after them
+  const int nmm = has_next ? 2 * D.N : 0;
+  const int ndmm = (METHOD == MMI_DP45 && (ST == 1 || ST == 2 || ST == 7)) ? 2 * D.N : 0;
+  constexpr bool kMax = (METHOD == MMI_DP45 && ST == 7) || (METHOD == MMI_RK4 && ST == 4);
+  constexpr int kMaxSlot = METHOD == MMI_DP45 ? MMI_SLOT_ERR : MMI_SLOT_BAD;
+  gather_list(D, nmm, ndmm, kMax, kMaxSlot, scale, tot);
   __syncthreads();
   if (threadIdx.x == 0) finalize<METHOD, ST>(D, C, tot);
 }
