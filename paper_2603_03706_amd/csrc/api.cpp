@@ -818,6 +818,12 @@ mm_status launch(mm_batch* b, const char* name, F&& f) {
   return MM_OK;
 }
 
+bool any_xfused(const mm_batch* b) {
+  for (const auto& g : b->groups)
+    if (g.xfused) return true;
+  return false;
+}
+
 // Demag convolution of the given stage's input.  For groups whose x passes
 // run inside the stage kernels, the x-forward pass is enqueued only when
 // `fwd` (the input was not produced by a stage kernel) and the x-inverse
@@ -828,9 +834,19 @@ mm_status enqueue_demag(mm_batch* b, int stage, int method = -1, bool fwd = true
                         int final_st = -1) {
   if (method < 0) method = b->method;
   const int nfinal = final_st >= 0 ? (int)b->ctxs.size() : 0;
+  // x-forward of the instances whose x passes run in the stage kernels: one
+  // launch on the stage grid (forward stepping; the adjoint's inputs go
+  // through the x kernels of their groups)
+  const bool cells_fwd = fwd && method != MMI_ADJ && any_xfused(b);
+  if (cells_fwd)
+    if (mm_status s = launch(b, "fft_x_forward", [&] {
+          return mmk_launch_xfwd_cells(method, stage, b->total_wg, b->d_desc, b->d_wg, g_twiddle, b->stage_lds,
+                                       b->stream);
+        }))
+      return s;
   for (auto& g : b->groups) {
     const bool first = &g == &b->groups[0];
-    if (!g.xfused || fwd)
+    if (!g.xfused || (fwd && !cells_fwd))
     if (mm_status s = launch(b, "fft_x_forward", [&] {
           if (g.Wx == 0)
             return mmk_launch_fft_xr(1, g.px / 4, g.n_xf, b->d_desc, g.xf, method, stage, g_twiddle, b->stream);
@@ -922,16 +938,11 @@ mm_status enqueue_stage(mm_batch* b, int st, bool with_final = true) {
 
 // x-forward pass of the state for groups whose x passes run in the stage kernels
 mm_status enqueue_x_forward(mm_batch* b, int stage) {
-  for (auto& g : b->groups) {
-    if (!g.xfused) continue;
-    if (mm_status s = launch(b, "fft_x_forward", [&] {
-          if (g.Wx == 0)
-            return mmk_launch_fft_xr(1, g.px / 4, g.n_xf, b->d_desc, g.xf, b->method, stage, g_twiddle, b->stream);
-          return mmk_launch_fft_xf(g.Wx, g.n_xf, g.lds_xf, b->d_desc, g.xf, b->method, stage, g_twiddle, b->stream);
-        }))
-      return s;
-  }
-  return MM_OK;
+  if (!any_xfused(b)) return MM_OK;
+  return launch(b, "fft_x_forward", [&] {
+    return mmk_launch_xfwd_cells(b->method, stage, b->total_wg, b->d_desc, b->d_wg, g_twiddle, b->stage_lds,
+                                 b->stream);
+  });
 }
 
 // Run start.  RK4: reductions of the state (and, for groups with x passes in

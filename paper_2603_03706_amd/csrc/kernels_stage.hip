@@ -419,6 +419,34 @@ hipError_t mmk_launch_stage(int method, int stage, bool final_pass, int nblocks,
 }
 
 namespace mmk {
+// x-forward pass of a stage input that no stage kernel produced (the DP45
+// stage-2 input y + h a21 k1, the run-start state), for the instances whose
+// x passes run inside the stage kernels: each MMI_WG-cell workgroup of the
+// stage grid forms its cells' input and writes the X rows of its own x-rows
+// with the stage kernels' R2C.  Other instances return at once.
+__global__ __launch_bounds__(MMI_WG) void k_xfwd_cells(const InstDesc* __restrict__ descs,
+                                                      const int* __restrict__ wg_inst, int method, int stage,
+                                                      const float2* __restrict__ tw) {
+  extern __shared__ float2 xl[];
+  const int lblk = xcd_block();
+  const InstDesc& D = descs[wg_inst[lblk]];
+  const MMG InstCtl* __restrict__ C = gbl(D.ctl);
+  if (C->done || !D.xfused) return;
+  const int lw = lblk - D.wg0;
+  const int nc = D.ncell;
+  const int i = lw * MMI_WG + threadIdx.x;
+  const Src src = stage_src(D, C, method, stage);
+  const XRows xq = xrows_setup(D, lw, xl);
+  load_twiddles(xq.twl, xq.Px, tw, MMI_WG);
+  float v[3] = {0.f, 0.f, 0.f};
+  if (i < nc) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = src.ld(c * nc + i);
+  }
+  // the barrier at the start of the pass orders the twiddle stores too
+  xrows_r2c(D, xq, v, false);
+}
+
 __global__ void k_gather_done(const InstDesc* __restrict__ d, int count, int* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) {
@@ -428,6 +456,13 @@ __global__ void k_gather_done(const InstDesc* __restrict__ d, int count, int* __
   }
 }
 }  // namespace mmk
+
+hipError_t mmk_launch_xfwd_cells(int method, int stage, int nblocks, const InstDesc* descs, const int* wg,
+                                 const float2* tw, size_t lds, hipStream_t s) {
+  if (method != MMI_RK4 && method != MMI_DP45) return hipErrorInvalidValue;
+  MM_LAUNCH(mmk::k_xfwd_cells, dim3(nblocks), dim3(MMI_WG), lds, s, descs, wg, method, stage, tw);
+  return hipGetLastError();
+}
 
 hipError_t mmk_launch_gather_done(int count, const InstDesc* d, int* out, hipStream_t s) {
   MM_LAUNCH(mmk::k_gather_done, dim3((count + 63) / 64), dim3(64), 0, s, d, count, out);

@@ -12,6 +12,8 @@ int padded(int n);
 void kernel_spectrum(int nx, int ny, int nz, double dx, double dy, double dz, std::vector<float>& out);
 }  // namespace mmh
 
+hipError_t mmk_launch_xfwd_cells(int method, int stage, int nblocks, const InstDesc* descs, const int* wg,
+                                 const float2* tw, size_t lds, hipStream_t s);
 hipError_t mmk_launch_stage(int method, int stage, bool final_pass, int nblocks, int count,
                             const InstDesc* descs, const int* wg, const float2* tw, size_t lds,
                             hipStream_t stream);
