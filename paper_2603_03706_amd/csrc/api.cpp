@@ -1404,7 +1404,11 @@ double algorithmic_bytes(const mm_batch* b, const std::string& name) {
     const double X = 8.0 * g.kx * 3.0 * g.ny * g.nz;       // complex after the x pass
     const double Y = 8.0 * g.kx * 3.0 * g.nz * g.py;       // complex after the y pass
     const double kern = 4.0 * 6.0 * (g.pz / 2 + 1) * (g.py / 2 + 1) * g.kx;
-    if (name == "fft_x_forward") total += m * (12.0 * cells + X);
+    // x-forward: the stage input read once (two fields, y and k1, for the
+    // DP45 stage-2 input, the only one left to this pass when the stage
+    // kernels do the x passes) and the X rows written
+    const double xin = (b->method == MM_DP45 && g.xfused) ? 24.0 : 12.0;
+    if (name == "fft_x_forward") total += m * (xin * cells + X);
     if (name == "fft_x_inverse") total += m * (X + 12.0 * cells);
     if (name == "fft_yz_convolve") total += m * 2.0 * X + kern;
     if (name == "fft_y_forward" || name == "fft_y_inverse") total += m * (X + Y);
