@@ -999,6 +999,9 @@ mm_status capture_steps(mm_batch* b, int steps, hipGraph_t* graph, hipGraphExec_
   if (e != hipSuccess) return fail(MM_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
   *graph = g;
   MM_HIP(hipGraphInstantiate(exec, g, nullptr, nullptr, 0));
+  // move the executable graph to the device now rather than at its first
+  // launch, which may fall inside a caller's timed region
+  MM_HIP(hipGraphUpload(*exec, b->stream));
   return MM_OK;
 }
 
