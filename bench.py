@@ -419,23 +419,18 @@ def build_batch(n, tol):
     return insts, ctxs, mmcav.Batch(ctxs)
 
 
-def accepted(ctxs):
-    return sum(c.stats()["accepted"] for c in ctxs)
-
-
 def timed_steps(batch, ctxs, steps, tol, warmup=0, marks=False):
-    """Wall time of exactly `steps` attempted steps of an open run.  A
-    warm-up run of `warmup` steps captures the step graphs; the timed run is
-    begun (run parameters, run-start derivative) and the device drained
-    before the clock starts, and its statistics are read back after the
-    clock stops, so the timed region holds only the steps' graph launches.
-    Returns (seconds, accepted instance-steps of the timed run)."""
+    """Wall time of exactly `steps` attempted steps of an open run.  The run
+    is begun (run parameters, run-start derivative, step graphs captured and
+    uploaded), `warmup` untimed steps are run, the device is drained, and the
+    clock runs around the next `steps` steps of the same run (graph launches
+    only) and a device synchronisation; counts and statistics are read back
+    outside the clock.  Returns (seconds, accepted instance-steps of the
+    timed steps)."""
     import torch
     batch.begin(tol)
     batch.advance(warmup)
-    batch.end()
-    a0 = accepted(ctxs)
-    batch.begin(tol)
+    a0, _ = batch.counts()
     torch.cuda.synchronize()
     if marks:
         mark()
@@ -445,8 +440,9 @@ def timed_steps(batch, ctxs, steps, tol, warmup=0, marks=False):
     dt = time.perf_counter() - t0
     if marks:
         mark()
+    a1, _ = batch.counts()
     batch.end()
-    return dt, accepted(ctxs) - a0
+    return dt, a1 - a0
 
 
 def plain_rate(insts, k, steps, warmup, tol):

@@ -280,6 +280,14 @@ mm_status mm_batch_begin(mm_batch* b, double tol);
 mm_status mm_batch_advance(mm_batch* b, int64_t steps);
 mm_status mm_batch_end(mm_batch* b);
 
+/* Accepted and rejected step counts summed over the batch's instances, as
+ * they stand once the work enqueued so far has finished (the call waits for
+ * the batch's streams).  Read only, so it is allowed during an open run,
+ * e.g. between two mm_batch_advance calls; the counts are cumulative over
+ * every run of the instances, as in mm_get_stats.  NULL outputs are
+ * skipped. */
+mm_status mm_batch_counts(mm_batch* b, int64_t* accepted, int64_t* rejected);
+
 /* Autotune the batch.  With two or more instances it first times whole
  * steps (32 + 2 x 64 attempted steps) of the batch run as 1, 2 and 3
  * concurrent sub-batches (mm_batch_set_streams) and keeps the fastest; then,

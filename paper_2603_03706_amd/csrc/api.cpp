@@ -2373,6 +2373,23 @@ mm_status mm_batch_advance(mm_batch* b, int64_t steps) {
   return launch_steps(b, steps);
 }
 
+mm_status mm_batch_counts(mm_batch* b, int64_t* accepted, int64_t* rejected) {
+  if (!b) return fail(MM_ERR_ARG, "batch is NULL");
+  if (mm_status s = set_device(b->ctxs[0])) return s;
+  MM_HIP(hipStreamSynchronize(b->stream));
+  for (mm_batch* p : b->parts) MM_HIP(hipStreamSynchronize(p->stream));
+  int64_t acc = 0, rej = 0;
+  for (const mm_ctx* c : b->ctxs) {
+    InstCtl h;
+    if (mm_status s = ctl_pull(c, h)) return s;
+    acc += h.accepted;
+    rej += h.rejected;
+  }
+  if (accepted) *accepted = acc;
+  if (rejected) *rejected = rej;
+  return MM_OK;
+}
+
 mm_status mm_batch_end(mm_batch* b) {
   if (!b) return fail(MM_ERR_ARG, "batch is NULL");
   if (!b->open) return fail(MM_ERR_STATE, "no open run (mm_batch_begin first)");

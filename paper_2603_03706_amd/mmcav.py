@@ -80,6 +80,7 @@ _SIGS = {
     "mm_batch_profile": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double, ctypes.c_int32, _P, _P, _P, _P,
                                         ctypes.POINTER(ctypes.c_int32)]),
     "mm_batch_tune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_size_t]),
+    "mm_batch_counts": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "mm_batch_set_fft_path": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_batch_set_fft_x": (ctypes.c_int, [_P, ctypes.c_int32]),
     "mm_batch_set_streams": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -373,6 +374,13 @@ class Batch:
     def end(self):
         """Wait for the open run and read every instance's statistics back."""
         _check(self._lib.mm_batch_end(self.h))
+
+    def counts(self):
+        """(accepted, rejected) steps summed over the instances once the
+        enqueued work has finished; allowed during an open run."""
+        acc, rej = ctypes.c_int64(), ctypes.c_int64()
+        _check(self._lib.mm_batch_counts(self.h, ctypes.byref(acc), ctypes.byref(rej)))
+        return acc.value, rej.value
 
     def tune(self, streams=True):
         """Autotune the sub-batch count (unless streams=False) and the FFT

@@ -79,9 +79,13 @@ def test_open_run_refuses_other_calls():
         with pytest.raises(mmcav.MMError) as e:
             call()
         assert e.value.status == mmcav.MM_ERR_STATE
+    acc4, rej4 = b.counts()                  # read only: allowed in the open run
+    assert acc4 + rej4 == 2 * 4
     b.advance(4)
+    acc8, rej8 = b.counts()
     b.end()
     assert all(c.stats()["accepted"] + c.stats()["rejected"] == 8 for c in ctxs)
+    assert (acc8, rej8) == (sum(c.stats()["accepted"] for c in ctxs), sum(c.stats()["rejected"] for c in ctxs))
     ctxs[0].get_m()                          # usable again
     b.begin(1e-6)
     b.close()                                # destroy waits and closes the open run
