@@ -49,6 +49,13 @@ def yz_flops_per_item(ny, nz, py, pz):
     return 2 * 3 * nz * fft(py) + 2 * 3 * py * fft(pz) + 30.0 * py * pz
 
 
+def yz_planes(nx):
+    """(instance, kx) planes of the y-z convolution in complex-plane units:
+    the planes kx = 0 and Px/2 of the x transform of real rows are real, and
+    a real plane's transforms count half those of a complex one."""
+    return padded(nx) // 2
+
+
 def padded(n):
     p = 1
     while p < 2 * n:
@@ -683,7 +690,7 @@ def main():
             # bound by FP32 vector issue (rocprofv3 SQ counters: VALU busy
             # about 80 %, HBM about 15 %): priced against the VALU peak
             nx, ny, nz = insts[0].grid
-            flops = len(insts) * (padded(nx) // 2 + 1) * yz_flops_per_item(ny, nz, padded(ny), padded(nz))
+            flops = len(insts) * yz_planes(nx) * yz_flops_per_item(ny, nz, padded(ny), padded(nz))
             tf = flops / (top["avg_us"] * 1e-6) / 1e12
             roof = {"bound": "alu", "achieved": round(tf, 2), "peak": FP32_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(tf / FP32_PEAK_TFLOPS, 4),

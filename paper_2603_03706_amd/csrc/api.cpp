@@ -167,7 +167,8 @@ bool reg8_fits(int ny, int nz, int py, int pz) { return reg_fits(ny, nz, py, pz)
 // two register passes per line with an LDS exchange: padded y of 16..128, padded z of 32 or 64
 size_t xch_lds(int py, int pz) {
   return sizeof(float2) * ((size_t)3 * (pz / 2) * (py + mmk_yzx_pad()) + py + pz) +
-         sizeof(float) * 6 * (size_t)(pz / 2 + 1) * (py / 2 + 1);
+         sizeof(float) * 6 * (size_t)(pz / 2 + 1) * (py / 2 + 1) +
+         (mmk_yzx_pairs(py, pz) ? sizeof(float2) * 6 * (size_t)pz : 0);
 }
 // split passes with the two-pass y line transforms: padded y of 16..256
 bool splitx_fits(int py) { return mmk_sx_rows(py) > 0; }
@@ -619,10 +620,16 @@ mm_status build_group(mm_batch::Group& g, DevArena* arena = nullptr) {
   const int wy = sx ? mmk_sx_rows(g.py) : g.Wy;
   const int tiles_y = (ylines + wy - 1) / wy;
   const int ky_tiles = (g.py + g.TW - 1) / g.TW;
+  // The two-pass kernel may take planes 0 and Px/2 of an instance as one
+  // item (item 0), which takes longer than the others: these items go first,
+  // so that none of them starts in the launch's last round.
+  const bool pairs = g.path == PATH_XCH && g.kx > 1 && mmk_yzx_pairs(g.py, g.pz);
+  if (pairs)
+    for (int m : g.members) yz.push_back({m, 0});
   for (int m : g.members) {
     for (int t = 0; t < tiles_x; ++t) xf.push_back({m, t});
     if (g.path != PATH_SPLIT && !sx) {
-      for (int k = 0; k < g.kx; ++k) yz.push_back({m, k});
+      for (int k = pairs ? 1 : 0; k < (pairs ? g.kx - 1 : g.kx); ++k) yz.push_back({m, k});
     } else {
       for (int t = 0; t < tiles_y; ++t) yy.push_back({m, t});
       for (int k = 0; k < g.kx * ky_tiles; ++k) zc.push_back({m, k});

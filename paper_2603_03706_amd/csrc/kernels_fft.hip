@@ -16,6 +16,7 @@
 // transforms by decimation in frequency (bit-reversed output), inverse
 // transforms by decimation in time (bit-reversed input), so no reordering
 // pass is needed between them.
+#include <type_traits>
 #include "mm_internal.h"
 #include "kernels_common.h"
 #include "launch.h"
@@ -961,12 +962,56 @@ struct YRow {
 #pragma unroll
       for (int p = 0; p < N; ++p) line[lam + N * j + Q * brevc(p, LP::lgL)] = u[j][p];
   }
+  // Two real rows A, B transformed as one row A + iB: afterwards slot
+  // SM::of(0, k) holds A[k] = (X[k] + conj X[P-k]) / 2 and SM::of(1, k) holds
+  // B[k] = (X[k] - conj X[P-k]) / 2i for k < P/2, except that the real values
+  // at k = 0 and P/2 share the slots of k = 0: (A[0], A[P/2]) and (B[0], B[P/2]).
+  template <class SM>
+  __device__ static void split_pair(float2* line, int lam) {
+    constexpr int H = P / 2, NI = H / N;
+    float2 r[NI], q[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int k = lam + N * i;
+      r[i] = line[k];
+      q[i] = line[k == 0 ? H : P - k];
+    }
+    wave_lds_order();
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      const int k = lam + N * i;
+      const bool z = k == 0;
+      line[SM::of(0, k)] = z ? make_float2(r[i].x, q[i].x) : make_float2(0.5f * (r[i].x + q[i].x), 0.5f * (r[i].y - q[i].y));
+      line[SM::of(1, k)] = z ? make_float2(r[i].y, q[i].y) : make_float2(0.5f * (r[i].y + q[i].y), 0.5f * (q[i].x - r[i].x));
+    }
+  }
+  // The inverse's input at k = k1 + Q k2 from two half spectra laid out as
+  // split_pair leaves them (both of real rows, so X[P-k] = conj X[k]):
+  // A[k] + i B[k], whose inverse has A's row as real and B's as imaginary part.
+  template <class SM>
+  __device__ static float2 pair_value(const float2* line, int k1, int k2) {
+    constexpr int H = P / 2;
+    if (k2 < N / 2) {                            // k < P/2
+      const int k = k1 + Q * k2;
+      const float2 a = line[SM::of(0, k)], b = line[SM::of(1, k)];
+      return k == 0 ? make_float2(a.x, b.x) : make_float2(a.x - b.y, a.y + b.x);
+    }
+    const int m = P - (k1 + Q * k2);             // 1 .. P/2
+    const int i = m == H ? 0 : m;
+    const float2 a = line[SM::of(0, i)], b = line[SM::of(1, i)];
+    return m == H ? make_float2(a.y, b.y) : make_float2(a.x + b.y, b.x - a.y);
+  }
+  // SM = void: a plain row; else two half spectra (split_pair's layout)
+  template <class SM = void>
   __device__ static void inverse(float2* line, int lam, const Tw& w) {
     float2 g[Q / N][N];
 #pragma unroll
     for (int j = 0; j < Q / N; ++j) {
 #pragma unroll
-      for (int k2 = 0; k2 < N; ++k2) g[j][k2] = line[lam + N * j + Q * k2];
+      for (int k2 = 0; k2 < N; ++k2) {
+        if constexpr (std::is_void_v<SM>) g[j][k2] = line[lam + N * j + Q * k2];
+        else g[j][k2] = pair_value<SM>(line, lam + N * j, k2);
+      }
       dif_stages<N, true, N / 2>(g[j]);
     }
     wave_lds_order();
@@ -1008,14 +1053,15 @@ struct ZCol {
 #pragma unroll
       for (int n1 = 0; n1 < N; ++n1) w.wv[j][n1] = conjf2(j == 0 ? w.wf[n1] : tw[n1 * (lam + N * j)]);
   }
-  template <class KMul>
-  __device__ static void convolve(float2* col, int RS, int nz, int lam, const Tw& w, KMul&& kmul) {
+  using Spec = float2[3][Q / N][N];
+  // frequency of sp[c][j][p] after forward(): k1 + Q brev(p), k1 = lam + N j
+  __device__ static int kz_of(int lam, int j, int p) { return lam + N * j + Q * brevc(p, LP::lgL); }
+  __device__ static void forward(float2* col, int RS, int lam, const Tw& w, Spec& sp) {
     float2 xin[3][Q / 2];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int n1 = 0; n1 < Q / 2; ++n1) xin[c][n1] = col[(c * ZR + N * n1 + lam) * RS];
-    float2 sp[3][Q / N][N];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float2 v[Q];
@@ -1037,11 +1083,10 @@ struct ZCol {
       }
       wave_lds_order();
     }
-    // sp[c][j][p] = X_c[k1 + Q brev(p)], k1 = lam + N j
-#pragma unroll
-    for (int j = 0; j < Q / N; ++j)
-#pragma unroll
-      for (int p = 0; p < N; ++p) kmul(lam + N * j + Q * brevc(p, LP::lgL), sp[0][j][p], sp[1][j][p], sp[2][j][p]);
+  }
+  // inverse z of sp (the column's slots are the exchange area); rows z < nz
+  // receive the result
+  __device__ static void inverse(float2* col, int RS, int nz, int lam, const Tw& w, Spec& sp) {
     float2 res[3][Q / 2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1075,6 +1120,16 @@ struct ZCol {
         if (z < nz) col[(c * ZR + z) * RS] = res[c][n2];
       }
   }
+  template <class KMul>
+  __device__ static void convolve(float2* col, int RS, int nz, int lam, const Tw& w, KMul&& kmul) {
+    Spec sp;
+    forward(col, RS, lam, w, sp);
+#pragma unroll
+    for (int j = 0; j < Q / N; ++j)
+#pragma unroll
+      for (int p = 0; p < N; ++p) kmul(kz_of(lam, j, p), sp[0][j][p], sp[1][j][p], sp[2][j][p]);
+    inverse(col, RS, nz, lam, w, sp);
+  }
 };
 
 // LDS bank layout shared by the kernels below (64 banks of four bytes; an
@@ -1099,10 +1154,44 @@ __device__ __forceinline__ int zcol_of(int t) {
   return wz % SZ + SZ * ((t & 63) / N) + SZ * CPW * (wz / SZ);
 }
 
-template <int MY, int MZ, int RPAD>
-__global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 32 ? 2 : 4, MY >= 32 ? 2 : 4))) void k_fft_yzx(
-    const InstDesc* __restrict__ descs, const WorkItem* __restrict__ work, const float2* __restrict__ tw,
-    int nyz, int fmethod, int fstage) {
+// Planes kx = 0 and kx = Px/2 of the x transform of real rows are real, and
+// in them the tensor components odd in x (xy, xz) vanish, so each plane's y-z
+// convolution is real as well.  Where one column per thread covers the padded
+// y range (Py NZ = MM_YZX_T), work item 0 of an instance carries both planes,
+// as A + iB through the forward y pass, which YRow::split_pair turns into the
+// two half spectra (ky <= Py/2 of each; the real columns ky = 0 and Py/2 of a
+// plane share one slot).  The z columns are then the columns of the two half
+// spectra, placed so that plane 0's fall in the first half of the
+// workgroup's wavefronts and plane Px/2's in the second: the first half
+// multiplies with the kernel of plane 0, then the second with that of plane
+// Px/2.  A shared column holds U + iV of two real columns U (ky = 0) and V
+// (ky = Py/2), whose spectra it separates as U[kz] = (Z[kz] + conj Z[-kz]) / 2
+// and V[kz] = (Z[kz] - conj Z[-kz]) / 2i, from a copy in LDS worked on by the
+// idle half.  The inverse y transforms A + iB rebuilt from the half spectra,
+// and the real and imaginary parts go back to the two planes.  An instance
+// then has Px/2 work items instead of Px/2 + 1.
+template <int PY, int PZ>
+struct YzxPairs {
+  static constexpr int NZ = ZCol<PZ>::N, NW = MM_YZX_T / 64;
+  static constexpr bool on = PY * NZ == MM_YZX_T;
+  // zcol_of<NZ, PY> gives wavefront w the columns s with s mod SZ = w mod SZ
+  // and s / (SZ CPW) = w / SZ.  Slot of half-spectrum column k of plane hi
+  // (0: plane 0, 1: plane Px/2) such that plane 0's columns fall in
+  // wavefronts 0 .. NW/2 - 1 and plane Px/2's in the others:
+  static constexpr int CPW = 64 / NZ, SZ = NZ < PY / CPW ? NZ : PY / CPW;
+  static_assert(!on || SZ == NW || (2 * SZ == NW && SZ * CPW == PY / 2), "column layout");
+  __device__ static int of(int hi, int k) {
+    if constexpr (SZ == NW) return k % (SZ / 2) + SZ * (k / (SZ / 2)) + hi * (SZ / 2);
+    else return k + hi * (PY / 2);
+  }
+  __device__ static int ky_of(int s) {
+    if constexpr (SZ == NW) return s % (SZ / 2) + (SZ / 2) * (s / SZ);
+    else return s & (PY / 2 - 1);
+  }
+};
+
+template <int MY, int MZ, int RPAD, bool PAIR>
+__device__ __forceinline__ void yzx_item(const InstDesc& D, int kx, const float2* __restrict__ tw, float2* lds) {
   constexpr int PY = 4 * MY, PZ = 4 * MZ, RS = PY + RPAD, ZR = 2 * MZ, YR = 2 * MY;
   using YR_ = YRow<PY>;
   using ZC = ZCol<PZ>;
@@ -1111,27 +1200,21 @@ __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 
   constexpr int RPW = 64 / NY;                  // y rows per wavefront
   constexpr int NW = MM_YZX_T / 64;             // wavefronts per workgroup
   constexpr int SY = NY / 2;
-  extern __shared__ float2 lds[];
-  if ((int)blockIdx.x >= nyz) {
-    final_any(fmethod, fstage, descs, (int)blockIdx.x - nyz, reinterpret_cast<double*>(lds));
-    return;
-  }
+  static_assert(!PAIR || YzxPairs<PY, PZ>::on, "paired planes need one z column per thread");
   float2* B = lds;
   float2* twy = B + 3 * ZR * RS;
   float2* twz = twy + PY;
   float* Ks = reinterpret_cast<float*>(twz + PZ);
   constexpr int HY1 = PY / 2 + 1, KPL = (PZ / 2 + 1) * HY1;
+  float2* Pk = reinterpret_cast<float2*>(Ks + 6 * KPL);   // PAIR: copies of the two shared columns' spectra
   constexpr int NK = (6 * KPL + MM_YZX_T - 1) / MM_YZX_T, NXE = 3 * ZR * PY;
   constexpr int NX = (NXE + MM_YZX_T - 1) / MM_YZX_T;
   load_twiddles(twy, PY, tw, MM_YZX_T);
   load_twiddles(twz, PZ, tw, MM_YZX_T);
-  const WorkItem wi = work[blockIdx.x];
-  const InstDesc& D = descs[wi.inst];
-  if (gbl(D.ctl)->done) return;
-  const int kx = wi.item;
   const int ny = D.ny, nz = D.nz;
   const int nrow = 3 * nz;
   MMG float2* X = gbl(D.fx) + (size_t)kx * nrow * ny;
+  MMG float2* X2 = gbl(D.fx) + (size_t)(D.kx - 1) * nrow * ny;   // PAIR: plane Px/2
   // Loads: thread t takes column y = t mod Py of rows it * RPI + t / Py.  The
   // row's (c, z) and the X offset (c nz + z) ny + y are a per-thread part
   // plus a part uniform over the workgroup, so each element costs a compare,
@@ -1155,7 +1238,8 @@ __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 
       const int z = (ZR % RPI == 0) ? (it * RPI) % ZR + r0 : row % ZR;
       const bool in = row < 3 * ZR && yin && z < nz;
       const int off = (ZR % RPI == 0) ? (c * nz + (it * RPI) % ZR) * ny + tb : (c * nz + z) * ny + y;
-      const float2 v = gld2(X + (in ? off : 0));
+      float2 v = gld2(X + (in ? off : 0));
+      if constexpr (PAIR) v = make_float2(v.x, gld2(X2 + (in ? off : 0)).x);
       xv[it] = make_float2(in ? v.x : 0.f, in ? v.y : 0.f);
     }
 #pragma unroll
@@ -1178,7 +1262,10 @@ __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 
 #pragma unroll 1
   for (int g0 = wave / SY; 32 * g0 < 3 * ZR; g0 += NW / SY) {
     const int rho = yrow_of<NY>(g0, wave, yrl);
-    if (rho < 3 * ZR && (rho & (ZR - 1)) < nz) YR_::forward(B + rho * RS, ylam, wy);
+    if (rho < 3 * ZR && (rho & (ZR - 1)) < nz) {
+      YR_::forward(B + rho * RS, ylam, wy);
+      if constexpr (PAIR) YR_::template split_pair<YzxPairs<PY, PZ>>(B + rho * RS, ylam);
+    }
   }
   __syncthreads();
   // z columns
@@ -1186,20 +1273,107 @@ __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 
     const int lam = threadIdx.x & (NZ - 1);
     typename ZC::Tw wz;
     ZC::twiddles(wz, twz, lam);
+    if constexpr (!PAIR) {
 #pragma unroll 1
-    for (int t = threadIdx.x; t < NZ * PY; t += MM_YZX_T) {
-      const int ky = zcol_of<NZ, PY>(t);
-      ZC::convolve(B + ky, RS, nz, lam, wz, [&](int kz, float2& a, float2& b, float2& c) {
-        kernel_mul_lds<PY, PZ>(Ks, ky, kz, a, b, c);
-      });
+      for (int t = threadIdx.x; t < NZ * PY; t += MM_YZX_T) {
+        const int ky = zcol_of<NZ, PY>(t);
+        ZC::convolve(B + ky, RS, nz, lam, wz, [&](int kz, float2& a, float2& b, float2& c) {
+          kernel_mul_lds<PY, PZ>(Ks, ky, kz, a, b, c);
+        });
+      }
+    } else {
+      // the kernel of plane Px/2, for the second half of the multiply (its
+      // loads complete during the forward z)
+      float kv2[NK];
+      {
+        const MMG float* K2 = gbl(D.kern) + (size_t)(D.kx - 1) * 6 * KPL;
+#pragma unroll
+        for (int it = 0; it < NK; ++it) kv2[it] = K2[min(it * MM_YZX_T + (int)threadIdx.x, 6 * KPL - 1)];
+      }
+      using PS = YzxPairs<PY, PZ>;
+      const int s = zcol_of<NZ, PY>(threadIdx.x);
+      const bool hi = wave >= NW / 2;           // columns of plane Px/2 (uniform per wavefront)
+      const int ky = PS::ky_of(s);
+      const bool shared = ky == 0;              // the column of ky = 0 and Py/2
+      typename ZC::Spec sp;
+      ZC::forward(B + s, RS, lam, wz, sp);
+      if (shared) {
+        float2* pk = Pk + (hi ? 3 * PZ : 0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int j = 0; j < ZC::Q / NZ; ++j)
+#pragma unroll
+            for (int p = 0; p < NZ; ++p) pk[c * PZ + ZC::kz_of(lam, j, p)] = sp[c][j][p];
+      }
+      __syncthreads();
+      // Multiply with the kernel in Ks: one half of the workgroup multiplies
+      // its columns while lanes kz < Pz of the other half (one wavefront) do
+      // the shared column of the same plane on its copy, each forming U[kz]
+      // and V[kz] from Z[kz] and Z[-kz].
+      auto columns = [&]() {
+        if (shared) return;
+#pragma unroll
+        for (int j = 0; j < ZC::Q / NZ; ++j)
+#pragma unroll
+          for (int p = 0; p < NZ; ++p)
+            kernel_mul_lds<PY, PZ>(Ks, ky, ZC::kz_of(lam, j, p), sp[0][j][p], sp[1][j][p], sp[2][j][p]);
+      };
+      auto shared_col = [&](float2* pk) {
+        const int kz = threadIdx.x & (MM_YZX_T / 2 - 1);
+        if (kz >= PZ) return;
+        const int mz = (PZ - kz) & (PZ - 1);
+        float2 u[3], v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float2 zk = pk[c * PZ + kz], zm = pk[c * PZ + mz];
+          u[c] = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+          v[c] = make_float2(0.5f * (zk.y + zm.y), 0.5f * (zm.x - zk.x));
+        }
+        wave_lds_order();                       // all of the copy read before it is overwritten
+        kernel_mul_lds<PY, PZ>(Ks, 0, kz, u[0], u[1], u[2]);
+        kernel_mul_lds<PY, PZ>(Ks, PY / 2, kz, v[0], v[1], v[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pk[c * PZ + kz] = make_float2(u[c].x - v[c].y, u[c].y + v[c].x);
+      };
+      auto read_back = [&](const float2* pk) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int j = 0; j < ZC::Q / NZ; ++j)
+#pragma unroll
+            for (int p = 0; p < NZ; ++p) sp[c][j][p] = pk[c * PZ + ZC::kz_of(lam, j, p)];
+      };
+      if (!hi) columns(); else shared_col(Pk);                   // kernel of plane 0
+      __syncthreads();
+      if (!hi && shared) read_back(Pk);
+      // the kernel of plane Px/2 replaces it
+#pragma unroll
+      for (int it = 0; it < NK; ++it) {
+        const int e = it * MM_YZX_T + threadIdx.x;
+        if (e < 6 * KPL) Ks[e] = kv2[it];
+      }
+      __syncthreads();
+      if (hi) columns(); else shared_col(Pk + 3 * PZ);
+      __syncthreads();
+      if (hi && shared) read_back(Pk + 3 * PZ);
+      ZC::inverse(B + s, RS, nz, lam, wz, sp);
     }
   }
   __syncthreads();
-  // inverse y of the rows z < nz, cropped to y < Py/2
+  // inverse y of the rows z < nz, cropped to y < Py/2 (the paired path takes
+  // its y twiddles again here: keeping them, or their LDS addresses, through
+  // its z pass spills; the empty asm makes the lane index opaque)
+  if constexpr (PAIR) {
+    int yl = ylam;
+    asm volatile("" : "+v"(yl));
+    YR_::twiddles(wy, twy, yl);
+  }
 #pragma unroll 1
   for (int g0 = wave / SY; 32 * g0 < 3 * ZR; g0 += NW / SY) {
     const int rho = yrow_of<NY>(g0, wave, yrl);
-    if (rho < 3 * ZR && (rho & (ZR - 1)) < nz) YR_::inverse(B + rho * RS, ylam, wy);
+    if (rho < 3 * ZR && (rho & (ZR - 1)) < nz)
+      YR_::template inverse<std::conditional_t<PAIR, YzxPairs<PY, PZ>, void>>(B + rho * RS, ylam, wy);
   }
   __syncthreads();
   {
@@ -1214,9 +1388,38 @@ __global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 
       const int c = (ZR % RPO == 0) ? (it * RPO) / ZR : row / ZR;
       const int z = (ZR % RPO == 0) ? (it * RPO) % ZR + r0 : row % ZR;
       const int off = (ZR % RPO == 0) ? (c * nz + (it * RPO) % ZR) * ny + tb : (c * nz + z) * ny + y;
-      if (row < 3 * ZR && z < nz && yin) gst2(X + off, B[row * RS + y]);
+      if (row < 3 * ZR && z < nz && yin) {
+        const float2 v = B[row * RS + y];
+        if constexpr (PAIR) {
+          gst2(X + off, make_float2(v.x, 0.f));
+          gst2(X2 + off, make_float2(v.y, 0.f));
+        } else {
+          gst2(X + off, v);
+        }
+      }
     }
   }
+}
+
+template <int MY, int MZ, int RPAD>
+__global__ __launch_bounds__(MM_YZX_T) __attribute__((amdgpu_waves_per_eu(MY >= 32 ? 2 : 4, MY >= 32 ? 2 : 4))) void k_fft_yzx(
+    const InstDesc* __restrict__ descs, const WorkItem* __restrict__ work, const float2* __restrict__ tw,
+    int nyz, int fmethod, int fstage) {
+  extern __shared__ float2 lds[];
+  if ((int)blockIdx.x >= nyz) {
+    final_any(fmethod, fstage, descs, (int)blockIdx.x - nyz, reinterpret_cast<double*>(lds));
+    return;
+  }
+  const WorkItem wi = work[blockIdx.x];
+  const InstDesc& D = descs[wi.inst];
+  if (gbl(D.ctl)->done) return;
+  if constexpr (YzxPairs<4 * MY, 4 * MZ>::on) {
+    if (wi.item == 0 && D.kx > 1) {
+      yzx_item<MY, MZ, RPAD, true>(D, 0, tw, lds);
+      return;
+    }
+  }
+  yzx_item<MY, MZ, RPAD, false>(D, wi.item, tw, lds);
 }
 
 // ------------------------ split y passes with the same line transforms (T = 512)
@@ -1728,6 +1931,9 @@ hipError_t mmk_launch_fft_yzx(int MY, int MZ, int nblocks, size_t lds, const Ins
   return hipErrorInvalidValue;
 }
 int mmk_yzx_pad() { return MM_YZX_PAD; }
+bool mmk_yzx_pairs(int py, int pz) {
+  return (pz == 32 && mmk::YzxPairs<128, 32>::on && py == 128) || (pz == 64 && mmk::YzxPairs<64, 64>::on && py == 64);
+}
 
 hipError_t mmk_launch_fft_ysx(int dir, int py, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                               const float2* tw, hipStream_t s, int nfinal, int fmethod, int fstage) {

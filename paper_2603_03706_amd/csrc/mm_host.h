@@ -38,6 +38,9 @@ hipError_t mmk_launch_fft_yzx(int MY, int MZ, int nblocks, size_t lds, const Ins
                               const float2* tw, hipStream_t s, int nfinal = 0, int fmethod = 0,
                               int fstage = 0);
 int mmk_yzx_pad();
+// k_fft_yzx for padded (py, pz) carries the real planes kx = 0 and Px/2 of an
+// instance in one work item (item 0; no item Px/2), with 6 pz float2 more LDS
+bool mmk_yzx_pairs(int py, int pz);
 hipError_t mmk_launch_fft_ysx(int dir, int py, int nblocks, size_t lds, const InstDesc* d, const WorkItem* w,
                               const float2* tw, hipStream_t s, int nfinal = 0, int fmethod = 0,
                               int fstage = 0);
