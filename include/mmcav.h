@@ -91,8 +91,9 @@ typedef struct {
 } mm_stats;
 
 /* Create a context for one instance.  Validates the parameters (grid >= 1,
- * cells > 0, Ms > 0, gamma > 0, alpha >= 0, demag in range, sublattices in
- * {1, 2}; FFT demag needs sublattices == 1 and padded sizes <= 1024) and
+ * nx ny nz sublattices <= 2^26, cells > 0, Ms > 0, gamma > 0, alpha >= 0,
+ * demag in range, sublattices in {1, 2}; FFT demag needs sublattices == 1
+ * and padded sizes <= 1024) and
  * copies the geometry.  Allocates no device memory.  *out is set only on
  * success. */
 mm_status mm_create(const mm_params* p, mm_ctx** out);

@@ -44,6 +44,7 @@ constexpr int kStepsPerGraph = 32;
 // Sub-batches (streams) a new batch runs as; mm_batch_tune may choose more.
 constexpr int kDefaultParts = 1;
 constexpr int kMaxTunedParts = 3;
+constexpr long long kMaxCellsSublattices = 1LL << 26;   // cells x sublattices of one instance
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -246,6 +247,10 @@ mm_status validate(const mm_params* p) {
     return fail(MM_ERR_ARG, "non-finite material parameter");
   if (p->demag < MM_DEMAG_NONE || p->demag > MM_DEMAG_FFT) return fail(MM_ERR_ARG, "demag mode out of range");
   if (p->sublattices != 1 && p->sublattices != 2) return fail(MM_ERR_ARG, "sublattices must be 1 or 2");
+  // the kernels address an instance's fields with unsigned 32-bit byte
+  // offsets (at most 48 bytes per cell and sublattice)
+  if ((long long)p->nx * p->ny * p->nz * p->sublattices > kMaxCellsSublattices)
+    return fail(MM_ERR_ARG, "grid too large: cells x sublattices must be <= 2^26");
   if (p->demag == MM_DEMAG_FFT) {
     if (p->sublattices != 1) return fail(MM_ERR_ARG, "FFT demag needs sublattices == 1");
     if (mmh::padded(p->nx) > MMI_TW_LEN || mmh::padded(p->ny) > MMI_TW_LEN || mmh::padded(p->nz) > MMI_TW_LEN)

@@ -27,14 +27,27 @@ __device__ __forceinline__ void gst2(MMG float2* p, float2 v) {
   q[1] = v.y;
 }
 
+// Element i of a global array through a scalar base and an unsigned 32-bit
+// byte offset (i >= 0 and i * sizeof(T) < 2^32; the host bounds instance
+// sizes accordingly): with a signed index every lane would form a 64-bit
+// address (sign extension and a 64-bit add per access).
+template <class T>
+__device__ __forceinline__ const MMG T& gat(const MMG T* p, int i) {
+  return *(const MMG T*)((const MMG char*)p + (uint32_t)i * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ MMG T& gat(MMG T* p, int i) {
+  return *(MMG T*)((MMG char*)p + (uint32_t)i * (uint32_t)sizeof(T));
+}
+
 // Stage input m = p0 + c1 * p1 (p1 optional), component-major per instance.
 struct Src {
   const MMG float* p0;
   const MMG float* p1;
   float c1;
   __device__ __forceinline__ float ld(int idx) const {
-    float v = p0[idx];
-    if (p1) v = fmaf(c1, p1[idx], v);
+    float v = gat(p0, idx);
+    if (p1) v = fmaf(c1, gat(p1, idx), v);
     return v;
   }
 };
@@ -48,8 +61,8 @@ struct SrcFixed {
   float c1;
   __device__ __forceinline__ explicit SrcFixed(const Src& s) : p0(s.p0), p1(s.p1), c1(s.c1) {}
   __device__ __forceinline__ float ld(int idx) const {
-    float v = p0[idx];
-    if (TWO) v = fmaf(c1, p1[idx], v);
+    float v = gat(p0, idx);
+    if (TWO) v = fmaf(c1, gat(p1, idx), v);
     return v;
   }
 };
@@ -116,7 +129,7 @@ __device__ __forceinline__ void field_at(const InstDesc& D, const SRC& src, int 
     const MMG uint8_t* G = gbl(D.geom);
     uint8_t g[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) g[q] = G[jn[q]];
+    for (int q = 0; q < 6; ++q) g[q] = gat(G, jn[q]);
 #pragma unroll
     for (int q = 0; q < 6; ++q) jn[q] = g[q] ? jn[q] : i;
   }
@@ -155,9 +168,9 @@ __device__ __forceinline__ void field_at(const InstDesc& D, const SRC& src, int 
     bz += bdv[2];
   } else if (has_bd) {
     const MMG float* bd = gbl(D.bd);
-    bx += bd[i];
-    by += bd[nc + i];
-    bz += bd[2 * nc + i];
+    bx += gat(bd, i);
+    by += gat(bd, nc + i);
+    bz += gat(bd, 2 * nc + i);
   }
   bx = fmaf(D.csign[s], fb, bx);
   if (D.S == 2) {

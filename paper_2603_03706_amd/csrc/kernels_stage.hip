@@ -115,7 +115,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   const int nc = D.ncell;
   const int i = lw * MMI_WG + threadIdx.x;
   const bool valid = i < nc;
-  const bool mag = valid && (!D.has_geom || gbl(D.geom)[i]);
+  const bool mag = valid && (!D.has_geom || gat(gbl(D.geom), i));
   const int cur = C->cur;
   const double h = C->h;
   const int S = D.S;
@@ -220,10 +220,10 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const int idx = (s * 3 + c) * nc + i;
-        if (needY) yv[s][c] = Y[idx];
+        if (needY) yv[s][c] = gat(Y, idx);
 #pragma unroll
         for (int j = 0; j < 6; ++j)
-          if (usedK & (1u << j)) kl[j][s][c] = K[j][idx];
+          if (usedK & (1u << j)) kl[j][s][c] = gat(K[j], idx);
       }
     }
 #pragma unroll
@@ -237,57 +237,57 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
           if (ST == 0) {
             nx_[s][c] = m[s][c];
           } else if (ST == 1) {
-            K[0][idx] = kk;
+            gat(K[0], idx) = kk;
             nx_[s][c] = fmaf((float)(0.5 * h), kk, m[s][c]);
-            st0[idx] = nx_[s][c];
+            gat(st0, idx) = nx_[s][c];
           } else if (ST == 2 || ST == 3) {
             const float acc = fmaf(2.f, kk, kl[0][s][c]);
-            K[0][idx] = acc;
+            gat(K[0], idx) = acc;
             const float cc = (float)(ST == 3 ? h : 0.5 * h);
             nx_[s][c] = fmaf(cc, kk, yv[s][c]);
-            (ST == 2 ? st1 : st0)[idx] = nx_[s][c];
+            gat(ST == 2 ? st1 : st0, idx) = nx_[s][c];
           } else {  // ST == 4
             nx_[s][c] = fmaf((float)(h / 6.0), kl[0][s][c] + kk, yv[s][c]);
           }
         } else {
           if (ST == 1) {
-            K[0][idx] = kk;
+            gat(K[0], idx) = kk;
             nx_[s][c] = m[s][c];
           } else if (ST == 2) {
-            K[1][idx] = kk;
+            gat(K[1], idx) = kk;
             aux[s][c] = m[s][c];
             nx_[s][c] = yv[s][c] + ((float)(h * P::a31) * kl[0][s][c] + (float)(h * P::a32) * kk);
-            st0[idx] = nx_[s][c];
+            gat(st0, idx) = nx_[s][c];
           } else if (ST == 3) {
-            K[2][idx] = kk;
+            gat(K[2], idx) = kk;
             nx_[s][c] = yv[s][c] + ((float)(h * P::a41) * kl[0][s][c] +
                                   (float)(h * P::a42) * kl[1][s][c] +
                                   (float)(h * P::a43) * kk);
-            st1[idx] = nx_[s][c];
+            gat(st1, idx) = nx_[s][c];
           } else if (ST == 4) {
-            K[3][idx] = kk;
+            gat(K[3], idx) = kk;
             nx_[s][c] = yv[s][c] + ((float)(h * P::a51) * kl[0][s][c] +
                                   (float)(h * P::a52) * kl[1][s][c] +
                                   (float)(h * P::a53) * kl[2][s][c] +
                                   (float)(h * P::a54) * kk);
-            st0[idx] = nx_[s][c];
+            gat(st0, idx) = nx_[s][c];
           } else if (ST == 5) {
-            K[4][idx] = kk;
+            gat(K[4], idx) = kk;
             nx_[s][c] = yv[s][c] + ((float)(h * P::a61) * kl[0][s][c] +
                                   (float)(h * P::a62) * kl[1][s][c] +
                                   (float)(h * P::a63) * kl[2][s][c] +
                                   (float)(h * P::a64) * kl[3][s][c] +
                                   (float)(h * P::a65) * kk);
-            st1[idx] = nx_[s][c];
+            gat(st1, idx) = nx_[s][c];
           } else if (ST == 6) {
-            K[5][idx] = kk;
+            gat(K[5], idx) = kk;
             nx_[s][c] = yv[s][c] + ((float)(h * P::b1) * kl[0][s][c] +
                                   (float)(h * P::b3) * kl[2][s][c] +
                                   (float)(h * P::b4) * kl[3][s][c] +
                                   (float)(h * P::b5) * kl[4][s][c] +
                                   (float)(h * P::b6) * kk);
           } else {  // ST == 7
-            K[6][idx] = kk;
+            gat(K[6], idx) = kk;
             const float e = (float)P::e1 * kl[0][s][c] + (float)P::e3 * kl[2][s][c] +
                             (float)P::e4 * kl[3][s][c] +
                             (float)P::e5 * kl[4][s][c] +
@@ -314,9 +314,9 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
         nx_[s][1] = v1;
         nx_[s][2] = v2;
         MMG float* Yn = gbl(D.y[1 - cur]);
-        Yn[(s * 3 + 0) * nc + i] = v0;
-        Yn[(s * 3 + 1) * nc + i] = v1;
-        Yn[(s * 3 + 2) * nc + i] = v2;
+        gat(Yn, (s * 3 + 0) * nc + i) = v0;
+        gat(Yn, (s * 3 + 1) * nc + i) = v1;
+        gat(Yn, (s * 3 + 2) * nc + i) = v2;
       }
     }
   }

@@ -56,8 +56,8 @@ __device__ __forceinline__ void xrows_c2r(const InstDesc& D, const XRows& q, flo
     const int j2 = e & (q.J - 1), rest = e >> q.lgJ;
     const int k = rest / 3, c = rest - 3 * k;
     const int j = 2 * j2;
-    const MMG float2* row = X + (size_t)k * q.rows + c * q.nyz + q.yz0;
-    float2 a = gld2(row + min(j, q.nrow - 1)), b = gld2(row + min(j + 1, q.nrow - 1));
+    const int e0 = k * q.rows + c * q.nyz + q.yz0;
+    float2 a = gld2(&gat(X, e0 + min(j, q.nrow - 1))), b = gld2(&gat(X, e0 + min(j + 1, q.nrow - 1)));
     if (j >= q.nrow) a = make_float2(0.f, 0.f);
     if (j + 1 >= q.nrow) b = make_float2(0.f, 0.f);
     const bool edge = k == 0 || k == half;
@@ -127,7 +127,7 @@ __device__ __forceinline__ void xrows_r2c(const InstDesc& D, const XRows& q, con
     const float2* zc = q.zb + c * q.cs + j2;
     const float2 Z = zc[brev(k & (q.Px - 1), q.lgx) * q.es];
     const float2 Zm = zc[brev((q.Px - k) & (q.Px - 1), q.lgx) * q.es];
-    MMG float2* row = X + (size_t)k * q.rows + c * q.nyz + q.yz0 + j;
+    MMG float2* row = &gat(X, k * q.rows + c * q.nyz + q.yz0 + j);
     gst2(row, make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y)));
     if (j + 1 < q.nrow) gst2(row + 1, make_float2(0.5f * (Z.y + Zm.y), -0.5f * (Z.x - Zm.x)));
   }

@@ -50,6 +50,23 @@ def test_create_rejects_invalid_parameters(bad):
     assert len(L.mm_last_error()) > 0
 
 
+def test_create_bounds_cells_times_sublattices():
+    """The kernels address an instance's fields with unsigned 32-bit byte
+    offsets, so cells x sublattices is bounded by 2^26 (accepted exactly at
+    the bound, refused one cell beyond it, for one and two sublattices)."""
+    L = mmcav.lib()
+    for grid, sub, ok in (((512, 512, 256), 1, True), ((512, 512, 257), 1, False),
+                          ((512, 512, 128), 2, True), ((512, 512, 129), 2, False)):
+        p, _ = _params(grid=grid, sublattices=sub)
+        h = ctypes.c_void_p()
+        st = L.mm_create(ctypes.byref(p), ctypes.byref(h))
+        assert st == (mmcav.MM_OK if ok else mmcav.MM_ERR_ARG), (grid, sub)
+        if ok:
+            assert L.mm_destroy(h) == mmcav.MM_OK
+        else:
+            assert h.value is None and b"too large" in L.mm_last_error()
+
+
 def test_create_destroy_and_host_only_calls():
     L = mmcav.lib()
     p, geo = _params()
