@@ -196,6 +196,21 @@ __device__ __forceinline__ int xcd_block() {
   return x * q + min(x, r) + (b >> 3);
 }
 
+// Workgroup (of MMI_WG cells) that the lw-th workgroup of an instance takes.
+// Where a z-plane is a whole number P >= 64 of workgroups, consecutive
+// workgroups walk z first (lw = b nz + z takes block b of plane z), so that
+// the planes a stencil reads above and below are fetched by workgroups that
+// run close together on the same XCD (otherwise P workgroups apart, about
+// the span an XCD has resident).  Smaller planes keep the plain order, in
+// which z-neighbours are already close.  A bijection on the instance's
+// workgroups; the workgroup's cells, x-rows and partial record follow it.
+__device__ __forceinline__ int zmajor_wg(const InstDesc& D, int lw) {
+  const int plane = D.nx * D.ny;
+  if ((plane & (MMI_WG - 1)) || plane < 64 * MMI_WG) return lw;
+  const int P = plane >> MMI_LG_WG, b = lw / D.nz;
+  return (lw - b * D.nz) * P + b;
+}
+
 // Coordinates of cell i = (z ny + y) nx + x: shifts and masks when nx and ny
 // are powers of two, integer divisions otherwise.
 __device__ __forceinline__ void cell_xyz(const InstDesc& D, int i, int& x, int& y, int& z) {

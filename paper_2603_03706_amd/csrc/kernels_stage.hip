@@ -111,7 +111,7 @@ __global__ __launch_bounds__(MMI_WG) void k_stage(const InstDesc* __restrict__ d
   // the control block is only read here (the finalisation kernel writes it)
   const MMG InstCtl* __restrict__ C = gbl(D.ctl);
   if (C->done) return;
-  const int lw = lblk - D.wg0;
+  const int lw = zmajor_wg(D, lblk - D.wg0);
   const int nc = D.ncell;
   const int i = lw * MMI_WG + threadIdx.x;
   const bool valid = i < nc;
